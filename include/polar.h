@@ -1,0 +1,193 @@
+/*
+ * polar.h -- C-ABI of libpolar: the online part of the method of polarized
+ * traces for the 2D Helmholtz equation (Zepeda-Nunez & Demanet, "The method
+ * of polarized traces for the 2D Helmholtz equation", 2014) on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Problem (paper Section 2.1): -Lap u - omega^2 m u = f, m = 1/c^2, on the
+ * PML-padded rectangle with homogeneous Dirichlet data, discretised by the
+ * 5-point stencil with the unsymmetric PML alpha = 1/(1 + i sigma/omega),
+ * sigma(d) = (C/delta)(d/delta)^2, delta = npml*h.  Physical nodes are
+ * x_p = p*h, p = 1..nx (same for z); the padded grid has
+ * NX = nx + 2 npml columns (x, fastest) and NZ = nz + 2 npml rows (z).
+ *
+ * Method: pt_setup runs the offline part (Alg. 1): the z axis is split into
+ * L layers (Section 2.2; physical rows split evenly, layer 1 and layer L own
+ * the global PML rows, interior sides get npml extension rows), each layer's
+ * operator is factored on the GPU line by line (block-tridiagonal Schur
+ * recurrence Delta_r = A_r - l_r u_{r-1} Delta_{r-1}^{-1}, appendix B,
+ * Def. 10, with dense pivoted inverses of the NX x NX blocks), and the local
+ * Green's trace blocks between local rows {0, 1, n, n+1} are extracted
+ * (Def. 1, Def. 2).  pt_solve runs the online part (Alg. 2): local solves
+ * for the Newton potentials (Def. 3), flexible GMRES on the polarized system
+ * closed by jump conditions (Def. 9) preconditioned by n_it Gauss-Seidel
+ * sweeps (Alg. 4), then one forced local solve per layer
+ * (eq. PDE_version_green_formula) for the volume field.
+ *
+ * Conventions shared by every entry point:
+ *  - complex numbers are interleaved (re, im) float64 pairs (the layout of
+ *    C99 double _Complex and numpy complex128);
+ *  - a volume field is (nrhs, NZ, NX), x fastest, right-hand sides slowest;
+ *  - a polarized trace vector is (nrhs, 2, L-1, 2, NX): [down part d | up part
+ *    a], then interface k = 0..L-2 (between layers k and k+1, 0-based), then
+ *    the two trace rows (row n and n+1 of layer k = rows 0 and 1 of layer
+ *    k+1), then x;
+ *  - a layer-local field is (nrhs, sum_l R_l, NX): layer l's R_l local rows
+ *    (top extension, owned rows, bottom extension) stacked by layer;
+ *  - `on_device` = 1: every data pointer is device memory on the solver's
+ *    device (the call is asynchronous on the solver's stream except where
+ *    stated); 0: host memory (the call copies and synchronises);
+ *  - the caller owns every pointer it passes; pt_setup copies the model and
+ *    keeps no caller pointer; the solver owns all its device memory until
+ *    pt_free;
+ *  - every call returns a pt_status; no exception crosses the ABI; on error
+ *    pt_last_error() returns a thread-local message;
+ *  - one solver is driven from one host thread at a time (calls on one solver
+ *    are not re-entrant); different solvers are independent.
+ */
+#ifndef POLAR_H
+#define POLAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PT_OK = 0,
+  PT_EINVAL = 1,     /* invalid argument; outputs untouched                      */
+  PT_ENOMEM = 2,     /* device allocation failed                                  */
+  PT_EHIP = 3,       /* HIP runtime error                                         */
+  PT_ESINGULAR = 4,  /* zero pivot in the local factorisation                     */
+  PT_ENOCONV = 5     /* GMRES reached maxit; u holds the last iterate's field     */
+} pt_status;
+
+typedef enum {
+  PT_F64 = 0,        /* every block apply and local solve in complex float64     */
+  PT_F32 = 1         /* Green's blocks and local factors stored and applied in
+                        complex float32 (FP32 accumulation); Krylov vectors,
+                        Arnoldi, least squares and true residuals stay float64 */
+} pt_precision;
+
+/* One Helmholtz problem (paper Section 2.1; Alg. 1 inputs m, omega). */
+typedef struct {
+  int32_t nx, nz;    /* physical nodes along x (fast) and z (layered axis); >= 1   */
+  int32_t npml;      /* PML nodes per side, also the layer extension width; >= 1 */
+  double h;          /* grid spacing, > 0                                         */
+  double omega;      /* angular frequency, > 0                                    */
+  double pml_C;      /* PML strength C of sigma = (C/delta)(d/delta)^2, >= 0      */
+  int32_t L;         /* number of layers, >= 1; every layer needs >= 2 physical
+                        rows (nz >= 2L)                                           */
+  const double* c;   /* host velocity on the padded grid, NZ*NX values, > 0,
+                        finite, x fastest                                         */
+} pt_problem;
+
+typedef struct {
+  int32_t precision; /* pt_precision                                              */
+  int32_t gs_iters;  /* n_it of the Gauss-Seidel preconditioner (Alg. 4), 0..4;
+                        0 = unpreconditioned GMRES. Paper: 2                      */
+  double tol;        /* GMRES stop: relative residual of the trace system         */
+  int32_t maxit;     /* GMRES iterations (no restart), 1..200                     */
+  int32_t max_nrhs;  /* largest nrhs pt_solve will be called with, >= 1           */
+} pt_options;
+
+typedef struct {
+  int32_t iters;     /* GMRES iterations used                                     */
+  int32_t converged; /* 1 if the residual estimate reached tol                    */
+  double est;        /* GMRES residual estimate at exit (relative)                */
+  double relres;     /* true relative residual ||s - A x|| / ||s|| in float64     */
+} pt_rhs_info;
+
+typedef struct {
+  int32_t NX, NZ, L;
+  int32_t sumR;      /* rows of a layer-local field                               */
+  int64_t ntrace;    /* complex entries of one polarized trace vector, 4(L-1)NX   */
+  int32_t R[64];     /* local rows per layer (first min(L,64) layers)             */
+  int32_t own_start[64], n_own[64], top_ext[64], bot_ext[64];
+  double setup_ms;   /* wall time of pt_setup                                     */
+  int64_t block_bytes;  /* device bytes of the trace blocks                       */
+  int64_t factor_bytes; /* device bytes of the local factors                      */
+} pt_layout;
+
+typedef struct pt_solver pt_solver;
+
+/* Offline part (Alg. 1).  Validates the problem (PT_EINVAL on nx, nz, npml < 1,
+ * h or omega <= 0, C < 0, L < 1, a layer with < 2 physical rows, c <= 0 or not
+ * finite, NX > 4096), allocates every device buffer for up to opt->max_nrhs
+ * right-hand sides, factors the local problems and extracts the trace blocks
+ * on the GPU.  `hip_stream` is a hipStream_t (NULL = the null stream) on the
+ * current device; it becomes the solver's stream.  Synchronous. */
+pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stream, pt_solver** out);
+
+/* Online part (Alg. 2): u = H^{-1} f for nrhs fields f (nrhs, NZ, NX).  f is
+ * restricted to each layer's owned rows (its PML part is used as given).
+ * info (host, nrhs entries, may be NULL) receives per-RHS GMRES data.
+ * Returns PT_ENOCONV if any right-hand side missed tol within maxit (u is
+ * still written).  Host-synchronising once per GMRES iteration. */
+pt_status pt_solve(pt_solver* s, int32_t nrhs, const double* f, double* u, int32_t on_device,
+                   pt_rhs_info* info);
+
+void pt_free(pt_solver* s); /* NULL is a no-op */
+
+const char* pt_status_str(pt_status st);
+const char* pt_last_error(void);
+
+/* ---- stages of the online path, for verification and profiling ---------- */
+
+pt_status pt_get_layout(const pt_solver* s, pt_layout* out);
+
+/* K^l_{j,k} = (A^l)^{-1}_{j,k}, A^l = h^2 H^l, the Green's trace block of layer
+ * l between local rows j, k in {0: row 0, 1: row 1, 2: row n, 3: row n+1}
+ * (Def. 1: G^l(z_j, z_k) = h K_{j,k}).  Written to host `out` as an NX x NX
+ * row-major complex matrix (rows: target x).  PT_EINVAL if the layer has no
+ * such row (layer 0 has no rows 0, 1; layer L-1 no rows n, n+1).  Reads the
+ * stored float64 blocks (PT_F32 solvers: the float32 copy, widened). */
+pt_status pt_get_block(const pt_solver* s, int32_t layer, int32_t j, int32_t k, double* out);
+
+typedef enum {
+  PT_OP_A = 0,       /* y = A x: polarized system closed by jump conditions (Def. 9) */
+  PT_OP_R = 1,       /* y = R x, R = A - D (eq. def_permuted_system_jump)            */
+  PT_OP_DINV = 2,    /* y = D^{-1} x: down sweep and up sweep (Section 4.1)          */
+  PT_OP_PRECOND = 3  /* y = M^{-1} x: Gauss-Seidel preconditioner, gs_iters (Alg. 4) */
+} pt_op;
+
+/* y = op(x) on polarized trace vectors (nrhs, 2, L-1, 2, NX); L >= 2. */
+pt_status pt_apply(pt_solver* s, int32_t op, int32_t nrhs, const double* x, double* y, int32_t on_device);
+
+/* x = (A^l)^{-1} b for every layer l at once on layer-local fields
+ * (nrhs, sumR, NX): the forward/backward block sweep with the stored factors. */
+pt_status pt_local_solve(pt_solver* s, int32_t nrhs, const double* b, double* x, int32_t on_device);
+
+/* Right-hand side of the polarized system for sources f (nrhs, NZ, NX):
+ * s_down,k = (N f)^k at rows n, n+1; s_up,k = (N f)^{k+1} at rows 0, 1 with
+ * N f = (A^l)^{-1} h^2 f^l (Def. 3, Alg. 2).  s: (nrhs, 2, L-1, 2, NX). */
+pt_status pt_trace_rhs(pt_solver* s, int32_t nrhs, const double* f, double* out, int32_t on_device);
+
+/* Volume field from sources f and polarized traces x (both as above): one
+ * forced local solve per layer with t = d + a (eq. PDE_version_green_formula). */
+pt_status pt_reconstruct(pt_solver* s, int32_t nrhs, const double* f, const double* x, double* u,
+                         int32_t on_device);
+
+/* ---- live kernel timing ----------------------------------------------- */
+
+typedef struct {
+  int64_t launches;   /* block-apply launches recorded                           */
+  double kernel_ms;   /* sum of their durations (HIP events on the solver stream) */
+  double alg_bytes;   /* algorithmic bytes: every matrix block once + the vectors
+                         each launch must read and write                          */
+  double alg_flops;   /* 8 flops per complex multiply-add                          */
+} pt_kernel_stats;
+
+/* enable = 1: reset the counters and record a HIP event pair around every
+ * block-apply launch (the kernel that streams the Green's blocks and local
+ * factors); enable = 0: stop recording (counters kept). */
+pt_status pt_profile(pt_solver* s, int32_t enable);
+/* Synchronises the solver stream and returns the accumulated counters. */
+pt_status pt_profile_read(pt_solver* s, pt_kernel_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLAR_H */

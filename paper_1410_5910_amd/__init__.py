@@ -1,0 +1,8 @@
+"""MI355X-native online solver of the method of polarized traces (2D Helmholtz).
+
+The compute path is libpolar.so (HIP for gfx950, C-ABI in include/polar.h);
+``polar`` is its thin Python binding and ``build`` compiles it in-tree.
+"""
+from .polar import Solver, PolarError, lib, OP_A, OP_R, OP_DINV, OP_PRECOND, EXPORTS  # noqa: F401
+
+__all__ = ["Solver", "PolarError", "lib", "OP_A", "OP_R", "OP_DINV", "OP_PRECOND", "EXPORTS"]

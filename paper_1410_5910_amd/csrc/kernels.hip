@@ -1,0 +1,809 @@
+// HIP kernels of libpolar (gfx950 / CDNA4, 64-wide wavefronts).
+//
+// The hot kernel is block_apply: a batched complex block matrix-vector
+// (matrix-matrix for several right-hand sides) product with fused input
+// combination and output epilogue,
+//     Y = P + alpha * sum_t M_t (Q_t + beta_t S_t),
+// which covers every dense operation of the online path: one step of a
+// layer's forward/backward block sweep with the stored inverse Schur
+// complements, one step of the down/up Gauss-Seidel sweeps through the
+// transfer blocks, the reflection terms, and the polarized operator itself.
+// The matrices are streamed from HBM once per launch: each lane of a wave
+// owns one matrix row and walks the columns of a column-major block, so a
+// wave reads 64 consecutive complex entries (1 KiB) per column; the input
+// vector slice is staged in LDS; work is split along the columns across
+// workgroups with a deterministic last-arriving-workgroup reduction.
+#include "polar_kernels.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace polar {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm for a / b
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.y + b.x * r;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ void cfma(Cx<T>& acc, Cx<T> m, Cx<T> v) {
+  acc.x = fma(m.x, v.x, acc.x);
+  acc.x = fma(-m.y, v.y, acc.x);
+  acc.y = fma(m.x, v.y, acc.y);
+  acc.y = fma(m.y, v.x, acc.y);
+}
+
+template <bool F32>
+struct MatT;
+template <>
+struct MatT<false> {
+  using vec = double2;
+  using real = double;
+};
+template <>
+struct MatT<true> {
+  using vec = float2;
+  using real = float;
+};
+
+// ----------------------------------------------------------------------------
+// block_apply
+// ----------------------------------------------------------------------------
+// grid.x = njobs * ntiles * ksplit, grid.y = ceil(nrhs / NR); 256 threads.
+// Dynamic LDS: max(kc, 128) * NR complex (accumulator type): staged inputs, then the
+// cross-wave reduction.
+template <int NR, bool F32>
+__global__ __launch_bounds__(kThreads) void block_apply_kernel(const Job* __restrict__ jobs, int njobs,
+                                                               ApplyGeom g, int nrhs, int64_t ld, Bases bases,
+                                                               double2* __restrict__ part,
+                                                               uint32_t* __restrict__ counters) {
+  using MV = typename MatT<F32>::vec;
+  using T = typename MatT<F32>::real;
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* red = xs;  // reused for the cross-wave reduction once xs is consumed
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int wid = blockIdx.x;
+  const int ks = wid % g.ksplit;
+  wid /= g.ksplit;
+  const int tile = wid % g.ntiles;
+  const int jb = wid / g.ntiles;
+  const Job& J = jobs[jb];
+  const int n = g.n;
+  const int r0 = blockIdx.y * NR;
+  const int K = J.nterms * n;
+  const int k0 = ks * g.kc;
+  const int k1 = min(K, k0 + g.kc);
+  const int kw = max(0, k1 - k0);
+
+  // stage x = Q + beta S for columns [k0, k1) and right-hand sides [r0, r0 + NR)
+  for (int c = tid; c < kw * NR; c += kThreads) {
+    const int kk = k0 + c / NR;
+    const int r = c % NR;
+    const int t = kk / n;
+    const int jj = kk - t * n;
+    double2 v = make_double2(0.0, 0.0);
+    if (r0 + r < nrhs) {
+      const VecRef q = J.Q[t];
+      if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + jj];
+      const VecRef s = J.S[t];
+      if (s.buf >= 0) v = cadd(v, cmul(J.beta[t], bases.b[s.buf][s.off + (int64_t)(r0 + r) * ld + jj]));
+    }
+    xs[c].x = (T)v.x;
+    xs[c].y = (T)v.y;
+  }
+  __syncthreads();
+
+  const int row = tile * 64 + lane;
+  const bool valid = row < n;
+  const int rowc = valid ? row : n - 1;
+  Cx<T> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
+
+  const int per = (kw + 3) / 4;
+  const int cb = wave * per;
+  const int ce = min(kw, cb + per);
+  int kk = k0 + cb;
+  const int kend = k0 + ce;
+  while (kk < kend) {
+    const int t = kk / n;
+    const int jj = kk - t * n;
+    const int cnt = min(kend - kk, n - jj);
+    const MV* __restrict__ M = reinterpret_cast<const MV*>(J.M[t]) + (size_t)jj * n + rowc;
+    const Cx<T>* xp = xs + (size_t)(kk - k0) * NR;
+    int c = 0;
+    for (; c + 8 <= cnt; c += 8) {
+      MV m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m[u] = M[(size_t)(c + u) * n];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const Cx<T> mm{(T)m[u].x, (T)m[u].y};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[(c + u) * NR + r]);
+      }
+    }
+    for (; c < cnt; ++c) {
+      const MV m = M[(size_t)c * n];
+      const Cx<T> mm{(T)m.x, (T)m.y};
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[c * NR + r]);
+    }
+    kk += cnt;
+  }
+
+  // pairwise reduction of the four waves' partial sums: (w0 + w2) + (w1 + w3)
+  __syncthreads();
+  if (wave >= 2) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[((wave - 2) * 64 + lane) * NR + r] = acc[r];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const Cx<T> v = red[(wave * 64 + lane) * NR + r];
+      acc[r].x += v.x;
+      acc[r].y += v.y;
+    }
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[lane * NR + r] = acc[r];
+  }
+  __syncthreads();
+  double2 sum[NR];
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const Cx<T> v = red[lane * NR + r];
+      sum[r] = make_double2((double)acc[r].x + (double)v.x, (double)acc[r].y + (double)v.y);
+    }
+  }
+
+  if (g.ksplit > 1) {
+    const size_t tileid = ((size_t)blockIdx.y * njobs + jb) * g.ntiles + tile;
+    double2* pp = part + tileid * (size_t)g.ksplit * 64 * NR;
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) pp[((size_t)ks * 64 + lane) * NR + r] = sum[r];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t prev = atomicAdd(&counters[tileid], 1u);
+      s_last = (prev == (uint32_t)(g.ksplit - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sum[r] = make_double2(0.0, 0.0);
+      for (int q = 0; q < g.ksplit; ++q) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          sum[r] = cadd(sum[r], pp[((size_t)q * 64 + lane) * NR + r]);
+        }
+      }
+    }
+    if (tid == 0) counters[tileid] = 0u;
+  }
+
+  if (wave == 0 && valid) {
+    const VecRef P = J.P;
+    const VecRef Y = J.Y;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r0 + r < nrhs) {
+        double2 y = cmul(J.alpha, sum[r]);
+        if (P.buf >= 0) y = cadd(y, bases.b[P.buf][P.off + (int64_t)(r0 + r) * ld + row]);
+        bases.b[Y.buf][Y.off + (int64_t)(r0 + r) * ld + row] = y;
+      }
+    }
+  }
+}
+
+template <int NR, bool F32>
+hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
+                           double2* part, uint32_t* counters, hipStream_t st) {
+  using T = typename MatT<F32>::real;
+  const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
+  dim3 grid((unsigned)njobs * g.ntiles * g.ksplit, (unsigned)((nrhs + NR - 1) / NR));
+  hipLaunchKernelGGL((block_apply_kernel<NR, F32>), grid, dim3(kThreads), lds, st, jobs, njobs, g, nrhs, ld,
+                     bases, part, counters);
+  return hipGetLastError();
+}
+
+template <bool F32>
+hipError_t launch_apply_t(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
+                          double2* part, uint32_t* counters, hipStream_t st) {
+  switch (g.nr) {
+    case 1: return launch_apply_nr<1, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    case 2: return launch_apply_nr<2, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    case 4: return launch_apply_nr<4, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    case 8: return launch_apply_nr<8, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    case 16: return launch_apply_nr<16, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// setup: Gauss-Jordan inversion with partial pivoting
+// ----------------------------------------------------------------------------
+// grid.x = ntile^2 (64 x 64 tiles), grid.y = matrix; 256 threads.
+__global__ __launch_bounds__(kThreads) void gj_step_kernel(double2* const* __restrict__ A,
+                                                           double2* const* __restrict__ B, int n, int k,
+                                                           int32_t* __restrict__ perm, int32_t* __restrict__ flag) {
+  const int b = blockIdx.y;
+  const double2* __restrict__ a = A[b];
+  double2* __restrict__ o = B[b];
+  const int tid = threadIdx.x;
+  __shared__ double sv[kThreads];
+  __shared__ int si[kThreads];
+  __shared__ double2 wj[64];
+  __shared__ double2 fi[64];
+
+  // pivot: largest |a_ik|^2 over i >= k, smallest index on ties
+  double bv = -1.0;
+  int bi = n;
+  for (int i = k + tid; i < n; i += kThreads) {
+    const double2 v = a[(size_t)k * n + i];
+    const double m = v.x * v.x + v.y * v.y;
+    if (m > bv) {
+      bv = m;
+      bi = i;
+    }
+  }
+  sv[tid] = bv;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double v2 = sv[tid + s];
+      const int i2 = si[tid + s];
+      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
+        sv[tid] = v2;
+        si[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  // a column of zeros or NaNs has no pivot: flag it and keep the row order
+  const bool singular = !(sv[0] > 0.0) || si[0] >= n;
+  const int p = singular ? k : si[0];
+  const double2 piv = singular ? make_double2(1.0, 0.0) : a[(size_t)k * n + p];
+  const double2 inv = cdiv(make_double2(1.0, 0.0), piv);
+  if (blockIdx.x == 0 && tid == 0) {
+    perm[(size_t)b * n + k] = p;
+    if (singular) atomicOr(flag, 1);
+  }
+
+  const int nt = (n + 63) / 64;
+  const int ti = blockIdx.x % nt;
+  const int tj = blockIdx.x / nt;
+  if (tid < 64) {
+    const int col = tj * 64 + tid;
+    if (col < n) wj[tid] = (col == k) ? inv : cmul(a[(size_t)col * n + p], inv);
+  } else if (tid < 128) {
+    const int row = ti * 64 + (tid - 64);
+    if (row < n) {
+      const int src = (row == k) ? p : (row == p ? k : row);
+      fi[tid - 64] = a[(size_t)k * n + src];
+    }
+  }
+  __syncthreads();
+
+  const int lr = tid & 63;
+  const int row = ti * 64 + lr;
+  if (row >= n) return;
+  const int src = (row == k) ? p : (row == p ? k : row);
+  const double2 f = fi[lr];
+  for (int q = 0; q < 16; ++q) {
+    const int lc = (tid >> 6) + 4 * q;
+    const int col = tj * 64 + lc;
+    if (col >= n) break;
+    double2 out;
+    if (row == k) {
+      out = wj[lc];
+    } else if (col == k) {
+      const double2 t = cmul(f, inv);
+      out = make_double2(-t.x, -t.y);
+    } else {
+      const double2 t = cmul(f, wj[lc]);
+      const double2 v = a[(size_t)col * n + src];
+      out = make_double2(v.x - t.x, v.y - t.y);
+    }
+    o[(size_t)col * n + row] = out;
+  }
+}
+
+__global__ void gj_perm_kernel(const int32_t* __restrict__ perm, int32_t* __restrict__ pi, int nb, int n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int32_t* q = pi + (size_t)b * n;
+  const int32_t* pm = perm + (size_t)b * n;
+  for (int c = 0; c < n; ++c) q[c] = c;
+  for (int k = n - 1; k >= 0; --k) {
+    const int pk = pm[k];
+    const int32_t t = q[k];
+    q[k] = q[pk];
+    q[pk] = t;
+  }
+}
+
+__device__ __forceinline__ double2 tridiag_entry(int i, int c, const double2* diag, const double2* west,
+                                                 const double2* east) {
+  if (i == c) return diag[i];
+  if (i == c + 1) return west[i];
+  if (i + 1 == c) return east[i];
+  return make_double2(0.0, 0.0);
+}
+
+// grid.x = ceil(n*n / 256), grid.y = matrix
+__global__ void init_delta_kernel(double2* const* out, const double2* const* diag, const double2* west,
+                                  const double2* east, int n) {
+  const int b = blockIdx.y;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int c = (int)(e / n), i = (int)(e % n);
+  out[b][e] = tridiag_entry(i, c, diag[b], west, east);
+}
+
+__global__ void finish_row_kernel(double2* const* B, const int32_t* pi, double2* const* dinv64,
+                                  float2* const* dinv32, double2* const* nextD, const double2* const* next_diag,
+                                  const double2* coef, const double2* west, const double2* east, int n) {
+  const int b = blockIdx.y;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int c = (int)(e / n), i = (int)(e % n);
+  const double2 v = B[b][(size_t)pi[(size_t)b * n + c] * n + i];
+  if (dinv64[b]) dinv64[b][e] = v;
+  if (dinv32[b]) dinv32[b][e] = make_float2((float)v.x, (float)v.y);
+  if (next_diag[b]) {
+    const double2 t = cmul(coef[b], v);
+    const double2 d = tridiag_entry(i, c, next_diag[b], west, east);
+    nextD[b][e] = make_double2(d.x - t.x, d.y - t.y);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// field kernels
+// ----------------------------------------------------------------------------
+__global__ void scatter_source_kernel(const double2* __restrict__ f, double2* __restrict__ W,
+                                      const int32_t* __restrict__ rowmap, int sumR, int NZ, int NX, int nrhs,
+                                      double scale) {
+  const size_t total = (size_t)nrhs * sumR * NX;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % NX);
+    const size_t rg = e / NX;
+    const int gr = (int)(rg % sumR);
+    const int r = (int)(rg / sumR);
+    const int src = rowmap[gr];
+    double2 v = make_double2(0.0, 0.0);
+    if (src >= 0) {
+      const double2 fv = f[((size_t)r * NZ + src) * NX + i];
+      v = make_double2(scale * fv.x, scale * fv.y);
+    }
+    W[e] = v;
+  }
+}
+
+__global__ void gather_owned_kernel(const double2* __restrict__ W, double2* __restrict__ u,
+                                    const int32_t* __restrict__ rowmap, int sumR, int NZ, int NX, int nrhs) {
+  const size_t total = (size_t)nrhs * sumR * NX;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % NX);
+    const size_t rg = e / NX;
+    const int gr = (int)(rg % sumR);
+    const int r = (int)(rg / sumR);
+    const int dst = rowmap[gr];
+    if (dst >= 0) u[((size_t)r * NZ + dst) * NX + i] = W[e];
+  }
+}
+
+// grid: x over NX, y over map entries, z over rhs
+__global__ void trace_map_kernel(double2* W, double2* s, const double2* x, const int32_t* seg,
+                                 const int32_t* row, const double* sign, int mode, int sumR, int NX,
+                                 int64_t ntrace, int64_t half) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NX) return;
+  const int m = blockIdx.y;
+  const int r = blockIdx.z;
+  const int64_t wi = ((int64_t)r * sumR + row[m]) * NX + i;
+  const int64_t si = (int64_t)r * ntrace + (int64_t)seg[m] * NX + i;
+  if (mode == 0) {
+    s[si] = W[wi];
+  } else {
+    const double2 t = cadd(x[si], x[si + half]);
+    const double sg = sign[m];
+    const double2 w = W[wi];
+    W[wi] = make_double2(w.x + sg * t.x, w.y + sg * t.y);
+  }
+}
+
+__global__ void identity_rhs_kernel(double2* W, const int32_t* rows, int nq, int n, int64_t ld) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (c >= n || q >= nq) return;
+  W[(int64_t)(q * n + c) * ld + (int64_t)rows[q] * n + c] = make_double2(1.0, 0.0);
+}
+
+__global__ void pack_block_kernel(const double2* __restrict__ W, int64_t ld, int q, int row, int n, double sign,
+                                  double shift, double2* dst64, float2* dst32) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int c = (int)(e / n), i = (int)(e % n);
+  const double2 v = W[(int64_t)(q * n + c) * ld + (int64_t)row * n + i];
+  double2 o = make_double2(sign * v.x, sign * v.y);
+  if (i == c) o.x += shift;
+  if (dst64) dst64[e] = o;
+  if (dst32) dst32[e] = make_float2((float)o.x, (float)o.y);
+}
+
+__global__ void copy_kernel(double2* __restrict__ d, const double2* __restrict__ s, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    d[e] = s[e];
+}
+__global__ void zero_kernel(double2* __restrict__ d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    d[e] = make_double2(0.0, 0.0);
+}
+__global__ void add_kernel(double2* y, const double2* x, const double2* z, double sign, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double2 a = x[e], b = z[e];
+    y[e] = make_double2(a.x + sign * b.x, a.y + sign * b.y);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Krylov kernels (float64)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// grid: (m, nrhs), 256 threads
+__global__ __launch_bounds__(kThreads) void kdot_kernel(const double2* __restrict__ V, const double2* __restrict__ w,
+                                                        double2* __restrict__ hout, int nrhs, int64_t N) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const double2* v = V + ((int64_t)i * nrhs + r) * N;
+  const double2* x = w + (int64_t)r * N;
+  double re = 0.0, im = 0.0;
+  for (int64_t e = threadIdx.x; e < N; e += kThreads) {
+    const double2 t = cconjmul(v[e], x[e]);
+    re += t.x;
+    im += t.y;
+  }
+  __shared__ double sre[4], sim[4];
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sre[wv] = re;
+    sim[wv] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) hout[(int64_t)i * nrhs + r] = make_double2(sre[0] + sre[1] + sre[2] + sre[3],
+                                                                  sim[0] + sim[1] + sim[2] + sim[3]);
+}
+
+__global__ void kupdate_kernel(const double2* __restrict__ V, double2* __restrict__ w, const double2* __restrict__ h,
+                               double2* __restrict__ hacc, int m, int nrhs, int64_t N) {
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < m * nrhs; t += blockDim.x) hacc[t] = cadd(hacc[t], h[t]);
+  }
+  const int64_t total = (int64_t)nrhs * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / N);
+    const int64_t k = e - (int64_t)r * N;
+    double2 acc = w[e];
+    for (int i = 0; i < m; ++i) {
+      const double2 t = cmul(h[(int64_t)i * nrhs + r], V[((int64_t)i * nrhs + r) * N + k]);
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    w[e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void knorm_kernel(const double2* __restrict__ w, double* __restrict__ nrm,
+                                                         int64_t N) {
+  const int r = blockIdx.x;
+  const double2* x = w + (int64_t)r * N;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < N; e += kThreads) s += x[e].x * x[e].x + x[e].y * x[e].y;
+  __shared__ double ss[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ss[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[r] = sqrt(ss[0] + ss[1] + ss[2] + ss[3]);
+}
+
+__global__ void kscale_kernel(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N) {
+  const int64_t total = (int64_t)nrhs * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / N);
+    const double s = nrm[r];
+    const double2 x = w[e];
+    v[e] = s > 0.0 ? make_double2(x.x / s, x.y / s) : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void givens_kernel(double2* Hc, const double2* hacc, const double* nrm, double* cs, double2* sn,
+                              double2* g, double* est, const double* beta, int32_t* iters, int32_t* done,
+                              double tol, int j, int mdim, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double2* H = Hc + (size_t)r * (mdim + 1) * mdim + (size_t)j * (mdim + 1);
+  for (int i = 0; i <= j; ++i) H[i] = hacc[(size_t)i * nrhs + r];
+  H[j + 1] = make_double2(nrm[r], 0.0);
+  double* c = cs + (size_t)r * mdim;
+  double2* s = sn + (size_t)r * mdim;
+  double2* gg = g + (size_t)r * (mdim + 1);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = H[i], b = H[i + 1];
+    const double2 sb = cmul(s[i], b);
+    const double2 sa = cconjmul(s[i], a);  // conj(s) a
+    H[i] = make_double2(c[i] * a.x + sb.x, c[i] * a.y + sb.y);
+    H[i + 1] = make_double2(-sa.x + c[i] * b.x, -sa.y + c[i] * b.y);
+  }
+  const double2 a = H[j], b = H[j + 1];
+  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  double cj;
+  double2 sj;
+  if (nb == 0.0) {
+    cj = 1.0;
+    sj = make_double2(0.0, 0.0);
+  } else if (na == 0.0) {
+    cj = 0.0;
+    sj = make_double2(1.0, 0.0);
+  } else {
+    const double t = hypot(na, nb);
+    cj = na / t;
+    const double2 ph = make_double2(a.x / na, a.y / na);
+    sj = cmul(ph, make_double2(b.x / t, -b.y / t));
+  }
+  c[j] = cj;
+  s[j] = sj;
+  const double2 sb = cmul(sj, b);
+  H[j] = make_double2(cj * a.x + sb.x, cj * a.y + sb.y);
+  H[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = gg[j];
+  const double2 t = cconjmul(sj, gj);
+  gg[j + 1] = make_double2(-t.x, -t.y);
+  gg[j] = make_double2(cj * gj.x, cj * gj.y);
+  const double e = hypot(gg[j + 1].x, gg[j + 1].y) / beta[r];
+  if (!done[r]) {
+    est[r] = e;
+    iters[r] = j + 1;
+    if (e < tol || !(nrm[r] > 0.0)) done[r] = 1;
+  }
+}
+
+__global__ void ksolve_kernel(const double2* Hc, const double2* g, double2* y, const int32_t* iters, int mdim,
+                              int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double2* H = Hc + (size_t)r * (mdim + 1) * mdim;
+  const double2* gg = g + (size_t)r * (mdim + 1);
+  double2* yy = y + (size_t)r * mdim;
+  const int k = iters[r];
+  for (int i = k - 1; i >= 0; --i) {
+    double2 acc = gg[i];
+    for (int c = i + 1; c < k; ++c) {
+      const double2 t = cmul(H[(size_t)c * (mdim + 1) + i], yy[c]);
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    const double2 d = H[(size_t)i * (mdim + 1) + i];
+    yy[i] = (d.x == 0.0 && d.y == 0.0) ? make_double2(0.0, 0.0) : cdiv(acc, d);
+  }
+}
+
+__global__ void kcombine_kernel(const double2* __restrict__ Z, const double2* __restrict__ y,
+                                const int32_t* __restrict__ iters, double2* __restrict__ x, int mdim, int nrhs,
+                                int64_t N) {
+  const int64_t total = (int64_t)nrhs * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / N);
+    const int64_t k = e - (int64_t)r * N;
+    double2 acc = make_double2(0.0, 0.0);
+    const int m = iters[r];
+    for (int j = 0; j < m; ++j) acc = cadd(acc, cmul(y[(size_t)r * mdim + j], Z[((int64_t)j * nrhs + r) * N + k]));
+    x[e] = acc;
+  }
+}
+
+__global__ void kinit_kernel(double2* g, const double* beta, int32_t* done, int32_t* iters, double* est, int mdim,
+                             int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double2* gg = g + (size_t)r * (mdim + 1);
+  for (int i = 0; i <= mdim; ++i) gg[i] = make_double2(0.0, 0.0);
+  gg[0] = make_double2(beta[r], 0.0);
+  done[r] = beta[r] > 0.0 ? 0 : 1;
+  iters[r] = 0;
+  est[r] = beta[r] > 0.0 ? 1.0 : 0.0;
+}
+
+__global__ void to_f32_kernel(float2* __restrict__ d, const double2* __restrict__ s, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    d[e] = make_float2((float)s[e].x, (float)s[e].y);
+}
+
+inline unsigned grid_for(int64_t n, int cap = 8192) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
+                              bool f32, double2* part, uint32_t* counters, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  return f32 ? launch_apply_t<true>(jobs, njobs, g, nrhs, ld, bases, part, counters, st)
+             : launch_apply_t<false>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+}
+
+hipError_t launch_gj_step(double2* const* A, double2* const* B, int nb, int n, int k, int32_t* perm, int32_t* flag,
+                          hipStream_t st) {
+  const int nt = (n + 63) / 64;
+  hipLaunchKernelGGL(gj_step_kernel, dim3(nt * nt, nb), dim3(kThreads), 0, st, A, B, n, k, perm, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipStream_t st) {
+  hipLaunchKernelGGL(gj_perm_kernel, dim3((nb + 63) / 64), dim3(64), 0, st, perm, pi, nb, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_delta(double2* const* out, const double2* const* diag, const double2* west,
+                             const double2* east, int nb, int n, hipStream_t st) {
+  const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(init_delta_kernel, dim3(gx, nb), dim3(kThreads), 0, st, out, diag, west, east, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64, float2* const* dinv32,
+                             double2* const* nextD, const double2* const* next_diag, const double2* coef,
+                             const double2* west, const double2* east, int nb, int n, hipStream_t st) {
+  const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(finish_row_kernel, dim3(gx, nb), dim3(kThreads), 0, st, B, pi, dinv64, dinv32, nextD,
+                     next_diag, coef, west, east, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_source(const double2* f, double2* W, const int32_t* rowmap, int sumR, int NZ, int NX,
+                                 int nrhs, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_source_kernel, dim3(grid_for((int64_t)nrhs * sumR * NX)), dim3(kThreads), 0, st, f,
+                     W, rowmap, sumR, NZ, NX, nrhs, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_owned(const double2* W, double2* u, const int32_t* rowmap, int sumR, int NZ, int NX,
+                               int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(gather_owned_kernel, dim3(grid_for((int64_t)nrhs * sumR * NX)), dim3(kThreads), 0, st, W, u,
+                     rowmap, sumR, NZ, NX, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_map(double2* W, double2* s, const double2* x, const int32_t* seg, const int32_t* row,
+                            const double* sign, int nmap, int mode, int sumR, int NX, int64_t ntrace, int nrhs,
+                            int64_t half, hipStream_t st) {
+  if (nmap <= 0) return hipSuccess;
+  dim3 grid((NX + 127) / 128, nmap, nrhs);
+  hipLaunchKernelGGL(trace_map_kernel, grid, dim3(128), 0, st, W, s, x, seg, row, sign, mode, sumR, NX, ntrace,
+                     half);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_rhs(double2* W, const int32_t* rows, int nq, int n, int64_t ld, hipStream_t st) {
+  hipLaunchKernelGGL(identity_rhs_kernel, dim3((n + 127) / 128, nq), dim3(128), 0, st, W, rows, nq, n, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n, double sign, double shift,
+                             double2* dst64, float2* dst32, hipStream_t st) {
+  const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(pack_block_kernel, dim3(gx), dim3(kThreads), 0, st, W, ld, q, row, n, sign, shift, dst64,
+                     dst32);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double2* dst, const double2* src, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero(double2* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_add(double2* y, const double2* x, const double2* z, double sign, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(add_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, y, x, z, sign, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_kdot(const double2* V, const double2* w, double2* hout, int m, int nrhs, int64_t N,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(kdot_kernel, dim3(m, nrhs), dim3(kThreads), 0, st, V, w, hout, nrhs, N);
+  return hipGetLastError();
+}
+hipError_t launch_kupdate(const double2* V, double2* w, const double2* h, double2* hacc, int m, int nrhs, int64_t N,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(kupdate_kernel, dim3(grid_for((int64_t)nrhs * N)), dim3(kThreads), 0, st, V, w, h, hacc, m,
+                     nrhs, N);
+  return hipGetLastError();
+}
+hipError_t launch_knorm(const double2* w, double* nrm, int nrhs, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(knorm_kernel, dim3(nrhs), dim3(kThreads), 0, st, w, nrm, N);
+  return hipGetLastError();
+}
+hipError_t launch_kscale(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(kscale_kernel, dim3(grid_for((int64_t)nrhs * N)), dim3(kThreads), 0, st, v, w, nrm, nrhs, N);
+  return hipGetLastError();
+}
+hipError_t launch_givens(double2* Hc, const double2* hacc, const double* nrm, double* cs, double2* sn, double2* g,
+                         double* est, const double* beta, int32_t* iters, int32_t* done, double tol, int j,
+                         int mdim, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, Hc, hacc, nrm, cs, sn, g, est, beta,
+                     iters, done, tol, j, mdim, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_ksolve(const double2* Hc, const double2* g, double2* y, const int32_t* iters, int mdim, int nrhs,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(ksolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, Hc, g, y, iters, mdim, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_kinit(double2* g, const double* beta, int32_t* done, int32_t* iters, double* est, int mdim,
+                        int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(kinit_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, g, beta, done, iters, est, mdim, nrhs);
+  return hipGetLastError();
+}
+hipError_t launch_to_f32(float2* d, const double2* s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, d, s, n);
+  return hipGetLastError();
+}
+hipError_t launch_kcombine(const double2* Z, const double2* y, const int32_t* iters, double2* x, int mdim, int nrhs,
+                           int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(kcombine_kernel, dim3(grid_for((int64_t)nrhs * N)), dim3(kThreads), 0, st, Z, y, iters, x,
+                     mdim, nrhs, N);
+  return hipGetLastError();
+}
+
+}  // namespace polar

@@ -1,0 +1,141 @@
+// Internal interface between the host orchestration (solver.hip) and the
+// HIP kernels (kernels.hip) of libpolar.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace polar {
+
+// A reference to a complex float64 vector inside one of the four base buffers
+// a launch receives: element (row i, right-hand side r) lives at
+// base[buf] + off + r * ld + i.  buf < 0 means "absent".
+struct VecRef {
+  int32_t buf;
+  int32_t pad;
+  int64_t off;
+};
+
+// One output block of a batched block apply:
+//   Y = P + alpha * sum_t M_t (Q_t + beta_t S_t)
+// Each M_t is an n x n column-major matrix (complex float64 or complex float32),
+// every vector has n rows and nrhs columns with the launch's column stride.
+struct Job {
+  const void* M[4];
+  VecRef Q[4];
+  VecRef S[4];
+  double2 beta[4];
+  VecRef P;
+  VecRef Y;
+  double2 alpha;
+  int32_t nterms;
+  int32_t pad;
+};
+
+struct Bases {
+  double2* b[4];
+};
+
+// Launch geometry of one block-apply launch (host-computed).
+struct ApplyGeom {
+  int n;        // block size NX
+  int ntiles;   // ceil(n / 64)
+  int ksplit;   // k-splits per (job, tile)
+  int kc;       // columns per split (multiple of 4)
+  int nr;       // right-hand sides per workgroup (template width)
+};
+
+// ---------------------------------------------------------------- block apply
+// part / counters: scratch for split-k partial sums, sized by the host for
+// njobs * ntiles * ksplit * 64 * nr * nchunks complex and njobs * ntiles *
+// nchunks counters (counters must start at zero; the kernel leaves them zero).
+hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld,
+                              Bases bases, bool f32, double2* part, uint32_t* counters,
+                              hipStream_t st);
+
+// ---------------------------------------------------------- setup kernels
+// Per-layer Gauss-Jordan inversion with partial pivoting of nb dense n x n
+// column-major matrices.  One call performs elimination step k on every
+// matrix: reads A[b], writes B[b], records perm[b*n + k], raises *flag on a
+// zero pivot.
+hipError_t launch_gj_step(double2* const* A, double2* const* B, int nb, int n, int k, int32_t* perm,
+                          int32_t* flag, hipStream_t st);
+// Composes the column un-scrambling permutation of each matrix (pi[b*n + c]).
+hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipStream_t st);
+
+// Delta_0 = tridiag(A_0) for nb layers: out[b] = west/east couplings + diag[b].
+hipError_t launch_init_delta(double2* const* out, const double2* const* diag, const double2* west,
+                             const double2* east, int nb, int n, hipStream_t st);
+
+// Finishes local row r of nb layers: Dinv = B[:, pi] (stored as f64 and/or
+// f32), and if next_diag[b] != nullptr also writes the next Schur complement
+// Delta_{r+1} = tridiag(A_{r+1}) - coef[b] * Dinv into nextD[b].
+hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64,
+                             float2* const* dinv32, double2* const* nextD,
+                             const double2* const* next_diag, const double2* coef, const double2* west,
+                             const double2* east, int nb, int n, hipStream_t st);
+
+// --------------------------------------------------------- field kernels
+// Local fields: (nrhs, sumR, NX); volume fields: (nrhs, NZ, NX).
+// rowmap[g] for local row g in 0..sumR-1: the padded-grid row it copies from
+// (owned rows) or -1 (extension rows).
+hipError_t launch_scatter_source(const double2* f, double2* W, const int32_t* rowmap, int sumR, int NZ,
+                                 int NX, int nrhs, double scale, hipStream_t st);
+// u[own rows] = W[rows with rowmap >= 0]
+hipError_t launch_gather_owned(const double2* W, double2* u, const int32_t* rowmap, int sumR, int NZ,
+                               int NX, int nrhs, hipStream_t st);
+// Trace exchange: for each of nmap (trace segment, local row, sign) triples:
+// mode 0: s[seg] = W[row]              (trace right-hand side)
+// mode 1: W[row] += sign * (x_d[seg] + x_a[seg])  (interface forcing)
+hipError_t launch_trace_map(double2* W, double2* s, const double2* x, const int32_t* seg,
+                            const int32_t* row, const double* sign, int nmap, int mode, int sumR,
+                            int NX, int64_t ntrace, int nrhs, int64_t half, hipStream_t st);
+
+// Extraction right-hand sides: W = 0 except W[c + q*n, row_q, c] = 1 for the
+// nq source rows row_q (local rows of one layer, offset already applied).
+hipError_t launch_identity_rhs(double2* W, const int32_t* rows, int nq, int n, int64_t ld, hipStream_t st);
+
+// Copy with optional scale/identity shift of one n x n block out of a local
+// field with nrhs = nq*n columns: dst(i, c) = sign * W[c + q*n, row, i] + shift*(i==c).
+hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n, double sign,
+                             double shift, double2* dst64, float2* dst32, hipStream_t st);
+
+// ---------------------------------------------------------- vector kernels
+hipError_t launch_copy(double2* dst, const double2* src, int64_t n, hipStream_t st);
+hipError_t launch_zero(double2* dst, int64_t n, hipStream_t st);
+// y[e] = x[e] + sign * z[e]
+hipError_t launch_add(double2* y, const double2* x, const double2* z, double sign, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------- Krylov kernels
+// Basis vectors are (nrhs, N) blocks, basis i at V + i * nrhs * N.
+// hout[i * nrhs + r] = <V_i[r], w[r]> = sum conj(V_i[r]) w[r], i < m
+hipError_t launch_kdot(const double2* V, const double2* w, double2* hout, int m, int nrhs, int64_t N,
+                       hipStream_t st);
+// w[r] -= sum_i h[i * nrhs + r] V_i[r]; hacc[i * nrhs + r] += h[...]
+hipError_t launch_kupdate(const double2* V, double2* w, const double2* h, double2* hacc, int m, int nrhs,
+                          int64_t N, hipStream_t st);
+// nrm[r] = ||w[r]||_2
+hipError_t launch_knorm(const double2* w, double* nrm, int nrhs, int64_t N, hipStream_t st);
+// v[r] = w[r] / nrm[r] (zero if nrm == 0)
+hipError_t launch_kscale(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N,
+                         hipStream_t st);
+// Per right-hand side: Hessenberg column j from hacc (j+1 entries) and nrm, the
+// previous Givens rotations, a new rotation, the rotated residual vector g and
+// the residual estimate |g[j+1]| / beta.  State arrays are per-RHS strided by mdim.
+hipError_t launch_givens(double2* Hc, const double2* hacc, const double* nrm, double* cs, double2* sn,
+                         double2* g, double* est, const double* beta, int32_t* iters, int32_t* done,
+                         double tol, int j, int mdim, int nrhs, hipStream_t st);
+// y = H(0:k,0:k)^{-1} g(0:k) per RHS with k = iters[r]
+hipError_t launch_ksolve(const double2* Hc, const double2* g, double2* y, const int32_t* iters, int mdim,
+                         int nrhs, hipStream_t st);
+// x[r] = sum_{j < iters[r]} y[r*mdim + j] Z_j[r]
+hipError_t launch_kcombine(const double2* Z, const double2* y, const int32_t* iters, double2* x, int mdim,
+                           int nrhs, int64_t N, hipStream_t st);
+
+// g[r] = (beta[r], 0, ...), done[r] = (beta[r] == 0), iters[r] = 0, est[r] = 1 (0 if beta == 0)
+hipError_t launch_kinit(double2* g, const double* beta, int32_t* done, int32_t* iters, double* est, int mdim,
+                        int nrhs, hipStream_t st);
+// d = (complex float32) s
+hipError_t launch_to_f32(float2* d, const double2* s, int64_t n, hipStream_t st);
+
+}  // namespace polar

@@ -1,0 +1,1345 @@
+// libpolar host side: validation, layer layout, coefficient assembly, the
+// offline factorisation / trace-block extraction on the GPU (Alg. 1), the
+// online solve (Alg. 2 with flexible GMRES on the jump-closed polarized
+// system, Def. 9, preconditioned by Gauss-Seidel sweeps, Alg. 4), and the
+// C-ABI of include/polar.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/polar.h"
+#include "polar_kernels.h"
+
+using namespace polar;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(PT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PTCHK(expr)               \
+  do {                            \
+    pt_status s_ = (expr);        \
+    if (s_ != PT_OK) return s_;   \
+  } while (0)
+
+struct cd {
+  double re, im;
+};
+inline cd cmk(double r, double i) { return {r, i}; }
+inline cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+inline cd operator-(cd a) { return {-a.re, -a.im}; }
+inline double2 d2(cd a) { return make_double2(a.re, a.im); }
+
+// alpha = 1 / (1 + i sigma / omega), sigma = (C/delta)(d/delta)^2
+cd pml_alpha(double d_len, double C, double delta, double omega) {
+  const double s = d_len > 0.0 ? (C / delta) * (d_len / delta) * (d_len / delta) : 0.0;
+  const double t = s / omega;  // 1/(1 + i t) = (1 - i t)/(1 + t^2)
+  return {1.0 / (1.0 + t * t), -t / (1.0 + t * t)};
+}
+
+// distance (in units of h) of a grid position beyond the physical segment [0, n+1]
+double beyond(double pos, int n) { return std::max(0.0, std::max(-pos, pos - (n + 1))); }
+
+struct Layer {
+  int own_start, n, top_ext, bot_ext, R, rowbase;
+  int r0, r1, rn, rn1;  // local rows of the paper's j = 0, 1, n, n+1 (-1 if absent)
+};
+
+struct Launch {
+  int job0 = 0, njobs = 0, maxterms = 0;
+  double mat_elems = 0;      // matrix entries streamed by one launch
+  double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
+};
+
+struct ProfPending {
+  int ev;  // index of the event pair
+  double bytes, flops;
+};
+
+// block types per layer; each is a 2x2 arrangement of NX x NX blocks
+enum { T_DN = 0, B_UP = 1, T_UP = 2, B_DN = 3 };
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)&p, count * sizeof(T));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct pt_solver {
+  // problem
+  int nx = 0, nz = 0, npml = 0, NX = 0, NZ = 0, L = 0;
+  double h = 0, omega = 0, C = 0;
+  pt_options opt{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  std::vector<Layer> lay;
+  int sumR = 0, Rmax = 0;
+  int64_t Nt = 0;  // complex entries of one polarized vector
+  bool f32 = false;
+  double setup_ms = 0;
+
+  // coefficients
+  std::vector<cd> lcoef, ucoef;  // z couplings of each local row (sumR)
+
+  // device data
+  DevBuf<double2> dinv64, blk64;
+  DevBuf<float2> dinv32, blk32;
+  int nblk = 0;
+  std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
+  DevBuf<int32_t> rowmap;
+  DevBuf<int32_t> g_seg, g_row, f_seg, f_row;
+  DevBuf<double> f_sign, g_sign;
+  int n_gather = 0, n_force = 0;
+
+  // job lists
+  std::vector<Job> hjobs;
+  DevBuf<Job> jobs;
+  std::vector<Launch> fwd, bwd, sweep;
+  Launch bterm, opA, opR;
+
+  // scratch
+  DevBuf<double2> part;
+  DevBuf<uint32_t> counters;
+
+  // live timing of block-apply launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // 2 per slot
+  int ev_next = 0;
+  std::vector<ProfPending> pend;
+  pt_kernel_stats stats{};
+
+  // work
+  DevBuf<double2> W, Bw, fio, uio, s, V, Z, U1, U2, tmp, zeros, x;
+  DevBuf<double2> hbuf, hacc, Hc, sn, g, y;
+  DevBuf<double> nrm, cs, est, beta;
+  DevBuf<int32_t> iters, done, flag;
+  int32_t* h_done = nullptr;  // pinned
+
+  size_t block_elems() const { return (size_t)NX * NX; }
+  const void* blk(int l, int type, int a, int b) const {
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    if (id < 0) return nullptr;
+    return f32 ? (const void*)(blk32.p + (size_t)id * block_elems()) : (const void*)(blk64.p + (size_t)id * block_elems());
+  }
+  const void* dinv(int l, int r) const {
+    const size_t off = (size_t)(lay[l].rowbase + r) * block_elems();
+    return f32 ? (const void*)(dinv32.p + off) : (const void*)(dinv64.p + off);
+  }
+  // offset of trace segment (half h: 0 down, 1 up; interface k; row a)
+  int64_t seg(int hh, int k, int a) const { return ((int64_t)(hh * (L - 1) + k) * 2 + a) * NX; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// geometry of one block-apply launch
+// ---------------------------------------------------------------------------
+ApplyGeom geom_for(int n, int njobs, int maxterms, int nrhs) {
+  ApplyGeom g{};
+  g.n = n;
+  g.ntiles = (n + 63) / 64;
+  g.nr = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16;
+  const int nchunks = (nrhs + g.nr - 1) / g.nr;
+  const int K = std::max(1, maxterms * n);
+  const int kcap = std::max(64, 2048 / g.nr);  // LDS: kc * nr complex doubles <= 32 KiB
+  const long base = (long)njobs * g.ntiles * nchunks;
+  const long target = 1024;
+  int ks = (int)std::max(1L, (target + base - 1) / base);
+  int kc = (K + ks - 1) / ks;
+  kc = std::max(kc, std::min(K, 64));
+  kc = std::min(kc, kcap);
+  kc = ((kc + 3) / 4) * 4;
+  g.kc = kc;
+  g.ksplit = (K + kc - 1) / kc;
+  return g;
+}
+
+size_t part_need(const ApplyGeom& g, int njobs, int nrhs) {
+  if (g.ksplit <= 1) return 0;
+  const int nchunks = (nrhs + g.nr - 1) / g.nr;
+  return (size_t)njobs * g.ntiles * g.ksplit * 64 * g.nr * nchunks;
+}
+size_t counter_need(const ApplyGeom& g, int njobs, int nrhs) {
+  const int nchunks = (nrhs + g.nr - 1) / g.nr;
+  return (size_t)njobs * g.ntiles * nchunks;
+}
+
+VecRef vr(int buf, int64_t off) { return VecRef{buf, 0, off}; }
+VecRef none() { return VecRef{-1, 0, 0}; }
+
+Job empty_job() {
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  for (int t = 0; t < 4; ++t) {
+    j.Q[t] = none();
+    j.S[t] = none();
+    j.beta[t] = make_double2(0.0, 0.0);
+  }
+  j.P = none();
+  j.Y = none();
+  j.alpha = make_double2(1.0, 0.0);
+  return j;
+}
+
+void add_term(Job& j, const void* M, VecRef q, VecRef s = VecRef{-1, 0, 0}, double2 beta = make_double2(1.0, 0.0)) {
+  const int t = j.nterms++;
+  j.M[t] = M;
+  j.Q[t] = q;
+  j.S[t] = s;
+  j.beta[t] = beta;
+}
+
+constexpr int kEventSlots = 2048;
+
+pt_status prof_harvest(pt_solver* S) {
+  if (S->pend.empty()) return PT_OK;
+  HIPCHK(hipStreamSynchronize(S->st));
+  for (const ProfPending& p : S->pend) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, S->ev[2 * p.ev], S->ev[2 * p.ev + 1]));
+    S->stats.launches += 1;
+    S->stats.kernel_ms += ms;
+    S->stats.alg_bytes += p.bytes;
+    S->stats.alg_flops += p.flops;
+  }
+  S->pend.clear();
+  S->ev_next = 0;
+  return PT_OK;
+}
+
+pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b) {
+  if (Lc.njobs == 0) return PT_OK;
+  const ApplyGeom g = geom_for(S->NX, Lc.njobs, Lc.maxterms, nrhs);
+  if (part_need(g, Lc.njobs, nrhs) > S->part.n || counter_need(g, Lc.njobs, nrhs) > S->counters.n)
+    return fail(PT_EINVAL, "internal: split-k scratch too small");
+  int slot = -1;
+  if (S->prof) {
+    if (S->ev_next >= kEventSlots) PTCHK(prof_harvest(S));
+    slot = S->ev_next++;
+    HIPCHK(hipEventRecord(S->ev[2 * slot], S->st));
+  }
+  HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->part.p, S->counters.p, S->st));
+  if (S->prof) {
+    HIPCHK(hipEventRecord(S->ev[2 * slot + 1], S->st));
+    const double es = S->f32 ? 8.0 : 16.0;
+    S->pend.push_back(ProfPending{slot, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
+                                  8.0 * Lc.mat_elems * nrhs});
+  }
+  return PT_OK;
+}
+
+Launch push_launch(pt_solver* S, const std::vector<Job>& js) {
+  Launch Lc;
+  Lc.job0 = (int)S->hjobs.size();
+  Lc.njobs = (int)js.size();
+  for (const Job& j : js) Lc.maxterms = std::max(Lc.maxterms, j.nterms);
+  const double n = S->NX;
+  for (const Job& j : js) {
+    Lc.mat_elems += j.nterms * n * n;
+    double v = (j.P.buf >= 0 ? n : 0) + n;  // epilogue read + output write
+    for (int t = 0; t < j.nterms; ++t) v += (j.Q[t].buf >= 0 ? n : 0) + (j.S[t].buf >= 0 ? n : 0);
+    Lc.vec_elems_rhs += v;
+  }
+  S->hjobs.insert(S->hjobs.end(), js.begin(), js.end());
+  return Lc;
+}
+
+// ---------------------------------------------------------------------------
+// layout and coefficients
+// ---------------------------------------------------------------------------
+pt_status validate(const pt_problem* p, const pt_options* o) {
+  if (!p || !o) return fail(PT_EINVAL, "null problem or options");
+  if (p->nx < 1 || p->nz < 1 || p->npml < 1) return fail(PT_EINVAL, "nx, nz, npml must be >= 1");
+  if (!(p->h > 0) || !(p->omega > 0) || !std::isfinite(p->h) || !std::isfinite(p->omega))
+    return fail(PT_EINVAL, "h and omega must be positive and finite");
+  if (!(p->pml_C >= 0) || !std::isfinite(p->pml_C)) return fail(PT_EINVAL, "pml_C must be >= 0 and finite");
+  if (p->L < 1) return fail(PT_EINVAL, "L must be >= 1");
+  if (p->nz / p->L < 2) return fail(PT_EINVAL, "every layer needs at least 2 physical rows (nz >= 2L)");
+  if (p->nx + 2 * p->npml > 4096) return fail(PT_EINVAL, "NX > 4096 is not supported");
+  if (!p->c) return fail(PT_EINVAL, "null velocity");
+  const size_t N = (size_t)(p->nx + 2 * p->npml) * (p->nz + 2 * p->npml);
+  for (size_t e = 0; e < N; ++e)
+    if (!(p->c[e] > 0) || !std::isfinite(p->c[e])) return fail(PT_EINVAL, "velocity must be positive and finite");
+  if (o->precision != PT_F64 && o->precision != PT_F32) return fail(PT_EINVAL, "unknown precision");
+  if (o->gs_iters < 0 || o->gs_iters > 4) return fail(PT_EINVAL, "gs_iters must be in 0..4");
+  if (o->maxit < 1 || o->maxit > 200) return fail(PT_EINVAL, "maxit must be in 1..200");
+  if (!(o->tol >= 0)) return fail(PT_EINVAL, "tol must be >= 0");
+  if (o->max_nrhs < 1) return fail(PT_EINVAL, "max_nrhs must be >= 1");
+  return PT_OK;
+}
+
+void make_layout(pt_solver* S) {
+  const int L = S->L, nz = S->nz, npml = S->npml;
+  const int base = nz / L, extra = nz % L;
+  int start = 0, rowbase = 0;
+  S->lay.clear();
+  for (int l = 0; l < L; ++l) {
+    Layer y{};
+    y.n = base + (l < extra ? 1 : 0) + (l == 0 ? npml : 0) + (l == L - 1 ? npml : 0);
+    y.own_start = start;
+    y.top_ext = l > 0 ? npml : 0;
+    y.bot_ext = l < L - 1 ? npml : 0;
+    y.R = y.top_ext + y.n + y.bot_ext;
+    y.rowbase = rowbase;
+    y.r0 = y.top_ext ? y.top_ext - 1 : -1;
+    y.r1 = y.top_ext ? y.top_ext : -1;
+    y.rn = y.bot_ext ? y.top_ext + y.n - 1 : -1;
+    y.rn1 = y.bot_ext ? y.top_ext + y.n : -1;
+    start += y.n;
+    rowbase += y.R;
+    S->lay.push_back(y);
+  }
+  S->sumR = rowbase;
+  S->Rmax = 0;
+  for (auto& y : S->lay) S->Rmax = std::max(S->Rmax, y.R);
+  S->Nt = (int64_t)4 * (L - 1) * S->NX;
+}
+
+// Local z data of every local row: alpha at the node and both half nodes
+// (owned rows use the global profile; extension rows a profile measured from
+// the first extension node), and the padded-grid row of the (normally
+// extended) model.
+struct RowZ {
+  cd a, am, ap;
+  int mrow;
+};
+
+std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
+  const double delta = S->npml * S->h;
+  const int q_start = y.own_start - S->npml + 1;  // global q of local j = 1
+  auto dist = [&](double zeta) -> double {
+    if (y.top_ext && zeta < 1) return std::max(0.0, -zeta);
+    if (y.bot_ext && zeta > y.n) return std::max(0.0, zeta - (y.n + 1));
+    return beyond(q_start + zeta - 1, S->nz);
+  };
+  std::vector<RowZ> out(y.R);
+  for (int r = 0; r < y.R; ++r) {
+    const double j = r - y.top_ext + 1;
+    out[r].a = pml_alpha(dist(j) * S->h, S->C, delta, S->omega);
+    out[r].am = pml_alpha(dist(j - 0.5) * S->h, S->C, delta, S->omega);
+    out[r].ap = pml_alpha(dist(j + 0.5) * S->h, S->C, delta, S->omega);
+    const int jj = std::min(std::max((int)j, 1), y.n);
+    out[r].mrow = y.own_start + jj - 1;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// local solves (forward/backward block sweeps with the stored inverses)
+// ---------------------------------------------------------------------------
+// Jobs of the sweep over the layers in `ls` on a local field whose layer l
+// starts at local row rb[l]: bases 0 = solution W, 1 = right-hand side B.
+void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vector<int>& rb,
+                      std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw) {
+  const int NX = S->NX;
+  int Rm = 0;
+  for (int l : ls) Rm = std::max(Rm, S->lay[l].R);
+  fw.assign(Rm, {});
+  bw.assign(std::max(0, Rm - 1), {});
+  for (size_t q = 0; q < ls.size(); ++q) {
+    const int l = ls[q];
+    const Layer& y = S->lay[l];
+    for (int r = 0; r < y.R; ++r) {
+      // y_r = Dinv_r (b_r - l_r y_{r-1})
+      Job j = empty_job();
+      j.Y = vr(0, (int64_t)(rb[q] + r) * NX);
+      const cd lr = S->lcoef[y.rowbase + r];
+      if (r > 0)
+        add_term(j, S->dinv(l, r), vr(1, (int64_t)(rb[q] + r) * NX), vr(0, (int64_t)(rb[q] + r - 1) * NX), d2(-lr));
+      else
+        add_term(j, S->dinv(l, r), vr(1, (int64_t)(rb[q] + r) * NX));
+      fw[r].push_back(j);
+    }
+    for (int r = y.R - 2; r >= 0; --r) {
+      // x_r = y_r - u_r Dinv_r x_{r+1}
+      Job j = empty_job();
+      j.Y = vr(0, (int64_t)(rb[q] + r) * NX);
+      j.P = j.Y;
+      j.alpha = d2(-S->ucoef[y.rowbase + r]);
+      add_term(j, S->dinv(l, r), vr(0, (int64_t)(rb[q] + r + 1) * NX));
+      bw[y.R - 2 - r].push_back(j);
+    }
+  }
+}
+
+pt_status run_local(pt_solver* S, const std::vector<Launch>& fw, const std::vector<Launch>& bw, int nrhs, int64_t ld,
+                    double2* Wsol, double2* Brhs) {
+  Bases b{{Wsol, Brhs, nullptr, nullptr}};
+  for (const Launch& Lc : fw) PTCHK(run_apply(S, Lc, nrhs, ld, b));
+  for (const Launch& Lc : bw) PTCHK(run_apply(S, Lc, nrhs, ld, b));
+  return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::vector<cd>& west,
+                    const std::vector<cd>& east) {
+  const int NX = S->NX, L = S->L;
+  const size_t E = S->block_elems();
+  hipStream_t st = S->st;
+  DevBuf<double2> dg, dw, de, gjA, gjB, coef;
+  DevBuf<int32_t> perm, pi;
+  DevBuf<double2*> pA, pB, pD, pN, pDiag;
+  DevBuf<float2*> pD32;
+  pt_status rc = PT_OK;
+  auto cleanup = [&]() {
+    for (auto* b : {&dg, &dw, &de, &gjA, &gjB, &coef}) b->release();
+    perm.release();
+    pi.release();
+    pA.release();
+    pB.release();
+    pD.release();
+    pN.release();
+    pDiag.release();
+    pD32.release();
+  };
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == PT_OK) rc = fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP,
+                                                  std::string(what) + ": " + hipGetErrorString(e));
+    return rc == PT_OK;
+  };
+  if (!chk(dg.alloc(diag_all.size()), "alloc diag") || !chk(dw.alloc(NX), "alloc") || !chk(de.alloc(NX), "alloc") ||
+      !chk(gjA.alloc(E * L), "alloc gj") || !chk(gjB.alloc(E * L), "alloc gj") || !chk(coef.alloc(L), "alloc") ||
+      !chk(perm.alloc((size_t)L * NX), "alloc") || !chk(pi.alloc((size_t)L * NX), "alloc") ||
+      !chk(pA.alloc(L), "alloc") || !chk(pB.alloc(L), "alloc") || !chk(pD.alloc(L), "alloc") ||
+      !chk(pN.alloc(L), "alloc") || !chk(pDiag.alloc(L), "alloc") || !chk(pD32.alloc(L), "alloc")) {
+    cleanup();
+    return rc;
+  }
+  chk(hipMemcpy(dg.p, diag_all.data(), diag_all.size() * sizeof(double2), hipMemcpyHostToDevice), "copy");
+  chk(hipMemcpy(dw.p, west.data(), NX * sizeof(double2), hipMemcpyHostToDevice), "copy");
+  chk(hipMemcpy(de.p, east.data(), NX * sizeof(double2), hipMemcpyHostToDevice), "copy");
+  chk(hipMemsetAsync(S->flag.p, 0, sizeof(int32_t), st), "memset");
+  if (rc != PT_OK) {
+    cleanup();
+    return rc;
+  }
+  // Each layer alternates between its two Gauss-Jordan buffers; cur[l] is
+  // the buffer holding the current Schur complement Delta_r.
+  std::vector<int> cur(L, 0);
+  std::vector<double2*> hA(L), hB(L), hD(L), hN(L), hDiag(L);
+  std::vector<float2*> hD32(L, nullptr);
+  std::vector<double2> hcoef(L);
+  {
+    std::vector<double2*> out(L), diag0(L);
+    for (int l = 0; l < L; ++l) {
+      out[l] = gjA.p + (size_t)l * E;
+      diag0[l] = (double2*)dg.p + (size_t)S->lay[l].rowbase * NX;
+    }
+    chk(hipMemcpy(pA.p, out.data(), L * sizeof(double2*), hipMemcpyHostToDevice), "copy");
+    chk(hipMemcpy(pDiag.p, diag0.data(), L * sizeof(double2*), hipMemcpyHostToDevice), "copy");
+    chk(launch_init_delta(pA.p, (const double2* const*)pDiag.p, dw.p, de.p, L, NX, st), "init_delta");
+  }
+  for (int r = 0; r < S->Rmax && rc == PT_OK; ++r) {
+    std::vector<int> act;
+    for (int l = 0; l < L; ++l)
+      if (r < S->lay[l].R) act.push_back(l);
+    const int nb = (int)act.size();
+    for (int q = 0; q < nb; ++q) {
+      const int l = act[q];
+      double2* bufs[2] = {gjA.p + (size_t)l * E, gjB.p + (size_t)l * E};
+      hA[q] = bufs[cur[l]];
+      hB[q] = bufs[1 - cur[l]];
+    }
+    chk(hipMemcpyAsync(pA.p, hA.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(pB.p, hB.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    for (int k = 0; k < NX && rc == PT_OK; ++k) {
+      // even steps read pA and write pB, odd steps the reverse
+      if (k % 2 == 0)
+        chk(launch_gj_step(pA.p, pB.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
+      else
+        chk(launch_gj_step(pB.p, pA.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
+    }
+    chk(launch_gj_perm(perm.p, pi.p, nb, NX, st), "gj_perm");
+    // result is in pB if NX is odd, else in pA
+    const bool inB = (NX % 2) == 1;
+    std::vector<double2*> hRes(nb);
+    for (int q = 0; q < nb; ++q) {
+      const int l = act[q];
+      const Layer& y = S->lay[l];
+      double2* res = inB ? hB[q] : hA[q];
+      double2* other = inB ? hA[q] : hB[q];
+      hRes[q] = res;
+      hD[q] = S->dinv64.p + (size_t)(y.rowbase + r) * E;
+      if (r + 1 < y.R) {
+        hN[q] = other;
+        hDiag[q] = (double2*)dg.p + (size_t)(y.rowbase + r + 1) * NX;
+        const cd c = S->lcoef[y.rowbase + r + 1] * S->ucoef[y.rowbase + r];
+        hcoef[q] = d2(c);
+        cur[l] = (other == gjA.p + (size_t)l * E) ? 0 : 1;
+      } else {
+        hN[q] = nullptr;
+        hDiag[q] = nullptr;
+        hcoef[q] = make_double2(0.0, 0.0);
+      }
+    }
+    // pB may still be read by the last elimination steps: the copy is stream-ordered after them
+    chk(hipMemcpyAsync(pB.p, hRes.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(pD.p, hD.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(pN.p, hN.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(pDiag.p, hDiag.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(pD32.p, hD32.data(), nb * sizeof(float2*), hipMemcpyHostToDevice, st), "copy");
+    chk(hipMemcpyAsync(coef.p, hcoef.data(), nb * sizeof(double2), hipMemcpyHostToDevice, st), "copy");
+    chk(launch_finish_row(pB.p, pi.p, pD.p, pD32.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, nb,
+                          NX, st),
+        "finish_row");
+    // the host vectors are reused next row: wait for the copies
+    chk(hipStreamSynchronize(st), "sync");
+  }
+  int32_t flag = 0;
+  if (rc == PT_OK) chk(hipMemcpy(&flag, S->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+  cleanup();
+  if (rc == PT_OK && flag) rc = fail(PT_ESINGULAR, "zero pivot in a local Schur complement");
+  return rc;
+}
+
+pt_status extract_blocks(pt_solver* S) {
+  const int NX = S->NX, L = S->L;
+  const size_t E = S->block_elems();
+  hipStream_t st = S->st;
+  // block numbering
+  S->bidx.assign((size_t)L * 16, -1);
+  int nb = 0;
+  for (int l = 0; l < L; ++l) {
+    const bool top = S->lay[l].top_ext > 0, bot = S->lay[l].bot_ext > 0;
+    const bool has[4] = {top && bot, bot, top && bot, top};
+    for (int t = 0; t < 4; ++t)
+      if (has[t])
+        for (int ab = 0; ab < 4; ++ab) S->bidx[(l * 4 + t) * 4 + ab] = nb++;
+  }
+  S->nblk = nb;
+  HIPCHK(S->blk64.alloc((size_t)nb * E));
+  if (L == 1) return PT_OK;
+
+  int maxq = 0;
+  int maxR = 0;
+  for (auto& y : S->lay) {
+    maxq = std::max(maxq, (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0));
+    maxR = std::max(maxR, y.R);
+  }
+  DevBuf<double2> Wx, Bx;
+  DevBuf<int32_t> rows;
+  const size_t wel = (size_t)maxq * NX * maxR * NX;
+  pt_status rc = PT_OK;
+  if (Wx.alloc(wel) != hipSuccess || Bx.alloc(wel) != hipSuccess || rows.alloc(4) != hipSuccess) {
+    Wx.release();
+    Bx.release();
+    rows.release();
+    return fail(PT_ENOMEM, "extraction workspace");
+  }
+  const size_t saved_jobs = S->hjobs.size();
+  for (int l = 0; l < L && rc == PT_OK; ++l) {
+    const Layer& y = S->lay[l];
+    std::vector<int32_t> src;
+    if (y.top_ext) {
+      src.push_back(y.r0);
+      src.push_back(y.r1);
+    }
+    if (y.bot_ext) {
+      src.push_back(y.rn);
+      src.push_back(y.rn1);
+    }
+    const int nq = (int)src.size();
+    const int nrhs = nq * NX;
+    const int64_t ld = (int64_t)y.R * NX;
+    // per-layer local solve jobs (this layer only, rows from 0)
+    std::vector<std::vector<Job>> fw, bw;
+    build_local_jobs(S, {l}, {0}, fw, bw);
+    S->hjobs.resize(saved_jobs);
+    std::vector<Launch> lf, lb;
+    for (auto& v : fw) lf.push_back(push_launch(S, v));
+    for (auto& v : bw) lb.push_back(push_launch(S, v));
+    S->jobs.release();
+    if (S->jobs.alloc(S->hjobs.size()) != hipSuccess) {
+      rc = fail(PT_ENOMEM, "jobs");
+      break;
+    }
+    if (hipMemcpy(S->jobs.p, S->hjobs.data(), S->hjobs.size() * sizeof(Job), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(rows.p, src.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(PT_EHIP, "upload extraction jobs");
+      break;
+    }
+    // split-k scratch for these launches
+    size_t pneed = 0, cneed = 0;
+    for (auto* v : {&lf, &lb})
+      for (auto& Lc : *v) {
+        const ApplyGeom g = geom_for(NX, Lc.njobs, Lc.maxterms, nrhs);
+        pneed = std::max(pneed, part_need(g, Lc.njobs, nrhs));
+        cneed = std::max(cneed, counter_need(g, Lc.njobs, nrhs));
+      }
+    if (pneed > S->part.n) {
+      S->part.release();
+      if (S->part.alloc(pneed) != hipSuccess) {
+        rc = fail(PT_ENOMEM, "split-k scratch");
+        break;
+      }
+    }
+    if (cneed > S->counters.n) {
+      S->counters.release();
+      if (S->counters.alloc(cneed) != hipSuccess) {
+        rc = fail(PT_ENOMEM, "counters");
+        break;
+      }
+      if (hipMemset(S->counters.p, 0, cneed * sizeof(uint32_t)) != hipSuccess) {
+        rc = fail(PT_EHIP, "memset");
+        break;
+      }
+    }
+    if (launch_zero(Bx.p, (int64_t)nrhs * ld, st) != hipSuccess ||
+        launch_identity_rhs(Bx.p, rows.p, nq, NX, ld, st) != hipSuccess) {
+      rc = fail(PT_EHIP, "identity rhs");
+      break;
+    }
+    rc = run_local(S, lf, lb, nrhs, ld, Wx.p, Bx.p);
+    if (rc != PT_OK) break;
+    // pack the signed blocks (column q of the solve = source row src[q])
+    auto qof = [&](int row) {
+      for (int q = 0; q < nq; ++q)
+        if (src[q] == row) return q;
+      return -1;
+    };
+    struct P {
+      int type, a, b, trow, srow;
+      double sign, shift;
+    };
+    std::vector<P> packs;
+    if (y.top_ext && y.bot_ext) {
+      // T_dn = [[K_{n,1}, -K_{n,0}], [K_{n+1,1}, -K_{n+1,0}]]
+      packs.push_back({T_DN, 0, 0, y.rn, y.r1, 1, 0});
+      packs.push_back({T_DN, 0, 1, y.rn, y.r0, -1, 0});
+      packs.push_back({T_DN, 1, 0, y.rn1, y.r1, 1, 0});
+      packs.push_back({T_DN, 1, 1, y.rn1, y.r0, -1, 0});
+      // T_up = [[-K_{0,n+1}, K_{0,n}], [-K_{1,n+1}, K_{1,n}]]
+      packs.push_back({T_UP, 0, 0, y.r0, y.rn1, -1, 0});
+      packs.push_back({T_UP, 0, 1, y.r0, y.rn, 1, 0});
+      packs.push_back({T_UP, 1, 0, y.r1, y.rn1, -1, 0});
+      packs.push_back({T_UP, 1, 1, y.r1, y.rn, 1, 0});
+    }
+    if (y.bot_ext) {
+      // B_up - J0 = [[-K_{n,n+1} - I, K_{n,n}], [-K_{n+1,n+1}, K_{n+1,n}]]
+      packs.push_back({B_UP, 0, 0, y.rn, y.rn1, -1, -1});
+      packs.push_back({B_UP, 0, 1, y.rn, y.rn, 1, 0});
+      packs.push_back({B_UP, 1, 0, y.rn1, y.rn1, -1, 0});
+      packs.push_back({B_UP, 1, 1, y.rn1, y.rn, 1, 0});
+    }
+    if (y.top_ext) {
+      // B_dn - J1 = [[K_{0,1}, -K_{0,0}], [K_{1,1}, -K_{1,0} - I]]
+      packs.push_back({B_DN, 0, 0, y.r0, y.r1, 1, 0});
+      packs.push_back({B_DN, 0, 1, y.r0, y.r0, -1, 0});
+      packs.push_back({B_DN, 1, 0, y.r1, y.r1, 1, 0});
+      packs.push_back({B_DN, 1, 1, y.r1, y.r0, -1, -1});
+    }
+    for (const P& pk : packs) {
+      const int id = S->bidx[((l * 4 + pk.type) * 2 + pk.a) * 2 + pk.b];
+      if (launch_pack_block(Wx.p, ld, qof(pk.srow), pk.trow, NX, pk.sign, pk.shift, S->blk64.p + (size_t)id * E,
+                            nullptr, st) != hipSuccess) {
+        rc = fail(PT_EHIP, "pack_block");
+        break;
+      }
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && rc == PT_OK) rc = fail(PT_EHIP, "extraction sync");
+  }
+  S->hjobs.resize(saved_jobs);
+  Wx.release();
+  Bx.release();
+  rows.release();
+  return rc;
+}
+
+void build_online_jobs(pt_solver* S) {
+  const int L = S->L, NX = S->NX;
+  S->hjobs.clear();
+  // local solves over all layers of the (nrhs, sumR, NX) fields
+  {
+    std::vector<int> ls(L), rb(L);
+    for (int l = 0; l < L; ++l) {
+      ls[l] = l;
+      rb[l] = S->lay[l].rowbase;
+    }
+    std::vector<std::vector<Job>> fw, bw;
+    build_local_jobs(S, ls, rb, fw, bw);
+    S->fwd.clear();
+    S->bwd.clear();
+    for (auto& v : fw) S->fwd.push_back(push_launch(S, v));
+    for (auto& v : bw) S->bwd.push_back(push_launch(S, v));
+  }
+  if (L < 2) return;
+  const double2 one = make_double2(1.0, 0.0);
+  // Gauss-Seidel sweep step s: bases 0 = r (unused), 1 = previous iterate, 2 = current iterate.
+  //   d_k += T_dn(k) (d_{k-1} + a^prev_{k-1}),  k = s
+  //   a_k += T_up(k+1) (a_{k+1} + d^prev_{k+1}), k = L-2-s
+  S->sweep.clear();
+  for (int s = 1; s <= L - 2; ++s) {
+    std::vector<Job> js;
+    const int kd = s, ku = L - 2 - s;
+    for (int a = 0; a < 2; ++a) {
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(0, kd, a));
+      j.P = j.Y;
+      for (int b = 0; b < 2; ++b) add_term(j, S->blk(kd, T_DN, a, b), vr(2, S->seg(0, kd - 1, b)), vr(1, S->seg(1, kd - 1, b)), one);
+      js.push_back(j);
+    }
+    for (int a = 0; a < 2; ++a) {
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(1, ku, a));
+      j.P = j.Y;
+      for (int b = 0; b < 2; ++b)
+        add_term(j, S->blk(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
+      js.push_back(j);
+    }
+    S->sweep.push_back(push_launch(S, js));
+  }
+  // reflection terms of a Gauss-Seidel pass: cur = r + (B_up - J0) a^prev, r + (B_dn - J1) d^prev
+  {
+    std::vector<Job> js;
+    for (int k = 0; k <= L - 2; ++k)
+      for (int a = 0; a < 2; ++a) {
+        Job j = empty_job();
+        j.Y = vr(2, S->seg(0, k, a));
+        j.P = vr(0, S->seg(0, k, a));
+        for (int b = 0; b < 2; ++b) add_term(j, S->blk(k, B_UP, a, b), vr(1, S->seg(1, k, b)));
+        js.push_back(j);
+        Job u = empty_job();
+        u.Y = vr(2, S->seg(1, k, a));
+        u.P = vr(0, S->seg(1, k, a));
+        for (int b = 0; b < 2; ++b) add_term(u, S->blk(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
+        js.push_back(u);
+      }
+    S->bterm = push_launch(S, js);
+  }
+  // polarized operator y = A x (bases 0 = x, 2 = y) and y = R x
+  for (int which = 0; which < 2; ++which) {
+    std::vector<Job> js;
+    const bool isA = which == 0;
+    for (int k = 0; k <= L - 2; ++k)
+      for (int a = 0; a < 2; ++a) {
+        // down rows: d_k - T_dn(k)(d_{k-1} + a_{k-1}) - (B_up(k) - J0) a_k
+        Job j = empty_job();
+        j.Y = vr(2, S->seg(0, k, a));
+        j.P = isA ? vr(0, S->seg(0, k, a)) : none();
+        j.alpha = make_double2(-1.0, 0.0);
+        if (k >= 1)
+          for (int b = 0; b < 2; ++b)
+            add_term(j, S->blk(k, T_DN, a, b), isA ? vr(0, S->seg(0, k - 1, b)) : vr(0, S->seg(1, k - 1, b)),
+                     isA ? vr(0, S->seg(1, k - 1, b)) : none(), one);
+        for (int b = 0; b < 2; ++b) add_term(j, S->blk(k, B_UP, a, b), vr(0, S->seg(1, k, b)));
+        js.push_back(j);
+        // up rows: a_k - T_up(k+1)(a_{k+1} + d_{k+1}) - (B_dn(k+1) - J1) d_k
+        Job u = empty_job();
+        u.Y = vr(2, S->seg(1, k, a));
+        u.P = isA ? vr(0, S->seg(1, k, a)) : none();
+        u.alpha = make_double2(-1.0, 0.0);
+        if (k + 1 <= L - 2)
+          for (int b = 0; b < 2; ++b)
+            add_term(u, S->blk(k + 1, T_UP, a, b), isA ? vr(0, S->seg(1, k + 1, b)) : vr(0, S->seg(0, k + 1, b)),
+                     isA ? vr(0, S->seg(0, k + 1, b)) : none(), one);
+        for (int b = 0; b < 2; ++b) add_term(u, S->blk(k + 1, B_DN, a, b), vr(0, S->seg(0, k, b)));
+        js.push_back(u);
+      }
+    if (isA)
+      S->opA = push_launch(S, js);
+    else
+      S->opR = push_launch(S, js);
+  }
+  (void)NX;
+}
+
+pt_status alloc_online(pt_solver* S) {
+  const int nr = S->opt.max_nrhs;
+  const int m = S->opt.maxit;
+  const size_t loc = (size_t)nr * S->sumR * S->NX;
+  const size_t vol = (size_t)nr * S->NZ * S->NX;
+  const size_t tr = (size_t)nr * std::max<int64_t>(S->Nt, 1);
+  // split-k scratch: the largest launch at max_nrhs (and the nrhs used by fewer columns)
+  size_t pneed = S->part.n, cneed = S->counters.n;
+  std::vector<const Launch*> all;
+  for (auto& v : {&S->fwd, &S->bwd, &S->sweep})
+    for (auto& Lc : *v) all.push_back(&Lc);
+  all.push_back(&S->bterm);
+  all.push_back(&S->opA);
+  all.push_back(&S->opR);
+  for (const Launch* Lc : all) {
+    if (Lc->njobs == 0) continue;
+    for (int q = 1; q <= nr; q = (q < 16 ? q * 2 : q + 16)) {
+      const int qq = std::min(q, nr);
+      const ApplyGeom g = geom_for(S->NX, Lc->njobs, Lc->maxterms, qq);
+      pneed = std::max(pneed, part_need(g, Lc->njobs, qq));
+      cneed = std::max(cneed, counter_need(g, Lc->njobs, qq));
+    }
+    const ApplyGeom g = geom_for(S->NX, Lc->njobs, Lc->maxterms, nr);
+    pneed = std::max(pneed, part_need(g, Lc->njobs, nr));
+    cneed = std::max(cneed, counter_need(g, Lc->njobs, nr));
+  }
+  if (pneed > S->part.n) {
+    S->part.release();
+    HIPCHK(S->part.alloc(pneed));
+  }
+  if (cneed > S->counters.n) {
+    S->counters.release();
+    HIPCHK(S->counters.alloc(cneed));
+  }
+  HIPCHK(hipMemset(S->counters.p, 0, S->counters.n * sizeof(uint32_t)));
+  HIPCHK(S->W.alloc(loc));
+  HIPCHK(S->Bw.alloc(loc));
+  HIPCHK(S->fio.alloc(vol));
+  HIPCHK(S->uio.alloc(vol));
+  if (S->L >= 2) {
+    HIPCHK(S->s.alloc(tr));
+    HIPCHK(S->V.alloc(tr * (m + 1)));
+    HIPCHK(S->Z.alloc(tr * m));
+    HIPCHK(S->U1.alloc(tr));
+    HIPCHK(S->U2.alloc(tr));
+    HIPCHK(S->tmp.alloc(tr));
+    HIPCHK(S->zeros.alloc(tr));
+    HIPCHK(S->x.alloc(tr));
+    HIPCHK(hipMemset(S->zeros.p, 0, tr * sizeof(double2)));
+    HIPCHK(S->hbuf.alloc((size_t)(m + 1) * nr));
+    HIPCHK(S->hacc.alloc((size_t)(m + 1) * nr));
+    HIPCHK(S->Hc.alloc((size_t)nr * (m + 1) * m));
+    HIPCHK(S->sn.alloc((size_t)nr * m));
+    HIPCHK(S->g.alloc((size_t)nr * (m + 1)));
+    HIPCHK(S->y.alloc((size_t)nr * m));
+    HIPCHK(S->nrm.alloc(nr));
+    HIPCHK(S->cs.alloc((size_t)nr * m));
+    HIPCHK(S->est.alloc(nr));
+    HIPCHK(S->beta.alloc(nr));
+    HIPCHK(S->iters.alloc(nr));
+    HIPCHK(S->done.alloc(nr));
+    HIPCHK(hipHostMalloc((void**)&S->h_done, (size_t)nr * sizeof(int32_t), hipHostMallocDefault));
+  }
+  return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// online stages
+// ---------------------------------------------------------------------------
+// Gauss-Seidel preconditioner (Alg. 4): z = u^{n_it}, u^0 = 0,
+// u^{i+1} = D^-1 (v - R u^i), each pass fused into one reflection launch and
+// L-2 sweep launches.
+pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs) {
+  const int nit = S->opt.gs_iters;
+  const int64_t n = (int64_t)nrhs * S->Nt;
+  const int64_t ld = S->Nt;
+  if (nit == 0) {
+    HIPCHK(launch_copy(z, v, n, S->st));
+    return PT_OK;
+  }
+  double2* prev = S->zeros.p;
+  for (int p = 1; p <= nit; ++p) {
+    double2* cur = (p == nit) ? z : ((p % 2) ? S->U1.p : S->U2.p);
+    Bases b{{const_cast<double2*>(v), prev, cur, nullptr}};
+    if (p == 1) {
+      HIPCHK(launch_copy(cur, v, n, S->st));
+    } else {
+      PTCHK(run_apply(S, S->bterm, nrhs, ld, b));
+    }
+    for (const Launch& Lc : S->sweep) PTCHK(run_apply(S, Lc, nrhs, ld, b));
+    prev = cur;
+  }
+  return PT_OK;
+}
+
+pt_status apply_dinv(pt_solver* S, const double2* v, double2* z, int nrhs) {
+  HIPCHK(launch_copy(z, v, (int64_t)nrhs * S->Nt, S->st));
+  Bases b{{const_cast<double2*>(v), S->zeros.p, z, nullptr}};
+  for (const Launch& Lc : S->sweep) PTCHK(run_apply(S, Lc, nrhs, S->Nt, b));
+  return PT_OK;
+}
+
+pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y, int nrhs) {
+  Bases b{{const_cast<double2*>(x), nullptr, y, nullptr}};
+  return run_apply(S, op, nrhs, S->Nt, b);
+}
+
+// Newton potentials w^l = (A^l)^-1 h^2 f^l of every layer into S->W
+pt_status newton(pt_solver* S, const double2* f, int nrhs) {
+  HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
+  return run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
+}
+
+pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
+  PTCHK(newton(S, f, nrhs));
+  HIPCHK(launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX, S->Nt,
+                          nrhs, 0, S->st));
+  return PT_OK;
+}
+
+pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2* u, int nrhs) {
+  HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
+  if (S->L >= 2)
+    HIPCHK(launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
+                            S->Nt, nrhs, (int64_t)2 * (S->L - 1) * S->NX, S->st));
+  PTCHK(run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
+  HIPCHK(launch_gather_owned(S->W.p, u, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->st));
+  return PT_OK;
+}
+
+// Flexible GMRES (right preconditioning, classical Gram-Schmidt applied twice,
+// x0 = 0, no restart) on A x = s for nrhs independent right-hand sides.
+pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv) {
+  hipStream_t st = S->st;
+  const int64_t N = S->Nt;
+  const int m = S->opt.maxit;
+  const size_t vs = (size_t)nrhs * N;
+  HIPCHK(launch_knorm(S->s.p, S->beta.p, nrhs, N, st));
+  HIPCHK(launch_kscale(S->V.p, S->s.p, S->beta.p, nrhs, N, st));
+  HIPCHK(launch_kinit(S->g.p, S->beta.p, S->done.p, S->iters.p, S->est.p, m, nrhs, st));
+  all_conv = false;
+  for (int j = 0; j < m; ++j) {
+    double2* vj = S->V.p + (size_t)j * vs;
+    double2* zj = S->Z.p + (size_t)j * vs;
+    PTCHK(precondition(S, vj, zj, nrhs));
+    PTCHK(apply_op(S, S->opA, zj, S->tmp.p, nrhs));
+    HIPCHK(launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st));
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(launch_kdot(S->V.p, S->tmp.p, S->hbuf.p, j + 1, nrhs, N, st));
+      HIPCHK(launch_kupdate(S->V.p, S->tmp.p, S->hbuf.p, S->hacc.p, j + 1, nrhs, N, st));
+    }
+    HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, N, st));
+    HIPCHK(launch_kscale(S->V.p + (size_t)(j + 1) * vs, S->tmp.p, S->nrm.p, nrhs, N, st));
+    HIPCHK(launch_givens(S->Hc.p, S->hacc.p, S->nrm.p, S->cs.p, S->sn.p, S->g.p, S->est.p, S->beta.p, S->iters.p,
+                         S->done.p, S->opt.tol, j, m, nrhs, st));
+    HIPCHK(hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && S->h_done[r];
+    if (all) {
+      all_conv = true;
+      break;
+    }
+  }
+  HIPCHK(launch_ksolve(S->Hc.p, S->g.p, S->y.p, S->iters.p, m, nrhs, st));
+  HIPCHK(launch_kcombine(S->Z.p, S->y.p, S->iters.p, S->x.p, m, nrhs, N, st));
+  return PT_OK;
+}
+
+pt_status check_nrhs(const pt_solver* S, int nrhs) {
+  if (!S) return fail(PT_EINVAL, "null solver");
+  if (nrhs < 1 || nrhs > S->opt.max_nrhs) return fail(PT_EINVAL, "nrhs must be in 1..max_nrhs");
+  return PT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char* pt_status_str(pt_status st) {
+  switch (st) {
+    case PT_OK: return "ok";
+    case PT_EINVAL: return "invalid argument";
+    case PT_ENOMEM: return "out of device memory";
+    case PT_EHIP: return "HIP runtime error";
+    case PT_ESINGULAR: return "singular local factor";
+    case PT_ENOCONV: return "GMRES did not converge";
+  }
+  return "unknown status";
+}
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+void pt_free(pt_solver* S) {
+  if (!S) return;
+  (void)hipStreamSynchronize(S->st);
+  for (auto* b : {&S->dinv64, &S->blk64, &S->part, &S->W, &S->Bw, &S->fio, &S->uio, &S->s, &S->V, &S->Z, &S->U1,
+                  &S->U2, &S->tmp, &S->zeros, &S->x, &S->hbuf, &S->hacc, &S->Hc, &S->sn, &S->g, &S->y})
+    b->release();
+  S->dinv32.release();
+  S->blk32.release();
+  for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
+  for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag}) b->release();
+  S->counters.release();
+  S->jobs.release();
+  if (S->h_done) (void)hipHostFree(S->h_done);
+  for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
+  delete S;
+}
+
+pt_status pt_profile(pt_solver* S, int32_t enable) {
+  if (!S) return fail(PT_EINVAL, "null solver");
+  if (enable) {
+    if (S->ev.empty()) {
+      S->ev.resize(2 * kEventSlots);
+      for (auto& e : S->ev) HIPCHK(hipEventCreate(&e));
+    }
+    PTCHK(prof_harvest(S));
+    S->stats = pt_kernel_stats{};
+    S->prof = true;
+  } else {
+    PTCHK(prof_harvest(S));
+    S->prof = false;
+  }
+  return PT_OK;
+}
+
+pt_status pt_profile_read(pt_solver* S, pt_kernel_stats* out) {
+  if (!S || !out) return fail(PT_EINVAL, "null argument");
+  PTCHK(prof_harvest(S));
+  *out = S->stats;
+  return PT_OK;
+}
+
+pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stream, pt_solver** out) {
+  if (!out) return fail(PT_EINVAL, "null output pointer");
+  *out = nullptr;
+  PTCHK(validate(prob, opt));
+  const auto t0 = std::chrono::steady_clock::now();
+  pt_solver* S = new pt_solver();
+  S->nx = prob->nx;
+  S->nz = prob->nz;
+  S->npml = prob->npml;
+  S->NX = prob->nx + 2 * prob->npml;
+  S->NZ = prob->nz + 2 * prob->npml;
+  S->L = prob->L;
+  S->h = prob->h;
+  S->omega = prob->omega;
+  S->C = prob->pml_C;
+  S->opt = *opt;
+  S->f32 = false;
+  S->st = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&S->device);
+  make_layout(S);
+  const int NX = S->NX, NZ = S->NZ;
+  const double delta = S->npml * S->h;
+  const double h2w2 = S->h * S->h * S->omega * S->omega;
+
+  // x-direction alphas (global profile) and the tridiagonal couplings
+  std::vector<cd> ax(NX), axm(NX), axp(NX), west(NX), east(NX);
+  for (int i = 0; i < NX; ++i) {
+    const double p = i - S->npml + 1;
+    ax[i] = pml_alpha(beyond(p, S->nx) * S->h, S->C, delta, S->omega);
+    axm[i] = pml_alpha(beyond(p - 0.5, S->nx) * S->h, S->C, delta, S->omega);
+    axp[i] = pml_alpha(beyond(p + 0.5, S->nx) * S->h, S->C, delta, S->omega);
+    west[i] = i > 0 ? -(ax[i] * axm[i]) : cmk(0, 0);
+    east[i] = i < NX - 1 ? -(ax[i] * axp[i]) : cmk(0, 0);
+  }
+  // per local row: diagonal of A_r and the z couplings l_r (to r-1), u_r (to r+1)
+  std::vector<cd> diag((size_t)S->sumR * NX);
+  S->lcoef.assign(S->sumR, cmk(0, 0));
+  S->ucoef.assign(S->sumR, cmk(0, 0));
+  std::vector<int32_t> rowmap(S->sumR, -1);
+  for (int l = 0; l < S->L; ++l) {
+    const Layer& y = S->lay[l];
+    const std::vector<RowZ> rz = local_rows(S, y);
+    for (int r = 0; r < y.R; ++r) {
+      const int g = y.rowbase + r;
+      S->lcoef[g] = -(rz[r].a * rz[r].am);
+      S->ucoef[g] = -(rz[r].a * rz[r].ap);
+      const cd zz = rz[r].a * (rz[r].am + rz[r].ap);
+      for (int i = 0; i < NX; ++i) {
+        const double c = prob->c[(size_t)rz[r].mrow * NX + i];
+        const cd xx = ax[i] * (axm[i] + axp[i]);
+        diag[(size_t)g * NX + i] = xx + zz + cmk(-h2w2 / (c * c), 0.0);
+      }
+      if (r >= y.top_ext && r < y.top_ext + y.n) rowmap[g] = y.own_start + (r - y.top_ext);
+    }
+  }
+  (void)NZ;
+  pt_status rc = PT_OK;
+  auto bail = [&](pt_status s) {
+    pt_free(S);
+    return s;
+  };
+  if (S->flag.alloc(1) != hipSuccess) return bail(fail(PT_ENOMEM, "flag"));
+  if (S->dinv64.alloc((size_t)S->sumR * S->block_elems()) != hipSuccess)
+    return bail(fail(PT_ENOMEM, "local factors"));
+  if (S->rowmap.alloc(S->sumR) != hipSuccess ||
+      hipMemcpy(S->rowmap.p, rowmap.data(), S->sumR * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(PT_EHIP, "rowmap"));
+
+  rc = factorize(S, diag, west, east);
+  if (rc != PT_OK) return bail(rc);
+  rc = extract_blocks(S);
+  if (rc != PT_OK) return bail(rc);
+
+  // trace gather (s = W rows) and forcing (W rows += sign * t) maps
+  if (S->L >= 2) {
+    std::vector<int32_t> gs, gr, fs, fr;
+    std::vector<double> fsg;
+    for (int k = 0; k < S->L - 1; ++k) {
+      const Layer& up = S->lay[k];
+      const Layer& lo = S->lay[k + 1];
+      const int su[2] = {up.rowbase + up.rn, up.rowbase + up.rn1};
+      const int sl[2] = {lo.rowbase + lo.r0, lo.rowbase + lo.r1};
+      for (int a = 0; a < 2; ++a) {
+        gs.push_back((0 * (S->L - 1) + k) * 2 + a);
+        gr.push_back(su[a]);
+        gs.push_back((1 * (S->L - 1) + k) * 2 + a);
+        gr.push_back(sl[a]);
+      }
+      // layer k (bottom interface k): - e_{n+1} t_0 + e_n t_1
+      fs.push_back(k * 2 + 0);
+      fr.push_back(su[1]);
+      fsg.push_back(-1.0);
+      fs.push_back(k * 2 + 1);
+      fr.push_back(su[0]);
+      fsg.push_back(1.0);
+      // layer k+1 (top interface k): + e_1 t_0 - e_0 t_1
+      fs.push_back(k * 2 + 0);
+      fr.push_back(sl[1]);
+      fsg.push_back(1.0);
+      fs.push_back(k * 2 + 1);
+      fr.push_back(sl[0]);
+      fsg.push_back(-1.0);
+    }
+    S->n_gather = (int)gs.size();
+    S->n_force = (int)fs.size();
+    if (S->g_seg.alloc(gs.size()) != hipSuccess || S->g_row.alloc(gr.size()) != hipSuccess ||
+        S->f_seg.alloc(fs.size()) != hipSuccess || S->f_row.alloc(fr.size()) != hipSuccess ||
+        S->f_sign.alloc(fsg.size()) != hipSuccess)
+      return bail(fail(PT_ENOMEM, "trace maps"));
+    if (hipMemcpy(S->g_seg.p, gs.data(), gs.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->g_row.p, gr.data(), gr.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->f_seg.p, fs.data(), fs.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->f_row.p, fr.data(), fr.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->f_sign.p, fsg.data(), fsg.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(PT_EHIP, "trace maps"));
+  }
+
+  // reduced-precision copies of the factors and blocks
+  if (opt->precision == PT_F32) {
+    if (S->dinv32.alloc(S->dinv64.n) != hipSuccess || S->blk32.alloc(S->blk64.n) != hipSuccess)
+      return bail(fail(PT_ENOMEM, "float32 copies"));
+    if (launch_to_f32(S->dinv32.p, S->dinv64.p, (int64_t)S->dinv64.n, S->st) != hipSuccess ||
+        (S->blk64.n && launch_to_f32(S->blk32.p, S->blk64.p, (int64_t)S->blk64.n, S->st) != hipSuccess) ||
+        hipStreamSynchronize(S->st) != hipSuccess)
+      return bail(fail(PT_EHIP, "float32 conversion"));
+    S->dinv64.release();
+    S->blk64.release();
+    S->f32 = true;
+  }
+
+  build_online_jobs(S);
+  S->jobs.release();
+  if (S->jobs.alloc(S->hjobs.size()) != hipSuccess ||
+      hipMemcpy(S->jobs.p, S->hjobs.data(), S->hjobs.size() * sizeof(Job), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(PT_ENOMEM, "jobs"));
+  rc = alloc_online(S);
+  if (rc != PT_OK) return bail(rc);
+  if (hipStreamSynchronize(S->st) != hipSuccess) return bail(fail(PT_EHIP, "setup sync"));
+  S->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = S;
+  return PT_OK;
+}
+
+pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
+  if (!S || !o) return fail(PT_EINVAL, "null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->NX = S->NX;
+  o->NZ = S->NZ;
+  o->L = S->L;
+  o->sumR = S->sumR;
+  o->ntrace = S->Nt;
+  for (int l = 0; l < std::min(S->L, 64); ++l) {
+    o->R[l] = S->lay[l].R;
+    o->own_start[l] = S->lay[l].own_start;
+    o->n_own[l] = S->lay[l].n;
+    o->top_ext[l] = S->lay[l].top_ext;
+    o->bot_ext[l] = S->lay[l].bot_ext;
+  }
+  o->setup_ms = S->setup_ms;
+  const size_t es = S->f32 ? sizeof(float2) : sizeof(double2);
+  o->block_bytes = (int64_t)S->nblk * S->block_elems() * es;
+  o->factor_bytes = (int64_t)S->sumR * S->block_elems() * es;
+  return PT_OK;
+}
+
+pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, double* out) {
+  if (!S || !out) return fail(PT_EINVAL, "null argument");
+  if (layer < 0 || layer >= S->L || j < 0 || j > 3 || k < 0 || k > 3) return fail(PT_EINVAL, "bad block index");
+  // K_{j,k} = sign * block(type, a, b) + shift I (inverse of the packing in extract_blocks)
+  static const int T[4][4] = {{B_DN, B_DN, T_UP, T_UP}, {B_DN, B_DN, T_UP, T_UP}, {T_DN, T_DN, B_UP, B_UP},
+                              {T_DN, T_DN, B_UP, B_UP}};
+  // (a, b, sign, shift) for each (j, k); rows: j in {0,1,n,n+1}, cols: k
+  struct E {
+    int a, b;
+    double sign, shift;
+  };
+  static const E M[4][4] = {
+      {{0, 1, -1, 0}, {0, 0, 1, 0}, {0, 1, 1, 0}, {0, 0, -1, 0}},
+      {{1, 1, -1, -1}, {1, 0, 1, 0}, {1, 1, 1, 0}, {1, 0, -1, 0}},
+      {{0, 1, -1, 0}, {0, 0, 1, 0}, {0, 1, 1, 0}, {0, 0, -1, -1}},
+      {{1, 1, -1, 0}, {1, 0, 1, 0}, {1, 1, 1, 0}, {1, 0, -1, 0}},
+  };
+  const int type = T[j][k];
+  const E e = M[j][k];
+  const int id = S->bidx[((layer * 4 + type) * 2 + e.a) * 2 + e.b];
+  if (id < 0) return fail(PT_EINVAL, "layer has no such trace rows");
+  const size_t n = S->block_elems();
+  std::vector<double2> col(n);
+  if (S->f32) {
+    std::vector<float2> tmp(n);
+    HIPCHK(hipMemcpy(tmp.data(), S->blk32.p + (size_t)id * n, n * sizeof(float2), hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < n; ++q) col[q] = make_double2(tmp[q].x, tmp[q].y);
+  } else {
+    HIPCHK(hipMemcpy(col.data(), S->blk64.p + (size_t)id * n, n * sizeof(double2), hipMemcpyDeviceToHost));
+  }
+  const int NX = S->NX;
+  for (int c = 0; c < NX; ++c)
+    for (int i = 0; i < NX; ++i) {
+      double2 v = col[(size_t)c * NX + i];
+      if (i == c) v.x -= e.shift;  // block = sign*K + shift*I  =>  K = sign*(block - shift*I)
+      out[2 * ((size_t)i * NX + c)] = e.sign * v.x;
+      out[2 * ((size_t)i * NX + c) + 1] = e.sign * v.y;
+    }
+  return PT_OK;
+}
+
+pt_status pt_apply(pt_solver* S, int32_t op, int32_t nrhs, const double* x, double* y, int32_t on_device) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
+  if (!x || !y) return fail(PT_EINVAL, "null vector");
+  const size_t n = (size_t)nrhs * S->Nt;
+  const double2* xd = (const double2*)x;
+  double2* yd = (double2*)y;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->U2.p, x, n * sizeof(double2), hipMemcpyHostToDevice, S->st));
+    xd = S->U2.p;
+    yd = S->tmp.p;
+  }
+  switch (op) {
+    case PT_OP_A: PTCHK(apply_op(S, S->opA, xd, yd, nrhs)); break;
+    case PT_OP_R: PTCHK(apply_op(S, S->opR, xd, yd, nrhs)); break;
+    case PT_OP_DINV: PTCHK(apply_dinv(S, xd, yd, nrhs)); break;
+    case PT_OP_PRECOND: {
+      // the preconditioner uses U1/U2 internally: stage the input in s
+      HIPCHK(hipMemcpyAsync(S->s.p, xd, n * sizeof(double2), hipMemcpyDeviceToDevice, S->st));
+      PTCHK(precondition(S, S->s.p, yd, nrhs));
+      break;
+    }
+    default: return fail(PT_EINVAL, "unknown operator");
+  }
+  if (!on_device) HIPCHK(hipMemcpyAsync(y, yd, n * sizeof(double2), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
+}
+
+pt_status pt_local_solve(pt_solver* S, int32_t nrhs, const double* b, double* x, int32_t on_device) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (!b || !x) return fail(PT_EINVAL, "null field");
+  const size_t n = (size_t)nrhs * S->sumR * S->NX;
+  HIPCHK(hipMemcpyAsync(S->Bw.p, b, n * sizeof(double2), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        S->st));
+  PTCHK(run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
+  HIPCHK(hipMemcpyAsync(x, S->W.p, n * sizeof(double2), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
+}
+
+pt_status pt_trace_rhs(pt_solver* S, int32_t nrhs, const double* f, double* out, int32_t on_device) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
+  if (!f || !out) return fail(PT_EINVAL, "null field");
+  const size_t nv = (size_t)nrhs * S->NZ * S->NX, nt = (size_t)nrhs * S->Nt;
+  const double2* fd = (const double2*)f;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->fio.p, f, nv * sizeof(double2), hipMemcpyHostToDevice, S->st));
+    fd = S->fio.p;
+  }
+  double2* sd = on_device ? (double2*)out : S->s.p;
+  PTCHK(trace_rhs(S, fd, sd, nrhs));
+  if (!on_device) HIPCHK(hipMemcpyAsync(out, sd, nt * sizeof(double2), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
+}
+
+pt_status pt_reconstruct(pt_solver* S, int32_t nrhs, const double* f, const double* x, double* u, int32_t on_device) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (!f || !u || (S->L >= 2 && !x)) return fail(PT_EINVAL, "null field");
+  const size_t nv = (size_t)nrhs * S->NZ * S->NX, nt = (size_t)nrhs * S->Nt;
+  const double2* fd = (const double2*)f;
+  const double2* xd = (const double2*)x;
+  double2* ud = (double2*)u;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->fio.p, f, nv * sizeof(double2), hipMemcpyHostToDevice, S->st));
+    fd = S->fio.p;
+    if (S->L >= 2) {
+      HIPCHK(hipMemcpyAsync(S->x.p, x, nt * sizeof(double2), hipMemcpyHostToDevice, S->st));
+      xd = S->x.p;
+    }
+    ud = S->uio.p;
+  }
+  PTCHK(reconstruct(S, fd, xd, ud, nrhs));
+  if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
+}
+
+pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32_t on_device, pt_rhs_info* info) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (!f || !u) return fail(PT_EINVAL, "null field");
+  const size_t nv = (size_t)nrhs * S->NZ * S->NX;
+  const double2* fd = (const double2*)f;
+  double2* ud = (double2*)u;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->fio.p, f, nv * sizeof(double2), hipMemcpyHostToDevice, S->st));
+    fd = S->fio.p;
+    ud = S->uio.p;
+  }
+  bool conv = true;
+  if (S->L == 1) {
+    // one layer: the local solve is the global solve
+    PTCHK(reconstruct(S, fd, nullptr, ud, nrhs));
+  } else {
+    PTCHK(trace_rhs(S, fd, S->s.p, nrhs));
+    PTCHK(fgmres(S, nrhs, conv));
+    PTCHK(reconstruct(S, fd, S->x.p, ud, nrhs));
+  }
+  if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, S->st));
+  if (info) {
+    if (S->L == 1) {
+      for (int r = 0; r < nrhs; ++r) info[r] = pt_rhs_info{0, 1, 0.0, 0.0};
+    } else {
+      // true residual ||s - A x|| / ||s|| in float64
+      PTCHK(apply_op(S, S->opA, S->x.p, S->tmp.p, nrhs));
+      HIPCHK(launch_add(S->tmp.p, S->s.p, S->tmp.p, -1.0, (int64_t)nrhs * S->Nt, S->st));
+      HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, S->Nt, S->st));
+      std::vector<double> nr(nrhs), be(nrhs), es(nrhs);
+      std::vector<int32_t> it(nrhs), dn(nrhs);
+      HIPCHK(hipMemcpyAsync(nr.data(), S->nrm.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(be.data(), S->beta.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(es.data(), S->est.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(it.data(), S->iters.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(dn.data(), S->done.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipStreamSynchronize(S->st));
+      for (int r = 0; r < nrhs; ++r)
+        info[r] = pt_rhs_info{it[r], dn[r], es[r], be[r] > 0 ? nr[r] / be[r] : 0.0};
+    }
+  }
+  HIPCHK(hipStreamSynchronize(S->st));
+  return conv ? PT_OK : fail(PT_ENOCONV, "GMRES reached maxit before tol");
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libpolar (include/polar.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Arrays may be NumPy complex128 arrays (host; the library copies and
+synchronises) or torch complex128 CUDA tensors on the solver's device
+(on_device; results are written in place of a tensor this module allocates
+on the same device).  The library must be built (paper_1410_5910_amd.build);
+importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolar.so")
+
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESINGULAR, PT_ENOCONV = range(6)
+PT_F64, PT_F32 = 0, 1
+OP_A, OP_R, OP_DINV, OP_PRECOND = 0, 1, 2, 3
+ROWS = {"0": 0, "1": 1, "n": 2, "n+1": 3}
+
+EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", "pt_get_layout", "pt_get_block",
+           "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct", "pt_profile", "pt_profile_read")
+
+
+class PtProblem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nz", C.c_int32), ("npml", C.c_int32), ("h", C.c_double),
+                ("omega", C.c_double), ("pml_C", C.c_double), ("L", C.c_int32), ("c", C.POINTER(C.c_double))]
+
+
+class PtOptions(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("gs_iters", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
+                ("max_nrhs", C.c_int32)]
+
+
+class PtRhsInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("est", C.c_double), ("relres", C.c_double)]
+
+
+class PtLayout(C.Structure):
+    _fields_ = [("NX", C.c_int32), ("NZ", C.c_int32), ("L", C.c_int32), ("sumR", C.c_int32), ("ntrace", C.c_int64),
+                ("R", C.c_int32 * 64), ("own_start", C.c_int32 * 64), ("n_own", C.c_int32 * 64),
+                ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
+                ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64)]
+
+
+class PtKernelStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("kernel_ms", C.c_double), ("alg_bytes", C.c_double),
+                ("alg_flops", C.c_double)]
+
+
+class PolarError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libpolar status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libpolar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: when torch is present, load it first so that
+        # libpolar's libamdhip64.so.7 dependency resolves to the runtime torch uses.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1410_5910_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dp = C.c_void_p, C.c_int32, C.POINTER(C.c_double)
+        L.pt_setup.argtypes = [C.POINTER(PtProblem), C.POINTER(PtOptions), vp, C.POINTER(vp)]
+        L.pt_solve.argtypes = [vp, i32, vp, vp, i32, C.POINTER(PtRhsInfo)]
+        L.pt_free.argtypes = [vp]
+        L.pt_free.restype = None
+        L.pt_status_str.argtypes = [i32]
+        L.pt_status_str.restype = C.c_char_p
+        L.pt_last_error.argtypes = []
+        L.pt_last_error.restype = C.c_char_p
+        L.pt_get_layout.argtypes = [vp, C.POINTER(PtLayout)]
+        L.pt_get_block.argtypes = [vp, i32, i32, i32, dp]
+        L.pt_apply.argtypes = [vp, i32, i32, vp, vp, i32]
+        L.pt_local_solve.argtypes = [vp, i32, vp, vp, i32]
+        L.pt_trace_rhs.argtypes = [vp, i32, vp, vp, i32]
+        L.pt_reconstruct.argtypes = [vp, i32, vp, vp, vp, i32]
+        L.pt_profile.argtypes = [vp, i32]
+        L.pt_profile_read.argtypes = [vp, C.POINTER(PtKernelStats)]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is C.c_int:  # default
+                f.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=()):
+    if st != PT_OK and st not in allow:
+        raise PolarError(st, lib().pt_last_error().decode())
+    return st
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class Solver:
+    """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
+
+    def __init__(self, nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
+                 max_nrhs=1, stream=None):
+        self._lib = lib()
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        NX, NZ = nx + 2 * npml, nz + 2 * npml
+        if c.size != NX * NZ:
+            raise ValueError(f"c must have (nz+2npml)*(nx+2npml) = {NZ * NX} values")
+        self._c = c
+        prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
+                         c.ctypes.data_as(C.POINTER(C.c_double)))
+        prec = {"f64": PT_F64, "f32": PT_F32}[precision]
+        opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs))
+        h_ = C.c_void_p()
+        _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
+        self._h = h_
+        self.NX, self.NZ, self.L = NX, NZ, int(L)
+        self.max_nrhs = int(max_nrhs)
+        lay = self.layout()
+        self.sumR = lay["sumR"]
+        self.ntrace = lay["ntrace"]
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        """Build from any object with nx, nz, npml, h, omega, C, L, c attributes."""
+        return cls(prob.nx, prob.nz, prob.npml, prob.h, prob.omega, prob.C, prob.L, prob.c, **kw)
+
+    # ----------------------------------------------------------------- admin
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pt_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self) -> dict:
+        o = PtLayout()
+        _check(self._lib.pt_get_layout(self._h, C.byref(o)))
+        L = o.L
+        return {"NX": o.NX, "NZ": o.NZ, "L": L, "sumR": o.sumR, "ntrace": o.ntrace, "R": list(o.R[:L]),
+                "own_start": list(o.own_start[:L]), "n_own": list(o.n_own[:L]), "top_ext": list(o.top_ext[:L]),
+                "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
+                "factor_bytes": o.factor_bytes}
+
+    def profile(self, enable: bool):
+        """Start (reset) / stop recording HIP events around every block-apply launch."""
+        _check(self._lib.pt_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        o = PtKernelStats()
+        _check(self._lib.pt_profile_read(self._h, C.byref(o)))
+        return {"launches": o.launches, "kernel_ms": o.kernel_ms, "alg_bytes": o.alg_bytes, "alg_flops": o.alg_flops}
+
+    def get_block(self, layer: int, j: str, k: str) -> np.ndarray:
+        """K^layer_{j,k} (NX x NX, rows: target x) for j, k in {'0', '1', 'n', 'n+1'}."""
+        out = np.empty((self.NX, self.NX), dtype=np.complex128)
+        _check(self._lib.pt_get_block(self._h, layer, ROWS[j], ROWS[k],
+                                      out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    # -------------------------------------------------------------- marshalling
+    def _prep(self, a, shape_tail):
+        """-> (pointer, on_device, array kept alive, nrhs)"""
+        if _is_torch(a):
+            import torch
+            if not a.is_cuda:
+                a = a.numpy()
+            else:
+                if a.dtype != torch.complex128:
+                    raise TypeError("device arrays must be complex128")
+                a = a.contiguous()
+                n = a.numel() // int(np.prod(shape_tail))
+                return C.c_void_p(a.data_ptr()), 1, a, n
+        a = np.ascontiguousarray(a, dtype=np.complex128)
+        n = a.size // int(np.prod(shape_tail))
+        return C.c_void_p(a.ctypes.data), 0, a, n
+
+    def _out(self, like, on_device, shape):
+        if on_device:
+            import torch
+            return torch.empty(shape, dtype=torch.complex128, device=like.device)
+        return np.empty(shape, dtype=np.complex128)
+
+    @staticmethod
+    def _ptr(a, on_device):
+        return C.c_void_p(a.data_ptr()) if on_device else C.c_void_p(a.ctypes.data)
+
+    # ------------------------------------------------------------------ online
+    def solve(self, f):
+        """u = H^{-1} f for f of shape (nrhs, NZ, NX) or (NZ, NX).  Returns (u, info list)."""
+        single = f.ndim == 2
+        p, dev, keep, n = self._prep(f, (self.NZ, self.NX))
+        u = self._out(keep, dev, (n, self.NZ, self.NX))
+        info = (PtRhsInfo * n)()
+        _check(self._lib.pt_solve(self._h, n, p, self._ptr(u, dev), dev, info), allow=(PT_ENOCONV,))
+        infos = [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres} for i in info]
+        return (u[0] if single else u), infos
+
+    def apply(self, op: int, x):
+        """y = op(x) for polarized vectors x (nrhs, 2, L-1, 2, NX)."""
+        p, dev, keep, n = self._prep(x, (self.ntrace,))
+        y = self._out(keep, dev, (n, 2, self.L - 1, 2, self.NX))
+        _check(self._lib.pt_apply(self._h, op, n, p, self._ptr(y, dev), dev))
+        return y
+
+    def local_solve(self, b):
+        """x = (A^l)^{-1} b on layer-local fields (nrhs, sumR, NX)."""
+        p, dev, keep, n = self._prep(b, (self.sumR * self.NX,))
+        x = self._out(keep, dev, (n, self.sumR, self.NX))
+        _check(self._lib.pt_local_solve(self._h, n, p, self._ptr(x, dev), dev))
+        return x
+
+    def trace_rhs(self, f):
+        p, dev, keep, n = self._prep(f, (self.NZ, self.NX))
+        s = self._out(keep, dev, (n, 2, self.L - 1, 2, self.NX))
+        _check(self._lib.pt_trace_rhs(self._h, n, p, self._ptr(s, dev), dev))
+        return s
+
+    def reconstruct(self, f, x):
+        pf, dev, kf, n = self._prep(f, (self.NZ, self.NX))
+        px, dev2, kx, _ = self._prep(x, (self.ntrace,))
+        if dev != dev2:
+            raise TypeError("f and x must both be host or both device arrays")
+        u = self._out(kf, dev, (n, self.NZ, self.NX))
+        _check(self._lib.pt_reconstruct(self._h, n, pf, px, self._ptr(u, dev), dev))
+        return u

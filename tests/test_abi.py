@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every entry point include/polar.h declares (CPU only),
+and host-side validation rejects invalid problems before touching the GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "polar.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("pt_setup", "pt_solve", "pt_free", "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct",
+              "pt_get_block", "pt_get_layout", "pt_status_str", "pt_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    P = pytest.importorskip("paper_1410_5910_amd")
+    L = P.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert L.pt_status_str(0) == b"ok"
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(L=50), "physical rows"),
+    (dict(omega=-1.0), "omega"),
+    (dict(h=0.0), "h and omega"),
+    (dict(npml=0), "npml"),
+    (dict(C=-1.0), "pml_C"),
+])
+def test_invalid_problems_rejected(change, msg):
+    P = pytest.importorskip("paper_1410_5910_amd")
+    prob, f = synth.config_small(nx=12, nz=16, npml=3, L=2)
+    kw = dict(nx=prob.nx, nz=prob.nz, npml=prob.npml, h=prob.h, omega=prob.omega, C_pml=prob.C, L=prob.L, c=prob.c)
+    if "C" in change:
+        kw["C_pml"] = change.pop("C")
+    kw.update(change)
+    if kw["npml"] != prob.npml:
+        kw["c"] = np.ones(((prob.nz + 2 * kw["npml"]), (prob.nx + 2 * kw["npml"])))
+    with pytest.raises(P.PolarError) as e:
+        P.Solver(**kw)
+    assert e.value.status == 1 and msg in str(e.value)
+
+
+def test_nonpositive_velocity_rejected():
+    P = pytest.importorskip("paper_1410_5910_amd")
+    prob, f = synth.config_small(nx=12, nz=16, npml=3, L=2)
+    c = prob.c.copy()
+    c[3, 4] = 0.0
+    with pytest.raises(P.PolarError) as e:
+        P.Solver(prob.nx, prob.nz, prob.npml, prob.h, prob.omega, prob.C, prob.L, c)
+    assert e.value.status == 1

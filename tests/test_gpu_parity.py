@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle, stage by stage and end to end.
+
+Tolerances: float64 stages agree with the oracle to ~1e-11 relative (the two
+sides differ only in rounding order: sparse LU vs dense Schur inverses);
+full solves match the direct solve to <= 1e-8 relative L2 over the whole
+padded grid at GMRES tol 1e-10 (the float64 bar).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.direct import DirectSolver
+from oracle.polarized import PolarizedSolver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1410_5910_amd")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small():
+    # NX = 34 (< 64: one ragged row tile), nz = 31 split 11/10/10 (uneven layers)
+    prob, f = synth.config_small(nx=24, nz=31, npml=5, L=3, nrhs=3, seed=21)
+    _flush(f"[gpu] setup small {prob.name}")
+    gs = P.Solver.from_problem(prob, max_nrhs=20, tol=1e-12, maxit=40)
+    ps = PolarizedSolver(prob)
+    return prob, f, gs, ps
+
+
+def test_layout_matches_oracle(small):
+    prob, f, gs, ps = small
+    lay = gs.layout()
+    assert lay["L"] == ps.L
+    for l, s in enumerate(ps.slabs):
+        assert (lay["own_start"][l], lay["n_own"][l], lay["top_ext"][l], lay["bot_ext"][l], lay["R"][l]) == \
+            (s.own_start, s.n, s.top_ext, s.bot_ext, s.R)
+
+
+def test_trace_blocks(small):
+    prob, f, gs, ps = small
+    for l, lp in enumerate(ps.loc):
+        for (j, k), K in lp.K.items():
+            Kg = gs.get_block(l, j, k)
+            assert rel(Kg, K) < 1e-10, (l, j, k, rel(Kg, K))
+
+
+def _random_local(ps, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    sumR = sum(s.R for s in ps.slabs)
+    return rng.standard_normal((nrhs, sumR, ps.NX)) + 1j * rng.standard_normal((nrhs, sumR, ps.NX))
+
+
+def test_local_solve(small):
+    prob, f, gs, ps = small
+    for nrhs in (1, 3, 20):
+        b = _random_local(ps, nrhs, nrhs)
+        x = gs.local_solve(b)
+        r0 = 0
+        for lp in ps.loc:
+            R = lp.slab.R
+            ref = lp.solve(b[:, r0:r0 + R])
+            assert rel(x[:, r0:r0 + R], ref) < 1e-10, (nrhs, lp.slab.index)
+            r0 += R
+
+
+def test_trace_rhs(small):
+    prob, f, gs, ps = small
+    s = gs.trace_rhs(f)
+    ref = ps.rhs(ps.newton(f))
+    assert rel(s, ref) < 1e-10
+
+
+@pytest.mark.parametrize("op", ["A", "R", "Dinv", "precond"])
+def test_operators(small, op):
+    prob, f, gs, ps = small
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(ps.zeros(5).shape) + 1j * rng.standard_normal(ps.zeros(5).shape)
+    code = {"A": P.OP_A, "R": P.OP_R, "Dinv": P.OP_DINV, "precond": P.OP_PRECOND}[op]
+    y = gs.apply(code, x)
+    ref = {"A": ps.apply_A, "R": ps.apply_R, "Dinv": ps.apply_D_inv, "precond": ps.precondition}[op](x)
+    assert rel(y, ref) < 1e-10, rel(y, ref)
+
+
+def test_reconstruct(small):
+    prob, f, gs, ps = small
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(ps.zeros(3).shape) + 1j * rng.standard_normal(ps.zeros(3).shape)
+    u = gs.reconstruct(f, x)
+    assert rel(u, ps.reconstruct(f, x)) < 1e-10
+
+
+def test_solve_small_matches_direct(small):
+    prob, f, gs, ps = small
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    assert rel(u, ud) < 1e-8
+    for i in info:
+        assert i["converged"] and i["relres"] < 1e-10
+    # per-RHS results do not depend on the batch they were solved in
+    u1, _ = gs.solve(f[1:2])
+    assert rel(u1[0], u[1]) < 1e-10
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_solve_edge_layer_counts(L):
+    prob, f = synth.config_small(nx=20, nz=24, npml=4, L=L, nrhs=2, seed=30 + L)
+    _flush(f"[gpu] edge L={L}")
+    gs = P.Solver.from_problem(prob, max_nrhs=2, tol=1e-12)
+    u, info = gs.solve(f)
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+    gs.close()
+
+
+def test_zero_source_gives_zero_field(small):
+    prob, f, gs, ps = small
+    u, info = gs.solve(np.zeros_like(f[:1]))
+    assert np.all(u == 0)
+    assert info[0]["iters"] == 0
+
+
+def test_config1_full_solve():
+    prob, f = synth.config1()
+    _flush("[gpu] config1 constant-100x100-L4")
+    gs = P.Solver.from_problem(prob, tol=1e-10)
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    assert rel(u, ud) < 1e-8, rel(u, ud)
+    assert info[0]["converged"]
+    gs.close()
+
+
+def test_device_arrays_roundtrip(small):
+    torch = pytest.importorskip("torch")
+    prob, f, gs, ps = small
+    fd = torch.from_numpy(f).to("cuda")
+    ud, info = gs.solve(fd)
+    uh, _ = gs.solve(f)
+    assert rel(ud.cpu().numpy(), uh) < 1e-14
+
+
+def test_bad_nrhs_is_rejected(small):
+    prob, f, gs, ps = small
+    with pytest.raises(P.PolarError):
+        gs.solve(np.zeros((21, prob.NZ, prob.NX), dtype=complex))
