@@ -8,12 +8,12 @@
 // layer's forward/backward block sweep with the stored inverse Schur
 // complements, one step of the down/up Gauss-Seidel sweeps through the
 // transfer blocks, the reflection terms, and the polarized operator itself.
-// The matrices are streamed from HBM once per launch: each lane of a wave
-// owns one matrix row and walks the columns of a column-major block, so a
-// wave reads 64 consecutive complex entries (1 KiB) per column; the input
-// vector slice is staged in LDS; work is split along the columns across
-// workgroups with a deterministic last-arriving-workgroup reduction.
+// The matrices are streamed from HBM once per launch (column-major blocks,
+// coalesced along rows), the input slice is staged in LDS, and every
+// reduction happens inside one workgroup in a fixed order.
 #include "polar_kernels.h"
+
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <type_traits>
@@ -69,97 +69,227 @@ struct MatT<true> {
 };
 
 // ----------------------------------------------------------------------------
-// block_apply
+// block_apply, few right-hand sides (NR <= 4): the HBM-streaming form
 // ----------------------------------------------------------------------------
-// grid.x = njobs * ntiles * ksplit, grid.y = ceil(nrhs / NR); 256 threads.
-// Dynamic LDS: max(kc, 128) * NR complex (accumulator type): staged inputs, then the
-// cross-wave reduction.
+// Blocks are stored row-major, so every output row is a contiguous stream.
+// One workgroup = kGvWaves waves = kGvWaves output rows (one per wave) over
+// the job's full column range; lane l of a wave reads columns l, l+64, ...
+// of its row, i.e. one contiguous 1 KiB segment per load instruction for
+// float64.  The row's partial sums are reduced by a fixed butterfly of
+// cross-lane shuffles, so no cross-workgroup reduction, atomic or fence is
+// needed and results are deterministic.  The first group of matrix loads of
+// every lane is issued before the input slice is staged in LDS, so its
+// latency overlaps the staging.
+constexpr int kGvWaves = 8;                 // rows per workgroup
+constexpr int kGvThreads = kGvWaves * 64;
+constexpr int kGvU = 8;                     // loads in flight per lane and group
+
+template <typename MV>
+__device__ __forceinline__ const MV* term_row(const Job& J, int t, int row, int n) {
+  return reinterpret_cast<const MV*>(t == 0 ? J.M[0] : t == 1 ? J.M[1] : t == 2 ? J.M[2] : J.M[3]) +
+         (size_t)row * n;
+}
+
 template <int NR, bool F32>
-__global__ __launch_bounds__(kThreads) void block_apply_kernel(const Job* __restrict__ jobs, int njobs,
-                                                               ApplyGeom g, int nrhs, int64_t ld, Bases bases,
-                                                               double2* __restrict__ part,
-                                                               uint32_t* __restrict__ counters) {
+__global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+                                                                int kc, int nrhs, int64_t ld, Bases bases) {
   using MV = typename MatT<F32>::vec;
   using T = typename MatT<F32>::real;
   extern __shared__ unsigned char smem_raw[];
-  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* red = xs;  // reused for the cross-wave reduction once xs is consumed
-  __shared__ int s_last;
+  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // kc * NR
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  int wid = blockIdx.x;
-  const int ks = wid % g.ksplit;
-  wid /= g.ksplit;
-  const int tile = wid % g.ntiles;
-  const int jb = wid / g.ntiles;
-  const Job& J = jobs[jb];
-  const int n = g.n;
+  const int tile = blockIdx.x % ntiles;
+  const Job& J = jobs[blockIdx.x / ntiles];
   const int r0 = blockIdx.y * NR;
+  const int row = tile * kGvWaves + wave;
+  const int rowc = row < n ? row : n - 1;
   const int K = J.nterms * n;
-  const int k0 = ks * g.kc;
-  const int k1 = min(K, k0 + g.kc);
-  const int kw = max(0, k1 - k0);
 
-  // stage x = Q + beta S for columns [k0, k1) and right-hand sides [r0, r0 + NR)
-  for (int c = tid; c < kw * NR; c += kThreads) {
-    const int kk = k0 + c / NR;
-    const int r = c % NR;
-    const int t = kk / n;
-    const int jj = kk - t * n;
-    double2 v = make_double2(0.0, 0.0);
-    if (r0 + r < nrhs) {
-      const VecRef q = J.Q[t];
-      if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + jj];
-      const VecRef s = J.S[t];
-      if (s.buf >= 0) v = cadd(v, cmul(J.beta[t], bases.b[s.buf][s.off + (int64_t)(r0 + r) * ld + jj]));
-    }
-    xs[c].x = (T)v.x;
-    xs[c].y = (T)v.y;
-  }
-  __syncthreads();
-
-  const int row = tile * 64 + lane;
-  const bool valid = row < n;
-  const int rowc = valid ? row : n - 1;
   Cx<T> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
 
-  const int per = (kw + 3) / 4;
-  const int cb = wave * per;
-  const int ce = min(kw, cb + per);
-  int kk = k0 + cb;
-  const int kend = k0 + ce;
-  while (kk < kend) {
-    const int t = kk / n;
-    const int jj = kk - t * n;
-    const int cnt = min(kend - kk, n - jj);
-    const MV* __restrict__ M = reinterpret_cast<const MV*>(J.M[t]) + (size_t)jj * n + rowc;
-    const Cx<T>* xp = xs + (size_t)(kk - k0) * NR;
-    int c = 0;
-    for (; c + 8 <= cnt; c += 8) {
-      MV m[8];
+  for (int k0 = 0; k0 < K; k0 += kc) {
+    const int kw = min(kc, K - k0);
+    const int cnt = lane < kw ? (kw - lane + 63) / 64 : 0;  // columns k0 + lane + 64 i
+    // (term, column) of this lane's element, advanced by 64 columns per element
+    int t = (k0 + lane) / n;
+    int jj = (k0 + lane) - t * n;
+    MV m[kGvU];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) m[u] = M[(size_t)(c + u) * n];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const Cx<T> mm{(T)m[u].x, (T)m[u].y};
-#pragma unroll
-        for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[(c + u) * NR + r]);
+    for (int u = 0; u < kGvU; ++u) {
+      m[u] = MV{};
+      if (u < cnt) {
+        m[u] = term_row<MV>(J, t, rowc, n)[jj];
+        jj += 64;
+        while (jj >= n) {
+          jj -= n;
+          ++t;
+        }
       }
     }
-    for (; c < cnt; ++c) {
-      const MV m = M[(size_t)c * n];
-      const Cx<T> mm{(T)m.x, (T)m.y};
+    if (k0 > 0) __syncthreads();  // previous chunk fully consumed
+    for (int c = tid; c < kw; c += kGvThreads) {
+      const int kk = k0 + c;
+      const int tt = kk / n;
+      const int cj = kk - tt * n;
+      const VecRef q = J.Q[tt];
+      const VecRef sv = J.S[tt];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[c * NR + r]);
+      for (int r = 0; r < NR; ++r) {
+        double2 v = make_double2(0.0, 0.0);
+        if (r0 + r < nrhs) {
+          if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + cj];
+          if (sv.buf >= 0) v = cadd(v, cmul(J.beta[tt], bases.b[sv.buf][sv.off + (int64_t)(r0 + r) * ld + cj]));
+        }
+        xs[(size_t)c * NR + r] = Cx<T>{(T)v.x, (T)v.y};
+      }
     }
-    kk += cnt;
+    __syncthreads();
+    for (int i0 = 0; i0 < cnt; i0 += kGvU) {
+      MV nx[kGvU];
+      const bool more = i0 + kGvU < cnt;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kGvU; ++u) {
+          nx[u] = MV{};
+          if (i0 + kGvU + u < cnt) {
+            nx[u] = term_row<MV>(J, t, rowc, n)[jj];
+            jj += 64;
+            while (jj >= n) {
+              jj -= n;
+              ++t;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGvU; ++u) {
+        const int i = i0 + u;
+        if (i < cnt) {
+          const Cx<T> mm{(T)m[u].x, (T)m[u].y};
+          const Cx<T>* xp = xs + (size_t)(lane + 64 * i) * NR;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[r]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kGvU; ++u) m[u] = nx[u];
+      }
+    }
   }
 
-  // pairwise reduction of the four waves' partial sums: (w0 + w2) + (w1 + w3)
+  // reduce the row over the 64 lanes (fixed butterfly), lane 0 writes
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc[r].x += __shfl_xor(acc[r].x, off, 64);
+      acc[r].y += __shfl_xor(acc[r].y, off, 64);
+    }
+  }
+  if (lane < NR && row < n && r0 + lane < nrhs) {
+    Cx<T> a = acc[0];
+#pragma unroll
+    for (int r = 1; r < NR; ++r)
+      if (lane == r) a = acc[r];
+    const int r = lane;
+    double2 y = cmul(J.alpha, make_double2((double)a.x, (double)a.y));
+    const VecRef P = J.P;
+    const VecRef Y = J.Y;
+    if (P.buf >= 0) y = cadd(y, bases.b[P.buf][P.off + (int64_t)(r0 + r) * ld + row]);
+    bases.b[Y.buf][Y.off + (int64_t)(r0 + r) * ld + row] = y;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// block_apply, many right-hand sides (NR = 8, 16): register-blocked form
+// ----------------------------------------------------------------------------
+// One workgroup = 4 waves = 64 output rows (one per lane) x NR right-hand
+// sides; the columns are walked in LDS-staged chunks of kc, the 4 waves take
+// contiguous quarters of each chunk; each lane walks its own (row-major) row,
+// and each matrix entry loaded is reused for the NR right-hand sides.
+// Cross-wave reduction in LDS, fixed order.
+template <int NR, bool F32>
+__global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restrict__ jobs, int n, int ntiles, int kc,
+                                                              int nrhs, int64_t ld, Bases bases) {
+  using MV = typename MatT<F32>::vec;
+  using T = typename MatT<F32>::real;
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // max(kc, 128) * NR
+  Cx<T>* red = xs;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tile = blockIdx.x % ntiles;
+  const Job& J = jobs[blockIdx.x / ntiles];
+  const int r0 = blockIdx.y * NR;
+  const int row = tile * 64 + lane;
+  const bool valid = row < n;
+  const int rowc = valid ? row : n - 1;
+  const int K = J.nterms * n;
+
+  Cx<T> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
+
+  for (int k0 = 0; k0 < K; k0 += kc) {
+    const int kw = min(kc, K - k0);
+    if (k0 > 0) __syncthreads();
+    for (int c = tid; c < kw * NR; c += kThreads) {
+      const int kk = k0 + c / NR;
+      const int r = c % NR;
+      const int t = kk / n;
+      const int jj = kk - t * n;
+      double2 v = make_double2(0.0, 0.0);
+      if (r0 + r < nrhs) {
+        const VecRef q = J.Q[t];
+        if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + jj];
+        const VecRef sv = J.S[t];
+        if (sv.buf >= 0) v = cadd(v, cmul(J.beta[t], bases.b[sv.buf][sv.off + (int64_t)(r0 + r) * ld + jj]));
+      }
+      xs[c] = Cx<T>{(T)v.x, (T)v.y};
+    }
+    __syncthreads();
+    const int per = (kw + 3) / 4;
+    const int cb = wave * per;
+    const int ce = min(kw, cb + per);
+    int kk = k0 + cb;
+    const int kend = k0 + ce;
+    while (kk < kend) {
+      const int t = kk / n;
+      const int jj = kk - t * n;
+      const int cnt = min(kend - kk, n - jj);
+      const MV* __restrict__ M = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n + jj;
+      const Cx<T>* xp = xs + (size_t)(kk - k0) * NR;
+      int c = 0;
+      for (; c + 4 <= cnt; c += 4) {
+        MV m[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[u] = M[c + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const Cx<T> mm{(T)m[u].x, (T)m[u].y};
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[(c + u) * NR + r]);
+        }
+      }
+      for (; c < cnt; ++c) {
+        const MV m = M[c];
+        const Cx<T> mm{(T)m.x, (T)m.y};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[c * NR + r]);
+      }
+      kk += cnt;
+    }
+  }
+
+  // pairwise reduction of the four waves: (w0 + w2) + (w1 + w3)
   __syncthreads();
   if (wave >= 2) {
 #pragma unroll
@@ -180,51 +310,14 @@ __global__ __launch_bounds__(kThreads) void block_apply_kernel(const Job* __rest
     for (int r = 0; r < NR; ++r) red[lane * NR + r] = acc[r];
   }
   __syncthreads();
-  double2 sum[NR];
-  if (wave == 0) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const Cx<T> v = red[lane * NR + r];
-      sum[r] = make_double2((double)acc[r].x + (double)v.x, (double)acc[r].y + (double)v.y);
-    }
-  }
-
-  if (g.ksplit > 1) {
-    const size_t tileid = ((size_t)blockIdx.y * njobs + jb) * g.ntiles + tile;
-    double2* pp = part + tileid * (size_t)g.ksplit * 64 * NR;
-    if (wave == 0) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) pp[((size_t)ks * 64 + lane) * NR + r] = sum[r];
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t prev = atomicAdd(&counters[tileid], 1u);
-      s_last = (prev == (uint32_t)(g.ksplit - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (wave == 0) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) sum[r] = make_double2(0.0, 0.0);
-      for (int q = 0; q < g.ksplit; ++q) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          sum[r] = cadd(sum[r], pp[((size_t)q * 64 + lane) * NR + r]);
-        }
-      }
-    }
-    if (tid == 0) counters[tileid] = 0u;
-  }
-
   if (wave == 0 && valid) {
     const VecRef P = J.P;
     const VecRef Y = J.Y;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       if (r0 + r < nrhs) {
-        double2 y = cmul(J.alpha, sum[r]);
+        const Cx<T> v = red[lane * NR + r];
+        double2 y = cmul(J.alpha, make_double2((double)acc[r].x + (double)v.x, (double)acc[r].y + (double)v.y));
         if (P.buf >= 0) y = cadd(y, bases.b[P.buf][P.off + (int64_t)(r0 + r) * ld + row]);
         bases.b[Y.buf][Y.off + (int64_t)(r0 + r) * ld + row] = y;
       }
@@ -232,26 +325,33 @@ __global__ __launch_bounds__(kThreads) void block_apply_kernel(const Job* __rest
   }
 }
 
+// ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
 template <int NR, bool F32>
 hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                           double2* part, uint32_t* counters, hipStream_t st) {
+                           hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   using T = typename MatT<F32>::real;
-  const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
-  dim3 grid((unsigned)njobs * g.ntiles * g.ksplit, (unsigned)((nrhs + NR - 1) / NR));
-  hipLaunchKernelGGL((block_apply_kernel<NR, F32>), grid, dim3(kThreads), lds, st, jobs, njobs, g, nrhs, ld,
-                     bases, part, counters);
+  dim3 grid((unsigned)njobs * g.ntiles, (unsigned)((nrhs + NR - 1) / NR));
+  if (NR <= 4) {
+    const size_t lds = (size_t)g.kc * NR * sizeof(Cx<T>);
+    hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1, 0,
+                          jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
+  } else {
+    const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
+    hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32>), grid, dim3(kThreads), (uint32_t)lds, st, ev0, ev1, 0, jobs,
+                          g.n, g.ntiles, g.kc, nrhs, ld, bases);
+  }
   return hipGetLastError();
 }
 
 template <bool F32>
 hipError_t launch_apply_t(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                          double2* part, uint32_t* counters, hipStream_t st) {
+                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   switch (g.nr) {
-    case 1: return launch_apply_nr<1, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
-    case 2: return launch_apply_nr<2, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
-    case 4: return launch_apply_nr<4, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
-    case 8: return launch_apply_nr<8, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
-    case 16: return launch_apply_nr<16, F32>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+    case 1: return launch_apply_nr<1, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+    case 2: return launch_apply_nr<2, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+    case 4: return launch_apply_nr<4, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+    case 8: return launch_apply_nr<8, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+    case 16: return launch_apply_nr<16, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -386,8 +486,9 @@ __global__ void finish_row_kernel(double2* const* B, const int32_t* pi, double2*
   if (e >= (size_t)n * n) return;
   const int c = (int)(e / n), i = (int)(e % n);
   const double2 v = B[b][(size_t)pi[(size_t)b * n + c] * n + i];
-  if (dinv64[b]) dinv64[b][e] = v;
-  if (dinv32[b]) dinv32[b][e] = make_float2((float)v.x, (float)v.y);
+  const size_t er = (size_t)i * n + c;  // stored factors are row-major
+  if (dinv64[b]) dinv64[b][er] = v;
+  if (dinv32[b]) dinv32[b][er] = make_float2((float)v.x, (float)v.y);
   if (next_diag[b]) {
     const double2 t = cmul(coef[b], v);
     const double2 d = tridiag_entry(i, c, next_diag[b], west, east);
@@ -459,9 +560,9 @@ __global__ void identity_rhs_kernel(double2* W, const int32_t* rows, int nq, int
 
 __global__ void pack_block_kernel(const double2* __restrict__ W, int64_t ld, int q, int row, int n, double sign,
                                   double shift, double2* dst64, float2* dst32) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // row-major destination index
   if (e >= (size_t)n * n) return;
-  const int c = (int)(e / n), i = (int)(e % n);
+  const int i = (int)(e / n), c = (int)(e % n);
   const double2 v = W[(int64_t)(q * n + c) * ld + (int64_t)row * n + i];
   double2 o = make_double2(sign * v.x, sign * v.y);
   if (i == c) o.x += shift;
@@ -675,10 +776,10 @@ inline unsigned grid_for(int64_t n, int cap = 8192) {
 // launchers
 // ----------------------------------------------------------------------------
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                              bool f32, double2* part, uint32_t* counters, hipStream_t st) {
+                              bool f32, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (njobs <= 0) return hipSuccess;
-  return f32 ? launch_apply_t<true>(jobs, njobs, g, nrhs, ld, bases, part, counters, st)
-             : launch_apply_t<false>(jobs, njobs, g, nrhs, ld, bases, part, counters, st);
+  return f32 ? launch_apply_t<true>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1)
+             : launch_apply_t<false>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
 }
 
 hipError_t launch_gj_step(double2* const* A, double2* const* B, int nb, int n, int k, int32_t* perm, int32_t* flag,

@@ -18,7 +18,7 @@ struct VecRef {
 
 // One output block of a batched block apply:
 //   Y = P + alpha * sum_t M_t (Q_t + beta_t S_t)
-// Each M_t is an n x n column-major matrix (complex float64 or complex float32),
+// Each M_t is an n x n row-major matrix (complex float64 or complex float32),
 // every vector has n rows and nrhs columns with the launch's column stride.
 struct Job {
   const void* M[4];
@@ -39,19 +39,16 @@ struct Bases {
 // Launch geometry of one block-apply launch (host-computed).
 struct ApplyGeom {
   int n;        // block size NX
-  int ntiles;   // ceil(n / 64)
-  int ksplit;   // k-splits per (job, tile)
-  int kc;       // columns per split (multiple of 4)
+  int ntiles;   // row tiles per job: ceil(n / 8) for nr <= 4 (one row per wave), ceil(n / 64) otherwise
+  int kc;       // columns staged in LDS per chunk
   int nr;       // right-hand sides per workgroup (template width)
 };
 
 // ---------------------------------------------------------------- block apply
-// part / counters: scratch for split-k partial sums, sized by the host for
-// njobs * ntiles * ksplit * 64 * nr * nchunks complex and njobs * ntiles *
-// nchunks counters (counters must start at zero; the kernel leaves them zero).
+// ev0/ev1 (may be null): events stamped with the kernel's own start and end.
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld,
-                              Bases bases, bool f32, double2* part, uint32_t* counters,
-                              hipStream_t st);
+                              Bases bases, bool f32, hipStream_t st, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 
 // ---------------------------------------------------------- setup kernels
 // Per-layer Gauss-Jordan inversion with partial pivoting of nb dense n x n
@@ -67,8 +64,8 @@ hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipSt
 hipError_t launch_init_delta(double2* const* out, const double2* const* diag, const double2* west,
                              const double2* east, int nb, int n, hipStream_t st);
 
-// Finishes local row r of nb layers: Dinv = B[:, pi] (stored as f64 and/or
-// f32), and if next_diag[b] != nullptr also writes the next Schur complement
+// Finishes local row r of nb layers: Dinv = B[:, pi] (stored row-major as f64
+// and/or f32), and if next_diag[b] != nullptr also writes the next Schur complement
 // Delta_{r+1} = tridiag(A_{r+1}) - coef[b] * Dinv into nextD[b].
 hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64,
                              float2* const* dinv32, double2* const* nextD,
@@ -96,7 +93,8 @@ hipError_t launch_trace_map(double2* W, double2* s, const double2* x, const int3
 hipError_t launch_identity_rhs(double2* W, const int32_t* rows, int nq, int n, int64_t ld, hipStream_t st);
 
 // Copy with optional scale/identity shift of one n x n block out of a local
-// field with nrhs = nq*n columns: dst(i, c) = sign * W[c + q*n, row, i] + shift*(i==c).
+// field with nrhs = nq*n columns: dst(i, c) = sign * W[c + q*n, row, i] + shift*(i==c),
+// stored row-major.
 hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n, double sign,
                              double shift, double2* dst64, float2* dst32, hipStream_t st);
 

@@ -125,10 +125,6 @@ struct pt_solver {
   std::vector<Launch> fwd, bwd, sweep;
   Launch bterm, opA, opR;
 
-  // scratch
-  DevBuf<double2> part;
-  DevBuf<uint32_t> counters;
-
   // live timing of block-apply launches
   bool prof = false;
   std::vector<hipEvent_t> ev;  // 2 per slot
@@ -162,34 +158,19 @@ namespace {
 // ---------------------------------------------------------------------------
 // geometry of one block-apply launch
 // ---------------------------------------------------------------------------
-ApplyGeom geom_for(int n, int njobs, int maxterms, int nrhs) {
+ApplyGeom geom_for(int n, int maxterms, int nrhs) {
   ApplyGeom g{};
   g.n = n;
-  g.ntiles = (n + 63) / 64;
   g.nr = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16;
-  const int nchunks = (nrhs + g.nr - 1) / g.nr;
   const int K = std::max(1, maxterms * n);
-  const int kcap = std::max(64, 2048 / g.nr);  // LDS: kc * nr complex doubles <= 32 KiB
-  const long base = (long)njobs * g.ntiles * nchunks;
-  const long target = 1024;
-  int ks = (int)std::max(1L, (target + base - 1) / base);
-  int kc = (K + ks - 1) / ks;
-  kc = std::max(kc, std::min(K, 64));
-  kc = std::min(kc, kcap);
-  kc = ((kc + 3) / 4) * 4;
-  g.kc = kc;
-  g.ksplit = (K + kc - 1) / kc;
+  if (g.nr <= 4) {
+    g.ntiles = (n + 7) / 8;
+    g.kc = std::min(K, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
+  } else {
+    g.ntiles = (n + 63) / 64;
+    g.kc = std::min(K, 2048 / g.nr);  // LDS = max(kc, 128) * nr complex doubles <= 32 KiB
+  }
   return g;
-}
-
-size_t part_need(const ApplyGeom& g, int njobs, int nrhs) {
-  if (g.ksplit <= 1) return 0;
-  const int nchunks = (nrhs + g.nr - 1) / g.nr;
-  return (size_t)njobs * g.ntiles * g.ksplit * 64 * g.nr * nchunks;
-}
-size_t counter_need(const ApplyGeom& g, int njobs, int nrhs) {
-  const int nchunks = (nrhs + g.nr - 1) / g.nr;
-  return (size_t)njobs * g.ntiles * nchunks;
 }
 
 VecRef vr(int buf, int64_t off) { return VecRef{buf, 0, off}; }
@@ -237,18 +218,18 @@ pt_status prof_harvest(pt_solver* S) {
 
 pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b) {
   if (Lc.njobs == 0) return PT_OK;
-  const ApplyGeom g = geom_for(S->NX, Lc.njobs, Lc.maxterms, nrhs);
-  if (part_need(g, Lc.njobs, nrhs) > S->part.n || counter_need(g, Lc.njobs, nrhs) > S->counters.n)
-    return fail(PT_EINVAL, "internal: split-k scratch too small");
+  const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs);
   int slot = -1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (S->prof) {
     if (S->ev_next >= kEventSlots) PTCHK(prof_harvest(S));
     slot = S->ev_next++;
-    HIPCHK(hipEventRecord(S->ev[2 * slot], S->st));
+    e0 = S->ev[2 * slot];
+    e1 = S->ev[2 * slot + 1];
   }
-  HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->part.p, S->counters.p, S->st));
+  // with profiling on, the dispatch itself stamps e0 / e1 at kernel start / end
+  HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   if (S->prof) {
-    HIPCHK(hipEventRecord(S->ev[2 * slot + 1], S->st));
     const double es = S->f32 ? 8.0 : 16.0;
     S->pend.push_back(ProfPending{slot, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
                                   8.0 * Lc.mat_elems * nrhs});
@@ -588,32 +569,6 @@ pt_status extract_blocks(pt_solver* S) {
       rc = fail(PT_EHIP, "upload extraction jobs");
       break;
     }
-    // split-k scratch for these launches
-    size_t pneed = 0, cneed = 0;
-    for (auto* v : {&lf, &lb})
-      for (auto& Lc : *v) {
-        const ApplyGeom g = geom_for(NX, Lc.njobs, Lc.maxterms, nrhs);
-        pneed = std::max(pneed, part_need(g, Lc.njobs, nrhs));
-        cneed = std::max(cneed, counter_need(g, Lc.njobs, nrhs));
-      }
-    if (pneed > S->part.n) {
-      S->part.release();
-      if (S->part.alloc(pneed) != hipSuccess) {
-        rc = fail(PT_ENOMEM, "split-k scratch");
-        break;
-      }
-    }
-    if (cneed > S->counters.n) {
-      S->counters.release();
-      if (S->counters.alloc(cneed) != hipSuccess) {
-        rc = fail(PT_ENOMEM, "counters");
-        break;
-      }
-      if (hipMemset(S->counters.p, 0, cneed * sizeof(uint32_t)) != hipSuccess) {
-        rc = fail(PT_EHIP, "memset");
-        break;
-      }
-    }
     if (launch_zero(Bx.p, (int64_t)nrhs * ld, st) != hipSuccess ||
         launch_identity_rhs(Bx.p, rows.p, nq, NX, ld, st) != hipSuccess) {
       rc = fail(PT_EHIP, "identity rhs");
@@ -779,35 +734,6 @@ pt_status alloc_online(pt_solver* S) {
   const size_t loc = (size_t)nr * S->sumR * S->NX;
   const size_t vol = (size_t)nr * S->NZ * S->NX;
   const size_t tr = (size_t)nr * std::max<int64_t>(S->Nt, 1);
-  // split-k scratch: the largest launch at max_nrhs (and the nrhs used by fewer columns)
-  size_t pneed = S->part.n, cneed = S->counters.n;
-  std::vector<const Launch*> all;
-  for (auto& v : {&S->fwd, &S->bwd, &S->sweep})
-    for (auto& Lc : *v) all.push_back(&Lc);
-  all.push_back(&S->bterm);
-  all.push_back(&S->opA);
-  all.push_back(&S->opR);
-  for (const Launch* Lc : all) {
-    if (Lc->njobs == 0) continue;
-    for (int q = 1; q <= nr; q = (q < 16 ? q * 2 : q + 16)) {
-      const int qq = std::min(q, nr);
-      const ApplyGeom g = geom_for(S->NX, Lc->njobs, Lc->maxterms, qq);
-      pneed = std::max(pneed, part_need(g, Lc->njobs, qq));
-      cneed = std::max(cneed, counter_need(g, Lc->njobs, qq));
-    }
-    const ApplyGeom g = geom_for(S->NX, Lc->njobs, Lc->maxterms, nr);
-    pneed = std::max(pneed, part_need(g, Lc->njobs, nr));
-    cneed = std::max(cneed, counter_need(g, Lc->njobs, nr));
-  }
-  if (pneed > S->part.n) {
-    S->part.release();
-    HIPCHK(S->part.alloc(pneed));
-  }
-  if (cneed > S->counters.n) {
-    S->counters.release();
-    HIPCHK(S->counters.alloc(cneed));
-  }
-  HIPCHK(hipMemset(S->counters.p, 0, S->counters.n * sizeof(uint32_t)));
   HIPCHK(S->W.alloc(loc));
   HIPCHK(S->Bw.alloc(loc));
   HIPCHK(S->fio.alloc(vol));
@@ -972,14 +898,13 @@ const char* pt_last_error(void) { return g_err.c_str(); }
 void pt_free(pt_solver* S) {
   if (!S) return;
   (void)hipStreamSynchronize(S->st);
-  for (auto* b : {&S->dinv64, &S->blk64, &S->part, &S->W, &S->Bw, &S->fio, &S->uio, &S->s, &S->V, &S->Z, &S->U1,
+  for (auto* b : {&S->dinv64, &S->blk64, &S->W, &S->Bw, &S->fio, &S->uio, &S->s, &S->V, &S->Z, &S->U1,
                   &S->U2, &S->tmp, &S->zeros, &S->x, &S->hbuf, &S->hacc, &S->Hc, &S->sn, &S->g, &S->y})
     b->release();
   S->dinv32.release();
   S->blk32.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag}) b->release();
-  S->counters.release();
   S->jobs.release();
   if (S->h_done) (void)hipHostFree(S->h_done);
   for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
@@ -1206,10 +1131,10 @@ pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, 
     HIPCHK(hipMemcpy(col.data(), S->blk64.p + (size_t)id * n, n * sizeof(double2), hipMemcpyDeviceToHost));
   }
   const int NX = S->NX;
-  for (int c = 0; c < NX; ++c)
-    for (int i = 0; i < NX; ++i) {
-      double2 v = col[(size_t)c * NX + i];
-      if (i == c) v.x -= e.shift;  // block = sign*K + shift*I  =>  K = sign*(block - shift*I)
+  for (int i = 0; i < NX; ++i)
+    for (int c = 0; c < NX; ++c) {
+      double2 v = col[(size_t)i * NX + c];  // stored row-major
+      if (i == c) v.x -= e.shift;           // block = sign*K + shift*I  =>  K = sign*(block - shift*I)
       out[2 * ((size_t)i * NX + c)] = e.sign * v.x;
       out[2 * ((size_t)i * NX + c) + 1] = e.sign * v.y;
     }
