@@ -150,3 +150,54 @@ def test_bad_nrhs_is_rejected(small):
     prob, f, gs, ps = small
     with pytest.raises(P.PolarError):
         gs.solve(np.zeros((21, prob.NZ, prob.NX), dtype=complex))
+
+
+# ---------------------------------------------------------------- precision forms
+def test_f32_blocks_and_factors_small():
+    prob, f = synth.config_small(nx=24, nz=31, npml=5, L=3, nrhs=3, seed=21)
+    _flush("[gpu] f32 small")
+    gs = P.Solver.from_problem(prob, precision="f32", max_nrhs=3, tol=1e-10, maxit=60)
+    u, info = gs.solve(f)
+    err = rel(u, DirectSolver(prob).solve(f))
+    _flush(f"[gpu] f32 small rel err {err:.2e}, iters {[i['iters'] for i in info]}")
+    # FP32 factors and blocks: the trace solve still converges in FP64 (flexible GMRES), the
+    # local solves carry FP32 rounding: the reduced-precision bar is 1e-6
+    assert err < 1e-6
+    gs.close()
+
+
+def test_f32_bumps440_single_source():
+    prob, f = synth.config2()
+    _flush("[gpu] f32 bumps-440x440-L8")
+    gs = P.Solver.from_problem(prob, precision="f32", tol=1e-10, maxit=60)
+    u, info = gs.solve(f)
+    err = rel(u, DirectSolver(prob).solve(f))
+    _flush(f"[gpu] f32 bumps440 rel err {err:.2e}, iters {info[0]['iters']}")
+    assert err < 1e-6
+    gs.close()
+
+
+# ---------------------------------------------------------------- full-size, bench launch configuration
+def test_bumps440_f64_matches_direct():
+    # the launch configuration bench.py times: one source, FP64, tol 1e-10
+    prob, f = synth.config2()
+    _flush("[gpu] f64 bumps-440x440-L8")
+    gs = P.Solver.from_problem(prob, tol=1e-10, maxit=50)
+    u, info = gs.solve(f)
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+    assert info[0]["converged"] and info[0]["relres"] < 1e-9
+    gs.close()
+
+
+def test_batched_many_sources_match_single():
+    # many right-hand sides in one call (NR = 16 path, ragged last chunk) vs the same sources one by one
+    prob, f = synth.config_small(nx=40, nz=48, npml=6, L=4, nrhs=37, seed=8)
+    _flush("[gpu] batched 37 sources")
+    gs = P.Solver.from_problem(prob, max_nrhs=37, tol=1e-11, maxit=60)
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    errs = [rel(u[i], ud[i]) for i in range(37)]
+    assert max(errs) < 1e-8, max(errs)
+    u5, _ = gs.solve(f[5:6])
+    assert rel(u5[0], u[5]) < 1e-9
+    gs.close()
