@@ -75,19 +75,20 @@ struct MatT<true> {
 // One workgroup = kGvWaves waves = kGvWaves output rows (one per wave) over
 // the job's full column range; lane l of a wave reads columns l, l+64, ...
 // of its row, i.e. one contiguous 1 KiB segment per load instruction for
-// float64.  The row's partial sums are reduced by a fixed butterfly of
-// cross-lane shuffles, so no cross-workgroup reduction, atomic or fence is
-// needed and results are deterministic.  The first group of matrix loads of
-// every lane is issued before the input slice is staged in LDS, so its
-// latency overlaps the staging.
+// float64.  Terms and column chunks are walked in a workgroup-uniform loop so
+// every block pointer sits in scalar registers and the matrix loads of a lane
+// are independent (kGvU in flight).  The row's partial sums are reduced by a
+// fixed butterfly of cross-lane shuffles, so no cross-workgroup reduction,
+// atomic or fence is needed and results are deterministic.  The first group
+// of matrix loads of every chunk is issued before its input slice is staged
+// in LDS, so its latency overlaps the staging.
 constexpr int kGvWaves = 8;                 // rows per workgroup
 constexpr int kGvThreads = kGvWaves * 64;
 constexpr int kGvU = 8;                     // loads in flight per lane and group
 
-template <typename MV>
-__device__ __forceinline__ const MV* term_row(const Job& J, int t, int row, int n) {
-  return reinterpret_cast<const MV*>(t == 0 ? J.M[0] : t == 1 ? J.M[1] : t == 2 ? J.M[2] : J.M[3]) +
-         (size_t)row * n;
+// base pointer of a VecRef without dynamic indexing of the by-value kernel argument
+__device__ __forceinline__ double2* base_of(const Bases& b, int buf) {
+  return buf == 0 ? b.b[0] : buf == 1 ? b.b[1] : buf == 2 ? b.b[2] : buf == 3 ? b.b[3] : nullptr;
 }
 
 template <int NR, bool F32>
@@ -102,88 +103,77 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tile = blockIdx.x % ntiles;
-  const Job& J = jobs[blockIdx.x / ntiles];
+  const Job& J = jobs[blockIdx.x / ntiles];  // read with workgroup-uniform indices only
   const int r0 = blockIdx.y * NR;
   const int row = tile * kGvWaves + wave;
   const int rowc = row < n ? row : n - 1;
-  const int K = J.nterms * n;
 
   Cx<T> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
 
-  for (int k0 = 0; k0 < K; k0 += kc) {
-    const int kw = min(kc, K - k0);
-    const int cnt = lane < kw ? (kw - lane + 63) / 64 : 0;  // columns k0 + lane + 64 i
-    // (term, column) of this lane's element, advanced by 64 columns per element
-    int t = (k0 + lane) / n;
-    int jj = (k0 + lane) - t * n;
-    MV m[kGvU];
+  bool first_chunk = true;
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    if (t >= J.nterms) break;
+    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
+    const VecRef qr = J.Q[t];
+    const VecRef sr = J.S[t];
+    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
+    const double2* __restrict__ sp = sr.buf >= 0 ? base_of(bases, sr.buf) + sr.off : nullptr;
+    const double2 be = J.beta[t];
+#pragma unroll 1
+    for (int c0 = 0; c0 < n; c0 += kc) {
+      const int kw = min(kc, n - c0);
+      const int cnt = lane < kw ? (kw - lane + 63) / 64 : 0;  // columns c0 + lane + 64 i of this row
+      // first group of matrix loads goes out before the inputs are staged
+      MV m[kGvU];
 #pragma unroll
-    for (int u = 0; u < kGvU; ++u) {
-      m[u] = MV{};
-      if (u < cnt) {
-        m[u] = term_row<MV>(J, t, rowc, n)[jj];
-        jj += 64;
-        while (jj >= n) {
-          jj -= n;
-          ++t;
+      for (int u = 0; u < kGvU; ++u) m[u] = u < cnt ? Mrow[c0 + lane + 64 * u] : MV{};
+      if (!first_chunk) __syncthreads();  // previous chunk fully consumed
+      first_chunk = false;
+      for (int c = tid; c < kw; c += kGvThreads) {
+        const int cj = c0 + c;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          double2 v = make_double2(0.0, 0.0);
+          if (r0 + r < nrhs) {
+            if (qp) v = qp[(int64_t)(r0 + r) * ld + cj];
+            if (sp) v = cadd(v, cmul(be, sp[(int64_t)(r0 + r) * ld + cj]));
+          }
+          xs[(size_t)c * NR + r] = Cx<T>{(T)v.x, (T)v.y};
         }
       }
-    }
-    if (k0 > 0) __syncthreads();  // previous chunk fully consumed
-    for (int c = tid; c < kw; c += kGvThreads) {
-      const int kk = k0 + c;
-      const int tt = kk / n;
-      const int cj = kk - tt * n;
-      const VecRef q = J.Q[tt];
-      const VecRef sv = J.S[tt];
+      __syncthreads();
+      for (int i0 = 0; i0 < cnt; i0 += kGvU) {
+        MV nx[kGvU];
+        const bool more = i0 + kGvU < cnt;
+        if (more) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double2 v = make_double2(0.0, 0.0);
-        if (r0 + r < nrhs) {
-          if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + cj];
-          if (sv.buf >= 0) v = cadd(v, cmul(J.beta[tt], bases.b[sv.buf][sv.off + (int64_t)(r0 + r) * ld + cj]));
-        }
-        xs[(size_t)c * NR + r] = Cx<T>{(T)v.x, (T)v.y};
-      }
-    }
-    __syncthreads();
-    for (int i0 = 0; i0 < cnt; i0 += kGvU) {
-      MV nx[kGvU];
-      const bool more = i0 + kGvU < cnt;
-      if (more) {
-#pragma unroll
-        for (int u = 0; u < kGvU; ++u) {
-          nx[u] = MV{};
-          if (i0 + kGvU + u < cnt) {
-            nx[u] = term_row<MV>(J, t, rowc, n)[jj];
-            jj += 64;
-            while (jj >= n) {
-              jj -= n;
-              ++t;
-            }
+          for (int u = 0; u < kGvU; ++u) {
+            const int i = i0 + kGvU + u;
+            nx[u] = i < cnt ? Mrow[c0 + lane + 64 * i] : MV{};
           }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < kGvU; ++u) {
-        const int i = i0 + u;
-        if (i < cnt) {
-          const Cx<T> mm{(T)m[u].x, (T)m[u].y};
-          const Cx<T>* xp = xs + (size_t)(lane + 64 * i) * NR;
+        for (int u = 0; u < kGvU; ++u) {
+          const int i = i0 + u;
+          if (i < cnt) {
+            const Cx<T> mm{(T)m[u].x, (T)m[u].y};
+            const Cx<T>* xp = xs + (size_t)(lane + 64 * i) * NR;
 #pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[r]);
+            for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[r]);
+          }
         }
-      }
-      if (more) {
+        if (more) {
 #pragma unroll
-        for (int u = 0; u < kGvU; ++u) m[u] = nx[u];
+          for (int u = 0; u < kGvU; ++u) m[u] = nx[u];
+        }
       }
     }
   }
 
-  // reduce the row over the 64 lanes (fixed butterfly), lane 0 writes
+  // reduce the row over the 64 lanes (fixed butterfly), lanes 0..NR-1 write
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
 #pragma unroll
@@ -199,10 +189,8 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
       if (lane == r) a = acc[r];
     const int r = lane;
     double2 y = cmul(J.alpha, make_double2((double)a.x, (double)a.y));
-    const VecRef P = J.P;
-    const VecRef Y = J.Y;
-    if (P.buf >= 0) y = cadd(y, bases.b[P.buf][P.off + (int64_t)(r0 + r) * ld + row]);
-    bases.b[Y.buf][Y.off + (int64_t)(r0 + r) * ld + row] = y;
+    if (J.P.buf >= 0) y = cadd(y, base_of(bases, J.P.buf)[J.P.off + (int64_t)(r0 + r) * ld + row]);
+    base_of(bases, J.Y.buf)[J.Y.off + (int64_t)(r0 + r) * ld + row] = y;
   }
 }
 
@@ -227,46 +215,49 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tile = blockIdx.x % ntiles;
-  const Job& J = jobs[blockIdx.x / ntiles];
+  const Job& J = jobs[blockIdx.x / ntiles];  // read with workgroup-uniform indices only
   const int r0 = blockIdx.y * NR;
   const int row = tile * 64 + lane;
   const bool valid = row < n;
   const int rowc = valid ? row : n - 1;
-  const int K = J.nterms * n;
 
   Cx<T> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
 
-  for (int k0 = 0; k0 < K; k0 += kc) {
-    const int kw = min(kc, K - k0);
-    if (k0 > 0) __syncthreads();
-    for (int c = tid; c < kw * NR; c += kThreads) {
-      const int kk = k0 + c / NR;
-      const int r = c % NR;
-      const int t = kk / n;
-      const int jj = kk - t * n;
-      double2 v = make_double2(0.0, 0.0);
-      if (r0 + r < nrhs) {
-        const VecRef q = J.Q[t];
-        if (q.buf >= 0) v = bases.b[q.buf][q.off + (int64_t)(r0 + r) * ld + jj];
-        const VecRef sv = J.S[t];
-        if (sv.buf >= 0) v = cadd(v, cmul(J.beta[t], bases.b[sv.buf][sv.off + (int64_t)(r0 + r) * ld + jj]));
+  bool first_chunk = true;
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    if (t >= J.nterms) break;
+    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
+    const VecRef qr = J.Q[t];
+    const VecRef sr = J.S[t];
+    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
+    const double2* __restrict__ sp = sr.buf >= 0 ? base_of(bases, sr.buf) + sr.off : nullptr;
+    const double2 be = J.beta[t];
+#pragma unroll 1
+    for (int c0 = 0; c0 < n; c0 += kc) {
+      const int kw = min(kc, n - c0);
+      if (!first_chunk) __syncthreads();
+      first_chunk = false;
+      for (int c = tid; c < kw * NR; c += kThreads) {
+        const int cj = c0 + c / NR;
+        const int r = c % NR;
+        double2 v = make_double2(0.0, 0.0);
+        if (r0 + r < nrhs) {
+          if (qp) v = qp[(int64_t)(r0 + r) * ld + cj];
+          if (sp) v = cadd(v, cmul(be, sp[(int64_t)(r0 + r) * ld + cj]));
+        }
+        xs[c] = Cx<T>{(T)v.x, (T)v.y};
       }
-      xs[c] = Cx<T>{(T)v.x, (T)v.y};
-    }
-    __syncthreads();
-    const int per = (kw + 3) / 4;
-    const int cb = wave * per;
-    const int ce = min(kw, cb + per);
-    int kk = k0 + cb;
-    const int kend = k0 + ce;
-    while (kk < kend) {
-      const int t = kk / n;
-      const int jj = kk - t * n;
-      const int cnt = min(kend - kk, n - jj);
-      const MV* __restrict__ M = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n + jj;
-      const Cx<T>* xp = xs + (size_t)(kk - k0) * NR;
+      __syncthreads();
+      // the 4 waves take contiguous quarters of the chunk; each lane walks its own row
+      const int per = (kw + 3) / 4;
+      const int cb = wave * per;
+      const int ce = min(kw, cb + per);
+      const MV* __restrict__ M = Mrow + c0 + cb;
+      const Cx<T>* xp = xs + (size_t)cb * NR;
+      const int cnt = max(0, ce - cb);
       int c = 0;
       for (; c + 4 <= cnt; c += 4) {
         MV m[4];
@@ -285,7 +276,6 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
 #pragma unroll
         for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[c * NR + r]);
       }
-      kk += cnt;
     }
   }
 
@@ -311,15 +301,13 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
   }
   __syncthreads();
   if (wave == 0 && valid) {
-    const VecRef P = J.P;
-    const VecRef Y = J.Y;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       if (r0 + r < nrhs) {
         const Cx<T> v = red[lane * NR + r];
         double2 y = cmul(J.alpha, make_double2((double)acc[r].x + (double)v.x, (double)acc[r].y + (double)v.y));
-        if (P.buf >= 0) y = cadd(y, bases.b[P.buf][P.off + (int64_t)(r0 + r) * ld + row]);
-        bases.b[Y.buf][Y.off + (int64_t)(r0 + r) * ld + row] = y;
+        if (J.P.buf >= 0) y = cadd(y, base_of(bases, J.P.buf)[J.P.off + (int64_t)(r0 + r) * ld + row]);
+        base_of(bases, J.Y.buf)[J.Y.off + (int64_t)(r0 + r) * ld + row] = y;
       }
     }
   }

@@ -163,12 +163,14 @@ ApplyGeom geom_for(int n, int maxterms, int nrhs) {
   g.n = n;
   g.nr = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16;
   const int K = std::max(1, maxterms * n);
+  // column chunks are taken inside one term (block) at a time
+  (void)K;
   if (g.nr <= 4) {
     g.ntiles = (n + 7) / 8;
-    g.kc = std::min(K, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
+    g.kc = std::min(n, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
   } else {
     g.ntiles = (n + 63) / 64;
-    g.kc = std::min(K, 2048 / g.nr);  // LDS = max(kc, 128) * nr complex doubles <= 32 KiB
+    g.kc = std::min(n, 2048 / g.nr);  // LDS = max(kc, 128) * nr complex doubles <= 32 KiB
   }
   return g;
 }
