@@ -313,6 +313,131 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
   }
 }
 
+// ----------------------------------------------------------------------------
+// block_apply, many right-hand sides in float64: MFMA form
+// ----------------------------------------------------------------------------
+// One workgroup = 4 waves = a 64-row x TN-right-hand-side output tile of one
+// job (TN = 16, 32 or 64, chosen per launch so that small launches still
+// fill the chip).  The columns of every term are walked in chunks of 16: the
+// 64 x 16 slice of the (row-major) block and the 16 x TN slice of the
+// combined input Q + beta S are staged in LDS (the next chunk is loaded into
+// registers while the current one is multiplied).  Wave w accumulates rows
+// 16w..16w+15 for all TN right-hand sides as TN/16 tiles of
+// v_mfma_f64_16x16x4 (lane l holds A[l%16][l/16] and B[l/16][l%16];
+// accumulator register i of lane l holds C[4i + l/16][l%16]).  A complex
+// product is four real MFMAs, Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br,
+// issued so that consecutive MFMAs update different accumulators.
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int kMmRows = 64;  // rows per workgroup tile
+constexpr int kMmK = 16;     // columns per staged chunk
+
+template <int TN>
+__global__ __launch_bounds__(kThreads) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+                                                                 int nrt, int nrhs, int64_t ld, Bases bases) {
+  constexpr int NB = TN / 16;           // MFMA tiles per wave
+  constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread
+  __shared__ double2 As[kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
+  __shared__ double2 Bs[kMmK][TN];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int bid = blockIdx.x;
+  const int ct = bid % nrt;  // right-hand-side tile
+  bid /= nrt;
+  const int tile = bid % ntiles;
+  const Job& J = jobs[bid / ntiles];
+  const int row0 = tile * kMmRows;
+  const int col0 = ct * TN;
+
+  // A staging: row tid/4, 4 consecutive columns (tid%4)*4
+  const int sr = tid >> 2;
+  const int sc = (tid & 3) * 4;
+  const int arow = min(row0 + sr, n - 1);
+  const bool arow_ok = row0 + sr < n;
+  // B staging: BPT consecutive columns of one right-hand side
+  const int bq = tid / (kMmK / BPT);
+  const int bc = (tid % (kMmK / BPT)) * BPT;
+  const int brhs = col0 + bq;
+  const bool brhs_ok = brhs < nrhs;
+
+  d4v cr[NB], ci[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    cr[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    ci[b] = d4v{0.0, 0.0, 0.0, 0.0};
+  }
+  const int wr = wave * 16;
+
+  const int nchunk_t = (n + kMmK - 1) / kMmK;
+  const int nchunks = J.nterms * nchunk_t;
+  double2 pa[4], pb[BPT];
+  auto fetch = [&](int q) {
+    const int t = q / nchunk_t;
+    const int c0 = (q - t * nchunk_t) * kMmK;
+    const double2* __restrict__ M = reinterpret_cast<const double2*>(J.M[t]) + (size_t)arow * n;
+    const VecRef qr = J.Q[t];
+    const VecRef svr = J.S[t];
+    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
+    const double2* __restrict__ sp = svr.buf >= 0 ? base_of(bases, svr.buf) + svr.off : nullptr;
+    const double2 be = J.beta[t];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + sc + u;
+      pa[u] = (c < n && arow_ok) ? M[c] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int c = c0 + bc + u;
+      double2 v = make_double2(0.0, 0.0);
+      if (c < n && brhs_ok) {
+        if (qp) v = qp[(int64_t)brhs * ld + c];
+        if (sp) v = cadd(v, cmul(be, sp[(int64_t)brhs * ld + c]));
+      }
+      pb[u] = v;
+    }
+  };
+  if (nchunks > 0) fetch(0);
+  for (int q = 0; q < nchunks; ++q) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) As[sc + u][sr] = pa[u];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) Bs[bc + u][bq] = pb[u];
+    __syncthreads();
+    if (q + 1 < nchunks) fetch(q + 1);  // next chunk in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < kMmK; kk += 4) {
+      const double2 av = As[kk + (lane >> 4)][wr + (lane & 15)];
+      double2 bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[kk + (lane >> 4)][b * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, cr[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) ci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].y, ci[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv[b].y, cr[b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) ci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[b].x, ci[b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  double2* __restrict__ Yb = base_of(bases, J.Y.buf) + J.Y.off;
+  const double2* __restrict__ Pb = J.P.buf >= 0 ? base_of(bases, J.P.buf) + J.P.off : nullptr;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + wr + 4 * i + (lane >> 4);
+      const int rhs = col0 + b * 16 + (lane & 15);
+      if (row < n && rhs < nrhs) {
+        double2 y = cmul(J.alpha, make_double2(cr[b][i], ci[b][i]));
+        if (Pb) y = cadd(y, Pb[(int64_t)rhs * ld + row]);
+        Yb[(int64_t)rhs * ld + row] = y;
+      }
+    }
+}
+
 // ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
 template <int NR, bool F32>
 hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
@@ -323,6 +448,20 @@ hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int n
     const size_t lds = (size_t)g.kc * NR * sizeof(Cx<T>);
     hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1, 0,
                           jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
+  } else if (!F32 && g.mfma) {
+    const int ntl = (g.n + kMmRows - 1) / kMmRows;
+    const int tn = g.mfma;  // right-hand sides per workgroup tile: 16, 32 or 64
+    const int nrt = (nrhs + tn - 1) / tn;
+    const dim3 grid2((unsigned)njobs * ntl * nrt);
+    if (tn == 64)
+      hipExtLaunchKernelGGL(block_mfma64_kernel<64>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
+                            nrhs, ld, bases);
+    else if (tn == 32)
+      hipExtLaunchKernelGGL(block_mfma64_kernel<32>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
+                            nrhs, ld, bases);
+    else
+      hipExtLaunchKernelGGL(block_mfma64_kernel<16>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
+                            nrhs, ld, bases);
   } else {
     const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
     hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32>), grid, dim3(kThreads), (uint32_t)lds, st, ev0, ev1, 0, jobs,

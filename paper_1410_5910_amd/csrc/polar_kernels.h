@@ -42,6 +42,8 @@ struct ApplyGeom {
   int ntiles;   // row tiles per job: ceil(n / 8) for nr <= 4 (one row per wave), ceil(n / 64) otherwise
   int kc;       // columns staged in LDS per chunk
   int nr;       // right-hand sides per workgroup (template width)
+  int mfma;     // float64 with many right-hand sides: MFMA kernel with this many right-hand
+                // sides per workgroup tile (16, 32 or 64); 0: not used
 };
 
 // ---------------------------------------------------------------- block apply

@@ -158,13 +158,24 @@ namespace {
 // ---------------------------------------------------------------------------
 // geometry of one block-apply launch
 // ---------------------------------------------------------------------------
-ApplyGeom geom_for(int n, int maxterms, int nrhs) {
+ApplyGeom geom_for(int n, int maxterms, int nrhs, int njobs = 1) {
   ApplyGeom g{};
   g.n = n;
   g.nr = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16;
   const int K = std::max(1, maxterms * n);
   // column chunks are taken inside one term (block) at a time
   (void)K;
+  // MFMA tile width: the widest that still gives about two workgroups per CU
+  g.mfma = 0;
+  if (nrhs >= 16) {
+    const long rows = (long)njobs * ((n + 63) / 64);
+    g.mfma = 16;
+    for (int tn : {64, 32})
+      if (rows * ((nrhs + tn - 1) / tn) >= 512) {
+        g.mfma = tn;
+        break;
+      }
+  }
   if (g.nr <= 4) {
     g.ntiles = (n + 7) / 8;
     g.kc = std::min(n, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
@@ -220,7 +231,7 @@ pt_status prof_harvest(pt_solver* S) {
 
 pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b) {
   if (Lc.njobs == 0) return PT_OK;
-  const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs);
+  const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
   int slot = -1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (S->prof) {
