@@ -86,12 +86,12 @@ class Oracle:
         return nsol / el, nsol, el
 
 
-def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True):
-    """Setup + warmup + timed steps (+ a profiled pass) for one (workload, precision)."""
+def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False):
+    """Setup + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
     nrhs = f.shape[0]
     t0 = time.perf_counter()
     s = P.Solver.from_problem(prob, precision=precision, tol=1e-10, maxit=60, max_nrhs=nrhs,
-                              stream=stream.cuda_stream)
+                              stream=stream.cuda_stream, plr=plr, plr_eps=1e-9)
     lay = s.layout()
     fd = torch.from_numpy(f).to("cuda:0")
     setup_s = time.perf_counter() - t0
@@ -104,7 +104,8 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     out = {"solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "nrhs": nrhs,
-           "precision": precision, "setup_s": setup_s, "iterations": sorted(set(i["iters"] for i in info)),
+           "precision": precision, "blocks": "plr eps 1e-9" if plr else "dense", "setup_s": setup_s,
+           "iterations": sorted(set(i["iters"] for i in info)),
            "max_true_relres": max(i["relres"] for i in info), "block_bytes": lay["block_bytes"],
            "factor_bytes": lay["factor_bytes"]}
     if profile:
@@ -209,22 +210,28 @@ def main():
         if args.precision != "auto" or chosen is form:
             break
     if not args.no_forms:
-        have = {(fm["workload"], fm["precision"]) for fm in forms}
-        extra = [(args.workload, "f64")] + [("bumps440", p) for p in ("f64", "f32")]
-        for wl, prec in extra:
-            if (wl, prec) in have or (wl == args.workload and args.nrhs):
+        have = {(fm["workload"], fm["precision"], False) for fm in forms}
+        extra = [(args.workload, "f64", False)] + [("bumps440", p, False) for p in ("f64", "f32")] + \
+            [("bumps440", "f64", True)]
+        orcs = {}
+        for wl, prec, plr in extra:
+            if (wl, prec, plr) in have or (wl == args.workload and args.nrhs):
                 continue
             pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
-            log(f"form {wl} {prec}")
+            log(f"form {wl} {prec}{' plr' if plr else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
-                               args.warmup, stream, profile=False)
+                               args.warmup, stream, profile=False, plr=plr)
             form["workload"] = wl
-            orc = oracle if wl == args.workload else Oracle(pw)
+            if wl == args.workload:
+                orc = oracle
+            else:
+                orc = orcs.get(wl) or Oracle(pw)
+                orcs[wl] = orc
             if orc is not None:
                 form["rel_err_vs_oracle"] = max(orc.errors(fw, u, min(k or 1, fw.shape[0])))
             log(f"  {form['solves_per_s']:.1f} solves/s, rel err {form.get('rel_err_vs_oracle', float('nan')):.2e}")
             forms.append(form)
-            have.add((wl, prec))
+            have.add((wl, prec, plr))
 
     f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"]
     out = {

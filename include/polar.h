@@ -90,6 +90,10 @@ typedef struct {
   double tol;        /* GMRES stop: relative residual of the trace system         */
   int32_t maxit;     /* GMRES iterations (no restart), 1..200                     */
   int32_t max_nrhs;  /* largest nrhs pt_solve will be called with, >= 1           */
+  int32_t plr;       /* 1: store and apply the trace blocks in partitioned
+                        low-rank form (Alg. 5 / Alg. 6); float64 only          */
+  double plr_eps;    /* absolute singular-value threshold of a leaf, > 0        */
+  int32_t plr_rmax;  /* leaf rank limit, 1..64 (0: ceil(sqrt(NX)))              */
 } pt_options;
 
 typedef struct {
@@ -106,8 +110,11 @@ typedef struct {
   int32_t R[64];     /* local rows per layer (first min(L,64) layers)             */
   int32_t own_start[64], n_own[64], top_ext[64], bot_ext[64];
   double setup_ms;   /* wall time of pt_setup                                     */
-  int64_t block_bytes;  /* device bytes of the trace blocks                       */
+  int64_t block_bytes;  /* device bytes of the trace blocks as applied (PLR storage
+                           when plr = 1)                                          */
   int64_t factor_bytes; /* device bytes of the local factors                      */
+  int64_t dense_block_bytes; /* device bytes the dense trace blocks take          */
+  int64_t plr_leaves;   /* leaves of all compressed blocks (0 without PLR)         */
 } pt_layout;
 
 typedef struct pt_solver pt_solver;

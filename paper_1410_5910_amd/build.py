@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpolar.so")
-SOURCES = ["kernels.hip", "solver.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "plr.hip"]
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")
 
 
@@ -33,6 +33,8 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         "-Wall", "-Wno-unused-result",
+        # host-side complex arithmetic (PLR compression) without the C99 Annex G inf/nan branches
+        "-Xarch_host", "-fcomplex-arithmetic=basic",
     ]
     objs = []
     procs = []
@@ -50,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         if verbose and out.strip():
             print(out)
     tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

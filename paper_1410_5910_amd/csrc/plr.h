@@ -1,0 +1,55 @@
+// Partitioned low-rank trace blocks (internal to libpolar).
+#pragma once
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <complex>
+#include <vector>
+
+#include "polar_kernels.h"
+
+namespace polar {
+
+constexpr int kPlrMaxRank = 64;
+
+// One leaf of a compressed block: rows [r0, r0+m) x columns [c0, c0+n).
+// k >= 0: low rank, U (m x k, row-major) at offU and V (k x n, row-major) at
+// offV of the block's data; k < 0: dense, D (m x n, row-major) at offU.
+struct PlrLeafDev {
+  int32_t r0, c0, m, n, k, pad;
+  int64_t offU, offV;
+};
+
+// A compressed block as the apply kernel sees it (Job::M points at one).
+struct PlrBlockDev {
+  int32_t nleaves, ntile;
+  const PlrLeafDev* leaves;
+  const int32_t* tile_ptr;   // ntile + 1 offsets into tile_leaf
+  const int32_t* tile_leaf;  // leaves intersecting each 64-row tile
+  const double2* data;
+};
+
+struct PlrSet {
+  int n = 0;
+  PlrLeafDev* d_leaves = nullptr;
+  int32_t* d_ptr = nullptr;
+  int32_t* d_list = nullptr;
+  double2* d_data = nullptr;
+  PlrBlockDev* d_blocks = nullptr;
+  size_t data_entries = 0, nleaves_total = 0;
+  std::vector<size_t> stored;  // complex entries stored per block
+
+  // Compress every n x n row-major block (host memory) and upload the result.
+  hipError_t build(const std::vector<const std::complex<double>*>& blocks, int n, int rmax, double eps, int nthreads);
+  size_t stored_entries(int b) const;
+  const PlrBlockDev* block(int b) const { return d_blocks + b; }
+  void release();
+};
+
+// Y = P + alpha * sum_t PLR_t (Q_t + beta_t S_t) for jobs whose M_t point at PlrBlockDev.
+hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1);
+
+}  // namespace polar

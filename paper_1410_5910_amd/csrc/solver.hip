@@ -9,9 +9,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/polar.h"
+#include "plr.h"
 #include "polar_kernels.h"
 
 using namespace polar;
@@ -63,6 +65,7 @@ struct Layer {
 
 struct Launch {
   int job0 = 0, njobs = 0, maxterms = 0;
+  bool plr = false;          // job terms point at compressed blocks
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
 };
@@ -110,6 +113,8 @@ struct pt_solver {
   std::vector<cd> lcoef, ucoef;  // z couplings of each local row (sumR)
 
   // device data
+  PlrSet plr;
+  bool use_plr = false;
   DevBuf<double2> dinv64, blk64;
   DevBuf<float2> dinv32, blk32;
   int nblk = 0;
@@ -144,6 +149,16 @@ struct pt_solver {
     const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
     if (id < 0) return nullptr;
     return f32 ? (const void*)(blk32.p + (size_t)id * block_elems()) : (const void*)(blk64.p + (size_t)id * block_elems());
+  }
+  // what a trace-block job term points at: the dense block or its compressed form
+  const void* blk_term(int l, int type, int a, int b) const {
+    if (!use_plr) return blk(l, type, a, b);
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    return id < 0 ? nullptr : (const void*)plr.block(id);
+  }
+  int blk_id(const void* term) const {
+    if (!use_plr) return -1;
+    return (int)((const PlrBlockDev*)term - plr.d_blocks);
   }
   const void* dinv(int l, int r) const {
     const size_t off = (size_t)(lay[l].rowbase + r) * block_elems();
@@ -241,7 +256,10 @@ pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases 
     e1 = S->ev[2 * slot + 1];
   }
   // with profiling on, the dispatch itself stamps e0 / e1 at kernel start / end
-  HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
+  if (Lc.plr)
+    HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
+  else
+    HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   if (S->prof) {
     const double es = S->f32 ? 8.0 : 16.0;
     S->pend.push_back(ProfPending{slot, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
@@ -250,14 +268,19 @@ pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases 
   return PT_OK;
 }
 
-Launch push_launch(pt_solver* S, const std::vector<Job>& js) {
+Launch push_launch(pt_solver* S, const std::vector<Job>& js, bool plr_terms = false) {
   Launch Lc;
   Lc.job0 = (int)S->hjobs.size();
   Lc.njobs = (int)js.size();
   for (const Job& j : js) Lc.maxterms = std::max(Lc.maxterms, j.nterms);
   const double n = S->NX;
   for (const Job& j : js) {
-    Lc.mat_elems += j.nterms * n * n;
+    if (S->use_plr && plr_terms) {
+      for (int t = 0; t < j.nterms; ++t) Lc.mat_elems += (double)S->plr.stored_entries(S->blk_id(j.M[t]));
+      Lc.plr = true;
+    } else {
+      Lc.mat_elems += j.nterms * n * n;
+    }
     double v = (j.P.buf >= 0 ? n : 0) + n;  // epilogue read + output write
     for (int t = 0; t < j.nterms; ++t) v += (j.Q[t].buf >= 0 ? n : 0) + (j.S[t].buf >= 0 ? n : 0);
     Lc.vec_elems_rhs += v;
@@ -287,6 +310,11 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
   if (o->maxit < 1 || o->maxit > 200) return fail(PT_EINVAL, "maxit must be in 1..200");
   if (!(o->tol >= 0)) return fail(PT_EINVAL, "tol must be >= 0");
   if (o->max_nrhs < 1) return fail(PT_EINVAL, "max_nrhs must be >= 1");
+  if (o->plr) {
+    if (o->precision != PT_F64) return fail(PT_EINVAL, "PLR blocks are float64 only");
+    if (!(o->plr_eps > 0)) return fail(PT_EINVAL, "plr_eps must be > 0");
+    if (o->plr_rmax < 0 || o->plr_rmax > kPlrMaxRank) return fail(PT_EINVAL, "plr_rmax must be in 0..64");
+  }
   return PT_OK;
 }
 
@@ -673,7 +701,7 @@ void build_online_jobs(pt_solver* S) {
       Job j = empty_job();
       j.Y = vr(2, S->seg(0, kd, a));
       j.P = j.Y;
-      for (int b = 0; b < 2; ++b) add_term(j, S->blk(kd, T_DN, a, b), vr(2, S->seg(0, kd - 1, b)), vr(1, S->seg(1, kd - 1, b)), one);
+      for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(kd, T_DN, a, b), vr(2, S->seg(0, kd - 1, b)), vr(1, S->seg(1, kd - 1, b)), one);
       js.push_back(j);
     }
     for (int a = 0; a < 2; ++a) {
@@ -681,10 +709,10 @@ void build_online_jobs(pt_solver* S) {
       j.Y = vr(2, S->seg(1, ku, a));
       j.P = j.Y;
       for (int b = 0; b < 2; ++b)
-        add_term(j, S->blk(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
+        add_term(j, S->blk_term(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
       js.push_back(j);
     }
-    S->sweep.push_back(push_launch(S, js));
+    S->sweep.push_back(push_launch(S, js, true));
   }
   // reflection terms of a Gauss-Seidel pass: cur = r + (B_up - J0) a^prev, r + (B_dn - J1) d^prev
   {
@@ -694,15 +722,15 @@ void build_online_jobs(pt_solver* S) {
         Job j = empty_job();
         j.Y = vr(2, S->seg(0, k, a));
         j.P = vr(0, S->seg(0, k, a));
-        for (int b = 0; b < 2; ++b) add_term(j, S->blk(k, B_UP, a, b), vr(1, S->seg(1, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(k, B_UP, a, b), vr(1, S->seg(1, k, b)));
         js.push_back(j);
         Job u = empty_job();
         u.Y = vr(2, S->seg(1, k, a));
         u.P = vr(0, S->seg(1, k, a));
-        for (int b = 0; b < 2; ++b) add_term(u, S->blk(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(u, S->blk_term(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
         js.push_back(u);
       }
-    S->bterm = push_launch(S, js);
+    S->bterm = push_launch(S, js, true);
   }
   // polarized operator y = A x (bases 0 = x, 2 = y) and y = R x
   for (int which = 0; which < 2; ++which) {
@@ -717,9 +745,9 @@ void build_online_jobs(pt_solver* S) {
         j.alpha = make_double2(-1.0, 0.0);
         if (k >= 1)
           for (int b = 0; b < 2; ++b)
-            add_term(j, S->blk(k, T_DN, a, b), isA ? vr(0, S->seg(0, k - 1, b)) : vr(0, S->seg(1, k - 1, b)),
+            add_term(j, S->blk_term(k, T_DN, a, b), isA ? vr(0, S->seg(0, k - 1, b)) : vr(0, S->seg(1, k - 1, b)),
                      isA ? vr(0, S->seg(1, k - 1, b)) : none(), one);
-        for (int b = 0; b < 2; ++b) add_term(j, S->blk(k, B_UP, a, b), vr(0, S->seg(1, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(k, B_UP, a, b), vr(0, S->seg(1, k, b)));
         js.push_back(j);
         // up rows: a_k - T_up(k+1)(a_{k+1} + d_{k+1}) - (B_dn(k+1) - J1) d_k
         Job u = empty_job();
@@ -728,15 +756,15 @@ void build_online_jobs(pt_solver* S) {
         u.alpha = make_double2(-1.0, 0.0);
         if (k + 1 <= L - 2)
           for (int b = 0; b < 2; ++b)
-            add_term(u, S->blk(k + 1, T_UP, a, b), isA ? vr(0, S->seg(1, k + 1, b)) : vr(0, S->seg(0, k + 1, b)),
+            add_term(u, S->blk_term(k + 1, T_UP, a, b), isA ? vr(0, S->seg(1, k + 1, b)) : vr(0, S->seg(0, k + 1, b)),
                      isA ? vr(0, S->seg(0, k + 1, b)) : none(), one);
-        for (int b = 0; b < 2; ++b) add_term(u, S->blk(k + 1, B_DN, a, b), vr(0, S->seg(0, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(u, S->blk_term(k + 1, B_DN, a, b), vr(0, S->seg(0, k, b)));
         js.push_back(u);
       }
     if (isA)
-      S->opA = push_launch(S, js);
+      S->opA = push_launch(S, js, true);
     else
-      S->opR = push_launch(S, js);
+      S->opR = push_launch(S, js, true);
   }
   (void)NX;
 }
@@ -919,6 +947,7 @@ void pt_free(pt_solver* S) {
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag}) b->release();
   S->jobs.release();
+  S->plr.release();
   if (S->h_done) (void)hipHostFree(S->h_done);
   for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
   delete S;
@@ -1065,6 +1094,22 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
       return bail(fail(PT_EHIP, "trace maps"));
   }
 
+  // partitioned low-rank form of the trace blocks (compressed on the host)
+  if (opt->plr && S->L >= 2) {
+    const size_t E = S->block_elems();
+    std::vector<std::complex<double>> host((size_t)S->nblk * E);
+    if (hipMemcpy(host.data(), S->blk64.p, host.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(fail(PT_EHIP, "download blocks"));
+    std::vector<const std::complex<double>*> ptrs(S->nblk);
+    for (int b = 0; b < S->nblk; ++b) ptrs[b] = host.data() + (size_t)b * E;
+    int rmax = opt->plr_rmax > 0 ? opt->plr_rmax : (int)std::ceil(std::sqrt((double)NX));
+    rmax = std::min(rmax, kPlrMaxRank);
+    const unsigned hw = std::thread::hardware_concurrency();
+    if (S->plr.build(ptrs, NX, rmax, opt->plr_eps, (int)std::max(1u, std::min(hw, 16u))) != hipSuccess)
+      return bail(fail(PT_ENOMEM, "PLR blocks"));
+    S->use_plr = true;
+  }
+
   // reduced-precision copies of the factors and blocks
   if (opt->precision == PT_F32) {
     if (S->dinv32.alloc(S->dinv64.n) != hipSuccess || S->blk32.alloc(S->blk64.n) != hipSuccess)
@@ -1108,7 +1153,9 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   }
   o->setup_ms = S->setup_ms;
   const size_t es = S->f32 ? sizeof(float2) : sizeof(double2);
-  o->block_bytes = (int64_t)S->nblk * S->block_elems() * es;
+  o->dense_block_bytes = (int64_t)S->nblk * S->block_elems() * es;
+  o->block_bytes = S->use_plr ? (int64_t)(S->plr.data_entries * sizeof(double2)) : o->dense_block_bytes;
+  o->plr_leaves = S->use_plr ? (int64_t)S->plr.nleaves_total : 0;
   o->factor_bytes = (int64_t)S->sumR * S->block_elems() * es;
   return PT_OK;
 }

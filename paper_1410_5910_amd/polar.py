@@ -33,7 +33,7 @@ class PtProblem(C.Structure):
 
 class PtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gs_iters", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
-                ("max_nrhs", C.c_int32)]
+                ("max_nrhs", C.c_int32), ("plr", C.c_int32), ("plr_eps", C.c_double), ("plr_rmax", C.c_int32)]
 
 
 class PtRhsInfo(C.Structure):
@@ -44,7 +44,8 @@ class PtLayout(C.Structure):
     _fields_ = [("NX", C.c_int32), ("NZ", C.c_int32), ("L", C.c_int32), ("sumR", C.c_int32), ("ntrace", C.c_int64),
                 ("R", C.c_int32 * 64), ("own_start", C.c_int32 * 64), ("n_own", C.c_int32 * 64),
                 ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
-                ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64)]
+                ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64), ("dense_block_bytes", C.c_int64),
+                ("plr_leaves", C.c_int64)]
 
 
 class PtKernelStats(C.Structure):
@@ -113,7 +114,7 @@ class Solver:
     """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
 
     def __init__(self, nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
-                 max_nrhs=1, stream=None):
+                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0):
         self._lib = lib()
         c = np.ascontiguousarray(c, dtype=np.float64)
         NX, NZ = nx + 2 * npml, nz + 2 * npml
@@ -123,7 +124,8 @@ class Solver:
         prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
                          c.ctypes.data_as(C.POINTER(C.c_double)))
         prec = {"f64": PT_F64, "f32": PT_F32}[precision]
-        opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs))
+        opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
+                        float(plr_eps), int(plr_rmax))
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
         self._h = h_
@@ -157,7 +159,8 @@ class Solver:
         return {"NX": o.NX, "NZ": o.NZ, "L": L, "sumR": o.sumR, "ntrace": o.ntrace, "R": list(o.R[:L]),
                 "own_start": list(o.own_start[:L]), "n_own": list(o.n_own[:L]), "top_ext": list(o.top_ext[:L]),
                 "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
-                "factor_bytes": o.factor_bytes}
+                "factor_bytes": o.factor_bytes, "dense_block_bytes": o.dense_block_bytes,
+                "plr_leaves": o.plr_leaves}
 
     def profile(self, enable: bool):
         """Start (reset) / stop recording HIP events around every block-apply launch."""

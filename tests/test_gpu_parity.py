@@ -201,3 +201,36 @@ def test_batched_many_sources_match_single():
     u5, _ = gs.solve(f[5:6])
     assert rel(u5[0], u[5]) < 1e-9
     gs.close()
+
+
+# ---------------------------------------------------------------- partitioned low-rank blocks
+def test_plr_operator_matches_dense_oracle():
+    prob, f = synth.config_small(nx=90, nz=60, npml=8, L=3, nrhs=2, seed=12)
+    _flush("[gpu] plr operator small")
+    gs = P.Solver.from_problem(prob, plr=True, plr_eps=1e-10, max_nrhs=3, tol=1e-12)
+    lay = gs.layout()
+    assert lay["plr_leaves"] > 0 and lay["block_bytes"] < lay["dense_block_bytes"]
+    ps = PolarizedSolver(prob)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(ps.zeros(3).shape) + 1j * rng.standard_normal(ps.zeros(3).shape)
+    for code, fn in ((P.OP_A, ps.apply_A), (P.OP_R, ps.apply_R), (P.OP_DINV, ps.apply_D_inv),
+                     (P.OP_PRECOND, ps.precondition)):
+        err = rel(gs.apply(code, x), fn(x))
+        assert err < 1e-8, (code, err)
+    u, info = gs.solve(f)
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-7
+    gs.close()
+
+
+def test_plr_bumps440_single_source():
+    prob, f = synth.config2()
+    _flush("[gpu] plr bumps-440x440-L8")
+    gs = P.Solver.from_problem(prob, plr=True, plr_eps=1e-9, tol=1e-10)
+    lay = gs.layout()
+    _flush(f"[gpu] plr ratio {lay['block_bytes'] / lay['dense_block_bytes']:.3f}, leaves {lay['plr_leaves']}, "
+           f"setup {lay['setup_ms'] / 1e3:.1f} s")
+    u, info = gs.solve(f)
+    err = rel(u, DirectSolver(prob).solve(f))
+    _flush(f"[gpu] plr bumps440 rel err {err:.2e}, iters {info[0]['iters']}")
+    assert err < 1e-6
+    gs.close()
