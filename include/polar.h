@@ -101,6 +101,8 @@ typedef struct {
   int32_t converged; /* 1 if the residual estimate reached tol                    */
   double est;        /* GMRES residual estimate at exit (relative)                */
   double relres;     /* true relative residual ||s - A x|| / ||s|| in float64     */
+  int32_t learned;   /* 1 if the result came from GMRES with the learned stage    */
+  int32_t learned_steps; /* GMRES steps of this RHS that used the network's output    */
 } pt_rhs_info;
 
 typedef struct {
@@ -192,6 +194,65 @@ typedef struct {
 pt_status pt_profile(pt_solver* s, int32_t enable);
 /* Synchronises the solver stream and returns the accumulated counters. */
 pt_status pt_profile_read(pt_solver* s, pt_kernel_stats* out);
+
+/* ---- learned preconditioner stage --------------------------------------
+ *
+ * Not in the paper.  A small 1D convolutional network N along the interface
+ * coordinate adds a stage to the Gauss-Seidel preconditioner GS inside
+ * flexible GMRES.  For the Krylov vector v of a step with z = GS(v), the
+ * residual of that step is r = v - A z, and N(r) estimates A^{-1} r, what z
+ * misses of A^{-1} v.  Two ways of using it (pt_learned_mode):
+ *   PT_LEARN_CORRECT: every step uses z + c, c = N(r), for a right-hand side
+ *     whose float64 residual drops (||r - A c|| < ||r||), else z alone;
+ *   PT_LEARN_AUGMENT: steps alternate: a sweep step z = GS(v), then a network
+ *     step whose direction is N(r) for the previous step's r; GMRES weighs
+ *     the two directions itself.  A network step costs one apply of A and no
+ *     sweeps.
+ * The network sees each interface separately as 8 real channels ({down, up}
+ * x {row n, row n+1} x {re, im}) of r divided by their RMS; its output is
+ * scaled back.  Architecture: 4 convolutions 8 -> 32 -> 32 -> 32 -> 8,
+ * kernel 5, zero padding, ReLU between layers; bfloat16 weights, float32
+ * activations and accumulation, float32 master weights trained with Adam.
+ * Training pairs (r, e) come from the method's own solves: for every Krylov
+ * vector v of a sweep-only GMRES, r = v - A GS(v) and e = A^{-1} r from a
+ * tight trace solve.  If a solve with the learned stage misses tol or its
+ * float64 true residual exceeds 10 tol, pt_solve repeats it with the sweeps
+ * only.  Parameter order (float32): w1 (32x8x5), b1 (32), w2 (32x32x5), b2,
+ * w3, b3, w4 (8x32x5), b4 (8); weights are (out, in, k) row-major.
+ * A network is used by one thread at a time: training and solves that use it
+ * must not overlap. */
+typedef enum { PT_LEARN_CORRECT = 0, PT_LEARN_AUGMENT = 1 } pt_learned_mode;
+typedef struct pt_learned pt_learned;
+
+/* Network with He-initialised weights (seeded) and room for `capacity`
+ * training samples; runs on `hip_stream`. */
+pt_status pt_learned_create(int32_t capacity, uint64_t seed, void* hip_stream, pt_learned** out);
+void pt_learned_free(pt_learned* net); /* NULL is a no-op */
+int64_t pt_learned_num_params(void);
+pt_status pt_learned_get_params(const pt_learned* net, float* out);   /* float32 master weights (host) */
+pt_status pt_learned_set_params(pt_learned* net, const float* in);     /* also refreshes the bf16 copy  */
+/* Loss (mean over samples of ||y - t||^2 / ||t||^2) and its gradient with
+ * respect to every parameter, for host inputs x, t of shape (batch, 8, n),
+ * computed by the GPU forward/backward kernels with the bf16 weights. */
+pt_status pt_learned_gradient(pt_learned* net, int32_t batch, int32_t n, const float* x, const float* t,
+                              double* loss, float* grad);
+pt_status pt_learned_forward(pt_learned* net, int32_t batch, int32_t n, const float* x, float* y);
+/* Training pairs (r, e) from solver s on sources f (nrhs <= max_nrhs of s,
+ * host or device array like pt_solve): every Krylov vector of its sweep-only
+ * GMRES, up to the fewest iterations any of the nrhs sources took, gives L-1
+ * samples (one per interface) until the capacity is reached.  All samples of
+ * one network share one interface length NX (PT_EINVAL otherwise); the
+ * network itself applies to any NX.  *added: samples added. */
+pt_status pt_learned_collect(pt_learned* net, pt_solver* s, int32_t nrhs, const double* f, int32_t on_device,
+                             int32_t* added);
+pt_status pt_learned_samples(const pt_learned* net, int32_t* count, int32_t* n);
+/* `steps` Adam steps on random mini-batches; loss_per_step (host, may be NULL). */
+pt_status pt_learned_train(pt_learned* net, int32_t steps, int32_t batch, double lr, double* loss_per_step);
+/* Use `net` as the learned stage of s in the given pt_learned_mode (NULL:
+ * sweeps only).  The network must outlive its use by s. */
+pt_status pt_solver_set_learned(pt_solver* s, pt_learned* net, int32_t mode);
+pt_status pt_learned_save(const pt_learned* net, const char* path);
+pt_status pt_learned_load(pt_learned* net, const char* path);
 
 #ifdef __cplusplus
 }

@@ -12,163 +12,9 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/polar.h"
-#include "plr.h"
-#include "polar_kernels.h"
+#include "solver_internal.h"
 
-using namespace polar;
-
-namespace {
-
-thread_local std::string g_err;
-
-pt_status fail(pt_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define HIPCHK(expr)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess) return fail(PT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-#define PTCHK(expr)               \
-  do {                            \
-    pt_status s_ = (expr);        \
-    if (s_ != PT_OK) return s_;   \
-  } while (0)
-
-struct cd {
-  double re, im;
-};
-inline cd cmk(double r, double i) { return {r, i}; }
-inline cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-inline cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-inline cd operator-(cd a) { return {-a.re, -a.im}; }
-inline double2 d2(cd a) { return make_double2(a.re, a.im); }
-
-// alpha = 1 / (1 + i sigma / omega), sigma = (C/delta)(d/delta)^2
-cd pml_alpha(double d_len, double C, double delta, double omega) {
-  const double s = d_len > 0.0 ? (C / delta) * (d_len / delta) * (d_len / delta) : 0.0;
-  const double t = s / omega;  // 1/(1 + i t) = (1 - i t)/(1 + t^2)
-  return {1.0 / (1.0 + t * t), -t / (1.0 + t * t)};
-}
-
-// distance (in units of h) of a grid position beyond the physical segment [0, n+1]
-double beyond(double pos, int n) { return std::max(0.0, std::max(-pos, pos - (n + 1))); }
-
-struct Layer {
-  int own_start, n, top_ext, bot_ext, R, rowbase;
-  int r0, r1, rn, rn1;  // local rows of the paper's j = 0, 1, n, n+1 (-1 if absent)
-};
-
-struct Launch {
-  int job0 = 0, njobs = 0, maxterms = 0;
-  bool plr = false;          // job terms point at compressed blocks
-  double mat_elems = 0;      // matrix entries streamed by one launch
-  double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
-};
-
-struct ProfPending {
-  int ev;  // index of the event pair
-  double bytes, flops;
-};
-
-// block types per layer; each is a 2x2 arrangement of NX x NX blocks
-enum { T_DN = 0, B_UP = 1, T_UP = 2, B_DN = 3 };
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t n = 0;
-  hipError_t alloc(size_t count) {
-    n = count;
-    if (count == 0) return hipSuccess;
-    return hipMalloc((void**)&p, count * sizeof(T));
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-};
-
-}  // namespace
-
-struct pt_solver {
-  // problem
-  int nx = 0, nz = 0, npml = 0, NX = 0, NZ = 0, L = 0;
-  double h = 0, omega = 0, C = 0;
-  pt_options opt{};
-  hipStream_t st = nullptr;
-  int device = 0;
-  std::vector<Layer> lay;
-  int sumR = 0, Rmax = 0;
-  int64_t Nt = 0;  // complex entries of one polarized vector
-  bool f32 = false;
-  double setup_ms = 0;
-
-  // coefficients
-  std::vector<cd> lcoef, ucoef;  // z couplings of each local row (sumR)
-
-  // device data
-  PlrSet plr;
-  bool use_plr = false;
-  DevBuf<double2> dinv64, blk64;
-  DevBuf<float2> dinv32, blk32;
-  int nblk = 0;
-  std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
-  DevBuf<int32_t> rowmap;
-  DevBuf<int32_t> g_seg, g_row, f_seg, f_row;
-  DevBuf<double> f_sign, g_sign;
-  int n_gather = 0, n_force = 0;
-
-  // job lists
-  std::vector<Job> hjobs;
-  DevBuf<Job> jobs;
-  std::vector<Launch> fwd, bwd, sweep;
-  Launch bterm, opA, opR;
-
-  // live timing of block-apply launches
-  bool prof = false;
-  std::vector<hipEvent_t> ev;  // 2 per slot
-  int ev_next = 0;
-  std::vector<ProfPending> pend;
-  pt_kernel_stats stats{};
-
-  // work
-  DevBuf<double2> W, Bw, fio, uio, s, V, Z, U1, U2, tmp, zeros, x;
-  DevBuf<double2> hbuf, hacc, Hc, sn, g, y;
-  DevBuf<double> nrm, cs, est, beta;
-  DevBuf<int32_t> iters, done, flag;
-  int32_t* h_done = nullptr;  // pinned
-
-  size_t block_elems() const { return (size_t)NX * NX; }
-  const void* blk(int l, int type, int a, int b) const {
-    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
-    if (id < 0) return nullptr;
-    return f32 ? (const void*)(blk32.p + (size_t)id * block_elems()) : (const void*)(blk64.p + (size_t)id * block_elems());
-  }
-  // what a trace-block job term points at: the dense block or its compressed form
-  const void* blk_term(int l, int type, int a, int b) const {
-    if (!use_plr) return blk(l, type, a, b);
-    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
-    return id < 0 ? nullptr : (const void*)plr.block(id);
-  }
-  int blk_id(const void* term) const {
-    if (!use_plr) return -1;
-    return (int)((const PlrBlockDev*)term - plr.d_blocks);
-  }
-  const void* dinv(int l, int r) const {
-    const size_t off = (size_t)(lay[l].rowbase + r) * block_elems();
-    return f32 ? (const void*)(dinv32.p + off) : (const void*)(dinv64.p + off);
-  }
-  // offset of trace segment (half h: 0 down, 1 up; interface k; row a)
-  int64_t seg(int hh, int k, int a) const { return ((int64_t)(hh * (L - 1) + k) * 2 + a) * NX; }
-};
-
-namespace {
+namespace polar_impl {
 
 // ---------------------------------------------------------------------------
 // geometry of one block-apply launch
@@ -872,7 +718,7 @@ pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2*
 
 // Flexible GMRES (right preconditioning, classical Gram-Schmidt applied twice,
 // x0 = 0, no restart) on A x = s for nrhs independent right-hand sides.
-pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv) {
+pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned) {
   hipStream_t st = S->st;
   const int64_t N = S->Nt;
   const int m = S->opt.maxit;
@@ -880,12 +726,23 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv) {
   HIPCHK(launch_knorm(S->s.p, S->beta.p, nrhs, N, st));
   HIPCHK(launch_kscale(S->V.p, S->s.p, S->beta.p, nrhs, N, st));
   HIPCHK(launch_kinit(S->g.p, S->beta.p, S->done.p, S->iters.p, S->est.p, m, nrhs, st));
+  if (learned) PTCHK(learned_begin(S, nrhs));
   all_conv = false;
   for (int j = 0; j < m; ++j) {
     double2* vj = S->V.p + (size_t)j * vs;
     double2* zj = S->Z.p + (size_t)j * vs;
-    PTCHK(precondition(S, vj, zj, nrhs));
-    PTCHK(apply_op(S, S->opA, zj, S->tmp.p, nrhs));
+    const bool augment = learned && S->learned_mode == PT_LEARN_AUGMENT;
+    if (augment && (j & 1)) {
+      PTCHK(learned_direction(S, zj, nrhs));
+    } else {
+      PTCHK(precondition(S, vj, zj, nrhs));
+    }
+    if (learned && !augment) {
+      PTCHK(learned_step(S, vj, zj, S->tmp.p, nrhs));
+    } else {
+      PTCHK(apply_op(S, S->opA, zj, S->tmp.p, nrhs));
+      if (augment && !(j & 1)) PTCHK(learned_residual(S, vj, S->tmp.p, nrhs));
+    }
     HIPCHK(launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st));
     for (int pass = 0; pass < 2; ++pass) {
       HIPCHK(launch_kdot(S->V.p, S->tmp.p, S->hbuf.p, j + 1, nrhs, N, st));
@@ -894,7 +751,7 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv) {
     HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, N, st));
     HIPCHK(launch_kscale(S->V.p + (size_t)(j + 1) * vs, S->tmp.p, S->nrm.p, nrhs, N, st));
     HIPCHK(launch_givens(S->Hc.p, S->hacc.p, S->nrm.p, S->cs.p, S->sn.p, S->g.p, S->est.p, S->beta.p, S->iters.p,
-                         S->done.p, S->opt.tol, j, m, nrhs, st));
+                         S->done.p, tol, j, m, nrhs, st));
     HIPCHK(hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool all = true;
@@ -915,7 +772,7 @@ pt_status check_nrhs(const pt_solver* S, int nrhs) {
   return PT_OK;
 }
 
-}  // namespace
+}  // namespace polar_impl
 
 // ===========================================================================
 // C-ABI
@@ -1294,33 +1151,51 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
     ud = S->uio.p;
   }
   bool conv = true;
+  bool used_learned = false;
+  std::vector<double> nr(nrhs), be(nrhs), es(nrhs);
+  std::vector<int32_t> it(nrhs), dn(nrhs), kept(nrhs, 0);
+  // true residual ||s - A x|| / ||s|| in float64, with the GMRES data, to the host
+  auto residuals = [&]() -> pt_status {
+    PTCHK(apply_op(S, S->opA, S->x.p, S->tmp.p, nrhs));
+    HIPCHK(launch_add(S->tmp.p, S->s.p, S->tmp.p, -1.0, (int64_t)nrhs * S->Nt, S->st));
+    HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, S->Nt, S->st));
+    HIPCHK(hipMemcpyAsync(nr.data(), S->nrm.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipMemcpyAsync(be.data(), S->beta.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipMemcpyAsync(es.data(), S->est.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipMemcpyAsync(it.data(), S->iters.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipMemcpyAsync(dn.data(), S->done.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    return PT_OK;
+  };
   if (S->L == 1) {
     // one layer: the local solve is the global solve
     PTCHK(reconstruct(S, fd, nullptr, ud, nrhs));
   } else {
     PTCHK(trace_rhs(S, fd, S->s.p, nrhs));
-    PTCHK(fgmres(S, nrhs, conv));
+    if (S->learned) {
+      // learned stage first; its float64 true residual decides, the sweeps are the fallback
+      PTCHK(fgmres(S, nrhs, conv, S->opt.tol, true));
+      PTCHK(learned_kept(S, nrhs, kept.data()));
+      PTCHK(residuals());
+      bool ok = conv;
+      for (int r = 0; r < nrhs; ++r) {
+        const double rr = be[r] > 0 ? nr[r] / be[r] : 0.0;
+        ok = ok && std::isfinite(rr) && rr <= 10.0 * S->opt.tol + 1e-300;
+      }
+      used_learned = ok;
+    }
+    if (!used_learned) PTCHK(fgmres(S, nrhs, conv, S->opt.tol, false));
     PTCHK(reconstruct(S, fd, S->x.p, ud, nrhs));
   }
   if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, S->st));
   if (info) {
     if (S->L == 1) {
-      for (int r = 0; r < nrhs; ++r) info[r] = pt_rhs_info{0, 1, 0.0, 0.0};
+      for (int r = 0; r < nrhs; ++r) info[r] = pt_rhs_info{0, 1, 0.0, 0.0, 0, 0};
     } else {
-      // true residual ||s - A x|| / ||s|| in float64
-      PTCHK(apply_op(S, S->opA, S->x.p, S->tmp.p, nrhs));
-      HIPCHK(launch_add(S->tmp.p, S->s.p, S->tmp.p, -1.0, (int64_t)nrhs * S->Nt, S->st));
-      HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, S->Nt, S->st));
-      std::vector<double> nr(nrhs), be(nrhs), es(nrhs);
-      std::vector<int32_t> it(nrhs), dn(nrhs);
-      HIPCHK(hipMemcpyAsync(nr.data(), S->nrm.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
-      HIPCHK(hipMemcpyAsync(be.data(), S->beta.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
-      HIPCHK(hipMemcpyAsync(es.data(), S->est.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
-      HIPCHK(hipMemcpyAsync(it.data(), S->iters.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
-      HIPCHK(hipMemcpyAsync(dn.data(), S->done.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
-      HIPCHK(hipStreamSynchronize(S->st));
+      if (!used_learned) PTCHK(residuals());
       for (int r = 0; r < nrhs; ++r)
-        info[r] = pt_rhs_info{it[r], dn[r], es[r], be[r] > 0 ? nr[r] / be[r] : 0.0};
+        info[r] = pt_rhs_info{it[r], dn[r], es[r], be[r] > 0 ? nr[r] / be[r] : 0.0, used_learned ? 1 : 0,
+                              used_learned ? kept[r] : 0};
     }
   }
   HIPCHK(hipStreamSynchronize(S->st));

@@ -1,0 +1,199 @@
+// Internal state of a libpolar solver, shared by the host translation units
+// (solver.hip, learned.hip).  Not part of the public C-ABI.
+#pragma once
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/polar.h"
+#include "plr.h"
+#include "polar_kernels.h"
+
+using namespace polar;
+
+namespace polar_impl {
+
+inline thread_local std::string g_err;
+
+inline pt_status fail(pt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(PT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PTCHK(expr)               \
+  do {                            \
+    pt_status s_ = (expr);        \
+    if (s_ != PT_OK) return s_;   \
+  } while (0)
+
+struct cd {
+  double re, im;
+};
+inline cd cmk(double r, double i) { return {r, i}; }
+inline cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+inline cd operator-(cd a) { return {-a.re, -a.im}; }
+inline double2 d2(cd a) { return make_double2(a.re, a.im); }
+
+// alpha = 1 / (1 + i sigma / omega), sigma = (C/delta)(d/delta)^2
+inline cd pml_alpha(double d_len, double C, double delta, double omega) {
+  const double s = d_len > 0.0 ? (C / delta) * (d_len / delta) * (d_len / delta) : 0.0;
+  const double t = s / omega;  // 1/(1 + i t) = (1 - i t)/(1 + t^2)
+  return {1.0 / (1.0 + t * t), -t / (1.0 + t * t)};
+}
+
+// distance (in units of h) of a grid position beyond the physical segment [0, n+1]
+inline double beyond(double pos, int n) { return std::max(0.0, std::max(-pos, pos - (n + 1))); }
+
+struct Layer {
+  int own_start, n, top_ext, bot_ext, R, rowbase;
+  int r0, r1, rn, rn1;  // local rows of the paper's j = 0, 1, n, n+1 (-1 if absent)
+};
+
+struct Launch {
+  int job0 = 0, njobs = 0, maxterms = 0;
+  bool plr = false;          // job terms point at compressed blocks
+  double mat_elems = 0;      // matrix entries streamed by one launch
+  double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
+};
+
+struct ProfPending {
+  int ev;  // index of the event pair
+  double bytes, flops;
+};
+
+// block types per layer; each is a 2x2 arrangement of NX x NX blocks
+enum { T_DN = 0, B_UP = 1, T_UP = 2, B_DN = 3 };
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)&p, count * sizeof(T));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace polar_impl
+
+using namespace polar_impl;
+
+struct pt_solver {
+  // problem
+  int nx = 0, nz = 0, npml = 0, NX = 0, NZ = 0, L = 0;
+  double h = 0, omega = 0, C = 0;
+  pt_options opt{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  std::vector<Layer> lay;
+  int sumR = 0, Rmax = 0;
+  int64_t Nt = 0;  // complex entries of one polarized vector
+  bool f32 = false;
+  double setup_ms = 0;
+
+  // coefficients
+  std::vector<cd> lcoef, ucoef;  // z couplings of each local row (sumR)
+
+  // device data
+  PlrSet plr;
+  bool use_plr = false;
+  DevBuf<double2> dinv64, blk64;
+  DevBuf<float2> dinv32, blk32;
+  int nblk = 0;
+  std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
+  DevBuf<int32_t> rowmap;
+  DevBuf<int32_t> g_seg, g_row, f_seg, f_row;
+  DevBuf<double> f_sign, g_sign;
+  int n_gather = 0, n_force = 0;
+
+  // job lists
+  std::vector<Job> hjobs;
+  DevBuf<Job> jobs;
+  std::vector<Launch> fwd, bwd, sweep;
+  Launch bterm, opA, opR;
+
+  // learned preconditioner stage (null: sweeps only)
+  pt_learned* learned = nullptr;
+  int learned_mode = PT_LEARN_CORRECT;
+
+  // live timing of block-apply launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // 2 per slot
+  int ev_next = 0;
+  std::vector<ProfPending> pend;
+  pt_kernel_stats stats{};
+
+  // work
+  DevBuf<double2> W, Bw, fio, uio, s, V, Z, U1, U2, tmp, zeros, x;
+  DevBuf<double2> hbuf, hacc, Hc, sn, g, y;
+  DevBuf<double> nrm, cs, est, beta;
+  DevBuf<int32_t> iters, done, flag;
+  int32_t* h_done = nullptr;  // pinned
+
+  size_t block_elems() const { return (size_t)NX * NX; }
+  const void* blk(int l, int type, int a, int b) const {
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    if (id < 0) return nullptr;
+    return f32 ? (const void*)(blk32.p + (size_t)id * block_elems()) : (const void*)(blk64.p + (size_t)id * block_elems());
+  }
+  // what a trace-block job term points at: the dense block or its compressed form
+  const void* blk_term(int l, int type, int a, int b) const {
+    if (!use_plr) return blk(l, type, a, b);
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    return id < 0 ? nullptr : (const void*)plr.block(id);
+  }
+  int blk_id(const void* term) const {
+    if (!use_plr) return -1;
+    return (int)((const PlrBlockDev*)term - plr.d_blocks);
+  }
+  const void* dinv(int l, int r) const {
+    const size_t off = (size_t)(lay[l].rowbase + r) * block_elems();
+    return f32 ? (const void*)(dinv32.p + off) : (const void*)(dinv64.p + off);
+  }
+  // offset of trace segment (half h: 0 down, 1 up; interface k; row a)
+  int64_t seg(int hh, int k, int a) const { return ((int64_t)(hh * (L - 1) + k) * 2 + a) * NX; }
+};
+
+
+namespace polar_impl {
+
+// stages of the online path (solver.hip)
+pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs);
+pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y, int nrhs);
+pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs);
+// flexible GMRES on A x = S->s for nrhs columns; result in S->x.  With
+// `learned`, every preconditioner output goes through the learned stage.
+pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned);
+
+// learned stage (learned.hip)
+// clears the per-RHS counters of steps that kept the correction
+pt_status learned_begin(pt_solver* S, int nrhs);
+// z = GS(v) on entry.  Computes w = A z, r = v - w, c = N(r), A c, and per RHS
+// keeps z += c, w += A c where ||r - A c|| < ||r||.  On return w = A z.
+pt_status learned_step(pt_solver* S, const double2* v, double2* z, double2* w, int nrhs);
+// augmenting form: r = v - w after a sweep step (w = A GS(v)), then z = N(r)
+// as the direction of the next step (counted per RHS not yet converged)
+pt_status learned_residual(pt_solver* S, const double2* v, const double2* w, int nrhs);
+pt_status learned_direction(pt_solver* S, double2* z, int nrhs);
+// per-RHS step counters to the host (asynchronous on the solver stream)
+pt_status learned_kept(pt_solver* S, int nrhs, int32_t* host);
+
+}  // namespace polar_impl

@@ -19,11 +19,15 @@ LIB_PATH = os.path.join(_HERE, "libpolar.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESINGULAR, PT_ENOCONV = range(6)
 PT_F64, PT_F32 = 0, 1
+PT_LEARN_CORRECT, PT_LEARN_AUGMENT = 0, 1
 OP_A, OP_R, OP_DINV, OP_PRECOND = 0, 1, 2, 3
 ROWS = {"0": 0, "1": 1, "n": 2, "n+1": 3}
 
 EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", "pt_get_layout", "pt_get_block",
-           "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct", "pt_profile", "pt_profile_read")
+           "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct", "pt_profile", "pt_profile_read",
+           "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
+           "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
+           "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load")
 
 
 class PtProblem(C.Structure):
@@ -37,7 +41,8 @@ class PtOptions(C.Structure):
 
 
 class PtRhsInfo(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("est", C.c_double), ("relres", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("est", C.c_double), ("relres", C.c_double),
+                ("learned", C.c_int32), ("learned_steps", C.c_int32)]
 
 
 class PtLayout(C.Structure):
@@ -92,6 +97,22 @@ def lib():
         L.pt_reconstruct.argtypes = [vp, i32, vp, vp, vp, i32]
         L.pt_profile.argtypes = [vp, i32]
         L.pt_profile_read.argtypes = [vp, C.POINTER(PtKernelStats)]
+        fp = C.POINTER(C.c_float)
+        L.pt_learned_create.argtypes = [i32, C.c_uint64, vp, C.POINTER(vp)]
+        L.pt_learned_free.argtypes = [vp]
+        L.pt_learned_free.restype = None
+        L.pt_learned_num_params.argtypes = []
+        L.pt_learned_num_params.restype = C.c_int64
+        L.pt_learned_get_params.argtypes = [vp, fp]
+        L.pt_learned_set_params.argtypes = [vp, fp]
+        L.pt_learned_gradient.argtypes = [vp, i32, i32, fp, fp, dp, fp]
+        L.pt_learned_forward.argtypes = [vp, i32, i32, fp, fp]
+        L.pt_learned_collect.argtypes = [vp, vp, i32, vp, i32, C.POINTER(i32)]
+        L.pt_learned_samples.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.pt_learned_train.argtypes = [vp, i32, i32, C.c_double, dp]
+        L.pt_solver_set_learned.argtypes = [vp, vp, i32]
+        L.pt_learned_save.argtypes = [vp, C.c_char_p]
+        L.pt_learned_load.argtypes = [vp, C.c_char_p]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is C.c_int:  # default
@@ -213,7 +234,8 @@ class Solver:
         u = self._out(keep, dev, (n, self.NZ, self.NX))
         info = (PtRhsInfo * n)()
         _check(self._lib.pt_solve(self._h, n, p, self._ptr(u, dev), dev, info), allow=(PT_ENOCONV,))
-        infos = [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres} for i in info]
+        infos = [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
+                  "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in info]
         return (u[0] if single else u), infos
 
     def apply(self, op: int, x):
@@ -244,3 +266,97 @@ class Solver:
         u = self._out(kf, dev, (n, self.NZ, self.NX))
         _check(self._lib.pt_reconstruct(self._h, n, pf, px, self._ptr(u, dev), dev))
         return u
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Learned:
+    """The learned preconditioner stage: a 1D CNN along the interfaces (8 -> 32 -> 32 -> 32 -> 8 channels,
+    kernel 5), trained on the GPU from the solver's own Krylov vectors and applied as z = GS(v) + N(v)."""
+
+    def __init__(self, capacity: int = 4096, seed: int = 0, stream=None):
+        self._lib = lib()
+        h_ = C.c_void_p()
+        _check(self._lib.pt_learned_create(int(capacity), int(seed), C.c_void_p(stream or 0), C.byref(h_)))
+        self._h = h_
+        self.nparams = int(self._lib.pt_learned_num_params())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pt_learned_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        """float32 master weights in the order w1, b1, w2, b2, w3, b3, w4, b4 (w: c_out x c_in x 5)."""
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(self._lib.pt_learned_get_params(self._h, _fptr(out)))
+        return out
+
+    @params.setter
+    def params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters")
+        _check(self._lib.pt_learned_set_params(self._h, _fptr(p)))
+
+    def forward(self, x):
+        """Network output for samples x (batch, 8, n) float32 (host)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.empty_like(x)
+        _check(self._lib.pt_learned_forward(self._h, x.shape[0], x.shape[2], _fptr(x), _fptr(y)))
+        return y
+
+    def gradient(self, x, t):
+        """(loss, gradient of every parameter) for samples x and targets t (batch, 8, n)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = C.c_double()
+        _check(self._lib.pt_learned_gradient(self._h, x.shape[0], x.shape[2], _fptr(x), _fptr(t), C.byref(loss),
+                                             _fptr(g)))
+        return loss.value, g
+
+    def collect(self, solver: "Solver", f) -> int:
+        """Add training pairs from the Krylov vectors of a sweep-only solve of the sources f."""
+        p, dev, keep, n = solver._prep(f, (solver.NZ, solver.NX))
+        added = C.c_int32()
+        _check(self._lib.pt_learned_collect(self._h, solver._h, n, p, dev, C.byref(added)))
+        return added.value
+
+    def samples(self):
+        cnt, n = C.c_int32(), C.c_int32()
+        _check(self._lib.pt_learned_samples(self._h, C.byref(cnt), C.byref(n)))
+        return cnt.value, n.value
+
+    def train(self, steps: int, batch: int = 32, lr: float = 1e-3) -> np.ndarray:
+        losses = np.empty(max(int(steps), 1), dtype=np.float64)
+        _check(self._lib.pt_learned_train(self._h, int(steps), int(batch), float(lr),
+                                          losses.ctypes.data_as(C.POINTER(C.c_double))))
+        return losses[:steps]
+
+    def attach(self, solver: "Solver", mode: str = "correct"):
+        """Use this network as the learned stage of `solver`: mode 'augment' (extra GMRES directions)
+        or 'correct' (guarded correction of every sweep step)."""
+        m = {"correct": PT_LEARN_CORRECT, "augment": PT_LEARN_AUGMENT}[mode]
+        _check(self._lib.pt_solver_set_learned(solver._h, self._h, m))
+        solver._learned = self
+
+    @staticmethod
+    def detach(solver: "Solver"):
+        _check(solver._lib.pt_solver_set_learned(solver._h, None, PT_LEARN_CORRECT))
+        solver._learned = None
+
+    def save(self, path: str):
+        _check(self._lib.pt_learned_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        _check(self._lib.pt_learned_load(self._h, os.fsencode(path)))

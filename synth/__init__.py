@@ -252,3 +252,37 @@ def config_small(nx: int = 24, nz: int = 30, npml: int = 5, L: int = 3, seed: in
     prob = Problem(f"small-{nx}x{nz}-L{L}", nx, nz, npml, h, omega, L, _pml_C(c), c, meta={"seed": seed})
     f = random_sources(prob, nrhs, seed + 1)
     return prob, f
+
+
+def learned_model(index: int, n: int = 256, L: int = 8, npml: int = 20, nrhs: int = 16,
+                  seed: int = 5) -> tuple[Problem, np.ndarray]:
+    """One model of the learned-stage workload: n x n interior, L layers, nrhs Gaussian sources.
+
+    Even indices draw a smooth-bump medium (as config2: h = 1/n, c ~ 1), odd
+    indices a dipping, faulted layered section (as config3, scaled to a 12 km
+    square: h = 12000/n m).  omega gives 10 points per wavelength at the
+    minimum velocity.  Sources (sigma = 2h) sit at uniform random interior
+    positions at least 3 sigma + h from the PML.  Model i uses the generator
+    seeded with (seed, i): training and held-out sets take disjoint index ranges.
+    """
+    rng = np.random.default_rng([seed, index])
+    if index % 2 == 0:
+        h = 1.0 / n
+        cp = bump_medium(n, n, h, rng)
+        kind = "bumps"
+    else:
+        h = 12000.0 / n
+        cp = layered_medium(n, n, h, rng)
+        kind = "layered"
+    c = normal_extend(cp, npml)
+    omega = 2 * math.pi * float(cp.min()) / (10.0 * h)
+    prob = Problem(f"{kind}{index}-{n + 2 * npml}sq-L{L}", n, n, npml, h, omega, L, _pml_C(c), c,
+                   meta={"seed": seed, "index": index, "kind": kind})
+    sig = 2 * h
+    lo, hi = 3 * sig + h, (n + 1) * h - 3 * sig - h
+    xs = rng.uniform(lo, hi, nrhs)
+    zs = rng.uniform(lo, hi, nrhs)
+    f = np.zeros((nrhs, prob.NZ, prob.NX), dtype=np.complex128)
+    for j in range(nrhs):
+        f[j] = gaussian_source(prob, xs[j], zs[j], sig)
+    return prob, f

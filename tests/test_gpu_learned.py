@@ -1,0 +1,169 @@
+"""The learned preconditioner stage on the GPU: network parity with the FP64 oracle network
+(bf16-rounded weights on both sides), training, and solves that use it.
+
+Tolerances: the GPU network reads bfloat16 weights and accumulates in float32;
+the oracle runs the same bf16-rounded weights in float64, so outputs and
+gradients agree to float32 accumulation error (<= 1e-4 relative, norm-wise).
+A solve with the learned stage must still reach the float64 bar against the
+direct solve (<= 1e-8 relative), whether the learned iteration is accepted or
+the library falls back to the sweeps-only iteration.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn
+from oracle.direct import DirectSolver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1410_5910_amd")
+
+CH = (8, 32, 32, 32, 8)
+K = 5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def unflatten(flat, bf16=True):
+    ps, o = [], 0
+    for ci, co in zip(CH[:-1], CH[1:]):
+        w = flat[o:o + co * ci * K].astype(np.float64).reshape(co, ci, K)
+        o += co * ci * K
+        b = flat[o:o + co].astype(np.float64)
+        o += co
+        ps.append((cnn.bf16_round(w) if bf16 else w, b))
+    assert o == flat.size
+    return ps
+
+
+def flatten(grads):
+    return np.concatenate([np.concatenate([dw.ravel(), db.ravel()]) for dw, db in grads])
+
+
+@pytest.fixture(scope="module")
+def net():
+    print("[gpu] learned: create network", flush=True)
+    N = P.Learned(capacity=2048, seed=5)
+    # non-zero biases so that they are exercised
+    p = N.params
+    rng = np.random.default_rng(1)
+    o = 0
+    for ci, co in zip(CH[:-1], CH[1:]):
+        o += co * ci * K
+        p[o:o + co] = 0.1 * rng.standard_normal(co).astype(np.float32)
+        o += co
+    N.params = p
+    return N
+
+
+def test_param_count(net):
+    assert net.nparams == sum(co * ci * K + co for ci, co in zip(CH[:-1], CH[1:]))
+
+
+@pytest.mark.parametrize("B,n", [(1, 7), (3, 70), (2, 300)])
+def test_forward_matches_oracle(net, B, n):
+    rng = np.random.default_rng(B * 1000 + n)
+    x = rng.standard_normal((B, 8, n)).astype(np.float32)
+    y = net.forward(x)
+    ref, _ = cnn.forward(unflatten(net.params), x.astype(np.float64))
+    assert rel(y, ref) < 1e-4, rel(y, ref)
+
+
+@pytest.mark.parametrize("B,n", [(1, 9), (4, 70), (3, 300)])
+def test_gradient_matches_oracle(net, B, n):
+    rng = np.random.default_rng(7 * B + n)
+    x = rng.standard_normal((B, 8, n)).astype(np.float32)
+    t = rng.standard_normal((B, 8, n)).astype(np.float32)
+    loss, g = net.gradient(x, t)
+    ps = unflatten(net.params)
+    y, acts = cnn.forward(ps, x.astype(np.float64))
+    ref_loss = cnn.loss(y, t.astype(np.float64))
+    ref_g = flatten(cnn.backward(ps, acts, cnn.loss_grad(y, t.astype(np.float64))))
+    assert abs(loss - ref_loss) < 1e-5 * ref_loss
+    assert rel(g, ref_g) < 1e-4, rel(g, ref_g)
+    # every layer's weight and bias gradient, not just the total
+    o = 0
+    for ci, co in zip(CH[:-1], CH[1:]):
+        for size in (co * ci * K, co):
+            assert rel(g[o:o + size], ref_g[o:o + size]) < 1e-3
+            o += size
+
+
+def test_save_load_roundtrip(net, tmp_path):
+    p0 = net.params
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    other = P.Learned(capacity=8, seed=99)
+    assert rel(other.params, p0) > 0.1
+    other.load(path)
+    assert np.array_equal(other.params, p0)
+    x = np.random.default_rng(3).standard_normal((2, 8, 40)).astype(np.float32)
+    assert np.array_equal(other.forward(x), net.forward(x))
+
+
+def test_bad_arguments_rejected(net):
+    with pytest.raises(P.PolarError):
+        P.Learned(capacity=0)
+    with pytest.raises(P.PolarError):
+        net.train(1, batch=4)  # no samples collected yet in this network
+    with pytest.raises(ValueError):
+        net.params = np.zeros(3, dtype=np.float32)
+
+
+def test_bad_mode_rejected(net):
+    prob, _ = synth.config_small(nx=24, nz=30, npml=5, L=3, seed=2)
+    gs = P.Solver.from_problem(prob)
+    assert gs._lib.pt_solver_set_learned(gs._h, net._h, 7) == P.polar.PT_EINVAL
+    gs.close()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A network trained on the method's own pairs from 8 small models of both medium types."""
+    N = P.Learned(capacity=20000, seed=3)
+    for i in range(8):
+        prob, f = synth.learned_model(i, n=96, L=4, npml=10, nrhs=4)
+        print(f"[gpu] learned: collect {prob.name}", flush=True)
+        gs = P.Solver.from_problem(prob, max_nrhs=4, tol=1e-10, maxit=60)
+        added = N.collect(gs, f)
+        assert added > 0 and added % (prob.L - 1) == 0
+        gs.close()
+    cnt, n = N.samples()
+    assert n == 116 and cnt > 0
+    losses = N.train(400, batch=32, lr=2e-3)
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() < 0.9 * losses[:10].mean()
+    return N
+
+
+@pytest.mark.parametrize("mode", ["correct", "augment"])
+def test_learned_solve_matches_direct_and_reports_gain(trained, mode):
+    """Held-out models at a larger size than the training ones: both learned forms reach the float64 bar
+    against the direct solve; the iterations and time with and without the network are printed."""
+    for idx in (1001, 1002):
+        prob, f = synth.learned_model(idx, n=160, L=4, npml=10, nrhs=4)
+        print(f"[gpu] learned eval {mode} {prob.name}", flush=True)
+        gs = P.Solver.from_problem(prob, max_nrhs=4, tol=1e-10, maxit=60)
+        u0, info0 = gs.solve(f)
+        trained.attach(gs, mode)
+        u1, info1 = gs.solve(f)
+        P.Learned.detach(gs)
+        u2, info2 = gs.solve(f)  # detached again: the sweeps-only path is unchanged
+        d = DirectSolver(prob)
+        for r in range(f.shape[0]):
+            ref = d.solve(f[r])
+            assert rel(u0[r], ref) < 1e-8
+            assert rel(u1[r], ref) < 1e-8, (r, info1[r])
+            assert info2[r]["iters"] == info0[r]["iters"] and not info2[r]["learned"]
+        it0 = [i["iters"] for i in info0]
+        it1 = [i["iters"] for i in info1]
+        ls = [i["learned_steps"] for i in info1]
+        acc = [i["learned"] for i in info1]
+        if all(acc):
+            assert all(0 <= s <= i for s, i in zip(ls, it1))
+        print(f"[gpu]   sweeps-only iters {it0} | learned ({mode}) iters {it1} network steps {ls} accepted {acc}",
+              flush=True)
+        gs.close()
