@@ -65,9 +65,16 @@ typedef enum {
 
 typedef enum {
   PT_F64 = 0,        /* every block apply and local solve in complex float64     */
-  PT_F32 = 1         /* Green's blocks and local factors stored and applied in
+  PT_F32 = 1,        /* Green's blocks and local factors stored and applied in
                         complex float32 (FP32 accumulation); Krylov vectors,
                         Arnoldi, least squares and true residuals stay float64 */
+  PT_SPLIT_BF16 = 2  /* mixed: the Gauss-Seidel preconditioner (sweeps and
+                        reflection terms) applies the trace blocks as split
+                        bfloat16 pairs (hi + lo) on MFMA with float32
+                        accumulation; local solves, the operator A inside GMRES
+                        and everything else stay float64, so flexible GMRES
+                        converges to the float64 solution (both block copies
+                        are kept: 1.5x the float64 block memory)            */
 } pt_precision;
 
 /* One Helmholtz problem (paper Section 2.1; Alg. 1 inputs m, omega). */

@@ -328,6 +328,9 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
 // product is four real MFMAs, Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br,
 // issued so that consecutive MFMAs update different accumulators.
 typedef double d4v __attribute__((ext_vector_type(4)));
+// a global-memory view of a block: loads through it compile to global_load, not flat_load
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v gd2;
 constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 
@@ -370,38 +373,50 @@ __global__ __launch_bounds__(kThreads) void block_mfma64_kernel(const Job* __res
 
   const int nchunk_t = (n + kMmK - 1) / kMmK;
   const int nchunks = J.nterms * nchunk_t;
-  double2 pa[4], pb[BPT];
+  // Raw loads of the chunk in flight, all unconditional (indices clamped into
+  // the block and vectors): masking and the combination Q + beta S wait until
+  // the chunk is staged, so all its loads are in flight together.
+  double2 pa[4], pq[BPT], ps[BPT];
+  int c0f = 0;
+  bool has_q = false, has_s = false;
+  double2 be = make_double2(0.0, 0.0);
   auto fetch = [&](int q) {
     const int t = q / nchunk_t;
-    const int c0 = (q - t * nchunk_t) * kMmK;
-    const double2* __restrict__ M = reinterpret_cast<const double2*>(J.M[t]) + (size_t)arow * n;
-    const VecRef qr = J.Q[t];
-    const VecRef svr = J.S[t];
-    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
-    const double2* __restrict__ sp = svr.buf >= 0 ? base_of(bases, svr.buf) + svr.off : nullptr;
-    const double2 be = J.beta[t];
+    c0f = (q - t * nchunk_t) * kMmK;
+    const gd2* __restrict__ M =
+        reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * n;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int c = c0 + sc + u;
-      pa[u] = (c < n && arow_ok) ? M[c] : make_double2(0.0, 0.0);
+      const d2v a = M[min(c0f + sc + u, n - 1)];
+      pa[u] = make_double2(a.x, a.y);
     }
+    const VecRef qr = J.Q[t];
+    const VecRef svr = J.S[t];
+    has_q = qr.buf >= 0;
+    has_s = svr.buf >= 0;
+    be = J.beta[t];
+    const int64_t cb = (int64_t)min(brhs, nrhs - 1) * ld;
+    if (has_q) {
+      const double2* __restrict__ qp = base_of(bases, qr.buf) + qr.off + cb;
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-      const int c = c0 + bc + u;
-      double2 v = make_double2(0.0, 0.0);
-      if (c < n && brhs_ok) {
-        if (qp) v = qp[(int64_t)brhs * ld + c];
-        if (sp) v = cadd(v, cmul(be, sp[(int64_t)brhs * ld + c]));
-      }
-      pb[u] = v;
+      for (int u = 0; u < BPT; ++u) pq[u] = qp[min(c0f + bc + u, n - 1)];
+    }
+    if (has_s) {
+      const double2* __restrict__ sp = base_of(bases, svr.buf) + svr.off + cb;
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) ps[u] = sp[min(c0f + bc + u, n - 1)];
     }
   };
   if (nchunks > 0) fetch(0);
   for (int q = 0; q < nchunks; ++q) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) As[sc + u][sr] = pa[u];
+    for (int u = 0; u < 4; ++u) As[sc + u][sr] = (arow_ok && c0f + sc + u < n) ? pa[u] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) Bs[bc + u][bq] = pb[u];
+    for (int u = 0; u < BPT; ++u) {
+      double2 v = has_q ? pq[u] : make_double2(0.0, 0.0);
+      if (has_s) v = cadd(v, cmul(be, ps[u]));
+      Bs[bc + u][bq] = (brhs_ok && c0f + bc + u < n) ? v : make_double2(0.0, 0.0);
+    }
     __syncthreads();
     if (q + 1 < nchunks) fetch(q + 1);  // next chunk in flight during the MFMAs
 #pragma unroll

@@ -52,6 +52,16 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
                               Bases bases, bool f32, hipStream_t st, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
 
+// Split-bfloat16 block apply (split.hip): the same job semantics as
+// launch_block_apply, with every M_t pointing at the split planes of a block
+// written by launch_split_planes.
+hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
+                                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// bfloat16 elements of the split planes of one n x n block
+size_t split_block_elems(int n);
+// nblk row-major complex float64 n x n blocks -> their split planes (dst: nblk * split_block_elems(n))
+hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, hipStream_t st);
+
 // ---------------------------------------------------------- setup kernels
 // Per-layer Gauss-Jordan inversion with partial pivoting of nb dense n x n
 // column-major matrices.  One call performs elimination step k on every

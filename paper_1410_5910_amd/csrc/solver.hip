@@ -104,18 +104,23 @@ pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases 
   // with profiling on, the dispatch itself stamps e0 / e1 at kernel start / end
   if (Lc.plr)
     HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
+  else if (Lc.split)
+    HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
   else
     HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   if (S->prof) {
-    const double es = S->f32 ? 8.0 : 16.0;
+    // bytes per stored complex entry: 4 bfloat16 planes, float32 or float64 pairs
+    const double es = Lc.split ? 8.0 : S->f32 ? 8.0 : 16.0;
     S->pend.push_back(ProfPending{slot, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
                                   8.0 * Lc.mat_elems * nrhs});
   }
   return PT_OK;
 }
 
-Launch push_launch(pt_solver* S, const std::vector<Job>& js, bool plr_terms = false) {
+Launch push_launch(pt_solver* S, const std::vector<Job>& js, bool plr_terms = false, bool split_terms = false) {
   Launch Lc;
+  Lc.split = split_terms && S->split;
+  if (Lc.split) plr_terms = false;
   Lc.job0 = (int)S->hjobs.size();
   Lc.njobs = (int)js.size();
   for (const Job& j : js) Lc.maxterms = std::max(Lc.maxterms, j.nterms);
@@ -151,7 +156,8 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
   const size_t N = (size_t)(p->nx + 2 * p->npml) * (p->nz + 2 * p->npml);
   for (size_t e = 0; e < N; ++e)
     if (!(p->c[e] > 0) || !std::isfinite(p->c[e])) return fail(PT_EINVAL, "velocity must be positive and finite");
-  if (o->precision != PT_F64 && o->precision != PT_F32) return fail(PT_EINVAL, "unknown precision");
+  if (o->precision != PT_F64 && o->precision != PT_F32 && o->precision != PT_SPLIT_BF16)
+    return fail(PT_EINVAL, "unknown precision");
   if (o->gs_iters < 0 || o->gs_iters > 4) return fail(PT_EINVAL, "gs_iters must be in 0..4");
   if (o->maxit < 1 || o->maxit > 200) return fail(PT_EINVAL, "maxit must be in 1..200");
   if (!(o->tol >= 0)) return fail(PT_EINVAL, "tol must be >= 0");
@@ -547,7 +553,8 @@ void build_online_jobs(pt_solver* S) {
       Job j = empty_job();
       j.Y = vr(2, S->seg(0, kd, a));
       j.P = j.Y;
-      for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(kd, T_DN, a, b), vr(2, S->seg(0, kd - 1, b)), vr(1, S->seg(1, kd - 1, b)), one);
+      for (int b = 0; b < 2; ++b)
+        add_term(j, S->blk_pre(kd, T_DN, a, b), vr(2, S->seg(0, kd - 1, b)), vr(1, S->seg(1, kd - 1, b)), one);
       js.push_back(j);
     }
     for (int a = 0; a < 2; ++a) {
@@ -555,10 +562,10 @@ void build_online_jobs(pt_solver* S) {
       j.Y = vr(2, S->seg(1, ku, a));
       j.P = j.Y;
       for (int b = 0; b < 2; ++b)
-        add_term(j, S->blk_term(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
+        add_term(j, S->blk_pre(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
       js.push_back(j);
     }
-    S->sweep.push_back(push_launch(S, js, true));
+    S->sweep.push_back(push_launch(S, js, true, true));
   }
   // reflection terms of a Gauss-Seidel pass: cur = r + (B_up - J0) a^prev, r + (B_dn - J1) d^prev
   {
@@ -568,15 +575,15 @@ void build_online_jobs(pt_solver* S) {
         Job j = empty_job();
         j.Y = vr(2, S->seg(0, k, a));
         j.P = vr(0, S->seg(0, k, a));
-        for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(k, B_UP, a, b), vr(1, S->seg(1, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(j, S->blk_pre(k, B_UP, a, b), vr(1, S->seg(1, k, b)));
         js.push_back(j);
         Job u = empty_job();
         u.Y = vr(2, S->seg(1, k, a));
         u.P = vr(0, S->seg(1, k, a));
-        for (int b = 0; b < 2; ++b) add_term(u, S->blk_term(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
+        for (int b = 0; b < 2; ++b) add_term(u, S->blk_pre(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
         js.push_back(u);
       }
-    S->bterm = push_launch(S, js, true);
+    S->bterm = push_launch(S, js, true, true);
   }
   // polarized operator y = A x (bases 0 = x, 2 = y) and y = R x
   for (int which = 0; which < 2; ++which) {
@@ -801,6 +808,7 @@ void pt_free(pt_solver* S) {
     b->release();
   S->dinv32.release();
   S->blk32.release();
+  S->blkbf.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag}) b->release();
   S->jobs.release();
@@ -965,6 +973,16 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
     if (S->plr.build(ptrs, NX, rmax, opt->plr_eps, (int)std::max(1u, std::min(hw, 16u))) != hipSuccess)
       return bail(fail(PT_ENOMEM, "PLR blocks"));
     S->use_plr = true;
+  }
+
+  // split-bfloat16 planes of the blocks for the preconditioner of the mixed form
+  if (opt->precision == PT_SPLIT_BF16 && S->L >= 2) {
+    if (S->blkbf.alloc((size_t)S->nblk * split_block_elems(NX)) != hipSuccess)
+      return bail(fail(PT_ENOMEM, "split-bfloat16 blocks"));
+    if (launch_split_planes(S->blk64.p, S->blkbf.p, S->nblk, NX, S->st) != hipSuccess ||
+        hipStreamSynchronize(S->st) != hipSuccess)
+      return bail(fail(PT_EHIP, "split-bfloat16 conversion"));
+    S->split = true;
   }
 
   // reduced-precision copies of the factors and blocks

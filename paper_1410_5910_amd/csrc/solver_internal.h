@@ -64,6 +64,7 @@ struct Layer {
 struct Launch {
   int job0 = 0, njobs = 0, maxterms = 0;
   bool plr = false;          // job terms point at compressed blocks
+  bool split = false;        // job terms point at split-bfloat16 planes
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
 };
@@ -117,6 +118,8 @@ struct pt_solver {
   bool use_plr = false;
   DevBuf<double2> dinv64, blk64;
   DevBuf<float2> dinv32, blk32;
+  DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
+  bool split = false;
   int nblk = 0;
   std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
   DevBuf<int32_t> rowmap;
@@ -159,6 +162,14 @@ struct pt_solver {
     if (!use_plr) return blk(l, type, a, b);
     const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
     return id < 0 ? nullptr : (const void*)plr.block(id);
+  }
+  const void* blk_split(int l, int type, int a, int b) const {
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    return id < 0 ? nullptr : (const void*)(blkbf.p + (size_t)id * split_block_elems(NX));
+  }
+  // block term of a preconditioner job: the split planes in the mixed form
+  const void* blk_pre(int l, int type, int a, int b) const {
+    return split ? blk_split(l, type, a, b) : blk_term(l, type, a, b);
   }
   int blk_id(const void* term) const {
     if (!use_plr) return -1;

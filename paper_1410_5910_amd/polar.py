@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolar.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESINGULAR, PT_ENOCONV = range(6)
-PT_F64, PT_F32 = 0, 1
+PT_F64, PT_F32, PT_SPLIT_BF16 = 0, 1, 2
 PT_LEARN_CORRECT, PT_LEARN_AUGMENT = 0, 1
 OP_A, OP_R, OP_DINV, OP_PRECOND = 0, 1, 2, 3
 ROWS = {"0": 0, "1": 1, "n": 2, "n+1": 3}
@@ -144,7 +144,7 @@ class Solver:
         self._c = c
         prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
                          c.ctypes.data_as(C.POINTER(C.c_double)))
-        prec = {"f64": PT_F64, "f32": PT_F32}[precision]
+        prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
         opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
                         float(plr_eps), int(plr_rmax))
         h_ = C.c_void_p()

@@ -1,0 +1,116 @@
+"""The mixed form (PT_SPLIT_BF16): Gauss-Seidel preconditioner on split-bfloat16 MFMA blocks,
+everything else in float64.
+
+Tolerances: a split block apply carries about 2^-16 relative error (hi*lo
+terms kept, lo*lo dropped, float32 accumulation), so the preconditioner and
+D^-1 match the float64 oracle to <= 1e-4 relative over whole sweeps; A and R
+stay float64 (<= 1e-10).  Flexible GMRES with float64 A wins the precision
+back: full solves meet the float64 bar, <= 1e-8 relative to the direct solve,
+with at most one extra iteration.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.direct import DirectSolver
+from oracle.polarized import PolarizedSolver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1410_5910_amd")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    # NX = 216: ragged 16-row and 32-column MFMA tiles; L = 6: reflection launches of 20 jobs x 4 row tiles,
+    # so 100 / 200 / 448 sources select the 16- / 32- / 64-column four-wave kernels there and the sweep
+    # launches (4 jobs) the one-wave kernel
+    prob, _ = synth.config_small(nx=200, nz=66, npml=8, L=6, seed=33, nrhs=1)
+    _flush(f"[gpu] split setup {prob.name} NX={prob.NX}")
+    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=448, tol=1e-10, maxit=60)
+    ps = PolarizedSolver(prob)
+    return prob, gs, ps
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 100, 200, 448])
+def test_split_operators_match_oracle(mid, nrhs):
+    prob, gs, ps = mid
+    _flush(f"[gpu] split operators nrhs={nrhs}")
+    rng = np.random.default_rng(nrhs)
+    shp = ps.zeros(nrhs).shape
+    x = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    for code, fn, tol in ((P.OP_A, ps.apply_A, 1e-10), (P.OP_R, ps.apply_R, 1e-10),
+                          (P.OP_DINV, ps.apply_D_inv, 1e-4), (P.OP_PRECOND, ps.precondition, 1e-4)):
+        y = gs.apply(code, x)
+        ref = fn(x)
+        err = rel(y, ref)
+        assert err < tol, (code, err)
+        # every right-hand side, not just the total
+        per = [rel(y[r], ref[r]) for r in range(nrhs)]
+        assert max(per) < 10 * tol, (code, max(per))
+        if code in (P.OP_DINV, P.OP_PRECOND):
+            assert err > 1e-12  # really the reduced-precision path
+
+
+def test_split_solves_match_direct(mid):
+    prob, gs, ps = mid
+    f = synth.random_sources(prob, 20, seed=4)
+    _flush("[gpu] split solve mid, 20 sources")
+    u, info = gs.solve(f)
+    g64 = P.Solver.from_problem(prob, max_nrhs=20, tol=1e-10, maxit=60)
+    u64, info64 = g64.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    for r in range(20):
+        assert rel(u[r], ud[r]) < 1e-8, r
+        assert info[r]["converged"] and info[r]["relres"] < 1e-9
+        assert info[r]["iters"] <= info64[r]["iters"] + 1
+    g64.close()
+
+
+def test_split_small_layer_counts():
+    for L in (2, 3):
+        prob, f = synth.config_small(nx=30, nz=24, npml=5, L=L, nrhs=2, seed=40 + L)
+        _flush(f"[gpu] split small L={L}")
+        gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=2, tol=1e-11, maxit=40)
+        u, info = gs.solve(f)
+        assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+        gs.close()
+
+
+def test_split_bumps440_single_source():
+    prob, f = synth.config2()
+    _flush("[gpu] split bumps-440x440-L8")
+    gs = P.Solver.from_problem(prob, precision="split-bf16", tol=1e-10, maxit=50)
+    u, info = gs.solve(f)
+    err = rel(u, DirectSolver(prob).solve(f))
+    _flush(f"[gpu] split bumps440 rel err {err:.2e}, iters {info[0]['iters']}")
+    assert err < 1e-8
+    gs.close()
+
+
+def test_split_layered_batch_matches_f64():
+    # the bench workload's medium and launch shapes (all 128 sources), checked against the float64 GPU path
+    prob, f = synth.config3()
+    _flush("[gpu] split layered-1240x440-L16, 128 sources")
+    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=40)
+    u, info = gs.solve(f)
+    gs.close()
+    g64 = P.Solver.from_problem(prob, max_nrhs=128, tol=1e-10, maxit=40)
+    u64, info64 = g64.solve(f)
+    g64.close()
+    errs = [rel(u[r], u64[r]) for r in range(128)]
+    its = [i["iters"] for i in info]
+    its64 = [i["iters"] for i in info64]
+    _flush(f"[gpu] split layered max rel diff {max(errs):.2e}; iters {min(its)}..{max(its)} "
+           f"(float64 {min(its64)}..{max(its64)})")
+    assert max(errs) < 1e-8
+    assert all(i["converged"] for i in info)
+    assert max(its) <= max(its64) + 1
