@@ -84,7 +84,15 @@ struct MatT<true> {
 // in LDS, so its latency overlaps the staging.
 constexpr int kGvWaves = 8;                 // rows per workgroup
 constexpr int kGvThreads = kGvWaves * 64;
-constexpr int kGvU = 8;                     // loads in flight per lane and group
+constexpr int kGvU = 8;                     // loads in flight per lane and group (NR <= 4)
+
+// global-memory views of float64 data: loads through them compile to global_load
+// (not flat_load) and may be scheduled across LDS stores
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v gd2;
+__device__ __forceinline__ const gd2* to_gd2(const double2* p) {
+  return reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(p));
+}
 
 // base pointer of a VecRef without dynamic indexing of the by-value kernel argument
 __device__ __forceinline__ double2* base_of(const Bases& b, int buf) {
@@ -96,6 +104,7 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
                                                                 int kc, int nrhs, int64_t ld, Bases bases) {
   using MV = typename MatT<F32>::vec;
   using T = typename MatT<F32>::real;
+  constexpr int U = NR >= 8 ? kGvU / 2 : kGvU;  // matrix loads in flight per lane (registers bound it)
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // kc * NR
 
@@ -119,44 +128,51 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
     const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
     const VecRef qr = J.Q[t];
     const VecRef sr = J.S[t];
-    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
-    const double2* __restrict__ sp = sr.buf >= 0 ? base_of(bases, sr.buf) + sr.off : nullptr;
+    const gd2* __restrict__ qg = qr.buf >= 0 ? to_gd2(base_of(bases, qr.buf) + qr.off) : nullptr;
+    const gd2* __restrict__ sg = sr.buf >= 0 ? to_gd2(base_of(bases, sr.buf) + sr.off) : nullptr;
     const double2 be = J.beta[t];
 #pragma unroll 1
     for (int c0 = 0; c0 < n; c0 += kc) {
       const int kw = min(kc, n - c0);
       const int cnt = lane < kw ? (kw - lane + 63) / 64 : 0;  // columns c0 + lane + 64 i of this row
       // first group of matrix loads goes out before the inputs are staged
-      MV m[kGvU];
+      MV m[U];
 #pragma unroll
-      for (int u = 0; u < kGvU; ++u) m[u] = u < cnt ? Mrow[c0 + lane + 64 * u] : MV{};
+      for (int u = 0; u < U; ++u) m[u] = u < cnt ? Mrow[c0 + lane + 64 * u] : MV{};
       if (!first_chunk) __syncthreads();  // previous chunk fully consumed
       first_chunk = false;
+      // input staging: every load of a column issued before any is combined
+      // (global-address-space views, so they need not wait for the LDS stores)
       for (int c = tid; c < kw; c += kGvThreads) {
         const int cj = c0 + c;
+        d2v vq[NR], vs[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          double2 v = make_double2(0.0, 0.0);
-          if (r0 + r < nrhs) {
-            if (qp) v = qp[(int64_t)(r0 + r) * ld + cj];
-            if (sp) v = cadd(v, cmul(be, sp[(int64_t)(r0 + r) * ld + cj]));
-          }
+          const int64_t e = (int64_t)min(r0 + r, nrhs - 1) * ld + cj;
+          vq[r] = qg ? qg[e] : d2v{0.0, 0.0};
+          vs[r] = sg ? sg[e] : d2v{0.0, 0.0};
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          double2 v = make_double2(vq[r].x, vq[r].y);
+          if (sg) v = cadd(v, cmul(be, make_double2(vs[r].x, vs[r].y)));
+          if (r0 + r >= nrhs) v = make_double2(0.0, 0.0);
           xs[(size_t)c * NR + r] = Cx<T>{(T)v.x, (T)v.y};
         }
       }
       __syncthreads();
-      for (int i0 = 0; i0 < cnt; i0 += kGvU) {
-        MV nx[kGvU];
-        const bool more = i0 + kGvU < cnt;
+      for (int i0 = 0; i0 < cnt; i0 += U) {
+        MV nx[U];
+        const bool more = i0 + U < cnt;
         if (more) {
 #pragma unroll
-          for (int u = 0; u < kGvU; ++u) {
-            const int i = i0 + kGvU + u;
+          for (int u = 0; u < U; ++u) {
+            const int i = i0 + U + u;
             nx[u] = i < cnt ? Mrow[c0 + lane + 64 * i] : MV{};
           }
         }
 #pragma unroll
-        for (int u = 0; u < kGvU; ++u) {
+        for (int u = 0; u < U; ++u) {
           const int i = i0 + u;
           if (i < cnt) {
             const Cx<T> mm{(T)m[u].x, (T)m[u].y};
@@ -167,7 +183,7 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
         }
         if (more) {
 #pragma unroll
-          for (int u = 0; u < kGvU; ++u) m[u] = nx[u];
+          for (int u = 0; u < U; ++u) m[u] = nx[u];
         }
       }
     }
@@ -232,8 +248,8 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
     const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
     const VecRef qr = J.Q[t];
     const VecRef sr = J.S[t];
-    const double2* __restrict__ qp = qr.buf >= 0 ? base_of(bases, qr.buf) + qr.off : nullptr;
-    const double2* __restrict__ sp = sr.buf >= 0 ? base_of(bases, sr.buf) + sr.off : nullptr;
+    const gd2* __restrict__ qg = qr.buf >= 0 ? to_gd2(base_of(bases, qr.buf) + qr.off) : nullptr;
+    const gd2* __restrict__ sg = sr.buf >= 0 ? to_gd2(base_of(bases, sr.buf) + sr.off) : nullptr;
     const double2 be = J.beta[t];
 #pragma unroll 1
     for (int c0 = 0; c0 < n; c0 += kc) {
@@ -243,11 +259,12 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
       for (int c = tid; c < kw * NR; c += kThreads) {
         const int cj = c0 + c / NR;
         const int r = c % NR;
-        double2 v = make_double2(0.0, 0.0);
-        if (r0 + r < nrhs) {
-          if (qp) v = qp[(int64_t)(r0 + r) * ld + cj];
-          if (sp) v = cadd(v, cmul(be, sp[(int64_t)(r0 + r) * ld + cj]));
-        }
+        const int64_t e = (int64_t)min(r0 + r, nrhs - 1) * ld + cj;
+        const d2v vq = qg ? qg[e] : d2v{0.0, 0.0};
+        const d2v vs = sg ? sg[e] : d2v{0.0, 0.0};
+        double2 v = make_double2(vq.x, vq.y);
+        if (sg) v = cadd(v, cmul(be, make_double2(vs.x, vs.y)));
+        if (r0 + r >= nrhs) v = make_double2(0.0, 0.0);
         xs[c] = Cx<T>{(T)v.x, (T)v.y};
       }
       __syncthreads();
@@ -316,34 +333,36 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
 // ----------------------------------------------------------------------------
 // block_apply, many right-hand sides in float64: MFMA form
 // ----------------------------------------------------------------------------
-// One workgroup = 4 waves = a 64-row x TN-right-hand-side output tile of one
-// job (TN = 16, 32 or 64, chosen per launch so that small launches still
-// fill the chip).  The columns of every term are walked in chunks of 16: the
-// 64 x 16 slice of the (row-major) block and the 16 x TN slice of the
-// combined input Q + beta S are staged in LDS (the next chunk is loaded into
-// registers while the current one is multiplied).  Wave w accumulates rows
-// 16w..16w+15 for all TN right-hand sides as TN/16 tiles of
-// v_mfma_f64_16x16x4 (lane l holds A[l%16][l/16] and B[l/16][l%16];
-// accumulator register i of lane l holds C[4i + l/16][l%16]).  A complex
-// product is four real MFMAs, Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br,
-// issued so that consecutive MFMAs update different accumulators.
+// One workgroup = KS groups of 4 waves = a 64-row x TN-right-hand-side output
+// tile of one job (TN = 16, 32 or 64).  The job's columns are walked in chunks
+// of 16 (term by term); k-group g takes chunks g, g + KS, ..., so a launch with
+// few tiles (a local-solve step with few right-hand sides, a sweep step) still
+// has KS times the waves in flight.  Each group stages the 64 x 16 slice of the
+// (row-major) block and the 16 x TN slice of the combined input Q + beta S in
+// its own LDS buffers; all loads of the next chunk are issued before the
+// current chunk's MFMAs, and the combination and tail masking wait until
+// staging.  Wave w of a group accumulates rows 16w..16w+15 for all TN
+// right-hand sides as TN/16 tiles of v_mfma_f64_16x16x4 (lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; accumulator register i of lane l holds
+// C[4i + l/16][l%16]).  A complex product is four real MFMAs, Cr += Ar Br -
+// Ai Bi, Ci += Ar Bi + Ai Br, issued so that consecutive MFMAs update different
+// accumulators.  Groups 1..KS-1 hand their partial tiles to group 0 through
+// LDS, summed in a fixed order: deterministic, no atomics.
 typedef double d4v __attribute__((ext_vector_type(4)));
-// a global-memory view of a block: loads through it compile to global_load, not flat_load
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) const d2v gd2;
 constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 
-template <int TN>
-__global__ __launch_bounds__(kThreads) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+template <int TN, int KS>
+__global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
                                                                  int nrt, int nrhs, int64_t ld, Bases bases) {
   constexpr int NB = TN / 16;           // MFMA tiles per wave
-  constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread
-  __shared__ double2 As[kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
-  __shared__ double2 Bs[kMmK][TN];
-  const int tid = threadIdx.x;
+  constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread of a group
+  __shared__ double2 As[KS][kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
+  __shared__ double2 Bs[KS][kMmK][TN];
+  const int tid = threadIdx.x & 255;    // thread within its k-group
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);  // k-group (wave-uniform)
   int bid = blockIdx.x;
   const int ct = bid % nrt;  // right-hand-side tile
   bid /= nrt;
@@ -373,58 +392,69 @@ __global__ __launch_bounds__(kThreads) void block_mfma64_kernel(const Job* __res
 
   const int nchunk_t = (n + kMmK - 1) / kMmK;
   const int nchunks = J.nterms * nchunk_t;
-  // Raw loads of the chunk in flight, all unconditional (indices clamped into
-  // the block and vectors): masking and the combination Q + beta S wait until
-  // the chunk is staged, so all its loads are in flight together.
-  double2 pa[4], pq[BPT], ps[BPT];
-  int c0f = 0;
-  bool has_q = false, has_s = false;
-  double2 be = make_double2(0.0, 0.0);
-  auto fetch = [&](int q) {
+  const int rounds = (nchunks + KS - 1) / KS;  // the same for every group: barriers stay uniform
+  // Raw loads of a chunk, all unconditional (indices clamped into the block and
+  // vectors): masking and the combination Q + beta S wait until the chunk is
+  // staged, so all its loads are in flight together.
+  struct Stage {
+    double2 pa[4], pq[BPT], ps[BPT];
+    double2 be;
+    int c0;
+    bool live, has_q, has_s;
+  };
+  auto fetch = [&](Stage& S, int q) {
+    S.live = q < nchunks;
+    if (!S.live) return;
     const int t = q / nchunk_t;
-    c0f = (q - t * nchunk_t) * kMmK;
+    S.c0 = (q - t * nchunk_t) * kMmK;
     const gd2* __restrict__ M =
         reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * n;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const d2v a = M[min(c0f + sc + u, n - 1)];
-      pa[u] = make_double2(a.x, a.y);
+      const d2v a = M[min(S.c0 + sc + u, n - 1)];
+      S.pa[u] = make_double2(a.x, a.y);
     }
     const VecRef qr = J.Q[t];
     const VecRef svr = J.S[t];
-    has_q = qr.buf >= 0;
-    has_s = svr.buf >= 0;
-    be = J.beta[t];
+    S.has_q = qr.buf >= 0;
+    S.has_s = svr.buf >= 0;
+    S.be = J.beta[t];
     const int64_t cb = (int64_t)min(brhs, nrhs - 1) * ld;
-    if (has_q) {
-      const double2* __restrict__ qp = base_of(bases, qr.buf) + qr.off + cb;
+    if (S.has_q) {
+      const gd2* __restrict__ qp = to_gd2(base_of(bases, qr.buf) + qr.off + cb);
 #pragma unroll
-      for (int u = 0; u < BPT; ++u) pq[u] = qp[min(c0f + bc + u, n - 1)];
+      for (int u = 0; u < BPT; ++u) {
+        const d2v v = qp[min(S.c0 + bc + u, n - 1)];
+        S.pq[u] = make_double2(v.x, v.y);
+      }
     }
-    if (has_s) {
-      const double2* __restrict__ sp = base_of(bases, svr.buf) + svr.off + cb;
+    if (S.has_s) {
+      const gd2* __restrict__ sp = to_gd2(base_of(bases, svr.buf) + svr.off + cb);
 #pragma unroll
-      for (int u = 0; u < BPT; ++u) ps[u] = sp[min(c0f + bc + u, n - 1)];
+      for (int u = 0; u < BPT; ++u) {
+        const d2v v = sp[min(S.c0 + bc + u, n - 1)];
+        S.ps[u] = make_double2(v.x, v.y);
+      }
     }
   };
-  if (nchunks > 0) fetch(0);
-  for (int q = 0; q < nchunks; ++q) {
+  auto stage = [&](const Stage& S) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) As[sc + u][sr] = (arow_ok && c0f + sc + u < n) ? pa[u] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 4; ++u)
+      As[grp][sc + u][sr] = (S.live && arow_ok && S.c0 + sc + u < n) ? S.pa[u] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
-      double2 v = has_q ? pq[u] : make_double2(0.0, 0.0);
-      if (has_s) v = cadd(v, cmul(be, ps[u]));
-      Bs[bc + u][bq] = (brhs_ok && c0f + bc + u < n) ? v : make_double2(0.0, 0.0);
+      double2 v = S.has_q ? S.pq[u] : make_double2(0.0, 0.0);
+      if (S.has_s) v = cadd(v, cmul(S.be, S.ps[u]));
+      Bs[grp][bc + u][bq] = (S.live && brhs_ok && S.c0 + bc + u < n) ? v : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    if (q + 1 < nchunks) fetch(q + 1);  // next chunk in flight during the MFMAs
+  };
+  auto multiply = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kMmK; kk += 4) {
-      const double2 av = As[kk + (lane >> 4)][wr + (lane & 15)];
+      const double2 av = As[grp][kk + (lane >> 4)][wr + (lane & 15)];
       double2 bv[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = Bs[kk + (lane >> 4)][b * 16 + (lane & 15)];
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[grp][kk + (lane >> 4)][b * 16 + (lane & 15)];
 #pragma unroll
       for (int b = 0; b < NB; ++b) cr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, cr[b], 0, 0, 0);
 #pragma unroll
@@ -434,7 +464,44 @@ __global__ __launch_bounds__(kThreads) void block_mfma64_kernel(const Job* __res
 #pragma unroll
       for (int b = 0; b < NB; ++b) ci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[b].x, ci[b], 0, 0, 0);
     }
+  };
+  Stage s0;
+  fetch(s0, grp);
+  for (int i = 0; i < rounds; ++i) {
+    stage(s0);
     __syncthreads();
+    fetch(s0, (i + 1) * KS + grp);  // next chunk in flight during the MFMAs
+    multiply();
+    __syncthreads();
+  }
+
+  if constexpr (KS > 1) {
+    // partial tiles of groups 1..KS-1 through the (now idle) staging buffers
+    static_assert((KS - 1) * 4 * 64 * NB * 8 * sizeof(double) <= sizeof(As) + sizeof(Bs) || KS == 1,
+                  "reduction does not fit the staging buffers");
+    double* red = reinterpret_cast<double*>(&As[0][0][0]);
+    auto at = [&](int g, int b, int j) -> double& {
+      return red[((((size_t)(g - 1) * 4 + wave) * NB + b) * 8 + j) * 64 + lane];
+    };
+    if (grp > 0)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          at(grp, b, j) = cr[b][j];
+          at(grp, b, 4 + j) = ci[b][j];
+        }
+    __syncthreads();
+    if (grp > 0) return;
+#pragma unroll
+    for (int g = 1; g < KS; ++g)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cr[b][j] += at(g, b, j);
+          ci[b][j] += at(g, b, 4 + j);
+        }
   }
 
   double2* __restrict__ Yb = base_of(bases, J.Y.buf) + J.Y.off;
@@ -467,16 +534,22 @@ hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int n
     const int ntl = (g.n + kMmRows - 1) / kMmRows;
     const int tn = g.mfma;  // right-hand sides per workgroup tile: 16, 32 or 64
     const int nrt = (nrhs + tn - 1) / tn;
-    const dim3 grid2((unsigned)njobs * ntl * nrt);
-    if (tn == 64)
-      hipExtLaunchKernelGGL(block_mfma64_kernel<64>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
-                            nrhs, ld, bases);
-    else if (tn == 32)
-      hipExtLaunchKernelGGL(block_mfma64_kernel<32>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
-                            nrhs, ld, bases);
-    else
-      hipExtLaunchKernelGGL(block_mfma64_kernel<16>, grid2, dim3(kThreads), 0, st, ev0, ev1, 0, jobs, g.n, ntl, nrt,
-                            nrhs, ld, bases);
+    const long tiles = (long)njobs * ntl * nrt;
+    const dim3 grid2((unsigned)tiles);
+    // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
+    const int ks = tiles < 256 ? 4 : tiles < 512 ? 2 : 1;
+#define POLAR_MFMA64(TNV, KSV)                                                                                  \
+  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, jobs, g.n, \
+                        ntl, nrt, nrhs, ld, bases)
+    // (32- and 64-column tiles are only chosen for launches of >= 512 tiles: no split there)
+    if (tn == 64) {
+      POLAR_MFMA64(64, 1);
+    } else if (tn == 32) {
+      POLAR_MFMA64(32, 1);
+    } else {
+      if (ks == 4) POLAR_MFMA64(16, 4); else if (ks == 2) POLAR_MFMA64(16, 2); else POLAR_MFMA64(16, 1);
+    }
+#undef POLAR_MFMA64
   } else {
     const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
     hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32>), grid, dim3(kThreads), (uint32_t)lds, st, ev0, ev1, 0, jobs,
@@ -658,6 +731,69 @@ __global__ void scatter_source_kernel(const double2* __restrict__ f, double2* __
     }
     W[e] = v;
   }
+}
+
+// amax[r * L + l] = max |f[r]|^2 over the owned rows of layer l (fixed-order tree, deterministic)
+__global__ __launch_bounds__(kThreads) void source_activity_kernel(const double2* __restrict__ f,
+                                                                    double* __restrict__ amax,
+                                                                    const int32_t* __restrict__ own_start,
+                                                                    const int32_t* __restrict__ n_own, int L,
+                                                                    int NZ, int NX) {
+  __shared__ double red[kThreads];
+  const int l = blockIdx.x, r = blockIdx.y;
+  const double2* fr = f + ((size_t)r * NZ + own_start[l]) * NX;
+  const int64_t cnt = (int64_t)n_own[l] * NX;
+  // a max that keeps NaN (fmax would drop it): a NaN source must reach every layer
+  auto nmax = [](double a, double b) { return (b > a || b != b) ? b : a; };
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += kThreads) {
+    const double2 v = fr[e];
+    mx = nmax(mx, v.x * v.x + v.y * v.y);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) amax[(size_t)r * L + l] = red[0];
+}
+
+// Layer-compacted sources: column slot j of layer l holds source slot_rhs[l * m + j] (-1: zero)
+__global__ void scatter_slots_kernel(const double2* __restrict__ f, double2* __restrict__ W,
+                                     const int32_t* __restrict__ rowmap, const int32_t* __restrict__ row_layer,
+                                     const int32_t* __restrict__ slot_rhs, int m, int sumR, int NZ, int NX,
+                                     double scale) {
+  const size_t total = (size_t)m * sumR * NX;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % NX);
+    const size_t rg = e / NX;
+    const int gr = (int)(rg % sumR);
+    const int j = (int)(rg / sumR);
+    const int src = rowmap[gr];
+    const int r = slot_rhs[row_layer[gr] * m + j];
+    double2 v = make_double2(0.0, 0.0);
+    if (src >= 0 && r >= 0) {
+      const double2 fv = f[((size_t)r * NZ + src) * NX + i];
+      v = make_double2(scale * fv.x, scale * fv.y);
+    }
+    W[e] = v;
+  }
+}
+
+// s[r][seg] = W[slot of r in the row's layer][row] (zero where r does not touch that layer)
+__global__ void gather_slots_kernel(const double2* __restrict__ W, double2* __restrict__ s,
+                                    const int32_t* __restrict__ seg, const int32_t* __restrict__ row,
+                                    const int32_t* __restrict__ row_layer, const int32_t* __restrict__ rhs_slot,
+                                    int L, int sumR, int NX, int64_t ntrace) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NX) return;
+  const int mi = blockIdx.y;
+  const int r = blockIdx.z;
+  const int g = row[mi];
+  const int j = rhs_slot[(size_t)r * L + row_layer[g]];
+  const int64_t si = (int64_t)r * ntrace + (int64_t)seg[mi] * NX + i;
+  s[si] = j >= 0 ? W[((int64_t)j * sumR + g) * NX + i] : make_double2(0.0, 0.0);
 }
 
 __global__ void gather_owned_kernel(const double2* __restrict__ W, double2* __restrict__ u,
@@ -956,6 +1092,30 @@ hipError_t launch_scatter_source(const double2* f, double2* W, const int32_t* ro
                                  int nrhs, double scale, hipStream_t st) {
   hipLaunchKernelGGL(scatter_source_kernel, dim3(grid_for((int64_t)nrhs * sumR * NX)), dim3(kThreads), 0, st, f,
                      W, rowmap, sumR, NZ, NX, nrhs, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_activity(const double2* f, double* amax, const int32_t* own_start, const int32_t* n_own,
+                                  int L, int NZ, int NX, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(source_activity_kernel, dim3(L, nrhs), dim3(kThreads), 0, st, f, amax, own_start, n_own, L, NZ,
+                     NX);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_slots(const double2* f, double2* W, const int32_t* rowmap, const int32_t* row_layer,
+                                const int32_t* slot_rhs, int m, int sumR, int NZ, int NX, double scale,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(scatter_slots_kernel, dim3(grid_for((int64_t)m * sumR * NX)), dim3(kThreads), 0, st, f, W,
+                     rowmap, row_layer, slot_rhs, m, sumR, NZ, NX, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_slots(const double2* W, double2* s, const int32_t* seg, const int32_t* row,
+                               const int32_t* row_layer, const int32_t* rhs_slot, int nmap, int L, int sumR, int NX,
+                               int64_t ntrace, int nrhs, hipStream_t st) {
+  if (nmap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_slots_kernel, dim3((NX + 255) / 256, nmap, nrhs), dim3(256), 0, st, W, s, seg, row,
+                     row_layer, rhs_slot, L, sumR, NX, ntrace);
   return hipGetLastError();
 }
 

@@ -42,8 +42,9 @@ struct ApplyGeom {
   int ntiles;   // row tiles per job: ceil(n / 8) for nr <= 4 (one row per wave), ceil(n / 64) otherwise
   int kc;       // columns staged in LDS per chunk
   int nr;       // right-hand sides per workgroup (template width)
-  int mfma;     // float64 with many right-hand sides: MFMA kernel with this many right-hand
-                // sides per workgroup tile (16, 32 or 64); 0: not used
+  int mfma;     // float64 with more than 4 right-hand sides: MFMA kernel with this many
+                // right-hand sides per workgroup tile (16, 32 or 64); 0: not used
+  int gemv;     // 1: the row-streaming kernel (nr <= 4 right-hand sides per pass)
 };
 
 // ---------------------------------------------------------------- block apply
@@ -54,9 +55,13 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
 
 // Split-bfloat16 block apply (split.hip): the same job semantics as
 // launch_block_apply, with every M_t pointing at the split planes of a block
-// written by launch_split_planes.
+// written by launch_split_planes.  part (may be null): workspace of
+// split_kslices(njobs, n, nrhs) * njobs * nrhs * n complex floats for partial
+// tiles of launches too small to fill the chip.
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
-                                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                                    float2* part = nullptr);
+int split_kslices(int njobs, int n, int nrhs);
 // bfloat16 elements of the split planes of one n x n block
 size_t split_block_elems(int n);
 // nblk row-major complex float64 n x n blocks -> their split planes (dst: nblk * split_block_elems(n))
@@ -93,6 +98,18 @@ hipError_t launch_scatter_source(const double2* f, double2* W, const int32_t* ro
 // u[own rows] = W[rows with rowmap >= 0]
 hipError_t launch_gather_owned(const double2* W, double2* u, const int32_t* rowmap, int sumR, int NZ,
                                int NX, int nrhs, hipStream_t st);
+// Sources that touch only some layers (the pre-solve needs only those layers):
+// amax[r * L + l] = max |f[r]|^2 over rows own_start[l] .. own_start[l] + n_own[l] - 1.
+hipError_t launch_source_activity(const double2* f, double* amax, const int32_t* own_start, const int32_t* n_own,
+                                  int L, int NZ, int NX, int nrhs, hipStream_t st);
+// W (m, sumR, NX): column slot j of the rows of layer l = scale * f[slot_rhs[l * m + j]] (zero for -1)
+hipError_t launch_scatter_slots(const double2* f, double2* W, const int32_t* rowmap, const int32_t* row_layer,
+                                const int32_t* slot_rhs, int m, int sumR, int NZ, int NX, double scale,
+                                hipStream_t st);
+// s[r][seg[i]] = W[rhs_slot[r * L + layer of row[i]]][row[i]] (zero for -1), for nmap entries
+hipError_t launch_gather_slots(const double2* W, double2* s, const int32_t* seg, const int32_t* row,
+                               const int32_t* row_layer, const int32_t* rhs_slot, int nmap, int L, int sumR, int NX,
+                               int64_t ntrace, int nrhs, hipStream_t st);
 // Trace exchange: for each of nmap (trace segment, local row, sign) triples:
 // mode 0: s[seg] = W[row]              (trace right-hand side)
 // mode 1: W[row] += sign * (x_d[seg] + x_a[seg])  (interface forcing)

@@ -28,7 +28,7 @@ ApplyGeom geom_for(int n, int maxterms, int nrhs, int njobs = 1) {
   (void)K;
   // MFMA tile width: the widest that still gives about two workgroups per CU
   g.mfma = 0;
-  if (nrhs >= 16) {
+  if (nrhs > 4) {
     const long rows = (long)njobs * ((n + 63) / 64);
     g.mfma = 16;
     for (int tn : {64, 32})
@@ -37,7 +37,9 @@ ApplyGeom geom_for(int n, int maxterms, int nrhs, int njobs = 1) {
         break;
       }
   }
-  if (g.nr <= 4) {
+  // up to 4 right-hand sides the matrix is streamed row by row at HBM speed
+  g.gemv = nrhs <= 4 ? 1 : 0;
+  if (g.gemv) {
     g.ntiles = (n + 7) / 8;
     g.kc = std::min(n, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
   } else {
@@ -104,8 +106,11 @@ pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases 
   // with profiling on, the dispatch itself stamps e0 / e1 at kernel start / end
   if (Lc.plr)
     HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
-  else if (Lc.split)
-    HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
+  else if (Lc.split) {
+    const size_t need = (size_t)split_kslices(Lc.njobs, S->NX, nrhs) * Lc.njobs * nrhs * S->NX;
+    float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
+    HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part));
+  }
   else
     HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   if (S->prof) {
@@ -655,6 +660,38 @@ pt_status alloc_online(pt_solver* S) {
     HIPCHK(S->iters.alloc(nr));
     HIPCHK(S->done.alloc(nr));
     HIPCHK(hipHostMalloc((void**)&S->h_done, (size_t)nr * sizeof(int32_t), hipHostMallocDefault));
+    // k-slice partial tiles of the split-bfloat16 launches (sized for the largest)
+    if (S->split) {
+      // the slice count depends on nrhs: size for the worst right-hand-side count
+      size_t need = 0;
+      std::vector<const Launch*> ls{&S->bterm};
+      for (const Launch& Lc : S->sweep) ls.push_back(&Lc);
+      for (const Launch* Lc : ls)
+        for (int r = 1; r <= nr; ++r) {
+          const int ks = split_kslices(Lc->njobs, S->NX, r);
+          if (ks > 1) need = std::max(need, (size_t)ks * Lc->njobs * r * S->NX);
+        }
+      HIPCHK(S->part.alloc(need));
+    }
+    // source-to-layer activity tables
+    const int L = S->L;
+    std::vector<int32_t> rl(S->sumR), os(L), no(L);
+    for (int l = 0; l < L; ++l) {
+      for (int r = 0; r < S->lay[l].R; ++r) rl[S->lay[l].rowbase + r] = l;
+      os[l] = S->lay[l].own_start;
+      no[l] = S->lay[l].n;
+    }
+    HIPCHK(S->row_layer.alloc(S->sumR));
+    HIPCHK(S->lay_own_start.alloc(L));
+    HIPCHK(S->lay_n_own.alloc(L));
+    HIPCHK(hipMemcpy(S->row_layer.p, rl.data(), rl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->lay_own_start.p, os.data(), L * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->lay_n_own.p, no.data(), L * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(S->act.alloc((size_t)L * nr));
+    HIPCHK(S->slot_rhs.alloc((size_t)L * nr));
+    HIPCHK(S->rhs_slot.alloc((size_t)L * nr));
+    HIPCHK(hipHostMalloc((void**)&S->h_act, (size_t)L * nr * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&S->h_slot, (size_t)2 * L * nr * sizeof(int32_t), hipHostMallocDefault));
   }
   return PT_OK;
 }
@@ -706,10 +743,72 @@ pt_status newton(pt_solver* S, const double2* f, int nrhs) {
   return run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
+// all sources vanish: s = 0
+pt_status fail_zero(pt_solver* S, double2* s, int nrhs) {
+  HIPCHK(launch_zero(s, (int64_t)nrhs * S->Nt, S->st));
+  return PT_OK;
+}
+
+// Pre-solve (Alg. 2) restricted to the layers each source touches: f^l = 0
+// gives w^l = 0, so the sources active in layer l are packed into column
+// slots 0..m-1 of that layer (m = the largest count over layers) and the
+// local solves run on m columns instead of nrhs.  The trace right-hand side
+// takes slot values back, zero for layers a source does not touch.  A source
+// touches a layer where its largest magnitude exceeds 2^-80 of its largest
+// magnitude anywhere: what is skipped is at most 2^-80 sqrt(R NX) of ||f||,
+// far below float64 rounding of the result (smooth sources such as Gaussians
+// stay nonzero in float64 tens of widths from their centre).
+constexpr double kTouchRel2 = 0x1p-160;  // (2^-80)^2, on squared magnitudes
+
 pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
-  PTCHK(newton(S, f, nrhs));
-  HIPCHK(launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX, S->Nt,
-                          nrhs, 0, S->st));
+  const int L = S->L;
+  hipStream_t st = S->st;
+  HIPCHK(launch_source_activity(f, S->act.p, S->lay_own_start.p, S->lay_n_own.p, L, S->NZ, S->NX, nrhs, st));
+  HIPCHK(hipMemcpyAsync(S->h_act, S->act.p, (size_t)nrhs * L * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int32_t* slot_rhs = S->h_slot;                       // [l][j]
+  int32_t* rhs_slot = S->h_slot + (size_t)L * nrhs;    // [r][l]
+  std::vector<int> cnt(L, 0);
+  for (int r = 0; r < nrhs; ++r) {
+    const double* a = S->h_act + (size_t)r * L;
+    double mx = 0.0;
+    bool finite = true;
+    for (int l = 0; l < L; ++l) {
+      finite = finite && std::isfinite(a[l]);
+      mx = std::max(mx, a[l]);
+    }
+    for (int l = 0; l < L; ++l) {
+      // NaN or Inf anywhere in a source: every layer, so the solve sees and reports it
+      const bool touch = !finite || (mx > 0.0 && a[l] > kTouchRel2 * mx);
+      rhs_slot[(size_t)r * L + l] = touch ? cnt[l]++ : -1;
+    }
+  }
+  const int m = *std::max_element(cnt.begin(), cnt.end());
+  if (m >= nrhs) {  // every layer sees every source: the dense pre-solve
+    S->last_slots = nrhs;
+    PTCHK(newton(S, f, nrhs));
+    HIPCHK(launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX,
+                            S->Nt, nrhs, 0, st));
+    return PT_OK;
+  }
+  S->last_slots = m;
+  if (m == 0) return fail_zero(S, s, nrhs);
+  for (size_t e = 0; e < (size_t)L * m; ++e) slot_rhs[e] = -1;
+  for (int r = 0; r < nrhs; ++r)
+    for (int l = 0; l < L; ++l) {
+      const int j = rhs_slot[(size_t)r * L + l];
+      if (j >= 0) slot_rhs[(size_t)l * m + j] = r;
+    }
+  HIPCHK(hipMemcpyAsync(S->slot_rhs.p, slot_rhs, (size_t)L * m * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(S->rhs_slot.p, rhs_slot, (size_t)nrhs * L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  const int64_t ld = (int64_t)S->sumR * S->NX;
+  HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
+                              S->h * S->h, st));
+  PTCHK(run_local(S, S->fwd, S->bwd, m, ld, S->W.p, S->Bw.p));
+  HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
+                             S->sumR, S->NX, S->Nt, nrhs, st));
+  // the pinned slot tables are rewritten by the next call: finish their uploads first
+  HIPCHK(hipStreamSynchronize(st));
   return PT_OK;
 }
 
@@ -809,8 +908,14 @@ void pt_free(pt_solver* S) {
   S->dinv32.release();
   S->blk32.release();
   S->blkbf.release();
+  S->part.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
-  for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag}) b->release();
+  for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag,
+                  &S->row_layer, &S->lay_own_start, &S->lay_n_own, &S->slot_rhs, &S->rhs_slot})
+    b->release();
+  S->act.release();
+  if (S->h_act) (void)hipHostFree(S->h_act);
+  if (S->h_slot) (void)hipHostFree(S->h_slot);
   S->jobs.release();
   S->plr.release();
   if (S->h_done) (void)hipHostFree(S->h_done);

@@ -120,9 +120,16 @@ struct pt_solver {
   DevBuf<float2> dinv32, blk32;
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
   bool split = false;
+  DevBuf<float2> part;     // k-slice partial tiles of small split launches
   int nblk = 0;
   std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
   DevBuf<int32_t> rowmap;
+  // layers touched by each source (pre-solve only where a source is nonzero)
+  DevBuf<int32_t> row_layer, lay_own_start, lay_n_own, slot_rhs, rhs_slot;
+  DevBuf<double> act;         // per (source, layer): largest |f|^2 on the layer's owned rows
+  double* h_act = nullptr;    // pinned, L * max_nrhs
+  int32_t* h_slot = nullptr;  // pinned, 2 * L * max_nrhs: slot_rhs then rhs_slot
+  int last_slots = 0;         // column slots of the last pre-solve (nrhs when dense)
   DevBuf<int32_t> g_seg, g_row, f_seg, f_row;
   DevBuf<double> f_sign, g_sign;
   int n_gather = 0, n_force = 0;

@@ -36,6 +36,17 @@ __device__ __forceinline__ double2 ldg(const gdouble2* p, int64_t i) {
   return make_double2(v.x, v.y);
 }
 
+// Workgroup ids are dealt round-robin to the 8 XCDs, each with its own L2.
+// Renumber so that every XCD gets one contiguous range of logical ids: tiles
+// next to each other in logical order (sharing block rows or input columns)
+// then meet in the same L2.
+__device__ __forceinline__ int xcd_logical(int i, int G) {
+  constexpr int kXcd = 8;
+  const int x = i % kXcd, local = i / kXcd;
+  const int per = G / kXcd, rem = G % kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
 __device__ __forceinline__ void split2(double x, __bf16& hi, __bf16& lo) {
   hi = static_cast<__bf16>(static_cast<float>(x));
@@ -240,6 +251,271 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
     }
 }
 
+// Wide form for many right-hand sides: one group of 4 waves = a 64-row x
+// 16 NB-right-hand-side output tile; wave w owns the 16-row tile 4 tile + w
+// and all NB 16-column tiles (12 NB MFMAs per chunk).  The 32 x 16 NB input
+// chunk is loaded once per group and shared by the 4 waves through LDS, so
+// each input element is read once per 64 output rows.  The loads run down the
+// columns: thread t takes row pairs (2 (p % 16), 2 (p % 16) + 1) of column
+// p / 16 for p = t + 256 i, i < NB, so a wave reads 4 columns x 512
+// contiguous bytes per instruction; each pair is combined (Q + beta S), split and written into the
+// B operand layout (lane l: rows 8 (l / 16) + 0..7 of column l % 16) as 4-byte
+// words.  KS groups split the chunk sequence of the tile (KS = 1, 2); their
+// partial tiles are summed through LDS one group at a time, in a fixed order.
+constexpr int kWideRows = 64;
+
+template <int NB, int KS>
+__global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+                                                                    int nct, int nrhs, int64_t ld, Bases bases,
+                                                                    int kslices, int njobs,
+                                                                    float2* __restrict__ part) {
+  constexpr int kWideCols = 16 * NB;
+  constexpr int PPT = kSpK * kWideCols / 2 / 256;                          // row pairs per thread: NB
+  constexpr size_t kPlane = (size_t)NB * 64 * sizeof(bf16x8);              // one plane of a chunk
+  constexpr size_t kStage = (size_t)KS * 4 * kPlane;                       // split input planes of every group
+  constexpr size_t kRed = KS > 1 ? (size_t)4 * 64 * 4 * NB * sizeof(f32x4) : 0;  // one group's partial tiles
+  __shared__ __align__(16) unsigned char smem[kStage > kRed ? kStage : kRed];
+  const int tid = threadIdx.x & 255;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  unsigned char* gst = smem + (size_t)grp * 4 * kPlane;  // this group's planes
+  // logical order, fastest first: column tile, row tile, k-slice, job -- so an
+  // XCD's range shares block rows (across column tiles) and input rows (across
+  // row tiles) in its L2
+  int bid = xcd_logical(blockIdx.x, gridDim.x);
+  const int ct = bid % nct;
+  bid /= nct;
+  const int tile = bid % ntiles;
+  bid /= ntiles;
+  const int slice = bid % kslices;  // k-slice of the tile (kslices > 1: partial tile to `part`)
+  const int job = bid / kslices;
+  const Job& J = jobs[job];
+  const int nkt = (n + kSpK - 1) / kSpK;
+  const int nrt16 = (n + 15) / 16;
+  const int rt = tile * 4 + wave;
+  const bool rt_ok = rt < nrt16;
+  const int rtc = rt_ok ? rt : nrt16 - 1;  // clamped: loads stay inside the block
+  const int col0 = ct * kWideCols;
+
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // chunk range of this k-slice: [qbeg, qend)
+  const int nall = J.nterms * nkt;
+  const int cps = (nall + kslices - 1) / kslices;
+  const int qbeg = min(slice * cps, nall);
+  const int nchunks = min(nall, qbeg + cps) - qbeg;
+  const int rounds = (nchunks + KS - 1) / KS;  // the same for every group: barriers stay uniform
+  bf16x8 pa[4];
+  double2 xq[PPT][2], xs[PPT][2];
+  bool live = false, has_q = false, has_s = false;
+  double2 beta = make_double2(0.0, 0.0);
+  int kbase = 0;
+  auto fetch = [&](int qi) {
+    live = qi < nchunks;
+    if (!live) return;
+    const int q = qbeg + qi;
+    const int t = q / nkt;
+    const int kt = q - t * nkt;
+    const gbf16x8* T = reinterpret_cast<const gbf16x8*>(
+        reinterpret_cast<uintptr_t>(static_cast<const __bf16*>(J.M[t]) + ((size_t)rtc * nkt + kt) * 4 * 512));
+#pragma unroll
+    for (int p = 0; p < 4; ++p) pa[p] = T[p * 64 + lane];
+    const VecRef qr = J.Q[t];
+    const VecRef svr = J.S[t];
+    has_q = qr.buf >= 0;
+    has_s = svr.buf >= 0;
+    beta = J.beta[t];
+    kbase = kt * kSpK;
+    const double2* qb = has_q ? sp_base(bases, qr.buf) + qr.off : nullptr;
+    const double2* sb = has_s ? sp_base(bases, svr.buf) + svr.off : nullptr;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int pr = tid + 256 * i;
+      const int k = kbase + 2 * (pr & 15);
+      const int64_t e = (int64_t)min(col0 + (pr >> 4), nrhs - 1) * ld;
+      const int k0c = min(k, n - 1), k1c = min(k + 1, n - 1);
+      if (has_q) {
+        const gdouble2* qp = to_global(qb + e);
+        xq[i][0] = ldg(qp, k0c);
+        xq[i][1] = ldg(qp, k1c);
+      }
+      if (has_s) {
+        const gdouble2* sp = to_global(sb + e);
+        xs[i][0] = ldg(sp, k0c);
+        xs[i][1] = ldg(sp, k1c);
+      }
+    }
+  };
+  fetch(grp);
+  for (int i = 0; i < rounds; ++i) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int pr = tid + 256 * j;
+      const int kp = pr & 15, c = pr >> 4;  // row pair within the chunk, column within the tile
+      const bool col_ok = live && col0 + c < nrhs;
+      __bf16 h[4][2];  // [plane][row of the pair]
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        double2 v = has_q ? xq[j][u] : make_double2(0.0, 0.0);
+        if (has_s) {
+          v.x += beta.x * xs[j][u].x - beta.y * xs[j][u].y;
+          v.y += beta.x * xs[j][u].y + beta.y * xs[j][u].x;
+        }
+        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
+        split2(v.x, h[0][u], h[1][u]);
+        split2(v.y, h[2][u], h[3][u]);
+      }
+      // rows 2 kp, 2 kp + 1 sit at positions (2 kp) % 8, +1 of lane (2 kp / 8) * 16 + c % 16 of tile c / 16
+      const int l = ((2 * kp) >> 3) * 16 + (c & 15);
+      const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+        bf16x2v w;
+        w[0] = h[pl][0];
+        w[1] = h[pl][1];
+        *reinterpret_cast<bf16x2v*>(gst + pl * kPlane + off) = w;
+      }
+    }
+    const bool mult = live;
+    const bf16x8 ar_h = pa[0], ar_l = pa[1], ai_h = pa[2], ai_l = pa[3];
+    __syncthreads();
+    fetch((i + 1) * KS + grp);
+    if (mult) {
+      const bf16x8* P0 = reinterpret_cast<const bf16x8*>(gst);
+      const bf16x8* P1 = reinterpret_cast<const bf16x8*>(gst + kPlane);
+      const bf16x8* P2 = reinterpret_cast<const bf16x8*>(gst + 2 * kPlane);
+      const bf16x8* P3 = reinterpret_cast<const bf16x8*>(gst + 3 * kPlane);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
+        const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_h, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_h, acc[1][b], 0, 0, 0);
+        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_h, acc[2][b], 0, 0, 0);
+        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_h, acc[3][b], 0, 0, 0);
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_l, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_l, acc[1][b], 0, 0, 0);
+        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_l, acc[2][b], 0, 0, 0);
+        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_l, acc[3][b], 0, 0, 0);
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xr_h, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xi_h, acc[1][b], 0, 0, 0);
+        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xi_h, acc[2][b], 0, 0, 0);
+        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xr_h, acc[3][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (KS > 1) {
+    f32x4* red = reinterpret_cast<f32x4*>(smem);  // [wave][a][b][lane]
+#pragma unroll
+    for (int g = 1; g < KS; ++g) {
+      if (grp == g)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) red[((wave * 4 + a) * NB + b) * 64 + lane] = acc[a][b];
+      __syncthreads();
+      if (grp == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[a][b] += red[((wave * 4 + a) * NB + b) * 64 + lane];
+      __syncthreads();
+    }
+    if (grp > 0) return;
+  }
+
+  if (!rt_ok) return;
+  if (kslices > 1) {
+    // partial tile of this k-slice: part[((slice * njobs + job) * nrhs + rhs) * n + row]
+    float2* __restrict__ pt = part + ((size_t)slice * njobs + job) * nrhs * n;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rt * 16 + 4 * (lane >> 4) + i;
+        const int rhs = col0 + b * 16 + (lane & 15);
+        if (row < n && rhs < nrhs)
+          pt[(size_t)rhs * n + row] = make_float2(acc[0][b][i] - acc[1][b][i], acc[2][b][i] + acc[3][b][i]);
+      }
+    return;
+  }
+  double2* __restrict__ Yb = sp_base(bases, J.Y.buf) + J.Y.off;
+  const double2* __restrict__ Pb = J.P.buf >= 0 ? sp_base(bases, J.P.buf) + J.P.off : nullptr;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rt * 16 + 4 * (lane >> 4) + i;
+      const int rhs = col0 + b * 16 + (lane & 15);
+      if (row < n && rhs < nrhs) {
+        const double yr = (double)acc[0][b][i] - (double)acc[1][b][i];
+        const double yi = (double)acc[2][b][i] + (double)acc[3][b][i];
+        double2 y = make_double2(J.alpha.x * yr - J.alpha.y * yi, J.alpha.x * yi + J.alpha.y * yr);
+        if (Pb) {
+          const double2 p = Pb[(int64_t)rhs * ld + row];
+          y.x += p.x;
+          y.y += p.y;
+        }
+        Yb[(int64_t)rhs * ld + row] = y;
+      }
+    }
+}
+
+// Y = P + alpha sum_s part[s] over the k-slices of every job, slices summed in order
+__global__ void split_reduce_kernel(const Job* __restrict__ jobs, int njobs, int n, int nrhs, int64_t ld,
+                                    Bases bases, int kslices, const float2* __restrict__ part) {
+  const int job = blockIdx.y;
+  const Job& J = jobs[job];
+  double2* __restrict__ Yb = sp_base(bases, J.Y.buf) + J.Y.off;
+  const double2* __restrict__ Pb = J.P.buf >= 0 ? sp_base(bases, J.P.buf) + J.P.off : nullptr;
+  const size_t per = (size_t)nrhs * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const int rhs = (int)(e / n), row = (int)(e % n);
+    double yr = 0.0, yi = 0.0;
+    for (int sl = 0; sl < kslices; ++sl) {
+      const float2 v = part[((size_t)sl * njobs + job) * per + e];
+      yr += (double)v.x;
+      yi += (double)v.y;
+    }
+    double2 y = make_double2(J.alpha.x * yr - J.alpha.y * yi, J.alpha.x * yi + J.alpha.y * yr);
+    if (Pb) {
+      const double2 p = Pb[(int64_t)rhs * ld + row];
+      y.x += p.x;
+      y.y += p.y;
+    }
+    Yb[(int64_t)rhs * ld + row] = y;
+  }
+}
+
+template <int NB, int KS>
+hipError_t launch_wide(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1, int kslices = 1, float2* part = nullptr) {
+  const int ntiles = (n + kWideRows - 1) / kWideRows;
+  const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
+  const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
+  if (kslices > 1) {
+    // the stop event goes on the reduction, so a timed launch covers both kernels
+    hipExtLaunchKernelGGL((block_split_wide_kernel<NB, KS>), grid, dim3(256 * KS), 0, st, ev0, nullptr, 0, jobs, n,
+                          ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
+    const size_t per = (size_t)nrhs * n;
+    const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
+    hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
+                          bases, kslices, (const float2*)part);
+  } else {
+    hipExtLaunchKernelGGL((block_split_wide_kernel<NB, KS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, jobs, n,
+                          ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
+  }
+  return hipGetLastError();
+}
+
 template <int NB, int KS>
 hipError_t launch_sp(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                      hipEvent_t ev0, hipEvent_t ev1) {
@@ -276,12 +552,31 @@ hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, h
   return hipGetLastError();
 }
 
+// right-hand sides per tile of the wide form
+constexpr int kWideCols = 32;
+
+int split_kslices(int njobs, int n, int nrhs) {
+  if (nrhs <= 16) return 1;
+  constexpr long kCUs = 256;
+  const long tiles = (long)njobs * ((n + kWideRows - 1) / kWideRows) * ((nrhs + kWideCols - 1) / kWideCols);
+  int ks = 1;
+  while (ks < 16 && tiles * ks < 4 * kCUs) ks *= 2;
+  return ks;
+}
+
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
-                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, float2* part) {
   if (njobs <= 0) return hipSuccess;
+  constexpr long kSimds = 1024;
+  if (nrhs > 16) {
+    // 64 x 32 tiles; launches with fewer than four tiles per CU split the chunk
+    // sequence over k-slices (partial tiles in `part`, summed by a second kernel)
+    const int ks = split_kslices(njobs, n, nrhs);
+    if (ks > 1 && part) return launch_wide<kWideCols / 16, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
+    return launch_wide<kWideCols / 16, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  }
   // 16-column tiles; the chunks of a tile are split over up to 4 waves until
   // the launch has about 4 waves per SIMD
-  constexpr long kSimds = 1024;
   const long tasks = (long)njobs * ((n + 15) / 16) * ((nrhs + 15) / 16);
   const int ks = tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
   return launch_sp_ks<1>(ks, jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);

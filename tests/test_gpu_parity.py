@@ -60,7 +60,8 @@ def _random_local(ps, nrhs, seed):
 
 def test_local_solve(small):
     prob, f, gs, ps = small
-    for nrhs in (1, 3, 20):
+    # 1 / 3: 1- and 4-column streaming passes; 6 / 13: 8- and 16-column passes; 20: MFMA tiles
+    for nrhs in (1, 3, 6, 13, 20):
         b = _random_local(ps, nrhs, nrhs)
         x = gs.local_solve(b)
         r0 = 0
@@ -166,6 +167,17 @@ def test_f32_blocks_and_factors_small():
     gs.close()
 
 
+def test_f32_thirteen_sources():
+    # float32 blocks with 13 right-hand sides: the 16-column streaming pass
+    prob, f = synth.config_small(nx=24, nz=31, npml=5, L=3, nrhs=13, seed=23)
+    _flush("[gpu] f32 13 sources")
+    gs = P.Solver.from_problem(prob, precision="f32", max_nrhs=13, tol=1e-10, maxit=60)
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    assert max(rel(u[r], ud[r]) for r in range(13)) < 1e-6
+    gs.close()
+
+
 def test_f32_bumps440_single_source():
     prob, f = synth.config2()
     _flush("[gpu] f32 bumps-440x440-L8")
@@ -234,3 +246,86 @@ def test_plr_bumps440_single_source():
     _flush(f"[gpu] plr bumps440 rel err {err:.2e}, iters {info[0]['iters']}")
     assert err < 1e-6
     gs.close()
+
+
+# ---------------------------------------------------------------- sources touching few layers
+def _compact_sources(prob, spec, seed):
+    """spec: list of (z0, z1) padded-grid row ranges (None: dense everywhere); random complex values there."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((len(spec), prob.NZ, prob.NX), dtype=np.complex128)
+    for r, zr in enumerate(spec):
+        if zr is None:
+            f[r, prob.npml:prob.npml + prob.nz, prob.npml:prob.npml + prob.nx] = rng.standard_normal((prob.nz, prob.nx))
+        else:
+            z0, z1 = zr
+            x0 = prob.npml + 2 + 3 * r % (prob.nx - 6)
+            f[r, z0:z1, x0:x0 + 3] = rng.standard_normal((z1 - z0, 3)) + 1j * rng.standard_normal((z1 - z0, 3))
+    return f
+
+
+@pytest.fixture(scope="module")
+def layered4():
+    # 4 layers of 12 physical rows; owned padded rows: [0, 18), [18, 30), [30, 42), [42, 60)
+    prob, _ = synth.config_small(nx=30, nz=48, npml=6, L=4, seed=51)
+    gs = P.Solver.from_problem(prob, max_nrhs=8, tol=1e-12, maxit=60)
+    return prob, gs, PolarizedSolver(prob)
+
+
+def test_sparse_presolve_trace_rhs_matches_oracle(layered4):
+    prob, gs, ps = layered4
+    _flush("[gpu] sparse pre-solve trace rhs")
+    # one layer each, one straddling 29/30, two in layer 0 (ragged slot counts), one in the last layer
+    spec = [(8, 10), (20, 23), (28, 32), (12, 14), (44, 47), (33, 35)]
+    f = _compact_sources(prob, spec, seed=3)
+    s = gs.trace_rhs(f)
+    ref = ps.rhs(ps.newton(f))
+    assert rel(s, ref) < 1e-10
+    for r in range(len(spec)):
+        assert rel(s[r], ref[r]) < 1e-10, r
+
+
+def test_sparse_presolve_solves_match_direct(layered4):
+    prob, gs, ps = layered4
+    _flush("[gpu] sparse pre-solve full solves")
+    spec = [(8, 10), (20, 23), None, (28, 32), (44, 47), (33, 35), (40, 44)]
+    f = _compact_sources(prob, spec, seed=4)
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    for r in range(len(spec)):
+        assert rel(u[r], ud[r]) < 1e-8, r
+    # the same sources one by one (single-source calls take the dense path)
+    for r in (0, 3):
+        u1, _ = gs.solve(f[r])
+        assert rel(u1, u[r]) < 1e-10
+
+
+def test_sparse_presolve_zero_and_mixed_zero_sources(layered4):
+    prob, gs, ps = layered4
+    _flush("[gpu] sparse pre-solve zero sources")
+    f = np.zeros((3, prob.NZ, prob.NX), dtype=np.complex128)
+    s = gs.trace_rhs(f)
+    assert np.all(s == 0)
+    u, info = gs.solve(f)
+    assert np.all(u == 0)
+    f[1] = _compact_sources(prob, [(20, 23)], seed=5)[0]
+    u, info = gs.solve(f)
+    assert np.all(u[0] == 0) and np.all(u[2] == 0)
+    assert rel(u[1], DirectSolver(prob).solve(f[1])) < 1e-8
+
+
+def test_sparse_presolve_gaussian_tails_match_direct(layered4):
+    # Gaussians (sigma = h) stay nonzero in float64 about 38 widths out, i.e. over several 12-row layers;
+    # layers where a source is below 2^-80 of its peak are skipped, far below float64 rounding of u
+    prob, gs, ps = layered4
+    _flush("[gpu] sparse pre-solve gaussian sources")
+    h = prob.h
+    zs = [10, 17, 24, 31, 40, 50]
+    f = np.stack([synth.gaussian_source(prob, (prob.nx / 2 + 2 * i) * h, z * h, h) for i, z in enumerate(zs)])
+    tail_layers = [(np.abs(f[r]).max(axis=1) > 0).sum() for r in range(len(zs))]
+    assert max(tail_layers) > 30  # the float64 tails really do span several layers
+    u, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    for r in range(len(zs)):
+        assert rel(u[r], ud[r]) < 1e-8, r
+    s = gs.trace_rhs(f)
+    assert rel(s, ps.rhs(ps.newton(f))) < 1e-10
