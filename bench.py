@@ -6,12 +6,15 @@ flexible GMRES with the Gauss-Seidel sweep preconditioner, reconstruction)
 over one batch of synthetic sources already resident in HBM.
 
 Headline workload (`value`): the batched layered section, 128 sources solved
-in one call, in the mixed form (float32 trace blocks and local factors,
-float64 Krylov vectors, Arnoldi, least squares and true residual) when that
-form meets the 1e-6 relative-error bar against the float64 oracle on the
-sampled sources, else in float64.  `forms` reports the float64 forms beside
-it (same workload batched, and the smooth bumps-440x440-L8 single-source
-workload in float64 and float32).
+in one call, in the mixed form -- the Gauss-Seidel sweeps apply the trace
+blocks as split-bfloat16 pairs on MFMA, while the local solves, the operator
+A inside GMRES, the Krylov vectors, Arnoldi, least squares and the true
+residual stay float64 -- when that form meets the 1e-6 relative-error bar
+against the float64 oracle on the sampled sources, else in float64.  `forms`
+reports the float64 form of the same workload beside it (and, with
+--all-forms, float32 blocks, the smooth single-source workload and
+compressed blocks).  Tile shapes are tuned (pt_tune) after setup, outside
+the timed steps.
 
 Prints one JSON line; progress goes to stderr.
 """
@@ -28,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "online Helmholtz solves/s on 1 MI355X at rel err<=1e-6: mixed+batched vs FP64"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # vector FP64 / FP32 (the block GEMM runs on the ALUs)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense peaks (FP64 MFMA, FP32, BF16 MFMA)
 ERR_BAR = 1e-6
 
 
@@ -86,8 +89,8 @@ class Oracle:
         return nsol / el, nsol, el
 
 
-def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False):
-    """Setup + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
+def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True):
+    """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
     nrhs = f.shape[0]
     t0 = time.perf_counter()
     s = P.Solver.from_problem(prob, precision=precision, tol=1e-10, maxit=60, max_nrhs=nrhs,
@@ -95,6 +98,11 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
     lay = s.layout()
     fd = torch.from_numpy(f).to("cuda:0")
     setup_s = time.perf_counter() - t0
+    tune_res, tune_s = None, 0.0
+    if tune:
+        t0 = time.perf_counter()
+        tune_res = s.tune(nrhs)
+        tune_s = time.perf_counter() - t0
     for _ in range(warmup):
         u, info = s.solve(fd)
     torch.cuda.synchronize()
@@ -105,6 +113,7 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
     el = time.perf_counter() - t0
     out = {"solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "nrhs": nrhs,
            "precision": precision, "blocks": "plr eps 1e-9" if plr else "dense", "setup_s": setup_s,
+           "tune_s": tune_s, "tuned": tune_res,
            "iterations": sorted(set(i["iters"] for i in info)),
            "max_true_relres": max(i["relres"] for i in info), "block_bytes": lay["block_bytes"],
            "factor_bytes": lay["factor_bytes"]}
@@ -113,30 +122,44 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
         nprof = max(1, min(steps, 3))
         for _ in range(nprof):
             s.solve(fd)
-        st = s.profile_read()
+        tot = s.profile_read()
+        cls = {c: s.profile_read_class(c) for c in P.polar.CLASSES}
         s.profile(False)
-        out["kernel"] = {"launches_per_step": st["launches"] / nprof, "kernel_ms": st["kernel_ms"] / nprof,
-                         "alg_bytes": st["alg_bytes"] / nprof, "alg_flops": st["alg_flops"] / nprof,
-                         "launches": st["launches"], "kernel_ms_total": st["kernel_ms"],
-                         "alg_bytes_total": st["alg_bytes"], "alg_flops_total": st["alg_flops"]}
+        out["kernel"] = {"nprof": nprof, "total": tot, "classes": cls}
     s.close()
     return out, u
 
 
+# the kernel each launch class runs with many right-hand sides, by form
+KERNELS = {
+    ("local", "f64"): ("block_mfma64_kernel", "f64"), ("local", "split-bf16"): ("block_mfma64_kernel", "f64"),
+    ("operator", "f64"): ("block_mfma64_kernel", "f64"), ("operator", "split-bf16"): ("block_mfma64_kernel", "f64"),
+    ("sweep", "f64"): ("block_mfma64_kernel", "f64"), ("reflect", "f64"): ("block_mfma64_kernel", "f64"),
+    ("sweep", "split-bf16"): ("block_split_wide_kernel", "bf16"),
+    ("reflect", "split-bf16"): ("block_split_wide_kernel", "bf16"),
+}
+
+
 def roofline(form):
+    """Roofline of the dominant launch class (most kernel time per step), from live HIP-event timing."""
     k = form["kernel"]
-    sec = k["kernel_ms_total"] / 1e3
-    gbs = k["alg_bytes_total"] / sec / 1e9
-    tfl = k["alg_flops_total"] / sec / 1e12
-    base = {"traffic": None, "kernel": "block_gemv_kernel" if form["nrhs"] < 8 else "block_gemm_kernel",
-            "launches_per_step": k["launches_per_step"], "avg_launch_us": 1e3 * k["kernel_ms_total"] / k["launches"],
-            "alg_bytes_per_launch": k["alg_bytes_total"] / k["launches"],
-            "alg_flops_per_launch": k["alg_flops_total"] / k["launches"],
-            "kernel_share_of_step": k["kernel_ms"] / form["ms_per_step"]}
-    if form["nrhs"] >= 8:
-        peak = PEAK_TFLOPS[form["precision"]]
-        r = {"bound": "alu", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak}
+    cls, st = max(k["classes"].items(), key=lambda kv: kv[1]["kernel_ms"])
+    sec = st["kernel_ms"] / 1e3
+    name, dt = KERNELS.get((cls, form["precision"]), ("block_gemm_kernel", form["precision"]))
+    base = {"traffic": None, "class": cls, "kernel": name, "launches_per_step": st["launches"] / k["nprof"],
+            "avg_launch_us": 1e3 * st["kernel_ms"] / st["launches"],
+            "alg_bytes_per_launch": st["alg_bytes"] / st["launches"],
+            "alg_flops_per_launch": st["alg_flops"] / st["launches"],
+            "class_share_of_step": st["kernel_ms"] / k["nprof"] / form["ms_per_step"],
+            "all_classes_ms_per_step": {c: v["kernel_ms"] / k["nprof"] for c, v in k["classes"].items()}}
+    if form["nrhs"] > 4 or dt == "bf16":
+        # a split-bfloat16 complex multiply-add is 3 x 4 real bfloat16 products: 3x the counted flops
+        fl = st["alg_flops"] * (3.0 if dt == "bf16" else 1.0)
+        tfl = fl / sec / 1e12
+        peak = PEAK_TFLOPS[dt]
+        r = {"bound": "mfma", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak}
     else:
+        gbs = st["alg_bytes"] / sec / 1e9
         r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     r.update(base)
     return r
@@ -158,12 +181,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="layered1240", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="auto", choices=["auto", "f64", "f32"],
-                    help="auto: mixed (f32 blocks) if it meets the 1e-6 bar on the sampled sources, else f64")
+    ap.add_argument("--precision", default="auto", choices=["auto", "f64", "f32", "split-bf16"],
+                    help="auto: mixed (split-bfloat16 sweeps) if it meets the 1e-6 bar on the sampled sources, "
+                         "else f64")
     ap.add_argument("--nrhs", type=int, default=0, help="sources per step (default: all of the workload's)")
     ap.add_argument("--check", type=int, default=4, help="sources compared with the oracle (0: none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-forms", action="store_true", help="skip the float64 comparison forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the float64 comparison form")
+    ap.add_argument("--all-forms", action="store_true",
+                    help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
+    ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -193,10 +220,10 @@ def main():
 
     forms = []
     chosen = None
-    order = ["f32", "f64"] if args.precision == "auto" else [args.precision]
+    order = ["split-bf16", "f64"] if args.precision == "auto" else [args.precision]
     for prec in order:
-        log(f"{args.workload} {prec}: setup + {args.warmup} warmup + {args.steps} timed steps")
-        form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream)
+        log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
+        form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune)
         form["workload"] = args.workload
         if k:
             errs = oracle.errors(f, u, k)
@@ -211,8 +238,10 @@ def main():
             break
     if not args.no_forms:
         have = {(fm["workload"], fm["precision"], False) for fm in forms}
-        extra = [(args.workload, "f64", False)] + [("bumps440", p, False) for p in ("f64", "f32")] + \
-            [("bumps440", "f64", True)]
+        extra = [(args.workload, "f64", False)]
+        if args.all_forms:
+            extra += [(args.workload, "f32", False)] + \
+                [("bumps440", p, False) for p in ("f64", "f32", "split-bf16")] + [("bumps440", "f64", True)]
         orcs = {}
         for wl, prec, plr in extra:
             if (wl, prec, plr) in have or (wl == args.workload and args.nrhs):
@@ -220,7 +249,7 @@ def main():
             pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
             log(f"form {wl} {prec}{' plr' if plr else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
-                               args.warmup, stream, profile=False, plr=plr)
+                               args.warmup, stream, profile=False, plr=plr, tune=not args.no_tune)
             form["workload"] = wl
             if wl == args.workload:
                 orc = oracle
@@ -237,10 +266,14 @@ def main():
     out = {
         "metric": METRIC, "value": chosen["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": chosen["precision"], "data": "synthetic",
+        "vs_baseline": None, "dtype": {"split-bf16": "f64+bf16x2", "f32": "f32+f64", "f64": "f64"}[chosen["precision"]],
+        "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": [prob.NZ, prob.NX], "L": prob.L, "nrhs": nrhs,
-                   "precision": chosen["precision"], "form": ("mixed: float32 blocks and factors, float64 Krylov"
-                                                              if chosen["precision"] == "f32" else "float64"),
+                   "precision": chosen["precision"],
+                   "form": {"split-bf16": "mixed: Gauss-Seidel sweeps on split-bfloat16 MFMA blocks, local solves, "
+                                          "operator A, Krylov vectors and residuals in float64",
+                            "f32": "float32 blocks and local factors, float64 Krylov vectors",
+                            "f64": "float64"}[chosen["precision"]],
                    "gmres_tol": 1e-10, "gs_iters": 2, "iterations": chosen["iterations"]},
         "roofline": roofline(chosen),
         "rel_err_vs_oracle": chosen.get("rel_err_vs_oracle"),

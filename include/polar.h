@@ -202,6 +202,40 @@ pt_status pt_profile(pt_solver* s, int32_t enable);
 /* Synchronises the solver stream and returns the accumulated counters. */
 pt_status pt_profile_read(pt_solver* s, pt_kernel_stats* out);
 
+/* Classes of block-apply launches (for per-class counters and tuning). */
+typedef enum {
+  PT_CLS_LOCAL = 0,    /* one row step of the local solves (pre-solve, reconstruction)  */
+  PT_CLS_SWEEP = 1,    /* one step of the Gauss-Seidel down and up sweeps (Alg. 4)       */
+  PT_CLS_REFLECT = 2,  /* the reflection terms of a Gauss-Seidel pass                    */
+  PT_CLS_OPERATOR = 3, /* the polarized operator A = D + R, or R alone                   */
+  PT_CLS_COUNT = 4
+} pt_launch_class;
+/* The counters of one launch class (same synchronisation as pt_profile_read). */
+pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out);
+
+/* ---- autotuner ----------------------------------------------------------
+ *
+ * Tile shapes of the block-apply kernels are chosen per launch by built-in
+ * rules.  pt_tune times, for nrhs right-hand sides, every candidate shape of
+ * each launch class on one representative launch of that class (HIP events,
+ * one warm-up and three timed runs on the solver's own work buffers, whose
+ * contents it overwrites) and keeps the fastest; later calls with the same
+ * nrhs use it.  Candidates: float64 MFMA tiles of 16, 32 or 64 right-hand
+ * sides, with the 16-wide tile's chunks split over 1, 2 or 4 wave groups;
+ * split-bfloat16 tiles of 32 or 64 right-hand sides, split over 1..16
+ * k-slices.  Classes with a single form (the row-streaming kernel for <= 4
+ * right-hand sides, float32 blocks, compressed blocks) are reported with
+ * tried = 1.  out: PT_CLS_COUNT entries (may be NULL). */
+typedef struct {
+  int32_t cls;        /* pt_launch_class                                          */
+  int32_t tried;      /* candidate shapes timed (0: the class has no launch)       */
+  int32_t tile_rhs;   /* chosen right-hand sides per tile (0: rule / single form)  */
+  int32_t ksplit;     /* chosen wave groups or k-slices per tile                   */
+  double best_us;     /* its mean launch time                                      */
+  double default_us;  /* the built-in rule's mean launch time                      */
+} pt_tune_entry;
+pt_status pt_tune(pt_solver* s, int32_t nrhs, pt_tune_entry* out);
+
 /* ---- learned preconditioner stage --------------------------------------
  *
  * Not in the paper.  A small 1D convolutional network N along the interface

@@ -537,7 +537,7 @@ hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int n
     const long tiles = (long)njobs * ntl * nrt;
     const dim3 grid2((unsigned)tiles);
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
-    const int ks = tiles < 256 ? 4 : tiles < 512 ? 2 : 1;
+    const int ks = g.ks > 0 ? g.ks : tiles < 256 ? 4 : tiles < 512 ? 2 : 1;
 #define POLAR_MFMA64(TNV, KSV)                                                                                  \
   hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, jobs, g.n, \
                         ntl, nrt, nrhs, ld, bases)

@@ -45,6 +45,13 @@ struct ApplyGeom {
   int mfma;     // float64 with more than 4 right-hand sides: MFMA kernel with this many
                 // right-hand sides per workgroup tile (16, 32 or 64); 0: not used
   int gemv;     // 1: the row-streaming kernel (nr <= 4 right-hand sides per pass)
+  int ks;       // float64 MFMA: wave groups splitting a tile's chunks (0: rule)
+};
+
+// Shape override of a split-bfloat16 launch (0: rule).
+struct SplitCfg {
+  int tile_rhs;  // 32 or 64 right-hand sides per tile (more than 16 right-hand sides)
+  int kslices;   // k-slices per tile
 };
 
 // ---------------------------------------------------------------- block apply
@@ -60,8 +67,9 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
 // tiles of launches too small to fill the chip.
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
                                     hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                                    float2* part = nullptr);
-int split_kslices(int njobs, int n, int nrhs);
+                                    float2* part = nullptr, SplitCfg cfg = SplitCfg{0, 0});
+// the rule's k-slice count of a split launch with the given tile width (0: the rule's width)
+int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block
 size_t split_block_elems(int n);
 // nblk row-major complex float64 n x n blocks -> their split planes (dst: nblk * split_block_elems(n))

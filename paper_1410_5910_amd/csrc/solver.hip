@@ -82,19 +82,32 @@ pt_status prof_harvest(pt_solver* S) {
   for (const ProfPending& p : S->pend) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, S->ev[2 * p.ev], S->ev[2 * p.ev + 1]));
-    S->stats.launches += 1;
-    S->stats.kernel_ms += ms;
-    S->stats.alg_bytes += p.bytes;
-    S->stats.alg_flops += p.flops;
+    for (pt_kernel_stats* k : {&S->stats, &S->cstats[p.cls]}) {
+      k->launches += 1;
+      k->kernel_ms += ms;
+      k->alg_bytes += p.bytes;
+      k->alg_flops += p.flops;
+    }
   }
   S->pend.clear();
   S->ev_next = 0;
   return PT_OK;
 }
 
-pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b) {
+// the shape of a launch: the tuned one for its class and nrhs, else the rules
+const TuneCfg* tuned(const pt_solver* S, const Launch& Lc, int nrhs) {
+  const auto& m = S->tune[Lc.cls];
+  const auto it = m.find(nrhs);
+  return it == m.end() ? nullptr : &it->second;
+}
+
+pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc) {
   if (Lc.njobs == 0) return PT_OK;
-  const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
+  ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
+  if (tc && g.mfma && tc->tn) {
+    g.mfma = tc->tn;
+    g.ks = tc->ks;
+  }
   int slot = -1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (S->prof) {
@@ -107,23 +120,31 @@ pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases 
   if (Lc.plr)
     HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
   else if (Lc.split) {
-    const size_t need = (size_t)split_kslices(Lc.njobs, S->NX, nrhs) * Lc.njobs * nrhs * S->NX;
+    const SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
+    const int ks = sc.kslices > 0 ? sc.kslices : split_kslices(Lc.njobs, S->NX, nrhs, sc.tile_rhs);
+    const size_t need = (size_t)ks * Lc.njobs * nrhs * S->NX;
     float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
-    HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part));
+    HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
   else
     HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   if (S->prof) {
     // bytes per stored complex entry: 4 bfloat16 planes, float32 or float64 pairs
     const double es = Lc.split ? 8.0 : S->f32 ? 8.0 : 16.0;
-    S->pend.push_back(ProfPending{slot, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
+    S->pend.push_back(ProfPending{slot, Lc.cls, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
                                   8.0 * Lc.mat_elems * nrhs});
   }
   return PT_OK;
 }
 
-Launch push_launch(pt_solver* S, const std::vector<Job>& js, bool plr_terms = false, bool split_terms = false) {
+pt_status run_apply(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b) {
+  return run_apply_cfg(S, Lc, nrhs, ld, b, tuned(S, Lc, nrhs));
+}
+
+Launch push_launch(pt_solver* S, const std::vector<Job>& js, int cls, bool plr_terms = false,
+                   bool split_terms = false) {
   Launch Lc;
+  Lc.cls = cls;
   Lc.split = split_terms && S->split;
   if (Lc.split) plr_terms = false;
   Lc.job0 = (int)S->hjobs.size();
@@ -455,8 +476,8 @@ pt_status extract_blocks(pt_solver* S) {
     build_local_jobs(S, {l}, {0}, fw, bw);
     S->hjobs.resize(saved_jobs);
     std::vector<Launch> lf, lb;
-    for (auto& v : fw) lf.push_back(push_launch(S, v));
-    for (auto& v : bw) lb.push_back(push_launch(S, v));
+    for (auto& v : fw) lf.push_back(push_launch(S, v, PT_CLS_LOCAL));
+    for (auto& v : bw) lb.push_back(push_launch(S, v, PT_CLS_LOCAL));
     S->jobs.release();
     if (S->jobs.alloc(S->hjobs.size()) != hipSuccess) {
       rc = fail(PT_ENOMEM, "jobs");
@@ -542,8 +563,8 @@ void build_online_jobs(pt_solver* S) {
     build_local_jobs(S, ls, rb, fw, bw);
     S->fwd.clear();
     S->bwd.clear();
-    for (auto& v : fw) S->fwd.push_back(push_launch(S, v));
-    for (auto& v : bw) S->bwd.push_back(push_launch(S, v));
+    for (auto& v : fw) S->fwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
+    for (auto& v : bw) S->bwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
   }
   if (L < 2) return;
   const double2 one = make_double2(1.0, 0.0);
@@ -570,7 +591,7 @@ void build_online_jobs(pt_solver* S) {
         add_term(j, S->blk_pre(ku + 1, T_UP, a, b), vr(2, S->seg(1, ku + 1, b)), vr(1, S->seg(0, ku + 1, b)), one);
       js.push_back(j);
     }
-    S->sweep.push_back(push_launch(S, js, true, true));
+    S->sweep.push_back(push_launch(S, js, PT_CLS_SWEEP, true, true));
   }
   // reflection terms of a Gauss-Seidel pass: cur = r + (B_up - J0) a^prev, r + (B_dn - J1) d^prev
   {
@@ -588,7 +609,7 @@ void build_online_jobs(pt_solver* S) {
         for (int b = 0; b < 2; ++b) add_term(u, S->blk_pre(k + 1, B_DN, a, b), vr(1, S->seg(0, k, b)));
         js.push_back(u);
       }
-    S->bterm = push_launch(S, js, true, true);
+    S->bterm = push_launch(S, js, PT_CLS_REFLECT, true, true);
   }
   // polarized operator y = A x (bases 0 = x, 2 = y) and y = R x
   for (int which = 0; which < 2; ++which) {
@@ -620,9 +641,9 @@ void build_online_jobs(pt_solver* S) {
         js.push_back(u);
       }
     if (isA)
-      S->opA = push_launch(S, js, true);
+      S->opA = push_launch(S, js, PT_CLS_OPERATOR, true);
     else
-      S->opR = push_launch(S, js, true);
+      S->opR = push_launch(S, js, PT_CLS_OPERATOR, true);
   }
   (void)NX;
 }
@@ -932,6 +953,7 @@ pt_status pt_profile(pt_solver* S, int32_t enable) {
     }
     PTCHK(prof_harvest(S));
     S->stats = pt_kernel_stats{};
+    for (auto& k : S->cstats) k = pt_kernel_stats{};
     S->prof = true;
   } else {
     PTCHK(prof_harvest(S));
@@ -944,6 +966,121 @@ pt_status pt_profile_read(pt_solver* S, pt_kernel_stats* out) {
   if (!S || !out) return fail(PT_EINVAL, "null argument");
   PTCHK(prof_harvest(S));
   *out = S->stats;
+  return PT_OK;
+}
+
+pt_status pt_profile_read_class(pt_solver* S, int32_t cls, pt_kernel_stats* out) {
+  if (!S || !out) return fail(PT_EINVAL, "null argument");
+  if (cls < 0 || cls >= PT_CLS_COUNT) return fail(PT_EINVAL, "unknown launch class");
+  PTCHK(prof_harvest(S));
+  *out = S->cstats[cls];
+  return PT_OK;
+}
+
+// mean time of `reps` launches of Lc with shape tc (after one warm-up)
+static pt_status time_launch(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc,
+                             int reps, double& us) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool prof = S->prof;
+  S->prof = false;
+  pt_status rc = run_apply_cfg(S, Lc, nrhs, ld, b, tc);
+  if (rc == PT_OK && hipEventRecord(e0, S->st) != hipSuccess) rc = fail(PT_EHIP, "event");
+  for (int r = 0; r < reps && rc == PT_OK; ++r) rc = run_apply_cfg(S, Lc, nrhs, ld, b, tc);
+  float ms = 0.f;
+  if (rc == PT_OK && (hipEventRecord(e1, S->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(PT_EHIP, "event timing");
+  S->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  us = 1e3 * ms / reps;
+  return rc;
+}
+
+pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
+  PTCHK(check_nrhs(S, nrhs));
+  constexpr int kReps = 3;
+  const int L = S->L;
+  // work buffers as inputs and outputs of the trial launches (contents overwritten)
+  HIPCHK(hipMemsetAsync(S->W.p, 0, S->W.n * sizeof(double2), S->st));
+  HIPCHK(hipMemsetAsync(S->Bw.p, 0, S->Bw.n * sizeof(double2), S->st));
+  if (L >= 2)
+    for (auto* bf : {&S->U1, &S->U2, &S->tmp, &S->s}) HIPCHK(hipMemsetAsync(bf->p, 0, bf->n * sizeof(double2), S->st));
+  for (int cls = 0; cls < PT_CLS_COUNT; ++cls) {
+    pt_tune_entry e{cls, 0, 0, 0, 0.0, 0.0};
+    const Launch* Lc = nullptr;
+    Bases b{};
+    int64_t ld = S->Nt;
+    if (cls == PT_CLS_LOCAL && !S->fwd.empty()) {
+      Lc = &S->fwd[S->fwd.size() / 2];
+      b = Bases{{S->W.p, S->Bw.p, nullptr, nullptr}};
+      ld = (int64_t)S->sumR * S->NX;
+    } else if (cls == PT_CLS_SWEEP && L >= 3 && !S->sweep.empty()) {
+      Lc = &S->sweep[S->sweep.size() / 2];
+      b = Bases{{S->s.p, S->U1.p, S->U2.p, nullptr}};
+    } else if (cls == PT_CLS_REFLECT && L >= 2) {
+      Lc = &S->bterm;
+      b = Bases{{S->s.p, S->U1.p, S->U2.p, nullptr}};
+    } else if (cls == PT_CLS_OPERATOR && L >= 2) {
+      Lc = &S->opA;
+      b = Bases{{S->U1.p, nullptr, S->tmp.p, nullptr}};
+    }
+    if (Lc && Lc->njobs > 0) {
+      // candidate shapes of this launch
+      std::vector<TuneCfg> cands;
+      const ApplyGeom g = geom_for(S->NX, Lc->maxterms, nrhs, Lc->njobs);
+      if (Lc->split) {
+        if (nrhs > 16) {
+          for (int tr : {32, 64})
+            for (int ks : {1, 2, 4, 8, 16})
+              if ((size_t)ks * Lc->njobs * nrhs * S->NX <= S->part.n || ks == 1) {
+                TuneCfg c;
+                c.sp = SplitCfg{tr, ks};
+                cands.push_back(c);
+              }
+        } else {
+          for (int ks : {1, 2, 4}) {
+            TuneCfg c;
+            c.sp = SplitCfg{0, ks};
+            cands.push_back(c);
+          }
+        }
+      } else if (!Lc->plr && !S->f32 && g.mfma) {
+        for (int tn : {16, 32, 64})
+          for (int ks : {1, 2, 4})
+            if (tn == 16 || ks == 1) {
+              TuneCfg c;
+              c.tn = tn;
+              c.ks = ks;
+              cands.push_back(c);
+            }
+      }
+      PTCHK(time_launch(S, *Lc, nrhs, ld, b, nullptr, kReps, e.default_us));
+      e.best_us = e.default_us;
+      e.tried = 1;
+      const TuneCfg* best = nullptr;
+      for (const TuneCfg& c : cands) {
+        double us = 0;
+        PTCHK(time_launch(S, *Lc, nrhs, ld, b, &c, kReps, us));
+        ++e.tried;
+        if (us < e.best_us) {
+          e.best_us = us;
+          best = &c;
+        }
+      }
+      if (best) {
+        S->tune[cls][nrhs] = *best;
+        e.tile_rhs = best->tn ? best->tn : best->sp.tile_rhs;
+        e.ksplit = best->tn ? best->ks : best->sp.kslices;
+      } else {
+        S->tune[cls].erase(nrhs);
+      }
+    }
+    if (out) out[cls] = e;
+  }
+  HIPCHK(hipStreamSynchronize(S->st));
   return PT_OK;
 }
 

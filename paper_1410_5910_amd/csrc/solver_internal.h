@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -63,6 +64,7 @@ struct Layer {
 
 struct Launch {
   int job0 = 0, njobs = 0, maxterms = 0;
+  int cls = PT_CLS_LOCAL;    // pt_launch_class
   bool plr = false;          // job terms point at compressed blocks
   bool split = false;        // job terms point at split-bfloat16 planes
   double mat_elems = 0;      // matrix entries streamed by one launch
@@ -71,7 +73,14 @@ struct Launch {
 
 struct ProfPending {
   int ev;  // index of the event pair
+  int cls;
   double bytes, flops;
+};
+
+// a tuned launch shape (0: the built-in rule)
+struct TuneCfg {
+  int tn = 0, ks = 0;         // float64 MFMA tile width and wave groups
+  SplitCfg sp{0, 0};          // split-bfloat16 tile width and k-slices
 };
 
 // block types per layer; each is a 2x2 arrangement of NX x NX blocks
@@ -150,6 +159,8 @@ struct pt_solver {
   int ev_next = 0;
   std::vector<ProfPending> pend;
   pt_kernel_stats stats{};
+  pt_kernel_stats cstats[PT_CLS_COUNT]{};
+  std::map<int, TuneCfg> tune[PT_CLS_COUNT];  // per class: nrhs -> shape
 
   // work
   DevBuf<double2> W, Bw, fio, uio, s, V, Z, U1, U2, tmp, zeros, x;

@@ -552,33 +552,40 @@ hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, h
   return hipGetLastError();
 }
 
-// right-hand sides per tile of the wide form
-constexpr int kWideCols = 32;
+// right-hand sides per tile of the wide form (rule)
+constexpr int kWideColsRule = 32;
 
-int split_kslices(int njobs, int n, int nrhs) {
+int split_kslices(int njobs, int n, int nrhs, int tile_rhs) {
   if (nrhs <= 16) return 1;
+  if (tile_rhs <= 0) tile_rhs = kWideColsRule;
   constexpr long kCUs = 256;
-  const long tiles = (long)njobs * ((n + kWideRows - 1) / kWideRows) * ((nrhs + kWideCols - 1) / kWideCols);
+  const long tiles = (long)njobs * ((n + kWideRows - 1) / kWideRows) * ((nrhs + tile_rhs - 1) / tile_rhs);
   int ks = 1;
   while (ks < 16 && tiles * ks < 4 * kCUs) ks *= 2;
   return ks;
 }
 
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
-                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, float2* part) {
+                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, float2* part, SplitCfg cfg) {
   if (njobs <= 0) return hipSuccess;
   constexpr long kSimds = 1024;
   if (nrhs > 16) {
-    // 64 x 32 tiles; launches with fewer than four tiles per CU split the chunk
-    // sequence over k-slices (partial tiles in `part`, summed by a second kernel)
-    const int ks = split_kslices(njobs, n, nrhs);
-    if (ks > 1 && part) return launch_wide<kWideCols / 16, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
-    return launch_wide<kWideCols / 16, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+    // 64 x 32 (or 64 x 64) tiles; launches with fewer than four tiles per CU
+    // split the chunk sequence over k-slices (partial tiles in `part`, summed
+    // by a second kernel)
+    const int tr = cfg.tile_rhs == 64 ? 64 : kWideColsRule;
+    const int ks = cfg.kslices > 0 ? cfg.kslices : split_kslices(njobs, n, nrhs, tr);
+    if (ks > 1 && part) {
+      return tr == 64 ? launch_wide<4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part)
+                      : launch_wide<2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
+    }
+    return tr == 64 ? launch_wide<4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1)
+                    : launch_wide<2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
   }
   // 16-column tiles; the chunks of a tile are split over up to 4 waves until
   // the launch has about 4 waves per SIMD
   const long tasks = (long)njobs * ((n + 15) / 16) * ((nrhs + 15) / 16);
-  const int ks = tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
+  const int ks = cfg.kslices > 0 ? cfg.kslices : tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
   return launch_sp_ks<1>(ks, jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
 }
 

@@ -27,7 +27,9 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct", "pt_profile", "pt_profile_read",
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
-           "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load")
+           "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
+           "pt_profile_read_class", "pt_tune")
+CLASSES = ("local", "sweep", "reflect", "operator")
 
 
 class PtProblem(C.Structure):
@@ -56,6 +58,11 @@ class PtLayout(C.Structure):
 class PtKernelStats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("kernel_ms", C.c_double), ("alg_bytes", C.c_double),
                 ("alg_flops", C.c_double)]
+
+
+class PtTuneEntry(C.Structure):
+    _fields_ = [("cls", C.c_int32), ("tried", C.c_int32), ("tile_rhs", C.c_int32), ("ksplit", C.c_int32),
+                ("best_us", C.c_double), ("default_us", C.c_double)]
 
 
 class PolarError(RuntimeError):
@@ -97,6 +104,8 @@ def lib():
         L.pt_reconstruct.argtypes = [vp, i32, vp, vp, vp, i32]
         L.pt_profile.argtypes = [vp, i32]
         L.pt_profile_read.argtypes = [vp, C.POINTER(PtKernelStats)]
+        L.pt_profile_read_class.argtypes = [vp, i32, C.POINTER(PtKernelStats)]
+        L.pt_tune.argtypes = [vp, i32, C.POINTER(PtTuneEntry)]
         fp = C.POINTER(C.c_float)
         L.pt_learned_create.argtypes = [i32, C.c_uint64, vp, C.POINTER(vp)]
         L.pt_learned_free.argtypes = [vp]
@@ -191,6 +200,19 @@ class Solver:
         o = PtKernelStats()
         _check(self._lib.pt_profile_read(self._h, C.byref(o)))
         return {"launches": o.launches, "kernel_ms": o.kernel_ms, "alg_bytes": o.alg_bytes, "alg_flops": o.alg_flops}
+
+    def profile_read_class(self, cls: str) -> dict:
+        """Counters of one launch class: 'local', 'sweep', 'reflect' or 'operator'."""
+        o = PtKernelStats()
+        _check(self._lib.pt_profile_read_class(self._h, CLASSES.index(cls), C.byref(o)))
+        return {"launches": o.launches, "kernel_ms": o.kernel_ms, "alg_bytes": o.alg_bytes, "alg_flops": o.alg_flops}
+
+    def tune(self, nrhs: int) -> dict:
+        """Time every candidate tile shape of each launch class for nrhs sources and keep the fastest."""
+        arr = (PtTuneEntry * len(CLASSES))()
+        _check(self._lib.pt_tune(self._h, int(nrhs), arr))
+        return {CLASSES[e.cls]: {"tried": e.tried, "tile_rhs": e.tile_rhs, "ksplit": e.ksplit,
+                                 "best_us": e.best_us, "default_us": e.default_us} for e in arr}
 
     def get_block(self, layer: int, j: str, k: str) -> np.ndarray:
         """K^layer_{j,k} (NX x NX, rows: target x) for j, k in {'0', '1', 'n', 'n+1'}."""

@@ -329,3 +329,27 @@ def test_sparse_presolve_gaussian_tails_match_direct(layered4):
         assert rel(u[r], ud[r]) < 1e-8, r
     s = gs.trace_rhs(f)
     assert rel(s, ps.rhs(ps.newton(f))) < 1e-10
+
+
+# ---------------------------------------------------------------- autotuner
+@pytest.mark.parametrize("precision,nrhs", [("f64", 40), ("split-bf16", 40), ("f64", 3)])
+def test_tune_keeps_results(precision, nrhs):
+    prob, f = synth.config_small(nx=60, nz=60, npml=6, L=5, nrhs=nrhs, seed=61)
+    _flush(f"[gpu] tune {precision} nrhs={nrhs}")
+    gs = P.Solver.from_problem(prob, precision=precision, max_nrhs=nrhs, tol=1e-11, maxit=60)
+    u0, _ = gs.solve(f)
+    res = gs.tune(nrhs)
+    _flush(f"[gpu]   {res}")
+    assert set(res) == {"local", "sweep", "reflect", "operator"}
+    for cls, e in res.items():
+        assert e["tried"] >= 1 and e["best_us"] > 0 and e["best_us"] <= e["default_us"]
+        if nrhs > 4 and precision == "f64":
+            assert e["tried"] > 1, cls  # float64 MFMA shapes were timed
+    s = gs.layout()  # the solver is still usable
+    assert s["L"] == prob.L
+    u1, info = gs.solve(f)
+    ud = DirectSolver(prob).solve(f)
+    for r in range(nrhs):
+        assert rel(u1[r], ud[r]) < 1e-8, r
+    assert rel(u1, u0) < 1e-9
+    gs.close()
