@@ -140,19 +140,46 @@ KERNELS = {
 }
 
 
+def measured_traffic(kernel, cls, workload, precision):
+    """HBM bytes per launch recorded by a rocprofv3 FETCH_SIZE/WRITE_SIZE profile under profiles/, if the
+    kernel source it was measured on is the current one (else None)."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if (kv.get("kernel"), kv.get("class"), kv.get("workload"), kv.get("precision")) != \
+                    (kernel, cls, workload, precision):
+                continue
+            src = os.path.join(ROOT, kv["source"])
+            if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == kv["sha256"]:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def roofline(form):
     """Roofline of the dominant launch class (most kernel time per step), from live HIP-event timing."""
     k = form["kernel"]
     cls, st = max(k["classes"].items(), key=lambda kv: kv[1]["kernel_ms"])
     sec = st["kernel_ms"] / 1e3
     name, dt = KERNELS.get((cls, form["precision"]), ("block_gemm_kernel", form["precision"]))
-    base = {"traffic": None, "class": cls, "kernel": name, "launches_per_step": st["launches"] / k["nprof"],
+    if form.get("blocks", "dense") != "dense" and cls in ("sweep", "reflect", "operator"):
+        name, dt = "plr_apply_kernel", "f64"
+    elif dt == "bf16" and form["nrhs"] <= 16:
+        name = "block_split_kernel"
+    elif dt != "bf16" and form["nrhs"] <= 4:
+        name = "block_gemv_kernel"
+    traffic = measured_traffic(name, cls, form.get("workload"), form["precision"])
+    base = {"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
+            "class": cls, "kernel": name, "launches_per_step": st["launches"] / k["nprof"],
             "avg_launch_us": 1e3 * st["kernel_ms"] / st["launches"],
             "alg_bytes_per_launch": st["alg_bytes"] / st["launches"],
             "alg_flops_per_launch": st["alg_flops"] / st["launches"],
             "class_share_of_step": st["kernel_ms"] / k["nprof"] / form["ms_per_step"],
             "all_classes_ms_per_step": {c: v["kernel_ms"] / k["nprof"] for c, v in k["classes"].items()}}
-    if form["nrhs"] > 4 or dt == "bf16":
+    if (form["nrhs"] > 4 and name != "plr_apply_kernel") or dt == "bf16":
         # a split-bfloat16 complex multiply-add is 3 x 4 real bfloat16 products: 3x the counted flops
         fl = st["alg_flops"] * (3.0 if dt == "bf16" else 1.0)
         tfl = fl / sec / 1e12
@@ -191,6 +218,9 @@ def main():
     ap.add_argument("--all-forms", action="store_true",
                     help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -206,6 +236,18 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(nel, dtype=torch.float64, device="cuda:0")
+        big = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0")  # 2 GiB sweep: src leaves the caches
+        big.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy {args.calibrate_copy} MiB done")
+        del src, dst, big
 
     prob, f = make_workload(args.workload)
     if args.nrhs:
@@ -225,6 +267,7 @@ def main():
         log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
         form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune)
         form["workload"] = args.workload
+        form["roofline"] = roofline(form)
         if k:
             errs = oracle.errors(f, u, k)
             form["rel_err_vs_oracle"] = max(errs)
@@ -249,8 +292,11 @@ def main():
             pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
             log(f"form {wl} {prec}{' plr' if plr else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
-                               args.warmup, stream, profile=False, plr=plr, tune=not args.no_tune)
+                               args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune)
             form["workload"] = wl
+            rf = roofline(form)
+            form["roofline_dominant_class"] = {kk: rf[kk] for kk in ("class", "kernel", "bound", "achieved", "unit",
+                                                                     "frac", "avg_launch_us", "class_share_of_step")}
             if wl == args.workload:
                 orc = oracle
             else:
@@ -275,11 +321,11 @@ def main():
                             "f32": "float32 blocks and local factors, float64 Krylov vectors",
                             "f64": "float64"}[chosen["precision"]],
                    "gmres_tol": 1e-10, "gs_iters": 2, "iterations": chosen["iterations"]},
-        "roofline": roofline(chosen),
+        "roofline": chosen["roofline"],
         "rel_err_vs_oracle": chosen.get("rel_err_vs_oracle"),
         "rel_err_checked_rhs": chosen.get("rel_err_checked_rhs"),
         "vs_fp64_same_workload": (chosen["solves_per_s"] / f64_same[0]["solves_per_s"]) if f64_same else None,
-        "forms": [{kk: vv for kk, vv in fm.items() if kk != "kernel"} for fm in forms],
+        "forms": [{kk: vv for kk, vv in fm.items() if kk not in ("kernel", "roofline")} for fm in forms],
     }
     if not args.no_cpu:
         log("cpu baseline (oracle direct solve, about 10 s)")

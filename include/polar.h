@@ -185,6 +185,18 @@ pt_status pt_trace_rhs(pt_solver* s, int32_t nrhs, const double* f, double* out,
 pt_status pt_reconstruct(pt_solver* s, int32_t nrhs, const double* f, const double* x, double* u,
                          int32_t on_device);
 
+/* Several independent problems at once (problems of uneven size and L):
+ * problem i is solved by s[i] for nrhs[i] sources, f[i] -> u[i], info[i]
+ * (each as in pt_solve; info[i] may be NULL).  Each problem runs on its own
+ * host thread and its solver's stream, so the launches of different problems
+ * overlap on the GPU when the solvers were set up on distinct streams (on a
+ * shared stream they run one after another, with the same results).  The
+ * solvers must be distinct.  Returns PT_OK, or the first non-OK status in
+ * problem order (every problem is still attempted; pt_last_error describes
+ * that problem's failure). */
+pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
+                         double* const* u, int32_t on_device, pt_rhs_info* const* info);
+
 /* ---- live kernel timing ----------------------------------------------- */
 
 typedef struct {

@@ -3,6 +3,6 @@
 The compute path is libpolar.so (HIP for gfx950, C-ABI in include/polar.h);
 ``polar`` is its thin Python binding and ``build`` compiles it in-tree.
 """
-from .polar import Solver, Learned, PolarError, lib, OP_A, OP_R, OP_DINV, OP_PRECOND, EXPORTS  # noqa: F401
+from .polar import Solver, Learned, PolarError, lib, solve_batch, OP_A, OP_R, OP_DINV, OP_PRECOND, EXPORTS  # noqa: F401
 
-__all__ = ["Solver", "Learned", "PolarError", "lib", "OP_A", "OP_R", "OP_DINV", "OP_PRECOND", "EXPORTS"]
+__all__ = ["Solver", "Learned", "PolarError", "solve_batch", "lib", "OP_A", "OP_R", "OP_DINV", "OP_PRECOND", "EXPORTS"]

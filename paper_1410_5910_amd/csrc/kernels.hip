@@ -94,6 +94,17 @@ __device__ __forceinline__ const gd2* to_gd2(const double2* p) {
   return reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(p));
 }
 
+// Workgroup ids are dealt round-robin to the 8 XCDs, each with its own L2.
+// Renumber so that every XCD gets one contiguous range of logical ids: tiles
+// next to each other in logical order (the right-hand-side tiles of one block
+// row range) then meet in the same L2 and the block is fetched from HBM once.
+__device__ __forceinline__ int xcd_logical(int i, int G) {
+  constexpr int kXcd = 8;
+  const int x = i % kXcd, local = i / kXcd;
+  const int per = G / kXcd, rem = G % kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // base pointer of a VecRef without dynamic indexing of the by-value kernel argument
 __device__ __forceinline__ double2* base_of(const Bases& b, int buf) {
   return buf == 0 ? b.b[0] : buf == 1 ? b.b[1] : buf == 2 ? b.b[2] : buf == 3 ? b.b[3] : nullptr;
@@ -363,8 +374,8 @@ __global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __res
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);  // k-group (wave-uniform)
-  int bid = blockIdx.x;
-  const int ct = bid % nrt;  // right-hand-side tile
+  int bid = xcd_logical(blockIdx.x, gridDim.x);
+  const int ct = bid % nrt;  // right-hand-side tile (fastest: tiles sharing block rows stay on one XCD)
   bid /= nrt;
   const int tile = bid % ntiles;
   const Job& J = jobs[bid / ntiles];

@@ -257,8 +257,12 @@ std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
 // ---------------------------------------------------------------------------
 // Jobs of the sweep over the layers in `ls` on a local field whose layer l
 // starts at local row rb[l]: bases 0 = solution W, 1 = right-hand side B.
+// Local-solve jobs of the layers ls (row bases rb).  The backward pass of
+// layer q stops at local row rmin[q] (empty: row 0): rows above the lowest row
+// a caller reads are never needed, since the backward recurrence runs upward.
 void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vector<int>& rb,
-                      std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw) {
+                      std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw,
+                      const std::vector<int>& rmin = {}) {
   const int NX = S->NX;
   int Rm = 0;
   for (int l : ls) Rm = std::max(Rm, S->lay[l].R);
@@ -278,7 +282,8 @@ void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vecto
         add_term(j, S->dinv(l, r), vr(1, (int64_t)(rb[q] + r) * NX));
       fw[r].push_back(j);
     }
-    for (int r = y.R - 2; r >= 0; --r) {
+    const int r_stop = rmin.empty() ? 0 : std::max(0, rmin[q]);
+    for (int r = y.R - 2; r >= r_stop; --r) {
       // x_r = y_r - u_r Dinv_r x_{r+1}
       Job j = empty_job();
       j.Y = vr(0, (int64_t)(rb[q] + r) * NX);
@@ -565,6 +570,24 @@ void build_online_jobs(pt_solver* S) {
     S->bwd.clear();
     for (auto& v : fw) S->fwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
     for (auto& v : bw) S->bwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
+    // backward passes that stop at the rows their caller reads: the trace
+    // rows (pre-solve: rows 0, 1 of layers with a top interface, rows n,
+    // n+1 otherwise) and the owned rows (reconstruction)
+    std::vector<int> rm_pre(L), rm_rec(L);
+    for (int l = 0; l < L; ++l) {
+      const Layer& y = S->lay[l];
+      rm_pre[l] = y.top_ext ? y.r0 : (y.bot_ext ? y.rn : 0);
+      rm_rec[l] = y.top_ext;
+    }
+    S->bwd_pre.clear();
+    S->bwd_rec.clear();
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<std::vector<Job>> f2, b2;
+      build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? rm_pre : rm_rec);
+      auto& dst = pass == 0 ? S->bwd_pre : S->bwd_rec;
+      for (auto& v : b2)
+        if (!v.empty()) dst.push_back(push_launch(S, v, PT_CLS_LOCAL));
+    }
   }
   if (L < 2) return;
   const double2 one = make_double2(1.0, 0.0);
@@ -761,7 +784,7 @@ pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y,
 // Newton potentials w^l = (A^l)^-1 h^2 f^l of every layer into S->W
 pt_status newton(pt_solver* S, const double2* f, int nrhs) {
   HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
-  return run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
+  return run_local(S, S->fwd, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
 // all sources vanish: s = 0
@@ -825,7 +848,7 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   const int64_t ld = (int64_t)S->sumR * S->NX;
   HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
                               S->h * S->h, st));
-  PTCHK(run_local(S, S->fwd, S->bwd, m, ld, S->W.p, S->Bw.p));
+  PTCHK(run_local(S, S->fwd, S->bwd_pre, m, ld, S->W.p, S->Bw.p));
   HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
                              S->sumR, S->NX, S->Nt, nrhs, st));
   // the pinned slot tables are rewritten by the next call: finish their uploads first
@@ -838,7 +861,7 @@ pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2*
   if (S->L >= 2)
     HIPCHK(launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
                             S->Nt, nrhs, (int64_t)2 * (S->L - 1) * S->NX, S->st));
-  PTCHK(run_local(S, S->fwd, S->bwd, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
+  PTCHK(run_local(S, S->fwd, S->bwd_rec, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
   HIPCHK(launch_gather_owned(S->W.p, u, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->st));
   return PT_OK;
 }
@@ -959,6 +982,29 @@ pt_status pt_profile(pt_solver* S, int32_t enable) {
     PTCHK(prof_harvest(S));
     S->prof = false;
   }
+  return PT_OK;
+}
+
+pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
+                         double* const* u, int32_t on_device, pt_rhs_info* const* info) {
+  if (nprob < 0 || (nprob > 0 && (!s || !nrhs || !f || !u))) return fail(PT_EINVAL, "null argument");
+  for (int i = 0; i < nprob; ++i) {
+    if (!s[i]) return fail(PT_EINVAL, "null solver");
+    for (int j = 0; j < i; ++j)
+      if (s[j] == s[i]) return fail(PT_EINVAL, "a solver appears twice in the batch");
+  }
+  std::vector<pt_status> st(nprob, PT_OK);
+  std::vector<std::string> msg(nprob);
+  std::vector<std::thread> th;
+  th.reserve(nprob);
+  for (int i = 0; i < nprob; ++i)
+    th.emplace_back([&, i]() {
+      st[i] = pt_solve(s[i], nrhs[i], f[i], u[i], on_device, info ? info[i] : nullptr);
+      if (st[i] != PT_OK) msg[i] = g_err;  // the message is per thread
+    });
+  for (auto& t : th) t.join();
+  for (int i = 0; i < nprob; ++i)
+    if (st[i] != PT_OK) return fail(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
   return PT_OK;
 }
 

@@ -147,6 +147,7 @@ struct pt_solver {
   std::vector<Job> hjobs;
   DevBuf<Job> jobs;
   std::vector<Launch> fwd, bwd, sweep;
+  std::vector<Launch> bwd_pre, bwd_rec;  // backward passes stopped at the trace rows / the owned rows
   Launch bterm, opA, opR;
 
   // learned preconditioner stage (null: sweeps only)

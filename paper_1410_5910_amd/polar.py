@@ -28,7 +28,7 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
-           "pt_profile_read_class", "pt_tune")
+           "pt_profile_read_class", "pt_tune", "pt_solve_batch")
 CLASSES = ("local", "sweep", "reflect", "operator")
 
 
@@ -106,6 +106,8 @@ def lib():
         L.pt_profile_read.argtypes = [vp, C.POINTER(PtKernelStats)]
         L.pt_profile_read_class.argtypes = [vp, i32, C.POINTER(PtKernelStats)]
         L.pt_tune.argtypes = [vp, i32, C.POINTER(PtTuneEntry)]
+        L.pt_solve_batch.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), i32,
+                                     C.POINTER(C.POINTER(PtRhsInfo))]
         fp = C.POINTER(C.c_float)
         L.pt_learned_create.argtypes = [i32, C.c_uint64, vp, C.POINTER(vp)]
         L.pt_learned_free.argtypes = [vp]
@@ -382,3 +384,32 @@ class Learned:
 
     def load(self, path: str):
         _check(self._lib.pt_learned_load(self._h, os.fsencode(path)))
+
+
+def solve_batch(solvers, fs):
+    """Solve independent problems at once (pt_solve_batch): solvers[i] on fs[i] (all host arrays or all device
+    tensors).  Returns [(u_i, infos_i)].  Give each solver its own stream for the problems to overlap."""
+    n = len(solvers)
+    if n != len(fs):
+        raise ValueError("one source array per solver")
+    L = lib()
+    preps, outs, infos = [], [], []
+    dev0 = None
+    for sv, f in zip(solvers, fs):
+        p, dev, keep, k = sv._prep(f, (sv.NZ, sv.NX))
+        if dev0 is None:
+            dev0 = dev
+        elif dev != dev0:
+            raise TypeError("all host arrays or all device tensors")
+        preps.append((p, keep, k))
+        outs.append(sv._out(keep, dev, (k, sv.NZ, sv.NX)))
+        infos.append((PtRhsInfo * k)())
+    hs = (C.c_void_p * n)(*[sv._h for sv in solvers])
+    ks = (C.c_int32 * n)(*[k for _, _, k in preps])
+    fp = (C.c_void_p * n)(*[p for p, _, _ in preps])
+    up = (C.c_void_p * n)(*[Solver._ptr(u, dev0) for u in outs])
+    ip = (C.POINTER(PtRhsInfo) * n)(*[C.cast(i, C.POINTER(PtRhsInfo)) for i in infos])
+    _check(L.pt_solve_batch(n, hs, ks, fp, up, dev0 or 0, ip), allow=(PT_ENOCONV,))
+    return [(u, [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
+                  "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in inf])
+            for u, inf in zip(outs, infos)]

@@ -353,3 +353,29 @@ def test_tune_keeps_results(precision, nrhs):
         assert rel(u1[r], ud[r]) < 1e-8, r
     assert rel(u1, u0) < 1e-9
     gs.close()
+
+
+# ---------------------------------------------------------------- several problems at once
+def test_solve_batch_uneven_problems():
+    import torch
+    probs = [synth.config_small(nx=nx, nz=nz, npml=5, L=L, nrhs=k, seed=70 + i)
+             for i, (nx, nz, L, k) in enumerate([(24, 30, 3, 2), (40, 48, 4, 5), (30, 24, 2, 1), (56, 40, 5, 3)])]
+    _flush("[gpu] solve_batch: 4 uneven problems")
+    streams = [torch.cuda.Stream() for _ in probs]
+    solvers = [P.Solver.from_problem(p, max_nrhs=f.shape[0], tol=1e-11, maxit=60, stream=st.cuda_stream)
+               for (p, f), st in zip(probs, streams)]
+    res = P.solve_batch(solvers, [f for _, f in probs])
+    for (p, f), sv, (u, infos) in zip(probs, solvers, res):
+        ud = DirectSolver(p).solve(f)
+        assert max(rel(u[r], ud[r]) for r in range(f.shape[0])) < 1e-8
+        assert all(i["converged"] for i in infos)
+        u1, _ = sv.solve(f)  # the same problem alone: the same result
+        assert rel(u1, u) < 1e-13
+    # device arrays
+    dres = P.solve_batch(solvers, [torch.from_numpy(f).to("cuda:0") for _, f in probs])
+    for (u, _), (ud, _) in zip(res, dres):
+        assert rel(ud.cpu().numpy(), u) < 1e-13
+    with pytest.raises(P.PolarError):
+        P.solve_batch([solvers[0], solvers[0]], [probs[0][1], probs[0][1]])
+    for sv in solvers:
+        sv.close()
