@@ -704,6 +704,19 @@ __global__ void init_delta_kernel(double2* const* out, const double2* const* dia
   out[b][e] = tridiag_entry(i, c, diag[b], west, east);
 }
 
+// G[b] += Y[b] - tridiag(A_m): the two halves of the middle Schur complement
+// of a two-ended elimination, each of which already holds tridiag(A_m)
+__global__ void twist_combine_kernel(double2* const* G, const double2* const* Y, const double2* const* diag,
+                                     const double2* west, const double2* east, int n) {
+  const int b = blockIdx.y;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int c = (int)(e / n), i = (int)(e % n);
+  const double2 d = tridiag_entry(i, c, diag[b], west, east);
+  const double2 g = G[b][e], y = Y[b][e];
+  G[b][e] = make_double2(g.x + y.x - d.x, g.y + y.y - d.y);
+}
+
 __global__ void finish_row_kernel(double2* const* B, const int32_t* pi, double2* const* dinv64,
                                   float2* const* dinv32, double2* const* nextD, const double2* const* next_diag,
                                   const double2* coef, const double2* west, const double2* east, int n) {
@@ -1087,6 +1100,13 @@ hipError_t launch_init_delta(double2* const* out, const double2* const* diag, co
                              const double2* east, int nb, int n, hipStream_t st) {
   const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(init_delta_kernel, dim3(gx, nb), dim3(kThreads), 0, st, out, diag, west, east, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_twist_combine(double2* const* G, const double2* const* Y, const double2* const* diag,
+                                const double2* west, const double2* east, int nb, int n, hipStream_t st) {
+  const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(twist_combine_kernel, dim3(gx, nb), dim3(kThreads), 0, st, G, Y, diag, west, east, n);
   return hipGetLastError();
 }
 

@@ -97,6 +97,11 @@ hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* cons
                              const double2* const* next_diag, const double2* coef, const double2* west,
                              const double2* east, int nb, int n, hipStream_t st);
 
+// Middle Schur complement of a two-ended elimination: G[b] += Y[b] - tridiag(diag[b]),
+// where G[b] and Y[b] (column-major) each hold tridiag(A_m) minus one side's term.
+hipError_t launch_twist_combine(double2* const* G, const double2* const* Y, const double2* const* diag,
+                                const double2* west, const double2* east, int nb, int n, hipStream_t st);
+
 // --------------------------------------------------------- field kernels
 // Local fields: (nrhs, sumR, NX); volume fields: (nrhs, NZ, NX).
 // rowmap[g] for local row g in 0..sumR-1: the padded-grid row it copies from

@@ -213,6 +213,7 @@ void make_layout(pt_solver* S) {
     y.r1 = y.top_ext ? y.top_ext : -1;
     y.rn = y.bot_ext ? y.top_ext + y.n - 1 : -1;
     y.rn1 = y.bot_ext ? y.top_ext + y.n : -1;
+    y.mid = y.R / 2;
     start += y.n;
     rowbase += y.R;
     S->lay.push_back(y);
@@ -257,40 +258,77 @@ std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
 // ---------------------------------------------------------------------------
 // Jobs of the sweep over the layers in `ls` on a local field whose layer l
 // starts at local row rb[l]: bases 0 = solution W, 1 = right-hand side B.
-// Local-solve jobs of the layers ls (row bases rb).  The backward pass of
-// layer q stops at local row rmin[q] (empty: row 0): rows above the lowest row
-// a caller reads are never needed, since the backward recurrence runs upward.
+// Local-solve jobs of the layers ls (row bases rb), two-ended (matching the
+// factorisation): forward launch f eliminates row f top-down and row R-1-f
+// bottom-up in every layer, y_r = Delta_r^-1 (b_r - l_r y_{r-1}) and
+// z_r = Sigma_r^-1 (b_r - u_r z_{r+1}); the last forward launch solves the
+// middle row, x_m = Gamma_m^-1 (b_m - l_m y_{m-1} - u_m z_{m+1}); backward
+// launches run outward, x_r = y_r - u_r Delta_r^-1 x_{r+1} above the middle and
+// x_r = z_r - l_r Sigma_r^-1 x_{r-1} below it, only as far as rows
+// rmin[q]..rmax[q] (empty: all rows): rows beyond the ones a caller reads are
+// never needed, since the backward recurrences run outward.
 void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vector<int>& rb,
                       std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw,
-                      const std::vector<int>& rmin = {}) {
+                      const std::vector<int>& rmin = {}, const std::vector<int>& rmax = {}) {
   const int NX = S->NX;
-  int Rm = 0;
-  for (int l : ls) Rm = std::max(Rm, S->lay[l].R);
-  fw.assign(Rm, {});
-  bw.assign(std::max(0, Rm - 1), {});
+  int F = 0, G = 0;
+  for (size_t q = 0; q < ls.size(); ++q) {
+    const Layer& y = S->lay[ls[q]];
+    const int lo = rmin.empty() ? 0 : rmin[q], hi = rmax.empty() ? y.R - 1 : rmax[q];
+    F = std::max(F, std::max(y.mid, y.R - 1 - y.mid));
+    G = std::max(G, std::max(y.mid - std::min(lo, y.mid), std::max(hi, y.mid) - y.mid));
+  }
+  fw.assign(F + 1, {});
+  bw.assign(G, {});
+  auto row = [&](size_t q, int r) { return (int64_t)(rb[q] + r) * NX; };
   for (size_t q = 0; q < ls.size(); ++q) {
     const int l = ls[q];
     const Layer& y = S->lay[l];
-    for (int r = 0; r < y.R; ++r) {
-      // y_r = Dinv_r (b_r - l_r y_{r-1})
+    const int m = y.mid;
+    const int lo = rmin.empty() ? 0 : rmin[q], hi = rmax.empty() ? y.R - 1 : rmax[q];
+    for (int r = 0; r < m; ++r) {  // top-down
       Job j = empty_job();
-      j.Y = vr(0, (int64_t)(rb[q] + r) * NX);
-      const cd lr = S->lcoef[y.rowbase + r];
+      j.Y = vr(0, row(q, r));
       if (r > 0)
-        add_term(j, S->dinv(l, r), vr(1, (int64_t)(rb[q] + r) * NX), vr(0, (int64_t)(rb[q] + r - 1) * NX), d2(-lr));
+        add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r - 1)), d2(-S->lcoef[y.rowbase + r]));
       else
-        add_term(j, S->dinv(l, r), vr(1, (int64_t)(rb[q] + r) * NX));
+        add_term(j, S->dinv(l, r), vr(1, row(q, r)));
       fw[r].push_back(j);
     }
-    const int r_stop = rmin.empty() ? 0 : std::max(0, rmin[q]);
-    for (int r = y.R - 2; r >= r_stop; --r) {
-      // x_r = y_r - u_r Dinv_r x_{r+1}
+    for (int r = y.R - 1; r > m; --r) {  // bottom-up
       Job j = empty_job();
-      j.Y = vr(0, (int64_t)(rb[q] + r) * NX);
+      j.Y = vr(0, row(q, r));
+      if (r < y.R - 1)
+        add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r + 1)), d2(-S->ucoef[y.rowbase + r]));
+      else
+        add_term(j, S->dinv(l, r), vr(1, row(q, r)));
+      fw[y.R - 1 - r].push_back(j);
+    }
+    {  // middle row
+      Job j = empty_job();
+      j.Y = vr(0, row(q, m));
+      if (m > 0)
+        add_term(j, S->dinv(l, m), vr(1, row(q, m)), vr(0, row(q, m - 1)), d2(-S->lcoef[y.rowbase + m]));
+      else
+        add_term(j, S->dinv(l, m), vr(1, row(q, m)));
+      if (m < y.R - 1) add_term(j, S->dinv(l, m), none(), vr(0, row(q, m + 1)), d2(-S->ucoef[y.rowbase + m]));
+      fw[F].push_back(j);
+    }
+    for (int r = m - 1; r >= lo; --r) {  // outward, upper part
+      Job j = empty_job();
+      j.Y = vr(0, row(q, r));
       j.P = j.Y;
       j.alpha = d2(-S->ucoef[y.rowbase + r]);
-      add_term(j, S->dinv(l, r), vr(0, (int64_t)(rb[q] + r + 1) * NX));
-      bw[y.R - 2 - r].push_back(j);
+      add_term(j, S->dinv(l, r), vr(0, row(q, r + 1)));
+      bw[m - 1 - r].push_back(j);
+    }
+    for (int r = m + 1; r <= hi; ++r) {  // outward, lower part
+      Job j = empty_job();
+      j.Y = vr(0, row(q, r));
+      j.P = j.Y;
+      j.alpha = d2(-S->lcoef[y.rowbase + r]);
+      add_term(j, S->dinv(l, r), vr(0, row(q, r - 1)));
+      bw[r - m - 1].push_back(j);
     }
   }
 }
@@ -306,25 +344,31 @@ pt_status run_local(pt_solver* S, const std::vector<Launch>& fw, const std::vect
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
+// Two-ended line-by-line factorisation of every layer (appendix B's
+// recurrence run from both ends).  Rows 0..m-1 are eliminated top-down,
+// Delta_0 = A_0, Delta_{r+1} = A_{r+1} - l_{r+1} u_r Delta_r^-1; rows R-1..m+1
+// bottom-up, Sigma_{R-1} = A_{R-1}, Sigma_{r-1} = A_{r-1} - u_{r-1} l_r Sigma_r^-1;
+// the middle row gets Gamma_m = A_m - l_m u_{m-1} Delta_{m-1}^-1 - u_m l_{m+1}
+// Sigma_{m+1}^-1.  The inverses are stored in the slot of their row.  Both
+// chains of all layers advance together, one pivoted Gauss-Jordan inversion
+// (FP64) per step; each chain's last step leaves its half of Gamma_m, and the
+// halves are combined and inverted last.
 pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::vector<cd>& west,
                     const std::vector<cd>& east) {
   const int NX = S->NX, L = S->L;
+  const int NC = 2 * L;  // chains: 2l top-down, 2l+1 bottom-up
   const size_t E = S->block_elems();
   hipStream_t st = S->st;
   DevBuf<double2> dg, dw, de, gjA, gjB, coef;
   DevBuf<int32_t> perm, pi;
-  DevBuf<double2*> pA, pB, pD, pN, pDiag;
+  DevBuf<double2*> pA, pB, pD, pN, pDiag, pY;
   DevBuf<float2*> pD32;
   pt_status rc = PT_OK;
   auto cleanup = [&]() {
     for (auto* b : {&dg, &dw, &de, &gjA, &gjB, &coef}) b->release();
     perm.release();
     pi.release();
-    pA.release();
-    pB.release();
-    pD.release();
-    pN.release();
-    pDiag.release();
+    for (auto* b : {&pA, &pB, &pD, &pN, &pDiag, &pY}) b->release();
     pD32.release();
   };
   auto chk = [&](hipError_t e, const char* what) {
@@ -333,10 +377,11 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
     return rc == PT_OK;
   };
   if (!chk(dg.alloc(diag_all.size()), "alloc diag") || !chk(dw.alloc(NX), "alloc") || !chk(de.alloc(NX), "alloc") ||
-      !chk(gjA.alloc(E * L), "alloc gj") || !chk(gjB.alloc(E * L), "alloc gj") || !chk(coef.alloc(L), "alloc") ||
-      !chk(perm.alloc((size_t)L * NX), "alloc") || !chk(pi.alloc((size_t)L * NX), "alloc") ||
-      !chk(pA.alloc(L), "alloc") || !chk(pB.alloc(L), "alloc") || !chk(pD.alloc(L), "alloc") ||
-      !chk(pN.alloc(L), "alloc") || !chk(pDiag.alloc(L), "alloc") || !chk(pD32.alloc(L), "alloc")) {
+      !chk(gjA.alloc(E * NC), "alloc gj") || !chk(gjB.alloc(E * NC), "alloc gj") || !chk(coef.alloc(NC), "alloc") ||
+      !chk(perm.alloc((size_t)NC * NX), "alloc") || !chk(pi.alloc((size_t)NC * NX), "alloc") ||
+      !chk(pA.alloc(NC), "alloc") || !chk(pB.alloc(NC), "alloc") || !chk(pD.alloc(NC), "alloc") ||
+      !chk(pN.alloc(NC), "alloc") || !chk(pDiag.alloc(NC), "alloc") || !chk(pY.alloc(NC), "alloc") ||
+      !chk(pD32.alloc(NC), "alloc")) {
     cleanup();
     return rc;
   }
@@ -348,76 +393,118 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
     cleanup();
     return rc;
   }
-  // Each layer alternates between its two Gauss-Jordan buffers; cur[l] is
-  // the buffer holding the current Schur complement Delta_r.
-  std::vector<int> cur(L, 0);
-  std::vector<double2*> hA(L), hB(L), hD(L), hN(L), hDiag(L);
-  std::vector<float2*> hD32(L, nullptr);
-  std::vector<double2> hcoef(L);
-  {
-    std::vector<double2*> out(L), diag0(L);
-    for (int l = 0; l < L; ++l) {
-      out[l] = gjA.p + (size_t)l * E;
-      diag0[l] = (double2*)dg.p + (size_t)S->lay[l].rowbase * NX;
-    }
-    chk(hipMemcpy(pA.p, out.data(), L * sizeof(double2*), hipMemcpyHostToDevice), "copy");
-    chk(hipMemcpy(pDiag.p, diag0.data(), L * sizeof(double2*), hipMemcpyHostToDevice), "copy");
-    chk(launch_init_delta(pA.p, (const double2* const*)pDiag.p, dw.p, de.p, L, NX, st), "init_delta");
-  }
-  for (int r = 0; r < S->Rmax && rc == PT_OK; ++r) {
-    std::vector<int> act;
-    for (int l = 0; l < L; ++l)
-      if (r < S->lay[l].R) act.push_back(l);
-    const int nb = (int)act.size();
-    for (int q = 0; q < nb; ++q) {
-      const int l = act[q];
-      double2* bufs[2] = {gjA.p + (size_t)l * E, gjB.p + (size_t)l * E};
-      hA[q] = bufs[cur[l]];
-      hB[q] = bufs[1 - cur[l]];
-    }
-    chk(hipMemcpyAsync(pA.p, hA.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
-    chk(hipMemcpyAsync(pB.p, hB.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+  auto diag_of = [&](int l, int r) { return (double2*)dg.p + (size_t)(S->lay[l].rowbase + r) * NX; };
+  auto buf = [&](int c, int which) { return (which ? gjB.p : gjA.p) + (size_t)c * E; };
+  // chain c: its layer, direction, length and the local row of its step f
+  auto chain_len = [&](int c) {
+    const Layer& y = S->lay[c / 2];
+    return (c & 1) ? y.R - 1 - y.mid : y.mid;
+  };
+  auto chain_row = [&](int c, int f) { return (c & 1) ? S->lay[c / 2].R - 1 - f : f; };
+  int F = 0;
+  for (int c = 0; c < NC; ++c) F = std::max(F, chain_len(c));
+  std::vector<int> cur(NC, 0);  // which of the chain's two buffers holds its current matrix
+
+  // Invert the nb matrices whose pointers are in pA (scratch in pB); returns whether the result is in pB.
+  auto gj_invert = [&](int nb) {
     for (int k = 0; k < NX && rc == PT_OK; ++k) {
-      // even steps read pA and write pB, odd steps the reverse
       if (k % 2 == 0)
         chk(launch_gj_step(pA.p, pB.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
       else
         chk(launch_gj_step(pB.p, pA.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
     }
     chk(launch_gj_perm(perm.p, pi.p, nb, NX, st), "gj_perm");
-    // result is in pB if NX is odd, else in pA
-    const bool inB = (NX % 2) == 1;
-    std::vector<double2*> hRes(nb);
+    return (NX % 2) == 1;
+  };
+  auto upload = [&](DevBuf<double2*>& d, const std::vector<double2*>& h) {
+    return chk(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+  };
+  // first matrix of every non-empty chain: tridiag of its first row; an empty
+  // chain's half of Gamma_m is tridiag(A_m) itself
+  {
+    std::vector<double2*> out, dia;
+    for (int c = 0; c < NC; ++c) {
+      const int l = c / 2;
+      out.push_back(buf(c, 0));
+      dia.push_back(chain_len(c) > 0 ? diag_of(l, chain_row(c, 0)) : diag_of(l, S->lay[l].mid));
+    }
+    upload(pA, out);
+    upload(pDiag, dia);
+    chk(launch_init_delta(pA.p, (const double2* const*)pDiag.p, dw.p, de.p, NC, NX, st), "init_delta");
+    chk(hipStreamSynchronize(st), "sync");
+  }
+  std::vector<float2*> hD32(NC, nullptr);
+  for (int f = 0; f < F && rc == PT_OK; ++f) {
+    std::vector<int> act;
+    for (int c = 0; c < NC; ++c)
+      if (f < chain_len(c)) act.push_back(c);
+    const int nb = (int)act.size();
+    std::vector<double2*> hA(nb), hB(nb), hD(nb), hN(nb), hDiag(nb), hRes(nb);
+    std::vector<double2> hcoef(nb);
     for (int q = 0; q < nb; ++q) {
-      const int l = act[q];
+      hA[q] = buf(act[q], cur[act[q]]);
+      hB[q] = buf(act[q], 1 - cur[act[q]]);
+    }
+    upload(pA, hA);
+    upload(pB, hB);
+    const bool inB = gj_invert(nb);
+    for (int q = 0; q < nb; ++q) {
+      const int c = act[q], l = c / 2;
       const Layer& y = S->lay[l];
-      double2* res = inB ? hB[q] : hA[q];
+      const int r = chain_row(c, f);
+      hRes[q] = inB ? hB[q] : hA[q];
       double2* other = inB ? hA[q] : hB[q];
-      hRes[q] = res;
       hD[q] = S->dinv64.p + (size_t)(y.rowbase + r) * E;
-      if (r + 1 < y.R) {
-        hN[q] = other;
-        hDiag[q] = (double2*)dg.p + (size_t)(y.rowbase + r + 1) * NX;
-        const cd c = S->lcoef[y.rowbase + r + 1] * S->ucoef[y.rowbase + r];
-        hcoef[q] = d2(c);
-        cur[l] = (other == gjA.p + (size_t)l * E) ? 0 : 1;
-      } else {
-        hN[q] = nullptr;
-        hDiag[q] = nullptr;
-        hcoef[q] = make_double2(0.0, 0.0);
-      }
+      // next matrix of the chain: the next row's Schur complement, or after the
+      // last step this chain's half of Gamma_m (the next row is then m)
+      const int rn = (c & 1) ? r - 1 : r + 1;
+      hN[q] = other;
+      hDiag[q] = diag_of(l, rn);
+      const cd cf = (c & 1) ? S->ucoef[y.rowbase + rn] * S->lcoef[y.rowbase + r]
+                            : S->lcoef[y.rowbase + rn] * S->ucoef[y.rowbase + r];
+      hcoef[q] = d2(cf);
+      cur[c] = (other == buf(c, 0)) ? 0 : 1;
     }
     // pB may still be read by the last elimination steps: the copy is stream-ordered after them
-    chk(hipMemcpyAsync(pB.p, hRes.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
-    chk(hipMemcpyAsync(pD.p, hD.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
-    chk(hipMemcpyAsync(pN.p, hN.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
-    chk(hipMemcpyAsync(pDiag.p, hDiag.data(), nb * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
+    upload(pB, hRes);
+    upload(pD, hD);
+    upload(pN, hN);
+    upload(pDiag, hDiag);
     chk(hipMemcpyAsync(pD32.p, hD32.data(), nb * sizeof(float2*), hipMemcpyHostToDevice, st), "copy");
     chk(hipMemcpyAsync(coef.p, hcoef.data(), nb * sizeof(double2), hipMemcpyHostToDevice, st), "copy");
     chk(launch_finish_row(pB.p, pi.p, pD.p, pD32.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, nb,
                           NX, st),
         "finish_row");
-    // the host vectors are reused next row: wait for the copies
+    chk(hipStreamSynchronize(st), "sync");
+  }
+  // Gamma_m = (top half) + (bottom half) - tridiag(A_m), inverted into the slot of row m
+  if (rc == PT_OK) {
+    std::vector<double2*> hG(L), hY(L), hDiag(L), hS(L), hD(L), hN(L, nullptr), hRes(L);
+    for (int l = 0; l < L; ++l) {
+      hG[l] = buf(2 * l, cur[2 * l]);
+      hY[l] = buf(2 * l + 1, cur[2 * l + 1]);
+      hDiag[l] = diag_of(l, S->lay[l].mid);
+      hS[l] = buf(2 * l, 1 - cur[2 * l]);
+      hD[l] = S->dinv64.p + (size_t)(S->lay[l].rowbase + S->lay[l].mid) * E;
+    }
+    upload(pA, hG);
+    upload(pY, hY);
+    upload(pDiag, hDiag);
+    chk(launch_twist_combine(pA.p, (const double2* const*)pY.p, (const double2* const*)pDiag.p, dw.p, de.p, L, NX,
+                             st),
+        "twist_combine");
+    upload(pB, hS);
+    const bool inB = gj_invert(L);
+    for (int l = 0; l < L; ++l) hRes[l] = inB ? hS[l] : hG[l];
+    upload(pB, hRes);
+    upload(pD, hD);
+    upload(pN, hN);
+    for (auto& d : hDiag) d = nullptr;
+    upload(pDiag, hDiag);
+    chk(hipMemcpyAsync(pD32.p, hD32.data(), L * sizeof(float2*), hipMemcpyHostToDevice, st), "copy");
+    chk(launch_finish_row(pB.p, pi.p, pD.p, pD32.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, L, NX,
+                          st),
+        "finish_row");
     chk(hipStreamSynchronize(st), "sync");
   }
   int32_t flag = 0;
@@ -571,19 +658,26 @@ void build_online_jobs(pt_solver* S) {
     for (auto& v : fw) S->fwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
     for (auto& v : bw) S->bwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
     // backward passes that stop at the rows their caller reads: the trace
-    // rows (pre-solve: rows 0, 1 of layers with a top interface, rows n,
-    // n+1 otherwise) and the owned rows (reconstruction)
-    std::vector<int> rm_pre(L), rm_rec(L);
+    // rows 0, 1, n, n+1 (pre-solve) and the owned rows (reconstruction)
+    std::vector<int> lo_pre(L), hi_pre(L), lo_rec(L), hi_rec(L);
     for (int l = 0; l < L; ++l) {
       const Layer& y = S->lay[l];
-      rm_pre[l] = y.top_ext ? y.r0 : (y.bot_ext ? y.rn : 0);
-      rm_rec[l] = y.top_ext;
+      int lo = y.R, hi = -1;
+      for (int r : {y.r0, y.r1, y.rn, y.rn1})
+        if (r >= 0) {
+          lo = std::min(lo, r);
+          hi = std::max(hi, r);
+        }
+      lo_pre[l] = hi >= 0 ? lo : y.mid;
+      hi_pre[l] = hi >= 0 ? hi : y.mid;
+      lo_rec[l] = y.top_ext;
+      hi_rec[l] = y.top_ext + y.n - 1;
     }
     S->bwd_pre.clear();
     S->bwd_rec.clear();
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<std::vector<Job>> f2, b2;
-      build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? rm_pre : rm_rec);
+      build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? lo_pre : lo_rec, pass == 0 ? hi_pre : hi_rec);
       auto& dst = pass == 0 ? S->bwd_pre : S->bwd_rec;
       for (auto& v : b2)
         if (!v.empty()) dst.push_back(push_launch(S, v, PT_CLS_LOCAL));

@@ -60,6 +60,7 @@ inline double beyond(double pos, int n) { return std::max(0.0, std::max(-pos, po
 struct Layer {
   int own_start, n, top_ext, bot_ext, R, rowbase;
   int r0, r1, rn, rn1;  // local rows of the paper's j = 0, 1, n, n+1 (-1 if absent)
+  int mid;              // middle row of the two-ended elimination (floor(R / 2))
 };
 
 struct Launch {
