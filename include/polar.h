@@ -101,6 +101,12 @@ typedef struct {
                         low-rank form (Alg. 5 / Alg. 6); float64 only          */
   double plr_eps;    /* absolute singular-value threshold of a leaf, > 0        */
   int32_t plr_rmax;  /* leaf rank limit, 1..64 (0: ceil(sqrt(NX)))              */
+  int32_t use_graph; /* 1: each GMRES iteration's launches (preconditioner,
+                        operator, Arnoldi, Givens, convergence flags) are
+                        captured once per (nrhs, iteration) into a hipGraph and
+                        replayed on later solves; needs a non-null stream; not
+                        used while profiling or with the learned stage; pt_tune
+                        discards the graphs.  0: plain stream launches.      */
 } pt_options;
 
 typedef struct {
@@ -184,6 +190,16 @@ pt_status pt_trace_rhs(pt_solver* s, int32_t nrhs, const double* f, double* out,
  * forced local solve per layer with t = d + a (eq. PDE_version_green_formula). */
 pt_status pt_reconstruct(pt_solver* s, int32_t nrhs, const double* f, const double* x, double* u,
                          int32_t on_device);
+
+/* Gauss-Seidel on the polarized system as a stand-alone solver (Alg. 3):
+ * u^0 = 0, u^{i+1} = D^-1 (s - R u^i) (the sweeps of Section 4.1), stopping
+ * when every source's relative update ||u^{i+1} - u^i|| / ||u^{i+1}|| is below
+ * tol or after maxit iterations; then the volume field is reconstructed as in
+ * pt_solve.  iters (may be NULL): iterations taken; relupd (may be NULL, nrhs
+ * entries): each source's last relative update.  PT_ENOCONV if maxit was
+ * reached (u holds the last iterate's field).  PT_EINVAL for L = 1. */
+pt_status pt_gauss_seidel(pt_solver* s, int32_t nrhs, const double* f, double* u, int32_t on_device, double tol,
+                          int32_t maxit, int32_t* iters, double* relupd);
 
 /* Several independent problems at once (problems of uneven size and L):
  * problem i is solved by s[i] for nrhs[i] sources, f[i] -> u[i], info[i]

@@ -960,6 +960,45 @@ pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2*
   return PT_OK;
 }
 
+// Launch iteration j of a GMRES solve with nrhs sources from its captured
+// graph, capturing it on first use.  Capture failure switches the solver to
+// plain launches for good (the iteration is then run directly).
+template <typename F>
+pt_status run_graph(pt_solver* S, int nrhs, int j, double tol, F&& iteration) {
+  const auto key = std::make_pair(nrhs, j);
+  auto it = S->graphs.find(key);
+  if (it == S->graphs.end()) {
+    (void)tol;
+    if (hipStreamBeginCapture(S->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      S->graph_failed = true;
+      return iteration(j);
+    }
+    const pt_status rc = iteration(j);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(S->st, &g);
+    if (rc != PT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ec != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      S->graph_failed = true;
+      return iteration(j);
+    }
+    (void)hipGraphDestroy(g);
+    it = S->graphs.emplace(key, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, S->st));
+  return PT_OK;
+}
+
+void drop_graphs(pt_solver* S) {
+  for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second);
+  S->graphs.clear();
+}
+
 // Flexible GMRES (right preconditioning, classical Gram-Schmidt applied twice,
 // x0 = 0, no restart) on A x = s for nrhs independent right-hand sides.
 pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned) {
@@ -972,7 +1011,8 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learne
   HIPCHK(launch_kinit(S->g.p, S->beta.p, S->done.p, S->iters.p, S->est.p, m, nrhs, st));
   if (learned) PTCHK(learned_begin(S, nrhs));
   all_conv = false;
-  for (int j = 0; j < m; ++j) {
+  // the launch sequence of iteration j (captured into a graph when enabled)
+  auto iteration = [&](int j) -> pt_status {
     double2* vj = S->V.p + (size_t)j * vs;
     double2* zj = S->Z.p + (size_t)j * vs;
     const bool augment = learned && S->learned_mode == PT_LEARN_AUGMENT;
@@ -997,6 +1037,17 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learne
     HIPCHK(launch_givens(S->Hc.p, S->hacc.p, S->nrm.p, S->cs.p, S->sn.p, S->g.p, S->est.p, S->beta.p, S->iters.p,
                          S->done.p, tol, j, m, nrhs, st));
     HIPCHK(hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    return PT_OK;
+  };
+  // (the tolerance is a kernel argument baked into a graph: graphs only for the solver's own tol)
+  const bool graphs = S->opt.use_graph && !learned && !S->prof && st != nullptr && !S->graph_failed &&
+                      tol == S->opt.tol;
+  for (int j = 0; j < m; ++j) {
+    if (graphs) {
+      PTCHK(run_graph(S, nrhs, j, tol, iteration));
+    } else {
+      PTCHK(iteration(j));
+    }
     HIPCHK(hipStreamSynchronize(st));
     bool all = true;
     for (int r = 0; r < nrhs; ++r) all = all && S->h_done[r];
@@ -1058,6 +1109,7 @@ void pt_free(pt_solver* S) {
   S->plr.release();
   if (S->h_done) (void)hipHostFree(S->h_done);
   for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
+  drop_graphs(S);
   delete S;
 }
 
@@ -1077,6 +1129,63 @@ pt_status pt_profile(pt_solver* S, int32_t enable) {
     S->prof = false;
   }
   return PT_OK;
+}
+
+pt_status pt_gauss_seidel(pt_solver* S, int32_t nrhs, const double* f, double* u, int32_t on_device, double tol,
+                          int32_t maxit, int32_t* iters, double* relupd) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (!f || !u) return fail(PT_EINVAL, "null field");
+  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
+  if (maxit < 1 || !(tol >= 0)) return fail(PT_EINVAL, "maxit must be >= 1 and tol >= 0");
+  hipStream_t st = S->st;
+  const size_t nv = (size_t)nrhs * S->NZ * S->NX;
+  const int64_t n = (int64_t)nrhs * S->Nt;
+  const double2* fd = (const double2*)f;
+  double2* ud = (double2*)u;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->fio.p, f, nv * sizeof(double2), hipMemcpyHostToDevice, st));
+    fd = S->fio.p;
+    ud = S->uio.p;
+  }
+  PTCHK(trace_rhs(S, fd, S->s.p, nrhs));
+  // u^{i+1} = D^-1 (s - R u^i): one fused reflection launch (none for u^0 = 0) and the sweeps
+  double2* prev = S->zeros.p;
+  std::vector<double> num(nrhs), den(nrhs);
+  int it = 0;
+  double worst = 0.0;
+  bool conv = false;
+  for (it = 1; it <= maxit; ++it) {
+    double2* cur = (it % 2) ? S->U1.p : S->U2.p;
+    Bases b{{S->s.p, prev, cur, nullptr}};
+    if (it == 1) {
+      HIPCHK(launch_copy(cur, S->s.p, n, st));
+    } else {
+      PTCHK(run_apply(S, S->bterm, nrhs, S->Nt, b));
+    }
+    for (const Launch& Lc : S->sweep) PTCHK(run_apply(S, Lc, nrhs, S->Nt, b));
+    HIPCHK(launch_add(S->tmp.p, cur, prev, -1.0, n, st));
+    HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, S->Nt, st));
+    HIPCHK(launch_knorm(cur, S->beta.p, nrhs, S->Nt, st));
+    HIPCHK(hipMemcpyAsync(num.data(), S->nrm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(den.data(), S->beta.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      const double ru = den[r] > 0 ? num[r] / den[r] : (num[r] > 0 ? INFINITY : 0.0);
+      if (relupd) relupd[r] = ru;
+      worst = std::max(worst, std::isnan(ru) ? INFINITY : ru);
+    }
+    prev = cur;
+    if (worst < tol) {
+      conv = true;
+      break;
+    }
+  }
+  if (iters) *iters = std::min(it, maxit);
+  PTCHK(reconstruct(S, fd, prev, ud, nrhs));
+  if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return conv ? PT_OK : fail(PT_ENOCONV, "Gauss-Seidel reached maxit before tol");
 }
 
 pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
@@ -1141,6 +1250,8 @@ static pt_status time_launch(pt_solver* S, const Launch& Lc, int nrhs, int64_t l
 
 pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
   PTCHK(check_nrhs(S, nrhs));
+  HIPCHK(hipStreamSynchronize(S->st));
+  drop_graphs(S);  // captured launches carry the old shapes
   constexpr int kReps = 3;
   const int L = S->L;
   // work buffers as inputs and outputs of the trial launches (contents overwritten)

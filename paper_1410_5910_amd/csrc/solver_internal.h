@@ -151,6 +151,10 @@ struct pt_solver {
   std::vector<Launch> bwd_pre, bwd_rec;  // backward passes stopped at the trace rows / the owned rows
   Launch bterm, opA, opR;
 
+  // captured GMRES iterations: (nrhs, iteration) -> executable graph
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  bool graph_failed = false;  // capture did not work on this stream: plain launches
+
   // learned preconditioner stage (null: sweeps only)
   pt_learned* learned = nullptr;
   int learned_mode = PT_LEARN_CORRECT;

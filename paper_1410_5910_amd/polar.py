@@ -28,7 +28,7 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
-           "pt_profile_read_class", "pt_tune", "pt_solve_batch")
+           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel")
 CLASSES = ("local", "sweep", "reflect", "operator")
 
 
@@ -39,7 +39,8 @@ class PtProblem(C.Structure):
 
 class PtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gs_iters", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
-                ("max_nrhs", C.c_int32), ("plr", C.c_int32), ("plr_eps", C.c_double), ("plr_rmax", C.c_int32)]
+                ("max_nrhs", C.c_int32), ("plr", C.c_int32), ("plr_eps", C.c_double), ("plr_rmax", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class PtRhsInfo(C.Structure):
@@ -106,6 +107,7 @@ def lib():
         L.pt_profile_read.argtypes = [vp, C.POINTER(PtKernelStats)]
         L.pt_profile_read_class.argtypes = [vp, i32, C.POINTER(PtKernelStats)]
         L.pt_tune.argtypes = [vp, i32, C.POINTER(PtTuneEntry)]
+        L.pt_gauss_seidel.argtypes = [vp, i32, vp, vp, i32, C.c_double, i32, C.POINTER(i32), dp]
         L.pt_solve_batch.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), i32,
                                      C.POINTER(C.POINTER(PtRhsInfo))]
         fp = C.POINTER(C.c_float)
@@ -146,7 +148,7 @@ class Solver:
     """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
 
     def __init__(self, nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
-                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0):
+                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False):
         self._lib = lib()
         c = np.ascontiguousarray(c, dtype=np.float64)
         NX, NZ = nx + 2 * npml, nz + 2 * npml
@@ -157,7 +159,7 @@ class Solver:
                          c.ctypes.data_as(C.POINTER(C.c_double)))
         prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
         opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
-                        float(plr_eps), int(plr_rmax))
+                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0)
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
         self._h = h_
@@ -261,6 +263,18 @@ class Solver:
         infos = [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
                   "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in info]
         return (u[0] if single else u), infos
+
+    def gauss_seidel(self, f, tol=1e-10, maxit=500):
+        """Alg. 3 as a stand-alone solver: (u, iterations, last relative update per source, converged)."""
+        single = f.ndim == 2
+        p, dev, keep, n = self._prep(f, (self.NZ, self.NX))
+        u = self._out(keep, dev, (n, self.NZ, self.NX))
+        it = C.c_int32()
+        ru = np.zeros(n)
+        st = _check(self._lib.pt_gauss_seidel(self._h, n, p, self._ptr(u, dev), dev, float(tol), int(maxit),
+                                              C.byref(it), ru.ctypes.data_as(C.POINTER(C.c_double))),
+                    allow=(PT_ENOCONV,))
+        return (u[0] if single else u), it.value, ru, st == PT_OK
 
     def apply(self, op: int, x):
         """y = op(x) for polarized vectors x (nrhs, 2, L-1, 2, NX)."""

@@ -379,3 +379,52 @@ def test_solve_batch_uneven_problems():
         P.solve_batch([solvers[0], solvers[0]], [probs[0][1], probs[0][1]])
     for sv in solvers:
         sv.close()
+
+
+# ---------------------------------------------------------------- Gauss-Seidel as a solver (Alg. 3)
+def test_gauss_seidel_solver_matches_oracle_iteration(small):
+    prob, f, gs, ps = small
+    _flush("[gpu] gauss-seidel solver")
+    s = ps.rhs(ps.newton(f))
+    for k in (1, 2, 5):
+        u, it, ru, conv = gs.gauss_seidel(f, tol=0.0, maxit=k)  # exactly k iterations
+        assert it == k and not conv
+        x_ref, hist = ps.gauss_seidel(s, tol=0.0, maxit=k)
+        u_ref = ps.reconstruct(f, x_ref)
+        assert rel(u, u_ref) < 1e-10, k
+        assert abs(max(ru) - hist[-1]) <= 1e-8 * max(1.0, hist[-1])
+    u, it, ru, conv = gs.gauss_seidel(f, tol=1e-11, maxit=400)
+    assert conv and max(ru) < 1e-11
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+    _flush(f"[gpu]   Gauss-Seidel alone: {it} iterations to 1e-11")
+
+
+# ---------------------------------------------------------------- graph-captured iterations
+@pytest.mark.parametrize("precision", ["f64", "split-bf16"])
+def test_graph_replays_match_plain_launches(precision):
+    import torch
+    prob, f = synth.config_small(nx=40, nz=48, npml=6, L=4, nrhs=24, seed=81)
+    _flush(f"[gpu] graphs {precision}")
+    st = torch.cuda.Stream()
+    g = P.Solver.from_problem(prob, precision=precision, max_nrhs=24, tol=1e-11, maxit=60,
+                              stream=st.cuda_stream, use_graph=True)
+    p = P.Solver.from_problem(prob, precision=precision, max_nrhs=24, tol=1e-11, maxit=60)
+    ud = DirectSolver(prob).solve(f)
+    fd = torch.from_numpy(f).to("cuda:0")
+    torch.cuda.synchronize()
+    for rep, k in enumerate([24, 24, 5, 24, 5, 1]):  # capture on first use of each nrhs, then replays
+        ref, _ = p.solve(f[:k])
+        junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda:0").sum()  # eager work in between
+        torch.cuda.synchronize()
+        u, info = g.solve(fd[:k] if rep % 2 else f[:k])
+        torch.cuda.synchronize()
+        u = u.cpu().numpy() if hasattr(u, "cpu") else u
+        assert rel(u, ref) < 1e-14, (rep, k, rel(u, ref))
+        assert max(rel(u[r], ud[r]) for r in range(k)) < 1e-8
+        assert all(i["converged"] for i in info)
+        del junk
+    g.tune(24)  # drops the graphs; the next solve captures again with the tuned shapes
+    u, _ = g.solve(f)
+    assert max(rel(u[r], ud[r]) for r in range(24)) < 1e-8
+    g.close()
+    p.close()
