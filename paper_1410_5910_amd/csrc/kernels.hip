@@ -364,7 +364,7 @@ constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 
 template <int TN, int KS>
-__global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+__global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
                                                                  int nrt, int nrhs, int64_t ld, Bases bases) {
   constexpr int NB = TN / 16;           // MFMA tiles per wave
   constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread of a group
@@ -393,11 +393,16 @@ __global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __res
   const int brhs = col0 + bq;
   const bool brhs_ok = brhs < nrhs;
 
-  d4v cr[NB], ci[NB];
+  // Three real products per complex one (Gauss): p1 = Re A Re B, p2 = Im A Im B,
+  // p3 = (Re A + Im A)(Re B + Im B); then Re = p1 - p2, Im = p3 - p1 - p2.
+  // A quarter fewer MFMAs than the four-product form; the error stays within a
+  // small multiple of the unit roundoff times |A||B| (normwise).
+  d4v p1[NB], p2[NB], p3[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    cr[b] = d4v{0.0, 0.0, 0.0, 0.0};
-    ci[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    p1[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    p2[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    p3[b] = d4v{0.0, 0.0, 0.0, 0.0};
   }
   const int wr = wave * 16;
 
@@ -463,17 +468,17 @@ __global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __res
 #pragma unroll
     for (int kk = 0; kk < kMmK; kk += 4) {
       const double2 av = As[grp][kk + (lane >> 4)][wr + (lane & 15)];
+      const double as = av.x + av.y;
       double2 bv[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) bv[b] = Bs[grp][kk + (lane >> 4)][b * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) cr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, cr[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b) p1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, p1[b], 0, 0, 0);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) ci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].y, ci[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b) p2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[b].y, p2[b], 0, 0, 0);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) cr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv[b].y, cr[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) ci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[b].x, ci[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b)
+        p3[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bv[b].x + bv[b].y, p3[b], 0, 0, 0);
     }
   };
   Stage s0;
@@ -484,6 +489,12 @@ __global__ __launch_bounds__(256 * KS) void block_mfma64_kernel(const Job* __res
     fetch(s0, (i + 1) * KS + grp);  // next chunk in flight during the MFMAs
     multiply();
     __syncthreads();
+  }
+  d4v cr[NB], ci[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    cr[b] = p1[b] - p2[b];
+    ci[b] = p3[b] - p1[b] - p2[b];
   }
 
   if constexpr (KS > 1) {

@@ -98,7 +98,11 @@ pt_status prof_harvest(pt_solver* S) {
 const TuneCfg* tuned(const pt_solver* S, const Launch& Lc, int nrhs) {
   const auto& m = S->tune[Lc.cls];
   const auto it = m.find(nrhs);
-  return it == m.end() ? nullptr : &it->second;
+  if (it == m.end()) return nullptr;
+  // a launch with far fewer jobs than the timed one (the tail rows of the
+  // longest layers) fills few CUs: the rules' k-split serves it better
+  if (4 * Lc.njobs < it->second.njobs) return nullptr;
+  return &it->second;
 }
 
 pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc) {
@@ -1323,6 +1327,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       }
       if (best) {
         S->tune[cls][nrhs] = *best;
+        S->tune[cls][nrhs].njobs = Lc->njobs;
         e.tile_rhs = best->tn ? best->tn : best->sp.tile_rhs;
         e.ksplit = best->tn ? best->ks : best->sp.kslices;
       } else {

@@ -82,6 +82,7 @@ struct ProfPending {
 struct TuneCfg {
   int tn = 0, ks = 0;         // float64 MFMA tile width and wave groups
   SplitCfg sp{0, 0};          // split-bfloat16 tile width and k-slices
+  int njobs = 0;              // jobs of the launch the shape was timed on
 };
 
 // block types per layer; each is a 2x2 arrangement of NX x NX blocks

@@ -97,13 +97,19 @@ def test_split_bumps440_single_source():
 
 
 def test_split_layered_batch_matches_f64():
-    # the bench workload's medium and launch shapes (all 128 sources), checked against the float64 GPU path
+    # the bench workload's medium and launch configuration (all 128 sources in one call, tuned tile shapes,
+    # device-resident input, tol 1e-10, maxit 60): every source against the float64 GPU path, and every
+    # eighth source against the direct solve of the oracle
+    torch = pytest.importorskip("torch")
     prob, f = synth.config3()
-    _flush("[gpu] split layered-1240x440-L16, 128 sources")
-    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=40)
-    u, info = gs.solve(f)
+    _flush("[gpu] split layered-1240x440-L16, 128 sources, tuned")
+    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=60)
+    gs.tune(128)
+    ud_dev, info = gs.solve(torch.from_numpy(f).to("cuda:0"))
+    u = ud_dev.cpu().numpy()
     gs.close()
-    g64 = P.Solver.from_problem(prob, max_nrhs=128, tol=1e-10, maxit=40)
+    g64 = P.Solver.from_problem(prob, max_nrhs=128, tol=1e-10, maxit=60)
+    g64.tune(128)
     u64, info64 = g64.solve(f)
     g64.close()
     errs = [rel(u[r], u64[r]) for r in range(128)]
@@ -114,3 +120,9 @@ def test_split_layered_batch_matches_f64():
     assert max(errs) < 1e-8
     assert all(i["converged"] for i in info)
     assert max(its) <= max(its64) + 1
+    pick = list(range(0, 128, 8)) + [127]
+    ud = DirectSolver(prob).solve(f[pick])
+    derr = [rel(u[r], ud[k]) for k, r in enumerate(pick)]
+    derr64 = [rel(u64[r], ud[k]) for k, r in enumerate(pick)]
+    _flush(f"[gpu] layered vs direct: mixed {max(derr):.2e}, float64 {max(derr64):.2e}")
+    assert max(derr) < 1e-8 and max(derr64) < 1e-8
