@@ -72,19 +72,18 @@ struct MatT<true> {
 // block_apply, few right-hand sides (NR <= 4): the HBM-streaming form
 // ----------------------------------------------------------------------------
 // Blocks are stored row-major, so every output row is a contiguous stream.
-// One workgroup = kGvWaves waves = kGvWaves output rows (one per wave) over
-// the job's full column range; lane l of a wave reads columns l, l+64, ...
-// of its row, i.e. one contiguous 1 KiB segment per load instruction for
-// float64.  Terms and column chunks are walked in a workgroup-uniform loop so
-// every block pointer sits in scalar registers and the matrix loads of a lane
-// are independent (kGvU in flight).  The row's partial sums are reduced by a
-// fixed butterfly of cross-lane shuffles, so no cross-workgroup reduction,
-// atomic or fence is needed and results are deterministic.  The first group
-// of matrix loads of every chunk is issued before its input slice is staged
-// in LDS, so its latency overlaps the staging.
+// One workgroup = kGvWaves waves = kGvWaves output rows (one per wave); lane l
+// of a wave reads columns l, l+64, ... of its row, one contiguous 1 KiB
+// segment per load instruction for float64.  The job's (term, column chunk)
+// steps are walked in a workgroup-uniform loop, software-pipelined: the matrix
+// loads and the input loads of step q+1 are in flight while step q is
+// multiplied, and the inputs go through a double-buffered LDS slice.  The
+// whole job record is fetched with loads issued back to back before any of
+// it is used, so a launch pays one scalar round trip, not one per field.  The
+// row's partial sums are reduced by a fixed butterfly of cross-lane shuffles:
+// no atomics or fences, deterministic results.
 constexpr int kGvWaves = 8;                 // rows per workgroup
 constexpr int kGvThreads = kGvWaves * 64;
-constexpr int kGvU = 8;                     // loads in flight per lane and group (NR <= 4)
 
 // global-memory views of float64 data: loads through them compile to global_load
 // (not flat_load) and may be scheduled across LDS stores
@@ -110,94 +109,137 @@ __device__ __forceinline__ double2* base_of(const Bases& b, int buf) {
   return buf == 0 ? b.b[0] : buf == 1 ? b.b[1] : buf == 2 ? b.b[2] : buf == 3 ? b.b[3] : nullptr;
 }
 
-template <int NR, bool F32>
+// columns per step of the streaming form: one load per lane and in-flight slot
+template <int NR>
+constexpr int gemv_u() { return NR >= 4 ? 4 : 8; }
+
+// PIPE: the launch has jobs of more than one step (several terms or column
+// chunks); without it every job is one step and one register set suffices.
+template <int NR, bool F32, bool PIPE>
 __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __restrict__ jobs, int n, int ntiles,
                                                                 int kc, int nrhs, int64_t ld, Bases bases) {
   using MV = typename MatT<F32>::vec;
   using T = typename MatT<F32>::real;
-  constexpr int U = NR >= 8 ? kGvU / 2 : kGvU;  // matrix loads in flight per lane (registers bound it)
+  constexpr int U = gemv_u<NR>();  // kc <= 64 U: every lane has at most U columns of a step
   extern __shared__ unsigned char smem_raw[];
-  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // kc * NR
+  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // 2 buffers of kc * NR
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tile = blockIdx.x % ntiles;
-  const Job& J = jobs[blockIdx.x / ntiles];  // read with workgroup-uniform indices only
+  // every field of the job, read into scalars up front (independent loads, one round trip)
+  const Job* __restrict__ Jp = jobs + blockIdx.x / ntiles;
+  const int nterms = Jp->nterms;
+  const void* const M0 = Jp->M[0];
+  const void* const M1 = Jp->M[1];
+  const void* const M2 = Jp->M[2];
+  const void* const M3 = Jp->M[3];
+  const VecRef Q0 = Jp->Q[0], Q1 = Jp->Q[1], Q2 = Jp->Q[2], Q3 = Jp->Q[3];
+  const VecRef S0 = Jp->S[0], S1 = Jp->S[1], S2 = Jp->S[2], S3 = Jp->S[3];
+  const double2 B0 = Jp->beta[0], B1 = Jp->beta[1], B2 = Jp->beta[2], B3 = Jp->beta[3];
+  const VecRef Pr = Jp->P, Yr = Jp->Y;
+  const double2 alpha = Jp->alpha;
   const int r0 = blockIdx.y * NR;
   const int row = tile * kGvWaves + wave;
   const int rowc = row < n ? row : n - 1;
+  const int nck = (n + kc - 1) / kc;
+  const int nq = nterms * nck;
+
+  // fields of term t (workgroup-uniform selects)
+  auto sel_m = [&](int t) { return t == 0 ? M0 : t == 1 ? M1 : t == 2 ? M2 : M3; };
+  auto sel_q = [&](int t) { return t == 0 ? Q0 : t == 1 ? Q1 : t == 2 ? Q2 : Q3; };
+  auto sel_s = [&](int t) { return t == 0 ? S0 : t == 1 ? S1 : t == 2 ? S2 : S3; };
+  auto sel_b = [&](int t) { return t == 0 ? B0 : t == 1 ? B1 : t == 2 ? B2 : B3; };
 
   Cx<T> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
 
-  bool first_chunk = true;
-#pragma unroll 1
-  for (int t = 0; t < 4; ++t) {
-    if (t >= J.nterms) break;
-    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
-    const VecRef qr = J.Q[t];
-    const VecRef sr = J.S[t];
-    const gd2* __restrict__ qg = qr.buf >= 0 ? to_gd2(base_of(bases, qr.buf) + qr.off) : nullptr;
-    const gd2* __restrict__ sg = sr.buf >= 0 ? to_gd2(base_of(bases, sr.buf) + sr.off) : nullptr;
-    const double2 be = J.beta[t];
-#pragma unroll 1
-    for (int c0 = 0; c0 < n; c0 += kc) {
-      const int kw = min(kc, n - c0);
-      const int cnt = lane < kw ? (kw - lane + 63) / 64 : 0;  // columns c0 + lane + 64 i of this row
-      // first group of matrix loads goes out before the inputs are staged
-      MV m[U];
+  // raw loads of one step: U matrix entries of this lane's row, one input column per thread
+  struct Step {
+    MV m[U];
+    d2v vq[NR], vs[NR];
+    double2 be;
+    int kw;
+    bool has_q, has_s;
+  };
+  auto fetch = [&](Step& F, int q) {
+    const int t = q / nck;
+    const int c0 = (q - t * nck) * kc;
+    F.kw = min(kc, n - c0);
+    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(sel_m(t)) + (size_t)rowc * n + c0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) m[u] = u < cnt ? Mrow[c0 + lane + 64 * u] : MV{};
-      if (!first_chunk) __syncthreads();  // previous chunk fully consumed
-      first_chunk = false;
-      // input staging: every load of a column issued before any is combined
-      // (global-address-space views, so they need not wait for the LDS stores)
-      for (int c = tid; c < kw; c += kGvThreads) {
-        const int cj = c0 + c;
-        d2v vq[NR], vs[NR];
+    for (int u = 0; u < U; ++u) {
+      const int c = lane + 64 * u;
+      F.m[u] = c < F.kw ? Mrow[c] : MV{};
+    }
+    const VecRef qr = sel_q(t), sr = sel_s(t);
+    F.has_q = qr.buf >= 0;
+    F.has_s = sr.buf >= 0;
+    F.be = sel_b(t);
+    const int cj = c0 + min(tid, F.kw - 1);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const int64_t e = (int64_t)min(r0 + r, nrhs - 1) * ld + cj;
-          vq[r] = qg ? qg[e] : d2v{0.0, 0.0};
-          vs[r] = sg ? sg[e] : d2v{0.0, 0.0};
-        }
+    for (int r = 0; r < NR; ++r) {
+      const int64_t e = (int64_t)min(r0 + r, nrhs - 1) * ld + cj;
+      F.vq[r] = F.has_q ? to_gd2(base_of(bases, qr.buf) + qr.off)[e] : d2v{0.0, 0.0};
+      F.vs[r] = F.has_s ? to_gd2(base_of(bases, sr.buf) + sr.off)[e] : d2v{0.0, 0.0};
+    }
+  };
+  // input column tid of a step: X = Q + beta S into LDS buffer b
+  auto stage = [&](const Step& F, int b) {
+    if (tid < F.kw) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          double2 v = make_double2(vq[r].x, vq[r].y);
-          if (sg) v = cadd(v, cmul(be, make_double2(vs[r].x, vs[r].y)));
-          if (r0 + r >= nrhs) v = make_double2(0.0, 0.0);
-          xs[(size_t)c * NR + r] = Cx<T>{(T)v.x, (T)v.y};
-        }
-      }
-      __syncthreads();
-      for (int i0 = 0; i0 < cnt; i0 += U) {
-        MV nx[U];
-        const bool more = i0 + U < cnt;
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int i = i0 + U + u;
-            nx[u] = i < cnt ? Mrow[c0 + lane + 64 * i] : MV{};
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u;
-          if (i < cnt) {
-            const Cx<T> mm{(T)m[u].x, (T)m[u].y};
-            const Cx<T>* xp = xs + (size_t)(lane + 64 * i) * NR;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[r]);
-          }
-        }
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) m[u] = nx[u];
-        }
+      for (int r = 0; r < NR; ++r) {
+        double2 v = make_double2(F.vq[r].x, F.vq[r].y);
+        if (F.has_s) v = cadd(v, cmul(F.be, make_double2(F.vs[r].x, F.vs[r].y)));
+        if (r0 + r >= nrhs) v = make_double2(0.0, 0.0);
+        xs[((size_t)b * kc + tid) * NR + r] = Cx<T>{(T)v.x, (T)v.y};
       }
     }
+  };
+  auto multiply = [&](const Step& F, int b) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = lane + 64 * u;
+      if (c < F.kw) {
+        const Cx<T> mm{(T)F.m[u].x, (T)F.m[u].y};
+        const Cx<T>* xp = xs + ((size_t)b * kc + c) * NR;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[r]);
+      }
+    }
+  };
+
+  if constexpr (!PIPE) {
+    if (nq > 0) {
+      Step f0;
+      fetch(f0, 0);
+      stage(f0, 0);
+      __syncthreads();
+      multiply(f0, 0);
+    }
+  } else {
+  Step f0, f1;
+  if (nq > 0) {
+    fetch(f0, 0);
+    stage(f0, 0);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int q = 0; q < nq; q += 2) {
+    // step q from f0 / buffer 0 while step q+1 is fetched into f1
+    if (q + 1 < nq) fetch(f1, q + 1);
+    multiply(f0, 0);
+    if (q + 1 < nq) stage(f1, 1);
+    __syncthreads();
+    if (q + 1 >= nq) break;
+    // step q+1 from f1 / buffer 1 while step q+2 is fetched into f0
+    if (q + 2 < nq) fetch(f0, q + 2);
+    multiply(f1, 1);
+    if (q + 2 < nq) stage(f0, 0);
+    __syncthreads();
+  }
   }
 
   // reduce the row over the 64 lanes (fixed butterfly), lanes 0..NR-1 write
@@ -215,9 +257,9 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
     for (int r = 1; r < NR; ++r)
       if (lane == r) a = acc[r];
     const int r = lane;
-    double2 y = cmul(J.alpha, make_double2((double)a.x, (double)a.y));
-    if (J.P.buf >= 0) y = cadd(y, base_of(bases, J.P.buf)[J.P.off + (int64_t)(r0 + r) * ld + row]);
-    base_of(bases, J.Y.buf)[J.Y.off + (int64_t)(r0 + r) * ld + row] = y;
+    double2 y = cmul(alpha, make_double2((double)a.x, (double)a.y));
+    if (Pr.buf >= 0) y = cadd(y, base_of(bases, Pr.buf)[Pr.off + (int64_t)(r0 + r) * ld + row]);
+    base_of(bases, Yr.buf)[Yr.off + (int64_t)(r0 + r) * ld + row] = y;
   }
 }
 
@@ -549,9 +591,13 @@ hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int n
   using T = typename MatT<F32>::real;
   dim3 grid((unsigned)njobs * g.ntiles, (unsigned)((nrhs + NR - 1) / NR));
   if (NR <= 4) {
-    const size_t lds = (size_t)g.kc * NR * sizeof(Cx<T>);
-    hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1, 0,
-                          jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
+    const size_t lds = 2 * (size_t)g.kc * NR * sizeof(Cx<T>);
+    if (g.steps == 1)  // every job one step (0: not known, the general form)
+      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, false>), grid, dim3(kGvThreads), (uint32_t)lds / 2, st, ev0,
+                            ev1, 0, jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
+    else
+      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
+                            0, jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
   } else if (!F32 && g.mfma) {
     const int ntl = (g.n + kMmRows - 1) / kMmRows;
     const int tn = g.mfma;  // right-hand sides per workgroup tile: 16, 32 or 64

@@ -46,6 +46,7 @@ struct ApplyGeom {
                 // right-hand sides per workgroup tile (16, 32 or 64); 0: not used
   int gemv;     // 1: the row-streaming kernel (nr <= 4 right-hand sides per pass)
   int ks;       // float64 MFMA: wave groups splitting a tile's chunks (0: rule)
+  int steps;    // streaming form: most (term, column chunk) steps of a job in the launch
 };
 
 // Shape override of a split-bfloat16 launch (0: rule).

@@ -41,7 +41,8 @@ ApplyGeom geom_for(int n, int maxterms, int nrhs, int njobs = 1) {
   g.gemv = nrhs <= 4 ? 1 : 0;
   if (g.gemv) {
     g.ntiles = (n + 7) / 8;
-    g.kc = std::min(n, 2048 / g.nr);  // LDS = kc * nr complex doubles <= 32 KiB
+    g.kc = std::min(n, g.nr >= 4 ? 256 : 512);  // <= 64 columns per in-flight load slot; LDS 2 kc nr complex
+    g.steps = std::max(1, maxterms) * ((n + g.kc - 1) / g.kc);
   } else {
     g.ntiles = (n + 63) / 64;
     g.kc = std::min(n, 2048 / g.nr);  // LDS = max(kc, 128) * nr complex doubles <= 32 KiB
