@@ -346,6 +346,60 @@ pt_status run_local(pt_solver* S, const std::vector<Launch>& fw, const std::vect
   return PT_OK;
 }
 
+// Record where each layer's jobs start in a local-solve launch (its jobs are
+// built layer by layer, each job's output row names its layer).
+void index_layers(pt_solver* S, Launch& Lc) {
+  const int L = S->L;
+  Lc.lay_off.assign(L + 1, 0);
+  int prev = 0;
+  for (int i = 0; i < Lc.njobs; ++i) {
+    const int64_t row = S->hjobs[Lc.job0 + i].Y.off / S->NX;
+    int l = 0;
+    while (l + 1 < L && row >= S->lay[l + 1].rowbase) ++l;
+    if (l < prev) {  // not in layer order: no sub-ranges for this launch
+      Lc.lay_off.clear();
+      return;
+    }
+    prev = l;
+    ++Lc.lay_off[l + 1];
+  }
+  for (int l = 0; l < L; ++l) Lc.lay_off[l + 1] += Lc.lay_off[l];
+}
+
+// The part of a local-solve launch on layers la..lb (njobs 0: nothing to do).
+Launch layer_range(const pt_solver* S, const Launch& Lc, int la, int lb) {
+  if (Lc.lay_off.empty() || (la == 0 && lb == S->L - 1)) return Lc;
+  Launch sub = Lc;
+  sub.job0 = Lc.job0 + Lc.lay_off[la];
+  sub.njobs = Lc.lay_off[lb + 1] - Lc.lay_off[la];
+  sub.lay_off.clear();
+  sub.maxterms = 0;
+  sub.mat_elems = 0;
+  sub.vec_elems_rhs = 0;
+  const double n = S->NX;
+  for (int i = 0; i < sub.njobs; ++i) {
+    const Job& j = S->hjobs[sub.job0 + i];
+    sub.maxterms = std::max(sub.maxterms, j.nterms);
+    sub.mat_elems += j.nterms * n * n;
+    double v = (j.P.buf >= 0 ? n : 0) + n;
+    for (int t = 0; t < j.nterms; ++t) v += (j.Q[t].buf >= 0 ? n : 0) + (j.S[t].buf >= 0 ? n : 0);
+    sub.vec_elems_rhs += v;
+  }
+  return sub;
+}
+
+// run_local restricted to the contiguous layers la..lb
+pt_status run_local_layers(pt_solver* S, const std::vector<Launch>& fw, const std::vector<Launch>& bw, int la, int lb,
+                           int nrhs, int64_t ld, double2* Wsol, double2* Brhs) {
+  Bases b{{Wsol, Brhs, nullptr, nullptr}};
+  for (const auto* list : {&fw, &bw})
+    for (const Launch& Lc : *list) {
+      const Launch sub = layer_range(S, Lc, la, lb);
+      if (sub.njobs > 0) PTCHK(run_apply(S, sub, nrhs, ld, b));
+    }
+  return PT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
@@ -660,7 +714,10 @@ void build_online_jobs(pt_solver* S) {
     build_local_jobs(S, ls, rb, fw, bw);
     S->fwd.clear();
     S->bwd.clear();
-    for (auto& v : fw) S->fwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
+    for (auto& v : fw) {
+      S->fwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
+      index_layers(S, S->fwd.back());
+    }
     for (auto& v : bw) S->bwd.push_back(push_launch(S, v, PT_CLS_LOCAL));
     // backward passes that stop at the rows their caller reads: the trace
     // rows 0, 1, n, n+1 (pre-solve) and the owned rows (reconstruction)
@@ -685,7 +742,10 @@ void build_online_jobs(pt_solver* S) {
       build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? lo_pre : lo_rec, pass == 0 ? hi_pre : hi_rec);
       auto& dst = pass == 0 ? S->bwd_pre : S->bwd_rec;
       for (auto& v : b2)
-        if (!v.empty()) dst.push_back(push_launch(S, v, PT_CLS_LOCAL));
+        if (!v.empty()) {
+          dst.push_back(push_launch(S, v, PT_CLS_LOCAL));
+          index_layers(S, dst.back());
+        }
     }
   }
   if (L < 2) return;
@@ -927,7 +987,14 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
     }
   }
   const int m = *std::max_element(cnt.begin(), cnt.end());
-  if (m >= nrhs) {  // every layer sees every source: the dense pre-solve
+  // the contiguous layer range holding every touched layer: local solves run there only
+  int la = L, lb = -1;
+  for (int l = 0; l < L; ++l)
+    if (cnt[l] > 0) {
+      la = std::min(la, l);
+      lb = std::max(lb, l);
+    }
+  if (m >= nrhs && la == 0 && lb == L - 1) {  // every layer sees every source: the dense pre-solve
     S->last_slots = nrhs;
     PTCHK(newton(S, f, nrhs));
     HIPCHK(launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX,
@@ -947,7 +1014,7 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   const int64_t ld = (int64_t)S->sumR * S->NX;
   HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
                               S->h * S->h, st));
-  PTCHK(run_local(S, S->fwd, S->bwd_pre, m, ld, S->W.p, S->Bw.p));
+  PTCHK(run_local_layers(S, S->fwd, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
   HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
                              S->sumR, S->NX, S->Nt, nrhs, st));
   // the pinned slot tables are rewritten by the next call: finish their uploads first

@@ -70,6 +70,7 @@ struct Launch {
   bool split = false;        // job terms point at split-bfloat16 planes
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
+  std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
 };
 
 struct ProfPending {
