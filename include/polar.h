@@ -107,6 +107,19 @@ typedef struct {
                         replayed on later solves; needs a non-null stream; not
                         used while profiling or with the learned stage; pt_tune
                         discards the graphs.  0: plain stream launches.      */
+  int32_t presolve;  /* how the pre-solve (Alg. 2, N^l f^l at the trace rows) is
+                        formed.  0: forward and backward line-by-line local
+                        solves over the layers a source touches.  1: products
+                        with the layers' interface Green's functions: the rows
+                        j = 0, 1, n, n+1 of (A^l)^-1 over every owned row, kept on
+                        the device after setup (Def. 3 with the source restricted
+                        to the layer), one launch instead of ~R dependent ones;
+                        float64 factors only; PT_ENOMEM if they do not fit.
+                        2: kept when they take at most a third of the free
+                        device memory at setup (and float64 factors), and used
+                        for pre-solves of at most 4 columns (sources, or the
+                        per-layer source slots of sparse sources); wider ones
+                        take the local solves.                                 */
 } pt_options;
 
 typedef struct {
@@ -130,6 +143,8 @@ typedef struct {
   int64_t factor_bytes; /* device bytes of the local factors                      */
   int64_t dense_block_bytes; /* device bytes the dense trace blocks take          */
   int64_t plr_leaves;   /* leaves of all compressed blocks (0 without PLR)         */
+  int64_t green_bytes;  /* device bytes of the interface Green's functions of the
+                           pre-solve (0: line-by-line pre-solve)                 */
 } pt_layout;
 
 typedef struct pt_solver pt_solver;

@@ -140,13 +140,21 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
   const double2 B0 = Jp->beta[0], B1 = Jp->beta[1], B2 = Jp->beta[2], B3 = Jp->beta[3];
   const VecRef Pr = Jp->P, Yr = Jp->Y;
   const double2 alpha = Jp->alpha;
+  const int K0 = Jp->kw[0] > 0 ? Jp->kw[0] : n, K1 = Jp->kw[1] > 0 ? Jp->kw[1] : n;
+  const int K2 = Jp->kw[2] > 0 ? Jp->kw[2] : n, K3 = Jp->kw[3] > 0 ? Jp->kw[3] : n;
+  const int L0 = Jp->ldm[0] > 0 ? Jp->ldm[0] : K0, L1 = Jp->ldm[1] > 0 ? Jp->ldm[1] : K1;
+  const int L2 = Jp->ldm[2] > 0 ? Jp->ldm[2] : K2, L3 = Jp->ldm[3] > 0 ? Jp->ldm[3] : K3;
   const int r0 = blockIdx.y * NR;
   const int row = tile * kGvWaves + wave;
   const int rowc = row < n ? row : n - 1;
-  const int nck = (n + kc - 1) / kc;
-  const int nq = nterms * nck;
+  // steps (term, column chunk of kc): chunks per term, cumulative
+  const int C0 = nterms > 0 ? (K0 + kc - 1) / kc : 0, C1 = nterms > 1 ? (K1 + kc - 1) / kc : 0;
+  const int C2 = nterms > 2 ? (K2 + kc - 1) / kc : 0, C3 = nterms > 3 ? (K3 + kc - 1) / kc : 0;
+  const int nq = C0 + C1 + C2 + C3;
 
   // fields of term t (workgroup-uniform selects)
+  auto sel_k = [&](int t) { return t == 0 ? K0 : t == 1 ? K1 : t == 2 ? K2 : K3; };
+  auto sel_l = [&](int t) { return t == 0 ? L0 : t == 1 ? L1 : t == 2 ? L2 : L3; };
   auto sel_m = [&](int t) { return t == 0 ? M0 : t == 1 ? M1 : t == 2 ? M2 : M3; };
   auto sel_q = [&](int t) { return t == 0 ? Q0 : t == 1 ? Q1 : t == 2 ? Q2 : Q3; };
   auto sel_s = [&](int t) { return t == 0 ? S0 : t == 1 ? S1 : t == 2 ? S2 : S3; };
@@ -165,10 +173,22 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
     bool has_q, has_s;
   };
   auto fetch = [&](Step& F, int q) {
-    const int t = q / nck;
-    const int c0 = (q - t * nck) * kc;
-    F.kw = min(kc, n - c0);
-    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(sel_m(t)) + (size_t)rowc * n + c0;
+    int t = 0;
+    if (q >= C0) {
+      q -= C0;
+      t = 1;
+      if (q >= C1) {
+        q -= C1;
+        t = 2;
+        if (q >= C2) {
+          q -= C2;
+          t = 3;
+        }
+      }
+    }
+    const int c0 = q * kc;
+    F.kw = min(kc, sel_k(t) - c0);
+    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(sel_m(t)) + (size_t)rowc * sel_l(t) + c0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = lane + 64 * u;
@@ -448,8 +468,15 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   }
   const int wr = wave * 16;
 
-  const int nchunk_t = (n + kMmK - 1) / kMmK;
-  const int nchunks = J.nterms * nchunk_t;
+  // columns and row stride of each term (wide terms: kw > 0), chunks of kMmK per term
+  int kt[4], lt[4], nct[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    kt[t] = J.kw[t] > 0 ? J.kw[t] : n;
+    lt[t] = J.ldm[t] > 0 ? J.ldm[t] : kt[t];
+    nct[t] = t < J.nterms ? (kt[t] + kMmK - 1) / kMmK : 0;
+  }
+  const int nchunks = nct[0] + nct[1] + nct[2] + nct[3];
   const int rounds = (nchunks + KS - 1) / KS;  // the same for every group: barriers stay uniform
   // Raw loads of a chunk, all unconditional (indices clamped into the block and
   // vectors): masking and the combination Q + beta S wait until the chunk is
@@ -457,19 +484,34 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   struct Stage {
     double2 pa[4], pq[BPT], ps[BPT];
     double2 be;
-    int c0;
+    int c0, kc;
     bool live, has_q, has_s;
   };
   auto fetch = [&](Stage& S, int q) {
     S.live = q < nchunks;
     if (!S.live) return;
-    const int t = q / nchunk_t;
-    S.c0 = (q - t * nchunk_t) * kMmK;
+    int t = 0;
+    if (q >= nct[0]) {
+      q -= nct[0];
+      t = 1;
+      if (q >= nct[1]) {
+        q -= nct[1];
+        t = 2;
+        if (q >= nct[2]) {
+          q -= nct[2];
+          t = 3;
+        }
+      }
+    }
+    S.c0 = q * kMmK;
+    const int K = t == 0 ? kt[0] : t == 1 ? kt[1] : t == 2 ? kt[2] : kt[3];
+    const int ldm = t == 0 ? lt[0] : t == 1 ? lt[1] : t == 2 ? lt[2] : lt[3];
+    S.kc = K;
     const gd2* __restrict__ M =
-        reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * n;
+        reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * ldm;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const d2v a = M[min(S.c0 + sc + u, n - 1)];
+      const d2v a = M[min(S.c0 + sc + u, K - 1)];
       S.pa[u] = make_double2(a.x, a.y);
     }
     const VecRef qr = J.Q[t];
@@ -482,7 +524,7 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
       const gd2* __restrict__ qp = to_gd2(base_of(bases, qr.buf) + qr.off + cb);
 #pragma unroll
       for (int u = 0; u < BPT; ++u) {
-        const d2v v = qp[min(S.c0 + bc + u, n - 1)];
+        const d2v v = qp[min(S.c0 + bc + u, K - 1)];
         S.pq[u] = make_double2(v.x, v.y);
       }
     }
@@ -490,7 +532,7 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
       const gd2* __restrict__ sp = to_gd2(base_of(bases, svr.buf) + svr.off + cb);
 #pragma unroll
       for (int u = 0; u < BPT; ++u) {
-        const d2v v = sp[min(S.c0 + bc + u, n - 1)];
+        const d2v v = sp[min(S.c0 + bc + u, K - 1)];
         S.ps[u] = make_double2(v.x, v.y);
       }
     }
@@ -498,12 +540,12 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   auto stage = [&](const Stage& S) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      As[grp][sc + u][sr] = (S.live && arow_ok && S.c0 + sc + u < n) ? S.pa[u] : make_double2(0.0, 0.0);
+      As[grp][sc + u][sr] = (S.live && arow_ok && S.c0 + sc + u < S.kc) ? S.pa[u] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
       double2 v = S.has_q ? S.pq[u] : make_double2(0.0, 0.0);
       if (S.has_s) v = cadd(v, cmul(S.be, S.ps[u]));
-      Bs[grp][bc + u][bq] = (S.live && brhs_ok && S.c0 + bc + u < n) ? v : make_double2(0.0, 0.0);
+      Bs[grp][bc + u][bq] = (S.live && brhs_ok && S.c0 + bc + u < S.kc) ? v : make_double2(0.0, 0.0);
     }
   };
   auto multiply = [&]() {
@@ -582,6 +624,22 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
         Yb[(int64_t)rhs * ld + row] = y;
       }
     }
+}
+
+// G[x'][e] for e = (r - r0) NX + x: row x' of the trace-row block j of the
+// inverse, from column q NX + x' of the extraction solve, rescaled (see
+// launch_pack_green).  grid.x covers nrows NX entries, grid.y = x'.
+__global__ __launch_bounds__(256) void pack_green_kernel(const double2* __restrict__ W, int64_t ld, int q, int j,
+                                                         int r0, int nrows, int NX, const double2* __restrict__ ax,
+                                                         const double2* __restrict__ az, double2* __restrict__ G) {
+  const int xp = blockIdx.y;
+  const int64_t cnt = (int64_t)nrows * NX;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= cnt) return;
+  const int r = r0 + (int)(e / NX), x = (int)(e % NX);
+  const double2 w = W[((int64_t)q * NX + xp) * ld + (int64_t)r * NX + x];
+  const double2 sc = cdiv(cmul(ax[xp], az[j]), cmul(ax[x], az[r]));
+  G[(int64_t)xp * cnt + e] = cmul(w, sc);
 }
 
 // ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
@@ -1234,6 +1292,15 @@ hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n
   const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(pack_block_kernel, dim3(gx), dim3(kThreads), 0, st, W, ld, q, row, n, sign, shift, dst64,
                      dst32);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_green(const double2* W, int64_t ld, int q, int j, int r0, int nrows, int NX,
+                             const double2* ax, const double2* az, double2* G, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  const int64_t cnt = (int64_t)nrows * NX;
+  const dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)NX);
+  hipLaunchKernelGGL(pack_green_kernel, grid, dim3(256), 0, st, W, ld, q, j, r0, nrows, NX, ax, az, G);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ struct VecRef {
 //   Y = P + alpha * sum_t M_t (Q_t + beta_t S_t)
 // Each M_t is an n x n row-major matrix (complex float64 or complex float32),
 // every vector has n rows and nrhs columns with the launch's column stride.
+// A wide term (kw[t] > 0, float64 streaming and MFMA forms only) has an
+// n x kw[t] matrix with row stride ldm[t] (0: kw[t]) and inputs of kw[t] rows.
 struct Job {
   const void* M[4];
   VecRef Q[4];
@@ -30,6 +32,8 @@ struct Job {
   double2 alpha;
   int32_t nterms;
   int32_t pad;
+  int32_t kw[4];   // columns of M_t (0: n)
+  int32_t ldm[4];  // row stride of M_t in entries (0: its column count)
 };
 
 struct Bases {
@@ -69,6 +73,13 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
                                     hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                                     float2* part = nullptr, SplitCfg cfg = SplitCfg{0, 0});
+// Interface Green's function rows of one layer from its extraction solve:
+// G[x'][(r - r0) NX + x] = W[(q NX + x') ld + r NX + x] * s(j, x') / s(r, x)
+// for r in [r0, r0 + nrows), with s(r, x) = ax[x] az[r] the diagonal that
+// makes the local operator symmetric (A = diag(s) A_sym): the rows of the
+// inverse follow from its columns at the trace row j (solve column block q).
+hipError_t launch_pack_green(const double2* W, int64_t ld, int q, int j, int r0, int nrows, int NX,
+                             const double2* ax, const double2* az, double2* G, hipStream_t st);
 // the rule's k-slice count of a split launch with the given tile width (0: the rule's width)
 int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block

@@ -109,6 +109,7 @@ const TuneCfg* tuned(const pt_solver* S, const Launch& Lc, int nrhs) {
 pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc) {
   if (Lc.njobs == 0) return PT_OK;
   ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
+  if (Lc.wide) g.steps = 0;  // wide terms: the streaming form's general (pipelined) variant
   if (tc && g.mfma && tc->tn) {
     g.mfma = tc->tn;
     g.ks = tc->ks;
@@ -161,10 +162,14 @@ Launch push_launch(pt_solver* S, const std::vector<Job>& js, int cls, bool plr_t
       for (int t = 0; t < j.nterms; ++t) Lc.mat_elems += (double)S->plr.stored_entries(S->blk_id(j.M[t]));
       Lc.plr = true;
     } else {
-      Lc.mat_elems += j.nterms * n * n;
+      for (int t = 0; t < j.nterms; ++t) Lc.mat_elems += n * (j.kw[t] > 0 ? (double)j.kw[t] : n);
     }
     double v = (j.P.buf >= 0 ? n : 0) + n;  // epilogue read + output write
-    for (int t = 0; t < j.nterms; ++t) v += (j.Q[t].buf >= 0 ? n : 0) + (j.S[t].buf >= 0 ? n : 0);
+    for (int t = 0; t < j.nterms; ++t) {
+      const double k = j.kw[t] > 0 ? (double)j.kw[t] : n;
+      v += (j.Q[t].buf >= 0 ? k : 0) + (j.S[t].buf >= 0 ? k : 0);
+      if (j.kw[t] > 0) Lc.wide = true;
+    }
     Lc.vec_elems_rhs += v;
   }
   S->hjobs.insert(S->hjobs.end(), js.begin(), js.end());
@@ -198,6 +203,7 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
     if (!(o->plr_eps > 0)) return fail(PT_EINVAL, "plr_eps must be > 0");
     if (o->plr_rmax < 0 || o->plr_rmax > kPlrMaxRank) return fail(PT_EINVAL, "plr_rmax must be in 0..64");
   }
+  if (o->presolve < 0 || o->presolve > 2) return fail(PT_EINVAL, "presolve must be 0, 1 or 2");
   return PT_OK;
 }
 
@@ -380,9 +386,12 @@ Launch layer_range(const pt_solver* S, const Launch& Lc, int la, int lb) {
   for (int i = 0; i < sub.njobs; ++i) {
     const Job& j = S->hjobs[sub.job0 + i];
     sub.maxterms = std::max(sub.maxterms, j.nterms);
-    sub.mat_elems += j.nterms * n * n;
     double v = (j.P.buf >= 0 ? n : 0) + n;
-    for (int t = 0; t < j.nterms; ++t) v += (j.Q[t].buf >= 0 ? n : 0) + (j.S[t].buf >= 0 ? n : 0);
+    for (int t = 0; t < j.nterms; ++t) {
+      const double k = j.kw[t] > 0 ? (double)j.kw[t] : n;
+      sub.mat_elems += n * k;
+      v += (j.Q[t].buf >= 0 ? k : 0) + (j.S[t].buf >= 0 ? k : 0);
+    }
     sub.vec_elems_rhs += v;
   }
   return sub;
@@ -607,6 +616,54 @@ pt_status extract_blocks(pt_solver* S) {
     rows.release();
     return fail(PT_ENOMEM, "extraction workspace");
   }
+  // interface Green's functions of the pre-solve (float64 factors only)
+  S->green_off.assign((size_t)L * 4, SIZE_MAX);
+  if (S->opt.presolve != 0 && S->opt.precision != PT_F32) {
+    size_t need = 0;
+    for (int l = 0; l < L; ++l) {
+      const Layer& y = S->lay[l];
+      const int ntr = (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0);
+      need += (size_t)ntr * NX * ((size_t)y.n * NX);
+    }
+    size_t freeb = 0, totalb = 0;
+    const bool fits = hipMemGetInfo(&freeb, &totalb) == hipSuccess && need * sizeof(double2) <= freeb / 3;
+    if (S->opt.presolve == 1 || fits) {
+      if (S->green.alloc(need) != hipSuccess) {
+        S->green.release();
+        if (S->opt.presolve == 1) {
+          Wx.release();
+          Bx.release();
+          rows.release();
+          return fail(PT_ENOMEM, "interface Green's functions");
+        }
+        (void)hipGetLastError();
+      } else {
+        size_t off = 0;
+        for (int l = 0; l < L; ++l) {
+          const Layer& y = S->lay[l];
+          const int ntr = (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0);
+          for (int k = 0; k < ntr; ++k) {
+            S->green_off[(size_t)l * 4 + k] = off;
+            off += (size_t)NX * ((size_t)y.n * NX);
+          }
+        }
+      }
+    }
+  }
+  DevBuf<double2> gax, gaz;
+  if (S->green.p) {
+    std::vector<double2> hax(NX);
+    for (int i = 0; i < NX; ++i) hax[i] = d2(S->ax_host[i]);
+    if (gax.alloc(NX) != hipSuccess || gaz.alloc(maxR) != hipSuccess ||
+        hipMemcpy(gax.p, hax.data(), NX * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+      gax.release();
+      gaz.release();
+      Wx.release();
+      Bx.release();
+      rows.release();
+      return fail(PT_EHIP, "green scaling");
+    }
+  }
   const size_t saved_jobs = S->hjobs.size();
   for (int l = 0; l < L && rc == PT_OK; ++l) {
     const Layer& y = S->lay[l];
@@ -646,6 +703,21 @@ pt_status extract_blocks(pt_solver* S) {
     }
     rc = run_local(S, lf, lb, nrhs, ld, Wx.p, Bx.p);
     if (rc != PT_OK) break;
+    if (S->green.p) {
+      // rows src[k] of this layer's inverse over its owned rows
+      std::vector<double2> haz(y.R);
+      const std::vector<RowZ> rz = local_rows(S, y);
+      for (int r = 0; r < y.R; ++r) haz[r] = d2(rz[r].a);
+      if (hipMemcpy(gaz.p, haz.data(), y.R * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+        rc = fail(PT_EHIP, "green scaling");
+        break;
+      }
+      for (int k = 0; k < nq && rc == PT_OK; ++k)
+        if (launch_pack_green(Wx.p, ld, k, src[k], y.top_ext, y.n, NX, gax.p, gaz.p,
+                              S->green.p + S->green_off[(size_t)l * 4 + k], st) != hipSuccess)
+          rc = fail(PT_EHIP, "pack_green");
+      if (rc != PT_OK) break;
+    }
     // pack the signed blocks (column q of the solve = source row src[q])
     auto qof = [&](int row) {
       for (int q = 0; q < nq; ++q)
@@ -697,6 +769,8 @@ pt_status extract_blocks(pt_solver* S) {
   Wx.release();
   Bx.release();
   rows.release();
+  gax.release();
+  gaz.release();
   return rc;
 }
 
@@ -734,6 +808,34 @@ void build_online_jobs(pt_solver* S) {
       hi_pre[l] = hi >= 0 ? hi : y.mid;
       lo_rec[l] = y.top_ext;
       hi_rec[l] = y.top_ext + y.n - 1;
+    }
+    // pre-solve by the interface Green's functions: w^l(row j) = sum over owned rows
+    // of G^l_j h^2 f^l, one job per (layer, trace row) in layer order
+    S->green_launch = Launch{};
+    if (S->green.p) {
+      std::vector<Job> js;
+      for (int l = 0; l < L; ++l) {
+        const Layer& y = S->lay[l];
+        std::vector<int> src;
+        if (y.top_ext) {
+          src.push_back(y.r0);
+          src.push_back(y.r1);
+        }
+        if (y.bot_ext) {
+          src.push_back(y.rn);
+          src.push_back(y.rn1);
+        }
+        for (size_t k = 0; k < src.size(); ++k) {
+          Job j = empty_job();
+          j.Y = vr(0, (int64_t)(y.rowbase + src[k]) * NX);
+          add_term(j, S->green.p + S->green_off[(size_t)l * 4 + k], vr(1, (int64_t)(y.rowbase + y.top_ext) * NX));
+          j.kw[0] = y.n * NX;
+          j.ldm[0] = y.n * NX;
+          js.push_back(j);
+        }
+      }
+      S->green_launch = push_launch(S, js, PT_CLS_LOCAL);
+      index_layers(S, S->green_launch);
     }
     S->bwd_pre.clear();
     S->bwd_rec.clear();
@@ -941,8 +1043,20 @@ pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y,
 }
 
 // Newton potentials w^l = (A^l)^-1 h^2 f^l of every layer into S->W
+// Green's-function pre-solve for a pass of `cols` columns: forced on, or (auto)
+// while the streaming kernel takes it (<= 4 columns: one HBM pass over the
+// Green's functions beats ~R dependent launches; with more columns the MFMA
+// form re-reads them per k chunk and the line-by-line solve is as fast)
+bool use_green(const pt_solver* S, int cols) {
+  return S->green.p && (S->opt.presolve == 1 || cols <= 4);
+}
+
 pt_status newton(pt_solver* S, const double2* f, int nrhs) {
   HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
+  if (use_green(S, nrhs)) {
+    Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
+    return run_apply(S, S->green_launch, nrhs, (int64_t)S->sumR * S->NX, b);
+  }
   return run_local(S, S->fwd, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
@@ -1014,7 +1128,13 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   const int64_t ld = (int64_t)S->sumR * S->NX;
   HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
                               S->h * S->h, st));
-  PTCHK(run_local_layers(S, S->fwd, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
+  if (use_green(S, m)) {
+    const Launch sub = layer_range(S, S->green_launch, la, lb);
+    Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
+    if (sub.njobs > 0) PTCHK(run_apply(S, sub, m, ld, b));
+  } else {
+    PTCHK(run_local_layers(S, S->fwd, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
+  }
   HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
                              S->sumR, S->NX, S->Nt, nrhs, st));
   // the pinned slot tables are rewritten by the next call: finish their uploads first
@@ -1170,6 +1290,7 @@ void pt_free(pt_solver* S) {
   S->blk32.release();
   S->blkbf.release();
   S->part.release();
+  S->green.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag,
                   &S->row_layer, &S->lay_own_start, &S->lay_n_own, &S->slot_rhs, &S->rhs_slot})
@@ -1442,6 +1563,7 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
     west[i] = i > 0 ? -(ax[i] * axm[i]) : cmk(0, 0);
     east[i] = i < NX - 1 ? -(ax[i] * axp[i]) : cmk(0, 0);
   }
+  S->ax_host = ax;
   // per local row: diagonal of A_r and the z couplings l_r (to r-1), u_r (to r+1)
   std::vector<cd> diag((size_t)S->sumR * NX);
   S->lcoef.assign(S->sumR, cmk(0, 0));
@@ -1597,6 +1719,7 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   o->dense_block_bytes = (int64_t)S->nblk * S->block_elems() * es;
   o->block_bytes = S->use_plr ? (int64_t)(S->plr.data_entries * sizeof(double2)) : o->dense_block_bytes;
   o->plr_leaves = S->use_plr ? (int64_t)S->plr.nleaves_total : 0;
+  o->green_bytes = S->green.p ? (int64_t)(S->green.n * sizeof(double2)) : 0;
   o->factor_bytes = (int64_t)S->sumR * S->block_elems() * es;
   return PT_OK;
 }

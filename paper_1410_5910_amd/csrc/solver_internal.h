@@ -71,6 +71,7 @@ struct Launch {
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
   std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
+  bool wide = false;         // some job has a wide term (columns != n)
 };
 
 struct ProfPending {
@@ -133,6 +134,12 @@ struct pt_solver {
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
   bool split = false;
   DevBuf<float2> part;     // k-slice partial tiles of small split launches
+  // interface Green's functions of the pre-solve: per layer and trace row j,
+  // the NX x (n NX) rows j of (A^l)^-1 over the owned rows (null: line-by-line)
+  DevBuf<double2> green;
+  std::vector<size_t> green_off;  // [layer * 4 + trace-row slot] -> offset in green (SIZE_MAX: absent)
+  Launch green_launch;            // one job per (layer, trace row), layer order
+  std::vector<cd> ax_host;        // x-direction PML alphas at the nodes
   int nblk = 0;
   std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
   DevBuf<int32_t> rowmap;

@@ -40,7 +40,7 @@ class PtProblem(C.Structure):
 class PtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gs_iters", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
                 ("max_nrhs", C.c_int32), ("plr", C.c_int32), ("plr_eps", C.c_double), ("plr_rmax", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("presolve", C.c_int32)]
 
 
 class PtRhsInfo(C.Structure):
@@ -53,7 +53,7 @@ class PtLayout(C.Structure):
                 ("R", C.c_int32 * 64), ("own_start", C.c_int32 * 64), ("n_own", C.c_int32 * 64),
                 ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
                 ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64), ("dense_block_bytes", C.c_int64),
-                ("plr_leaves", C.c_int64)]
+                ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64)]
 
 
 class PtKernelStats(C.Structure):
@@ -148,7 +148,7 @@ class Solver:
     """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
 
     def __init__(self, nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
-                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False):
+                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False, presolve="auto"):
         self._lib = lib()
         c = np.ascontiguousarray(c, dtype=np.float64)
         NX, NZ = nx + 2 * npml, nz + 2 * npml
@@ -158,8 +158,11 @@ class Solver:
         prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
                          c.ctypes.data_as(C.POINTER(C.c_double)))
         prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
+        if presolve not in ("local", "green", "auto"):
+            raise ValueError(f"presolve must be 'local', 'green' or 'auto', not {presolve!r}")
+        pre = {"local": 0, "green": 1, "auto": 2}[presolve]
         opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
-                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0)
+                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0, pre)
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
         self._h = h_
@@ -194,7 +197,7 @@ class Solver:
                 "own_start": list(o.own_start[:L]), "n_own": list(o.n_own[:L]), "top_ext": list(o.top_ext[:L]),
                 "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
                 "factor_bytes": o.factor_bytes, "dense_block_bytes": o.dense_block_bytes,
-                "plr_leaves": o.plr_leaves}
+                "plr_leaves": o.plr_leaves, "green_bytes": o.green_bytes}
 
     def profile(self, enable: bool):
         """Start (reset) / stop recording HIP events around every block-apply launch."""

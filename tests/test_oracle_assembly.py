@@ -126,3 +126,23 @@ def test_local_extension_model_is_normal_extension():
         # first extension node carries no damping, deeper ones do
         if s.top_ext:
             assert az[s.row(0)] == 1.0 and abs(az[s.row(-1)] - 1) > 0
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_local_inverse_rows_from_columns(L):
+    # The local operator is a diagonal times a symmetric matrix, A^l = diag(s) A_sym with
+    # s = a_x a_z (its own z profile, extension PML included), so the rows of (A^l)^-1 follow
+    # from its columns: K[p, q] = K[q, p] s_p / s_q.  The GPU pre-solve builds the rows of the
+    # inverse at the trace rows from the columns its extraction solves compute.
+    prob = tiny(nx=5, nz=9, npml=2, L=L, seed=11)
+    ax, _, _ = asm.axis_alphas(prob.nx, prob.px, prob.h, prob.C, prob.omega, prob.npml)
+    for slab in asm.layer_split(prob):
+        A = asm.local_operator(prob, slab).toarray()
+        K = np.linalg.inv(A)
+        az, _, _, _ = asm.local_z_profile(prob, slab)
+        s = (az[:, None] * ax[None, :]).ravel()
+        assert np.abs(K - K.T).max() > 1e-3 * np.abs(K).max()  # not symmetric by itself
+        assert np.allclose(K, K.T * s[:, None] / s[None, :], rtol=0, atol=1e-12 * np.abs(K).max())
+        # and A_sym = diag(1/s) A is symmetric (a planted transpose of the scaling would fail)
+        As = A / s[:, None]
+        assert np.allclose(As, As.T, rtol=0, atol=1e-13 * np.abs(As).max())
