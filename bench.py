@@ -14,7 +14,10 @@ against the float64 oracle on the sampled sources, else in float64.  `forms`
 reports the float64 form of the same workload beside it (and, with
 --all-forms, float32 blocks, the smooth single-source workload and
 compressed blocks).  Tile shapes are tuned (pt_tune) after setup, outside
-the timed steps.
+the timed steps.  GMRES stops at a relative trace residual of 1e-8 (--tol),
+which keeps every sampled source within 1e-8 of the oracle, so both the
+mixed form and the float64 form it is compared with meet the 1e-6 bar and
+the float64 path's own 1e-8 bar.
 
 Prints one JSON line; progress goes to stderr.
 """
@@ -71,10 +74,13 @@ class Oracle:
         self.t_fact = time.perf_counter() - t0
 
     def errors(self, f, u, k):
+        """Relative error of k sources spread evenly over the batch (first and last included)."""
         import numpy as np
-        ref = self.ds.solve(f[:k])
-        got = u[:k].cpu().numpy()
-        return [float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(k)]
+        n = f.shape[0]
+        idx = sorted({round(i * (n - 1) / max(k - 1, 1)) for i in range(k)}) if k > 1 else [0]
+        ref = self.ds.solve(f[idx])
+        got = u[idx].cpu().numpy()
+        return [float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(idx))]
 
     def baseline(self, f, budget_s=10.0):
         """Repeated single-source solves of the factored system for about budget_s seconds."""
@@ -89,11 +95,11 @@ class Oracle:
         return nsol / el, nsol, el
 
 
-def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True):
+def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8):
     """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
     nrhs = f.shape[0]
     t0 = time.perf_counter()
-    s = P.Solver.from_problem(prob, precision=precision, tol=1e-10, maxit=60, max_nrhs=nrhs,
+    s = P.Solver.from_problem(prob, precision=precision, tol=tol, maxit=60, max_nrhs=nrhs,
                               stream=stream.cuda_stream, plr=plr, plr_eps=1e-9)
     lay = s.layout()
     fd = torch.from_numpy(f).to("cuda:0")
@@ -212,7 +218,12 @@ def main():
                     help="auto: mixed (split-bfloat16 sweeps) if it meets the 1e-6 bar on the sampled sources, "
                          "else f64")
     ap.add_argument("--nrhs", type=int, default=0, help="sources per step (default: all of the workload's)")
-    ap.add_argument("--check", type=int, default=4, help="sources compared with the oracle (0: none)")
+    ap.add_argument("--check", type=int, default=16,
+                    help="sources compared with the oracle, spread over the batch (0: none)")
+    ap.add_argument("--tol", type=float, default=1e-8,
+                    help="GMRES stop: relative residual of the trace system.  1e-8 meets the 1e-6 bar of the "
+                         "reduced-precision forms and the 1e-8 bar of the float64 path with margin to spare in "
+                         "the error; the paper's own runs stop at 1e-7")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the float64 comparison form")
     ap.add_argument("--all-forms", action="store_true",
@@ -265,7 +276,8 @@ def main():
     order = ["split-bf16", "f64"] if args.precision == "auto" else [args.precision]
     for prec in order:
         log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
-        form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune)
+        form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune,
+                           tol=args.tol)
         form["workload"] = args.workload
         form["roofline"] = roofline(form)
         if k:
@@ -292,7 +304,7 @@ def main():
             pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
             log(f"form {wl} {prec}{' plr' if plr else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
-                               args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune)
+                               args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol)
             form["workload"] = wl
             rf = roofline(form)
             form["roofline_dominant_class"] = {kk: rf[kk] for kk in ("class", "kernel", "bound", "achieved", "unit",
@@ -320,7 +332,7 @@ def main():
                                           "operator A, Krylov vectors and residuals in float64",
                             "f32": "float32 blocks and local factors, float64 Krylov vectors",
                             "f64": "float64"}[chosen["precision"]],
-                   "gmres_tol": 1e-10, "gs_iters": 2, "iterations": chosen["iterations"]},
+                   "gmres_tol": args.tol, "gs_iters": 2, "iterations": chosen["iterations"]},
         "roofline": chosen["roofline"],
         "rel_err_vs_oracle": chosen.get("rel_err_vs_oracle"),
         "rel_err_checked_rhs": chosen.get("rel_err_checked_rhs"),
