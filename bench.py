@@ -95,6 +95,47 @@ class Oracle:
         return nsol / el, nsol, el
 
 
+def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
+    """The uneven batch: 8 independent problems (grids 240..850 padded, L 4..16), 32 sources each, one
+    pt_solve_batch call per step, each problem on its own stream; sources device-resident."""
+    import synth
+    probs = synth.config4()
+    streams = [torch.cuda.Stream() for _ in probs]
+    t0 = time.perf_counter()
+    solvers = [P.Solver.from_problem(p, precision=precision, tol=tol, maxit=60, max_nrhs=f.shape[0],
+                                     stream=st.cuda_stream) for (p, f), st in zip(probs, streams)]
+    setup_s = time.perf_counter() - t0
+    fds = [torch.from_numpy(f).to("cuda:0") for _, f in probs]
+    for _ in range(warmup):
+        res = P.solve_batch(solvers, fds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = P.solve_batch(solvers, fds)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nrhs = sum(f.shape[0] for _, f in probs)
+    out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs,
+           "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
+           "problems": [{"name": p.name, "L": p.L, "nrhs": f.shape[0],
+                         "iterations": sorted(set(i["iters"] for i in r[1])),
+                         "max_true_relres": max(i["relres"] for i in r[1]),
+                         "presolve": "green" if sv.layout()["green_bytes"] else "local"}
+                        for (p, f), r, sv in zip(probs, res, solvers)]}
+    # the smallest problem's first and last sources against the oracle
+    small = min(range(len(probs)), key=lambda i: probs[i][0].NX)
+    p, f = probs[small]
+    ds = Oracle(p)
+    got = res[small][0][[0, f.shape[0] - 1]].cpu().numpy()
+    ref = ds.ds.solve(f[[0, f.shape[0] - 1]])
+    import numpy as np
+    out["rel_err_vs_oracle"] = max(float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(2))
+    out["rel_err_checked"] = f"{p.name}: 2 sources"
+    for sv in solvers:
+        sv.close()
+    return out
+
+
 def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8):
     """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
     nrhs = f.shape[0]
@@ -319,6 +360,13 @@ def main():
             log(f"  {form['solves_per_s']:.1f} solves/s, rel err {form.get('rel_err_vs_oracle', float('nan')):.2e}")
             forms.append(form)
             have.add((wl, prec, plr))
+        if args.all_forms:
+            for prec in ("split-bf16", "f64"):
+                log(f"form uneven8 {prec}: 8 problems x 32 sources, one pt_solve_batch per step")
+                form = run_uneven(P, torch, prec, args.steps, args.warmup, tol=args.tol)
+                log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step, rel err "
+                    f"{form['rel_err_vs_oracle']:.2e}")
+                forms.append(form)
 
     f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"]
     out = {

@@ -4,6 +4,7 @@
 // system, Def. 9, preconditioned by Gauss-Seidel sweeps, Alg. 4), and the
 // C-ABI of include/polar.h.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -582,6 +583,14 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
   return rc;
 }
 
+// device bytes of interface Green's functions held by all solvers of the process
+std::atomic<size_t> g_green_total{0};
+
+void release_green(pt_solver* S) {
+  if (S->green.p) g_green_total -= S->green.n * sizeof(double2);
+  S->green.release();
+}
+
 pt_status extract_blocks(pt_solver* S) {
   const int NX = S->NX, L = S->L;
   const size_t E = S->block_elems();
@@ -625,8 +634,13 @@ pt_status extract_blocks(pt_solver* S) {
       const int ntr = (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0);
       need += (size_t)ntr * NX * ((size_t)y.n * NX);
     }
+    // auto: at most a third of the free memory, a sixteenth of the device per
+    // solver and a quarter of the device over all solvers of the process, so
+    // that solvers set up later still find room for their factors
     size_t freeb = 0, totalb = 0;
-    const bool fits = hipMemGetInfo(&freeb, &totalb) == hipSuccess && need * sizeof(double2) <= freeb / 3;
+    const size_t bytes = need * sizeof(double2);
+    const bool fits = hipMemGetInfo(&freeb, &totalb) == hipSuccess && bytes <= freeb / 3 && bytes <= totalb / 16 &&
+                      g_green_total.load() + bytes <= totalb / 4;
     if (S->opt.presolve == 1 || fits) {
       if (S->green.alloc(need) != hipSuccess) {
         S->green.release();
@@ -638,6 +652,7 @@ pt_status extract_blocks(pt_solver* S) {
         }
         (void)hipGetLastError();
       } else {
+        g_green_total += bytes;
         size_t off = 0;
         for (int l = 0; l < L; ++l) {
           const Layer& y = S->lay[l];
@@ -1290,7 +1305,7 @@ void pt_free(pt_solver* S) {
   S->blk32.release();
   S->blkbf.release();
   S->part.release();
-  S->green.release();
+  release_green(S);
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag,
                   &S->row_layer, &S->lay_own_start, &S->lay_n_own, &S->slot_rhs, &S->rhs_slot})
