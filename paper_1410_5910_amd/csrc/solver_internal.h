@@ -46,6 +46,10 @@ inline cd operator*(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im
 inline cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 inline cd operator-(cd a) { return {-a.re, -a.im}; }
 inline double2 d2(cd a) { return make_double2(a.re, a.im); }
+inline double2 cdiv_h(cd a, cd b) {  // a / b on the host
+  const double den = b.re * b.re + b.im * b.im;
+  return make_double2((a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den);
+}
 
 // alpha = 1 / (1 + i sigma / omega), sigma = (C/delta)(d/delta)^2
 inline cd pml_alpha(double d_len, double C, double delta, double omega) {
@@ -159,6 +163,7 @@ struct pt_solver {
   std::vector<Launch> fwd, bwd, sweep;
   std::vector<Launch> bwd_pre, bwd_rec;  // backward passes stopped at the trace rows / the owned rows
   Launch bterm, opA, opR;
+  Launch opA2;  // second launch of A in the extrapolated form (njobs 0: A is one launch)
 
   // captured GMRES iterations: (nrhs, iteration) -> executable graph
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;

@@ -231,3 +231,32 @@ def test_gauss_seidel_iteration_converges():
     assert hist[-1] < 1e-10
     u = ps.reconstruct(f, x)
     assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+
+
+def test_operator_rows_by_extrapolation(small3):
+    # Lemma 4 turns the second row of each interface pair of y = A x into one extrapolation of
+    # the first: y_dn[k, n+1] = d_k[n+1] - E_dn(k) (d_k[n] - y_dn[k, n]) and
+    # y_up[k, 0] = a_k[0] - E_up(k+1) (a_k[1] - y_up[k, 1]); with general couplings the
+    # identities K_{n+1,n+1} - E_dn K_{n,n+1} = Sigma^-1 and K_{0,0} - E_up K_{1,0} = Delta^-1 (the
+    # one-row Schur complements) add (Sigma^-1 - E_dn) a_k[n] resp. (Delta^-1 - E_up) d_k[n+1],
+    # which vanish in the A scaling (couplings -1 at the trace rows).
+    prob, f, ps, u = small3
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(ps.zeros(3).shape) + 1j * rng.standard_normal(ps.zeros(3).shape)
+    y = ps.apply_A(x)
+    d, a = x[:, 0], x[:, 1]
+    for k in range(ps.L - 1):
+        up, lo = ps.loc[k], ps.loc[k + 1]
+        Kt, Kb = up.K, lo.K
+        Edn = np.linalg.solve(Kt[("n", "n")], Kt[("n", "n+1")])
+        Eup = np.linalg.solve(Kb[("1", "1")], Kb[("1", "0")])
+        Sig = Kt[("n+1", "n+1")] - Edn @ Kt[("n", "n+1")]
+        Dlt = Kb[("0", "0")] - Eup @ Kb[("1", "0")]
+        y1 = d[:, k, 1] - (d[:, k, 0] - y[:, 0, k, 0] + a[:, k, 0]) @ Edn.T + a[:, k, 0] @ Sig.T
+        y0 = a[:, k, 0] - (a[:, k, 1] - y[:, 1, k, 1] + d[:, k, 1]) @ Eup.T + d[:, k, 1] @ Dlt.T
+        assert rel(y1, y[:, 0, k, 1]) < 1e-10, k
+        assert rel(y0, y[:, 1, k, 0]) < 1e-10, k
+        # A scaling: the one-row Schur complements are the extrapolators themselves
+        assert rel(Sig, Edn) < 1e-10 and rel(Dlt, Eup) < 1e-10
+        assert rel(d[:, k, 1] - (d[:, k, 0] - y[:, 0, k, 0]) @ Edn.T, y[:, 0, k, 1]) < 1e-10
+        assert rel(a[:, k, 0] - (a[:, k, 1] - y[:, 1, k, 1]) @ Eup.T, y[:, 1, k, 0]) < 1e-10
