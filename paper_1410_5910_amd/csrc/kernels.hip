@@ -642,6 +642,22 @@ __global__ __launch_bounds__(256) void pack_green_kernel(const double2* __restri
   G[(int64_t)xp * cnt + e] = cmul(w, sc);
 }
 
+// W[c][dst[e]] = sum over s < cnt[e] of W[c][src0[e] + s] (rows of NX entries,
+// column stride ld), the partial rows summed in order.  grid: (NX / 256, entries, columns).
+__global__ __launch_bounds__(256) void sum_rows_kernel(double2* __restrict__ W, int64_t ld, int NX,
+                                                       const int32_t* __restrict__ dst,
+                                                       const int32_t* __restrict__ src0,
+                                                       const int32_t* __restrict__ cnt) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= NX) return;
+  const int e = blockIdx.y;
+  double2* col = W + (int64_t)blockIdx.z * ld;
+  const int s0 = src0[e], n = cnt[e];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < n; ++k) acc = cadd(acc, col[(int64_t)(s0 + k) * NX + x]);
+  col[(int64_t)dst[e] * NX + x] = acc;
+}
+
 // ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
 template <int NR, bool F32>
 hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
@@ -1301,6 +1317,14 @@ hipError_t launch_pack_green(const double2* W, int64_t ld, int q, int j, int r0,
   const int64_t cnt = (int64_t)nrows * NX;
   const dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)NX);
   hipLaunchKernelGGL(pack_green_kernel, grid, dim3(256), 0, st, W, ld, q, j, r0, nrows, NX, ax, az, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(double2* W, int64_t ld, int NX, const int32_t* dst, const int32_t* src0,
+                           const int32_t* cnt, int nentries, int ncols, hipStream_t st) {
+  if (nentries <= 0 || ncols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((NX + 255) / 256), (unsigned)nentries, (unsigned)ncols);
+  hipLaunchKernelGGL(sum_rows_kernel, grid, dim3(256), 0, st, W, ld, NX, dst, src0, cnt);
   return hipGetLastError();
 }
 

@@ -80,6 +80,10 @@ hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs,
 // inverse follow from its columns at the trace row j (solve column block q).
 hipError_t launch_pack_green(const double2* W, int64_t ld, int q, int j, int r0, int nrows, int NX,
                              const double2* ax, const double2* az, double2* G, hipStream_t st);
+// W[c][dst[e]] = sum_{s < cnt[e]} W[c][src0[e] + s] for entries e < nentries and columns c < ncols
+// (rows of NX complex entries, column stride ld; the rows summed in order)
+hipError_t launch_sum_rows(double2* W, int64_t ld, int NX, const int32_t* dst, const int32_t* src0,
+                           const int32_t* cnt, int nentries, int ncols, hipStream_t st);
 // the rule's k-slice count of a split launch with the given tile width (0: the rule's width)
 int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block

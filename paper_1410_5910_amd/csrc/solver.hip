@@ -32,8 +32,8 @@ ApplyGeom geom_for(int n, int maxterms, int nrhs, int njobs = 1) {
   if (nrhs > 4) {
     const long rows = (long)njobs * ((n + 63) / 64);
     g.mfma = 16;
-    for (int tn : {64, 32})
-      if (rows * ((nrhs + tn - 1) / tn) >= 512) {
+    for (int tn : {64, 32})  // never wider than the right-hand sides rounded up to 16
+      if (tn <= 16 * ((nrhs + 15) / 16) && rows * ((nrhs + tn - 1) / tn) >= 512) {
         g.mfma = tn;
         break;
       }
@@ -851,6 +851,61 @@ void build_online_jobs(pt_solver* S) {
       }
       S->green_launch = push_launch(S, js, PT_CLS_LOCAL);
       index_layers(S, S->green_launch);
+      // K-split form for wide passes: each (layer, trace row) product split into
+      // S_l ranges of owned rows, partial sums in S_l free owned rows per trace
+      // row (rows te+2 .. te+2+4 S_l-1, clear of the trace rows), then summed
+      std::vector<Job> jsp;
+      std::vector<int32_t> hd, hs, hc;
+      S->gsum_off.assign(L + 1, 0);
+      bool room = true;  // every layer has 4 free owned rows between its trace rows
+      for (const Layer& y : S->lay) room = room && (y.n - 3) / 4 >= 1;
+      for (int l = 0; l < L && room; ++l) {
+        const Layer& y = S->lay[l];
+        std::vector<int> src;
+        if (y.top_ext) {
+          src.push_back(y.r0);
+          src.push_back(y.r1);
+        }
+        if (y.bot_ext) {
+          src.push_back(y.rn);
+          src.push_back(y.rn1);
+        }
+        const int ns = std::min(8, (y.n - 3) / 4);  // rows te+2 .. te+1+4 ns stay below row n-1
+        const int per = (y.n + ns - 1) / ns;
+        for (size_t k = 0; k < src.size(); ++k) {
+          const int prow0 = y.rowbase + y.top_ext + 2 + (int)k * ns;
+          int cnt = 0;
+          for (int p = 0; p < ns; ++p) {
+            const int r_lo = p * per, r_hi = std::min(y.n, r_lo + per);
+            if (r_lo >= r_hi) continue;
+            Job j = empty_job();
+            j.Y = vr(0, (int64_t)(prow0 + cnt) * NX);
+            add_term(j, S->green.p + S->green_off[(size_t)l * 4 + k] + (size_t)r_lo * NX,
+                     vr(1, (int64_t)(y.rowbase + y.top_ext + r_lo) * NX));
+            j.kw[0] = (r_hi - r_lo) * NX;
+            j.ldm[0] = y.n * NX;
+            jsp.push_back(j);
+            ++cnt;
+          }
+          hd.push_back(y.rowbase + src[k]);
+          hs.push_back(prow0);
+          hc.push_back(cnt);
+        }
+        S->gsum_off[l + 1] = (int)hd.size();
+      }
+      if (room) {
+        S->green_split = push_launch(S, jsp, PT_CLS_LOCAL);
+        index_layers(S, S->green_split);
+      }
+      if (!room) {
+        S->green_split = Launch{};
+      } else if (S->gsum_dst.alloc(hd.size()) != hipSuccess || S->gsum_src.alloc(hd.size()) != hipSuccess ||
+          S->gsum_cnt.alloc(hd.size()) != hipSuccess ||
+          hipMemcpy(S->gsum_dst.p, hd.data(), hd.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(S->gsum_src.p, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(S->gsum_cnt.p, hc.data(), hc.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        S->green_split = Launch{};  // the unsplit form then serves every width
+      }
     }
     S->bwd_pre.clear();
     S->bwd_rec.clear();
@@ -1109,15 +1164,31 @@ pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y,
 // Green's functions beats ~R dependent launches; with more columns the MFMA
 // form re-reads them per k chunk and the line-by-line solve is as fast)
 bool use_green(const pt_solver* S, int cols) {
-  return S->green.p && (S->opt.presolve == 1 || cols <= 4);
+  return S->green.p && (S->opt.presolve == 1 || cols <= 4 || S->green_split.njobs > 0);
+}
+
+// w^l at the trace rows of layers la..lb from the Green's functions: one
+// launch of whole row blocks for narrow passes (the streaming kernel reads
+// each block once), K-split products plus a row sum for wider ones (the MFMA
+// form then has enough workgroups to stream them)
+pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
+  Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
+  if (cols <= 4 || S->green_split.njobs == 0) {
+    const Launch sub = layer_range(S, S->green_launch, la, lb);
+    if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
+    return PT_OK;
+  }
+  const Launch sub = layer_range(S, S->green_split, la, lb);
+  if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
+  const int e0 = S->gsum_off[la], e1 = S->gsum_off[lb + 1];
+  HIPCHK(launch_sum_rows(S->W.p, ld, S->NX, S->gsum_dst.p + e0, S->gsum_src.p + e0, S->gsum_cnt.p + e0, e1 - e0,
+                         cols, S->st));
+  return PT_OK;
 }
 
 pt_status newton(pt_solver* S, const double2* f, int nrhs) {
   HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
-  if (use_green(S, nrhs)) {
-    Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
-    return run_apply(S, S->green_launch, nrhs, (int64_t)S->sumR * S->NX, b);
-  }
+  if (use_green(S, nrhs)) return green_presolve(S, 0, S->L - 1, nrhs, (int64_t)S->sumR * S->NX);
   return run_local(S, S->fwd, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
@@ -1190,9 +1261,7 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
                               S->h * S->h, st));
   if (use_green(S, m)) {
-    const Launch sub = layer_range(S, S->green_launch, la, lb);
-    Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
-    if (sub.njobs > 0) PTCHK(run_apply(S, sub, m, ld, b));
+    PTCHK(green_presolve(S, la, lb, m, ld));
   } else {
     PTCHK(run_local_layers(S, S->fwd, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
   }
@@ -1352,6 +1421,9 @@ void pt_free(pt_solver* S) {
   S->blkbf.release();
   S->part.release();
   release_green(S);
+  S->gsum_dst.release();
+  S->gsum_src.release();
+  S->gsum_cnt.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag,
                   &S->row_layer, &S->lay_own_start, &S->lay_n_own, &S->slot_rhs, &S->rhs_slot})

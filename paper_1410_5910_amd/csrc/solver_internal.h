@@ -143,6 +143,11 @@ struct pt_solver {
   DevBuf<double2> green;
   std::vector<size_t> green_off;  // [layer * 4 + trace-row slot] -> offset in green (SIZE_MAX: absent)
   Launch green_launch;            // one job per (layer, trace row), layer order
+  // the same products with each row block split over K ranges (wide passes):
+  // partial rows in free rows of each layer, summed into the trace rows
+  Launch green_split;
+  DevBuf<int32_t> gsum_dst, gsum_src, gsum_cnt;  // per (layer, trace row), layer order
+  std::vector<int> gsum_off;                     // first entry of each layer (L + 1)
   std::vector<cd> ax_host;        // x-direction PML alphas at the nodes
   int nblk = 0;
   std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
