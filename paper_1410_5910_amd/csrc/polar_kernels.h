@@ -55,8 +55,10 @@ struct ApplyGeom {
 
 // Shape override of a split-bfloat16 launch (0: rule).
 struct SplitCfg {
-  int tile_rhs;  // 32 or 64 right-hand sides per tile (more than 16 right-hand sides)
-  int kslices;   // k-slices per tile
+  int tile_rhs;    // 32 or 64 right-hand sides per tile (more than 16 right-hand sides)
+  int kslices;     // k-slices per tile
+  int stream = 0;  // > 16 right-hand sides, every job two terms with Q: the branch-free
+                   // two-chunks-in-flight form, 1 without S terms, 2 with (0: general form)
 };
 
 // ---------------------------------------------------------------- block apply

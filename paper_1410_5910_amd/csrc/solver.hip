@@ -127,7 +127,8 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
   if (Lc.plr)
     HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
   else if (Lc.split) {
-    const SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
+    SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
+    if (sc.stream && sc.stream != Lc.two_term) sc.stream = 0;  // the form only serves launches it fits
     const int ks = sc.kslices > 0 ? sc.kslices : split_kslices(Lc.njobs, S->NX, nrhs, sc.tile_rhs);
     const size_t need = (size_t)ks * Lc.njobs * nrhs * S->NX;
     float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
@@ -172,6 +173,17 @@ Launch push_launch(pt_solver* S, const std::vector<Job>& js, int cls, bool plr_t
       if (j.kw[t] > 0) Lc.wide = true;
     }
     Lc.vec_elems_rhs += v;
+  }
+  if (Lc.split && !js.empty()) {
+    bool all_s = true, no_s = true, ok = true;
+    for (const Job& j : js) {
+      ok = ok && j.nterms == 2 && j.Q[0].buf >= 0 && j.Q[1].buf >= 0;
+      for (int t = 0; t < 2; ++t) {
+        all_s = all_s && j.S[t].buf >= 0;
+        no_s = no_s && j.S[t].buf < 0;
+      }
+    }
+    Lc.two_term = !ok ? 0 : all_s ? 2 : no_s ? 1 : 0;
   }
   S->hjobs.insert(S->hjobs.end(), js.begin(), js.end());
   return Lc;
@@ -1610,13 +1622,16 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       const ApplyGeom g = geom_for(S->NX, Lc->maxterms, nrhs, Lc->njobs);
       if (Lc->split) {
         if (nrhs > 16) {
-          for (int tr : {32, 64})
-            for (int ks : {1, 2, 4, 8, 16})
-              if ((size_t)ks * Lc->njobs * nrhs * S->NX <= S->part.n || ks == 1) {
-                TuneCfg c;
-                c.sp = SplitCfg{tr, ks};
-                cands.push_back(c);
-              }
+          std::vector<int> forms{0};
+          if (Lc->two_term) forms.push_back(Lc->two_term);
+          for (int form : forms)
+            for (int tr : {32, 64})
+              for (int ks : {1, 2, 4, 8, 16})
+                if ((size_t)ks * Lc->njobs * nrhs * S->NX <= S->part.n || ks == 1) {
+                  TuneCfg c;
+                  c.sp = SplitCfg{tr, ks, form};
+                  cands.push_back(c);
+                }
         } else {
           for (int ks : {1, 2, 4}) {
             TuneCfg c;

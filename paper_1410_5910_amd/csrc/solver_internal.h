@@ -76,6 +76,7 @@ struct Launch {
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
   std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
   bool wide = false;         // some job has a wide term (columns != n)
+  int two_term = 0;          // split launches: every job two terms with Q and (2) every S or (1) no S
 };
 
 struct ProfPending {

@@ -47,6 +47,11 @@ __device__ __forceinline__ int xcd_logical(int i, int G) {
   return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
+// Workgroup barrier that orders LDS only: waits for this wave's LDS operations,
+// not for its global loads, so loads issued for later chunks stay in flight
+// across it (a full __syncthreads() also drains the vector-memory counter).
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
 __device__ __forceinline__ void split2(double x, __bf16& hi, __bf16& lo) {
   hi = static_cast<__bf16>(static_cast<float>(x));
@@ -469,6 +474,204 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
     }
 }
 
+// The wide form specialised for launches whose jobs all have two terms with
+// an input Q each and, when HAS_S, an S each (the Gauss-Seidel sweep steps and
+// the reflection terms).  Every fetch issues the same loads with no branches
+// (chunk index clamped, term pointers picked by selects), so two chunks can be
+// in flight while a third is multiplied; the arithmetic and its order are those
+// of block_split_wide_kernel<NB, 1>.
+template <int NB, bool HAS_S>
+__global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+                                                                 int nct, int nrhs, int64_t ld, Bases bases,
+                                                                 int kslices, int njobs,
+                                                                 float2* __restrict__ part) {
+  constexpr int kWideCols = 16 * NB;
+  constexpr int PPT = kSpK * kWideCols / 2 / 256;              // row pairs per thread: NB
+  constexpr size_t kPlane = (size_t)NB * 64 * sizeof(bf16x8);  // one plane of a chunk
+  __shared__ __align__(16) unsigned char gst[4 * kPlane];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int bid = xcd_logical(blockIdx.x, gridDim.x);
+  const int ct = bid % nct;
+  bid /= nct;
+  const int tile = bid % ntiles;
+  bid /= ntiles;
+  const int slice = bid % kslices;
+  const int job = bid / kslices;
+  const Job& J = jobs[job];
+  const int nkt = (n + kSpK - 1) / kSpK;
+  const int nrt16 = (n + 15) / 16;
+  const int rt = tile * 4 + wave;
+  const bool rt_ok = rt < nrt16;
+  const int rtc = rt_ok ? rt : nrt16 - 1;
+  const int col0 = ct * kWideCols;
+  const __bf16* const M0 = static_cast<const __bf16*>(J.M[0]);
+  const __bf16* const M1 = static_cast<const __bf16*>(J.M[1]);
+  const double2* const q0 = sp_base(bases, J.Q[0].buf) + J.Q[0].off;
+  const double2* const q1 = sp_base(bases, J.Q[1].buf) + J.Q[1].off;
+  const double2* const s0 = HAS_S ? sp_base(bases, J.S[0].buf) + J.S[0].off : q0;
+  const double2* const s1 = HAS_S ? sp_base(bases, J.S[1].buf) + J.S[1].off : q1;
+  const double2 be0 = J.beta[0], be1 = J.beta[1];
+
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nall = 2 * nkt;
+  const int cps = (nall + kslices - 1) / kslices;
+  const int qbeg = min(slice * cps, nall);
+  const int nchunks = min(nall, qbeg + cps) - qbeg;
+  struct InFlight {
+    bf16x8 pa[4];
+    double2 xq[PPT][2];
+    double2 xs[HAS_S ? PPT : 1][2];
+    int qi;
+  };
+  auto fetch = [&](InFlight& F, int qi) {
+    F.qi = qi;
+    const int q = qbeg + min(qi, nchunks - 1);
+    const bool t1 = q >= nkt;
+    const int kt = t1 ? q - nkt : q;
+    const __bf16* Mt = t1 ? M1 : M0;
+    const gbf16x8* T =
+        reinterpret_cast<const gbf16x8*>(reinterpret_cast<uintptr_t>(Mt + ((size_t)rtc * nkt + kt) * 4 * 512));
+#pragma unroll
+    for (int p = 0; p < 4; ++p) F.pa[p] = T[p * 64 + lane];
+    const double2* qb = t1 ? q1 : q0;
+    const double2* sb = t1 ? s1 : s0;
+    const int kbase = kt * kSpK;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int pr = tid + 256 * i;
+      const int k = kbase + 2 * (pr & 15);
+      const int64_t e = (int64_t)min(col0 + (pr >> 4), nrhs - 1) * ld;
+      const int k0c = min(k, n - 1), k1c = min(k + 1, n - 1);
+      const gdouble2* qp = to_global(qb + e);
+      F.xq[i][0] = ldg(qp, k0c);
+      F.xq[i][1] = ldg(qp, k1c);
+      if constexpr (HAS_S) {
+        const gdouble2* sp = to_global(sb + e);
+        F.xs[i][0] = ldg(sp, k0c);
+        F.xs[i][1] = ldg(sp, k1c);
+      }
+    }
+  };
+  auto stage = [&](const InFlight& F) {
+    const bool live = F.qi < nchunks;
+    const int q = qbeg + min(F.qi, nchunks - 1);
+    const bool t1 = q >= nkt;
+    const int kbase = (t1 ? q - nkt : q) * kSpK;
+    const double2 beta = t1 ? be1 : be0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int pr = tid + 256 * j;
+      const int kp = pr & 15, c = pr >> 4;
+      const bool col_ok = live && col0 + c < nrhs;
+      __bf16 h[4][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        double2 v = F.xq[j][u];
+        if constexpr (HAS_S) {
+          v.x += beta.x * F.xs[j][u].x - beta.y * F.xs[j][u].y;
+          v.y += beta.x * F.xs[j][u].y + beta.y * F.xs[j][u].x;
+        }
+        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
+        split2(v.x, h[0][u], h[1][u]);
+        split2(v.y, h[2][u], h[3][u]);
+      }
+      const int l = ((2 * kp) >> 3) * 16 + (c & 15);
+      const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+        bf16x2v w;
+        w[0] = h[pl][0];
+        w[1] = h[pl][1];
+        *reinterpret_cast<bf16x2v*>(gst + pl * kPlane + off) = w;
+      }
+    }
+  };
+  auto multiply = [&](const bf16x8& ar_h, const bf16x8& ar_l, const bf16x8& ai_h, const bf16x8& ai_l) {
+    const bf16x8* P0 = reinterpret_cast<const bf16x8*>(gst);
+    const bf16x8* P1 = reinterpret_cast<const bf16x8*>(gst + kPlane);
+    const bf16x8* P2 = reinterpret_cast<const bf16x8*>(gst + 2 * kPlane);
+    const bf16x8* P3 = reinterpret_cast<const bf16x8*>(gst + 3 * kPlane);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
+      const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
+      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_h, acc[0][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_h, acc[1][b], 0, 0, 0);
+      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_h, acc[2][b], 0, 0, 0);
+      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_h, acc[3][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_l, acc[0][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_l, acc[1][b], 0, 0, 0);
+      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_l, acc[2][b], 0, 0, 0);
+      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_l, acc[3][b], 0, 0, 0);
+      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xr_h, acc[0][b], 0, 0, 0);
+      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xi_h, acc[1][b], 0, 0, 0);
+      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xi_h, acc[2][b], 0, 0, 0);
+      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xr_h, acc[3][b], 0, 0, 0);
+    }
+  };
+  auto round = [&](InFlight& F, int ahead) {
+    stage(F);
+    const bool mult = F.qi < nchunks;
+    const bf16x8 ar_h = F.pa[0], ar_l = F.pa[1], ai_h = F.pa[2], ai_l = F.pa[3];
+    lds_barrier();
+    fetch(F, ahead);
+    if (mult) multiply(ar_h, ar_l, ai_h, ai_l);
+    lds_barrier();
+  };
+  if (nchunks > 0) {  // workgroup-uniform
+    InFlight f0, f1;
+    fetch(f0, 0);
+    fetch(f1, 1);
+    for (int i = 0; i < nchunks; i += 2) {
+      round(f0, i + 2);
+      if (i + 1 < nchunks) round(f1, i + 3);
+    }
+  }
+
+  if (!rt_ok) return;
+  if (kslices > 1) {
+    float2* __restrict__ pt = part + ((size_t)slice * njobs + job) * nrhs * n;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rt * 16 + 4 * (lane >> 4) + i;
+        const int rhs = col0 + b * 16 + (lane & 15);
+        if (row < n && rhs < nrhs)
+          pt[(size_t)rhs * n + row] = make_float2(acc[0][b][i] - acc[1][b][i], acc[2][b][i] + acc[3][b][i]);
+      }
+    return;
+  }
+  double2* __restrict__ Yb = sp_base(bases, J.Y.buf) + J.Y.off;
+  const double2* __restrict__ Pb = J.P.buf >= 0 ? sp_base(bases, J.P.buf) + J.P.off : nullptr;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rt * 16 + 4 * (lane >> 4) + i;
+      const int rhs = col0 + b * 16 + (lane & 15);
+      if (row < n && rhs < nrhs) {
+        const double yr = (double)acc[0][b][i] - (double)acc[1][b][i];
+        const double yi = (double)acc[2][b][i] + (double)acc[3][b][i];
+        double2 y = make_double2(J.alpha.x * yr - J.alpha.y * yi, J.alpha.x * yi + J.alpha.y * yr);
+        if (Pb) {
+          const double2 p = Pb[(int64_t)rhs * ld + row];
+          y.x += p.x;
+          y.y += p.y;
+        }
+        Yb[(int64_t)rhs * ld + row] = y;
+      }
+    }
+}
+
 // Y = P + alpha sum_s part[s] over the k-slices of every job, slices summed in order
 __global__ void split_reduce_kernel(const Job* __restrict__ jobs, int njobs, int n, int nrhs, int64_t ld,
                                     Bases bases, int kslices, const float2* __restrict__ part) {
@@ -511,6 +714,26 @@ hipError_t launch_wide(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, 
                           bases, kslices, (const float2*)part);
   } else {
     hipExtLaunchKernelGGL((block_split_wide_kernel<NB, KS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, jobs, n,
+                          ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
+  }
+  return hipGetLastError();
+}
+
+template <int NB, bool HAS_S>
+hipError_t launch_stream(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1, int kslices, float2* part) {
+  const int ntiles = (n + kWideRows - 1) / kWideRows;
+  const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
+  const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
+  if (kslices > 1) {
+    hipExtLaunchKernelGGL((block_split_stream_kernel<NB, HAS_S>), grid, dim3(256), 0, st, ev0, nullptr, 0, jobs, n,
+                          ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
+    const size_t per = (size_t)nrhs * n;
+    const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
+    hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
+                          bases, kslices, (const float2*)part);
+  } else {
+    hipExtLaunchKernelGGL((block_split_stream_kernel<NB, HAS_S>), grid, dim3(256), 0, st, ev0, ev1, 0, jobs, n,
                           ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
   }
   return hipGetLastError();
@@ -575,6 +798,14 @@ hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs,
     // by a second kernel)
     const int tr = cfg.tile_rhs == 64 ? 64 : kWideColsRule;
     const int ks = cfg.kslices > 0 ? cfg.kslices : split_kslices(njobs, n, nrhs, tr);
+    if (cfg.stream) {  // every job: two terms with Q (and S iff stream == 2)
+      const int k = part ? ks : 1;
+      if (cfg.stream == 2)
+        return tr == 64 ? launch_stream<4, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
+                        : launch_stream<2, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
+      return tr == 64 ? launch_stream<4, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
+                      : launch_stream<2, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
+    }
     if (ks > 1 && part) {
       return tr == 64 ? launch_wide<4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part)
                       : launch_wide<2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
