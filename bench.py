@@ -182,6 +182,7 @@ KERNELS = {
     ("local", "f64"): ("block_mfma64_kernel", "f64"), ("local", "split-bf16"): ("block_mfma64_kernel", "f64"),
     ("operator", "f64"): ("block_mfma64_kernel", "f64"), ("operator", "split-bf16"): ("block_mfma64_kernel", "f64"),
     ("sweep", "f64"): ("block_mfma64_kernel", "f64"), ("reflect", "f64"): ("block_mfma64_kernel", "f64"),
+    ("presolve", "f64"): ("block_mfma64_kernel", "f64"), ("presolve", "split-bf16"): ("block_mfma64_kernel", "f64"),
     ("sweep", "split-bf16"): ("block_split_wide_kernel", "bf16"),
     ("reflect", "split-bf16"): ("block_split_wide_kernel", "bf16"),
 }

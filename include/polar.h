@@ -251,7 +251,10 @@ typedef enum {
   PT_CLS_SWEEP = 1,    /* one step of the Gauss-Seidel down and up sweeps (Alg. 4)       */
   PT_CLS_REFLECT = 2,  /* the reflection terms of a Gauss-Seidel pass                    */
   PT_CLS_OPERATOR = 3, /* the polarized operator A = D + R, or R alone                   */
-  PT_CLS_COUNT = 4
+  PT_CLS_PRESOLVE = 4, /* pre-solve products with the interface Green's functions; with
+                          skipped all-zero input chunks (MFMA form) the counters hold
+                          the bytes and flops of the chunks actually streamed            */
+  PT_CLS_COUNT = 5
 } pt_launch_class;
 /* The counters of one launch class (same synchronisation as pt_profile_read). */
 pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out);
@@ -268,10 +271,11 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * split-bfloat16 tiles of 32 or 64 right-hand sides, split over 1..16
  * k-slices.  Classes with a single form (the row-streaming kernel for <= 4
  * right-hand sides, float32 blocks, compressed blocks) are reported with
- * tried = 1.  out: PT_CLS_COUNT entries (may be NULL). */
+ * tried = 1; the pre-solve products are not tuned (tried = 0).
+ * out: PT_CLS_COUNT entries (may be NULL). */
 typedef struct {
   int32_t cls;        /* pt_launch_class                                          */
-  int32_t tried;      /* candidate shapes timed (0: the class has no launch)       */
+  int32_t tried;      /* candidate shapes timed (0: no launch, or not tuned)       */
   int32_t tile_rhs;   /* chosen right-hand sides per tile (0: rule / single form)  */
   int32_t ksplit;     /* chosen wave groups or k-slices per tile                   */
   double best_us;     /* its mean launch time                                      */

@@ -424,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
 typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
+static_assert(kMmK == kNzChunk, "nonzero-chunk lists count MFMA staging chunks");
 
 template <int TN, int KS>
 __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
@@ -432,6 +433,7 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread of a group
   __shared__ double2 As[KS][kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
   __shared__ double2 Bs[KS][kMmK][TN];
+  __shared__ int32_t kls[kKlMax];
   const int tid = threadIdx.x & 255;    // thread within its k-group
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -469,12 +471,23 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   const int wr = wave * 16;
 
   // columns and row stride of each term (wide terms: kw > 0), chunks of kMmK per term
+  // chunks of term 0 with nonzero inputs (null: all), copied to LDS once so
+  // that looking one up waits on LDS only, not on the chunk loads in flight
+  typedef __attribute__((address_space(1))) const int32_t gi32;
+  const bool kl = J.kl != nullptr;
+  int kl_cnt = 0;
+  if (kl) {
+    gi32* __restrict__ src = reinterpret_cast<gi32*>(reinterpret_cast<uintptr_t>(J.kl));
+    kl_cnt = min((int)src[0], kKlMax);
+    for (int i = threadIdx.x; i < kl_cnt; i += 256 * KS) kls[i] = src[1 + i];
+    __syncthreads();
+  }
   int kt[4], lt[4], nct[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     kt[t] = J.kw[t] > 0 ? J.kw[t] : n;
     lt[t] = J.ldm[t] > 0 ? J.ldm[t] : kt[t];
-    nct[t] = t < J.nterms ? (kt[t] + kMmK - 1) / kMmK : 0;
+    nct[t] = t < J.nterms ? (t == 0 && kl ? kl_cnt : (kt[t] + kMmK - 1) / kMmK) : 0;
   }
   const int nchunks = nct[0] + nct[1] + nct[2] + nct[3];
   const int rounds = (nchunks + KS - 1) / KS;  // the same for every group: barriers stay uniform
@@ -490,22 +503,17 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   auto fetch = [&](Stage& S, int q) {
     S.live = q < nchunks;
     if (!S.live) return;
-    int t = 0;
-    if (q >= nct[0]) {
-      q -= nct[0];
-      t = 1;
-      if (q >= nct[1]) {
-        q -= nct[1];
-        t = 2;
-        if (q >= nct[2]) {
-          q -= nct[2];
-          t = 3;
-        }
+    // term t of chunk q and the chunk within it (array indices stay compile-time constants)
+    int t = 0, K = kt[0], ldm = lt[0];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (t == u && q >= nct[u]) {
+        q -= nct[u];
+        t = u + 1;
+        K = kt[u + 1];
+        ldm = lt[u + 1];
       }
-    }
-    S.c0 = q * kMmK;
-    const int K = t == 0 ? kt[0] : t == 1 ? kt[1] : t == 2 ? kt[2] : kt[3];
-    const int ldm = t == 0 ? lt[0] : t == 1 ? lt[1] : t == 2 ? lt[2] : lt[3];
+    S.c0 = (kl && t == 0 ? kls[q] : q) * kMmK;
     S.kc = K;
     const gd2* __restrict__ M =
         reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * ldm;
@@ -656,6 +664,45 @@ __global__ __launch_bounds__(256) void sum_rows_kernel(double2* __restrict__ W, 
   double2 acc = make_double2(0.0, 0.0);
   for (int k = 0; k < n; ++k) acc = cadd(acc, col[(int64_t)(s0 + k) * NX + x]);
   col[(int64_t)dst[e] * NX + x] = acc;
+}
+
+// One workgroup per input e: flags its chunks (one per thread and pass), then
+// writes the flagged indices in ascending order through a ballot prefix.
+__global__ __launch_bounds__(256) void nonzero_chunks_kernel(const double2* __restrict__ B, int64_t ld, int ncols,
+                                                             const int64_t* __restrict__ off,
+                                                             const int32_t* __restrict__ kk,
+                                                             int32_t* __restrict__ list, int stride) {
+  __shared__ int wcnt[4];
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t o = off[e];
+  const int K = kk[e];
+  const int nch = (K + kNzChunk - 1) / kNzChunk;
+  int32_t* __restrict__ out = list + (int64_t)e * stride;
+  int base = 0;
+  for (int c0 = 0; c0 < nch; c0 += 256) {
+    const int c = c0 + tid;
+    bool nz = false;
+    if (c < nch) {
+      const int lim = min(kNzChunk, K - c * kNzChunk);
+      for (int col = 0; col < ncols && !nz; ++col) {
+        const double2* __restrict__ p = B + (int64_t)col * ld + o + (int64_t)c * kNzChunk;
+        for (int i = 0; i < lim; ++i) {
+          const double2 v = p[i];
+          nz = nz || !(v.x == 0.0 && v.y == 0.0);
+        }
+      }
+    }
+    const uint64_t m = __ballot(nz);
+    if (lane == 0) wcnt[wave] = __popcll(m);
+    __syncthreads();
+    int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; ++w) pos += wcnt[w];
+    if (nz) out[1 + pos] = c;
+    base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = base;
 }
 
 // ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
@@ -1204,6 +1251,14 @@ inline unsigned grid_for(int64_t n, int cap = 8192) {
 }
 
 }  // namespace
+
+hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const int64_t* off, const int32_t* kk,
+                                 int nentries, int32_t* list, int stride, hipStream_t st) {
+  if (nentries <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nonzero_chunks_kernel, dim3(nentries), dim3(256), 0, st, B, ld, ncols, off, kk, list, stride);
+  return hipGetLastError();
+}
+
 
 // ----------------------------------------------------------------------------
 // launchers

@@ -34,7 +34,15 @@ struct Job {
   int32_t pad;
   int32_t kw[4];   // columns of M_t (0: n)
   int32_t ldm[4];  // row stride of M_t in entries (0: its column count)
+  // float64 MFMA form only: the column chunks (kNzChunk columns each) of term 0
+  // whose inputs are not all zero, kl[0] = their count (at most kKlMax) and
+  // kl[1..kl[0]] their indices in ascending order; the others add exact zeros
+  // and are skipped (null: every chunk)
+  const int32_t* kl;
 };
+
+constexpr int kNzChunk = 16;
+constexpr int kKlMax = 512;  // longest chunk list: terms of at most kKlMax * kNzChunk columns
 
 struct Bases {
   double2* b[4];
@@ -86,6 +94,13 @@ hipError_t launch_pack_green(const double2* W, int64_t ld, int q, int j, int r0,
 // (rows of NX complex entries, column stride ld; the rows summed in order)
 hipError_t launch_sum_rows(double2* W, int64_t ld, int NX, const int32_t* dst, const int32_t* src0,
                            const int32_t* cnt, int nentries, int ncols, hipStream_t st);
+// list[e * stride] = number of kNzChunk-entry chunks of input e with an entry
+// that is not zero (NaN and Inf count as not zero) in any of ncols columns,
+// list[e * stride + 1 ..] = their indices in ascending order; input e holds
+// entries off[e] .. off[e] + kk[e] - 1 of each column (stride ld) of B.
+// stride >= 1 + ceil(kk[e] / kNzChunk) for every e.
+hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const int64_t* off, const int32_t* kk,
+                                 int nentries, int32_t* list, int stride, hipStream_t st);
 // the rule's k-slice count of a split launch with the given tile width (0: the rule's width)
 int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block

@@ -134,8 +134,10 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
     float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
-  else
+  else {
+    if (Lc.klist && (S->f32 || !g.mfma)) return fail(PT_EINVAL, "nonzero-chunk lists need the float64 MFMA form");
     HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
+  }
   if (S->prof) {
     // bytes per stored complex entry: 4 bfloat16 planes, float32 or float64 pairs
     const double es = Lc.split ? 8.0 : S->f32 ? 8.0 : 16.0;
@@ -237,7 +239,10 @@ void make_layout(pt_solver* S) {
     y.r1 = y.top_ext ? y.top_ext : -1;
     y.rn = y.bot_ext ? y.top_ext + y.n - 1 : -1;
     y.rn1 = y.bot_ext ? y.top_ext + y.n : -1;
-    y.mid = y.R / 2;
+    // middle of the rows where the online right-hand sides can be nonzero
+    // (trace rows 0..n+1, or the layer's own end without an extension), so
+    // both chains of a solve that starts at them are equally long
+    y.mid = ((y.top_ext ? y.r0 : 0) + (y.bot_ext ? y.rn1 : y.R - 1)) / 2;
     start += y.n;
     rowbase += y.R;
     S->lay.push_back(y);
@@ -280,8 +285,6 @@ std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
 // ---------------------------------------------------------------------------
 // local solves (forward/backward block sweeps with the stored inverses)
 // ---------------------------------------------------------------------------
-// Jobs of the sweep over the layers in `ls` on a local field whose layer l
-// starts at local row rb[l]: bases 0 = solution W, 1 = right-hand side B.
 // Local-solve jobs of the layers ls (row bases rb), two-ended (matching the
 // factorisation): forward launch f eliminates row f top-down and row R-1-f
 // bottom-up in every layer, y_r = Delta_r^-1 (b_r - l_r y_{r-1}) and
@@ -291,15 +294,27 @@ std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
 // x_r = z_r - l_r Sigma_r^-1 x_{r-1} below it, only as far as rows
 // rmin[q]..rmax[q] (empty: all rows): rows beyond the ones a caller reads are
 // never needed, since the backward recurrences run outward.
+//
+// zlo[q]..zhi[q] (empty: all rows) is where the right-hand side may be nonzero.
+// Above zlo the top-down recurrence gives y_r = 0 and below zhi the bottom-up
+// one z_r = 0, so both chains start at the window's ends (launch f then holds
+// rows zlo + f and zhi - f) and the backward steps outside it take y_r = 0.
 void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vector<int>& rb,
                       std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw,
-                      const std::vector<int>& rmin = {}, const std::vector<int>& rmax = {}) {
+                      const std::vector<int>& rmin = {}, const std::vector<int>& rmax = {},
+                      const std::vector<int>& zlo = {}, const std::vector<int>& zhi = {}) {
   const int NX = S->NX;
   int F = 0, G = 0;
+  auto win = [&](size_t q, const Layer& y, int& a, int& b) {  // the window, widened to hold the middle row
+    a = zlo.empty() ? 0 : std::min(std::max(0, zlo[q]), y.mid);
+    b = zhi.empty() ? y.R - 1 : std::max(std::min(y.R - 1, zhi[q]), y.mid);
+  };
   for (size_t q = 0; q < ls.size(); ++q) {
     const Layer& y = S->lay[ls[q]];
     const int lo = rmin.empty() ? 0 : rmin[q], hi = rmax.empty() ? y.R - 1 : rmax[q];
-    F = std::max(F, std::max(y.mid, y.R - 1 - y.mid));
+    int a, b;
+    win(q, y, a, b);
+    F = std::max(F, std::max(y.mid - a, b - y.mid));
     G = std::max(G, std::max(y.mid - std::min(lo, y.mid), std::max(hi, y.mid) - y.mid));
   }
   fw.assign(F + 1, {});
@@ -310,38 +325,40 @@ void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vecto
     const Layer& y = S->lay[l];
     const int m = y.mid;
     const int lo = rmin.empty() ? 0 : rmin[q], hi = rmax.empty() ? y.R - 1 : rmax[q];
-    for (int r = 0; r < m; ++r) {  // top-down
+    int a, b;
+    win(q, y, a, b);
+    for (int r = a; r < m; ++r) {  // top-down from the window's top
       Job j = empty_job();
       j.Y = vr(0, row(q, r));
-      if (r > 0)
+      if (r > a)
         add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r - 1)), d2(-S->lcoef[y.rowbase + r]));
       else
         add_term(j, S->dinv(l, r), vr(1, row(q, r)));
-      fw[r].push_back(j);
+      fw[r - a].push_back(j);
     }
-    for (int r = y.R - 1; r > m; --r) {  // bottom-up
+    for (int r = b; r > m; --r) {  // bottom-up from the window's bottom
       Job j = empty_job();
       j.Y = vr(0, row(q, r));
-      if (r < y.R - 1)
+      if (r < b)
         add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r + 1)), d2(-S->ucoef[y.rowbase + r]));
       else
         add_term(j, S->dinv(l, r), vr(1, row(q, r)));
-      fw[y.R - 1 - r].push_back(j);
+      fw[b - r].push_back(j);
     }
     {  // middle row
       Job j = empty_job();
       j.Y = vr(0, row(q, m));
-      if (m > 0)
+      if (m > a)
         add_term(j, S->dinv(l, m), vr(1, row(q, m)), vr(0, row(q, m - 1)), d2(-S->lcoef[y.rowbase + m]));
       else
         add_term(j, S->dinv(l, m), vr(1, row(q, m)));
-      if (m < y.R - 1) add_term(j, S->dinv(l, m), none(), vr(0, row(q, m + 1)), d2(-S->ucoef[y.rowbase + m]));
+      if (m < b) add_term(j, S->dinv(l, m), none(), vr(0, row(q, m + 1)), d2(-S->ucoef[y.rowbase + m]));
       fw[F].push_back(j);
     }
     for (int r = m - 1; r >= lo; --r) {  // outward, upper part
       Job j = empty_job();
       j.Y = vr(0, row(q, r));
-      j.P = j.Y;
+      if (r >= a) j.P = j.Y;  // y_r = 0 above the window
       j.alpha = d2(-S->ucoef[y.rowbase + r]);
       add_term(j, S->dinv(l, r), vr(0, row(q, r + 1)));
       bw[m - 1 - r].push_back(j);
@@ -349,11 +366,24 @@ void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vecto
     for (int r = m + 1; r <= hi; ++r) {  // outward, lower part
       Job j = empty_job();
       j.Y = vr(0, row(q, r));
-      j.P = j.Y;
+      if (r <= b) j.P = j.Y;  // z_r = 0 below the window
       j.alpha = d2(-S->lcoef[y.rowbase + r]);
       add_term(j, S->dinv(l, r), vr(0, row(q, r - 1)));
       bw[r - m - 1].push_back(j);
     }
+  }
+}
+
+// Rows where the right-hand sides of the pre-solve, the reconstruction and the
+// extraction can be nonzero: the trace rows 0..n+1 of the layer (a layer
+// without an extension on one side: its own end there).
+void rhs_window(const pt_solver* S, std::vector<int>& zlo, std::vector<int>& zhi) {
+  zlo.resize(S->L);
+  zhi.resize(S->L);
+  for (int l = 0; l < S->L; ++l) {
+    const Layer& y = S->lay[l];
+    zlo[l] = y.top_ext ? y.r0 : 0;
+    zhi[l] = y.bot_ext ? y.rn1 : y.R - 1;
   }
 }
 
@@ -706,9 +736,13 @@ pt_status extract_blocks(pt_solver* S) {
     const int nq = (int)src.size();
     const int nrhs = nq * NX;
     const int64_t ld = (int64_t)y.R * NX;
-    // per-layer local solve jobs (this layer only, rows from 0)
+    // per-layer local solve jobs (this layer only, rows from 0): the unit
+    // right-hand sides sit in the trace rows, and the rows read back (trace
+    // rows, owned rows) lie between them
     std::vector<std::vector<Job>> fw, bw;
-    build_local_jobs(S, {l}, {0}, fw, bw);
+    std::vector<int> zlo, zhi;
+    rhs_window(S, zlo, zhi);
+    build_local_jobs(S, {l}, {0}, fw, bw, {zlo[l]}, {zhi[l]}, {zlo[l]}, {zhi[l]});
     S->hjobs.resize(saved_jobs);
     std::vector<Launch> lf, lb;
     for (auto& v : fw) lf.push_back(push_launch(S, v, PT_CLS_LOCAL));
@@ -861,7 +895,7 @@ void build_online_jobs(pt_solver* S) {
           js.push_back(j);
         }
       }
-      S->green_launch = push_launch(S, js, PT_CLS_LOCAL);
+      S->green_launch = push_launch(S, js, PT_CLS_PRESOLVE);
       index_layers(S, S->green_launch);
       // K-split form for wide passes: each (layer, trace row) product split into
       // S_l ranges of owned rows, partial sums in S_l free owned rows per trace
@@ -871,6 +905,35 @@ void build_online_jobs(pt_solver* S) {
       S->gsum_off.assign(L + 1, 0);
       bool room = true;  // every layer has 4 free owned rows between its trace rows
       for (const Layer& y : S->lay) room = room && (y.n - 3) / 4 >= 1;
+      // one nonzero-chunk list per (layer, owned-row range), shared by the
+      // layer's trace rows: the products skip the chunks where every source
+      // column is zero (compact sources leave most of a layer's inputs zero)
+      std::vector<int64_t> nzo;
+      std::vector<int32_t> nzk;
+      S->nz_off.assign(L + 1, 0);
+      int stride = 1;
+      for (int l = 0; l < L && room; ++l) {
+        const Layer& y = S->lay[l];
+        const int ns = std::min(8, (y.n - 3) / 4), per = (y.n + ns - 1) / ns;
+        for (int p = 0; p < ns; ++p) {
+          const int r_lo = p * per, r_hi = std::min(y.n, r_lo + per);
+          if (r_lo >= r_hi) continue;
+          nzo.push_back((int64_t)(y.rowbase + y.top_ext + r_lo) * NX);
+          nzk.push_back((r_hi - r_lo) * NX);
+          stride = std::max(stride, 1 + ((r_hi - r_lo) * NX + kNzChunk - 1) / kNzChunk);
+        }
+        S->nz_off[l + 1] = (int)nzo.size();
+      }
+      S->nz_stride = stride;
+      // a list must fit the kernel's LDS copy: longer ranges keep every chunk
+      const bool lists = room && stride - 1 <= kKlMax;
+      if (lists && (S->nz_list.alloc(nzo.size() * (size_t)stride) != hipSuccess ||
+                   S->nz_in_off.alloc(nzo.size()) != hipSuccess || S->nz_in_k.alloc(nzk.size()) != hipSuccess ||
+                   hipMemcpy(S->nz_in_off.p, nzo.data(), nzo.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+                       hipSuccess ||
+                   hipMemcpy(S->nz_in_k.p, nzk.data(), nzk.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                       hipSuccess))
+        room = false;  // no device memory for the lists: the unsplit form serves every width
       for (int l = 0; l < L && room; ++l) {
         const Layer& y = S->lay[l];
         std::vector<int> src;
@@ -896,6 +959,7 @@ void build_online_jobs(pt_solver* S) {
                      vr(1, (int64_t)(y.rowbase + y.top_ext + r_lo) * NX));
             j.kw[0] = (r_hi - r_lo) * NX;
             j.ldm[0] = y.n * NX;
+            if (S->nz_list.p) j.kl = S->nz_list.p + (size_t)(S->nz_off[l] + cnt) * stride;
             jsp.push_back(j);
             ++cnt;
           }
@@ -906,7 +970,8 @@ void build_online_jobs(pt_solver* S) {
         S->gsum_off[l + 1] = (int)hd.size();
       }
       if (room) {
-        S->green_split = push_launch(S, jsp, PT_CLS_LOCAL);
+        S->green_split = push_launch(S, jsp, PT_CLS_PRESOLVE);
+        S->green_split.klist = S->nz_list.p != nullptr;
         index_layers(S, S->green_split);
       }
       if (!room) {
@@ -921,9 +986,17 @@ void build_online_jobs(pt_solver* S) {
     }
     S->bwd_pre.clear();
     S->bwd_rec.clear();
+    S->fwd_win.clear();
+    std::vector<int> zlo, zhi;
+    rhs_window(S, zlo, zhi);
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<std::vector<Job>> f2, b2;
-      build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? lo_pre : lo_rec, pass == 0 ? hi_pre : hi_rec);
+      build_local_jobs(S, ls, rb, f2, b2, pass == 0 ? lo_pre : lo_rec, pass == 0 ? hi_pre : hi_rec, zlo, zhi);
+      if (pass == 0)
+        for (auto& v : f2) {
+          S->fwd_win.push_back(push_launch(S, v, PT_CLS_LOCAL));
+          index_layers(S, S->fwd_win.back());
+        }
       auto& dst = pass == 0 ? S->bwd_pre : S->bwd_rec;
       for (auto& v : b2)
         if (!v.empty()) {
@@ -1191,7 +1264,30 @@ pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
     return PT_OK;
   }
   const Launch sub = layer_range(S, S->green_split, la, lb);
+  const int n0 = S->nz_off[la], n1 = S->nz_off[lb + 1];
+  if (S->green_split.klist)
+    HIPCHK(launch_nonzero_chunks(S->Bw.p, ld, cols, S->nz_in_off.p + n0, S->nz_in_k.p + n0, n1 - n0,
+                                 S->nz_list.p + (size_t)n0 * S->nz_stride, S->nz_stride, S->st));
   if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
+  if (S->prof && sub.klist && sub.njobs > 0 && !S->pend.empty()) {
+    // count what the launch streamed: the chunks its lists kept
+    std::vector<int32_t> h((size_t)(n1 - n0) * S->nz_stride);
+    HIPCHK(hipMemcpyAsync(h.data(), S->nz_list.p + (size_t)n0 * S->nz_stride, h.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    double mat = 0, vec = 0;
+    const double n = S->NX;
+    for (int i = 0; i < sub.njobs; ++i) {
+      const Job& j = S->hjobs[sub.job0 + i];
+      const int64_t e = (j.kl - S->nz_list.p) / S->nz_stride - n0;
+      const double k = std::min((double)j.kw[0], (double)h[(size_t)e * S->nz_stride] * kNzChunk);
+      mat += n * k;
+      vec += k + n;  // inputs of the kept chunks, output rows
+    }
+    ProfPending& pp = S->pend.back();
+    pp.bytes = mat * 16.0 + vec * cols * 16.0;
+    pp.flops = 8.0 * mat * cols;
+  }
   const int e0 = S->gsum_off[la], e1 = S->gsum_off[lb + 1];
   HIPCHK(launch_sum_rows(S->W.p, ld, S->NX, S->gsum_dst.p + e0, S->gsum_src.p + e0, S->gsum_cnt.p + e0, e1 - e0,
                          cols, S->st));
@@ -1201,7 +1297,7 @@ pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
 pt_status newton(pt_solver* S, const double2* f, int nrhs) {
   HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
   if (use_green(S, nrhs)) return green_presolve(S, 0, S->L - 1, nrhs, (int64_t)S->sumR * S->NX);
-  return run_local(S, S->fwd, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
+  return run_local(S, S->fwd_win, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
 // all sources vanish: s = 0
@@ -1275,7 +1371,7 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   if (use_green(S, m)) {
     PTCHK(green_presolve(S, la, lb, m, ld));
   } else {
-    PTCHK(run_local_layers(S, S->fwd, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
+    PTCHK(run_local_layers(S, S->fwd_win, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
   }
   HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
                              S->sumR, S->NX, S->Nt, nrhs, st));
@@ -1289,7 +1385,7 @@ pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2*
   if (S->L >= 2)
     HIPCHK(launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
                             S->Nt, nrhs, (int64_t)2 * (S->L - 1) * S->NX, S->st));
-  PTCHK(run_local(S, S->fwd, S->bwd_rec, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
+  PTCHK(run_local(S, S->fwd_win, S->bwd_rec, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
   HIPCHK(launch_gather_owned(S->W.p, u, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->st));
   return PT_OK;
 }
@@ -1436,6 +1532,9 @@ void pt_free(pt_solver* S) {
   S->gsum_dst.release();
   S->gsum_src.release();
   S->gsum_cnt.release();
+  S->nz_list.release();
+  S->nz_in_k.release();
+  S->nz_in_off.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();
   for (auto* b : {&S->rowmap, &S->g_seg, &S->g_row, &S->f_seg, &S->f_row, &S->iters, &S->done, &S->flag,
                   &S->row_layer, &S->lay_own_start, &S->lay_n_own, &S->slot_rhs, &S->rhs_slot})

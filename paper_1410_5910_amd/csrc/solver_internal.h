@@ -77,6 +77,7 @@ struct Launch {
   std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
   bool wide = false;         // some job has a wide term (columns != n)
   int two_term = 0;          // split launches: every job two terms with Q and (2) every S or (1) no S
+  bool klist = false;        // jobs carry nonzero-chunk lists: float64 MFMA form only
 };
 
 struct ProfPending {
@@ -149,6 +150,11 @@ struct pt_solver {
   Launch green_split;
   DevBuf<int32_t> gsum_dst, gsum_src, gsum_cnt;  // per (layer, trace row), layer order
   std::vector<int> gsum_off;                     // first entry of each layer (L + 1)
+  // nonzero-chunk lists of the split products' inputs, per (layer, row range)
+  DevBuf<int32_t> nz_list, nz_in_k;
+  DevBuf<int64_t> nz_in_off;
+  std::vector<int> nz_off;  // first list of each layer (L + 1)
+  int nz_stride = 1;
   std::vector<cd> ax_host;        // x-direction PML alphas at the nodes
   int nblk = 0;
   std::vector<int> bidx;  // [layer][type][a][b] -> block number, -1 absent
@@ -168,6 +174,7 @@ struct pt_solver {
   DevBuf<Job> jobs;
   std::vector<Launch> fwd, bwd, sweep;
   std::vector<Launch> bwd_pre, bwd_rec;  // backward passes stopped at the trace rows / the owned rows
+  std::vector<Launch> fwd_win;           // forward passes of right-hand sides zero outside the trace rows 0..n+1
   Launch bterm, opA, opR;
   Launch opA2;  // second launch of A in the extrapolated form (njobs 0: A is one launch)
 

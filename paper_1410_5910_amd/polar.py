@@ -29,7 +29,7 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
            "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel")
-CLASSES = ("local", "sweep", "reflect", "operator")
+CLASSES = ("local", "sweep", "reflect", "operator", "presolve")
 
 
 class PtProblem(C.Structure):
@@ -209,7 +209,7 @@ class Solver:
         return {"launches": o.launches, "kernel_ms": o.kernel_ms, "alg_bytes": o.alg_bytes, "alg_flops": o.alg_flops}
 
     def profile_read_class(self, cls: str) -> dict:
-        """Counters of one launch class: 'local', 'sweep', 'reflect' or 'operator'."""
+        """Counters of one launch class: 'local', 'sweep', 'reflect', 'operator' or 'presolve'."""
         o = PtKernelStats()
         _check(self._lib.pt_profile_read_class(self._h, CLASSES.index(cls), C.byref(o)))
         return {"launches": o.launches, "kernel_ms": o.kernel_ms, "alg_bytes": o.alg_bytes, "alg_flops": o.alg_flops}

@@ -60,7 +60,21 @@ def test_green_layout(pair):
     assert loc.layout()["green_bytes"] == 0
 
 
-@pytest.mark.parametrize("kind", ["dense3", "dense6", "sparse", "single"])
+def _points(prob, nsrc, npts, seed):
+    """Sources nonzero at a few scattered nodes: most 16-entry chunks of a layer's inputs are zero."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((nsrc, prob.NZ, prob.NX), dtype=np.complex128)
+    for r in range(nsrc):
+        zs = rng.integers(prob.npml, prob.npml + prob.nz, npts)
+        xs = rng.integers(prob.npml, prob.npml + prob.nx, npts)
+        f[r, zs, xs] = rng.standard_normal(npts) + 1j * rng.standard_normal(npts)
+    # the last physical node of a row and of the section: ragged chunk ends
+    f[0, prob.npml + prob.nz - 1, prob.npml + prob.nx - 1] = 1.0 - 0.5j
+    f[1, prob.npml + 11, prob.npml + prob.nx - 1] = 0.25
+    return f
+
+
+@pytest.mark.parametrize("kind", ["dense3", "dense6", "sparse", "single", "points"])
 def test_green_trace_rhs_matches_oracle(pair, kind):
     prob, g, loc, ps = pair
     _flush(f"[gpu] green trace rhs {kind}")
@@ -70,6 +84,8 @@ def test_green_trace_rhs_matches_oracle(pair, kind):
         f = rng.standard_normal((k, prob.NZ, prob.NX)) + 1j * rng.standard_normal((k, prob.NZ, prob.NX))
     elif kind == "sparse":
         f = _compact(prob, [(8, 10), (20, 23), (28, 32), (12, 14), (44, 47), (33, 35)], seed=3)
+    elif kind == "points":  # MFMA form with most chunks skipped
+        f = _points(prob, 6, 12, seed=11)
     else:
         f = _compact(prob, [(28, 32)], seed=5)  # straddles layers 1 and 2: a two-layer range
     ref = ps.rhs(ps.newton(f))

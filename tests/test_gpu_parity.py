@@ -340,7 +340,8 @@ def test_tune_keeps_results(precision, nrhs):
     u0, _ = gs.solve(f)
     res = gs.tune(nrhs)
     _flush(f"[gpu]   {res}")
-    assert set(res) == {"local", "sweep", "reflect", "operator"}
+    assert set(res) == {"local", "sweep", "reflect", "operator", "presolve"}
+    assert res.pop("presolve")["tried"] == 0  # the pre-solve products keep the rule's shape
     for cls, e in res.items():
         assert e["tried"] >= 1 and e["best_us"] > 0 and e["best_us"] <= e["default_us"]
         if nrhs > 4 and precision == "f64":
