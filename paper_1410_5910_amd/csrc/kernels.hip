@@ -1031,6 +1031,25 @@ __global__ void trace_map_kernel(double2* W, double2* s, const double2* x, const
   }
 }
 
+__global__ void rec_rhs_kernel(double2* __restrict__ T, const double2* __restrict__ f, const double2* __restrict__ x,
+                               const int32_t* __restrict__ dst, const int32_t* __restrict__ src,
+                               const int32_t* __restrict__ seg, const double* __restrict__ sign, int NX, int64_t ld,
+                               int64_t ntrace, int64_t half, double h2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NX) return;
+  const int e = blockIdx.y;
+  const int r = blockIdx.z;
+  double2 v = make_double2(0.0, 0.0);
+  if (src[e] >= 0) {
+    const double2 fv = f[(int64_t)r * ld + (int64_t)src[e] * NX + i];
+    v = make_double2(h2 * fv.x, h2 * fv.y);
+  }
+  const int64_t si = (int64_t)r * ntrace + (int64_t)seg[e] * NX + i;
+  const double2 t = cadd(x[si], x[si + half]);
+  const double sg = sign[e];
+  T[(int64_t)r * ld + (int64_t)dst[e] * NX + i] = make_double2(v.x + sg * t.x, v.y + sg * t.y);
+}
+
 __global__ void identity_rhs_kernel(double2* W, const int32_t* rows, int nq, int n, int64_t ld) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
@@ -1350,6 +1369,15 @@ hipError_t launch_trace_map(double2* W, double2* s, const double2* x, const int3
   dim3 grid((NX + 127) / 128, nmap, nrhs);
   hipLaunchKernelGGL(trace_map_kernel, grid, dim3(128), 0, st, W, s, x, seg, row, sign, mode, sumR, NX, ntrace,
                      half);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_rhs(double2* T, const double2* f, const double2* x, const int32_t* dst, const int32_t* src,
+                          const int32_t* seg, const double* sign, int ne, int NX, int64_t ld, int64_t ntrace,
+                          int64_t half, double h2, int nrhs, hipStream_t st) {
+  if (ne <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rec_rhs_kernel, dim3((NX + 127) / 128, ne, nrhs), dim3(128), 0, st, T, f, x, dst, src, seg, sign,
+                     NX, ld, ntrace, half, h2);
   return hipGetLastError();
 }
 

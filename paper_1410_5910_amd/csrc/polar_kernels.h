@@ -101,6 +101,13 @@ hipError_t launch_sum_rows(double2* W, int64_t ld, int NX, const int32_t* dst, c
 // stride >= 1 + ceil(kk[e] / kNzChunk) for every e.
 hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const int64_t* off, const int32_t* kk,
                                  int nentries, int32_t* list, int stride, hipStream_t st);
+// Forced right-hand-side rows of an in-place reconstruction: for entries e <
+// ne and right-hand sides r < nrhs, row dst[e] of T = h2 f(row src[e]) (0 if
+// src[e] < 0) + sign[e] (x + x[half])(segment seg[e]); T and f have column
+// stride ld, x column stride ntrace; rows of NX entries.
+hipError_t launch_rec_rhs(double2* T, const double2* f, const double2* x, const int32_t* dst, const int32_t* src,
+                          const int32_t* seg, const double* sign, int ne, int NX, int64_t ld, int64_t ntrace,
+                          int64_t half, double h2, int nrhs, hipStream_t st);
 // the rule's k-slice count of a split launch with the given tile width (0: the rule's width)
 int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <thread>
 #include <vector>
@@ -299,10 +300,22 @@ std::vector<RowZ> local_rows(const pt_solver* S, const Layer& y) {
 // Above zlo the top-down recurrence gives y_r = 0 and below zhi the bottom-up
 // one z_r = 0, so both chains start at the window's ends (launch f then holds
 // rows zlo + f and zhi - f) and the backward steps outside it take y_r = 0.
+//
+// Addresses default to a layer-local field: row r of layer q is row rb[q] + r
+// of base 0 (solution) and of base 1 (right-hand side).  `ad` overrides them:
+// ad->w(q, r) is the solution row, ad->b(q, r) the right-hand-side row and
+// ad->s(q, r) a scale the right-hand side is taken with (the forward step then
+// reads y_r = s Delta_r^-1 (b_r - (l_r / s) y_{r-1})).
+struct LocalAddr {
+  std::function<VecRef(size_t, int)> w, b;
+  std::function<double(size_t, int)> s;
+};
+
 void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vector<int>& rb,
                       std::vector<std::vector<Job>>& fw, std::vector<std::vector<Job>>& bw,
                       const std::vector<int>& rmin = {}, const std::vector<int>& rmax = {},
-                      const std::vector<int>& zlo = {}, const std::vector<int>& zhi = {}) {
+                      const std::vector<int>& zlo = {}, const std::vector<int>& zhi = {},
+                      const LocalAddr* ad = nullptr) {
   const int NX = S->NX;
   int F = 0, G = 0;
   auto win = [&](size_t q, const Layer& y, int& a, int& b) {  // the window, widened to hold the middle row
@@ -319,7 +332,11 @@ void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vecto
   }
   fw.assign(F + 1, {});
   bw.assign(G, {});
-  auto row = [&](size_t q, int r) { return (int64_t)(rb[q] + r) * NX; };
+  auto W = [&](size_t q, int r) { return ad ? ad->w(q, r) : vr(0, (int64_t)(rb[q] + r) * NX); };
+  auto B = [&](size_t q, int r) { return ad ? ad->b(q, r) : vr(1, (int64_t)(rb[q] + r) * NX); };
+  auto sc = [&](size_t q, int r) { return ad ? ad->s(q, r) : 1.0; };
+  // beta -c / s of a coupling c on a right-hand side taken with scale s
+  auto cb = [&](cd c, double sv) { return make_double2(-c.re / sv, -c.im / sv); };
   for (size_t q = 0; q < ls.size(); ++q) {
     const int l = ls[q];
     const Layer& y = S->lay[l];
@@ -329,46 +346,52 @@ void build_local_jobs(pt_solver* S, const std::vector<int>& ls, const std::vecto
     win(q, y, a, b);
     for (int r = a; r < m; ++r) {  // top-down from the window's top
       Job j = empty_job();
-      j.Y = vr(0, row(q, r));
+      j.Y = W(q, r);
+      const double sv = sc(q, r);
+      j.alpha = make_double2(sv, 0.0);
       if (r > a)
-        add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r - 1)), d2(-S->lcoef[y.rowbase + r]));
+        add_term(j, S->dinv(l, r), B(q, r), W(q, r - 1), cb(S->lcoef[y.rowbase + r], sv));
       else
-        add_term(j, S->dinv(l, r), vr(1, row(q, r)));
+        add_term(j, S->dinv(l, r), B(q, r));
       fw[r - a].push_back(j);
     }
     for (int r = b; r > m; --r) {  // bottom-up from the window's bottom
       Job j = empty_job();
-      j.Y = vr(0, row(q, r));
+      j.Y = W(q, r);
+      const double sv = sc(q, r);
+      j.alpha = make_double2(sv, 0.0);
       if (r < b)
-        add_term(j, S->dinv(l, r), vr(1, row(q, r)), vr(0, row(q, r + 1)), d2(-S->ucoef[y.rowbase + r]));
+        add_term(j, S->dinv(l, r), B(q, r), W(q, r + 1), cb(S->ucoef[y.rowbase + r], sv));
       else
-        add_term(j, S->dinv(l, r), vr(1, row(q, r)));
+        add_term(j, S->dinv(l, r), B(q, r));
       fw[b - r].push_back(j);
     }
     {  // middle row
       Job j = empty_job();
-      j.Y = vr(0, row(q, m));
+      j.Y = W(q, m);
+      const double sv = sc(q, m);
+      j.alpha = make_double2(sv, 0.0);
       if (m > a)
-        add_term(j, S->dinv(l, m), vr(1, row(q, m)), vr(0, row(q, m - 1)), d2(-S->lcoef[y.rowbase + m]));
+        add_term(j, S->dinv(l, m), B(q, m), W(q, m - 1), cb(S->lcoef[y.rowbase + m], sv));
       else
-        add_term(j, S->dinv(l, m), vr(1, row(q, m)));
-      if (m < b) add_term(j, S->dinv(l, m), none(), vr(0, row(q, m + 1)), d2(-S->ucoef[y.rowbase + m]));
+        add_term(j, S->dinv(l, m), B(q, m));
+      if (m < b) add_term(j, S->dinv(l, m), none(), W(q, m + 1), cb(S->ucoef[y.rowbase + m], sv));
       fw[F].push_back(j);
     }
     for (int r = m - 1; r >= lo; --r) {  // outward, upper part
       Job j = empty_job();
-      j.Y = vr(0, row(q, r));
+      j.Y = W(q, r);
       if (r >= a) j.P = j.Y;  // y_r = 0 above the window
       j.alpha = d2(-S->ucoef[y.rowbase + r]);
-      add_term(j, S->dinv(l, r), vr(0, row(q, r + 1)));
+      add_term(j, S->dinv(l, r), W(q, r + 1));
       bw[m - 1 - r].push_back(j);
     }
     for (int r = m + 1; r <= hi; ++r) {  // outward, lower part
       Job j = empty_job();
-      j.Y = vr(0, row(q, r));
+      j.Y = W(q, r);
       if (r <= b) j.P = j.Y;  // z_r = 0 below the window
       j.alpha = d2(-S->lcoef[y.rowbase + r]);
-      add_term(j, S->dinv(l, r), vr(0, row(q, r - 1)));
+      add_term(j, S->dinv(l, r), W(q, r - 1));
       bw[r - m - 1].push_back(j);
     }
   }
@@ -835,6 +858,84 @@ pt_status extract_blocks(pt_solver* S) {
   return rc;
 }
 
+// Reconstruction jobs that address the volume fields in place (no copies in
+// or out of a layer-local field): the owned rows of layer l are rows
+// own_start.. of the output u (base 1) and of the sources f (base 2, taken
+// with the scale h^2), all with the column stride NZ NX of those fields.  The
+// only other rows a reconstruction touches are the extension rows 0 and n+1
+// (solution rows 2l and 2l + 1 of a scratch field, base 0) and the forced
+// right-hand-side rows 0, 1, n, n+1 (rows 2L + e of the same scratch field,
+// one per forcing entry e, written by launch_rec_rhs).  Not built when the
+// scratch rows do not fit NZ rows.
+void build_direct_reconstruction(pt_solver* S, const std::vector<int>& lo, const std::vector<int>& hi,
+                                 const std::vector<int>& zlo, const std::vector<int>& zhi) {
+  const int L = S->L, NX = S->NX;
+  S->fwd_rec.clear();
+  S->bwd_rec2.clear();
+  S->rec_direct = false;
+  // forcing entries (interface k, segment t_a, layer, local row, sign): as the trace map's
+  std::vector<int32_t> hdst, hsrc, hseg;
+  std::vector<double> hsg;
+  std::map<std::pair<int, int>, int> trow;  // (layer, local row) -> scratch row of its right-hand side
+  auto add = [&](int k, int a, int l, int r, double sg) {
+    const Layer& y = S->lay[l];
+    const int e = (int)hdst.size();
+    trow[{l, r}] = 2 * L + e;
+    hdst.push_back(2 * L + e);
+    const bool owned = r >= y.top_ext && r < y.top_ext + y.n;
+    hsrc.push_back(owned ? y.own_start + r - y.top_ext : -1);
+    hseg.push_back(k * 2 + a);
+    hsg.push_back(sg);
+  };
+  for (int k = 0; k + 1 < L; ++k) {
+    const Layer& up = S->lay[k];
+    const Layer& dn = S->lay[k + 1];
+    add(k, 0, k, up.rn1, -1.0);  // layer k, bottom interface: - e_{n+1} t_0 + e_n t_1
+    add(k, 1, k, up.rn, 1.0);
+    add(k, 0, k + 1, dn.r1, 1.0);  // layer k+1, top interface: + e_1 t_0 - e_0 t_1
+    add(k, 1, k + 1, dn.r0, -1.0);
+  }
+  if (2 * L + (int)hdst.size() > S->NZ) return;
+  bool bad = false;
+  const double h2 = S->h * S->h;
+  LocalAddr ad;
+  ad.w = [&](size_t q, int r) -> VecRef {
+    const Layer& y = S->lay[q];
+    if (r >= y.top_ext && r < y.top_ext + y.n) return vr(1, (int64_t)(y.own_start + r - y.top_ext) * NX);
+    if (r == y.r0) return vr(0, (int64_t)(2 * q) * NX);
+    if (r == y.rn1) return vr(0, (int64_t)(2 * q + 1) * NX);
+    bad = true;
+    return none();
+  };
+  ad.b = [&](size_t q, int r) -> VecRef {
+    const auto it = trow.find({(int)q, r});
+    if (it != trow.end()) return vr(0, (int64_t)it->second * NX);
+    const Layer& y = S->lay[q];
+    if (r >= y.top_ext && r < y.top_ext + y.n) return vr(2, (int64_t)(y.own_start + r - y.top_ext) * NX);
+    bad = true;
+    return none();
+  };
+  ad.s = [&](size_t q, int r) { return trow.count({(int)q, r}) ? 1.0 : h2; };
+  std::vector<int> ls(L), rb(L, 0);
+  for (int l = 0; l < L; ++l) ls[l] = l;
+  std::vector<std::vector<Job>> fw, bw;
+  build_local_jobs(S, ls, rb, fw, bw, lo, hi, zlo, zhi, &ad);
+  if (bad) return;
+  if (!hdst.empty() && (S->rr_dst.alloc(hdst.size()) != hipSuccess || S->rr_src.alloc(hsrc.size()) != hipSuccess ||
+                        S->rr_seg.alloc(hseg.size()) != hipSuccess || S->rr_sign.alloc(hsg.size()) != hipSuccess ||
+                        hipMemcpy(S->rr_dst.p, hdst.data(), hdst.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                        hipMemcpy(S->rr_src.p, hsrc.data(), hsrc.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                        hipMemcpy(S->rr_seg.p, hseg.data(), hseg.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                        hipMemcpy(S->rr_sign.p, hsg.data(), hsg.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
+    return;
+  for (auto& v : fw)
+    if (!v.empty()) S->fwd_rec.push_back(push_launch(S, v, PT_CLS_LOCAL));
+  for (auto& v : bw)
+    if (!v.empty()) S->bwd_rec2.push_back(push_launch(S, v, PT_CLS_LOCAL));
+  S->n_rec_rhs = (int)hdst.size();
+  S->rec_direct = true;
+}
+
 void build_online_jobs(pt_solver* S) {
   const int L = S->L, NX = S->NX;
   S->hjobs.clear();
@@ -1004,6 +1105,7 @@ void build_online_jobs(pt_solver* S) {
           index_layers(S, dst.back());
         }
     }
+    build_direct_reconstruction(S, lo_rec, hi_rec, zlo, zhi);
   }
   if (L < 2) return;
   const double2 one = make_double2(1.0, 0.0);
@@ -1381,6 +1483,18 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
 }
 
 pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2* u, int nrhs) {
+  const int64_t nv = (int64_t)nrhs * S->NZ * S->NX;
+  const bool overlap = f < u + nv && u < f + nv;  // u written in place while f is read: keep them apart
+  if (S->rec_direct && !overlap && (x || S->n_rec_rhs == 0)) {
+    const int64_t ld = (int64_t)S->NZ * S->NX;
+    if (S->n_rec_rhs > 0)
+      HIPCHK(launch_rec_rhs(S->W.p, f, x, S->rr_dst.p, S->rr_src.p, S->rr_seg.p, S->rr_sign.p, S->n_rec_rhs, S->NX, ld,
+                            S->Nt, (int64_t)2 * (S->L - 1) * S->NX, S->h * S->h, nrhs, S->st));
+    Bases b{{S->W.p, u, const_cast<double2*>(f), nullptr}};
+    for (const Launch& Lc : S->fwd_rec) PTCHK(run_apply(S, Lc, nrhs, ld, b));
+    for (const Launch& Lc : S->bwd_rec2) PTCHK(run_apply(S, Lc, nrhs, ld, b));
+    return PT_OK;
+  }
   HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
   if (S->L >= 2)
     HIPCHK(launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
@@ -1533,6 +1647,10 @@ void pt_free(pt_solver* S) {
   S->gsum_src.release();
   S->gsum_cnt.release();
   S->nz_list.release();
+  S->rr_dst.release();
+  S->rr_src.release();
+  S->rr_seg.release();
+  S->rr_sign.release();
   S->nz_in_k.release();
   S->nz_in_off.release();
   for (auto* b : {&S->nrm, &S->cs, &S->est, &S->beta, &S->f_sign, &S->g_sign}) b->release();

@@ -175,6 +175,12 @@ struct pt_solver {
   std::vector<Launch> fwd, bwd, sweep;
   std::vector<Launch> bwd_pre, bwd_rec;  // backward passes stopped at the trace rows / the owned rows
   std::vector<Launch> fwd_win;           // forward passes of right-hand sides zero outside the trace rows 0..n+1
+  // reconstruction on the volume fields in place (no layer-local copies)
+  std::vector<Launch> fwd_rec, bwd_rec2;
+  bool rec_direct = false;
+  int n_rec_rhs = 0;  // forced right-hand-side rows
+  DevBuf<int32_t> rr_dst, rr_src, rr_seg;
+  DevBuf<double> rr_sign;
   Launch bterm, opA, opR;
   Launch opA2;  // second launch of A in the extrapolated form (njobs 0: A is one launch)
 

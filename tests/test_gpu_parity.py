@@ -98,6 +98,27 @@ def test_reconstruct(small):
     assert rel(u, ps.reconstruct(f, x)) < 1e-10
 
 
+def test_reconstruct_in_place_and_aliased(small):
+    """The reconstruction addresses f and u in place; with u overlapping f
+    (the C-ABI allows one buffer for both) it takes copies first."""
+    import ctypes as C
+    import torch
+    prob, f, gs, ps = small
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(ps.zeros(3).shape) + 1j * rng.standard_normal(ps.zeros(3).shape)
+    ref = ps.reconstruct(f, x)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ud = gs.reconstruct(fd, xd)  # device arrays: f and u distinct
+    assert rel(ud.cpu().numpy(), ref) < 1e-10
+    assert torch.equal(fd.cpu(), torch.from_numpy(np.ascontiguousarray(f)))  # f left untouched
+    buf = fd.clone()
+    rc = gs._lib.pt_reconstruct(gs._h, f.shape[0], C.c_void_p(buf.data_ptr()), C.c_void_p(xd.data_ptr()),
+                                C.c_void_p(buf.data_ptr()), 1)
+    assert rc == 0
+    assert rel(buf.cpu().numpy(), ref) < 1e-10
+
+
 def test_solve_small_matches_direct(small):
     prob, f, gs, ps = small
     u, info = gs.solve(f)
