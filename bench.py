@@ -240,6 +240,41 @@ def roofline(form):
     return r
 
 
+def run_spectral(P, torch, cpu=True):
+    """Spectral diagnostics: D^-1 A assembled on the GPU (the library's applies on
+    unit vectors) for a homogeneous medium at three PML widths and the cavity
+    medium at three frequencies; eigenvalue cluster summaries, the GPU
+    assembly time and, as the CPU baseline of this row, the oracle's time for
+    the same assembly on the host."""
+    import numpy as np
+    import synth
+    from paper_1410_5910_amd import spectral
+    cases = [("homogeneous", synth.homogeneous_problem(32, p, L=3)) for p in (4, 8, 16)] + \
+            [("cavity", synth.cavity_problem(64, w, npml=8, L=4)) for w in (8.0, 16.0, 32.0)]
+    out = []
+    for kind, prob in cases:
+        s = P.Solver.from_problem(prob, max_nrhs=64, tol=1e-10, maxit=60)
+        spectral.operator_matrix(s, "DinvA")  # warm-up
+        t0 = time.perf_counter()
+        M = spectral.operator_matrix(s, "DinvA")
+        t_gpu = time.perf_counter() - t0
+        ev = np.linalg.eigvals(M.cpu().numpy())
+        s.close()
+        row = {"case": prob.name, "kind": kind, "ntrace": int(M.shape[0]), "gpu_assembly_ms": 1e3 * t_gpu}
+        if cpu:  # CPU baseline leg: the oracle's dense assembly of the same operator
+            from oracle.polarized import PolarizedSolver
+            ps = PolarizedSolver(prob)
+            t0 = time.perf_counter()
+            ps.dense("Dinv") @ ps.dense("A")
+            row["cpu_baseline_assembly_ms"] = 1e3 * (time.perf_counter() - t0)
+        row.update(spectral.cluster_summary(ev))
+        log(f"  spectral {prob.name}: max|lambda-1| {row['max_dist_from_1']:.3g}, {row['outside']} outside 0.2, "
+            f"assembly {row['gpu_assembly_ms']:.1f} ms GPU" +
+            (f" / {row['cpu_baseline_assembly_ms']:.0f} ms oracle" if cpu else ""))
+        out.append(row)
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -271,6 +306,9 @@ def main():
     ap.add_argument("--all-forms", action="store_true",
                     help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
+    ap.add_argument("--spectral", action="store_true",
+                    help="also the spectral diagnostics of D^-1 A (homogeneous medium vs PML width, resonant "
+                         "cavity vs frequency); on with --all-forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
@@ -369,6 +407,11 @@ def main():
                     f"{form['rel_err_vs_oracle']:.2e}")
                 forms.append(form)
 
+    spec = None
+    if args.spectral or args.all_forms:
+        log("spectral diagnostics")
+        spec = run_spectral(P, torch, cpu=not args.no_cpu)
+
     f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"]
     out = {
         "metric": METRIC, "value": chosen["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -388,6 +431,8 @@ def main():
         "vs_fp64_same_workload": (chosen["solves_per_s"] / f64_same[0]["solves_per_s"]) if f64_same else None,
         "forms": [{kk: vv for kk, vv in fm.items() if kk not in ("kernel", "roofline")} for fm in forms],
     }
+    if spec is not None:
+        out["spectral"] = spec
     if not args.no_cpu:
         log("cpu baseline (oracle direct solve, about 10 s)")
         rate, nsol, el = oracle.baseline(f[:1])

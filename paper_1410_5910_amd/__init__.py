@@ -1,7 +1,9 @@
 """MI355X-native online solver of the method of polarized traces (2D Helmholtz).
 
 The compute path is libpolar.so (HIP for gfx950, C-ABI in include/polar.h);
-``polar`` is its thin Python binding and ``build`` compiles it in-tree.
+``polar`` is its thin Python binding and ``build`` compiles it in-tree;
+``spectral`` assembles the preconditioned operator on the GPU for eigenvalue
+diagnostics.
 """
 from .polar import Solver, Learned, PolarError, lib, solve_batch, OP_A, OP_R, OP_DINV, OP_PRECOND, EXPORTS  # noqa: F401
 

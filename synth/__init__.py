@@ -32,6 +32,9 @@ __all__ = [
     "config_small",
     "bump_medium",
     "layered_medium",
+    "homogeneous_problem",
+    "cavity_medium",
+    "cavity_problem",
 ]
 
 
@@ -286,3 +289,37 @@ def learned_model(index: int, n: int = 256, L: int = 8, npml: int = 20, nrhs: in
     for j in range(nrhs):
         f[j] = gaussian_source(prob, xs[j], zs[j], sig)
     return prob, f
+
+
+def homogeneous_problem(n: int = 32, npml: int = 8, L: int = 3, ppw: float = 10.0) -> Problem:
+    """c = 1 on [0, 1]^2 (n x n nodes, h = 1/n), ppw points per wavelength, npml-point PML.
+
+    The spectral workload for PML quality: with no heterogeneity every
+    reflection comes from the truncation of the PML.
+    """
+    h = 1.0 / n
+    c = normal_extend(np.ones((n, n)), npml)
+    return Problem(f"homogeneous-{n}-pml{npml}-L{L}", n, n, npml, h, 2 * math.pi / (ppw * h), L, _pml_C(c), c,
+                   meta={"ppw": ppw})
+
+
+def cavity_medium(n: int, c_red: float = 5.0) -> np.ndarray:
+    """A resonant wave-guide on [0, 1]^2 (n x n nodes, h = 1/n): smooth background
+    c = 1 + 0.1 x + 0.1 z and a ring of speed c_red (radii 0.18-0.30 around the
+    centre) with a 60-degree opening facing +x.  The ring shape is invented for
+    this workload; only the background and c_red follow the cavity experiment.
+    """
+    h = 1.0 / n
+    X, Z = _phys_coords(n, n, h)
+    c = 1.0 + 0.1 * X + 0.1 * Z
+    r = np.hypot(X - 0.5, Z - 0.5)
+    ang = np.arctan2(Z - 0.5, X - 0.5)
+    ring = (r > 0.18) & (r < 0.30) & (np.abs(ang) > math.pi / 6)
+    return np.where(ring, c_red, c)
+
+
+def cavity_problem(n: int = 64, omega: float = 16.0, npml: int = 8, L: int = 4, c_red: float = 5.0) -> Problem:
+    """The cavity medium of `cavity_medium` at angular frequency omega, L layers."""
+    c = normal_extend(cavity_medium(n, c_red), npml)
+    return Problem(f"cavity-{n}-w{omega:g}-L{L}", n, n, npml, 1.0 / n, float(omega), L, _pml_C(c), c,
+                   meta={"c_red": c_red})
