@@ -234,13 +234,16 @@ class PolarizedSolver:
         return u, hist
 
     # ---------------------------------------------------------------- FGMRES
-    def fgmres(self, s: np.ndarray, tol: float = 1e-10, maxit: int = 50, precond=True):
+    def fgmres(self, s: np.ndarray, tol: float = 1e-10, maxit: int = 50, precond=True, op=None, prec=None):
         """Flexible right-preconditioned GMRES with modified Gram-Schmidt, x0 = 0, no restart.
 
-        Returns (x, info) with info a list of dicts per right-hand side:
-        iterations, residual history (least-squares estimates) and the true
-        relative residual ||s - A x|| / ||s||.
+        op / prec (default: this system's apply_A / precondition) select the
+        operator and the preconditioner.  Returns (x, info) with info a list of
+        dicts per right-hand side: iterations, residual history (least-squares
+        estimates) and the true relative residual ||s - A x|| / ||s||.
         """
+        apply_A = op or self.apply_A
+        precondition = prec or self.precondition
         nrhs = s.shape[0]
         shape = s.shape[1:]
         x = np.zeros_like(s)
@@ -257,9 +260,9 @@ class PolarizedSolver:
             hist = [1.0]
             y = np.zeros(0, dtype=np.complex128)
             for j in range(maxit):
-                z = self.precondition(V[j]) if precond else V[j].copy()
+                z = precondition(V[j]) if precond else V[j].copy()
                 Z.append(z)
-                w = self.apply_A(z)
+                w = apply_A(z)
                 for i in range(j + 1):
                     H[i, j] = np.vdot(V[i], w)
                     w = w - H[i, j] * V[i]
@@ -274,7 +277,7 @@ class PolarizedSolver:
                 V.append(w / H[j + 1, j])
             xr = sum(y[i] * Z[i] for i in range(len(y)))
             x[r] = xr[0]
-            true = np.linalg.norm(b - self.apply_A(xr)) / beta
+            true = np.linalg.norm(b - apply_A(xr)) / beta
             infos.append({"iters": len(y), "hist": hist, "relres": float(true)})
         return x, infos
 
