@@ -136,12 +136,14 @@ def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
     return out
 
 
-def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8):
-    """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form)."""
+def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8,
+             closure="jump"):
+    """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form,
+    closure of the polarized system)."""
     nrhs = f.shape[0]
     t0 = time.perf_counter()
     s = P.Solver.from_problem(prob, precision=precision, tol=tol, maxit=60, max_nrhs=nrhs,
-                              stream=stream.cuda_stream, plr=plr, plr_eps=1e-9)
+                              stream=stream.cuda_stream, plr=plr, plr_eps=1e-9, closure=closure)
     lay = s.layout()
     fd = torch.from_numpy(f).to("cuda:0")
     setup_s = time.perf_counter() - t0
@@ -159,7 +161,8 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     out = {"solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "nrhs": nrhs,
-           "precision": precision, "blocks": "plr eps 1e-9" if plr else "dense", "setup_s": setup_s,
+           "precision": precision, "blocks": "plr eps 1e-9" if plr else "dense", "closure": closure,
+           "setup_s": setup_s,
            "tune_s": tune_s, "tuned": tune_res,
            "iterations": sorted(set(i["iters"] for i in info)),
            "max_true_relres": max(i["relres"] for i in info), "block_bytes": lay["block_bytes"],
@@ -372,19 +375,22 @@ def main():
         if args.precision != "auto" or chosen is form:
             break
     if not args.no_forms:
-        have = {(fm["workload"], fm["precision"], False) for fm in forms}
-        extra = [(args.workload, "f64", False)]
+        have = {(fm["workload"], fm["precision"], False, "jump") for fm in forms}
+        extra = [(args.workload, "f64", False, "jump")]
         if args.all_forms:
-            extra += [(args.workload, "f32", False)] + \
-                [("bumps440", p, False) for p in ("f64", "f32", "split-bf16")] + [("bumps440", "f64", True)]
+            extra += [(args.workload, "f32", False, "jump")] + \
+                [(args.workload, p, False, "extrap") for p in ("split-bf16", "f64")] + \
+                [("bumps440", p, False, "jump") for p in ("f64", "f32", "split-bf16")] + \
+                [("bumps440", "f64", True, "jump")]
         orcs = {}
-        for wl, prec, plr in extra:
-            if (wl, prec, plr) in have or (wl == args.workload and args.nrhs):
+        for wl, prec, plr, clo in extra:
+            if (wl, prec, plr, clo) in have or (wl == args.workload and args.nrhs):
                 continue
             pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
-            log(f"form {wl} {prec}{' plr' if plr else ''}")
+            log(f"form {wl} {prec}{' plr' if plr else ''}{' extrapolation closure' if clo == 'extrap' else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
-                               args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol)
+                               args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol,
+                               closure=clo)
             form["workload"] = wl
             rf = roofline(form)
             form["roofline_dominant_class"] = {kk: rf[kk] for kk in ("class", "kernel", "bound", "achieved", "unit",
@@ -398,7 +404,7 @@ def main():
                 form["rel_err_vs_oracle"] = max(orc.errors(fw, u, min(k or 1, fw.shape[0])))
             log(f"  {form['solves_per_s']:.1f} solves/s, rel err {form.get('rel_err_vs_oracle', float('nan')):.2e}")
             forms.append(form)
-            have.add((wl, prec, plr))
+            have.add((wl, prec, plr, clo))
         if args.all_forms:
             for prec in ("split-bf16", "f64"):
                 log(f"form uneven8 {prec}: 8 problems x 32 sources, one pt_solve_batch per step")
@@ -412,7 +418,8 @@ def main():
         log("spectral diagnostics")
         spec = run_spectral(P, torch, cpu=not args.no_cpu)
 
-    f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"]
+    f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"
+                and fm.get("closure", "jump") == "jump"]
     out = {
         "metric": METRIC, "value": chosen["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "higher_is_better": True, "scaling": "weak",

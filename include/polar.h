@@ -116,10 +116,21 @@ typedef struct {
                         to the layer), one launch instead of ~R dependent ones;
                         float64 factors only; PT_ENOMEM if they do not fit.
                         2: kept when they take at most a third of the free
-                        device memory at setup (and float64 factors), and used
-                        for pre-solves of at most 4 columns (sources, or the
-                        per-layer source slots of sparse sources); wider ones
-                        take the local solves.                                 */
+                        device memory at setup (and float64 factors); used for
+                        every pre-solve (passes of more than 4 columns split
+                        each product over row ranges).                         */
+  int32_t closure;   /* how the polarized system is closed (Section 3.4).
+                        0: jump conditions (Def. 9) with the Gauss-Seidel
+                        preconditioner of its splitting (Alg. 4).  1: the
+                        extrapolation relations (Def. polarized_out_going):
+                        the rows at row n / row 1 are kept and the other row
+                        of each pair becomes u_{n+1} = E_down u_n,
+                        u_0 = E_up u_1, with the one-sided extrapolators taken
+                        from the stored factors (E_down = -l Sigma_{n+1}^-1,
+                        E_up = -u Delta_0^-1); Gauss-Seidel on its splitting
+                        (eq. splitting_out_going), D^-1 as the jump system's
+                        sweeps after one extrapolation step.  Same solution;
+                        float64 factors without PLR blocks only (PT_EINVAL).   */
 } pt_options;
 
 typedef struct {
@@ -186,7 +197,12 @@ typedef enum {
   PT_OP_A = 0,       /* y = A x: polarized system closed by jump conditions (Def. 9) */
   PT_OP_R = 1,       /* y = R x, R = A - D (eq. def_permuted_system_jump)            */
   PT_OP_DINV = 2,    /* y = D^{-1} x: down sweep and up sweep (Section 4.1)          */
-  PT_OP_PRECOND = 3  /* y = M^{-1} x: Gauss-Seidel preconditioner, gs_iters (Alg. 4) */
+  PT_OP_PRECOND = 3, /* y = M^{-1} x: Gauss-Seidel preconditioner, gs_iters (Alg. 4) */
+  /* the same four for the system closed by extrapolation (closure = 1 only) */
+  PT_OP_A_EXTRAP = 4,
+  PT_OP_R_EXTRAP = 5,
+  PT_OP_DINV_EXTRAP = 6,
+  PT_OP_PRECOND_EXTRAP = 7
 } pt_op;
 
 /* y = op(x) on polarized trace vectors (nrhs, 2, L-1, 2, NX); L >= 2. */

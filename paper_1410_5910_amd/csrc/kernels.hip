@@ -1050,6 +1050,15 @@ __global__ void rec_rhs_kernel(double2* __restrict__ T, const double2* __restric
   T[(int64_t)r * ld + (int64_t)dst[e] * NX + i] = make_double2(v.x + sg * t.x, v.y + sg * t.y);
 }
 
+__global__ void zero_extrap_rows_kernel(double2* __restrict__ v, int L, int NX, int64_t ntrace) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NX) return;
+  const int k = blockIdx.y;
+  double2* col = v + (int64_t)blockIdx.z * ntrace;
+  col[(int64_t)((0 * (L - 1) + k) * 2 + 1) * NX + i] = make_double2(0.0, 0.0);  // down pair, row n+1
+  col[(int64_t)((1 * (L - 1) + k) * 2 + 0) * NX + i] = make_double2(0.0, 0.0);  // up pair, row 0
+}
+
 __global__ void identity_rhs_kernel(double2* W, const int32_t* rows, int nq, int n, int64_t ld) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
@@ -1378,6 +1387,13 @@ hipError_t launch_rec_rhs(double2* T, const double2* f, const double2* x, const 
   if (ne <= 0 || nrhs <= 0) return hipSuccess;
   hipLaunchKernelGGL(rec_rhs_kernel, dim3((NX + 127) / 128, ne, nrhs), dim3(128), 0, st, T, f, x, dst, src, seg, sign,
                      NX, ld, ntrace, half, h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_extrap_rows(double2* v, int L, int NX, int64_t ntrace, int nrhs, hipStream_t st) {
+  if (L < 2 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_extrap_rows_kernel, dim3((NX + 127) / 128, L - 1, nrhs), dim3(128), 0, st, v, L, NX,
+                     ntrace);
   return hipGetLastError();
 }
 

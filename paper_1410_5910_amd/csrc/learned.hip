@@ -429,7 +429,7 @@ pt_status learned_step(pt_solver* S, const double2* v, double2* z, double2* w, i
   const int L1 = S->L - 1, n = S->NX, B = nrhs * L1;
   const int64_t tot = (int64_t)nrhs * S->Nt;
   hipStream_t st = S->st;
-  PTCHK(apply_op(S, S->opA, z, w, nrhs));              // w = A z
+  PTCHK(system_A(S, z, w, nrhs));                      // w = A z
   HIPCHK(launch_add(N->rh.p, v, w, -1.0, tot, st));    // r = v - A z
   hipLaunchKernelGGL(pack_kernel, dim3(B), dim3(kThreadsL), 0, st, (const double2*)N->rh.p, N->act[0].p, N->scale.p,
                      L1, n, 0);
@@ -443,7 +443,7 @@ pt_status learned_step(pt_solver* S, const double2* v, double2* z, double2* w, i
   hipLaunchKernelGGL(unpack_add_kernel, dim3(B), dim3(kThreadsL), 0, st, N->act[kLayers].p, N->scale.p, N->cv.p, L1,
                      n, N->flag.p);
   HIPCHK(hipGetLastError());
-  PTCHK(apply_op(S, S->opA, N->cv.p, N->ac.p, nrhs));  // A c
+  PTCHK(system_A(S, N->cv.p, N->ac.p, nrhs));          // A c
   HIPCHK(launch_knorm(N->rh.p, N->nr.p, nrhs, S->Nt, st));
   HIPCHK(launch_add(N->rh.p, N->rh.p, N->ac.p, -1.0, tot, st));  // r - A c
   HIPCHK(launch_knorm(N->rh.p, N->nt.p, nrhs, S->Nt, st));
@@ -637,8 +637,8 @@ pt_status pt_learned_collect(pt_learned* N, pt_solver* S, int32_t nrhs, const do
   for (int j = 0; j < J && rc == PT_OK; ++j) {
     const double2* vj = vs.p + (size_t)j * nrhs * Nt;
     // r = v - A GS(v) becomes the right-hand side of a tight trace solve for e = A^-1 r
-    rc = precondition(S, vj, gs.p, nrhs);
-    if (rc == PT_OK) rc = apply_op(S, S->opA, gs.p, S->tmp.p, nrhs);
+    rc = system_M(S, vj, gs.p, nrhs);
+    if (rc == PT_OK) rc = system_A(S, gs.p, S->tmp.p, nrhs);
     if (rc != PT_OK) break;
     if (!hchk(launch_add(S->s.p, vj, S->tmp.p, -1.0, (int64_t)nrhs * Nt, st))) break;
     float* Xo = N->X.p + (size_t)N->count * 8 * n;

@@ -101,6 +101,9 @@ hipError_t launch_sum_rows(double2* W, int64_t ld, int NX, const int32_t* dst, c
 // stride >= 1 + ceil(kk[e] / kNzChunk) for every e.
 hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const int64_t* off, const int32_t* kk,
                                  int nentries, int32_t* list, int stride, hipStream_t st);
+// Zeroes the extrapolation rows of polarized vectors (nrhs, 2, L-1, 2, NX),
+// column stride ntrace: row n+1 of every down pair and row 0 of every up pair.
+hipError_t launch_zero_extrap_rows(double2* v, int L, int NX, int64_t ntrace, int nrhs, hipStream_t st);
 // Forced right-hand-side rows of an in-place reconstruction: for entries e <
 // ne and right-hand sides r < nrhs, row dst[e] of T = h2 f(row src[e]) (0 if
 // src[e] < 0) + sign[e] (x + x[half])(segment seg[e]); T and f have column

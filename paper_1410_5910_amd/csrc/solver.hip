@@ -220,6 +220,9 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
     if (o->plr_rmax < 0 || o->plr_rmax > kPlrMaxRank) return fail(PT_EINVAL, "plr_rmax must be in 0..64");
   }
   if (o->presolve < 0 || o->presolve > 2) return fail(PT_EINVAL, "presolve must be 0, 1 or 2");
+  if (o->closure < 0 || o->closure > 1) return fail(PT_EINVAL, "closure must be 0 (jump) or 1 (extrapolation)");
+  if (o->closure == 1 && (o->precision == PT_F32 || o->plr))
+    return fail(PT_EINVAL, "the extrapolation closure needs float64 factors without PLR blocks");
   return PT_OK;
 }
 
@@ -936,6 +939,126 @@ void build_direct_reconstruction(pt_solver* S, const std::vector<int>& lo, const
   S->rec_direct = true;
 }
 
+// The system closed by extrapolation relations (Section 3.4, Def.
+// polarized_out_going), unknowns as in the jump system.  Per interface k the
+// rows at row n of layer k and row 1 of layer k+1 are the jump system's (the
+// regularised integral equations); the other row of each pair is an
+// extrapolation relation with the one-sided extrapolators of Def. extrapolator,
+// E_down = -l Sigma_{n+1}^-1 (layer k) and E_up = -u Delta_0^-1 (layer k+1),
+// the layers' one-row Schur complements (l, u the couplings of those rows):
+//   y_dn(k, n+1) = d_k(n+1) - E_down d_k(n),   y_up(k, 0) = a_k(0) - E_up a_k(1).
+// D (eq. splitting_out_going) keeps the couplings within a polarization and R
+// the rest, so R's extrapolation rows vanish and its other rows are the jump
+// system's R rows.  Since E_down K_{n,j} = K_{n+1,j} for the sources above row n
+// (Lemma extrapolator_def), D^-1 = D_jump^-1 T with T the one-step
+// extrapolation r_dn(n+1) += E_down r_dn(n), r_up(0) += E_up r_up(1).
+// Launches: opX + opX2 (bases 0 = x, 2 = y: the integral rows, the
+// extrapolation rows), opRX (y = R x
+// on the two rows it has), gsRX (cur = v - R prev: bases 0 = v, 1 = prev,
+// 2 = cur; the split planes in the mixed form), tX (T in place on base 2).
+void build_extrap_jobs(pt_solver* S) {
+  const int L = S->L;
+  const double2 one = make_double2(1.0, 0.0);
+  std::vector<Job> jx, jx2, jr, jg, jt;
+  for (int k = 0; k <= L - 2; ++k) {
+    const Layer& ya = S->lay[k];
+    const Layer& yb = S->lay[k + 1];
+    const cd l = S->lcoef[ya.rowbase + ya.rn1];
+    const cd uc = S->ucoef[yb.rowbase + yb.r0];
+    const void* Sg = S->dinv(k, ya.rn1);      // Sigma_{n+1}^-1 of layer k
+    const void* Dl = S->dinv(k + 1, yb.r0);   // Delta_0^-1 of layer k+1
+    // A, row n of the down pair: d_k(n) + a_k(n) - T_dn(k)(d + a)_{k-1} - (B_up(k) - J0) a_k
+    {
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(0, k, 0));
+      j.P = vr(0, S->seg(0, k, 0));
+      j.alpha = make_double2(-1.0, 0.0);
+      if (k >= 1)
+        for (int b = 0; b < 2; ++b)
+          add_term(j, S->blk_term(k, T_DN, 0, b), vr(0, S->seg(0, k - 1, b)), vr(0, S->seg(1, k - 1, b)), one);
+      for (int b = 0; b < 2; ++b) add_term(j, S->blk_term(k, B_UP, 0, b), vr(0, S->seg(1, k, b)));
+      jx.push_back(j);
+    }
+    // A, row 1 of the up pair: a_k(1) + d_k(1) - T_up(k+1)(a + d)_{k+1} - (B_dn(k+1) - J1) d_k
+    {
+      Job u = empty_job();
+      u.Y = vr(2, S->seg(1, k, 1));
+      u.P = vr(0, S->seg(1, k, 1));
+      u.alpha = make_double2(-1.0, 0.0);
+      if (k + 1 <= L - 2)
+        for (int b = 0; b < 2; ++b)
+          add_term(u, S->blk_term(k + 1, T_UP, 1, b), vr(0, S->seg(1, k + 1, b)), vr(0, S->seg(0, k + 1, b)), one);
+      for (int b = 0; b < 2; ++b) add_term(u, S->blk_term(k + 1, B_DN, 1, b), vr(0, S->seg(0, k, b)));
+      jx.push_back(u);
+    }
+    // A, extrapolation rows: d_k(n+1) + l Sigma^-1 d_k(n), a_k(0) + u Delta^-1 a_k(1)
+    {
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(0, k, 1));
+      j.P = vr(0, S->seg(0, k, 1));
+      j.alpha = d2(l);
+      add_term(j, Sg, vr(0, S->seg(0, k, 0)));
+      jx2.push_back(j);
+      Job u = empty_job();
+      u.Y = vr(2, S->seg(1, k, 0));
+      u.P = vr(0, S->seg(1, k, 0));
+      u.alpha = d2(uc);
+      add_term(u, Dl, vr(0, S->seg(1, k, 1)));
+      jx2.push_back(u);
+    }
+    // R rows (0, k, n) and (1, k, 1): -(T_dn(k) a_{k-1} + (B_up(k) - J0) a_k), likewise up
+    for (int gs = 0; gs < 2; ++gs) {
+      // gs = 0: y = R x (bases 0 = x, 2 = y); gs = 1: cur = v - R prev (0 = v, 1 = prev, 2 = cur)
+      const int xin = gs ? 1 : 0;
+      auto term = [&](int l_, int type, int a, int b) { return gs ? S->blk_pre(l_, type, a, b) : S->blk_term(l_, type, a, b); };
+      // R's rows are -(T a + (B - J) a): y = R x takes alpha -1, cur = v - R prev alpha +1
+      const double2 al = make_double2(gs ? 1.0 : -1.0, 0.0);
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(0, k, 0));
+      j.P = gs ? vr(0, S->seg(0, k, 0)) : none();
+      j.alpha = al;
+      if (k >= 1)
+        for (int b = 0; b < 2; ++b) add_term(j, term(k, T_DN, 0, b), vr(xin, S->seg(1, k - 1, b)));
+      for (int b = 0; b < 2; ++b) add_term(j, term(k, B_UP, 0, b), vr(xin, S->seg(1, k, b)));
+      Job u = empty_job();
+      u.Y = vr(2, S->seg(1, k, 1));
+      u.P = gs ? vr(0, S->seg(1, k, 1)) : none();
+      u.alpha = al;
+      if (k + 1 <= L - 2)
+        for (int b = 0; b < 2; ++b) add_term(u, term(k + 1, T_UP, 1, b), vr(xin, S->seg(0, k + 1, b)));
+      for (int b = 0; b < 2; ++b) add_term(u, term(k + 1, B_DN, 1, b), vr(xin, S->seg(0, k, b)));
+      (gs ? jg : jr).push_back(j);
+      (gs ? jg : jr).push_back(u);
+    }
+    // T in place: c_dn(n+1) -= l Sigma^-1 c_dn(n), c_up(0) -= u Delta^-1 c_up(1)
+    // (a preconditioner step: the split-bfloat16 planes of the two factors in the mixed form)
+    {
+      const size_t E = split_block_elems(S->NX);
+      const void* Tsg = S->split ? (const void*)(S->xbf.p + (size_t)(2 * k) * E) : Sg;
+      const void* Tdl = S->split ? (const void*)(S->xbf.p + (size_t)(2 * k + 1) * E) : Dl;
+      Job j = empty_job();
+      j.Y = vr(2, S->seg(0, k, 1));
+      j.P = j.Y;
+      j.alpha = d2(-l);
+      add_term(j, Tsg, vr(2, S->seg(0, k, 0)));
+      jt.push_back(j);
+      Job u = empty_job();
+      u.Y = vr(2, S->seg(1, k, 0));
+      u.P = u.Y;
+      u.alpha = d2(-uc);
+      add_term(u, Tdl, vr(2, S->seg(1, k, 1)));
+      jt.push_back(u);
+    }
+  }
+  // the integral rows (four blocks each) and the extrapolation rows (one) in
+  // separate launches: mixed in one, the long jobs' tiles would set its length
+  S->opX = push_launch(S, jx, PT_CLS_OPERATOR);
+  S->opX2 = push_launch(S, jx2, PT_CLS_OPERATOR);
+  S->opRX = push_launch(S, jr, PT_CLS_OPERATOR);
+  S->gsRX = push_launch(S, jg, PT_CLS_REFLECT, true, true);
+  S->tX = push_launch(S, jt, PT_CLS_REFLECT, false, S->split);
+}
+
 void build_online_jobs(pt_solver* S) {
   const int L = S->L, NX = S->NX;
   S->hjobs.clear();
@@ -1229,6 +1352,7 @@ void build_online_jobs(pt_solver* S) {
       S->opR = push_launch(S, js, PT_CLS_OPERATOR, true);
     }
   }
+  if (S->opt.closure == 1) build_extrap_jobs(S);
   (void)NX;
 }
 
@@ -1330,6 +1454,46 @@ pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs) {
   return PT_OK;
 }
 
+// D^-1 of the extrapolation closure: the one-step extrapolation T, then the
+// jump system's sweeps (no previous iterate: base 1 = zeros)
+pt_status dinv_extrap_inplace(pt_solver* S, double2* c, int nrhs) {
+  Bases b{{nullptr, S->zeros.p, c, nullptr}};
+  PTCHK(run_apply(S, S->tX, nrhs, S->Nt, b));
+  for (const Launch& Lc : S->sweep) PTCHK(run_apply(S, Lc, nrhs, S->Nt, b));
+  return PT_OK;
+}
+
+// Gauss-Seidel on the extrapolation splitting (Alg. 4): u^{p} = D^-1 (v - R u^{p-1}), u^0 = 0
+pt_status precondition_extrap(pt_solver* S, const double2* v, double2* z, int nrhs) {
+  const int nit = S->opt.gs_iters;
+  const int64_t n = (int64_t)nrhs * S->Nt;
+  if (nit == 0) {
+    HIPCHK(launch_copy(z, v, n, S->st));
+    return PT_OK;
+  }
+  const double2* prev = nullptr;
+  for (int p = 1; p <= nit; ++p) {
+    double2* cur = (p == nit) ? z : ((p % 2) ? S->U1.p : S->U2.p);
+    HIPCHK(launch_copy(cur, v, n, S->st));  // rows R does not touch keep v
+    if (prev) {
+      Bases b{{const_cast<double2*>(v), const_cast<double2*>(prev), cur, nullptr}};
+      PTCHK(run_apply(S, S->gsRX, nrhs, S->Nt, b));
+    }
+    PTCHK(dinv_extrap_inplace(S, cur, nrhs));
+    prev = cur;
+  }
+  return PT_OK;
+}
+
+pt_status system_A(pt_solver* S, const double2* x, double2* y, int nrhs) {
+  if (S->opt.closure == 1) return apply_op(S, S->opX, x, y, nrhs);
+  return apply_op(S, S->opA, x, y, nrhs);
+}
+
+pt_status system_M(pt_solver* S, const double2* v, double2* z, int nrhs) {
+  return S->opt.closure == 1 ? precondition_extrap(S, v, z, nrhs) : precondition(S, v, z, nrhs);
+}
+
 pt_status apply_dinv(pt_solver* S, const double2* v, double2* z, int nrhs) {
   HIPCHK(launch_copy(z, v, (int64_t)nrhs * S->Nt, S->st));
   Bases b{{const_cast<double2*>(v), S->zeros.p, z, nullptr}};
@@ -1342,6 +1506,7 @@ pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y,
   PTCHK(run_apply(S, op, nrhs, S->Nt, b));
   // A in the extrapolated form: the second rows of each pair from the first
   if (&op == &S->opA && S->opA2.njobs > 0) PTCHK(run_apply(S, S->opA2, nrhs, S->Nt, b));
+  if (&op == &S->opX) PTCHK(run_apply(S, S->opX2, nrhs, S->Nt, b));
   return PT_OK;
 }
 
@@ -1563,12 +1728,12 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learne
     if (augment && (j & 1)) {
       PTCHK(learned_direction(S, zj, nrhs));
     } else {
-      PTCHK(precondition(S, vj, zj, nrhs));
+      PTCHK(system_M(S, vj, zj, nrhs));
     }
     if (learned && !augment) {
       PTCHK(learned_step(S, vj, zj, S->tmp.p, nrhs));
     } else {
-      PTCHK(apply_op(S, S->opA, zj, S->tmp.p, nrhs));
+      PTCHK(system_A(S, zj, S->tmp.p, nrhs));
       if (augment && !(j & 1)) PTCHK(learned_residual(S, vj, S->tmp.p, nrhs));
     }
     HIPCHK(launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st));
@@ -1647,6 +1812,7 @@ void pt_free(pt_solver* S) {
   S->gsum_src.release();
   S->gsum_cnt.release();
   S->nz_list.release();
+  S->xbf.release();
   S->rr_dst.release();
   S->rr_src.release();
   S->rr_seg.release();
@@ -2036,6 +2202,19 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
         hipStreamSynchronize(S->st) != hipSuccess)
       return bail(fail(PT_EHIP, "split-bfloat16 conversion"));
     S->split = true;
+    // the one-sided extrapolators of the extrapolation closure's D^-1 (T step), likewise
+    if (opt->closure == 1) {
+      const size_t E = split_block_elems(NX);
+      if (S->xbf.alloc((size_t)2 * (S->L - 1) * E) != hipSuccess) return bail(fail(PT_ENOMEM, "split extrapolators"));
+      for (int k = 0; k + 1 < S->L; ++k) {
+        const double2* sg = S->dinv64.p + (size_t)(S->lay[k].rowbase + S->lay[k].rn1) * S->block_elems();
+        const double2* dl = S->dinv64.p + (size_t)(S->lay[k + 1].rowbase + S->lay[k + 1].r0) * S->block_elems();
+        if (launch_split_planes(sg, S->xbf.p + (size_t)(2 * k) * E, 1, NX, S->st) != hipSuccess ||
+            launch_split_planes(dl, S->xbf.p + (size_t)(2 * k + 1) * E, 1, NX, S->st) != hipSuccess)
+          return bail(fail(PT_EHIP, "split extrapolators"));
+      }
+      if (hipStreamSynchronize(S->st) != hipSuccess) return bail(fail(PT_EHIP, "split extrapolators"));
+    }
   }
 
   // reduced-precision copies of the factors and blocks
@@ -2152,6 +2331,24 @@ pt_status pt_apply(pt_solver* S, int32_t op, int32_t nrhs, const double* x, doub
       PTCHK(precondition(S, S->s.p, yd, nrhs));
       break;
     }
+    case PT_OP_A_EXTRAP:
+    case PT_OP_R_EXTRAP:
+    case PT_OP_DINV_EXTRAP:
+    case PT_OP_PRECOND_EXTRAP:
+      if (S->opt.closure != 1) return fail(PT_EINVAL, "extrapolation operators need closure = 1");
+      if (op == PT_OP_A_EXTRAP) {
+        PTCHK(apply_op(S, S->opX, xd, yd, nrhs));
+      } else if (op == PT_OP_R_EXTRAP) {
+        HIPCHK(launch_zero(yd, (int64_t)n, S->st));  // its extrapolation rows are zero
+        PTCHK(apply_op(S, S->opRX, xd, yd, nrhs));
+      } else if (op == PT_OP_DINV_EXTRAP) {
+        HIPCHK(launch_copy(yd, xd, (int64_t)n, S->st));
+        PTCHK(dinv_extrap_inplace(S, yd, nrhs));
+      } else {
+        HIPCHK(hipMemcpyAsync(S->s.p, xd, n * sizeof(double2), hipMemcpyDeviceToDevice, S->st));
+        PTCHK(precondition_extrap(S, S->s.p, yd, nrhs));
+      }
+      break;
     default: return fail(PT_EINVAL, "unknown operator");
   }
   if (!on_device) HIPCHK(hipMemcpyAsync(y, yd, n * sizeof(double2), hipMemcpyDeviceToHost, S->st));
@@ -2228,7 +2425,7 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
   std::vector<int32_t> it(nrhs), dn(nrhs), kept(nrhs, 0);
   // true residual ||s - A x|| / ||s|| in float64, with the GMRES data, to the host
   auto residuals = [&]() -> pt_status {
-    PTCHK(apply_op(S, S->opA, S->x.p, S->tmp.p, nrhs));
+    PTCHK(system_A(S, S->x.p, S->tmp.p, nrhs));
     HIPCHK(launch_add(S->tmp.p, S->s.p, S->tmp.p, -1.0, (int64_t)nrhs * S->Nt, S->st));
     HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, S->Nt, S->st));
     HIPCHK(hipMemcpyAsync(nr.data(), S->nrm.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
@@ -2244,6 +2441,8 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
     PTCHK(reconstruct(S, fd, nullptr, ud, nrhs));
   } else {
     PTCHK(trace_rhs(S, fd, S->s.p, nrhs));
+    if (S->opt.closure == 1)  // extrapolation rows: zero right-hand side
+      HIPCHK(launch_zero_extrap_rows(S->s.p, S->L, S->NX, S->Nt, nrhs, S->st));
     if (S->learned) {
       // learned stage first; its float64 true residual decides, the sweeps are the fallback
       PTCHK(fgmres(S, nrhs, conv, S->opt.tol, true));

@@ -183,6 +183,9 @@ struct pt_solver {
   DevBuf<double> rr_sign;
   Launch bterm, opA, opR;
   Launch opA2;  // second launch of A in the extrapolated form (njobs 0: A is one launch)
+  // the system closed by extrapolation relations (closure 1)
+  Launch opX, opX2, opRX, gsRX, tX;
+  DevBuf<uint16_t> xbf;  // split-bfloat16 planes of the extrapolators' factors (mixed form)
 
   // captured GMRES iterations: (nrhs, iteration) -> executable graph
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -247,6 +250,11 @@ namespace polar_impl {
 pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs);
 pt_status apply_op(pt_solver* S, const Launch& op, const double2* x, double2* y, int nrhs);
 pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs);
+// the operator and preconditioner of the system GMRES solves (closure 0: jump, 1: extrapolation)
+pt_status system_A(pt_solver* S, const double2* x, double2* y, int nrhs);
+pt_status system_M(pt_solver* S, const double2* v, double2* z, int nrhs);
+pt_status precondition_extrap(pt_solver* S, const double2* v, double2* z, int nrhs);
+pt_status dinv_extrap_inplace(pt_solver* S, double2* c, int nrhs);
 // flexible GMRES on A x = S->s for nrhs columns; result in S->x.  With
 // `learned`, every preconditioner output goes through the learned stage.
 pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned);

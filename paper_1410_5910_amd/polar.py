@@ -21,6 +21,8 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESINGULAR, PT_ENOCONV = range(6)
 PT_F64, PT_F32, PT_SPLIT_BF16 = 0, 1, 2
 PT_LEARN_CORRECT, PT_LEARN_AUGMENT = 0, 1
 OP_A, OP_R, OP_DINV, OP_PRECOND = 0, 1, 2, 3
+# the same operators of the system closed by extrapolation (closure="extrap")
+OP_A_EXTRAP, OP_R_EXTRAP, OP_DINV_EXTRAP, OP_PRECOND_EXTRAP = 4, 5, 6, 7
 ROWS = {"0": 0, "1": 1, "n": 2, "n+1": 3}
 
 EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", "pt_get_layout", "pt_get_block",
@@ -40,7 +42,7 @@ class PtProblem(C.Structure):
 class PtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gs_iters", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32),
                 ("max_nrhs", C.c_int32), ("plr", C.c_int32), ("plr_eps", C.c_double), ("plr_rmax", C.c_int32),
-                ("use_graph", C.c_int32), ("presolve", C.c_int32)]
+                ("use_graph", C.c_int32), ("presolve", C.c_int32), ("closure", C.c_int32)]
 
 
 class PtRhsInfo(C.Structure):
@@ -148,7 +150,8 @@ class Solver:
     """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
 
     def __init__(self, nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
-                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False, presolve="auto"):
+                 max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False, presolve="auto",
+                 closure="jump"):
         self._lib = lib()
         c = np.ascontiguousarray(c, dtype=np.float64)
         NX, NZ = nx + 2 * npml, nz + 2 * npml
@@ -161,8 +164,11 @@ class Solver:
         if presolve not in ("local", "green", "auto"):
             raise ValueError(f"presolve must be 'local', 'green' or 'auto', not {presolve!r}")
         pre = {"local": 0, "green": 1, "auto": 2}[presolve]
+        if closure not in ("jump", "extrap"):
+            raise ValueError(f"closure must be 'jump' or 'extrap', not {closure!r}")
         opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
-                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0, pre)
+                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0, pre,
+                        {"jump": 0, "extrap": 1}[closure])
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
         self._h = h_
