@@ -626,13 +626,18 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
     if (mult) multiply(ar_h, ar_l, ai_h, ai_l);
     lds_barrier();
   };
+  // DEPTH chunks in flight: three for the 32-column form with S terms (the
+  // sweep steps: 48 registers a chunk still fit two workgroups per CU), two
+  // otherwise
+  constexpr int DEPTH = (NB == 2 && HAS_S) ? 3 : 2;
   if (nchunks > 0) {  // workgroup-uniform
-    InFlight f0, f1;
-    fetch(f0, 0);
-    fetch(f1, 1);
-    for (int i = 0; i < nchunks; i += 2) {
-      round(f0, i + 2);
-      if (i + 1 < nchunks) round(f1, i + 3);
+    InFlight f[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) fetch(f[d], d);
+    for (int i = 0; i < nchunks; i += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d)
+        if (d == 0 || i + d < nchunks) round(f[d], i + d + DEPTH);
     }
   }
 
