@@ -270,15 +270,22 @@ __device__ __forceinline__ double2* zbase(const Bases& b, int buf) {
 }
 
 // grid.x = njobs * ntiles (64-row tiles), grid.y = right-hand side; 4 waves.
-// Every job term is a PLR block; wave w takes the leaves w, w+4, ... of the
-// tile's leaf list; lane = output row.  A low-rank leaf first forms
-// t = V x[cols] (k dot products, each reduced across the wave), then adds
-// U[row] t; a dense leaf adds D[row] x[cols].  Wave partials are summed in a
-// fixed order through LDS.
-__global__ __launch_bounds__(256) void plr_apply_kernel(const Job* __restrict__ jobs, int n, int ntiles, int64_t ld,
-                                                         Bases bases) {
-  __shared__ double2 part[4][64];
-  __shared__ double2 tb[4][kPlrMaxRank];
+// Every job term is a PLR block; wave w of NW takes the leaves w, w + NW, ...
+// of the tile's leaf list; lane = output row.  The leaf's input columns (Q + beta S)
+// are staged in LDS in chunks of kXs, shared by the wave.  A low-rank leaf
+// forms t = V x with V stored column by column (n x k): lane l takes rank
+// l % k of the columns congruent to l / k modulo 64 / k, so one load
+// instruction reads 64 consecutive entries, and the 64 / k partial sums of a
+// rank are added in order through LDS; then U[row] t.  A dense leaf adds
+// D[row] x.  Wave partials are summed in a fixed order through LDS.
+constexpr int kXs = 128;
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restrict__ jobs, int n, int ntiles,
+                                                            int64_t ld, Bases bases) {
+  __shared__ double2 part[NW][64];
+  __shared__ double2 tb[NW][kPlrMaxRank];
+  __shared__ double2 xs[NW][kXs];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = blockIdx.x % ntiles;
   const Job& J = jobs[blockIdx.x / ntiles];
@@ -295,46 +302,64 @@ __global__ __launch_bounds__(256) void plr_apply_kernel(const Job* __restrict__ 
     const double2* sp = sr.buf >= 0 ? zbase(bases, sr.buf) + sr.off + (int64_t)r * ld : nullptr;
     const double2 be = J.beta[t];
     const int l0 = B->tile_ptr[tile], l1 = B->tile_ptr[tile + 1];
-    for (int li = l0 + wave; li < l1; li += 4) {
+    for (int li = l0 + wave; li < l1; li += NW) {
       const PlrLeafDev L = B->leaves[B->tile_leaf[li]];
+      if (L.k == 0) continue;  // a zero leaf
       const bool in = row >= L.r0 && row < L.r0 + L.m;
-      if (L.k < 0) {
-        const double2* D = B->data + L.offU + (size_t)(in ? row - L.r0 : 0) * L.n;
-        for (int c = 0; c < L.n; ++c) {
-          double2 x = qp ? qp[L.c0 + c] : make_double2(0.0, 0.0);
-          if (sp) x = zadd(x, zmul(be, sp[L.c0 + c]));
-          if (in) acc = zadd(acc, zmul(D[c], x));
+      const bool lowrank = L.k > 0;
+      const int G = lowrank ? 64 / L.k : 1;           // column groups of a rank
+      const int jr = lowrank ? lane % L.k : 0, cg = lowrank ? lane / L.k : 0;
+      const bool act = lowrank && cg < G;
+      const double2* Dr = B->data + L.offU + (size_t)(in ? row - L.r0 : 0) * L.n;  // dense leaf row
+      const double2* Vt = B->data + L.offV;                                       // n x k
+      double2 s = make_double2(0.0, 0.0);
+      for (int c0 = 0; c0 < L.n; c0 += kXs) {
+        const int cn = min(kXs, L.n - c0);
+        for (int c = lane; c < cn; c += 64) {
+          double2 x = qp ? qp[L.c0 + c0 + c] : make_double2(0.0, 0.0);
+          if (sp) x = zadd(x, zmul(be, sp[L.c0 + c0 + c]));
+          xs[wave][c] = x;
         }
-      } else {
-        const double2* V = B->data + L.offV;
-        for (int j = 0; j < L.k; ++j) {
-          double2 s = make_double2(0.0, 0.0);
-          for (int c = lane; c < L.n; c += 64) {
-            double2 x = qp ? qp[L.c0 + c] : make_double2(0.0, 0.0);
-            if (sp) x = zadd(x, zmul(be, sp[L.c0 + c]));
-            s = zadd(s, zmul(V[(size_t)j * L.n + c], x));
-          }
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            s.x += __shfl_xor(s.x, off, 64);
-            s.y += __shfl_xor(s.y, off, 64);
-          }
-          if (lane == 0) tb[wave][j] = s;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (act) {
+#pragma unroll 4
+          for (int c = cg; c < cn; c += G) s = zadd(s, zmul(Vt[(size_t)(c0 + c) * L.k + jr], xs[wave][c]));
+        } else if (!lowrank && in) {
+#pragma unroll 4
+          for (int c = 0; c < cn; ++c) acc = zadd(acc, zmul(Dr[c0 + c], xs[wave][c]));
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      if (lowrank) {
+        part[wave][lane] = act ? s : make_double2(0.0, 0.0);  // (part is free until the end)
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane < L.k) {
+          double2 tj = make_double2(0.0, 0.0);
+          for (int g = 0; g < G; ++g) tj = zadd(tj, part[wave][g * L.k + lane]);
+          tb[wave][lane] = tj;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         if (in) {
           const double2* U = B->data + L.offU + (size_t)(row - L.r0) * L.k;
+#pragma unroll 4
           for (int j = 0; j < L.k; ++j) acc = zadd(acc, zmul(U[j], tb[wave][j]));
         }
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
     }
   }
+  __syncthreads();  // every wave is done with its LDS rows before they hold the partials
   part[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && row < n) {
-    const double2 s = zadd(zadd(part[0][lane], part[2][lane]), zadd(part[1][lane], part[3][lane]));
+    double2 s = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = zadd(s, part[w][lane]);
     double2 y = zmul(J.alpha, s);
     if (J.P.buf >= 0) y = zadd(y, zbase(bases, J.P.buf)[J.P.off + (int64_t)r * ld + row]);
     zbase(bases, J.Y.buf)[J.Y.off + (int64_t)r * ld + row] = y;
@@ -388,8 +413,10 @@ hipError_t PlrSet::build(const std::vector<const std::complex<double>*>& blocks,
       } else {
         d.offU = (int64_t)(hdata.size() - data0[b]);
         hdata.insert(hdata.end(), lf.U.begin(), lf.U.end());
+        // V stored transposed (n x k): the apply reads one column's k values per step
         d.offV = (int64_t)(hdata.size() - data0[b]);
-        hdata.insert(hdata.end(), lf.V.begin(), lf.V.end());
+        for (int i = 0; i < lf.n; ++i)
+          for (int c = 0; c < lf.k; ++c) hdata.push_back(lf.V[(size_t)c * lf.n + i]);
         stored[b] += lf.U.size() + lf.V.size();
       }
       hl.push_back(d);
@@ -448,8 +475,13 @@ hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t
                             hipEvent_t ev0, hipEvent_t ev1) {
   if (njobs <= 0) return hipSuccess;
   const int ntiles = (n + 63) / 64;
-  hipExtLaunchKernelGGL(plr_apply_kernel, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(256), 0, st, ev0, ev1,
-                        0, jobs, n, ntiles, ld, bases);
+  // few workgroups (one source, a sweep step's four blocks): 16 waves share a tile's leaves
+  if ((long)njobs * ntiles * nrhs < 512)
+    hipExtLaunchKernelGGL(plr_apply_kernel<16>, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(1024), 0, st, ev0,
+                          ev1, 0, jobs, n, ntiles, ld, bases);
+  else
+    hipExtLaunchKernelGGL(plr_apply_kernel<4>, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(256), 0, st, ev0,
+                          ev1, 0, jobs, n, ntiles, ld, bases);
   return hipGetLastError();
 }
 

@@ -237,15 +237,16 @@ def test_batched_many_sources_match_single():
 
 
 # ---------------------------------------------------------------- partitioned low-rank blocks
-def test_plr_operator_matches_dense_oracle():
+@pytest.mark.parametrize("nrhs", [3, 40])  # 16 waves per tile (few workgroups) / 4 waves
+def test_plr_operator_matches_dense_oracle(nrhs):
     prob, f = synth.config_small(nx=90, nz=60, npml=8, L=3, nrhs=2, seed=12)
-    _flush("[gpu] plr operator small")
-    gs = P.Solver.from_problem(prob, plr=True, plr_eps=1e-10, max_nrhs=3, tol=1e-12)
+    _flush(f"[gpu] plr operator small, {nrhs} sources")
+    gs = P.Solver.from_problem(prob, plr=True, plr_eps=1e-10, max_nrhs=nrhs, tol=1e-12)
     lay = gs.layout()
     assert lay["plr_leaves"] > 0 and lay["block_bytes"] < lay["dense_block_bytes"]
     ps = PolarizedSolver(prob)
     rng = np.random.default_rng(9)
-    x = rng.standard_normal(ps.zeros(3).shape) + 1j * rng.standard_normal(ps.zeros(3).shape)
+    x = rng.standard_normal(ps.zeros(nrhs).shape) + 1j * rng.standard_normal(ps.zeros(nrhs).shape)
     for code, fn in ((P.OP_A, ps.apply_A), (P.OP_R, ps.apply_R), (P.OP_DINV, ps.apply_D_inv),
                      (P.OP_PRECOND, ps.precondition)):
         err = rel(gs.apply(code, x), fn(x))
