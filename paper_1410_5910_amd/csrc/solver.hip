@@ -1648,8 +1648,9 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
 }
 
 pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2* u, int nrhs) {
-  const int64_t nv = (int64_t)nrhs * S->NZ * S->NX;
-  const bool overlap = f < u + nv && u < f + nv;  // u written in place while f is read: keep them apart
+  const uintptr_t nb = (uintptr_t)nrhs * S->NZ * S->NX * sizeof(double2);
+  const uintptr_t fa = reinterpret_cast<uintptr_t>(f), ua = reinterpret_cast<uintptr_t>(u);
+  const bool overlap = fa < ua + nb && ua < fa + nb;  // u written in place while f is read: keep them apart
   if (S->rec_direct && !overlap && (x || S->n_rec_rhs == 0)) {
     const int64_t ld = (int64_t)S->NZ * S->NX;
     if (S->n_rec_rhs > 0)
