@@ -659,6 +659,19 @@ void release_green(pt_solver* S) {
   S->green.release();
 }
 
+// Rows of a layer's inverse kept as interface Green's functions: row 1 (with
+// a top interface) and row n (with a bottom one).  Rows 0 and n+1 of the
+// pre-solve follow from them by one-sided extrapolation: the sources lie on
+// the owned rows, where G(z_0, z_j) = E_up G(z_1, z_j) and
+// G(z_{n+1}, z_j) = E_down G(z_n, z_j) (Lemma extrapolator_def), with
+// E_up = -u Delta_0^-1 and E_down = -l Sigma_{n+1}^-1 from the factors.
+std::vector<int> green_rows(const Layer& y) {
+  std::vector<int> g;
+  if (y.top_ext) g.push_back(y.r1);
+  if (y.bot_ext) g.push_back(y.rn);
+  return g;
+}
+
 pt_status extract_blocks(pt_solver* S) {
   const int NX = S->NX, L = S->L;
   const size_t E = S->block_elems();
@@ -699,8 +712,7 @@ pt_status extract_blocks(pt_solver* S) {
     size_t need = 0;
     for (int l = 0; l < L; ++l) {
       const Layer& y = S->lay[l];
-      const int ntr = (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0);
-      need += (size_t)ntr * NX * ((size_t)y.n * NX);
+      need += green_rows(y).size() * NX * ((size_t)y.n * NX);
     }
     // auto: at most a third of the free memory, a sixteenth of the device per
     // solver and a quarter of the device over all solvers of the process, so
@@ -724,8 +736,8 @@ pt_status extract_blocks(pt_solver* S) {
         size_t off = 0;
         for (int l = 0; l < L; ++l) {
           const Layer& y = S->lay[l];
-          const int ntr = (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0);
-          for (int k = 0; k < ntr; ++k) {
+          const size_t ng = green_rows(y).size();
+          for (size_t k = 0; k < ng; ++k) {
             S->green_off[(size_t)l * 4 + k] = off;
             off += (size_t)NX * ((size_t)y.n * NX);
           }
@@ -799,10 +811,14 @@ pt_status extract_blocks(pt_solver* S) {
         rc = fail(PT_EHIP, "green scaling");
         break;
       }
-      for (int k = 0; k < nq && rc == PT_OK; ++k)
-        if (launch_pack_green(Wx.p, ld, k, src[k], y.top_ext, y.n, NX, gax.p, gaz.p,
-                              S->green.p + S->green_off[(size_t)l * 4 + k], st) != hipSuccess)
+      const std::vector<int> gr = green_rows(y);
+      for (size_t g = 0; g < gr.size() && rc == PT_OK; ++g) {
+        int q = 0;  // the extraction solve's column block of that source row
+        while (src[q] != gr[g]) ++q;
+        if (launch_pack_green(Wx.p, ld, q, gr[g], y.top_ext, y.n, NX, gax.p, gaz.p,
+                              S->green.p + S->green_off[(size_t)l * 4 + g], st) != hipSuccess)
           rc = fail(PT_EHIP, "pack_green");
+      }
       if (rc != PT_OK) break;
     }
     // pack the signed blocks (column q of the solve = source row src[q])
@@ -1097,18 +1113,26 @@ void build_online_jobs(pt_solver* S) {
     // pre-solve by the interface Green's functions: w^l(row j) = sum over owned rows
     // of G^l_j h^2 f^l, one job per (layer, trace row) in layer order
     S->green_launch = Launch{};
+    S->green_ext = Launch{};
     if (S->green.p) {
-      std::vector<Job> js;
+      std::vector<Job> js, jext;
       for (int l = 0; l < L; ++l) {
         const Layer& y = S->lay[l];
-        std::vector<int> src;
+        const std::vector<int> src = green_rows(y);
+        // rows 0 and n+1 from rows 1 and n: w(0) = -u Delta_0^-1 w(1), w(n+1) = -l Sigma_{n+1}^-1 w(n)
         if (y.top_ext) {
-          src.push_back(y.r0);
-          src.push_back(y.r1);
+          Job j = empty_job();
+          j.Y = vr(0, (int64_t)(y.rowbase + y.r0) * NX);
+          j.alpha = d2(-S->ucoef[y.rowbase + y.r0]);
+          add_term(j, S->dinv(l, y.r0), vr(0, (int64_t)(y.rowbase + y.r1) * NX));
+          jext.push_back(j);
         }
         if (y.bot_ext) {
-          src.push_back(y.rn);
-          src.push_back(y.rn1);
+          Job j = empty_job();
+          j.Y = vr(0, (int64_t)(y.rowbase + y.rn1) * NX);
+          j.alpha = d2(-S->lcoef[y.rowbase + y.rn1]);
+          add_term(j, S->dinv(l, y.rn1), vr(0, (int64_t)(y.rowbase + y.rn) * NX));
+          jext.push_back(j);
         }
         for (size_t k = 0; k < src.size(); ++k) {
           Job j = empty_job();
@@ -1121,6 +1145,8 @@ void build_online_jobs(pt_solver* S) {
       }
       S->green_launch = push_launch(S, js, PT_CLS_PRESOLVE);
       index_layers(S, S->green_launch);
+      S->green_ext = push_launch(S, jext, PT_CLS_PRESOLVE);
+      index_layers(S, S->green_ext);
       // K-split form for wide passes: each (layer, trace row) product split into
       // S_l ranges of owned rows, partial sums in S_l free owned rows per trace
       // row (rows te+2 .. te+2+4 S_l-1, clear of the trace rows), then summed
@@ -1160,16 +1186,8 @@ void build_online_jobs(pt_solver* S) {
         room = false;  // no device memory for the lists: the unsplit form serves every width
       for (int l = 0; l < L && room; ++l) {
         const Layer& y = S->lay[l];
-        std::vector<int> src;
-        if (y.top_ext) {
-          src.push_back(y.r0);
-          src.push_back(y.r1);
-        }
-        if (y.bot_ext) {
-          src.push_back(y.rn);
-          src.push_back(y.rn1);
-        }
-        const int ns = std::min(8, (y.n - 3) / 4);  // rows te+2 .. te+1+4 ns stay below row n-1
+        const std::vector<int> src = green_rows(y);
+        const int ns = std::min(8, (y.n - 3) / 4);  // rows te+2 .. te+1+2 ns stay below row n-1
         const int per = (y.n + ns - 1) / ns;
         for (size_t k = 0; k < src.size(); ++k) {
           const int prow0 = y.rowbase + y.top_ext + 2 + (int)k * ns;
@@ -1525,9 +1543,11 @@ bool use_green(const pt_solver* S, int cols) {
 // form then has enough workgroups to stream them)
 pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
   Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
+  const Launch ext = layer_range(S, S->green_ext, la, lb);
   if (cols <= 4 || S->green_split.njobs == 0) {
     const Launch sub = layer_range(S, S->green_launch, la, lb);
     if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
+    if (ext.njobs > 0) PTCHK(run_apply(S, ext, cols, ld, b));
     return PT_OK;
   }
   const Launch sub = layer_range(S, S->green_split, la, lb);
@@ -1558,6 +1578,7 @@ pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
   const int e0 = S->gsum_off[la], e1 = S->gsum_off[lb + 1];
   HIPCHK(launch_sum_rows(S->W.p, ld, S->NX, S->gsum_dst.p + e0, S->gsum_src.p + e0, S->gsum_cnt.p + e0, e1 - e0,
                          cols, S->st));
+  if (ext.njobs > 0) PTCHK(run_apply(S, ext, cols, ld, b));
   return PT_OK;
 }
 

@@ -140,11 +140,12 @@ struct pt_solver {
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
   bool split = false;
   DevBuf<float2> part;     // k-slice partial tiles of small split launches
-  // interface Green's functions of the pre-solve: per layer and trace row j,
-  // the NX x (n NX) rows j of (A^l)^-1 over the owned rows (null: line-by-line)
+  // interface Green's functions of the pre-solve: per layer, rows 1 and n of
+  // (A^l)^-1 over the owned rows, NX x (n NX) each (null: line-by-line)
   DevBuf<double2> green;
   std::vector<size_t> green_off;  // [layer * 4 + trace-row slot] -> offset in green (SIZE_MAX: absent)
-  Launch green_launch;            // one job per (layer, trace row), layer order
+  Launch green_launch;            // one job per (layer, kept row 1 / n), layer order
+  Launch green_ext;               // rows 0 and n+1 by extrapolation from rows 1 and n, layer order
   // the same products with each row block split over K ranges (wide passes):
   // partial rows in free rows of each layer, summed into the trace rows
   Launch green_split;

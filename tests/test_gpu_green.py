@@ -1,9 +1,11 @@
 """Pre-solve by interface Green's functions (presolve="green") against the
 line-by-line local solves (presolve="local") and the oracle.
 
-The rows j = 0, 1, n, n+1 of each layer's inverse over its owned rows are
-built at setup from the extraction solves (the columns at those rows) and the
-diagonal scaling that makes the local operator symmetric.  The pre-solve is
+The rows j = 1 and n of each layer's inverse over its owned rows are built at
+setup from the extraction solves (the columns at those rows) and the diagonal
+scaling that makes the local operator symmetric; rows 0 and n+1 of the
+pre-solve follow by one-sided extrapolation (Lemma extrapolator_def: the
+sources lie on the owned rows).  The pre-solve is
 then one product per (layer, trace row) instead of ~R dependent launches, so
 the trace right-hand side must match the oracle's N^l f^l at the trace rows
 (Alg. 2, Def. 3) to float64 rounding, for dense, sparse and single sources,
@@ -53,8 +55,8 @@ def test_green_layout(pair):
     prob, g, loc, ps = pair
     lay = g.layout()
     want = 0
-    for s in ps.slabs:
-        ntr = (2 if s.top_ext else 0) + (2 if s.bot_ext else 0)
+    for s in ps.slabs:  # rows 1 and n only: rows 0 and n+1 follow by extrapolation
+        ntr = (1 if s.top_ext else 0) + (1 if s.bot_ext else 0)
         want += ntr * prob.NX * s.n * prob.NX * 16
     assert lay["green_bytes"] == want
     assert loc.layout()["green_bytes"] == 0

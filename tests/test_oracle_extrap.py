@@ -63,6 +63,26 @@ def test_extrapolators_reproduce_green_rows(sys4):
     assert rel(ex.E_dn[1] @ Kt[("n", "n+1")], Kt[("n+1", "n+1")]) > 1e-3
 
 
+def test_extrapolators_reach_every_owned_source(sys4):
+    """Lemma extrapolator_def over all owned source rows (not only the trace rows):
+    row n+1 of a layer's inverse is E_down times row n on the columns of rows j <= n,
+    row 0 is E_up times row 1 on the columns of rows j >= 1."""
+    prob, f, ps, ex, u = sys4
+    NX = ps.NX
+    for k in range(ps.L - 1):
+        for lay, E, tgt, src, cols in ((ps.loc[k], ex.E_dn[k], "n+1", "n", "le_n"),
+                                      (ps.loc[k + 1], ex.E_up[k], "0", "1", "ge_1")):
+            s = lay.slab
+            R = s.R
+            inv = lay.solve(np.eye(R * NX, dtype=np.complex128).reshape(R * NX, R, NX))  # columns of the inverse
+            inv = inv.reshape(R * NX, R * NX).T  # inv[i, c] = (A^l)^-1 entry (row i, column c)
+            rt, rs = lay.rows[tgt], lay.rows[src]
+            own = slice(s.top_ext * NX, (s.top_ext + s.n) * NX)  # owned rows j = 1..n
+            rows_t = inv[rt * NX:(rt + 1) * NX, own]
+            rows_s = inv[rs * NX:(rs + 1) * NX, own]
+            assert rel(E @ rows_s, rows_t) < 1e-9, (k, tgt)
+
+
 def test_polarized_traces_solve_the_system(sys4):
     prob, f, ps, ex, u = sys4
     x = _traces(ps, u, f)
