@@ -60,7 +60,9 @@ typedef enum {
   PT_ENOMEM = 2,     /* device allocation failed                                  */
   PT_EHIP = 3,       /* HIP runtime error                                         */
   PT_ESINGULAR = 4,  /* zero pivot in the local factorisation                     */
-  PT_ENOCONV = 5     /* GMRES reached maxit; u holds the last iterate's field     */
+  PT_ENOCONV = 5     /* some source did not converge (GMRES reached maxit, or the
+                        source is not finite); u holds the last iterate's field,
+                        the per-source info says which                           */
 } pt_status;
 
 typedef enum {
@@ -135,7 +137,8 @@ typedef struct {
 
 typedef struct {
   int32_t iters;     /* GMRES iterations used                                     */
-  int32_t converged; /* 1 if the residual estimate reached tol                    */
+  int32_t converged; /* 1 if the residual estimate reached tol (0 for a source
+                        with a NaN or Inf: it stops at once, est and relres NaN)  */
   double est;        /* GMRES residual estimate at exit (relative)                */
   double relres;     /* true relative residual ||s - A x|| / ||s|| in float64     */
   int32_t learned;   /* 1 if the result came from GMRES with the learned stage    */

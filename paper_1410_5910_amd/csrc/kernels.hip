@@ -1261,9 +1261,9 @@ __global__ void kinit_kernel(double2* g, const double* beta, int32_t* done, int3
   double2* gg = g + (size_t)r * (mdim + 1);
   for (int i = 0; i <= mdim; ++i) gg[i] = make_double2(0.0, 0.0);
   gg[0] = make_double2(beta[r], 0.0);
-  done[r] = beta[r] > 0.0 ? 0 : 1;
+  done[r] = beta[r] > 0.0 ? 0 : 1;  // zero, or not finite (NaN / Inf source): nothing to iterate
   iters[r] = 0;
-  est[r] = beta[r] > 0.0 ? 1.0 : 0.0;
+  est[r] = beta[r] > 0.0 ? 1.0 : (beta[r] == 0.0 ? 0.0 : __builtin_nan(""));
 }
 
 __global__ void to_f32_kernel(float2* __restrict__ d, const double2* __restrict__ s, int64_t n) {

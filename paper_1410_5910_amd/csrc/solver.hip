@@ -2486,13 +2486,17 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
       for (int r = 0; r < nrhs; ++r) info[r] = pt_rhs_info{0, 1, 0.0, 0.0, 0, 0};
     } else {
       if (!used_learned) PTCHK(residuals());
-      for (int r = 0; r < nrhs; ++r)
-        info[r] = pt_rhs_info{it[r], dn[r], es[r], be[r] > 0 ? nr[r] / be[r] : 0.0, used_learned ? 1 : 0,
-                              used_learned ? kept[r] : 0};
+      for (int r = 0; r < nrhs; ++r) {
+        // a source that is not finite stops at once and is reported not converged
+        const double rr = be[r] > 0 ? nr[r] / be[r] : (be[r] == 0.0 ? 0.0 : std::nan(""));
+        const bool ok = dn[r] && std::isfinite(es[r]) && std::isfinite(rr);
+        conv = conv && ok;
+        info[r] = pt_rhs_info{it[r], ok ? 1 : 0, es[r], rr, used_learned ? 1 : 0, used_learned ? kept[r] : 0};
+      }
     }
   }
   HIPCHK(hipStreamSynchronize(S->st));
-  return conv ? PT_OK : fail(PT_ENOCONV, "GMRES reached maxit before tol");
+  return conv ? PT_OK : fail(PT_ENOCONV, "GMRES did not converge for every source (maxit, or a source not finite)");
 }
 
 }  // extern "C"

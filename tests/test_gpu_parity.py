@@ -451,3 +451,26 @@ def test_graph_replays_match_plain_launches(precision):
     assert max(rel(u[r], ud[r]) for r in range(24)) < 1e-8
     g.close()
     p.close()
+
+
+# ---------------------------------------------------------------- a source with a NaN
+@pytest.mark.parametrize("nrhs", [3, 20])  # streaming kernel / MFMA kernel paths
+def test_nan_source_stays_in_its_column(nrhs):
+    """A NaN in one source touches every layer of that source only: the other
+    sources of the batch are solved as without it, and the NaN source is
+    reported not converged with a non-finite field."""
+    prob, f = synth.config_small(nx=40, nz=48, npml=6, L=4, nrhs=nrhs, seed=77)
+    _flush(f"[gpu] nan source, {nrhs} sources")
+    gs = P.Solver.from_problem(prob, max_nrhs=nrhs, tol=1e-10, maxit=40)
+    bad = nrhs // 2
+    fb = f.copy()
+    fb[bad, prob.npml + 20, prob.npml + 7] = np.nan
+    u, info = gs.solve(fb)
+    ref = DirectSolver(prob).solve(f)
+    assert not np.all(np.isfinite(u[bad]))
+    assert not info[bad]["converged"]
+    for r in range(nrhs):
+        if r != bad:
+            assert np.all(np.isfinite(u[r])) and info[r]["converged"], r
+            assert rel(u[r], ref[r]) < 1e-8, r
+    gs.close()
