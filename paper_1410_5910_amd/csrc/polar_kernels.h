@@ -34,10 +34,10 @@ struct Job {
   int32_t pad;
   int32_t kw[4];   // columns of M_t (0: n)
   int32_t ldm[4];  // row stride of M_t in entries (0: its column count)
-  // float64 MFMA form only: the column chunks (kNzChunk columns each) of term 0
+  // float64 MFMA form: the column chunks (kNzChunk columns each) of term 0
   // whose inputs are not all zero, kl[0] = their count (at most kKlMax) and
   // kl[1..kl[0]] their indices in ascending order; the others add exact zeros
-  // and are skipped (null: every chunk)
+  // and are skipped (null: every chunk).  The other forms read every chunk.
   const int32_t* kl;
 };
 

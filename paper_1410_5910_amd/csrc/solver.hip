@@ -136,7 +136,6 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
   else {
-    if (Lc.klist && (S->f32 || !g.mfma)) return fail(PT_EINVAL, "nonzero-chunk lists need the float64 MFMA form");
     HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
   }
   if (S->prof) {
@@ -1537,26 +1536,30 @@ bool use_green(const pt_solver* S, int cols) {
   return S->green.p && (S->opt.presolve == 1 || cols <= 4 || S->green_split.njobs > 0);
 }
 
-// w^l at the trace rows of layers la..lb from the Green's functions: one
-// launch of whole row blocks for narrow passes (the streaming kernel reads
-// each block once), K-split products plus a row sum for wider ones (the MFMA
-// form then has enough workgroups to stream them)
+// w^l at the trace rows of layers la..lb from the Green's functions: K-split
+// products (each kept row's product over up to 8 ranges of owned rows, so
+// both the streaming and the MFMA form get enough workgroups to stream the
+// Green's functions), a row sum, then rows 0 and n+1 by extrapolation; one
+// launch of whole row blocks when a layer has no room for the partial rows
 pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
   Bases b{{S->W.p, S->Bw.p, nullptr, nullptr}};
   const Launch ext = layer_range(S, S->green_ext, la, lb);
-  if (cols <= 4 || S->green_split.njobs == 0) {
+  if (S->green_split.njobs == 0) {
     const Launch sub = layer_range(S, S->green_launch, la, lb);
     if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
     if (ext.njobs > 0) PTCHK(run_apply(S, ext, cols, ld, b));
     return PT_OK;
   }
+  // the MFMA form (> 4 columns) walks fresh nonzero-chunk lists; the streaming
+  // form reads every chunk (the skipped ones would add zeros) and no list is made
+  const bool lists = cols > 4 && S->green_split.klist;
   const Launch sub = layer_range(S, S->green_split, la, lb);
   const int n0 = S->nz_off[la], n1 = S->nz_off[lb + 1];
-  if (S->green_split.klist)
+  if (lists)
     HIPCHK(launch_nonzero_chunks(S->Bw.p, ld, cols, S->nz_in_off.p + n0, S->nz_in_k.p + n0, n1 - n0,
                                  S->nz_list.p + (size_t)n0 * S->nz_stride, S->nz_stride, S->st));
   if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
-  if (S->prof && sub.klist && sub.njobs > 0 && !S->pend.empty()) {
+  if (S->prof && lists && sub.njobs > 0 && !S->pend.empty()) {
     // count what the launch streamed: the chunks its lists kept
     std::vector<int32_t> h((size_t)(n1 - n0) * S->nz_stride);
     HIPCHK(hipMemcpyAsync(h.data(), S->nz_list.p + (size_t)n0 * S->nz_stride, h.size() * sizeof(int32_t),
