@@ -196,6 +196,17 @@ pt_status pt_get_layout(const pt_solver* s, pt_layout* out);
  * stored float64 blocks (PT_F32 solvers: the float32 copy, widened). */
 pt_status pt_get_block(const pt_solver* s, int32_t layer, int32_t j, int32_t k, double* out);
 
+/* The same block as pt_get_block, expanded from its partitioned low-rank form
+ * (Section 5, Alg. 5: the adaptive quadtree of low-rank and dense leaves, built
+ * on the GPU at setup when plr = 1): the product U V of every low-rank leaf and
+ * the entries of every dense leaf, written to host `out` (NX x NX row-major
+ * complex).  `nleaves` and `stored` (either may be NULL) receive the block's
+ * leaf count and stored complex entries.  PT_EINVAL if the solver was set up
+ * without plr or the block does not exist; allocates one NX x NX device
+ * buffer for the call. */
+pt_status pt_get_plr_block(const pt_solver* s, int32_t layer, int32_t j, int32_t k, double* out, int32_t* nleaves,
+                           int64_t* stored);
+
 typedef enum {
   PT_OP_A = 0,       /* y = A x: polarized system closed by jump conditions (Def. 9) */
   PT_OP_R = 1,       /* y = R x, R = A - D (eq. def_permuted_system_jump)            */

@@ -33,8 +33,6 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         "-Wall", "-Wno-unused-result",
-        # host-side complex arithmetic (PLR compression) without the C99 Annex G inf/nan branches
-        "-Xarch_host", "-fcomplex-arithmetic=basic",
     ]
     objs = []
     procs = []

@@ -5,7 +5,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <complex>
 #include <vector>
 
 #include "polar_kernels.h"
@@ -40,9 +39,13 @@ struct PlrSet {
   PlrBlockDev* d_blocks = nullptr;
   size_t data_entries = 0, nleaves_total = 0;
   std::vector<size_t> stored;  // complex entries stored per block
+  std::vector<int> nleaves;    // leaves per block
 
-  // Compress every n x n row-major block (host memory) and upload the result.
-  hipError_t build(const std::vector<const std::complex<double>*>& blocks, int n, int rmax, double eps, int nthreads);
+  // Compress the nb row-major n x n blocks at `blocks` (device memory) on the
+  // GPU, on stream st; the result stays in device memory.
+  hipError_t build(const double2* blocks, int nb, int n, int rmax, double eps, hipStream_t st);
+  // Write block b back as a dense row-major n x n matrix (device `out`).
+  hipError_t expand(int b, double2* out, hipStream_t st) const;
   size_t stored_entries(int b) const;
   const PlrBlockDev* block(int b) const { return d_blocks + b; }
   void release();

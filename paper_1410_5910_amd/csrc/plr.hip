@@ -1,22 +1,29 @@
-// Partitioned low-rank (PLR) trace blocks: compression at setup (host) and
-// the online apply kernel (GPU).
+// Partitioned low-rank (PLR) trace blocks: compression at setup and the online
+// apply kernel, both on the GPU.
 //
 // Compression follows the adaptive quadtree of the paper's Alg. 5: a block
 // becomes a leaf when its (r_max+1)-th singular value is below eps (absolute),
 // keeping the k <= r_max triplets with sigma >= eps; otherwise it is split
 // into four (ceil/floor halves) and each quarter is compressed; a block whose
 // smaller side is <= r_max is a dense leaf.  The singular values are those of
-// a randomized sketch: Y = (M M^H) M Omega with r_max + 1 + 10 columns (one
-// power iteration, re-orthonormalised), B = Q^H M, and a one-sided Jacobi SVD
-// of B (accurate small singular values, unlike an eigen-solve of B B^H).  A
-// candidate leaf is accepted only if four random probes see an error below
+// a randomized sketch (Section 7: the compression uses a randomized SVD):
+// Y = M Omega with s = r_max + 1 + 10 Gaussian columns, one power iteration
+// Y = M (M^H Q) with re-orthonormalisation, B = Q^H M, and a one-sided
+// (Hestenes) Jacobi SVD of B, which keeps the small singular values accurate.
+// A candidate leaf is accepted only if four random probes see an error below
 // eps.  The leaves are applied in the factored form y[rows] += U (V x[cols])
 // of the paper's Alg. 6 / sparse-factorised product.
+//
+// The quadtree is processed one level at a time: every candidate node of a
+// level (across all blocks) is one entry of a node table, and each step of the
+// randomized SVD is one batched launch over that table (one workgroup per node,
+// or per node and 64-row tile for the products).  The host reads back only the
+// per-node decision (accepted, rank) to form the next level; the factors go
+// from the staging buffer straight into the packed leaf data on the device.
 #include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
-#include <thread>
 #include <vector>
 
 #include "plr.h"
@@ -25,246 +32,428 @@ namespace polar {
 
 namespace {
 
-using cplx = std::complex<double>;
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double znorm(double2 a) { return a.x * a.x + a.y * a.y; }
 
-// SplitMix64 (Steele, Lea, Flood 2014) -> two uniforms -> Box-Muller normal pair
-struct Rng {
-  uint64_t s;
-  explicit Rng(uint64_t seed) : s(seed) {}
-  uint64_t next() {
-    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-  }
-  double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
-  cplx normal() {
-    const double u1 = uniform(), u2 = uniform();
-    const double r = std::sqrt(-2.0 * std::log(u1));
-    return cplx(r * std::cos(6.283185307179586 * u2), r * std::sin(6.283185307179586 * u2));
-  }
+// ----------------------------------------------------------------------------
+// compression (setup)
+// ----------------------------------------------------------------------------
+constexpr int kSMax = kPlrMaxRank + 1 + 10;  // widest sketch
+constexpr int kCpw = (kSMax + 3) / 4;        // product columns per wave (4 waves)
+constexpr int kKc = 16;                      // inner-dimension chunk of the products
+
+// per-node staging slots (complex entries, column-major unless noted)
+enum Slot {
+  S_OM = 0,  // Omega, n x s
+  S_Y,       // Y = M Omega, then Q (m x s)
+  S_T,       // M^H Q (n x s); at the end X = B^H, rotated into Z diag(sigma)
+  S_W,       // Jacobi rotations, s x s
+  S_U,       // leaf U = Q W diag(sigma), m x k row-major
+  S_V,       // leaf V^T, n x k row-major (V = Z^H)
+  S_P4,      // probe vectors, n x 4
+  S_Y4,      // M times the probes, m x 4
+  S_NSLOT
 };
 
-// view of a sub-block of a row-major matrix
-struct View {
-  const cplx* p;
-  int m, n, ld;
-  cplx at(int i, int j) const { return p[(size_t)i * ld + j]; }
+struct CNode {
+  int32_t blk, r0, c0, m, n, s;
+  int64_t off[S_NSLOT];
 };
 
-// orthonormalise the columns of Y (m x s, column-major) in place by modified
-// Gram-Schmidt applied twice; returns the number of independent columns
-int orthonormalise(std::vector<cplx>& Y, int m, int s) {
-  int r = 0;
-  for (int j = 0; j < s; ++j) {
-    cplx* y = &Y[(size_t)j * m];
-    double n0 = 0;
-    for (int i = 0; i < m; ++i) n0 += std::norm(y[i]);
-    n0 = std::sqrt(n0);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int q = 0; q < r; ++q) {
-        const cplx* u = &Y[(size_t)q * m];
-        cplx d = 0;
-        for (int i = 0; i < m; ++i) d += std::conj(u[i]) * y[i];
-        for (int i = 0; i < m; ++i) y[i] -= d * u[i];
+// per-node results: r = orthonormal sketch rank, k = leaf rank, ok = accepted
+struct CRes {
+  int32_t r, k, ok, pad;
+};
+
+// A leaf to copy into the packed data: k < 0 dense (from the block), else U
+// and V^T from the staging buffer.
+struct EmitRec {
+  int32_t blk, r0, c0, m, n, k;
+  int64_t srcU, srcV, dst;
+};
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014) as a counter-based generator;
+// two uniforms -> one complex normal by Box-Muller.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double2 cnormal(uint64_t key, uint64_t i) {
+  const uint64_t a = mix64(key + (2 * i + 1) * 0x9E3779B97F4A7C15ull);
+  const uint64_t b = mix64(key + (2 * i + 2) * 0x9E3779B97F4A7C15ull);
+  const double u1 = ((double)(a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((double)(b >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double rr = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  return make_double2(rr * cs, rr * sn);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  // xor butterfly: every lane ends with the same bits (each step adds a pair in both orders)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over the 256 threads of a workgroup, in a fixed order; every thread gets it
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// slot `slot` of each node <- complex normals, n x s (four = 0) or n x 4 (four = 1)
+__global__ __launch_bounds__(256) void plr_random_kernel(const CNode* __restrict__ nodes, double2* __restrict__ buf,
+                                                         int slot, int four, uint64_t seed) {
+  const CNode& nd = nodes[blockIdx.x];
+  uint64_t key = mix64(seed ^ (uint64_t)nd.blk);
+  key = mix64(key ^ ((uint64_t)nd.r0 << 32 | (uint32_t)nd.c0));
+  key = mix64(key ^ ((uint64_t)nd.m << 32 | (uint32_t)nd.n));
+  const int64_t cnt = (int64_t)nd.n * (four ? 4 : nd.s);
+  double2* out = buf + nd.off[slot];
+  for (int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.y * blockDim.x)
+    out[i] = cnormal(key, (uint64_t)i);
+}
+
+// out = op(M_node) P with op(M) = M (m x n, CONJ = false) or M^H (n x m, CONJ =
+// true); P is inner x cols and out outer x cols, column-major with leading
+// dimensions inner and outer.  cols: the node's sketch width s (cols_mode 0),
+// its orthonormal rank r (1) or 4 (2).  grid = (nodes, 64-row tiles of the
+// widest node); lane = output row, wave w takes the columns w, w + 4, ...; the
+// operand tiles are staged in LDS with coalesced loads.
+template <bool CONJ>
+__global__ __launch_bounds__(256) void plr_panel_kernel(const CNode* __restrict__ nodes, const CRes* __restrict__ res,
+                                                        const double2* __restrict__ blocks, int N,
+                                                        double2* __restrict__ buf, int in_slot, int out_slot,
+                                                        int cols_mode) {
+  __shared__ double2 Ms[64][kKc + 1];
+  __shared__ double2 Ps[kSMax][kKc + 1];
+  const CNode& nd = nodes[blockIdx.x];
+  const int outer = CONJ ? nd.n : nd.m, inner = CONJ ? nd.m : nd.n;
+  const int tile0 = blockIdx.y * 64;
+  if (tile0 >= outer) return;
+  const int cols = cols_mode == 0 ? nd.s : (cols_mode == 1 ? res[blockIdx.x].r : 4);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double2* M = blocks + (size_t)nd.blk * N * N + (size_t)nd.r0 * N + nd.c0;
+  const double2* P = buf + nd.off[in_slot];
+  double2 acc[kCpw];
+#pragma unroll
+  for (int jj = 0; jj < kCpw; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < inner; i0 += kKc) {
+    __syncthreads();
+    if (!CONJ) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // Ms[o][i] = M(tile0 + o, i0 + i): 16 consecutive columns per row
+        const int o = (t >> 4) + 16 * q, i = t & 15;
+        double2 v = make_double2(0.0, 0.0);
+        if (tile0 + o < outer && i0 + i < inner) v = M[(size_t)(tile0 + o) * N + i0 + i];
+        Ms[o][i] = v;
       }
-    double nn = 0;
-    for (int i = 0; i < m; ++i) nn += std::norm(y[i]);
-    nn = std::sqrt(nn);
-    if (nn <= 1e-14 * std::max(n0, 1e-300)) continue;  // dependent column: dropped
-    cplx* dst = &Y[(size_t)r * m];
-    for (int i = 0; i < m; ++i) dst[i] = y[i] / nn;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // Ms[o][i] = conj(M(i0 + i, tile0 + o)): 64 consecutive columns per row
+        const int o = t & 63, i = (t >> 6) + 4 * q;
+        double2 v = make_double2(0.0, 0.0);
+        if (tile0 + o < outer && i0 + i < inner) {
+          v = M[(size_t)(i0 + i) * N + tile0 + o];
+          v.y = -v.y;
+        }
+        Ms[o][i] = v;
+      }
+    }
+    for (int e = t; e < cols * kKc; e += 256) {
+      const int j = e / kKc, i = e % kKc;
+      Ps[j][i] = (i0 + i < inner) ? P[(size_t)j * inner + i0 + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int ni = min(kKc, inner - i0);
+    for (int i = 0; i < ni; ++i) {
+      const double2 a = Ms[lane][i];
+#pragma unroll
+      for (int jj = 0; jj < kCpw; ++jj) {
+        const int j = w + 4 * jj;
+        if (j < cols) acc[jj] = zadd(acc[jj], zmul(a, Ps[j][i]));
+      }
+    }
+  }
+  const int o = tile0 + lane;
+  if (o < outer) {
+    double2* O = buf + nd.off[out_slot];
+#pragma unroll
+    for (int jj = 0; jj < kCpw; ++jj) {
+      const int j = w + 4 * jj;
+      if (j < cols) O[(size_t)j * outer + o] = acc[jj];
+    }
+  }
+}
+
+// Orthonormalise the columns of slot `slot` (m x cols, cols = s or the node's
+// current r) in place: classical Gram-Schmidt applied twice per column, a
+// column whose remaining norm is below 1e-14 of its original norm dropped, the
+// kept ones compacted to the front; res.r = the number kept.  One workgroup per
+// node; the column being orthogonalised lives in global memory (L2-resident).
+__global__ __launch_bounds__(256) void plr_orth_kernel(const CNode* __restrict__ nodes, CRes* __restrict__ res,
+                                                       double2* __restrict__ buf, int slot, int use_r) {
+  __shared__ double2 d[kSMax];
+  __shared__ double red[4];
+  const CNode& nd = nodes[blockIdx.x];
+  const int m = nd.m;
+  const int cols = use_r ? res[blockIdx.x].r : nd.s;
+  double2* Y = buf + nd.off[slot];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int r = 0;
+  for (int j = 0; j < cols; ++j) {
+    double2* yj = Y + (size_t)j * m;
+    double s0 = 0.0;
+    for (int i = t; i < m; i += 256) s0 += znorm(yj[i]);
+    const double n0 = sqrt(block_sum(s0, red));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = w; q < r; q += 4) {  // d[q] = q-th basis column^H y
+        const double2* uq = Y + (size_t)q * m;
+        double re = 0.0, im = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          const double2 a = uq[i], b = yj[i];
+          re += a.x * b.x + a.y * b.y;
+          im += a.x * b.y - a.y * b.x;
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) d[q] = make_double2(re, im);
+      }
+      __syncthreads();
+      for (int i = t; i < m; i += 256) {
+        double2 v = yj[i];
+        for (int q = 0; q < r; ++q) v = zsub(v, zmul(Y[(size_t)q * m + i], d[q]));
+        yj[i] = v;
+      }
+      __syncthreads();
+    }
+    double s1 = 0.0;
+    for (int i = t; i < m; i += 256) s1 += znorm(yj[i]);
+    const double nn = sqrt(block_sum(s1, red));
+    if (!(nn > 1e-14 * fmax(n0, 1e-300))) continue;  // dependent column: dropped (uniform over the group)
+    const double inv = 1.0 / nn;
+    double2* dst = Y + (size_t)r * m;
+    for (int i = t; i < m; i += 256) dst[i] = zscale(yj[i], inv);
+    __syncthreads();
     ++r;
   }
-  return r;
+  if (t == 0) res[blockIdx.x].r = r;
 }
 
-// One-sided (Hestenes) Jacobi SVD of the s x n matrix B (row-major): returns
-// sigma (descending), W (s x s, column-major) and Z (n x s, column-major) with
-// B = W diag(sigma) Z^H.  Works on X = B^H (n x s) whose columns are rotated
-// until mutually orthogonal: X W = Z diag(sigma).
-void jacobi_svd(const std::vector<cplx>& B, int s, int n, std::vector<double>& sig, std::vector<cplx>& W,
-                std::vector<cplx>& Z) {
-  std::vector<cplx> X((size_t)n * s);
-  for (int j = 0; j < s; ++j)
-    for (int i = 0; i < n; ++i) X[(size_t)j * n + i] = std::conj(B[(size_t)j * n + i]);
-  W.assign((size_t)s * s, 0.0);
-  for (int j = 0; j < s; ++j) W[(size_t)j * s + j] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < s - 1; ++p)
-      for (int q = p + 1; q < s; ++q) {
-        cplx* xp = &X[(size_t)p * n];
-        cplx* xq = &X[(size_t)q * n];
-        double a = 0, b = 0;
-        cplx g = 0;
-        for (int i = 0; i < n; ++i) {
-          a += std::norm(xp[i]);
-          b += std::norm(xq[i]);
-          g += std::conj(xp[i]) * xq[i];
+// One-sided Jacobi SVD of B = Q^H M (r x n) through X = B^H = M^H Q (slot T,
+// n x r): pairs of columns are rotated until mutually orthogonal, X W = Z
+// diag(sigma), so B = W diag(sigma) Z^H.  Disjoint pairs in round-robin order
+// (one wave per pair, r - 1 rounds per sweep, a sweep without rotations ends
+// it).  Then sigma = column norms sorted descending, the leaf decision of
+// Alg. 5 (sigma_{r_max+1} < eps), k = #{sigma >= eps, first r_max}, and for a
+// candidate leaf U = Q W(:, :k) diag(sigma) (slot U) and V^T = conj(Z(:, :k))
+// (slot V).  One workgroup per node.
+__global__ __launch_bounds__(256) void plr_svd_kernel(const CNode* __restrict__ nodes, CRes* __restrict__ res,
+                                                      double2* __restrict__ buf, int rmax, double eps) {
+  __shared__ double nrm[kSMax];
+  __shared__ int ord[kSMax];
+  __shared__ int rotated;
+  const CNode& nd = nodes[blockIdx.x];
+  const int n = nd.n, m = nd.m, r = res[blockIdx.x].r;
+  double2* X = buf + nd.off[S_T];
+  double2* W = buf + nd.off[S_W];
+  const double2* Q = buf + nd.off[S_Y];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = t; e < r * r; e += 256) W[e] = make_double2(e % r == e / r ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  const int rp = r + (r & 1);  // a phantom column when r is odd
+  for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < rp - 1; ++round) {
+      for (int pi = w; pi < rp / 2; pi += 4) {
+        // circle method: column 0 fixed, the others rotate by one position per round
+        int p, q;
+        if (pi == 0) {
+          p = 0;
+          q = 1 + round;
+        } else {
+          p = 1 + (round + pi) % (rp - 1);
+          q = 1 + (round - pi + rp - 1) % (rp - 1);
         }
-        const double ag = std::abs(g);
-        if (ag <= 1e-15 * std::sqrt(a * b) || ag == 0.0) continue;
-        rotated = true;
-        const cplx ph = g / ag;  // x_q' = conj(ph) x_q makes the inner product real
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= r) continue;
+        double2* xp = X + (size_t)p * n;
+        double2* xq = X + (size_t)q * n;
+        double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          const double2 u = xp[i], v = xq[i];
+          a += znorm(u);
+          b += znorm(v);
+          gr += u.x * v.x + u.y * v.y;
+          gi += u.x * v.y - u.y * v.x;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double ag = sqrt(gr * gr + gi * gi);
+        if (ag == 0.0 || ag <= 1e-15 * sqrt(a * b)) continue;
+        if (lane == 0) rotated = 1;
+        // x_q' = conj(ph) x_q makes the inner product real; then a real rotation
+        const double2 phc = make_double2(gr / ag, -gi / ag);
         const double zeta = (b - a) / (2.0 * ag);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
-        for (int i = 0; i < n; ++i) {
-          const cplx u = xp[i], v = std::conj(ph) * xq[i];
-          xp[i] = c * u - sn * v;
-          xq[i] = sn * u + c * v;
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+        for (int i = lane; i < n; i += 64) {
+          const double2 u = xp[i], v = zmul(phc, xq[i]);
+          xp[i] = zsub(zscale(u, c), zscale(v, sn));
+          xq[i] = zadd(zscale(u, sn), zscale(v, c));
         }
-        cplx* wp = &W[(size_t)p * s];
-        cplx* wq = &W[(size_t)q * s];
-        for (int i = 0; i < s; ++i) {
-          const cplx u = wp[i], v = std::conj(ph) * wq[i];
-          wp[i] = c * u - sn * v;
-          wq[i] = sn * u + c * v;
+        double2* wp = W + (size_t)p * r;
+        double2* wq = W + (size_t)q * r;
+        for (int i = lane; i < r; i += 64) {
+          const double2 u = wp[i], v = zmul(phc, wq[i]);
+          wp[i] = zsub(zscale(u, c), zscale(v, sn));
+          wq[i] = zadd(zscale(u, sn), zscale(v, c));
         }
       }
-    if (!rotated) break;
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
   }
-  std::vector<int> ord(s);
-  std::vector<double> nrm(s);
-  for (int j = 0; j < s; ++j) {
-    double a = 0;
-    for (int i = 0; i < n; ++i) a += std::norm(X[(size_t)j * n + i]);
-    nrm[j] = std::sqrt(a);
-    ord[j] = j;
+  for (int j = w; j < r; j += 4) {
+    double a = 0.0;
+    for (int i = lane; i < n; i += 64) a += znorm(X[(size_t)j * n + i]);
+    a = wave_sum(a);
+    if (lane == 0) nrm[j] = sqrt(a);
   }
-  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
-  sig.resize(s);
-  Z.assign((size_t)n * s, 0.0);
-  std::vector<cplx> W2((size_t)s * s);
-  for (int jj = 0; jj < s; ++jj) {
-    const int j = ord[jj];
-    sig[jj] = nrm[j];
-    for (int i = 0; i < s; ++i) W2[(size_t)jj * s + i] = W[(size_t)j * s + i];
-    if (nrm[j] > 0)
-      for (int i = 0; i < n; ++i) Z[(size_t)jj * n + i] = X[(size_t)j * n + i] / nrm[j];
+  __syncthreads();
+  if (t < r) {  // descending order, ties by index
+    int rank = 0;
+    for (int l = 0; l < r; ++l) rank += (nrm[l] > nrm[t] || (nrm[l] == nrm[t] && l < t)) ? 1 : 0;
+    ord[rank] = t;
   }
-  W.swap(W2);
+  __syncthreads();
+  const double s_next = rmax < r ? nrm[ord[rmax]] : 0.0;
+  const int ok = s_next < eps ? 1 : 0;
+  int k = 0;
+  while (k < r && k < rmax && nrm[ord[k]] >= eps) ++k;
+  if (t == 0) {
+    res[blockIdx.x].k = k;
+    res[blockIdx.x].ok = ok;
+  }
+  if (!ok) return;
+  double2* U = buf + nd.off[S_U];
+  double2* Vt = buf + nd.off[S_V];
+  for (int e = t; e < m * k; e += 256) {
+    const int i = e / k, c = e % k;
+    const double2* wc = W + (size_t)ord[c] * r;
+    double2 a = make_double2(0.0, 0.0);
+    for (int j = 0; j < r; ++j) a = zadd(a, zmul(Q[(size_t)j * m + i], wc[j]));
+    U[e] = zscale(a, nrm[ord[c]]);
+  }
+  for (int e = t; e < n * k; e += 256) {
+    const int i = e / k, c = e % k;
+    const double2 z = X[(size_t)ord[c] * n + i];
+    const double inv = 1.0 / nrm[ord[c]];
+    Vt[e] = make_double2(z.x * inv, -z.y * inv);
+  }
 }
 
-struct HostLeaf {
-  int r0, c0, m, n, k;  // k < 0: dense
-  std::vector<cplx> U, V, D;
-};
-
-struct Compressor {
-  int rmax;
-  double eps;
-  Rng rng;
-  std::vector<HostLeaf> out;
-
-  void dense(const View& M, int r0, int c0) {
-    HostLeaf lf{r0, c0, M.m, M.n, -1, {}, {}, {}};
-    lf.D.resize((size_t)M.m * M.n);
-    for (int i = 0; i < M.m; ++i)
-      for (int j = 0; j < M.n; ++j) lf.D[(size_t)i * M.n + j] = M.at(i, j);
-    out.push_back(std::move(lf));
-  }
-
-  // y = M x (x length n) and y = M^H x (x length m)
-  static void mv(const View& M, const cplx* x, cplx* y) {
-    for (int i = 0; i < M.m; ++i) {
-      cplx a = 0;
-      for (int j = 0; j < M.n; ++j) a += M.at(i, j) * x[j];
-      y[i] = a;
+// Posterior check of a candidate leaf with the four probes w_p (slot P4) and
+// M w_p (slot Y4): accepted iff ||M w_p - U (V w_p)|| <= eps ||w_p|| for all p.
+__global__ __launch_bounds__(256) void plr_probe_kernel(const CNode* __restrict__ nodes, CRes* __restrict__ res,
+                                                        const double2* __restrict__ buf, double eps) {
+  __shared__ double2 tv[kPlrMaxRank][4];
+  __shared__ double red[4];
+  const CNode& nd = nodes[blockIdx.x];
+  if (!res[blockIdx.x].ok) return;
+  const int m = nd.m, n = nd.n, k = res[blockIdx.x].k;
+  const double2* U = buf + nd.off[S_U];
+  const double2* Vt = buf + nd.off[S_V];
+  const double2* P4 = buf + nd.off[S_P4];
+  const double2* Y4 = buf + nd.off[S_Y4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = w; e < 4 * k; e += 4) {  // tv[c][p] = (V w_p)_c
+    const int c = e >> 2, p = e & 3;
+    double re = 0.0, im = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double2 v = zmul(Vt[(size_t)i * k + c], P4[(size_t)p * n + i]);
+      re += v.x;
+      im += v.y;
     }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) tv[c][p] = make_double2(re, im);
   }
-  static void mhv(const View& M, const cplx* x, cplx* y) {
-    for (int j = 0; j < M.n; ++j) y[j] = 0;
-    for (int i = 0; i < M.m; ++i)
-      for (int j = 0; j < M.n; ++j) y[j] += std::conj(M.at(i, j)) * x[i];
+  __syncthreads();
+  int good = 1;
+  for (int p = 0; p < 4; ++p) {
+    double en = 0.0, wn = 0.0;
+    for (int i = t; i < m; i += 256) {
+      double2 a = Y4[(size_t)p * m + i];
+      for (int c = 0; c < k; ++c) a = zsub(a, zmul(U[(size_t)i * k + c], tv[c][p]));
+      en += znorm(a);
+    }
+    for (int i = t; i < n; i += 256) wn += znorm(P4[(size_t)p * n + i]);
+    en = block_sum(en, red);
+    wn = block_sum(wn, red);
+    if (!(sqrt(en) <= eps * sqrt(wn))) good = 0;
   }
+  if (t == 0) res[blockIdx.x].ok = good;
+}
 
-  bool try_leaf(const View& M, int r0, int c0) {
-    const int m = M.m, n = M.n;
-    const int s = std::min(std::min(m, n), rmax + 1 + 10);
-    std::vector<cplx> Y((size_t)m * s), T((size_t)n * s), om(n);
-    for (int j = 0; j < s; ++j) {
-      for (int i = 0; i < n; ++i) om[i] = rng.normal();
-      mv(M, om.data(), &Y[(size_t)j * m]);
-    }
-    int r = orthonormalise(Y, m, s);
-    // one power iteration: Y = M (M^H Q)
-    for (int j = 0; j < r; ++j) mhv(M, &Y[(size_t)j * m], &T[(size_t)j * n]);
-    std::vector<cplx> Y2((size_t)m * r);
-    for (int j = 0; j < r; ++j) mv(M, &T[(size_t)j * n], &Y2[(size_t)j * m]);
-    r = orthonormalise(Y2, m, r);
-    // B = Q^H M (r x n, row-major)
-    std::vector<cplx> B((size_t)r * n);
-    for (int j = 0; j < r; ++j) {
-      mhv(M, &Y2[(size_t)j * m], &T[0]);  // row j of Q^H M is conj(M^H q_j)
-      for (int i = 0; i < n; ++i) B[(size_t)j * n + i] = std::conj(T[i]);
-    }
-    std::vector<double> sig;
-    std::vector<cplx> W, Z;
-    jacobi_svd(B, r, n, sig, W, Z);
-    const double s_next = rmax < r ? sig[rmax] : 0.0;
-    if (!(s_next < eps)) return false;
-    int k = 0;
-    while (k < r && k < rmax && sig[k] >= eps) ++k;
-    HostLeaf lf{r0, c0, m, n, k, {}, {}, {}};
-    lf.U.assign((size_t)m * k, 0.0);  // U = Q W(:, :k) diag(sigma), row-major m x k
-    for (int i = 0; i < m; ++i)
-      for (int c = 0; c < k; ++c) {
-        cplx a = 0;
-        for (int j = 0; j < r; ++j) a += Y2[(size_t)j * m + i] * W[(size_t)c * r + j];
-        lf.U[(size_t)i * k + c] = a * sig[c];
-      }
-    lf.V.assign((size_t)k * n, 0.0);  // V = Z(:, :k)^H, row-major k x n
-    for (int c = 0; c < k; ++c)
-      for (int i = 0; i < n; ++i) lf.V[(size_t)c * n + i] = std::conj(Z[(size_t)c * n + i]);
-    // posterior check with random probes: ||(M - U V) w|| <= eps ||w||
-    std::vector<cplx> w(n), y(m), t(k > 0 ? k : 1);
-    for (int probe = 0; probe < 4; ++probe) {
-      double wn = 0;
-      for (int i = 0; i < n; ++i) {
-        w[i] = rng.normal();
-        wn += std::norm(w[i]);
-      }
-      mv(M, w.data(), y.data());
-      for (int c = 0; c < k; ++c) {
-        cplx a = 0;
-        for (int i = 0; i < n; ++i) a += lf.V[(size_t)c * n + i] * w[i];
-        t[c] = a;
-      }
-      double en = 0;
-      for (int i = 0; i < m; ++i) {
-        cplx a = y[i];
-        for (int c = 0; c < k; ++c) a -= lf.U[(size_t)i * k + c] * t[c];
-        en += std::norm(a);
-      }
-      if (std::sqrt(en) > eps * std::sqrt(wn)) return false;
-    }
-    out.push_back(std::move(lf));
-    return true;
+// Copy accepted leaves into the packed data: a dense leaf from its block
+// (row-major m x n), a low-rank one as U (m x k) then V^T (n x k) from staging.
+__global__ __launch_bounds__(256) void plr_emit_kernel(const EmitRec* __restrict__ recs,
+                                                       const double2* __restrict__ blocks, int N,
+                                                       const double2* __restrict__ stage, double2* __restrict__ out) {
+  const EmitRec& e = recs[blockIdx.x];
+  if (e.k < 0) {
+    const double2* M = blocks + (size_t)e.blk * N * N + (size_t)e.r0 * N + e.c0;
+    for (int64_t x = threadIdx.x; x < (int64_t)e.m * e.n; x += blockDim.x)
+      out[e.dst + x] = M[(size_t)(x / e.n) * N + x % e.n];
+  } else {
+    const int64_t nu = (int64_t)e.m * e.k, nv = (int64_t)e.n * e.k;
+    for (int64_t x = threadIdx.x; x < nu; x += blockDim.x) out[e.dst + x] = stage[e.srcU + x];
+    for (int64_t x = threadIdx.x; x < nv; x += blockDim.x) out[e.dst + nu + x] = stage[e.srcV + x];
   }
+}
 
-  void compress(const View& M, int r0, int c0) {
-    if (std::min(M.m, M.n) <= rmax) {
-      dense(M, r0, c0);
-      return;
+// Dense N x N expansion of one compressed block (one workgroup per leaf; the
+// leaves tile the block, so every entry is written once).
+__global__ __launch_bounds__(256) void plr_expand_kernel(const PlrBlockDev* __restrict__ B, int N,
+                                                         double2* __restrict__ out) {
+  const PlrLeafDev L = B->leaves[blockIdx.x];
+  for (int64_t x = threadIdx.x; x < (int64_t)L.m * L.n; x += blockDim.x) {
+    const int i = (int)(x / L.n), j = (int)(x % L.n);
+    double2 v = make_double2(0.0, 0.0);
+    if (L.k < 0) {
+      v = B->data[L.offU + x];
+    } else {
+      for (int c = 0; c < L.k; ++c)
+        v = zadd(v, zmul(B->data[L.offU + (int64_t)i * L.k + c], B->data[L.offV + (int64_t)j * L.k + c]));
     }
-    if (try_leaf(M, r0, c0)) return;
-    const int m1 = (M.m + 1) / 2, n1 = (M.n + 1) / 2;
-    compress(View{M.p, m1, n1, M.ld}, r0, c0);
-    compress(View{M.p + n1, m1, M.n - n1, M.ld}, r0, c0 + n1);
-    compress(View{M.p + (size_t)m1 * M.ld, M.m - m1, n1, M.ld}, r0 + m1, c0);
-    compress(View{M.p + (size_t)m1 * M.ld + n1, M.m - m1, M.n - n1, M.ld}, r0 + m1, c0 + n1);
+    out[(size_t)(L.r0 + i) * N + L.c0 + j] = v;
   }
-};
+}
 
 // ----------------------------------------------------------------------------
 // online apply
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
 __device__ __forceinline__ double2* zbase(const Bases& b, int buf) {
   return buf == 0 ? b.b[0] : buf == 1 ? b.b[1] : buf == 2 ? b.b[2] : buf == 3 ? b.b[3] : nullptr;
 }
@@ -370,91 +559,246 @@ __global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restric
 
 size_t PlrSet::stored_entries(int b) const { return stored[b]; }
 
-hipError_t PlrSet::build(const std::vector<const std::complex<double>*>& blocks, int n, int rmax, double eps,
-                         int nthreads) {
-  release();
-  this->n = n;
-  const int nb = (int)blocks.size();
-  std::vector<std::vector<HostLeaf>> res(nb);
-  std::vector<std::thread> th;
-  const int T = std::max(1, std::min(nthreads, nb));
-  for (int w = 0; w < T; ++w)
-    th.emplace_back([&, w]() {
-      for (int b = w; b < nb; b += T) {
-        Compressor c{rmax, eps, Rng(0x5EED0000ull + (uint64_t)b), {}};
-        c.compress(View{reinterpret_cast<const cplx*>(blocks[b]), n, n, n}, 0, 0);
-        res[b] = std::move(c.out);
-      }
-    });
-  for (auto& t : th) t.join();
+namespace {
 
-  // flatten: per block, leaves + per-tile leaf lists + data
-  const int ntile = (n + 63) / 64;
+// device buffer that grows by doubling, keeping its contents (stream-ordered)
+struct Grow {
+  double2* p = nullptr;
+  size_t cap = 0;
+  hipError_t reserve(size_t want, hipStream_t st) {
+    if (want <= cap) return hipSuccess;
+    size_t nc = std::max<size_t>(want, 2 * cap);
+    double2* q = nullptr;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&q, nc * sizeof(double2))) != hipSuccess) return e;
+    if (cap && (e = hipMemcpyAsync(q, p, cap * sizeof(double2), hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (p) (void)hipFree(p);
+    p = q;
+    cap = nc;
+    return hipSuccess;
+  }
+};
+
+template <typename T>
+struct Tmp {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t fit(size_t want) {
+    if (want <= cap) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void**)&p, std::max<size_t>(1, want) * sizeof(T));
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  ~Tmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+hipError_t PlrSet::build(const double2* blocks, int nb, int N, int rmax, double eps, hipStream_t st) {
+  release();
+  this->n = N;
+  if (rmax < 1 || rmax > kPlrMaxRank) return hipErrorInvalidValue;
+  struct HN {
+    int blk, r0, c0, m, n;
+  };
+  struct HLeaf {
+    int blk, r0, c0, m, n, k;
+    int64_t off;
+  };
+  std::vector<HLeaf> hleaves;
+  std::vector<HN> cur;
+  for (int b = 0; b < nb; ++b) cur.push_back({b, 0, 0, N, N});
+  Grow data;
+  size_t used = 0;
+  Tmp<CNode> dnodes;
+  Tmp<CRes> dres;
+  Tmp<double2> stage;
+  Tmp<EmitRec> drec;
+  constexpr int64_t kStageCap = (int64_t)1 << 25;  // staging entries per batch of nodes (512 MiB)
+  const uint64_t seed = 0x5EED5EEDull;
+  hipError_t e;
+
+  // copy a list of leaves into the packed data (appending) and record them
+  auto emit = [&](std::vector<EmitRec>& recs) -> hipError_t {
+    if (recs.empty()) return hipSuccess;
+    size_t need = used;
+    for (EmitRec& r : recs) {
+      r.dst = (int64_t)need;
+      need += r.k < 0 ? (size_t)r.m * r.n : (size_t)(r.m + r.n) * r.k;
+      hleaves.push_back({r.blk, r.r0, r.c0, r.m, r.n, r.k, r.dst});
+    }
+    hipError_t er;
+    if ((er = data.reserve(need, st)) != hipSuccess) return er;
+    if ((er = drec.fit(recs.size())) != hipSuccess) return er;
+    if ((er = hipMemcpyAsync(drec.p, recs.data(), recs.size() * sizeof(EmitRec), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+      return er;
+    hipLaunchKernelGGL(plr_emit_kernel, dim3((unsigned)recs.size()), dim3(256), 0, st, drec.p, blocks, N, stage.p,
+                       data.p);
+    if ((er = hipGetLastError()) != hipSuccess) return er;
+    used = need;
+    // the record list and the staging buffer are reused by the next batch
+    return hipStreamSynchronize(st);
+  };
+
+  while (!cur.empty()) {
+    std::vector<HN> work, next;
+    std::vector<EmitRec> dense;
+    for (const HN& h : cur) {
+      if (std::min(h.m, h.n) <= rmax)
+        dense.push_back({h.blk, h.r0, h.c0, h.m, h.n, -1, 0, 0, 0});
+      else
+        work.push_back(h);
+    }
+    if ((e = emit(dense)) != hipSuccess) return e;
+    size_t w0 = 0;
+    while (w0 < work.size()) {
+      std::vector<CNode> cn;
+      int64_t so = 0;
+      int wide = 0;
+      size_t w1 = w0;
+      for (; w1 < work.size(); ++w1) {
+        const HN& h = work[w1];
+        const int s = std::min(std::min(h.m, h.n), rmax + 1 + 10);
+        const int64_t need = (int64_t)(3 * h.n + 2 * h.m) * s + (int64_t)s * s + 4 * (int64_t)(h.m + h.n);
+        if (!cn.empty() && so + need > kStageCap) break;
+        CNode c{};
+        c.blk = h.blk;
+        c.r0 = h.r0;
+        c.c0 = h.c0;
+        c.m = h.m;
+        c.n = h.n;
+        c.s = s;
+        const int64_t sz[S_NSLOT] = {(int64_t)h.n * s, (int64_t)h.m * s, (int64_t)h.n * s, (int64_t)s * s,
+                                     (int64_t)h.m * s, (int64_t)h.n * s, 4 * (int64_t)h.n, 4 * (int64_t)h.m};
+        for (int q = 0; q < S_NSLOT; ++q) {
+          c.off[q] = so;
+          so += sz[q];
+        }
+        wide = std::max(wide, std::max(h.m, h.n));
+        cn.push_back(c);
+      }
+      const int cnt = (int)cn.size();
+      if ((e = dnodes.fit(cnt)) != hipSuccess || (e = dres.fit(cnt)) != hipSuccess || (e = stage.fit(so)) != hipSuccess)
+        return e;
+      if ((e = hipMemcpyAsync(dnodes.p, cn.data(), cnt * sizeof(CNode), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+      const dim3 g1(cnt), gr(cnt, 8), gt(cnt, (wide + 63) / 64), b(256);
+      // range finder with one power iteration, then the SVD of B = Q^H M
+      hipLaunchKernelGGL(plr_random_kernel, gr, b, 0, st, dnodes.p, stage.p, (int)S_OM, 0, seed);
+      hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_OM,
+                         (int)S_Y, 0);
+      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 0);
+      hipLaunchKernelGGL(plr_panel_kernel<true>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_Y,
+                         (int)S_T, 1);
+      hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_T,
+                         (int)S_Y, 1);
+      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 1);
+      hipLaunchKernelGGL(plr_panel_kernel<true>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_Y,
+                         (int)S_T, 1);
+      hipLaunchKernelGGL(plr_svd_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, rmax, eps);
+      // posterior probes
+      hipLaunchKernelGGL(plr_random_kernel, gr, b, 0, st, dnodes.p, stage.p, (int)S_P4, 1, seed ^ 0xA5A5A5A5ull);
+      hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_P4,
+                         (int)S_Y4, 2);
+      hipLaunchKernelGGL(plr_probe_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, eps);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      std::vector<CRes> hr(cnt);
+      if ((e = hipMemcpyAsync(hr.data(), dres.p, cnt * sizeof(CRes), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return e;
+      std::vector<EmitRec> acc;
+      for (int i = 0; i < cnt; ++i) {
+        const CNode& c = cn[i];
+        if (hr[i].ok) {
+          acc.push_back({c.blk, c.r0, c.c0, c.m, c.n, hr[i].k, c.off[S_U], c.off[S_V], 0});
+        } else {
+          const int m1 = (c.m + 1) / 2, n1 = (c.n + 1) / 2;
+          next.push_back({c.blk, c.r0, c.c0, m1, n1});
+          next.push_back({c.blk, c.r0, c.c0 + n1, m1, c.n - n1});
+          next.push_back({c.blk, c.r0 + m1, c.c0, c.m - m1, n1});
+          next.push_back({c.blk, c.r0 + m1, c.c0 + n1, c.m - m1, c.n - n1});
+        }
+      }
+      if ((e = emit(acc)) != hipSuccess) return e;
+      w0 = w1;
+    }
+    cur.swap(next);
+  }
+
+  // per block: leaves (in the order found), per-tile leaf lists
+  const int ntile = (N + 63) / 64;
+  std::vector<std::vector<int>> per(nb);
+  for (size_t i = 0; i < hleaves.size(); ++i) per[hleaves[i].blk].push_back((int)i);
   std::vector<PlrLeafDev> hl;
   std::vector<int32_t> hptr, hlist;
-  std::vector<cplx> hdata;
   std::vector<PlrBlockDev> hb(nb);
-  std::vector<size_t> leaf0(nb), ptr0(nb), list0(nb), data0(nb);
+  std::vector<size_t> leaf0(nb), ptr0(nb), list0(nb);
   stored.assign(nb, 0);
-  for (int b = 0; b < nb; ++b) {
-    leaf0[b] = hl.size();
-    data0[b] = hdata.size();
-    for (const HostLeaf& lf : res[b]) {
+  nleaves.assign(nb, 0);
+  for (int bb = 0; bb < nb; ++bb) {
+    leaf0[bb] = hl.size();
+    for (int i : per[bb]) {
+      const HLeaf& lf = hleaves[i];
       PlrLeafDev d{};
       d.r0 = lf.r0;
       d.c0 = lf.c0;
       d.m = lf.m;
       d.n = lf.n;
       d.k = lf.k;
-      if (lf.k < 0) {
-        d.offU = (int64_t)(hdata.size() - data0[b]);
-        hdata.insert(hdata.end(), lf.D.begin(), lf.D.end());
-        stored[b] += lf.D.size();
-      } else {
-        d.offU = (int64_t)(hdata.size() - data0[b]);
-        hdata.insert(hdata.end(), lf.U.begin(), lf.U.end());
-        // V stored transposed (n x k): the apply reads one column's k values per step
-        d.offV = (int64_t)(hdata.size() - data0[b]);
-        for (int i = 0; i < lf.n; ++i)
-          for (int c = 0; c < lf.k; ++c) hdata.push_back(lf.V[(size_t)c * lf.n + i]);
-        stored[b] += lf.U.size() + lf.V.size();
-      }
+      d.offU = lf.off;
+      d.offV = lf.k < 0 ? 0 : lf.off + (int64_t)lf.m * lf.k;
+      stored[bb] += lf.k < 0 ? (size_t)lf.m * lf.n : (size_t)(lf.m + lf.n) * lf.k;
       hl.push_back(d);
     }
-    ptr0[b] = hptr.size();
-    list0[b] = hlist.size();
+    nleaves[bb] = (int)per[bb].size();
+    ptr0[bb] = hptr.size();
+    list0[bb] = hlist.size();
     hptr.push_back(0);
     for (int t = 0; t < ntile; ++t) {
-      const int a = t * 64, e = std::min(n, a + 64);
-      for (int i = 0; i < (int)res[b].size(); ++i) {
-        const HostLeaf& lf = res[b][i];
-        if (lf.r0 < e && lf.r0 + lf.m > a) hlist.push_back(i);
+      const int a = t * 64, z = std::min(N, a + 64);
+      for (int i = 0; i < (int)per[bb].size(); ++i) {
+        const PlrLeafDev& lf = hl[leaf0[bb] + i];
+        if (lf.r0 < z && lf.r0 + lf.m > a) hlist.push_back(i);
       }
-      hptr.push_back((int32_t)(hlist.size() - list0[b]));
+      hptr.push_back((int32_t)(hlist.size() - list0[bb]));
     }
-    nleaves_total += res[b].size();
+    nleaves_total += per[bb].size();
   }
-  hipError_t e;
+  d_data = data.p;  // owned from here on
+  data.p = nullptr;
   if ((e = hipMalloc((void**)&d_leaves, std::max<size_t>(1, hl.size()) * sizeof(PlrLeafDev))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&d_ptr, std::max<size_t>(1, hptr.size()) * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&d_list, std::max<size_t>(1, hlist.size()) * sizeof(int32_t))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&d_data, std::max<size_t>(1, hdata.size()) * sizeof(double2))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&d_blocks, std::max(1, nb) * sizeof(PlrBlockDev))) != hipSuccess) return e;
-  for (int b = 0; b < nb; ++b) {
-    hb[b].nleaves = (int)res[b].size();
-    hb[b].ntile = ntile;
-    hb[b].leaves = d_leaves + leaf0[b];
-    hb[b].tile_ptr = d_ptr + ptr0[b];
-    hb[b].tile_leaf = d_list + list0[b];
-    hb[b].data = d_data + data0[b];
+  for (int bb = 0; bb < nb; ++bb) {
+    hb[bb].nleaves = nleaves[bb];
+    hb[bb].ntile = ntile;
+    hb[bb].leaves = d_leaves + leaf0[bb];
+    hb[bb].tile_ptr = d_ptr + ptr0[bb];
+    hb[bb].tile_leaf = d_list + list0[bb];
+    hb[bb].data = d_data;  // leaf offsets are global
   }
   if ((e = hipMemcpy(d_leaves, hl.data(), hl.size() * sizeof(PlrLeafDev), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(d_ptr, hptr.data(), hptr.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(d_list, hlist.data(), hlist.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
-  if ((e = hipMemcpy(d_data, hdata.data(), hdata.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(d_blocks, hb.data(), nb * sizeof(PlrBlockDev), hipMemcpyHostToDevice)) != hipSuccess) return e;
-  data_entries = hdata.size();
+  data_entries = used;
   return hipSuccess;
+}
+
+hipError_t PlrSet::expand(int b, double2* out, hipStream_t st) const {
+  if (b < 0 || b >= (int)nleaves.size()) return hipErrorInvalidValue;
+  if (nleaves[b] == 0) return hipSuccess;
+  hipLaunchKernelGGL(plr_expand_kernel, dim3((unsigned)nleaves[b]), dim3(256), 0, st, d_blocks + b, n, out);
+  return hipGetLastError();
 }
 
 void PlrSet::release() {
@@ -469,6 +813,8 @@ void PlrSet::release() {
   d_blocks = nullptr;
   data_entries = 0;
   nleaves_total = 0;
+  stored.clear();
+  nleaves.clear();
 }
 
 hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,

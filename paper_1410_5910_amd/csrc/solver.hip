@@ -2203,19 +2203,12 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
       return bail(fail(PT_EHIP, "trace maps"));
   }
 
-  // partitioned low-rank form of the trace blocks (compressed on the host)
+  // partitioned low-rank form of the trace blocks (Alg. 5, compressed on the GPU)
   if (opt->plr && S->L >= 2) {
-    const size_t E = S->block_elems();
-    std::vector<std::complex<double>> host((size_t)S->nblk * E);
-    if (hipMemcpy(host.data(), S->blk64.p, host.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess)
-      return bail(fail(PT_EHIP, "download blocks"));
-    std::vector<const std::complex<double>*> ptrs(S->nblk);
-    for (int b = 0; b < S->nblk; ++b) ptrs[b] = host.data() + (size_t)b * E;
     int rmax = opt->plr_rmax > 0 ? opt->plr_rmax : (int)std::ceil(std::sqrt((double)NX));
     rmax = std::min(rmax, kPlrMaxRank);
-    const unsigned hw = std::thread::hardware_concurrency();
-    if (S->plr.build(ptrs, NX, rmax, opt->plr_eps, (int)std::max(1u, std::min(hw, 16u))) != hipSuccess)
-      return bail(fail(PT_ENOMEM, "PLR blocks"));
+    const hipError_t pe = S->plr.build(S->blk64.p, S->nblk, NX, rmax, opt->plr_eps, S->st);
+    if (pe != hipSuccess) return bail(fail(pe == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP, "PLR compression"));
     S->use_plr = true;
   }
 
@@ -2293,10 +2286,12 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   return PT_OK;
 }
 
-pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, double* out) {
-  if (!S || !out) return fail(PT_EINVAL, "null argument");
+namespace {
+
+// stored block id, sign and diagonal shift of K^l_{j,k}: block = sign * K + shift * I
+// (inverse of the packing in extract_blocks)
+pt_status block_of(const pt_solver* S, int32_t layer, int32_t j, int32_t k, int* id, double* sign, double* shift) {
   if (layer < 0 || layer >= S->L || j < 0 || j > 3 || k < 0 || k > 3) return fail(PT_EINVAL, "bad block index");
-  // K_{j,k} = sign * block(type, a, b) + shift I (inverse of the packing in extract_blocks)
   static const int T[4][4] = {{B_DN, B_DN, T_UP, T_UP}, {B_DN, B_DN, T_UP, T_UP}, {T_DN, T_DN, B_UP, B_UP},
                               {T_DN, T_DN, B_UP, B_UP}};
   // (a, b, sign, shift) for each (j, k); rows: j in {0,1,n,n+1}, cols: k
@@ -2310,10 +2305,32 @@ pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, 
       {{0, 1, -1, 0}, {0, 0, 1, 0}, {0, 1, 1, 0}, {0, 0, -1, -1}},
       {{1, 1, -1, 0}, {1, 0, 1, 0}, {1, 1, 1, 0}, {1, 0, -1, 0}},
   };
-  const int type = T[j][k];
   const E e = M[j][k];
-  const int id = S->bidx[((layer * 4 + type) * 2 + e.a) * 2 + e.b];
-  if (id < 0) return fail(PT_EINVAL, "layer has no such trace rows");
+  *id = S->bidx[((layer * 4 + T[j][k]) * 2 + e.a) * 2 + e.b];
+  if (*id < 0) return fail(PT_EINVAL, "layer has no such trace rows");
+  *sign = e.sign;
+  *shift = e.shift;
+  return PT_OK;
+}
+
+void unpack_block(const std::vector<double2>& col, int NX, double sign, double shift, double* out) {
+  for (int i = 0; i < NX; ++i)
+    for (int c = 0; c < NX; ++c) {
+      double2 v = col[(size_t)i * NX + c];  // stored row-major
+      if (i == c) v.x -= shift;             // block = sign*K + shift*I  =>  K = sign*(block - shift*I)
+      out[2 * ((size_t)i * NX + c)] = sign * v.x;
+      out[2 * ((size_t)i * NX + c) + 1] = sign * v.y;
+    }
+}
+
+}  // namespace
+
+pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, double* out) {
+  if (!S || !out) return fail(PT_EINVAL, "null argument");
+  int id;
+  double sign, shift;
+  const pt_status st = block_of(S, layer, j, k, &id, &sign, &shift);
+  if (st != PT_OK) return st;
   const size_t n = S->block_elems();
   std::vector<double2> col(n);
   if (S->f32) {
@@ -2323,14 +2340,30 @@ pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, 
   } else {
     HIPCHK(hipMemcpy(col.data(), S->blk64.p + (size_t)id * n, n * sizeof(double2), hipMemcpyDeviceToHost));
   }
-  const int NX = S->NX;
-  for (int i = 0; i < NX; ++i)
-    for (int c = 0; c < NX; ++c) {
-      double2 v = col[(size_t)i * NX + c];  // stored row-major
-      if (i == c) v.x -= e.shift;           // block = sign*K + shift*I  =>  K = sign*(block - shift*I)
-      out[2 * ((size_t)i * NX + c)] = e.sign * v.x;
-      out[2 * ((size_t)i * NX + c) + 1] = e.sign * v.y;
-    }
+  unpack_block(col, S->NX, sign, shift, out);
+  return PT_OK;
+}
+
+pt_status pt_get_plr_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, double* out, int32_t* nleaves,
+                           int64_t* stored) {
+  if (!S || !out) return fail(PT_EINVAL, "null argument");
+  if (!S->use_plr) return fail(PT_EINVAL, "solver has no compressed blocks (plr = 0)");
+  int id;
+  double sign, shift;
+  const pt_status st = block_of(S, layer, j, k, &id, &sign, &shift);
+  if (st != PT_OK) return st;
+  const size_t n = S->block_elems();
+  double2* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, n * sizeof(double2)));
+  std::vector<double2> col(n);
+  hipError_t e = S->plr.expand(id, d, S->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(col.data(), d, n * sizeof(double2), hipMemcpyDeviceToHost, S->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(PT_EHIP, hipGetErrorString(e));
+  unpack_block(col, S->NX, sign, shift, out);
+  if (nleaves) *nleaves = S->plr.nleaves[id];
+  if (stored) *stored = (int64_t)S->plr.stored_entries(id);
   return PT_OK;
 }
 

@@ -26,6 +26,7 @@ OP_A_EXTRAP, OP_R_EXTRAP, OP_DINV_EXTRAP, OP_PRECOND_EXTRAP = 4, 5, 6, 7
 ROWS = {"0": 0, "1": 1, "n": 2, "n+1": 3}
 
 EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", "pt_get_layout", "pt_get_block",
+           "pt_get_plr_block",
            "pt_apply", "pt_local_solve", "pt_trace_rhs", "pt_reconstruct", "pt_profile", "pt_profile_read",
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
@@ -101,6 +102,7 @@ def lib():
         L.pt_last_error.restype = C.c_char_p
         L.pt_get_layout.argtypes = [vp, C.POINTER(PtLayout)]
         L.pt_get_block.argtypes = [vp, i32, i32, i32, dp]
+        L.pt_get_plr_block.argtypes = [vp, i32, i32, i32, dp, C.POINTER(i32), C.POINTER(C.c_int64)]
         L.pt_apply.argtypes = [vp, i32, i32, vp, vp, i32]
         L.pt_local_solve.argtypes = [vp, i32, vp, vp, i32]
         L.pt_trace_rhs.argtypes = [vp, i32, vp, vp, i32]
@@ -233,6 +235,14 @@ class Solver:
         _check(self._lib.pt_get_block(self._h, layer, ROWS[j], ROWS[k],
                                       out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def get_plr_block(self, layer: int, j: str, k: str):
+        """The same block expanded from its compressed (PLR) form: (matrix, leaves, stored complex entries)."""
+        out = np.empty((self.NX, self.NX), dtype=np.complex128)
+        nl, ns = C.c_int32(0), C.c_int64(0)
+        _check(self._lib.pt_get_plr_block(self._h, layer, ROWS[j], ROWS[k],
+                                          out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nl), C.byref(ns)))
+        return out, int(nl.value), int(ns.value)
 
     # -------------------------------------------------------------- marshalling
     def _prep(self, a, shape_tail):
