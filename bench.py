@@ -167,6 +167,9 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
            "iterations": sorted(set(i["iters"] for i in info)),
            "max_true_relres": max(i["relres"] for i in info), "block_bytes": lay["block_bytes"],
            "factor_bytes": lay["factor_bytes"]}
+    if plr:
+        out.update({"plr_compress_ms": lay["plr_ms"], "plr_leaves": lay["plr_leaves"],
+                    "plr_ratio": lay["block_bytes"] / lay["dense_block_bytes"]})
     if profile:
         s.profile(True)
         nprof = max(1, min(steps, 3))

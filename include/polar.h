@@ -100,7 +100,8 @@ typedef struct {
   int32_t maxit;     /* GMRES iterations (no restart), 1..200                     */
   int32_t max_nrhs;  /* largest nrhs pt_solve will be called with, >= 1           */
   int32_t plr;       /* 1: store and apply the trace blocks in partitioned
-                        low-rank form (Alg. 5 / Alg. 6); float64 only          */
+                        low-rank form (Alg. 5 / Alg. 6), compressed on the GPU
+                        at setup; float64 only                                  */
   double plr_eps;    /* absolute singular-value threshold of a leaf, > 0        */
   int32_t plr_rmax;  /* leaf rank limit, 1..64 (0: ceil(sqrt(NX)))              */
   int32_t use_graph; /* 1: each GMRES iteration's launches (preconditioner,
@@ -159,6 +160,8 @@ typedef struct {
   int64_t plr_leaves;   /* leaves of all compressed blocks (0 without PLR)         */
   int64_t green_bytes;  /* device bytes of the interface Green's functions of the
                            pre-solve (0: line-by-line pre-solve)                 */
+  double plr_ms;        /* wall time of the GPU compression inside pt_setup
+                           (0 without PLR)                                        */
 } pt_layout;
 
 typedef struct pt_solver pt_solver;

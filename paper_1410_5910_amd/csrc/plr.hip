@@ -7,9 +7,10 @@
 // into four (ceil/floor halves) and each quarter is compressed; a block whose
 // smaller side is <= r_max is a dense leaf.  The singular values are those of
 // a randomized sketch (Section 7: the compression uses a randomized SVD):
-// Y = M Omega with s = r_max + 1 + 10 Gaussian columns, one power iteration
-// Y = M (M^H Q) with re-orthonormalisation, B = Q^H M, and a one-sided
-// (Hestenes) Jacobi SVD of B, which keeps the small singular values accurate.
+// Y = M Omega with s = r_max + 1 + 10 Gaussian columns (at most 70), one power
+// iteration Y = M (M^H Q) with re-orthonormalisation, B = Q^H M, and the SVD
+// of B from X = B^H = Q2 R and a one-sided (Hestenes) Jacobi SVD of the small
+// factor R, which keeps the small singular values accurate.
 // A candidate leaf is accepted only if four random probes see an error below
 // eps.  The leaves are applied in the factored form y[rows] += U (V x[cols])
 // of the paper's Alg. 6 / sparse-factorised product.
@@ -43,16 +44,19 @@ __device__ __forceinline__ double znorm(double2 a) { return a.x * a.x + a.y * a.
 // ----------------------------------------------------------------------------
 // compression (setup)
 // ----------------------------------------------------------------------------
-constexpr int kSMax = kPlrMaxRank + 1 + 10;  // widest sketch
+// widest sketch: r_max + 1 + 10 columns, at most 70 so that the Jacobi SVD's
+// two s x s factors fit the 160 KiB of LDS (the oversampling drops to 5 at r_max = 64)
+constexpr int kSMax = 70;
 constexpr int kCpw = (kSMax + 3) / 4;        // product columns per wave (4 waves)
 constexpr int kKc = 16;                      // inner-dimension chunk of the products
+constexpr int kGsq = 6;                      // Gram-Schmidt dot products per wave and pass
 
 // per-node staging slots (complex entries, column-major unless noted)
 enum Slot {
   S_OM = 0,  // Omega, n x s
   S_Y,       // Y = M Omega, then Q (m x s)
-  S_T,       // M^H Q (n x s); at the end X = B^H, rotated into Z diag(sigma)
-  S_W,       // Jacobi rotations, s x s
+  S_T,       // M^H Q (n x s); at the end X = B^H, then Q2 of X = Q2 R
+  S_R,       // R of X = Q2 R (column-major, leading dimension s)
   S_U,       // leaf U = Q W diag(sigma), m x k row-major
   S_V,       // leaf V^T, n x k row-major (V = Z^H)
   S_P4,      // probe vectors, n x 4
@@ -65,9 +69,10 @@ struct CNode {
   int64_t off[S_NSLOT];
 };
 
-// per-node results: r = orthonormal sketch rank, k = leaf rank, ok = accepted
+// per-node results: r = orthonormal sketch rank, r2 = rank of X = B^H, k = leaf
+// rank, ok = accepted
 struct CRes {
-  int32_t r, k, ok, pad;
+  int32_t r, r2, k, ok;
 };
 
 // A leaf to copy into the packed data: k < 0 dense (from the block), else U
@@ -100,6 +105,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   // xor butterfly: every lane ends with the same bits (each step adds a pair in both orders)
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over an aligned group of 16 lanes (same bits in every lane of the group)
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
   return v;
 }
 
@@ -197,42 +209,64 @@ __global__ __launch_bounds__(256) void plr_panel_kernel(const CNode* __restrict_
   }
 }
 
-// Orthonormalise the columns of slot `slot` (m x cols, cols = s or the node's
-// current r) in place: classical Gram-Schmidt applied twice per column, a
-// column whose remaining norm is below 1e-14 of its original norm dropped, the
-// kept ones compacted to the front; res.r = the number kept.  One workgroup per
+// Orthonormalise the columns of slot `slot` (m x cols, m = the node's outer
+// size `rows`, cols = s or the node's current r) in place: classical
+// Gram-Schmidt applied twice per column, a column whose remaining norm is below
+// 1e-14 of its original norm dropped, the kept ones compacted to the front.
+// Without R (rslot < 0) res.r = the number kept; with R, res.r2 = that number
+// and slot rslot holds R (column j: the coefficients of input column j on the
+// kept columns, leading dimension s), so input = kept R.  One workgroup per
 // node; the column being orthogonalised lives in global memory (L2-resident).
 __global__ __launch_bounds__(256) void plr_orth_kernel(const CNode* __restrict__ nodes, CRes* __restrict__ res,
-                                                       double2* __restrict__ buf, int slot, int use_r) {
+                                                       double2* __restrict__ buf, int slot, int use_r, int by_n,
+                                                       int rslot) {
   __shared__ double2 d[kSMax];
   __shared__ double red[4];
   const CNode& nd = nodes[blockIdx.x];
-  const int m = nd.m;
+  const int m = by_n ? nd.n : nd.m;
   const int cols = use_r ? res[blockIdx.x].r : nd.s;
   double2* Y = buf + nd.off[slot];
+  double2* R = rslot >= 0 ? buf + nd.off[rslot] : nullptr;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int r = 0;
   for (int j = 0; j < cols; ++j) {
     double2* yj = Y + (size_t)j * m;
+    if (R && t < nd.s) R[(size_t)j * nd.s + t] = make_double2(0.0, 0.0);
     double s0 = 0.0;
     for (int i = t; i < m; i += 256) s0 += znorm(yj[i]);
     const double n0 = sqrt(block_sum(s0, red));
     for (int pass = 0; pass < 2; ++pass) {
-      for (int q = w; q < r; q += 4) {  // d[q] = q-th basis column^H y
-        const double2* uq = Y + (size_t)q * m;
-        double re = 0.0, im = 0.0;
+      // d[q] = q-th basis column^H y; wave w takes q = w, w + 4, ..., kGsq of them per pass over the rows
+      for (int qb = 0; qb < r; qb += 4 * kGsq) {
+        double re[kGsq], im[kGsq];
+#pragma unroll
+        for (int u = 0; u < kGsq; ++u) re[u] = im[u] = 0.0;
         for (int i = lane; i < m; i += 64) {
-          const double2 a = uq[i], b = yj[i];
-          re += a.x * b.x + a.y * b.y;
-          im += a.x * b.y - a.y * b.x;
+          const double2 b = yj[i];
+#pragma unroll
+          for (int u = 0; u < kGsq; ++u) {
+            const int q = qb + w + 4 * u;
+            if (q < r) {
+              const double2 a = Y[(size_t)q * m + i];
+              re[u] += a.x * b.x + a.y * b.y;
+              im[u] += a.x * b.y - a.y * b.x;
+            }
+          }
         }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) d[q] = make_double2(re, im);
+#pragma unroll
+        for (int u = 0; u < kGsq; ++u) {
+          const int q = qb + w + 4 * u;
+          if (q < r) {  // uniform over the wave
+            const double x = wave_sum(re[u]), y = wave_sum(im[u]);
+            if (lane == 0) d[q] = make_double2(x, y);
+          }
+        }
       }
       __syncthreads();
+      if (R && t < r) R[(size_t)j * nd.s + t] = zadd(R[(size_t)j * nd.s + t], d[t]);
       for (int i = t; i < m; i += 256) {
         double2 v = yj[i];
+#pragma unroll 8
         for (int q = 0; q < r; ++q) v = zsub(v, zmul(Y[(size_t)q * m + i], d[q]));
         yj[i] = v;
       }
@@ -245,39 +279,56 @@ __global__ __launch_bounds__(256) void plr_orth_kernel(const CNode* __restrict__
     const double inv = 1.0 / nn;
     double2* dst = Y + (size_t)r * m;
     for (int i = t; i < m; i += 256) dst[i] = zscale(yj[i], inv);
+    if (R && t == 0) R[(size_t)j * nd.s + r] = make_double2(nn, 0.0);
     __syncthreads();
     ++r;
   }
-  if (t == 0) res[blockIdx.x].r = r;
+  if (t == 0) {
+    if (R)
+      res[blockIdx.x].r2 = r;
+    else
+      res[blockIdx.x].r = r;
+  }
 }
 
-// One-sided Jacobi SVD of B = Q^H M (r x n) through X = B^H = M^H Q (slot T,
-// n x r): pairs of columns are rotated until mutually orthogonal, X W = Z
-// diag(sigma), so B = W diag(sigma) Z^H.  Disjoint pairs in round-robin order
-// (one wave per pair, r - 1 rounds per sweep, a sweep without rotations ends
-// it).  Then sigma = column norms sorted descending, the leaf decision of
-// Alg. 5 (sigma_{r_max+1} < eps), k = #{sigma >= eps, first r_max}, and for a
-// candidate leaf U = Q W(:, :k) diag(sigma) (slot U) and V^T = conj(Z(:, :k))
-// (slot V).  One workgroup per node.
+// SVD of B = Q^H M (r x n) from X = B^H = M^H Q = Q2 R (slots T and R; R is
+// r2 x r): a one-sided Jacobi SVD of R, whose columns are rotated until
+// mutually orthogonal, R W = Z' diag(sigma), so X W = (Q2 Z') diag(sigma) and
+// B = W diag(sigma) (Q2 Z')^H.  R and W sit in LDS (leading dimension ld);
+// disjoint pairs in round-robin order (16 lanes per pair, 16 pairs at a time,
+// r - 1 rounds per sweep, a sweep without rotations ends it).  Then sigma = column norms sorted
+// descending, the leaf decision of Alg. 5 (sigma_{r_max+1} < eps), k =
+// #{sigma >= eps, first r_max}, and for a candidate leaf U = Q W(:, :k)
+// diag(sigma) (slot U) and V^T = conj(Q2 Z'(:, :k)) (slot V).  One workgroup
+// per node.
 __global__ __launch_bounds__(256) void plr_svd_kernel(const CNode* __restrict__ nodes, CRes* __restrict__ res,
-                                                      double2* __restrict__ buf, int rmax, double eps) {
+                                                      double2* __restrict__ buf, int ld, int rmax, double eps) {
+  extern __shared__ double2 lds[];
   __shared__ double nrm[kSMax];
   __shared__ int ord[kSMax];
   __shared__ int rotated;
+  double2* Xs = lds;            // R, then R W: column j at j * ld, rows < r2
+  double2* Ws = lds + ld * ld;  // W: column j at j * ld, rows < r
   const CNode& nd = nodes[blockIdx.x];
-  const int n = nd.n, m = nd.m, r = res[blockIdx.x].r;
-  double2* X = buf + nd.off[S_T];
-  double2* W = buf + nd.off[S_W];
+  const int n = nd.n, m = nd.m, r = res[blockIdx.x].r, r2 = res[blockIdx.x].r2;
+  const double2* Rg = buf + nd.off[S_R];
   const double2* Q = buf + nd.off[S_Y];
+  const double2* Q2 = buf + nd.off[S_T];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < r * r; e += 256) W[e] = make_double2(e % r == e / r ? 1.0 : 0.0, 0.0);
+  for (int e = t; e < r * r; e += 256) {
+    const int i = e % r, j = e / r;
+    Xs[j * ld + i] = i < r2 ? Rg[(size_t)j * nd.s + i] : make_double2(0.0, 0.0);
+    Ws[j * ld + i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
   __syncthreads();
   const int rp = r + (r & 1);  // a phantom column when r is odd
+  const double tol = 2.220446049250313e-16 * fmax(1.0, (double)r2);
+  const int slot = t >> 4, sl = t & 15;  // 16 pair slots of 16 lanes
   for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < rp - 1; ++round) {
-      for (int pi = w; pi < rp / 2; pi += 4) {
+      for (int pi = slot; pi < rp / 2; pi += 16) {
         // circle method: column 0 fixed, the others rotate by one position per round
         int p, q;
         if (pi == 0) {
@@ -293,36 +344,37 @@ __global__ __launch_bounds__(256) void plr_svd_kernel(const CNode* __restrict__ 
           q = tmp;
         }
         if (q >= r) continue;
-        double2* xp = X + (size_t)p * n;
-        double2* xq = X + (size_t)q * n;
+        double2* xp = Xs + p * ld;
+        double2* xq = Xs + q * ld;
         double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = sl; i < r2; i += 16) {
           const double2 u = xp[i], v = xq[i];
           a += znorm(u);
           b += znorm(v);
           gr += u.x * v.x + u.y * v.y;
           gi += u.x * v.y - u.y * v.x;
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        gr = wave_sum(gr);
-        gi = wave_sum(gi);
+        a = group16_sum(a);
+        b = group16_sum(b);
+        gr = group16_sum(gr);
+        gi = group16_sum(gi);
         const double ag = sqrt(gr * gr + gi * gi);
-        if (ag == 0.0 || ag <= 1e-15 * sqrt(a * b)) continue;
-        if (lane == 0) rotated = 1;
+        // orthogonal to working accuracy: the rounding of a length-r2 inner product
+        if (ag == 0.0 || ag <= tol * sqrt(a * b)) continue;
+        if (sl == 0) rotated = 1;
         // x_q' = conj(ph) x_q makes the inner product real; then a real rotation
         const double2 phc = make_double2(gr / ag, -gi / ag);
         const double zeta = (b - a) / (2.0 * ag);
         const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = sl; i < r2; i += 16) {
           const double2 u = xp[i], v = zmul(phc, xq[i]);
           xp[i] = zsub(zscale(u, c), zscale(v, sn));
           xq[i] = zadd(zscale(u, sn), zscale(v, c));
         }
-        double2* wp = W + (size_t)p * r;
-        double2* wq = W + (size_t)q * r;
-        for (int i = lane; i < r; i += 64) {
+        double2* wp = Ws + p * ld;
+        double2* wq = Ws + q * ld;
+        for (int i = sl; i < r; i += 16) {
           const double2 u = wp[i], v = zmul(phc, wq[i]);
           wp[i] = zsub(zscale(u, c), zscale(v, sn));
           wq[i] = zadd(zscale(u, sn), zscale(v, c));
@@ -336,7 +388,7 @@ __global__ __launch_bounds__(256) void plr_svd_kernel(const CNode* __restrict__ 
   }
   for (int j = w; j < r; j += 4) {
     double a = 0.0;
-    for (int i = lane; i < n; i += 64) a += znorm(X[(size_t)j * n + i]);
+    for (int i = lane; i < r2; i += 64) a += znorm(Xs[j * ld + i]);
     a = wave_sum(a);
     if (lane == 0) nrm[j] = sqrt(a);
   }
@@ -358,18 +410,41 @@ __global__ __launch_bounds__(256) void plr_svd_kernel(const CNode* __restrict__ 
   if (!ok) return;
   double2* U = buf + nd.off[S_U];
   double2* Vt = buf + nd.off[S_V];
-  for (int e = t; e < m * k; e += 256) {
-    const int i = e / k, c = e % k;
-    const double2* wc = W + (size_t)ord[c] * r;
-    double2 a = make_double2(0.0, 0.0);
-    for (int j = 0; j < r; ++j) a = zadd(a, zmul(Q[(size_t)j * m + i], wc[j]));
-    U[e] = zscale(a, nrm[ord[c]]);
-  }
-  for (int e = t; e < n * k; e += 256) {
-    const int i = e / k, c = e % k;
-    const double2 z = X[(size_t)ord[c] * n + i];
-    const double inv = 1.0 / nrm[ord[c]];
-    Vt[e] = make_double2(z.x * inv, -z.y * inv);
+  // one thread per row, 16 ranks at a time: the basis entries load coalesced
+  // across the workgroup, the rotation columns are LDS broadcasts
+  for (int c0 = 0; c0 < k; c0 += 16) {
+    const int kc = min(16, k - c0);
+    for (int i = t; i < m; i += 256) {  // U = Q W(:, ord) diag(sigma)
+      double2 a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = make_double2(0.0, 0.0);
+      for (int j = 0; j < r; ++j) {
+        const double2 q = Q[(size_t)j * m + i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < kc) a[c] = zadd(a[c], zmul(q, Ws[ord[c0 + c] * ld + j]));
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < kc) U[(size_t)i * k + c0 + c] = zscale(a[c], nrm[ord[c0 + c]]);
+    }
+    for (int i = t; i < n; i += 256) {  // V^T = conj(Q2 Z'(:, ord)), Z' = R W diag(sigma)^-1
+      double2 a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = make_double2(0.0, 0.0);
+      for (int j = 0; j < r2; ++j) {
+        const double2 q = Q2[(size_t)j * n + i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < kc) a[c] = zadd(a[c], zmul(q, Xs[ord[c0 + c] * ld + j]));
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < kc) {
+          const double inv = 1.0 / nrm[ord[c0 + c]];
+          Vt[(size_t)i * k + c0 + c] = make_double2(a[c].x * inv, -a[c].y * inv);
+        }
+    }
   }
 }
 
@@ -662,11 +737,11 @@ hipError_t PlrSet::build(const double2* blocks, int nb, int N, int rmax, double 
     while (w0 < work.size()) {
       std::vector<CNode> cn;
       int64_t so = 0;
-      int wide = 0;
+      int wide = 0, smax = 1;
       size_t w1 = w0;
       for (; w1 < work.size(); ++w1) {
         const HN& h = work[w1];
-        const int s = std::min(std::min(h.m, h.n), rmax + 1 + 10);
+        const int s = std::min(std::min(std::min(h.m, h.n), rmax + 1 + 10), kSMax);
         const int64_t need = (int64_t)(3 * h.n + 2 * h.m) * s + (int64_t)s * s + 4 * (int64_t)(h.m + h.n);
         if (!cn.empty() && so + need > kStageCap) break;
         CNode c{};
@@ -683,6 +758,7 @@ hipError_t PlrSet::build(const double2* blocks, int nb, int N, int rmax, double 
           so += sz[q];
         }
         wide = std::max(wide, std::max(h.m, h.n));
+        smax = std::max(smax, s);
         cn.push_back(c);
       }
       const int cnt = (int)cn.size();
@@ -695,15 +771,21 @@ hipError_t PlrSet::build(const double2* blocks, int nb, int N, int rmax, double 
       hipLaunchKernelGGL(plr_random_kernel, gr, b, 0, st, dnodes.p, stage.p, (int)S_OM, 0, seed);
       hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_OM,
                          (int)S_Y, 0);
-      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 0);
+      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 0, 0, -1);
       hipLaunchKernelGGL(plr_panel_kernel<true>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_Y,
                          (int)S_T, 1);
       hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_T,
                          (int)S_Y, 1);
-      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 1);
+      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_Y, 1, 0, -1);
       hipLaunchKernelGGL(plr_panel_kernel<true>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_Y,
                          (int)S_T, 1);
-      hipLaunchKernelGGL(plr_svd_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, rmax, eps);
+      hipLaunchKernelGGL(plr_orth_kernel, g1, b, 0, st, dnodes.p, dres.p, stage.p, (int)S_T, 1, 1, (int)S_R);
+      const size_t svd_lds = (size_t)2 * smax * smax * sizeof(double2);
+      if (svd_lds > 65536 &&
+          (e = hipFuncSetAttribute(reinterpret_cast<const void*>(&plr_svd_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)svd_lds)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(plr_svd_kernel, g1, b, svd_lds, st, dnodes.p, dres.p, stage.p, smax, rmax, eps);
       // posterior probes
       hipLaunchKernelGGL(plr_random_kernel, gr, b, 0, st, dnodes.p, stage.p, (int)S_P4, 1, seed ^ 0xA5A5A5A5ull);
       hipLaunchKernelGGL(plr_panel_kernel<false>, gt, b, 0, st, dnodes.p, dres.p, blocks, N, stage.p, (int)S_P4,

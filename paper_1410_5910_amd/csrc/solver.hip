@@ -2207,8 +2207,10 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
   if (opt->plr && S->L >= 2) {
     int rmax = opt->plr_rmax > 0 ? opt->plr_rmax : (int)std::ceil(std::sqrt((double)NX));
     rmax = std::min(rmax, kPlrMaxRank);
+    const auto tp = std::chrono::steady_clock::now();
     const hipError_t pe = S->plr.build(S->blk64.p, S->nblk, NX, rmax, opt->plr_eps, S->st);
     if (pe != hipSuccess) return bail(fail(pe == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP, "PLR compression"));
+    S->plr_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
     S->use_plr = true;
   }
 
@@ -2277,6 +2279,7 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
     o->bot_ext[l] = S->lay[l].bot_ext;
   }
   o->setup_ms = S->setup_ms;
+  o->plr_ms = S->plr_ms;
   const size_t es = S->f32 ? sizeof(float2) : sizeof(double2);
   o->dense_block_bytes = (int64_t)S->nblk * S->block_elems() * es;
   o->block_bytes = S->use_plr ? (int64_t)(S->plr.data_entries * sizeof(double2)) : o->dense_block_bytes;

@@ -127,6 +127,7 @@ struct pt_solver {
   int sumR = 0, Rmax = 0;
   int64_t Nt = 0;  // complex entries of one polarized vector
   bool f32 = false;
+  double plr_ms = 0;
   double setup_ms = 0;
 
   // coefficients

@@ -56,7 +56,7 @@ class PtLayout(C.Structure):
                 ("R", C.c_int32 * 64), ("own_start", C.c_int32 * 64), ("n_own", C.c_int32 * 64),
                 ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
                 ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64), ("dense_block_bytes", C.c_int64),
-                ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64)]
+                ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64), ("plr_ms", C.c_double)]
 
 
 class PtKernelStats(C.Structure):
@@ -205,7 +205,8 @@ class Solver:
                 "own_start": list(o.own_start[:L]), "n_own": list(o.n_own[:L]), "top_ext": list(o.top_ext[:L]),
                 "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
                 "factor_bytes": o.factor_bytes, "dense_block_bytes": o.dense_block_bytes,
-                "plr_leaves": o.plr_leaves, "green_bytes": o.green_bytes}
+                "plr_leaves": o.plr_leaves, "green_bytes": o.green_bytes,
+                "plr_ms": o.plr_ms}
 
     def profile(self, enable: bool):
         """Start (reset) / stop recording HIP events around every block-apply launch."""

@@ -30,13 +30,14 @@ def _flush(msg):
 SHIFTED = {("1", "0"), ("n", "n+1")}
 
 
-@pytest.mark.parametrize("eps", [1e-10, 1e-6])
-def test_compressed_blocks_within_bound_and_match_oracle_tree(eps):
+# rmax 0: ceil(sqrt(NX)) = 11 (33-column sketches); 64: the widest sketch (70 columns)
+@pytest.mark.parametrize("eps,rmax", [(1e-10, 0), (1e-6, 0), (1e-10, 64)])
+def test_compressed_blocks_within_bound_and_match_oracle_tree(eps, rmax):
     prob, _ = synth.config_small(nx=90, nz=60, npml=8, L=3, nrhs=1, seed=12)
-    _flush(f"[gpu] plr compression, eps {eps:g}")
-    gs = P.Solver.from_problem(prob, plr=True, plr_eps=eps)
+    _flush(f"[gpu] plr compression, eps {eps:g}, rmax {rmax}")
+    gs = P.Solver.from_problem(prob, plr=True, plr_eps=eps, plr_rmax=rmax)
     ps = PolarizedSolver(prob)
-    rmax = math.ceil(math.sqrt(ps.NX))
+    rmax = rmax or math.ceil(math.sqrt(ps.NX))
     total = same = 0
     st_gpu = st_or = 0
     leaves = 0
