@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--all-forms", action="store_true",
                     help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
+    ap.add_argument("--plr", action="store_true",
+                    help="the main form with partitioned low-rank trace blocks (eps 1e-9, float64)")
     ap.add_argument("--spectral", action="store_true",
                     help="also the spectral diagnostics of D^-1 A (homogeneous medium vs PML width, resonant "
                          "cavity vs frequency); on with --all-forms")
@@ -319,6 +321,9 @@ def main():
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
     args = ap.parse_args()
+    if args.plr and args.precision not in ("auto", "f64"):
+        print("--plr takes float64 blocks: use --precision f64", file=sys.stderr)
+        return 2
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -359,11 +364,11 @@ def main():
 
     forms = []
     chosen = None
-    order = ["split-bf16", "f64"] if args.precision == "auto" else [args.precision]
+    order = ["f64"] if args.plr else (["split-bf16", "f64"] if args.precision == "auto" else [args.precision])
     for prec in order:
         log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
         form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune,
-                           tol=args.tol)
+                           tol=args.tol, plr=args.plr)
         form["workload"] = args.workload
         form["roofline"] = roofline(form)
         if k:
@@ -375,10 +380,10 @@ def main():
         forms.append(form)
         if chosen is None and (not k or form["rel_err_vs_oracle"] <= ERR_BAR or prec == order[-1]):
             chosen = form
-        if args.precision != "auto" or chosen is form:
+        if args.precision != "auto" or args.plr or chosen is form:
             break
     if not args.no_forms:
-        have = {(fm["workload"], fm["precision"], False, "jump") for fm in forms}
+        have = {(fm["workload"], fm["precision"], args.plr, "jump") for fm in forms}
         extra = [(args.workload, "f64", False, "jump")]
         if args.all_forms:
             extra += [(args.workload, "f32", False, "jump")] + \
