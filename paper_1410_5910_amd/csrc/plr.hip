@@ -654,6 +654,9 @@ struct Grow {
     cap = nc;
     return hipSuccess;
   }
+  ~Grow() {
+    if (p) (void)hipFree(p);
+  }
 };
 
 template <typename T>

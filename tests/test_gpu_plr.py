@@ -30,11 +30,13 @@ def _flush(msg):
 SHIFTED = {("1", "0"), ("n", "n+1")}
 
 
-# rmax 0: ceil(sqrt(NX)) = 11 (33-column sketches); 64: the widest sketch (70 columns)
-@pytest.mark.parametrize("eps,rmax", [(1e-10, 0), (1e-6, 0), (1e-10, 64)])
-def test_compressed_blocks_within_bound_and_match_oracle_tree(eps, rmax):
-    prob, _ = synth.config_small(nx=90, nz=60, npml=8, L=3, nrhs=1, seed=12)
-    _flush(f"[gpu] plr compression, eps {eps:g}, rmax {rmax}")
+# NX = 106: rmax 0 -> ceil(sqrt(NX)) = 11 (22-column sketches); 64: the widest sketch (70 columns).
+# NX = 34 with rmax 2: odd halves down to 2-3 rows, six levels deep, 13-column sketches.
+@pytest.mark.parametrize("nx,nz,npml,eps,rmax", [(90, 60, 8, 1e-10, 0), (90, 60, 8, 1e-6, 0), (90, 60, 8, 1e-10, 64),
+                                                 (24, 30, 5, 1e-10, 2)])
+def test_compressed_blocks_within_bound_and_match_oracle_tree(nx, nz, npml, eps, rmax):
+    prob, _ = synth.config_small(nx=nx, nz=nz, npml=npml, L=3, nrhs=1, seed=12)
+    _flush(f"[gpu] plr compression, NX {nx + 2 * npml}, eps {eps:g}, rmax {rmax}")
     gs = P.Solver.from_problem(prob, plr=True, plr_eps=eps, plr_rmax=rmax)
     ps = PolarizedSolver(prob)
     rmax = rmax or math.ceil(math.sqrt(ps.NX))
