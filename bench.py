@@ -115,7 +115,7 @@ def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     nrhs = sum(f.shape[0] for _, f in probs)
-    out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs,
+    out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs, "gs_iters": 2,
            "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
            "problems": [{"name": p.name, "L": p.L, "nrhs": f.shape[0],
                          "iterations": sorted(set(i["iters"] for i in r[1])),
@@ -136,14 +136,43 @@ def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
     return out
 
 
-def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8,
-             closure="jump"):
-    """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form,
-    closure of the polarized system)."""
+GS_CANDIDATES = (2, 4)
+
+
+def pick_gs_iters(P, torch, prob, f, precision, stream, tune, tol, plr, closure):
+    """The Gauss-Seidel sweep count n_it (Alg. 4) of a form: each candidate is set up (and tuned), then timed
+    over two solves after one warm-up; the fastest is kept.  More sweeps cost more per GMRES iteration and
+    save iterations; the balance depends on the precision form."""
     nrhs = f.shape[0]
+    fd = torch.from_numpy(f).to("cuda:0")
+    trial = {}
+    for gs in GS_CANDIDATES:
+        s = P.Solver.from_problem(prob, precision=precision, tol=tol, maxit=60, max_nrhs=nrhs,
+                                  stream=stream.cuda_stream, plr=plr, plr_eps=1e-9, closure=closure, gs_iters=gs)
+        if tune:
+            s.tune(nrhs)
+        s.solve(fd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            s.solve(fd)
+        torch.cuda.synchronize()
+        trial[gs] = 1e3 * (time.perf_counter() - t0) / 2
+        s.close()
+    return min(trial, key=trial.get), trial
+
+
+def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, plr=False, tune=True, tol=1e-8,
+             closure="jump", gs_iters="auto"):
+    """Setup (+ tuning) + warmup + timed steps (+ a profiled pass) for one (workload, precision, block form,
+    closure of the polarized system); gs_iters "auto" picks n_it by pick_gs_iters (outside the timed steps)."""
+    nrhs = f.shape[0]
+    gs_trial = None
+    if gs_iters == "auto":
+        gs_iters, gs_trial = pick_gs_iters(P, torch, prob, f, precision, stream, tune, tol, plr, closure)
     t0 = time.perf_counter()
     s = P.Solver.from_problem(prob, precision=precision, tol=tol, maxit=60, max_nrhs=nrhs,
-                              stream=stream.cuda_stream, plr=plr, plr_eps=1e-9, closure=closure)
+                              stream=stream.cuda_stream, plr=plr, plr_eps=1e-9, closure=closure, gs_iters=gs_iters)
     lay = s.layout()
     fd = torch.from_numpy(f).to("cuda:0")
     setup_s = time.perf_counter() - t0
@@ -162,6 +191,7 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
     el = time.perf_counter() - t0
     out = {"solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "nrhs": nrhs,
            "precision": precision, "blocks": "plr eps 1e-9" if plr else "dense", "closure": closure,
+           "gs_iters": gs_iters, "gs_trial_ms_per_step": gs_trial,
            "setup_s": setup_s,
            "tune_s": tune_s, "tuned": tune_res,
            "iterations": sorted(set(i["iters"] for i in info)),
@@ -312,6 +342,9 @@ def main():
     ap.add_argument("--all-forms", action="store_true",
                     help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
+    ap.add_argument("--gs-iters", default="auto",
+                    help="Gauss-Seidel sweeps n_it of the preconditioner: an integer 0..8, or auto (the faster of "
+                         "2 and 4 per form, from a short timed trial before the timed steps)")
     ap.add_argument("--plr", action="store_true",
                     help="the main form with partitioned low-rank trace blocks (eps 1e-9, float64)")
     ap.add_argument("--spectral", action="store_true",
@@ -321,6 +354,7 @@ def main():
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
     args = ap.parse_args()
+    gs_arg = args.gs_iters if args.gs_iters == "auto" else int(args.gs_iters)
     if args.plr and args.precision not in ("auto", "f64"):
         print("--plr takes float64 blocks: use --precision f64", file=sys.stderr)
         return 2
@@ -368,7 +402,7 @@ def main():
     for prec in order:
         log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
         form, u = run_form(P, torch, prob, f, prec, args.steps, args.warmup, stream, tune=not args.no_tune,
-                           tol=args.tol, plr=args.plr)
+                           tol=args.tol, plr=args.plr, gs_iters=gs_arg)
         form["workload"] = args.workload
         form["roofline"] = roofline(form)
         if k:
@@ -398,7 +432,7 @@ def main():
             log(f"form {wl} {prec}{' plr' if plr else ''}{' extrapolation closure' if clo == 'extrap' else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
                                args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol,
-                               closure=clo)
+                               closure=clo, gs_iters=gs_arg)
             form["workload"] = wl
             rf = roofline(form)
             form["roofline_dominant_class"] = {kk: rf[kk] for kk in ("class", "kernel", "bound", "achieved", "unit",
@@ -439,7 +473,7 @@ def main():
                                           "operator A, Krylov vectors and residuals in float64",
                             "f32": "float32 blocks and local factors, float64 Krylov vectors",
                             "f64": "float64"}[chosen["precision"]],
-                   "gmres_tol": args.tol, "gs_iters": 2, "iterations": chosen["iterations"]},
+                   "gmres_tol": args.tol, "gs_iters": chosen["gs_iters"], "iterations": chosen["iterations"]},
         "roofline": chosen["roofline"],
         "rel_err_vs_oracle": chosen.get("rel_err_vs_oracle"),
         "rel_err_checked_rhs": chosen.get("rel_err_checked_rhs"),

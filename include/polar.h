@@ -94,7 +94,7 @@ typedef struct {
 
 typedef struct {
   int32_t precision; /* pt_precision                                              */
-  int32_t gs_iters;  /* n_it of the Gauss-Seidel preconditioner (Alg. 4), 0..4;
+  int32_t gs_iters;  /* n_it of the Gauss-Seidel preconditioner (Alg. 4), 0..8;
                         0 = unpreconditioned GMRES. Paper: 2                      */
   double tol;        /* GMRES stop: relative residual of the trace system         */
   int32_t maxit;     /* GMRES iterations (no restart), 1..200                     */

@@ -209,7 +209,7 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
     if (!(p->c[e] > 0) || !std::isfinite(p->c[e])) return fail(PT_EINVAL, "velocity must be positive and finite");
   if (o->precision != PT_F64 && o->precision != PT_F32 && o->precision != PT_SPLIT_BF16)
     return fail(PT_EINVAL, "unknown precision");
-  if (o->gs_iters < 0 || o->gs_iters > 4) return fail(PT_EINVAL, "gs_iters must be in 0..4");
+  if (o->gs_iters < 0 || o->gs_iters > 8) return fail(PT_EINVAL, "gs_iters must be in 0..8");
   if (o->maxit < 1 || o->maxit > 200) return fail(PT_EINVAL, "maxit must be in 1..200");
   if (!(o->tol >= 0)) return fail(PT_EINVAL, "tol must be >= 0");
   if (o->max_nrhs < 1) return fail(PT_EINVAL, "max_nrhs must be >= 1");
