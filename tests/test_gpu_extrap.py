@@ -50,6 +50,17 @@ def test_operators_match_oracle(small, op, nrhs):
     assert rel(y, ref) < 1e-10, (op, rel(y, ref))
 
 
+@pytest.mark.parametrize("n_it", [1, 4])
+def test_preconditioner_sweep_counts(small, n_it):
+    prob, f, ps, ex, gx = small
+    g = P.Solver.from_problem(prob, max_nrhs=8, tol=1e-11, maxit=80, closure="extrap", gs_iters=n_it)
+    rng = np.random.default_rng(10 + n_it)
+    x = rng.standard_normal(ps.zeros(6).shape) + 1j * rng.standard_normal(ps.zeros(6).shape)
+    err = rel(g.apply(P.OP_PRECOND_EXTRAP, x), ex.precondition(x, n_it))
+    assert err < 1e-10, err
+    g.close()
+
+
 def test_solves_match_direct(small):
     prob, f, ps, ex, gx = small
     _flush("[gpu] extrap solves")

@@ -90,6 +90,20 @@ def test_operators(small, op):
     assert rel(y, ref) < 1e-10, rel(y, ref)
 
 
+@pytest.mark.parametrize("n_it", [1, 3, 4, 8])
+@pytest.mark.parametrize("precision", ["f64", "split-bf16"])
+def test_preconditioner_sweep_counts(small, n_it, precision):
+    # Alg. 4 with n_it Gauss-Seidel sweeps from u^0 = 0 (the bench runs the mixed form with 4)
+    prob, f, gs, ps = small
+    g = P.Solver.from_problem(prob, precision=precision, gs_iters=n_it, max_nrhs=20, tol=1e-12, maxit=40)
+    rng = np.random.default_rng(n_it)
+    for nrhs in (3, 20):  # the 16-column and the wide split-bfloat16 kernels
+        x = rng.standard_normal(ps.zeros(nrhs).shape) + 1j * rng.standard_normal(ps.zeros(nrhs).shape)
+        err = rel(g.apply(P.OP_PRECOND, x), ps.precondition(x, n_it))
+        assert err < (1e-10 if precision == "f64" else 1e-4), (nrhs, err)
+    g.close()
+
+
 def test_reconstruct(small):
     prob, f, gs, ps = small
     rng = np.random.default_rng(4)

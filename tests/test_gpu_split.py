@@ -96,14 +96,15 @@ def test_split_bumps440_single_source():
     gs.close()
 
 
-def test_split_layered_batch_matches_f64():
+@pytest.mark.parametrize("n_it", [2, 4])  # the paper's sweep count / the bench's for this form
+def test_split_layered_batch_matches_f64(n_it):
     # the bench workload's medium and launch configuration (all 128 sources in one call, tuned tile shapes,
     # device-resident input, tol 1e-10, maxit 60): every source against the float64 GPU path, and every
     # eighth source against the direct solve of the oracle
     torch = pytest.importorskip("torch")
     prob, f = synth.config3()
-    _flush("[gpu] split layered-1240x440-L16, 128 sources, tuned")
-    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=60)
+    _flush(f"[gpu] split layered-1240x440-L16, 128 sources, tuned, n_it {n_it}")
+    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=60, gs_iters=n_it)
     gs.tune(128)
     ud_dev, info = gs.solve(torch.from_numpy(f).to("cuda:0"))
     u = ud_dev.cpu().numpy()
