@@ -62,3 +62,21 @@ def test_cavity_spectrum_spreads_with_frequency():
         dist.append(float(d.max()))
     assert 0 < outside[0] < outside[1] < outside[2]
     assert dist[0] < dist[1] < dist[2]
+
+
+def test_gauss_seidel_with_n_sweeps_is_a_truncated_neumann_series():
+    # Alg. 4 from u^0 = 0 with n sweeps: M_n^-1 = sum_{j<n} (-D^-1 R)^j D^-1, so M_n^-1 A = I - (-D^-1 R)^n;
+    # pins the oracle's sweep loop for every n the GPU path is compared at
+    ps = PolarizedSolver(synth.config_small(nx=12, nz=24, npml=4, L=3, nrhs=1, seed=5)[0])
+    n = 4 * (ps.L - 1) * ps.NX
+    E = np.eye(n, dtype=np.complex128).reshape(n, 2, ps.L - 1, 2, ps.NX)
+    G = -ps.dense("Dinv") @ ps.dense("R")
+    AE = ps.apply_A(E)
+    for n_it in (1, 3, 4, 8):
+        M = ps.precondition(AE, n_it=n_it).reshape(n, n).T
+        ref = np.eye(n) - np.linalg.matrix_power(G, n_it)
+        assert np.abs(M - ref).max() < 1e-10 * max(1.0, np.abs(ref).max()), n_it
+        # an off-by-one in the sweep count fails it (where G^n is not yet negligible)
+        if np.abs(ref - np.eye(n)).max() > 1e-5:
+            assert np.abs(M - (np.eye(n) - np.linalg.matrix_power(G, n_it + 1))).max() > 1e-6, n_it
+    assert np.abs(np.linalg.matrix_power(G, 4)).max() > 1e-5  # the off-by-one check ran for n = 1, 3 and 4
