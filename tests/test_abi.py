@@ -61,3 +61,19 @@ def test_nonpositive_velocity_rejected():
     with pytest.raises(P.PolarError) as e:
         P.Solver(prob.nx, prob.nz, prob.npml, prob.h, prob.omega, prob.C, prob.L, c)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("opt,msg", [
+    (dict(gs_iters=9), "gs_iters"),
+    (dict(gs_iters=-1), "gs_iters"),
+    (dict(plr=True, plr_rmax=65), "plr_rmax"),
+    (dict(plr=True, plr_eps=0.0), "plr_eps"),
+    (dict(plr=True, precision="f32"), "float64 only"),
+])
+def test_invalid_options_rejected(opt, msg):
+    # option checks run before any device work (no GPU needed)
+    P = pytest.importorskip("paper_1410_5910_amd")
+    prob, f = synth.config_small(nx=12, nz=16, npml=3, L=2)
+    with pytest.raises(P.PolarError) as e:
+        P.Solver(prob.nx, prob.nz, prob.npml, prob.h, prob.omega, prob.C, prob.L, prob.c, **opt)
+    assert e.value.status == 1 and msg in str(e.value)
