@@ -212,8 +212,14 @@ class PolarizedSolver:
         return u
 
     def precondition(self, r: np.ndarray, n_it: int | None = None) -> np.ndarray:
-        """Gauss-Seidel preconditioner (Alg. 4): u^0 = 0, u^{i+1} = D^-1 (r - R u^i), n_it times."""
+        """Gauss-Seidel preconditioner (Alg. 4): u^0 = 0, u^{i+1} = D^-1 (r - R u^i), n_it times.
+
+        n_it = 0 is read as GMRES on the polarized system with no preconditioner
+        (Section 4.2 runs GMRES on the system itself before preconditioning it):
+        the identity, not the zero map that a loop of no passes would leave."""
         n_it = self.n_it if n_it is None else n_it
+        if n_it == 0:
+            return r.copy()
         u = np.zeros_like(r)
         for _ in range(n_it):
             u = self.apply_D_inv(r - self.apply_R(u))

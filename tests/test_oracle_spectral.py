@@ -80,3 +80,5 @@ def test_gauss_seidel_with_n_sweeps_is_a_truncated_neumann_series():
         if np.abs(ref - np.eye(n)).max() > 1e-5:
             assert np.abs(M - (np.eye(n) - np.linalg.matrix_power(G, n_it + 1))).max() > 1e-6, n_it
     assert np.abs(np.linalg.matrix_power(G, 4)).max() > 1e-5  # the off-by-one check ran for n = 1, 3 and 4
+    # no sweeps: no preconditioner, so the preconditioned operator is A itself
+    assert np.abs(ps.precondition(AE, n_it=0).reshape(n, n).T - ps.dense("A")).max() == 0.0
