@@ -9,15 +9,17 @@ Headline workload (`value`): the batched layered section, 128 sources solved
 in one call, in the mixed form -- the Gauss-Seidel sweeps apply the trace
 blocks as split-bfloat16 pairs on MFMA, while the local solves, the operator
 A inside GMRES, the Krylov vectors, Arnoldi, least squares and the true
-residual stay float64 -- when that form meets the 1e-6 relative-error bar
-against the float64 oracle on the sampled sources, else in float64.  `forms`
-reports the float64 form of the same workload beside it (and, with
---all-forms, float32 blocks, the smooth single-source workload and
-compressed blocks).  Tile shapes are tuned (pt_tune) after setup, outside
-the timed steps.  GMRES stops at a relative trace residual of 1e-8 (--tol),
-which keeps every sampled source within 1e-8 of the oracle, so both the
-mixed form and the float64 form it is compared with meet the 1e-6 bar and
-the float64 path's own 1e-8 bar.
+residual stay float64 -- when every one of its sources meets the 1e-6
+relative-error bar against the float64 oracle's direct solve, else in
+float64.  `forms` reports beside it the float64 form of the same workload,
+the smooth single-source workload in float64 (HBM-bound) and the uneven batch
+of eight problems in the mixed and the float64 form (with --all-forms also
+float32 blocks, the extrapolation closure and compressed blocks).  Every
+source of every default form is compared with the oracle after the timed
+steps.  Tile shapes are tuned (pt_tune) after setup, outside the timed steps.
+GMRES stops at a relative trace residual of 1e-8 (--tol), which keeps every
+source within 1e-8 of the oracle, so both the mixed form and the float64 form
+it is compared with meet the 1e-6 bar and the float64 path's own 1e-8 bar.
 
 Prints one JSON line; progress goes to stderr.
 """
@@ -64,35 +66,84 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-class Oracle:
-    """The CPU oracle's direct solver for a workload, factored once (test infrastructure)."""
+def rel_errors(u, ref):
+    """Per-source relative L2 error over the whole padded grid (the oracle's u* as reference)."""
+    import numpy as np
+    return [float(np.linalg.norm(u[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(ref.shape[0])]
 
-    def __init__(self, prob):
-        from oracle.direct import DirectSolver
+
+def oracle_reference(prob, f, workers=8):
+    """The oracle's direct solve of every source (factored in `workers` separate processes)."""
+    from oracle.direct import direct_solve_parallel
+    return direct_solve_parallel(prob, f, workers)
+
+
+def cpu_direct_baseline(prob, f, nsample=32, reps=3):
+    """The oracle's sparse direct solve on the host (SuperLU, one core): factorisation time, then the
+    first `nsample` sources solved as one matrix; medians of `reps` runs each."""
+    import statistics
+    from oracle.direct import DirectSolver
+    tf, ts = [], []
+    ds = None
+    for _ in range(reps):
         t0 = time.perf_counter()
-        self.ds = DirectSolver(prob)
-        self.t_fact = time.perf_counter() - t0
-
-    def errors(self, f, u, k):
-        """Relative error of k sources spread evenly over the batch (first and last included)."""
-        import numpy as np
-        n = f.shape[0]
-        idx = sorted({round(i * (n - 1) / max(k - 1, 1)) for i in range(k)}) if k > 1 else [0]
-        ref = self.ds.solve(f[idx])
-        got = u[idx].cpu().numpy()
-        return [float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(idx))]
-
-    def baseline(self, f, budget_s=10.0):
-        """Repeated single-source solves of the factored system for about budget_s seconds."""
-        nsol = 0
+        ds = DirectSolver(prob)
+        tf.append(time.perf_counter() - t0)
+    fs = f[:nsample]
+    for _ in range(reps):
         t0 = time.perf_counter()
-        while True:
-            self.ds.solve(f[nsol % f.shape[0]])
-            nsol += 1
-            el = time.perf_counter() - t0
-            if el > budget_s:
-                break
-        return nsol / el, nsol, el
+        ds.solve(fs)
+        ts.append(time.perf_counter() - t0)
+    return {"factor_s": statistics.median(tf), "batch": fs.shape[0], "batch_solve_s": statistics.median(ts),
+            "reps": reps}
+
+
+def cpu_polar_child():
+    """Entry of the child process that times the oracle's naive polarized-traces solve (Alg. 1 offline,
+    Alg. 2 online) on the smooth single-source workload; prints one JSON line."""
+    import statistics
+    import synth
+    from oracle.polarized import PolarizedSolver
+    prob, f = synth.config2()
+    t0 = time.perf_counter()
+    ps = PolarizedSolver(prob)
+    setup = time.perf_counter() - t0
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ps.solve(f, tol=1e-8)
+        ts.append(time.perf_counter() - t0)
+    print(json.dumps({"workload": "bumps440", "setup_s": setup, "online_s_per_rhs": statistics.median(ts),
+                      "reps": 3}), flush=True)
+
+
+def start_cpu_polar():
+    """Start the oracle's polarized-solve timing in a child process (one core) that runs beside the GPU work."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-polar-child"], env=env,
+                            stdout=subprocess.PIPE, text=True)
+
+
+def profile_classes(solvers, nprof, run):
+    """Per-class live kernel counters summed over solvers, over `nprof` calls of run()."""
+    import paper_1410_5910_amd as P
+    for s in solvers:
+        s.profile(True)
+    for _ in range(nprof):
+        run()
+    tot = {"launches": 0, "kernel_ms": 0.0, "alg_bytes": 0.0, "alg_flops": 0.0}
+    cls = {c: dict(tot) for c in P.polar.CLASSES}
+    for s in solvers:
+        t = s.profile_read()
+        for kk in tot:
+            tot[kk] += t[kk]
+        for c in P.polar.CLASSES:
+            v = s.profile_read_class(c)
+            for kk in tot:
+                cls[c][kk] += v[kk]
+        s.profile(False)
+    return {"nprof": nprof, "total": tot, "classes": cls}
 
 
 def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
@@ -117,23 +168,18 @@ def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
     nrhs = sum(f.shape[0] for _, f in probs)
     out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs, "gs_iters": 2,
            "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
+           "iterations": sorted({i["iters"] for r in res for i in r[1]}),
            "problems": [{"name": p.name, "L": p.L, "nrhs": f.shape[0],
                          "iterations": sorted(set(i["iters"] for i in r[1])),
                          "max_true_relres": max(i["relres"] for i in r[1]),
                          "presolve": "green" if sv.layout()["green_bytes"] else "local"}
                         for (p, f), r, sv in zip(probs, res, solvers)]}
-    # the smallest problem's first and last sources against the oracle
-    small = min(range(len(probs)), key=lambda i: probs[i][0].NX)
-    p, f = probs[small]
-    ds = Oracle(p)
-    got = res[small][0][[0, f.shape[0] - 1]].cpu().numpy()
-    ref = ds.ds.solve(f[[0, f.shape[0] - 1]])
-    import numpy as np
-    out["rel_err_vs_oracle"] = max(float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(2))
-    out["rel_err_checked"] = f"{p.name}: 2 sources"
+    out["kernel"] = profile_classes(solvers, 1, lambda: P.solve_batch(solvers, fds))
+    torch.cuda.synchronize()
+    parts = [(p, f, r[0].cpu().numpy()) for (p, f), r in zip(probs, res)]
     for sv in solvers:
         sv.close()
-    return out
+    return out, parts
 
 
 GS_CANDIDATES = (2, 4)
@@ -201,14 +247,9 @@ def run_form(P, torch, prob, f, precision, steps, warmup, stream, profile=True, 
         out.update({"plr_compress_ms": lay["plr_ms"], "plr_leaves": lay["plr_leaves"],
                     "plr_ratio": lay["block_bytes"] / lay["dense_block_bytes"]})
     if profile:
-        s.profile(True)
-        nprof = max(1, min(steps, 3))
-        for _ in range(nprof):
-            s.solve(fd)
-        tot = s.profile_read()
-        cls = {c: s.profile_read_class(c) for c in P.polar.CLASSES}
-        s.profile(False)
-        out["kernel"] = {"nprof": nprof, "total": tot, "classes": cls}
+        out["kernel"] = profile_classes([s], max(1, min(steps, 3)), lambda: s.solve(fd))
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
     s.close()
     return out, u
 
@@ -262,15 +303,16 @@ def roofline(form):
             "alg_bytes_per_launch": st["alg_bytes"] / st["launches"],
             "alg_flops_per_launch": st["alg_flops"] / st["launches"],
             "class_share_of_step": st["kernel_ms"] / k["nprof"] / form["ms_per_step"],
+            "nprof": k["nprof"],
             "all_classes_ms_per_step": {c: v["kernel_ms"] / k["nprof"] for c, v in k["classes"].items()}}
+    gbs = st["alg_bytes"] / sec / 1e9
     if (form["nrhs"] > 4 and name != "plr_apply_kernel") or dt == "bf16":
-        # a split-bfloat16 complex multiply-add is 3 x 4 real bfloat16 products: 3x the counted flops
-        fl = st["alg_flops"] * (3.0 if dt == "bf16" else 1.0)
-        tfl = fl / sec / 1e12
+        # algorithmic flops: 8 per complex multiply-add, whatever the number of real products that form it
+        tfl = st["alg_flops"] / sec / 1e12
         peak = PEAK_TFLOPS[dt]
-        r = {"bound": "mfma", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak}
+        r = {"bound": "mfma", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak,
+             "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
     else:
-        gbs = st["alg_bytes"] / sec / 1e9
         r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     r.update(base)
     return r
@@ -331,16 +373,20 @@ def main():
                     help="auto: mixed (split-bfloat16 sweeps) if it meets the 1e-6 bar on the sampled sources, "
                          "else f64")
     ap.add_argument("--nrhs", type=int, default=0, help="sources per step (default: all of the workload's)")
-    ap.add_argument("--check", type=int, default=16,
-                    help="sources compared with the oracle, spread over the batch (0: none)")
+    ap.add_argument("--check", type=int, default=1,
+                    help="1: compare every source of every form with the oracle's direct solve after the timed "
+                         "steps; 0: no comparison")
     ap.add_argument("--tol", type=float, default=1e-8,
                     help="GMRES stop: relative residual of the trace system.  1e-8 meets the 1e-6 bar of the "
                          "reduced-precision forms and the 1e-8 bar of the float64 path with margin to spare in "
                          "the error; the paper's own runs stop at 1e-7")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-forms", action="store_true", help="skip the float64 comparison form")
+    ap.add_argument("--no-forms", action="store_true", help="only the headline workload's forms")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch of eight problems")
+    ap.add_argument("--cpu-polar-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--all-forms", action="store_true",
-                    help="also float32 blocks, the bumps-440 single-source workload and compressed blocks")
+                    help="also float32 blocks, the extrapolation closure, the bumps-440 workload in float32 and "
+                         "mixed form, and compressed blocks")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile-shape rules, no pt_tune")
     ap.add_argument("--gs-iters", default="auto",
                     help="Gauss-Seidel sweeps n_it of the preconditioner: an integer 0..8, or auto (the faster of "
@@ -354,6 +400,9 @@ def main():
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
     args = ap.parse_args()
+    if args.cpu_polar_child:
+        cpu_polar_child()
+        return 0
     gs_arg = args.gs_iters if args.gs_iters == "auto" else int(args.gs_iters)
     if args.plr and args.precision not in ("auto", "f64"):
         print("--plr takes float64 blocks: use --precision f64", file=sys.stderr)
@@ -364,6 +413,10 @@ def main():
         print("bench.py runs on one GPU only: the polarized-traces layers are batched inside one device "
               "and there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
+
+    # the oracle's polarized-traces timing runs in a child process beside the GPU work (started before this
+    # process touches the GPU)
+    polar_child = start_cpu_polar() if not args.no_cpu else None
 
     import numpy as np  # noqa: F401
     import torch
@@ -390,14 +443,9 @@ def main():
         f = f[: args.nrhs]
     nrhs = f.shape[0]
     log(f"workload {prob.name}: grid {prob.NZ}x{prob.NX}, L={prob.L}, nrhs={nrhs}")
-    oracle = None
-    if args.check or not args.no_cpu:
-        oracle = Oracle(prob)
-        log(f"oracle factorisation {oracle.t_fact:.1f} s")
-    k = min(args.check, nrhs)
 
-    forms = []
-    chosen = None
+    # ---- GPU forms (timed); every output is kept on the host for the oracle check afterwards
+    runs = []   # (form, workload, [(problem, sources, field)])
     order = ["f64"] if args.plr else (["split-bf16", "f64"] if args.precision == "auto" else [args.precision])
     for prec in order:
         log(f"{args.workload} {prec}: setup + tune + {args.warmup} warmup + {args.steps} timed steps")
@@ -405,26 +453,17 @@ def main():
                            tol=args.tol, plr=args.plr, gs_iters=gs_arg)
         form["workload"] = args.workload
         form["roofline"] = roofline(form)
-        if k:
-            errs = oracle.errors(f, u, k)
-            form["rel_err_vs_oracle"] = max(errs)
-            form["rel_err_checked_rhs"] = k
         log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.2f} ms/step, iterations "
-            f"{form['iterations']}, rel err {form.get('rel_err_vs_oracle', float('nan')):.2e}")
-        forms.append(form)
-        if chosen is None and (not k or form["rel_err_vs_oracle"] <= ERR_BAR or prec == order[-1]):
-            chosen = form
-        if args.precision != "auto" or args.plr or chosen is form:
-            break
+            f"{form['iterations']}")
+        runs.append((form, args.workload, [(prob, f, u)]))
     if not args.no_forms:
-        have = {(fm["workload"], fm["precision"], args.plr, "jump") for fm in forms}
-        extra = [(args.workload, "f64", False, "jump")]
+        have = {(args.workload, fm["precision"], args.plr, "jump") for fm, _, _ in runs}
+        extra = [(args.workload, "f64", False, "jump"), ("bumps440", "f64", False, "jump")]
         if args.all_forms:
             extra += [(args.workload, "f32", False, "jump")] + \
                 [(args.workload, p, False, "extrap") for p in ("split-bf16", "f64")] + \
-                [("bumps440", p, False, "jump") for p in ("f64", "f32", "split-bf16")] + \
+                [("bumps440", p, False, "jump") for p in ("f32", "split-bf16")] + \
                 [("bumps440", "f64", True, "jump")]
-        orcs = {}
         for wl, prec, plr, clo in extra:
             if (wl, prec, plr, clo) in have or (wl == args.workload and args.nrhs):
                 continue
@@ -434,34 +473,54 @@ def main():
                                args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol,
                                closure=clo, gs_iters=gs_arg)
             form["workload"] = wl
-            rf = roofline(form)
-            form["roofline_dominant_class"] = {kk: rf[kk] for kk in ("class", "kernel", "bound", "achieved", "unit",
-                                                                     "frac", "avg_launch_us", "class_share_of_step")}
-            if wl == args.workload:
-                orc = oracle
-            else:
-                orc = orcs.get(wl) or Oracle(pw)
-                orcs[wl] = orc
-            if orc is not None:
-                form["rel_err_vs_oracle"] = max(orc.errors(fw, u, min(k or 1, fw.shape[0])))
-            log(f"  {form['solves_per_s']:.1f} solves/s, rel err {form.get('rel_err_vs_oracle', float('nan')):.2e}")
-            forms.append(form)
+            form["roofline"] = roofline(form)
+            log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.2f} ms/step")
+            runs.append((form, wl, [(pw, fw, u)]))
             have.add((wl, prec, plr, clo))
-        if args.all_forms:
+        if not args.no_uneven:
             for prec in ("split-bf16", "f64"):
                 log(f"form uneven8 {prec}: 8 problems x 32 sources, one pt_solve_batch per step")
-                form = run_uneven(P, torch, prec, args.steps, args.warmup, tol=args.tol)
-                log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step, rel err "
-                    f"{form['rel_err_vs_oracle']:.2e}")
-                forms.append(form)
+                form, parts = run_uneven(P, torch, prec, args.steps, args.warmup, tol=args.tol)
+                form["roofline"] = roofline(form)
+                log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step")
+                runs.append((form, "uneven8", parts))
 
     spec = None
     if args.spectral or args.all_forms:
         log("spectral diagnostics")
         spec = run_spectral(P, torch, cpu=not args.no_cpu)
 
-    f64_same = [fm for fm in forms if fm["workload"] == args.workload and fm["precision"] == "f64"
-                and fm.get("closure", "jump") == "jump"]
+    # ---- oracle check of every source (outside every timed region)
+    if args.check:
+        refs = {}
+        for form, wl, parts in runs:
+            errs_all = []
+            for i, (pw, fw, uu) in enumerate(parts):
+                key = (wl, i)
+                if key not in refs:
+                    t0 = time.perf_counter()
+                    refs[key] = oracle_reference(pw, fw)
+                    log(f"oracle direct solve of {pw.name}, {fw.shape[0]} sources: {time.perf_counter() - t0:.1f} s")
+                errs = rel_errors(uu, refs[key])
+                errs_all += errs
+                if wl == "uneven8":
+                    form["problems"][i]["rel_err_vs_oracle"] = max(errs)
+            form["rel_err_vs_oracle"] = max(errs_all)
+            form["rel_err_checked_rhs"] = len(errs_all)
+            form["within_bar"] = form["rel_err_vs_oracle"] <= (1e-8 if form["precision"] == "f64" else ERR_BAR)
+            log(f"  {wl} {form['precision']}: max rel err {form['rel_err_vs_oracle']:.2e} over "
+                f"{len(errs_all)} sources")
+        refs.clear()
+
+    head = [fm for fm, wl, _ in runs if wl == args.workload]
+    chosen = None
+    for fm in head:
+        if not args.check or fm["rel_err_vs_oracle"] <= ERR_BAR:
+            chosen = fm
+            break
+    chosen = chosen or head[-1]
+    forms = [fm for fm, _, _ in runs]
+    f64_same = [fm for fm in head if fm["precision"] == "f64" and fm.get("closure", "jump") == "jump"]
     out = {
         "metric": METRIC, "value": chosen["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -478,17 +537,29 @@ def main():
         "rel_err_vs_oracle": chosen.get("rel_err_vs_oracle"),
         "rel_err_checked_rhs": chosen.get("rel_err_checked_rhs"),
         "vs_fp64_same_workload": (chosen["solves_per_s"] / f64_same[0]["solves_per_s"]) if f64_same else None,
-        "forms": [{kk: vv for kk, vv in fm.items() if kk not in ("kernel", "roofline")} for fm in forms],
+        "forms": [{kk: vv for kk, vv in fm.items() if kk != "kernel"} for fm in forms],
     }
     if spec is not None:
         out["spectral"] = spec
     if not args.no_cpu:
-        log("cpu baseline (oracle direct solve, about 10 s)")
-        rate, nsol, el = oracle.baseline(f[:1])
+        log("cpu baseline: oracle direct solve (factorisation and a 32-source batch, medians of 3)")
+        cb = cpu_direct_baseline(prob, f)
+        polar = None
+        if polar_child is not None:
+            try:
+                txt, _ = polar_child.communicate(timeout=600)
+                polar = json.loads(txt.strip().splitlines()[-1]) if polar_child.returncode == 0 else None
+            except Exception as e:  # the polarized oracle's timing is reported when it finishes
+                polar_child.kill()
+                log(f"polarized oracle timing failed: {e}")
         out["cpu_baseline"] = {
-            "value": rate, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"SuperLU factorisation of the {prob.NZ}x{prob.NX} padded system ({oracle.t_fact:.1f} s, "
-                       f"offline, excluded), then {nsol} single-source solves in {el:.1f} s"),
+            "value": cb["batch"] / cb["batch_solve_s"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"SuperLU sparse direct solve of the {prob.NZ}x{prob.NX} padded system: factorisation "
+                       f"{cb['factor_s']:.1f} s (offline, excluded), then the first {cb['batch']} sources solved "
+                       f"as one matrix in {cb['batch_solve_s']:.1f} s; medians of {cb['reps']} runs"),
+            "direct_factor_s": cb["factor_s"], "direct_batch_solve_s": cb["batch_solve_s"],
+            "direct_batch": cb["batch"],
+            "polar_oracle": polar,
             "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
     print(json.dumps(out), flush=True)
     return 0

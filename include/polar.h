@@ -177,8 +177,10 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
 /* Online part (Alg. 2): u = H^{-1} f for nrhs fields f (nrhs, NZ, NX).  f is
  * restricted to each layer's owned rows (its PML part is used as given).
  * info (host, nrhs entries, may be NULL) receives per-RHS GMRES data.
- * Returns PT_ENOCONV if any right-hand side missed tol within maxit (u is
- * still written).  Host-synchronising once per GMRES iteration. */
+ * Returns PT_ENOCONV if any right-hand side missed tol within maxit or is not
+ * finite (decided whether or not info is given; u is still written: the
+ * field of the last GMRES iterate).  Host-synchronising once per GMRES
+ * iteration. */
 pt_status pt_solve(pt_solver* s, int32_t nrhs, const double* f, double* u, int32_t on_device,
                    pt_rhs_info* info);
 

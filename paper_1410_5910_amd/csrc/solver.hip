@@ -1383,6 +1383,7 @@ pt_status alloc_online(pt_solver* S) {
   HIPCHK(S->Bw.alloc(loc));
   HIPCHK(S->fio.alloc(vol));
   HIPCHK(S->uio.alloc(vol));
+  HIPCHK(S->nrm.alloc(nr));  // per-source norms (also the finiteness check of the one-layer solve)
   if (S->L >= 2) {
     HIPCHK(S->s.alloc(tr));
     HIPCHK(S->V.alloc(tr * (m + 1)));
@@ -1399,7 +1400,6 @@ pt_status alloc_online(pt_solver* S) {
     HIPCHK(S->sn.alloc((size_t)nr * m));
     HIPCHK(S->g.alloc((size_t)nr * (m + 1)));
     HIPCHK(S->y.alloc((size_t)nr * m));
-    HIPCHK(S->nrm.alloc(nr));
     HIPCHK(S->cs.alloc((size_t)nr * m));
     HIPCHK(S->est.alloc(nr));
     HIPCHK(S->beta.alloc(nr));
@@ -2520,18 +2520,34 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
     PTCHK(reconstruct(S, fd, S->x.p, ud, nrhs));
   }
   if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, S->st));
-  if (info) {
-    if (S->L == 1) {
-      for (int r = 0; r < nrhs; ++r) info[r] = pt_rhs_info{0, 1, 0.0, 0.0, 0, 0};
-    } else {
+  // Convergence is decided whether or not the caller asked for info: a source
+  // that is not finite is reported PT_ENOCONV either way.
+  if (S->L == 1) {
+    // one local solve, no iteration: the field is finite or the source was not
+    HIPCHK(launch_knorm(ud, S->nrm.p, nrhs, (int64_t)S->NZ * S->NX, S->st));
+    HIPCHK(hipMemcpyAsync(nr.data(), S->nrm.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    for (int r = 0; r < nrhs; ++r) {
+      const bool ok = std::isfinite(nr[r]);
+      conv = conv && ok;
+      if (info) info[r] = pt_rhs_info{0, ok ? 1 : 0, ok ? 0.0 : std::nan(""), ok ? 0.0 : std::nan(""), 0, 0};
+    }
+  } else {
+    if (info) {
       if (!used_learned) PTCHK(residuals());
-      for (int r = 0; r < nrhs; ++r) {
-        // a source that is not finite stops at once and is reported not converged
-        const double rr = be[r] > 0 ? nr[r] / be[r] : (be[r] == 0.0 ? 0.0 : std::nan(""));
-        const bool ok = dn[r] && std::isfinite(es[r]) && std::isfinite(rr);
-        conv = conv && ok;
+    } else {
+      HIPCHK(hipMemcpyAsync(be.data(), S->beta.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(es.data(), S->est.p, nrhs * 8, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(dn.data(), S->done.p, nrhs * 4, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipStreamSynchronize(S->st));
+    }
+    for (int r = 0; r < nrhs; ++r) {
+      // a source that is not finite stops at once and is reported not converged
+      const double rr = be[r] > 0 ? nr[r] / be[r] : (be[r] == 0.0 ? 0.0 : std::nan(""));
+      const bool ok = dn[r] && std::isfinite(es[r]) && std::isfinite(be[r]) && (!info || std::isfinite(rr));
+      conv = conv && ok;
+      if (info)
         info[r] = pt_rhs_info{it[r], ok ? 1 : 0, es[r], rr, used_learned ? 1 : 0, used_learned ? kept[r] : 0};
-      }
     }
   }
   HIPCHK(hipStreamSynchronize(S->st));

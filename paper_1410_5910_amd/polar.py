@@ -4,8 +4,12 @@ Argument marshalling only: every step of the solve runs in the HIP library.
 Arrays may be NumPy complex128 arrays (host; the library copies and
 synchronises) or torch complex128 CUDA tensors on the solver's device
 (on_device; results are written in place of a tensor this module allocates
-on the same device).  The library must be built (paper_1410_5910_amd.build);
-importing this module without it raises.
+on the same device).  With device tensors the solver's stream first waits for
+the caller's current torch stream (so inputs produced there are complete and
+the output's memory is free), and the current stream then waits for the
+solver's stream (so the results are ordered before later work on it).
+The library must be built (paper_1410_5910_amd.build); importing this module
+without it raises.
 """
 from __future__ import annotations
 
@@ -174,6 +178,7 @@ class Solver:
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
         self._h = h_
+        self._stream = int(stream or 0)
         self.NX, self.NZ, self.L = NX, NZ, int(L)
         self.max_nrhs = int(max_nrhs)
         lay = self.layout()
@@ -272,6 +277,32 @@ class Solver:
     def _ptr(a, on_device):
         return C.c_void_p(a.data_ptr()) if on_device else C.c_void_p(a.ctypes.data)
 
+    def _enter(self, like, on_device):
+        """Order the solver's stream after the caller's current torch stream; returns what _leave needs."""
+        if not on_device:
+            return None
+        import torch
+        cur = torch.cuda.current_stream(like.device)
+        if cur.cuda_stream == self._stream:
+            return None
+        mine = (torch.cuda.ExternalStream(self._stream, device=like.device) if self._stream
+                else torch.cuda.default_stream(like.device))
+        mine.wait_stream(cur)
+        return cur, mine
+
+    @staticmethod
+    def _leave(pair):
+        """Order the caller's current stream after the solver's stream."""
+        if pair is not None:
+            pair[0].wait_stream(pair[1])
+
+    def _call(self, like, on_device, fn, *args, allow=()):
+        pair = self._enter(like, on_device)
+        try:
+            return _check(fn(*args), allow=allow)
+        finally:
+            self._leave(pair)
+
     # ------------------------------------------------------------------ online
     def solve(self, f):
         """u = H^{-1} f for f of shape (nrhs, NZ, NX) or (NZ, NX).  Returns (u, info list)."""
@@ -279,7 +310,7 @@ class Solver:
         p, dev, keep, n = self._prep(f, (self.NZ, self.NX))
         u = self._out(keep, dev, (n, self.NZ, self.NX))
         info = (PtRhsInfo * n)()
-        _check(self._lib.pt_solve(self._h, n, p, self._ptr(u, dev), dev, info), allow=(PT_ENOCONV,))
+        self._call(keep, dev, self._lib.pt_solve, self._h, n, p, self._ptr(u, dev), dev, info, allow=(PT_ENOCONV,))
         infos = [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
                   "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in info]
         return (u[0] if single else u), infos
@@ -291,29 +322,28 @@ class Solver:
         u = self._out(keep, dev, (n, self.NZ, self.NX))
         it = C.c_int32()
         ru = np.zeros(n)
-        st = _check(self._lib.pt_gauss_seidel(self._h, n, p, self._ptr(u, dev), dev, float(tol), int(maxit),
-                                              C.byref(it), ru.ctypes.data_as(C.POINTER(C.c_double))),
-                    allow=(PT_ENOCONV,))
+        st = self._call(keep, dev, self._lib.pt_gauss_seidel, self._h, n, p, self._ptr(u, dev), dev, float(tol),
+                        int(maxit), C.byref(it), ru.ctypes.data_as(C.POINTER(C.c_double)), allow=(PT_ENOCONV,))
         return (u[0] if single else u), it.value, ru, st == PT_OK
 
     def apply(self, op: int, x):
         """y = op(x) for polarized vectors x (nrhs, 2, L-1, 2, NX)."""
         p, dev, keep, n = self._prep(x, (self.ntrace,))
         y = self._out(keep, dev, (n, 2, self.L - 1, 2, self.NX))
-        _check(self._lib.pt_apply(self._h, op, n, p, self._ptr(y, dev), dev))
+        self._call(keep, dev, self._lib.pt_apply, self._h, op, n, p, self._ptr(y, dev), dev)
         return y
 
     def local_solve(self, b):
         """x = (A^l)^{-1} b on layer-local fields (nrhs, sumR, NX)."""
         p, dev, keep, n = self._prep(b, (self.sumR * self.NX,))
         x = self._out(keep, dev, (n, self.sumR, self.NX))
-        _check(self._lib.pt_local_solve(self._h, n, p, self._ptr(x, dev), dev))
+        self._call(keep, dev, self._lib.pt_local_solve, self._h, n, p, self._ptr(x, dev), dev)
         return x
 
     def trace_rhs(self, f):
         p, dev, keep, n = self._prep(f, (self.NZ, self.NX))
         s = self._out(keep, dev, (n, 2, self.L - 1, 2, self.NX))
-        _check(self._lib.pt_trace_rhs(self._h, n, p, self._ptr(s, dev), dev))
+        self._call(keep, dev, self._lib.pt_trace_rhs, self._h, n, p, self._ptr(s, dev), dev)
         return s
 
     def reconstruct(self, f, x):
@@ -322,7 +352,7 @@ class Solver:
         if dev != dev2:
             raise TypeError("f and x must both be host or both device arrays")
         u = self._out(kf, dev, (n, self.NZ, self.NX))
-        _check(self._lib.pt_reconstruct(self._h, n, pf, px, self._ptr(u, dev), dev))
+        self._call(kf, dev, self._lib.pt_reconstruct, self._h, n, pf, px, self._ptr(u, dev), dev)
         return u
 
 
@@ -387,7 +417,7 @@ class Learned:
         """Add training pairs from the Krylov vectors of a sweep-only solve of the sources f."""
         p, dev, keep, n = solver._prep(f, (solver.NZ, solver.NX))
         added = C.c_int32()
-        _check(self._lib.pt_learned_collect(self._h, solver._h, n, p, dev, C.byref(added)))
+        solver._call(keep, dev, self._lib.pt_learned_collect, self._h, solver._h, n, p, dev, C.byref(added))
         return added.value
 
     def samples(self):
@@ -443,7 +473,12 @@ def solve_batch(solvers, fs):
     fp = (C.c_void_p * n)(*[p for p, _, _ in preps])
     up = (C.c_void_p * n)(*[Solver._ptr(u, dev0) for u in outs])
     ip = (C.POINTER(PtRhsInfo) * n)(*[C.cast(i, C.POINTER(PtRhsInfo)) for i in infos])
-    _check(L.pt_solve_batch(n, hs, ks, fp, up, dev0 or 0, ip), allow=(PT_ENOCONV,))
+    pairs = [sv._enter(keep, dev0) for sv, (_, keep, _) in zip(solvers, preps)]
+    try:
+        _check(L.pt_solve_batch(n, hs, ks, fp, up, dev0 or 0, ip), allow=(PT_ENOCONV,))
+    finally:
+        for pr in pairs:
+            Solver._leave(pr)
     return [(u, [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
                   "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in inf])
             for u, inf in zip(outs, infos)]

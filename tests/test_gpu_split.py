@@ -96,34 +96,43 @@ def test_split_bumps440_single_source():
     gs.close()
 
 
-@pytest.mark.parametrize("n_it", [2, 4])  # the paper's sweep count / the bench's for this form
-def test_split_layered_batch_matches_f64(n_it):
-    # the bench workload's medium and launch configuration (all 128 sources in one call, tuned tile shapes,
-    # device-resident input, tol 1e-10, maxit 60): every source against the float64 GPU path, and every
-    # eighth source against the direct solve of the oracle
-    torch = pytest.importorskip("torch")
+@pytest.fixture(scope="module")
+def layered_ref():
+    # the oracle's direct solve of all 128 sources of the layered workload (eight processes, each factoring)
+    from oracle.direct import direct_solve_parallel
     prob, f = synth.config3()
-    _flush(f"[gpu] split layered-1240x440-L16, 128 sources, tuned, n_it {n_it}")
-    gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=1e-10, maxit=60, gs_iters=n_it)
-    gs.tune(128)
-    ud_dev, info = gs.solve(torch.from_numpy(f).to("cuda:0"))
-    u = ud_dev.cpu().numpy()
-    gs.close()
-    g64 = P.Solver.from_problem(prob, max_nrhs=128, tol=1e-10, maxit=60)
-    g64.tune(128)
-    u64, info64 = g64.solve(f)
-    g64.close()
-    errs = [rel(u[r], u64[r]) for r in range(128)]
-    its = [i["iters"] for i in info]
-    its64 = [i["iters"] for i in info64]
-    _flush(f"[gpu] split layered max rel diff {max(errs):.2e}; iters {min(its)}..{max(its)} "
-           f"(float64 {min(its64)}..{max(its64)})")
-    assert max(errs) < 1e-8
-    assert all(i["converged"] for i in info)
-    assert max(its) <= max(its64) + 1
-    pick = list(range(0, 128, 8)) + [127]
-    ud = DirectSolver(prob).solve(f[pick])
-    derr = [rel(u[r], ud[k]) for k, r in enumerate(pick)]
-    derr64 = [rel(u64[r], ud[k]) for k, r in enumerate(pick)]
-    _flush(f"[gpu] layered vs direct: mixed {max(derr):.2e}, float64 {max(derr64):.2e}")
-    assert max(derr) < 1e-8 and max(derr64) < 1e-8
+    _flush("[gpu] oracle direct solve of layered-1240x440-L16, 128 sources")
+    return prob, f, direct_solve_parallel(prob, f, 8)
+
+
+@pytest.mark.parametrize("n_it", [2, 4])  # the paper's sweep count / the bench's for this form
+def test_split_layered_batch_matches_oracle(layered_ref, n_it):
+    # the bench workload's medium and launch configuration (all 128 sources in one call, tuned tile shapes,
+    # device-resident input, maxit 60): every source against the oracle's direct solve, for the mixed form
+    # and the float64 form, at the bench's GMRES tolerance 1e-8 (float64 bar 1e-8 met with margin) and at 1e-10
+    torch = pytest.importorskip("torch")
+    prob, f, ud = layered_ref
+    fd = torch.from_numpy(f).to("cuda:0")
+    for tol in (1e-8, 1e-10):
+        _flush(f"[gpu] split layered-1240x440-L16, 128 sources, tuned, n_it {n_it}, tol {tol:g}")
+        gs = P.Solver.from_problem(prob, precision="split-bf16", max_nrhs=128, tol=tol, maxit=60, gs_iters=n_it)
+        gs.tune(128)
+        u_dev, info = gs.solve(fd)
+        u = u_dev.cpu().numpy()
+        gs.close()
+        g64 = P.Solver.from_problem(prob, max_nrhs=128, tol=tol, maxit=60, gs_iters=n_it)
+        g64.tune(128)
+        u64_dev, info64 = g64.solve(fd)
+        u64 = u64_dev.cpu().numpy()
+        g64.close()
+        its = [i["iters"] for i in info]
+        its64 = [i["iters"] for i in info64]
+        derr = [rel(u[r], ud[r]) for r in range(128)]
+        derr64 = [rel(u64[r], ud[r]) for r in range(128)]
+        _flush(f"[gpu] layered vs direct, all 128: mixed {max(derr):.2e}, float64 {max(derr64):.2e}; iters "
+               f"{min(its)}..{max(its)} (float64 {min(its64)}..{max(its64)})")
+        assert all(i["converged"] for i in info) and all(i["converged"] for i in info64)
+        assert max(its) <= max(its64) + 1
+        assert max(derr) < 1e-6 and max(derr64) < 1e-8
+        if tol == 1e-10:
+            assert max(derr) < 1e-8

@@ -20,29 +20,31 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def test_uneven_batch_full_size_mixed():
-    torch = pytest.importorskip("torch")
+@pytest.fixture(scope="module")
+def uneven_ref():
+    from oracle.direct import direct_solve_jobs
     probs = synth.config4()
-    print("[gpu] uneven batch: " + ", ".join(p.name for p, _ in probs), flush=True)
+    print("[gpu] oracle direct solve of the uneven batch: " + ", ".join(p.name for p, _ in probs), flush=True)
+    return probs, direct_solve_jobs(probs, 8)
+
+
+@pytest.mark.parametrize("precision", ["split-bf16", "f64"])
+def test_uneven_batch_full_size(uneven_ref, precision):
+    torch = pytest.importorskip("torch")
+    probs, refs = uneven_ref
+    print(f"[gpu] uneven batch {precision}", flush=True)
     streams = [torch.cuda.Stream() for _ in probs]
-    solvers = [P.Solver.from_problem(p, precision="split-bf16", max_nrhs=f.shape[0], tol=1e-8, maxit=60,
+    solvers = [P.Solver.from_problem(p, precision=precision, max_nrhs=f.shape[0], tol=1e-8, maxit=60,
                                      stream=st.cuda_stream) for (p, f), st in zip(probs, streams)]
     res = P.solve_batch(solvers, [torch.from_numpy(f).to("cuda:0") for _, f in probs])
-    torch.cuda.synchronize()
-    for (p, f), (u, infos) in zip(probs, res):
+    bar = 1e-6 if precision != "f64" else 1e-8
+    for (p, f), (u, infos), ud in zip(probs, res, refs):
         assert all(i["converged"] for i in infos), p.name
         assert max(i["relres"] for i in infos) < 1e-7, p.name
-    sizes = [p.NX for p, _ in probs]
-    bumps = [i for i, (p, _) in enumerate(probs) if p.meta["index"] % 2 == 1]  # odd problems: bump media
-    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), max(bumps, key=lambda i: sizes[i])})
-    for i in pick:
-        p, f = probs[i]
-        u = res[i][0].cpu().numpy()
-        idx = [0, f.shape[0] - 1]
-        ud = DirectSolver(p).solve(f[idx])
-        errs = [rel(u[r], ud[k]) for k, r in enumerate(idx)]
-        print(f"[gpu] {p.name}: iters {sorted(set(x['iters'] for x in res[i][1]))}, rel err {max(errs):.2e}",
-              flush=True)
-        assert max(errs) < 1e-6, p.name
+        uh = u.cpu().numpy()
+        errs = [rel(uh[r], ud[r]) for r in range(f.shape[0])]
+        print(f"[gpu] {p.name}: iters {sorted(set(x['iters'] for x in infos))}, max rel err over "
+              f"{len(errs)} sources {max(errs):.2e}", flush=True)
+        assert max(errs) < bar, p.name
     for sv in solvers:
         sv.close()

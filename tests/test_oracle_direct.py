@@ -50,3 +50,16 @@ def test_second_order_convergence_to_hankel():
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert errs[2] < 2e-3
     assert 3.5 <= r1 <= 4.5 and 3.5 <= r2 <= 4.5, (errs, r1, r2)
+
+
+def test_parallel_direct_solve_equals_serial():
+    # splitting the sources over separate processes changes nothing: each process factors the same matrix
+    # with the same SuperLU and solves its share (bitwise equal to one process solving them all)
+    import synth
+    from oracle.direct import DirectSolver, direct_solve_jobs, direct_solve_parallel
+    prob, f = synth.config_small(nx=20, nz=24, npml=4, L=2, nrhs=5, seed=9)
+    ref = DirectSolver(prob).solve(f)
+    assert np.array_equal(direct_solve_parallel(prob, f, 3), ref)
+    prob2, f2 = synth.config_small(nx=16, nz=18, npml=3, L=2, nrhs=2, seed=10)
+    out = direct_solve_jobs([(prob, f[:2]), (prob2, f2)], 2)
+    assert np.array_equal(out[0], ref[:2]) and np.array_equal(out[1], DirectSolver(prob2).solve(f2))

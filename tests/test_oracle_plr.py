@@ -75,3 +75,27 @@ def test_recursive_and_sparse_factorized_products_agree():
     b = plr.sparse_factorized_matvec(H, X)
     assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(a).max())
     assert np.allclose(a, plr.to_dense(H) @ X, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+
+
+def test_stored_entries_hand_counted_tree():
+    # 8 x 8 block [[rank 1, rank 2], [0, full rank]] with r_max = 2: the whole block has rank > 2 and splits;
+    # top-left: one low-rank leaf of rank 1 (4 + 4) * 1 = 8 entries; top-right: rank 2, (4 + 4) * 2 = 16;
+    # bottom-left: rank 0 (no stored entries); bottom-right: full rank, splits into four 2 x 2 dense leaves
+    # (min side 2 <= r_max), 4 * 4 = 16.  Hand count: 8 + 16 + 0 + 16 = 40 entries in 7 leaves.
+    rng = np.random.default_rng(5)
+    M = np.zeros((8, 8), dtype=np.complex128)
+    M[:4, :4] = rand_lowrank(4, 4, 1, rng)
+    M[:4, 4:] = rand_lowrank(4, 4, 2, rng)
+    M[4:, 4:] = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    H = plr.compress(M, rmax=2, eps=1e-9)
+    lv = plr.leaves(H)
+    assert len(lv) == 7
+    assert sorted((lf.kind, lf.m, lf.n) for lf in lv) == sorted(
+        [("lr", 4, 4)] * 3 + [("dense", 2, 2)] * 4)
+    assert plr.stored_entries(H) == 40
+    # odd sides: 7 x 7 full rank, r_max = 2 -> quarters 4x4, 4x3, 3x4, 3x3 (all still full rank, min side > 2)
+    # -> each splits again into 2x2 / 2x1 / 1x2 / 1x1 dense pieces covering it: 49 stored entries in 16 leaves
+    N = rng.standard_normal((7, 7)) + 1j * rng.standard_normal((7, 7))
+    H = plr.compress(N, rmax=2, eps=1e-9)
+    assert plr.stored_entries(H) == 49 and len(plr.leaves(H)) == 16
+    assert all(lf.kind == "dense" for lf in plr.leaves(H))
