@@ -72,10 +72,33 @@ def rel_errors(u, ref):
     return [float(np.linalg.norm(u[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(ref.shape[0])]
 
 
-def oracle_reference(prob, f, workers=8):
-    """The oracle's direct solve of every source (factored in `workers` separate processes)."""
-    from oracle.direct import direct_solve_parallel
-    return direct_solve_parallel(prob, f, workers)
+class OracleReferences:
+    """The oracle's direct solve of every source of the checked workloads, computed in separate processes
+    (started before this process touches the GPU, at lowered priority) while the GPU forms run."""
+
+    def __init__(self, workloads, parts=4):
+        from oracle.direct import DirectSolveJobs, split_sources
+        self.keys, jobs = [], []
+        for wl, probs in workloads.items():
+            for i, (pw, fw) in enumerate(probs):
+                for job in split_sources(pw, fw, parts if len(probs) == 1 else 1):
+                    self.keys.append((wl, i))
+                    jobs.append(job)
+        self.handle = DirectSolveJobs(jobs, nice=10)
+        self.refs = None
+
+    def get(self, wl, i, prob, f):
+        import numpy as np
+        if self.refs is None:
+            out = self.handle.results(timeout=900)
+            self.refs = {}
+            for key, u in zip(self.keys, out):
+                self.refs.setdefault(key, []).append(u)
+            self.refs = {k: np.concatenate(v, axis=0) for k, v in self.refs.items()}
+        if (wl, i) not in self.refs:  # a workload not started in the background: solved here
+            from oracle.direct import DirectSolver
+            self.refs[(wl, i)] = DirectSolver(prob).solve(f)
+        return self.refs[(wl, i)]
 
 
 def cpu_direct_baseline(prob, f, nsample=32, reps=3):
@@ -146,11 +169,9 @@ def profile_classes(solvers, nprof, run):
     return {"nprof": nprof, "total": tot, "classes": cls}
 
 
-def run_uneven(P, torch, precision, steps, warmup, tol=1e-8):
+def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8):
     """The uneven batch: 8 independent problems (grids 240..850 padded, L 4..16), 32 sources each, one
     pt_solve_batch call per step, each problem on its own stream; sources device-resident."""
-    import synth
-    probs = synth.config4()
     streams = [torch.cuda.Stream() for _ in probs]
     t0 = time.perf_counter()
     solvers = [P.Solver.from_problem(p, precision=precision, tol=tol, maxit=60, max_nrhs=f.shape[0],
@@ -414,8 +435,19 @@ def main():
               "and there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
-    # the oracle's polarized-traces timing runs in a child process beside the GPU work (started before this
-    # process touches the GPU)
+    # inputs first, then the oracle's processes (reference solves of every checked source, and the timing of
+    # the naive polarized solve) beside the GPU work: all started before this process touches the GPU
+    import synth
+    prob, f = make_workload(args.workload)
+    if args.nrhs:
+        f = f[: args.nrhs]
+    nrhs = f.shape[0]
+    inputs = {args.workload: [(prob, f)]}
+    if not args.no_forms:
+        inputs.setdefault("bumps440", [make_workload("bumps440")])
+        if not args.no_uneven:
+            inputs["uneven8"] = synth.config4()
+    refs = OracleReferences(inputs) if args.check else None
     polar_child = start_cpu_polar() if not args.no_cpu else None
 
     import numpy as np  # noqa: F401
@@ -438,10 +470,6 @@ def main():
         log(f"calibration copy {args.calibrate_copy} MiB done")
         del src, dst, big
 
-    prob, f = make_workload(args.workload)
-    if args.nrhs:
-        f = f[: args.nrhs]
-    nrhs = f.shape[0]
     log(f"workload {prob.name}: grid {prob.NZ}x{prob.NX}, L={prob.L}, nrhs={nrhs}")
 
     # ---- GPU forms (timed); every output is kept on the host for the oracle check afterwards
@@ -467,7 +495,7 @@ def main():
         for wl, prec, plr, clo in extra:
             if (wl, prec, plr, clo) in have or (wl == args.workload and args.nrhs):
                 continue
-            pw, fw = (prob, f) if wl == args.workload else make_workload(wl)
+            pw, fw = inputs[wl][0] if wl in inputs else make_workload(wl)
             log(f"form {wl} {prec}{' plr' if plr else ''}{' extrapolation closure' if clo == 'extrap' else ''}")
             form, u = run_form(P, torch, pw, fw, prec, max(args.steps, 10) if fw.shape[0] == 1 else args.steps,
                                args.warmup, stream, profile=True, plr=plr, tune=not args.no_tune, tol=args.tol,
@@ -480,7 +508,7 @@ def main():
         if not args.no_uneven:
             for prec in ("split-bf16", "f64"):
                 log(f"form uneven8 {prec}: 8 problems x 32 sources, one pt_solve_batch per step")
-                form, parts = run_uneven(P, torch, prec, args.steps, args.warmup, tol=args.tol)
+                form, parts = run_uneven(P, torch, prec, args.steps, args.warmup, inputs["uneven8"], tol=args.tol)
                 form["roofline"] = roofline(form)
                 log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step")
                 runs.append((form, "uneven8", parts))
@@ -492,16 +520,10 @@ def main():
 
     # ---- oracle check of every source (outside every timed region)
     if args.check:
-        refs = {}
         for form, wl, parts in runs:
             errs_all = []
             for i, (pw, fw, uu) in enumerate(parts):
-                key = (wl, i)
-                if key not in refs:
-                    t0 = time.perf_counter()
-                    refs[key] = oracle_reference(pw, fw)
-                    log(f"oracle direct solve of {pw.name}, {fw.shape[0]} sources: {time.perf_counter() - t0:.1f} s")
-                errs = rel_errors(uu, refs[key])
+                errs = rel_errors(uu, refs.get(wl, i, pw, fw))
                 errs_all += errs
                 if wl == "uneven8":
                     form["problems"][i]["rel_err_vs_oracle"] = max(errs)
@@ -510,7 +532,7 @@ def main():
             form["within_bar"] = form["rel_err_vs_oracle"] <= (1e-8 if form["precision"] == "f64" else ERR_BAR)
             log(f"  {wl} {form['precision']}: max rel err {form['rel_err_vs_oracle']:.2e} over "
                 f"{len(errs_all)} sources")
-        refs.clear()
+        refs = None
 
     head = [fm for fm, wl, _ in runs if wl == args.workload]
     chosen = None

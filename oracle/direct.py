@@ -45,57 +45,86 @@ def direct_solve(prob, f: np.ndarray) -> np.ndarray:
 
 
 def _worker() -> None:
-    """Child-process entry of direct_solve_jobs: argv = job file, result file."""
+    """Child-process entry of DirectSolveJobs: argv = job file, result file, niceness."""
+    import os
     import pickle
     import sys
 
+    if int(sys.argv[3]):
+        os.nice(int(sys.argv[3]))
     with open(sys.argv[1], "rb") as fh:
         prob, f = pickle.load(fh)
     np.save(sys.argv[2], DirectSolver(prob).solve(f))
+    print(f"[oracle] direct solve of {getattr(prob, 'name', 'problem')}, {f.shape[0]} sources: done",
+          file=sys.stderr, flush=True)
+
+
+class DirectSolveJobs:
+    """u* = A^{-1} h^2 f for a list of independent (problem, sources) jobs, each factored and solved in a
+    separate Python process, all started at once; results() waits for them.
+
+    The arithmetic is exactly DirectSolver's; the processes only bound the wall time of checking every source
+    of a large batch.  Start them before the calling process initialises a GPU runtime (a process that holds
+    one should not spawn programs).  `nice` lowers their scheduling priority.
+    """
+
+    def __init__(self, jobs, nice: int = 0):
+        import os
+        import pickle
+        import subprocess
+        import sys
+        import tempfile
+
+        self.n = len(jobs)
+        self._tmp = tempfile.TemporaryDirectory(prefix="oracle_direct_")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        env = dict(os.environ)
+        env["PYTHONPATH"] = root + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
+        env["OMP_NUM_THREADS"] = "1"
+        self._procs = []
+        for i, job in enumerate(jobs):
+            jf, rf = os.path.join(self._tmp.name, f"job{i}.pkl"), os.path.join(self._tmp.name, f"u{i}.npy")
+            with open(jf, "wb") as fh:
+                pickle.dump(job, fh, protocol=pickle.HIGHEST_PROTOCOL)
+            cmd = [sys.executable, "-c", "from oracle.direct import _worker; _worker()", jf, rf, str(int(nice))]
+            self._procs.append((rf, subprocess.Popen(cmd, env=env)))
+
+    def results(self, timeout: float | None = None) -> list:
+        import time
+
+        t_end = None if timeout is None else time.monotonic() + timeout
+        out = []
+        try:
+            for i, (rf, p) in enumerate(self._procs):
+                left = None if t_end is None else max(1.0, t_end - time.monotonic())
+                if p.wait(timeout=left) != 0:
+                    raise RuntimeError(f"oracle direct-solve worker for job {i} failed (exit {p.returncode})")
+                out.append(np.load(rf))
+        finally:
+            for _, p in self._procs:
+                if p.poll() is None:
+                    p.kill()
+                    p.wait()
+            self._tmp.cleanup()
+        return out
 
 
 def direct_solve_jobs(jobs, workers: int = 8) -> list:
-    """u* = A^{-1} h^2 f for a list of independent (problem, sources) jobs.
-
-    Each job is factored and solved on its own in a separate Python process
-    (at most `workers` at a time), with exactly the arithmetic of DirectSolver;
-    this only bounds the wall time of checking every source of a large batch.
-    """
-    import os
-    import pickle
-    import subprocess
-    import sys
-    import tempfile
-
+    """DirectSolveJobs over `jobs`, at most `workers` processes at a time."""
     jobs = list(jobs)
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ)
-    env["PYTHONPATH"] = root + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
-    env["OMP_NUM_THREADS"] = "1"
-    out = [None] * len(jobs)
-    with tempfile.TemporaryDirectory(prefix="oracle_direct_") as tmp:
-        todo = list(range(len(jobs)))
-        running = []
-        while todo or running:
-            while todo and len(running) < max(1, workers):
-                i = todo.pop(0)
-                jf, rf = os.path.join(tmp, f"job{i}.pkl"), os.path.join(tmp, f"u{i}.npy")
-                with open(jf, "wb") as fh:
-                    pickle.dump(jobs[i], fh, protocol=pickle.HIGHEST_PROTOCOL)
-                cmd = [sys.executable, "-c", "import sys; from oracle.direct import _worker; _worker()", jf, rf]
-                running.append((i, rf, subprocess.Popen(cmd, env=env)))
-            i, rf, p = running.pop(0)
-            if p.wait() != 0:
-                for _, _, q in running:
-                    q.kill()
-                raise RuntimeError(f"oracle direct-solve worker for job {i} failed (exit {p.returncode})")
-            out[i] = np.load(rf)
-            os.remove(rf)
+    out = []
+    for k in range(0, len(jobs), max(1, workers)):
+        out += DirectSolveJobs(jobs[k:k + max(1, workers)]).results()
     return out
+
+
+def split_sources(prob, f: np.ndarray, parts: int) -> list:
+    """(problem, sources) jobs of about equal size covering f's sources in order."""
+    f = np.asarray(f, dtype=np.complex128)
+    idx = [p for p in np.array_split(np.arange(f.shape[0]), max(1, min(parts, f.shape[0]))) if p.size]
+    return [(prob, f[p]) for p in idx]
 
 
 def direct_solve_parallel(prob, f: np.ndarray, workers: int = 8) -> np.ndarray:
     """direct_solve for (nrhs, NZ, NX) sources, the sources split evenly over `workers` processes."""
-    f = np.asarray(f, dtype=np.complex128)
-    parts = [p for p in np.array_split(np.arange(f.shape[0]), max(1, min(workers, f.shape[0]))) if p.size]
-    return np.concatenate(direct_solve_jobs([(prob, f[p]) for p in parts], workers), axis=0)
+    return np.concatenate(direct_solve_jobs(split_sources(prob, f, workers), workers), axis=0)

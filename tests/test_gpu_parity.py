@@ -126,8 +126,10 @@ def test_maxit_reports_noconv_and_last_iterate(small):
     g = P.Solver.from_problem(prob, max_nrhs=3, tol=1e-14, maxit=2)
     u, info = g.solve(f)
     assert all(not i["converged"] and i["iters"] == 2 for i in info)
+    fc = np.ascontiguousarray(f)
+    uc = np.empty_like(fc)  # kept alive: the call writes the field into it
     with pytest.raises(P.PolarError) as e:
-        P.polar._check(g._lib.pt_solve(g._h, 3, f.ctypes.data, np.empty_like(f).ctypes.data, 0, None))
+        P.polar._check(g._lib.pt_solve(g._h, 3, fc.ctypes.data, uc.ctypes.data, 0, None))
     assert e.value.status == P.polar.PT_ENOCONV
     s = ps.rhs(ps.newton(f))
     x, oinfo = ps.fgmres(s, tol=1e-14, maxit=2)
@@ -156,6 +158,7 @@ def test_reruns_are_bitwise_identical(precision, nrhs):
 def test_nan_source_without_info_is_noconv(L):
     # the convergence decision does not depend on the caller asking for per-source info
     prob, f = synth.config_small(nx=24, nz=30, npml=5, L=L, nrhs=2, seed=93)
+    f = np.ascontiguousarray(f, dtype=np.complex128)
     g = P.Solver.from_problem(prob, max_nrhs=2, tol=1e-10, maxit=40)
     fb = f.copy()
     fb[1, prob.npml + 10, prob.npml + 5] = np.nan

@@ -98,11 +98,10 @@ def test_split_bumps440_single_source():
 
 @pytest.fixture(scope="module")
 def layered_ref():
-    # the oracle's direct solve of all 128 sources of the layered workload (eight processes, each factoring)
-    from oracle.direct import direct_solve_parallel
+    # the oracle's direct solve of all 128 sources of the layered workload (one factorisation, one batched solve)
     prob, f = synth.config3()
     _flush("[gpu] oracle direct solve of layered-1240x440-L16, 128 sources")
-    return prob, f, direct_solve_parallel(prob, f, 8)
+    return prob, f, DirectSolver(prob).solve(f)
 
 
 @pytest.mark.parametrize("n_it", [2, 4])  # the paper's sweep count / the bench's for this form

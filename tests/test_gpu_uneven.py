@@ -22,10 +22,9 @@ def rel(a, b):
 
 @pytest.fixture(scope="module")
 def uneven_ref():
-    from oracle.direct import direct_solve_jobs
     probs = synth.config4()
     print("[gpu] oracle direct solve of the uneven batch: " + ", ".join(p.name for p, _ in probs), flush=True)
-    return probs, direct_solve_jobs(probs, 8)
+    return probs, [DirectSolver(p).solve(f) for p, f in probs]
 
 
 @pytest.mark.parametrize("precision", ["split-bf16", "f64"])
