@@ -73,31 +73,21 @@ def rel_errors(u, ref):
 
 
 class OracleReferences:
-    """The oracle's direct solve of every source of the checked workloads, computed in separate processes
-    (started before this process touches the GPU, at lowered priority) while the GPU forms run."""
+    """The oracle's direct solve of every source of a checked workload, computed on first use after the GPU
+    forms (outside every timed region) and kept for the forms that share the workload."""
 
-    def __init__(self, workloads, parts=4):
-        from oracle.direct import DirectSolveJobs, split_sources
-        self.keys, jobs = [], []
-        for wl, probs in workloads.items():
-            for i, (pw, fw) in enumerate(probs):
-                for job in split_sources(pw, fw, parts if len(probs) == 1 else 1):
-                    self.keys.append((wl, i))
-                    jobs.append(job)
-        self.handle = DirectSolveJobs(jobs, nice=10)
-        self.refs = None
+    def __init__(self):
+        self.refs = {}
+        self.factor_s = {}
 
     def get(self, wl, i, prob, f):
-        import numpy as np
-        if self.refs is None:
-            out = self.handle.results(timeout=900)
-            self.refs = {}
-            for key, u in zip(self.keys, out):
-                self.refs.setdefault(key, []).append(u)
-            self.refs = {k: np.concatenate(v, axis=0) for k, v in self.refs.items()}
-        if (wl, i) not in self.refs:  # a workload not started in the background: solved here
-            from oracle.direct import DirectSolver
-            self.refs[(wl, i)] = DirectSolver(prob).solve(f)
+        from oracle.direct import DirectSolver
+        if (wl, i) not in self.refs:
+            t0 = time.perf_counter()
+            ds = DirectSolver(prob)
+            self.factor_s[(wl, i)] = time.perf_counter() - t0
+            self.refs[(wl, i)] = ds.solve(f)
+            log(f"  oracle direct solve of {prob.name}, {f.shape[0]} sources: {time.perf_counter() - t0:.1f} s")
         return self.refs[(wl, i)]
 
 
@@ -121,31 +111,21 @@ def cpu_direct_baseline(prob, f, nsample=32, reps=3):
             "reps": reps}
 
 
-def cpu_polar_child():
-    """Entry of the child process that times the oracle's naive polarized-traces solve (Alg. 1 offline,
-    Alg. 2 online) on the smooth single-source workload; prints one JSON line."""
+def cpu_polar_baseline(workload="constant100", reps=3):
+    """The oracle's naive polarized-traces solve (Alg. 1 offline, Alg. 2 online) on the host: setup time, then
+    the median online time of one source over `reps` runs."""
     import statistics
-    import synth
     from oracle.polarized import PolarizedSolver
-    prob, f = synth.config2()
+    prob, f = make_workload(workload)
     t0 = time.perf_counter()
     ps = PolarizedSolver(prob)
     setup = time.perf_counter() - t0
     ts = []
-    for _ in range(3):
+    for _ in range(reps):
         t0 = time.perf_counter()
-        ps.solve(f, tol=1e-8)
+        ps.solve(f[:1], tol=1e-8)
         ts.append(time.perf_counter() - t0)
-    print(json.dumps({"workload": "bumps440", "setup_s": setup, "online_s_per_rhs": statistics.median(ts),
-                      "reps": 3}), flush=True)
-
-
-def start_cpu_polar():
-    """Start the oracle's polarized-solve timing in a child process (one core) that runs beside the GPU work."""
-    import subprocess
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-polar-child"], env=env,
-                            stdout=subprocess.PIPE, text=True)
+    return {"workload": prob.name, "setup_s": setup, "online_s_per_rhs": statistics.median(ts), "reps": reps}
 
 
 def profile_classes(solvers, nprof, run):
@@ -404,7 +384,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="only the headline workload's forms")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch of eight problems")
-    ap.add_argument("--cpu-polar-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--all-forms", action="store_true",
                     help="also float32 blocks, the extrapolation closure, the bumps-440 workload in float32 and "
                          "mixed form, and compressed blocks")
@@ -421,9 +400,6 @@ def main():
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
     args = ap.parse_args()
-    if args.cpu_polar_child:
-        cpu_polar_child()
-        return 0
     gs_arg = args.gs_iters if args.gs_iters == "auto" else int(args.gs_iters)
     if args.plr and args.precision not in ("auto", "f64"):
         print("--plr takes float64 blocks: use --precision f64", file=sys.stderr)
@@ -435,8 +411,6 @@ def main():
               "and there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
-    # inputs first, then the oracle's processes (reference solves of every checked source, and the timing of
-    # the naive polarized solve) beside the GPU work: all started before this process touches the GPU
     import synth
     prob, f = make_workload(args.workload)
     if args.nrhs:
@@ -447,8 +421,6 @@ def main():
         inputs.setdefault("bumps440", [make_workload("bumps440")])
         if not args.no_uneven:
             inputs["uneven8"] = synth.config4()
-    refs = OracleReferences(inputs) if args.check else None
-    polar_child = start_cpu_polar() if not args.no_cpu else None
 
     import numpy as np  # noqa: F401
     import torch
@@ -519,6 +491,7 @@ def main():
         spec = run_spectral(P, torch, cpu=not args.no_cpu)
 
     # ---- oracle check of every source (outside every timed region)
+    refs = OracleReferences()
     if args.check:
         for form, wl, parts in runs:
             errs_all = []
@@ -532,7 +505,6 @@ def main():
             form["within_bar"] = form["rel_err_vs_oracle"] <= (1e-8 if form["precision"] == "f64" else ERR_BAR)
             log(f"  {wl} {form['precision']}: max rel err {form['rel_err_vs_oracle']:.2e} over "
                 f"{len(errs_all)} sources")
-        refs = None
 
     head = [fm for fm, wl, _ in runs if wl == args.workload]
     chosen = None
@@ -566,14 +538,9 @@ def main():
     if not args.no_cpu:
         log("cpu baseline: oracle direct solve (factorisation and a 32-source batch, medians of 3)")
         cb = cpu_direct_baseline(prob, f)
-        polar = None
-        if polar_child is not None:
-            try:
-                txt, _ = polar_child.communicate(timeout=600)
-                polar = json.loads(txt.strip().splitlines()[-1]) if polar_child.returncode == 0 else None
-            except Exception as e:  # the polarized oracle's timing is reported when it finishes
-                polar_child.kill()
-                log(f"polarized oracle timing failed: {e}")
+        pw = "bumps440" if args.all_forms else "constant100"
+        log(f"cpu baseline: the oracle's polarized-traces solve on {pw} (setup, then the online part, median of 3)")
+        polar = cpu_polar_baseline(pw)
         out["cpu_baseline"] = {
             "value": cb["batch"] / cb["batch_solve_s"], "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": (f"SuperLU sparse direct solve of the {prob.NZ}x{prob.NX} padded system: factorisation "
