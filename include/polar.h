@@ -263,6 +263,23 @@ pt_status pt_gauss_seidel(pt_solver* s, int32_t nrhs, const double* f, double* u
 pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
                          double* const* u, int32_t on_device, pt_rhs_info* const* info);
 
+/* The variant of pt_apply that allocates nothing, for callers that cannot
+ * allocate device memory at call time (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same operators and the
+ * same result as pt_apply (bit for bit); x and y are device pointers
+ * (nrhs, 2, L-1, 2, NX) on the solver's device, and y must not overlap x.
+ * Instead of the solver's work buffers, the Gauss-Seidel iterates, the staged
+ * input and the k-slice partial tiles of the split-bfloat16 launches live in
+ * one fixed 64 MiB device array per GPU (held until the process ends; its
+ * address is taken at the first pt_setup on that device).  It needs
+ * 3 * nrhs * 4(L-1)NX * 16 bytes (each rounded up to 256) plus the partial
+ * tiles; larger calls return PT_EINVAL with the size in pt_last_error().
+ * Every call on one GPU shares that array and overwrites it (nothing in it
+ * needs to start at zero), so calls that overlap on one GPU, from any
+ * solvers or streams, race: serialise them.  Synchronises the solver's
+ * stream before returning. */
+pt_status pt_apply_noalloc(pt_solver* s, int32_t op, int32_t nrhs, const double* x, double* y);
+
 /* ---- live kernel timing ----------------------------------------------- */
 
 typedef struct {

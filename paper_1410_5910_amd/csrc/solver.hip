@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -108,6 +109,13 @@ const TuneCfg* tuned(const pt_solver* S, const Launch& Lc, int nrhs) {
   return &it->second;
 }
 
+// complex floats of k-slice partial tiles a split-bfloat16 launch writes (0: one slice)
+size_t split_part_need(const pt_solver* S, const Launch& Lc, int nrhs, const TuneCfg* tc) {
+  const SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
+  const int ks = sc.kslices > 0 ? sc.kslices : split_kslices(Lc.njobs, S->NX, nrhs, sc.tile_rhs);
+  return ks > 1 ? (size_t)ks * Lc.njobs * nrhs * S->NX : 0;
+}
+
 pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc) {
   if (Lc.njobs == 0) return PT_OK;
   ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
@@ -130,8 +138,7 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
   else if (Lc.split) {
     SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
     if (sc.stream && sc.stream != Lc.two_term) sc.stream = 0;  // the form only serves launches it fits
-    const int ks = sc.kslices > 0 ? sc.kslices : split_kslices(Lc.njobs, S->NX, nrhs, sc.tile_rhs);
-    const size_t need = (size_t)ks * Lc.njobs * nrhs * S->NX;
+    const size_t need = split_part_need(S, Lc, nrhs, tc);
     float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
@@ -1803,6 +1810,34 @@ pt_status check_nrhs(const pt_solver* S, int nrhs) {
 
 }  // namespace polar_impl
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of pt_apply_noalloc: the Gauss-Seidel iterates, the
+// staged input and the k-slice partial tiles live here instead of in the
+// solver's buffers.  In host code `scratch` names a host-side stand-in; its
+// device address comes from hipGetSymbolAddress, once per device, at the first
+// pt_setup on that device (with the device current).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;  // 64 MiB per device
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+namespace polar_impl {
+pt_status scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(PT_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PT_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(PT_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = (unsigned char*)ptr;
+  return PT_OK;
+}
+}  // namespace polar_impl
+
 // ===========================================================================
 // C-ABI
 // ===========================================================================
@@ -2104,6 +2139,10 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
   S->f32 = false;
   S->st = (hipStream_t)hip_stream;
   (void)hipGetDevice(&S->device);
+  if (const pt_status sc = scratch_init(S->device); sc != PT_OK) {
+    delete S;
+    return sc;
+  }
   make_layout(S);
   const int NX = S->NX, NZ = S->NZ;
   const double delta = S->npml * S->h;
@@ -2370,18 +2409,13 @@ pt_status pt_get_plr_block(const pt_solver* S, int32_t layer, int32_t j, int32_t
   return PT_OK;
 }
 
-pt_status pt_apply(pt_solver* S, int32_t op, int32_t nrhs, const double* x, double* y, int32_t on_device) {
-  PTCHK(check_nrhs(S, nrhs));
-  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
-  if (!x || !y) return fail(PT_EINVAL, "null vector");
+}  // extern "C"
+
+namespace polar_impl {
+
+// y = op(x) on device vectors (both pt_apply and pt_apply_noalloc)
+pt_status apply_dispatch(pt_solver* S, int32_t op, const double2* xd, double2* yd, int nrhs) {
   const size_t n = (size_t)nrhs * S->Nt;
-  const double2* xd = (const double2*)x;
-  double2* yd = (double2*)y;
-  if (!on_device) {
-    HIPCHK(hipMemcpyAsync(S->U2.p, x, n * sizeof(double2), hipMemcpyHostToDevice, S->st));
-    xd = S->U2.p;
-    yd = S->tmp.p;
-  }
   switch (op) {
     case PT_OP_A: PTCHK(apply_op(S, S->opA, xd, yd, nrhs)); break;
     case PT_OP_R: PTCHK(apply_op(S, S->opR, xd, yd, nrhs)); break;
@@ -2412,6 +2446,26 @@ pt_status pt_apply(pt_solver* S, int32_t op, int32_t nrhs, const double* x, doub
       break;
     default: return fail(PT_EINVAL, "unknown operator");
   }
+  return PT_OK;
+}
+
+}  // namespace polar_impl
+
+extern "C" {
+
+pt_status pt_apply(pt_solver* S, int32_t op, int32_t nrhs, const double* x, double* y, int32_t on_device) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
+  if (!x || !y) return fail(PT_EINVAL, "null vector");
+  const size_t n = (size_t)nrhs * S->Nt;
+  const double2* xd = (const double2*)x;
+  double2* yd = (double2*)y;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(S->U2.p, x, n * sizeof(double2), hipMemcpyHostToDevice, S->st));
+    xd = S->U2.p;
+    yd = S->tmp.p;
+  }
+  PTCHK(apply_dispatch(S, op, xd, yd, nrhs));
   if (!on_device) HIPCHK(hipMemcpyAsync(y, yd, n * sizeof(double2), hipMemcpyDeviceToHost, S->st));
   HIPCHK(hipStreamSynchronize(S->st));
   return PT_OK;
@@ -2552,6 +2606,53 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
   }
   HIPCHK(hipStreamSynchronize(S->st));
   return conv ? PT_OK : fail(PT_ENOCONV, "GMRES did not converge for every source (maxit, or a source not finite)");
+}
+
+
+/* The variant of pt_apply that allocates nothing (see polar.h). */
+pt_status pt_apply_noalloc(pt_solver* S, int32_t op, int32_t nrhs, const double* x, double* y) {
+  PTCHK(check_nrhs(S, nrhs));
+  if (S->L < 2) return fail(PT_EINVAL, "no interfaces (L = 1)");
+  if (!x || !y) return fail(PT_EINVAL, "null vector");
+  if (op < PT_OP_A || op > PT_OP_PRECOND_EXTRAP) return fail(PT_EINVAL, "unknown operator");
+  unsigned char* base = (S->device >= 0 && S->device < kMaxDevices) ? g_scratch_ptr[S->device] : nullptr;
+  if (!base) return fail(PT_EHIP, "no scratch address for this device");
+  // scratch layout: U1 | U2 | staged input | k-slice partial tiles (each 256-byte aligned)
+  const size_t vec = ((size_t)nrhs * S->Nt * sizeof(double2) + 255) & ~(size_t)255;
+  size_t part = 0;  // the largest partial-tile set a launch of this call writes
+  if (S->split) {
+    std::vector<const Launch*> ls{&S->bterm, &S->opA, &S->opA2, &S->opR, &S->opX, &S->opX2, &S->opRX,
+                                  &S->gsRX, &S->tX};
+    for (const Launch& Lc : S->sweep) ls.push_back(&Lc);
+    for (const Launch* Lc : ls)
+      if (Lc->split && Lc->njobs > 0) {
+        const size_t need = split_part_need(S, *Lc, nrhs, tuned(S, *Lc, nrhs));
+        if (need <= S->part.n) part = std::max(part, need);  // the same k-slice decision as pt_apply
+      }
+  }
+  const size_t bytes = 3 * vec + part * sizeof(float2);
+  if (bytes > kScratchBytes)
+    return fail(PT_EINVAL, "pt_apply_noalloc needs " + std::to_string(bytes) + " bytes of scratch for nrhs = " +
+                               std::to_string(nrhs) + "; the maximum is " + std::to_string(kScratchBytes));
+  // run the shared dispatch with the solver's work buffers pointed at the scratch; restored on every path
+  struct Swap {
+    pt_solver* S;
+    double2 *u1, *u2, *s;
+    float2* part;
+    ~Swap() {
+      S->U1.p = u1;
+      S->U2.p = u2;
+      S->s.p = s;
+      S->part.p = part;
+    }
+  } keep{S, S->U1.p, S->U2.p, S->s.p, S->part.p};
+  S->U1.p = (double2*)base;
+  S->U2.p = (double2*)(base + vec);
+  S->s.p = (double2*)(base + 2 * vec);
+  S->part.p = part ? (float2*)(base + 3 * vec) : nullptr;
+  PTCHK(apply_dispatch(S, op, (const double2*)x, (double2*)y, nrhs));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
 }
 
 }  // extern "C"

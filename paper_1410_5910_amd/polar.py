@@ -35,7 +35,7 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
-           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel")
+           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel", "pt_apply_noalloc")
 CLASSES = ("local", "sweep", "reflect", "operator", "presolve")
 
 
@@ -108,6 +108,7 @@ def lib():
         L.pt_get_block.argtypes = [vp, i32, i32, i32, dp]
         L.pt_get_plr_block.argtypes = [vp, i32, i32, i32, dp, C.POINTER(i32), C.POINTER(C.c_int64)]
         L.pt_apply.argtypes = [vp, i32, i32, vp, vp, i32]
+        L.pt_apply_noalloc.argtypes = [vp, i32, i32, vp, vp]
         L.pt_local_solve.argtypes = [vp, i32, vp, vp, i32]
         L.pt_trace_rhs.argtypes = [vp, i32, vp, vp, i32]
         L.pt_reconstruct.argtypes = [vp, i32, vp, vp, vp, i32]
