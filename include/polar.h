@@ -162,6 +162,8 @@ typedef struct {
                            pre-solve (0: line-by-line pre-solve)                 */
   double plr_ms;        /* wall time of the GPU compression inside pt_setup
                            (0 without PLR)                                        */
+  int32_t max_nrhs;     /* the options' max_nrhs                                  */
+  int32_t precision;    /* the options' pt_precision                              */
 } pt_layout;
 
 typedef struct pt_solver pt_solver;
@@ -185,6 +187,32 @@ pt_status pt_solve(pt_solver* s, int32_t nrhs, const double* f, double* u, int32
                    pt_rhs_info* info);
 
 void pt_free(pt_solver* s); /* NULL is a no-op */
+
+/* Several problems' offline parts (Alg. 1) at once, e.g. the problems of an
+ * uneven batch: problem i is set up as by pt_setup(&probs[i], &opts[i],
+ * hip_streams[i], &out[i]) on its own host thread, on the caller's current
+ * device, so the latency-bound factorisation launches of different problems
+ * overlap on the GPU when their streams are distinct (hip_streams may be NULL:
+ * every problem on the null stream, one after another in effect).  On any
+ * failure every solver of the batch is freed, out[] is all NULL, and the
+ * first failing problem's status is returned (pt_last_error names it). */
+pt_status pt_setup_batch(int32_t nprob, const pt_problem* probs, const pt_options* opts, void* const* hip_streams,
+                         pt_solver** out);
+
+/* The offline state of a solver -- the local factors, the trace blocks, the
+ * interface Green's functions when kept, the compressed (PLR) blocks and the
+ * tuned launch shapes, with the problem and the options -- written to the
+ * file `path` (Alg. 1's output, which Alg. 2 reuses for every right-hand
+ * side).  Synchronises the solver's stream.  PT_EINVAL if the file cannot be
+ * written. */
+pt_status pt_save(const pt_solver* s, const char* path);
+
+/* A solver read back from a file written by pt_save, on `hip_stream` of the
+ * current device: no factorisation, extraction or compression is repeated,
+ * and pt_solve returns bit-identical results to the saved solver's.
+ * PT_EINVAL for a file that is not a saved solver of this library version
+ * (or is truncated), PT_ENOMEM if the device memory does not suffice. */
+pt_status pt_load(const char* path, void* hip_stream, pt_solver** out);
 
 const char* pt_status_str(pt_status st);
 const char* pt_last_error(void);

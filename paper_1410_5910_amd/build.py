@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpolar.so")
-SOURCES = ["kernels.hip", "solver.hip", "plr.hip", "learned.hip", "split.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "plr.hip", "learned.hip", "split.hip", "persist.hip"]
 ARCH = os.environ.get("POLAR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdio>
 #include <vector>
 
 #include "polar_kernels.h"
@@ -47,6 +48,10 @@ struct PlrSet {
   // Write block b back as a dense row-major n x n matrix (device `out`).
   hipError_t expand(int b, double2* out, hipStream_t st) const;
   size_t stored_entries(int b) const;
+  // Write the compressed blocks (leaves, tile lists, data) as records to fp /
+  // read them back into fresh device memory (false on an I/O or HIP error).
+  bool save(FILE* fp) const;
+  bool load(FILE* fp);
   const PlrBlockDev* block(int b) const { return d_blocks + b; }
   void release();
 };

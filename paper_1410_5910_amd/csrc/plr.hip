@@ -27,6 +27,7 @@
 #include <cstring>
 #include <vector>
 
+#include "persist.h"
 #include "plr.h"
 
 namespace polar {
@@ -914,6 +915,81 @@ hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t
     hipExtLaunchKernelGGL(plr_apply_kernel<4>, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(256), 0, st, ev0,
                           ev1, 0, jobs, n, ntiles, ld, bases);
   return hipGetLastError();
+}
+
+}  // namespace polar
+
+namespace polar {
+
+bool PlrSet::save(FILE* fp) const {
+  const int64_t nb = (int64_t)stored.size();
+  const int64_t ntile = (n + 63) / 64;
+  std::vector<PlrBlockDev> hb(nb);
+  if (nb && hipMemcpy(hb.data(), d_blocks, nb * sizeof(PlrBlockDev), hipMemcpyDeviceToHost) != hipSuccess)
+    return false;
+  std::vector<int64_t> offs(3 * nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    offs[3 * b] = hb[b].leaves - d_leaves;
+    offs[3 * b + 1] = hb[b].tile_ptr - d_ptr;
+    offs[3 * b + 2] = hb[b].tile_leaf - d_list;
+  }
+  const int64_t nptr = nb * (ntile + 1);
+  int64_t nlist = 0;
+  if (nb) {
+    int32_t last = 0;
+    if (hipMemcpy(&last, d_ptr + offs[3 * (nb - 1) + 1] + ntile, sizeof(int32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return false;
+    nlist = offs[3 * (nb - 1) + 2] + last;
+  }
+  const int64_t head[7] = {n, nb, ntile, (int64_t)nleaves_total, nptr, nlist, (int64_t)data_entries};
+  std::vector<uint64_t> st(stored.begin(), stored.end());
+  return rec_write_host(fp, head, 7, sizeof(int64_t)) && rec_write_host(fp, offs.data(), offs.size(), 8) &&
+         rec_write_host(fp, nleaves.data(), nb, sizeof(int)) && rec_write_host(fp, st.data(), nb, 8) &&
+         rec_write_device(fp, d_leaves, nleaves_total, sizeof(PlrLeafDev)) &&
+         rec_write_device(fp, d_ptr, nptr, sizeof(int32_t)) && rec_write_device(fp, d_list, nlist, sizeof(int32_t)) &&
+         rec_write_device(fp, d_data, data_entries, sizeof(double2));
+}
+
+bool PlrSet::load(FILE* fp) {
+  release();
+  int64_t head[7];
+  if (!rec_read_host(fp, head, 7, sizeof(int64_t))) return false;
+  const int64_t nb = head[1], ntile = head[2], nlv = head[3], nptr = head[4], nlist = head[5], nd = head[6];
+  if (nb < 0 || ntile != (head[0] + 63) / 64 || nlv < 0 || nptr != nb * (ntile + 1) || nlist < 0 || nd < 0)
+    return false;
+  n = (int)head[0];
+  std::vector<int64_t> offs(3 * nb);
+  std::vector<uint64_t> st(nb);
+  nleaves.assign(nb, 0);
+  if (!rec_read_host(fp, offs.data(), offs.size(), 8) || !rec_read_host(fp, nleaves.data(), nb, sizeof(int)) ||
+      !rec_read_host(fp, st.data(), nb, 8))
+    return false;
+  stored.assign(st.begin(), st.end());
+  nleaves_total = (size_t)nlv;
+  data_entries = (size_t)nd;
+  if (hipMalloc((void**)&d_leaves, std::max<int64_t>(1, nlv) * sizeof(PlrLeafDev)) != hipSuccess ||
+      hipMalloc((void**)&d_ptr, std::max<int64_t>(1, nptr) * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void**)&d_list, std::max<int64_t>(1, nlist) * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void**)&d_data, std::max<int64_t>(1, nd) * sizeof(double2)) != hipSuccess ||
+      hipMalloc((void**)&d_blocks, std::max<int64_t>(1, nb) * sizeof(PlrBlockDev)) != hipSuccess)
+    return false;
+  if (!rec_read_device(fp, d_leaves, nlv, sizeof(PlrLeafDev)) || !rec_read_device(fp, d_ptr, nptr, 4) ||
+      !rec_read_device(fp, d_list, nlist, 4) || !rec_read_device(fp, d_data, nd, sizeof(double2)))
+    return false;
+  std::vector<PlrBlockDev> hb(nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (offs[3 * b] < 0 || offs[3 * b] + nleaves[b] > nlv || offs[3 * b + 1] < 0 ||
+        offs[3 * b + 1] + ntile + 1 > nptr || offs[3 * b + 2] < 0 || offs[3 * b + 2] > nlist)
+      return false;
+    hb[b].nleaves = nleaves[b];
+    hb[b].ntile = (int)ntile;
+    hb[b].leaves = d_leaves + offs[3 * b];
+    hb[b].tile_ptr = d_ptr + offs[3 * b + 1];
+    hb[b].tile_leaf = d_list + offs[3 * b + 2];
+    hb[b].data = d_data;
+  }
+  return nb == 0 || hipMemcpy(d_blocks, hb.data(), nb * sizeof(PlrBlockDev), hipMemcpyHostToDevice) == hipSuccess;
 }
 
 }  // namespace polar

@@ -15,6 +15,7 @@
 #include <thread>
 #include <vector>
 
+#include "persist.h"
 #include "solver_internal.h"
 
 namespace polar_impl {
@@ -678,7 +679,7 @@ std::vector<int> green_rows(const Layer& y) {
   return g;
 }
 
-pt_status extract_blocks(pt_solver* S) {
+pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
   const int NX = S->NX, L = S->L;
   const size_t E = S->block_elems();
   hipStream_t st = S->st;
@@ -693,8 +694,34 @@ pt_status extract_blocks(pt_solver* S) {
         for (int ab = 0; ab < 4; ++ab) S->bidx[(l * 4 + t) * 4 + ab] = nb++;
   }
   S->nblk = nb;
+  if (src && src->f32) return PT_OK;  // the float32 copies are read after the other offline data
   HIPCHK(S->blk64.alloc((size_t)nb * E));
   if (L == 1) return PT_OK;
+  if (src) {
+    // blocks and (when they were kept) the interface Green's functions from the file
+    if (!rec_read_device(src->fp, S->blk64.p, (uint64_t)nb * E, sizeof(double2)))
+      return fail(PT_EINVAL, "saved solver: trace blocks");
+    S->green_off.assign((size_t)L * 4, SIZE_MAX);
+    if (!src->green) return PT_OK;
+    size_t need = 0;
+    std::vector<size_t> offs((size_t)L * 4, SIZE_MAX);
+    for (int l = 0; l < L; ++l) {
+      const size_t ng = green_rows(S->lay[l]).size();
+      for (size_t k = 0; k < ng; ++k) {
+        offs[(size_t)l * 4 + k] = need;
+        need += (size_t)NX * ((size_t)S->lay[l].n * NX);
+      }
+    }
+    if (S->green.alloc(need) != hipSuccess) {
+      S->green.release();
+      return fail(PT_ENOMEM, "interface Green's functions");
+    }
+    g_green_total += need * sizeof(double2);
+    S->green_off = offs;
+    if (!rec_read_device(src->fp, S->green.p, need, sizeof(double2)))
+      return fail(PT_EINVAL, "saved solver: interface Green's functions");
+    return PT_OK;
+  }
 
   int maxq = 0;
   int maxR = 0;
@@ -1983,12 +2010,42 @@ pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs
   th.reserve(nprob);
   for (int i = 0; i < nprob; ++i)
     th.emplace_back([&, i]() {
+      (void)hipSetDevice(s[i]->device);  // a new thread starts on device 0
       st[i] = pt_solve(s[i], nrhs[i], f[i], u[i], on_device, info ? info[i] : nullptr);
       if (st[i] != PT_OK) msg[i] = g_err;  // the message is per thread
     });
   for (auto& t : th) t.join();
   for (int i = 0; i < nprob; ++i)
     if (st[i] != PT_OK) return fail(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
+  return PT_OK;
+}
+
+pt_status pt_setup_batch(int32_t nprob, const pt_problem* probs, const pt_options* opts, void* const* hip_streams,
+                         pt_solver** out) {
+  if (nprob < 0 || (nprob > 0 && (!probs || !opts || !out))) return fail(PT_EINVAL, "null argument");
+  for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+  if (nprob == 0) return PT_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::vector<pt_status> st(nprob, PT_OK);
+  std::vector<std::string> msg(nprob);
+  std::vector<std::thread> th;
+  th.reserve(nprob);
+  for (int i = 0; i < nprob; ++i)
+    th.emplace_back([&, i]() {
+      (void)hipSetDevice(dev);  // the caller's device, not a new thread's default
+      st[i] = setup_impl(&probs[i], &opts[i], hip_streams ? hip_streams[i] : nullptr, &out[i], nullptr);
+      if (st[i] != PT_OK) msg[i] = g_err;  // the message is per thread
+    });
+  for (auto& t : th) t.join();
+  for (int i = 0; i < nprob; ++i)
+    if (st[i] != PT_OK) {
+      for (int j = 0; j < nprob; ++j) {
+        pt_free(out[j]);
+        out[j] = nullptr;
+      }
+      return fail(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
+    }
   return PT_OK;
 }
 
@@ -2121,6 +2178,13 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
 }
 
 pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stream, pt_solver** out) {
+  return setup_impl(prob, opt, hip_stream, out, nullptr);
+}
+
+}  // extern "C"
+
+pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, void* hip_stream, pt_solver** out,
+                                 const LoadSrc* src) {
   if (!out) return fail(PT_EINVAL, "null output pointer");
   *out = nullptr;
   PTCHK(validate(prob, opt));
@@ -2145,6 +2209,7 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
   }
   make_layout(S);
   const int NX = S->NX, NZ = S->NZ;
+  S->c_host.assign(prob->c, prob->c + (size_t)NX * NZ);
   const double delta = S->npml * S->h;
   const double h2w2 = S->h * S->h * S->omega * S->omega;
 
@@ -2187,15 +2252,19 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
     return s;
   };
   if (S->flag.alloc(1) != hipSuccess) return bail(fail(PT_ENOMEM, "flag"));
-  if (S->dinv64.alloc((size_t)S->sumR * S->block_elems()) != hipSuccess)
+  if (!(src && src->f32) && S->dinv64.alloc((size_t)S->sumR * S->block_elems()) != hipSuccess)
     return bail(fail(PT_ENOMEM, "local factors"));
   if (S->rowmap.alloc(S->sumR) != hipSuccess ||
       hipMemcpy(S->rowmap.p, rowmap.data(), S->sumR * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(PT_EHIP, "rowmap"));
 
-  rc = factorize(S, diag, west, east);
+  if (!src) {
+    rc = factorize(S, diag, west, east);
+  } else if (!src->f32 && !rec_read_device(src->fp, S->dinv64.p, S->dinv64.n, sizeof(double2))) {
+    rc = fail(PT_EINVAL, "saved solver: local factors");
+  }
   if (rc != PT_OK) return bail(rc);
-  rc = extract_blocks(S);
+  rc = extract_blocks(S, src);
   if (rc != PT_OK) return bail(rc);
 
   // trace gather (s = W rows) and forcing (W rows += sign * t) maps
@@ -2247,8 +2316,13 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
     int rmax = opt->plr_rmax > 0 ? opt->plr_rmax : (int)std::ceil(std::sqrt((double)NX));
     rmax = std::min(rmax, kPlrMaxRank);
     const auto tp = std::chrono::steady_clock::now();
-    const hipError_t pe = S->plr.build(S->blk64.p, S->nblk, NX, rmax, opt->plr_eps, S->st);
-    if (pe != hipSuccess) return bail(fail(pe == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP, "PLR compression"));
+    if (src) {
+      if (!src->plr || !S->plr.load(src->fp) || (int)S->plr.stored.size() != S->nblk || S->plr.n != NX)
+        return bail(fail(PT_EINVAL, "saved solver: compressed blocks"));
+    } else {
+      const hipError_t pe = S->plr.build(S->blk64.p, S->nblk, NX, rmax, opt->plr_eps, S->st);
+      if (pe != hipSuccess) return bail(fail(pe == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP, "PLR compression"));
+    }
     S->plr_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
     S->use_plr = true;
   }
@@ -2277,7 +2351,15 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
   }
 
   // reduced-precision copies of the factors and blocks
-  if (opt->precision == PT_F32) {
+  if (opt->precision == PT_F32 && src) {
+    const size_t nd = (size_t)S->sumR * S->block_elems(), nbk = (size_t)S->nblk * S->block_elems();
+    if (S->dinv32.alloc(nd) != hipSuccess || S->blk32.alloc(nbk) != hipSuccess)
+      return bail(fail(PT_ENOMEM, "float32 copies"));
+    if (!rec_read_device(src->fp, S->dinv32.p, nd, sizeof(float2)) ||
+        !rec_read_device(src->fp, S->blk32.p, nbk, sizeof(float2)))
+      return bail(fail(PT_EINVAL, "saved solver: float32 factors and blocks"));
+    S->f32 = true;
+  } else if (opt->precision == PT_F32) {
     if (S->dinv32.alloc(S->dinv64.n) != hipSuccess || S->blk32.alloc(S->blk64.n) != hipSuccess)
       return bail(fail(PT_ENOMEM, "float32 copies"));
     if (launch_to_f32(S->dinv32.p, S->dinv64.p, (int64_t)S->dinv64.n, S->st) != hipSuccess ||
@@ -2302,6 +2384,8 @@ pt_status pt_setup(const pt_problem* prob, const pt_options* opt, void* hip_stre
   return PT_OK;
 }
 
+extern "C" {
+
 pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   if (!S || !o) return fail(PT_EINVAL, "null argument");
   std::memset(o, 0, sizeof(*o));
@@ -2325,6 +2409,8 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   o->plr_leaves = S->use_plr ? (int64_t)S->plr.nleaves_total : 0;
   o->green_bytes = S->green.p ? (int64_t)(S->green.n * sizeof(double2)) : 0;
   o->factor_bytes = (int64_t)S->sumR * S->block_elems() * es;
+  o->max_nrhs = S->opt.max_nrhs;
+  o->precision = S->opt.precision;
   return PT_OK;
 }
 

@@ -132,6 +132,7 @@ struct pt_solver {
 
   // coefficients
   std::vector<cd> lcoef, ucoef;  // z couplings of each local row (sumR)
+  std::vector<double> c_host;    // the velocity on the padded grid (kept for pt_save)
 
   // device data
   PlrSet plr;
@@ -247,6 +248,18 @@ struct pt_solver {
 
 
 namespace polar_impl {
+
+// A saved solver being read back (pt_load): setup takes the factors, blocks,
+// Green's functions and compressed blocks from fp, in the order it needs them,
+// instead of computing them.
+struct LoadSrc {
+  FILE* fp = nullptr;
+  bool f32 = false;    // float32 factors and blocks stored (no float64 copies)
+  bool green = false;  // interface Green's functions stored
+  bool plr = false;    // compressed blocks stored
+};
+pt_status setup_impl(const pt_problem* prob, const pt_options* opt, void* hip_stream, pt_solver** out,
+                     const LoadSrc* src);
 
 // stages of the online path (solver.hip)
 pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs);

@@ -35,7 +35,8 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
-           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel", "pt_apply_noalloc")
+           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel", "pt_apply_noalloc",
+           "pt_setup_batch", "pt_save", "pt_load")
 CLASSES = ("local", "sweep", "reflect", "operator", "presolve")
 
 
@@ -60,7 +61,8 @@ class PtLayout(C.Structure):
                 ("R", C.c_int32 * 64), ("own_start", C.c_int32 * 64), ("n_own", C.c_int32 * 64),
                 ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
                 ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64), ("dense_block_bytes", C.c_int64),
-                ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64), ("plr_ms", C.c_double)]
+                ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64), ("plr_ms", C.c_double),
+                ("max_nrhs", C.c_int32), ("precision", C.c_int32)]
 
 
 class PtKernelStats(C.Structure):
@@ -98,6 +100,9 @@ def lib():
         vp, i32, dp = C.c_void_p, C.c_int32, C.POINTER(C.c_double)
         L.pt_setup.argtypes = [C.POINTER(PtProblem), C.POINTER(PtOptions), vp, C.POINTER(vp)]
         L.pt_solve.argtypes = [vp, i32, vp, vp, i32, C.POINTER(PtRhsInfo)]
+        L.pt_setup_batch.argtypes = [i32, C.POINTER(PtProblem), C.POINTER(PtOptions), C.POINTER(vp), C.POINTER(vp)]
+        L.pt_save.argtypes = [vp, C.c_char_p]
+        L.pt_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
         L.pt_free.argtypes = [vp]
         L.pt_free.restype = None
         L.pt_status_str.argtypes = [i32]
@@ -153,6 +158,27 @@ def _is_torch(a) -> bool:
     return type(a).__module__.startswith("torch")
 
 
+def _problem_options(nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs_iters=2, tol=1e-10, maxit=50,
+                     max_nrhs=1, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False, presolve="auto",
+                     closure="jump"):
+    """(PtProblem, PtOptions, the contiguous velocity the problem points at)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    NX, NZ = nx + 2 * npml, nz + 2 * npml
+    if c.size != NX * NZ:
+        raise ValueError(f"c must have (nz+2npml)*(nx+2npml) = {NZ * NX} values")
+    prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
+                     c.ctypes.data_as(C.POINTER(C.c_double)))
+    prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
+    if presolve not in ("local", "green", "auto"):
+        raise ValueError(f"presolve must be 'local', 'green' or 'auto', not {presolve!r}")
+    if closure not in ("jump", "extrap"):
+        raise ValueError(f"closure must be 'jump' or 'extrap', not {closure!r}")
+    opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
+                    float(plr_eps), int(plr_rmax), 1 if use_graph else 0, {"local": 0, "green": 1, "auto": 2}[presolve],
+                    {"jump": 0, "extrap": 1}[closure])
+    return prob, opt, c
+
+
 class Solver:
     """Offline setup on construction (Alg. 1), online solves with solve() (Alg. 2)."""
 
@@ -160,31 +186,37 @@ class Solver:
                  max_nrhs=1, stream=None, plr=False, plr_eps=1e-9, plr_rmax=0, use_graph=False, presolve="auto",
                  closure="jump"):
         self._lib = lib()
-        c = np.ascontiguousarray(c, dtype=np.float64)
-        NX, NZ = nx + 2 * npml, nz + 2 * npml
-        if c.size != NX * NZ:
-            raise ValueError(f"c must have (nz+2npml)*(nx+2npml) = {NZ * NX} values")
-        self._c = c
-        prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
-                         c.ctypes.data_as(C.POINTER(C.c_double)))
-        prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
-        if presolve not in ("local", "green", "auto"):
-            raise ValueError(f"presolve must be 'local', 'green' or 'auto', not {presolve!r}")
-        pre = {"local": 0, "green": 1, "auto": 2}[presolve]
-        if closure not in ("jump", "extrap"):
-            raise ValueError(f"closure must be 'jump' or 'extrap', not {closure!r}")
-        opt = PtOptions(prec, int(gs_iters), float(tol), int(maxit), int(max_nrhs), 1 if plr else 0,
-                        float(plr_eps), int(plr_rmax), 1 if use_graph else 0, pre,
-                        {"jump": 0, "extrap": 1}[closure])
+        prob, opt, self._c = _problem_options(nx, nz, npml, h, omega, C_pml, L, c, precision=precision,
+                                              gs_iters=gs_iters, tol=tol, maxit=maxit, max_nrhs=max_nrhs, plr=plr,
+                                              plr_eps=plr_eps, plr_rmax=plr_rmax, use_graph=use_graph,
+                                              presolve=presolve, closure=closure)
         h_ = C.c_void_p()
         _check(self._lib.pt_setup(C.byref(prob), C.byref(opt), C.c_void_p(stream or 0), C.byref(h_)))
-        self._h = h_
+        self._adopt(h_, stream)
+
+    def _adopt(self, handle, stream):
+        """Take ownership of a set-up solver handle."""
+        self._lib = lib()
+        self._h = handle
         self._stream = int(stream or 0)
-        self.NX, self.NZ, self.L = NX, NZ, int(L)
-        self.max_nrhs = int(max_nrhs)
         lay = self.layout()
+        self.NX, self.NZ, self.L = lay["NX"], lay["NZ"], lay["L"]
+        self.max_nrhs = lay["max_nrhs"]
         self.sumR = lay["sumR"]
         self.ntrace = lay["ntrace"]
+
+    @classmethod
+    def load(cls, path: str, stream=None) -> "Solver":
+        """A solver read back from a file written by save() (no factorisation, extraction or compression)."""
+        h_ = C.c_void_p()
+        _check(lib().pt_load(os.fsencode(path), C.c_void_p(stream or 0), C.byref(h_)))
+        self = cls.__new__(cls)
+        self._adopt(h_, stream)
+        return self
+
+    def save(self, path: str):
+        """Write the offline state (factors, blocks, Green's functions, compressed blocks, tuned shapes)."""
+        _check(self._lib.pt_save(self._h, os.fsencode(path)))
 
     @classmethod
     def from_problem(cls, prob, **kw):
@@ -212,7 +244,7 @@ class Solver:
                 "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
                 "factor_bytes": o.factor_bytes, "dense_block_bytes": o.dense_block_bytes,
                 "plr_leaves": o.plr_leaves, "green_bytes": o.green_bytes,
-                "plr_ms": o.plr_ms}
+                "plr_ms": o.plr_ms, "max_nrhs": o.max_nrhs, "precision": o.precision}
 
     def profile(self, enable: bool):
         """Start (reset) / stop recording HIP events around every block-apply launch."""
@@ -483,3 +515,26 @@ def solve_batch(solvers, fs):
     return [(u, [{"iters": i.iters, "converged": bool(i.converged), "est": i.est, "relres": i.relres,
                   "learned": bool(i.learned), "learned_steps": i.learned_steps} for i in inf])
             for u, inf in zip(outs, infos)]
+
+
+def setup_batch(probs, streams=None, **kw):
+    """Set up several problems at once (pt_setup_batch): one host thread per problem, each on its stream
+    (streams[i], or the null stream), so their factorisations overlap on the GPU.  probs: objects with nx, nz,
+    npml, h, omega, C, L, c; kw: the Solver options, shared by all (max_nrhs may be a list).  -> [Solver]"""
+    n = len(probs)
+    mx = kw.pop("max_nrhs", 1)
+    mx = list(mx) if isinstance(mx, (list, tuple)) else [mx] * n
+    made = [_problem_options(p.nx, p.nz, p.npml, p.h, p.omega, p.C, p.L, p.c, max_nrhs=m, **kw)
+            for p, m in zip(probs, mx)]
+    pa = (PtProblem * n)(*[m[0] for m in made])
+    oa = (PtOptions * n)(*[m[1] for m in made])
+    sa = (C.c_void_p * n)(*[int(s or 0) for s in (streams or [0] * n)])
+    out = (C.c_void_p * n)()
+    _check(lib().pt_setup_batch(n, pa, oa, sa, out))
+    res = []
+    for i in range(n):
+        sv = Solver.__new__(Solver)
+        sv._c = made[i][2]
+        sv._adopt(C.c_void_p(out[i]), streams[i] if streams else None)
+        res.append(sv)
+    return res

@@ -77,3 +77,17 @@ def test_invalid_options_rejected(opt, msg):
     with pytest.raises(P.PolarError) as e:
         P.Solver(prob.nx, prob.nz, prob.npml, prob.h, prob.omega, prob.C, prob.L, prob.c, **opt)
     assert e.value.status == 1 and msg in str(e.value)
+
+
+def test_load_rejects_non_solver_files_without_a_gpu(tmp_path):
+    # pt_load checks the file's magic before any device call
+    P = pytest.importorskip("paper_1410_5910_amd")
+    L = P.lib()
+    import ctypes as C
+    bad = tmp_path / "x.pts"
+    bad.write_bytes(b"definitely not a saved solver")
+    out = C.c_void_p()
+    assert L.pt_load(str(bad).encode(), None, C.byref(out)) == P.polar.PT_EINVAL
+    assert out.value is None
+    assert L.pt_load(str(tmp_path / "missing").encode(), None, C.byref(out)) == P.polar.PT_EINVAL
+    assert L.pt_setup_batch(0, None, None, None, None) == P.polar.PT_OK
