@@ -70,13 +70,22 @@ typedef enum {
   PT_F32 = 1,        /* Green's blocks and local factors stored and applied in
                         complex float32 (FP32 accumulation); Krylov vectors,
                         Arnoldi, least squares and true residuals stay float64 */
-  PT_SPLIT_BF16 = 2  /* mixed: the Gauss-Seidel preconditioner (sweeps and
+  PT_SPLIT_BF16 = 2, /* mixed: the Gauss-Seidel preconditioner (sweeps and
                         reflection terms) applies the trace blocks as split
                         bfloat16 pairs (hi + lo) on MFMA with float32
                         accumulation; local solves, the operator A inside GMRES
                         and everything else stay float64, so flexible GMRES
                         converges to the float64 solution (both block copies
                         are kept: 1.5x the float64 block memory)            */
+  PT_SPLIT_F16 = 3   /* mixed, as PT_SPLIT_BF16 but with float16 pairs on the
+                        float16 MFMA (about 22 significant bits per pair
+                        instead of 16).  float16 has a 5-bit exponent: every
+                        split matrix is stored times one power of two chosen at
+                        setup (the largest Frobenius norm of a trace block maps
+                        to 2^14) and the inputs are split at 2^12 times their
+                        value, sized for unit-norm inputs (GMRES's Krylov
+                        vectors; pt_apply and pt_gauss_seidel scale their
+                        inputs to unit norm per source and back)             */
 } pt_precision;
 
 /* One Helmholtz problem (paper Section 2.1; Alg. 1 inputs m, omega). */

@@ -1169,6 +1169,14 @@ __global__ void kscale_kernel(double2* v, const double2* w, const double* nrm, i
   }
 }
 
+__global__ void kmulnorm_kernel(double2* v, const double* nrm, int nrhs, int64_t N) {
+  const int64_t total = (int64_t)nrhs * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const double s = nrm[(int)(e / N)];
+    v[e] = make_double2(v[e].x * s, v[e].y * s);
+  }
+}
+
 __global__ void givens_kernel(double2* Hc, const double2* hacc, const double* nrm, double* cs, double2* sn,
                               double2* g, double* est, const double* beta, int32_t* iters, int32_t* done,
                               double tol, int j, int mdim, int nrhs) {
@@ -1457,6 +1465,10 @@ hipError_t launch_knorm(const double2* w, double* nrm, int nrhs, int64_t N, hipS
 }
 hipError_t launch_kscale(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N, hipStream_t st) {
   hipLaunchKernelGGL(kscale_kernel, dim3(grid_for((int64_t)nrhs * N)), dim3(kThreads), 0, st, v, w, nrm, nrhs, N);
+  return hipGetLastError();
+}
+hipError_t launch_kmulnorm(double2* v, const double* nrm, int nrhs, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(kmulnorm_kernel, dim3(grid_for((int64_t)nrhs * N)), dim3(kThreads), 0, st, v, nrm, nrhs, N);
   return hipGetLastError();
 }
 hipError_t launch_givens(double2* Hc, const double2* hacc, const double* nrm, double* cs, double2* sn, double2* g,

@@ -67,6 +67,7 @@ struct SplitCfg {
   int kslices;     // k-slices per tile
   int stream = 0;  // > 16 right-hand sides, every job two terms with Q: the branch-free
                    // two-chunks-in-flight form, 1 without S terms, 2 with (0: general form)
+  int f16 = 0;     // planes and MFMA in float16 (1) or bfloat16 (0)
 };
 
 // ---------------------------------------------------------------- block apply
@@ -115,8 +116,12 @@ hipError_t launch_rec_rhs(double2* T, const double2* f, const double2* x, const 
 int split_kslices(int njobs, int n, int nrhs, int tile_rhs = 0);
 // bfloat16 elements of the split planes of one n x n block
 size_t split_block_elems(int n);
-// nblk row-major complex float64 n x n blocks -> their split planes (dst: nblk * split_block_elems(n))
-hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, hipStream_t st);
+// nblk row-major complex float64 n x n blocks -> their split planes (dst: nblk * split_block_elems(n)
+// 16-bit elements): bfloat16 (f16 = 0), or float16 of the entries times `scale` (a power of two)
+hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, hipStream_t st, int f16 = 0,
+                               double scale = 1.0);
+// the factor the float16 form multiplies its inputs by as it splits them (1 for bfloat16)
+double split_input_scale(int f16);
 
 // ---------------------------------------------------------- setup kernels
 // Per-layer Gauss-Jordan inversion with partial pivoting of nb dense n x n
@@ -199,6 +204,8 @@ hipError_t launch_kupdate(const double2* V, double2* w, const double2* h, double
                           int64_t N, hipStream_t st);
 // nrm[r] = ||w[r]||_2
 hipError_t launch_knorm(const double2* w, double* nrm, int nrhs, int64_t N, hipStream_t st);
+// v[r] *= nrm[r] for each of the nrhs vectors of length N
+hipError_t launch_kmulnorm(double2* v, const double* nrm, int nrhs, int64_t N, hipStream_t st);
 // v[r] = w[r] / nrm[r] (zero if nrm == 0)
 hipError_t launch_kscale(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N,
                          hipStream_t st);

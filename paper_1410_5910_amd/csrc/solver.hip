@@ -139,6 +139,7 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
   else if (Lc.split) {
     SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
     if (sc.stream && sc.stream != Lc.two_term) sc.stream = 0;  // the form only serves launches it fits
+    sc.f16 = S->split_f16 ? 1 : 0;
     const size_t need = split_part_need(S, Lc, nrhs, tc);
     float2* part = need <= S->part.n ? S->part.p : nullptr;  // null: no k-slices
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
@@ -215,7 +216,8 @@ pt_status validate(const pt_problem* p, const pt_options* o) {
   const size_t N = (size_t)(p->nx + 2 * p->npml) * (p->nz + 2 * p->npml);
   for (size_t e = 0; e < N; ++e)
     if (!(p->c[e] > 0) || !std::isfinite(p->c[e])) return fail(PT_EINVAL, "velocity must be positive and finite");
-  if (o->precision != PT_F64 && o->precision != PT_F32 && o->precision != PT_SPLIT_BF16)
+  if (o->precision != PT_F64 && o->precision != PT_F32 && o->precision != PT_SPLIT_BF16 &&
+      o->precision != PT_SPLIT_F16)
     return fail(PT_EINVAL, "unknown precision");
   if (o->gs_iters < 0 || o->gs_iters > 8) return fail(PT_EINVAL, "gs_iters must be in 0..8");
   if (o->maxit < 1 || o->maxit > 200) return fail(PT_EINVAL, "maxit must be in 1..200");
@@ -1956,6 +1958,11 @@ pt_status pt_gauss_seidel(pt_solver* S, int32_t nrhs, const double* f, double* u
     ud = S->uio.p;
   }
   PTCHK(trace_rhs(S, fd, S->s.p, nrhs));
+  // float16 split planes: iterate on s scaled to unit norm per source (the inputs' range), scale back at the end
+  if (S->split_f16) {
+    HIPCHK(launch_knorm(S->s.p, S->est.p, nrhs, S->Nt, st));
+    HIPCHK(launch_kscale(S->s.p, S->s.p, S->est.p, nrhs, S->Nt, st));
+  }
   // u^{i+1} = D^-1 (s - R u^i): one fused reflection launch (none for u^0 = 0) and the sweeps
   double2* prev = S->zeros.p;
   std::vector<double> num(nrhs), den(nrhs);
@@ -1990,6 +1997,7 @@ pt_status pt_gauss_seidel(pt_solver* S, int32_t nrhs, const double* f, double* u
     }
   }
   if (iters) *iters = std::min(it, maxit);
+  if (S->split_f16) HIPCHK(launch_kmulnorm(const_cast<double2*>(prev), S->est.p, nrhs, S->Nt, st));
   PTCHK(reconstruct(S, fd, prev, ud, nrhs));
   if (!on_device) HIPCHK(hipMemcpyAsync(u, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -2327,25 +2335,49 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
     S->use_plr = true;
   }
 
-  // split-bfloat16 planes of the blocks for the preconditioner of the mixed form
-  if (opt->precision == PT_SPLIT_BF16 && S->L >= 2) {
-    if (S->blkbf.alloc((size_t)S->nblk * split_block_elems(NX)) != hipSuccess)
-      return bail(fail(PT_ENOMEM, "split-bfloat16 blocks"));
-    if (launch_split_planes(S->blk64.p, S->blkbf.p, S->nblk, NX, S->st) != hipSuccess ||
-        hipStreamSynchronize(S->st) != hipSuccess)
-      return bail(fail(PT_EHIP, "split-bfloat16 conversion"));
-    S->split = true;
-    // the one-sided extrapolators of the extrapolation closure's D^-1 (T step), likewise
-    if (opt->closure == 1) {
-      const size_t E = split_block_elems(NX);
-      if (S->xbf.alloc((size_t)2 * (S->L - 1) * E) != hipSuccess) return bail(fail(PT_ENOMEM, "split extrapolators"));
+  // split planes (bfloat16 or float16) of the blocks for the preconditioner of the mixed forms
+  if ((opt->precision == PT_SPLIT_BF16 || opt->precision == PT_SPLIT_F16) && S->L >= 2) {
+    const bool f16 = opt->precision == PT_SPLIT_F16;
+    const size_t E = split_block_elems(NX);
+    // the one-sided extrapolators of the extrapolation closure's D^-1 (T step) are split likewise
+    std::vector<const double2*> xsrc;
+    if (opt->closure == 1)
       for (int k = 0; k + 1 < S->L; ++k) {
-        const double2* sg = S->dinv64.p + (size_t)(S->lay[k].rowbase + S->lay[k].rn1) * S->block_elems();
-        const double2* dl = S->dinv64.p + (size_t)(S->lay[k + 1].rowbase + S->lay[k + 1].r0) * S->block_elems();
-        if (launch_split_planes(sg, S->xbf.p + (size_t)(2 * k) * E, 1, NX, S->st) != hipSuccess ||
-            launch_split_planes(dl, S->xbf.p + (size_t)(2 * k + 1) * E, 1, NX, S->st) != hipSuccess)
-          return bail(fail(PT_EHIP, "split extrapolators"));
+        xsrc.push_back(S->dinv64.p + (size_t)(S->lay[k].rowbase + S->lay[k].rn1) * S->block_elems());
+        xsrc.push_back(S->dinv64.p + (size_t)(S->lay[k + 1].rowbase + S->lay[k + 1].r0) * S->block_elems());
       }
+    double scale = 1.0;
+    if (f16) {
+      // one power of two for every split matrix: the largest Frobenius norm maps to at most 2^14, so no
+      // entry exceeds float16's range (65504) and entries down to 2^-17 of it keep every bit of the pair
+      DevBuf<double> nb;
+      const size_t cnt = (size_t)S->nblk + xsrc.size();
+      std::vector<double> hn(cnt, 0.0);
+      bool ok = nb.alloc(cnt) == hipSuccess &&
+                launch_knorm(S->blk64.p, nb.p, S->nblk, (int64_t)NX * NX, S->st) == hipSuccess;
+      for (size_t i = 0; ok && i < xsrc.size(); ++i)
+        ok = launch_knorm(xsrc[i], nb.p + S->nblk + i, 1, (int64_t)NX * NX, S->st) == hipSuccess;
+      ok = ok && hipMemcpyAsync(hn.data(), nb.p, cnt * sizeof(double), hipMemcpyDeviceToHost, S->st) == hipSuccess &&
+           hipStreamSynchronize(S->st) == hipSuccess;
+      nb.release();
+      if (!ok) return bail(fail(PT_EHIP, "split-float16 scale"));
+      double mx = 0.0;
+      for (double v : hn) mx = std::max(mx, v);
+      if (!std::isfinite(mx)) return bail(fail(PT_ESINGULAR, "trace blocks are not finite"));
+      if (mx > 0.0) scale = std::ldexp(1.0, 14 - (int)std::ceil(std::log2(mx)));
+    }
+    S->split_f16 = f16;
+    S->split_alpha = 1.0 / (scale * split_input_scale(f16 ? 1 : 0));
+    if (S->blkbf.alloc((size_t)S->nblk * E) != hipSuccess) return bail(fail(PT_ENOMEM, "split blocks"));
+    if (launch_split_planes(S->blk64.p, S->blkbf.p, S->nblk, NX, S->st, f16 ? 1 : 0, scale) != hipSuccess ||
+        hipStreamSynchronize(S->st) != hipSuccess)
+      return bail(fail(PT_EHIP, "split conversion"));
+    S->split = true;
+    if (!xsrc.empty()) {
+      if (S->xbf.alloc(xsrc.size() * E) != hipSuccess) return bail(fail(PT_ENOMEM, "split extrapolators"));
+      for (size_t i = 0; i < xsrc.size(); ++i)
+        if (launch_split_planes(xsrc[i], S->xbf.p + i * E, 1, NX, S->st, f16 ? 1 : 0, scale) != hipSuccess)
+          return bail(fail(PT_EHIP, "split extrapolators"));
       if (hipStreamSynchronize(S->st) != hipSuccess) return bail(fail(PT_EHIP, "split extrapolators"));
     }
   }
@@ -2372,6 +2404,19 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
   }
 
   build_online_jobs(S);
+  if (S->split_f16) {
+    // the float16 planes hold scale x the blocks and the inputs are split at 2^12 x their value:
+    // the jobs of every split launch multiply their sums back (a power of two: exact)
+    std::vector<const Launch*> ls{&S->bterm, &S->opA, &S->opA2, &S->opR, &S->opX, &S->opX2, &S->opRX,
+                                  &S->gsRX, &S->tX};
+    for (const Launch& Lc : S->sweep) ls.push_back(&Lc);
+    for (const Launch* Lc : ls)
+      if (Lc->split)
+        for (int j = Lc->job0; j < Lc->job0 + Lc->njobs; ++j) {
+          S->hjobs[j].alpha.x *= S->split_alpha;
+          S->hjobs[j].alpha.y *= S->split_alpha;
+        }
+  }
   S->jobs.release();
   if (S->jobs.alloc(S->hjobs.size()) != hipSuccess ||
       hipMemcpy(S->jobs.p, S->hjobs.data(), S->hjobs.size() * sizeof(Job), hipMemcpyHostToDevice) != hipSuccess)
@@ -2499,19 +2544,41 @@ pt_status pt_get_plr_block(const pt_solver* S, int32_t layer, int32_t j, int32_t
 
 namespace polar_impl {
 
-// y = op(x) on device vectors (both pt_apply and pt_apply_noalloc)
+// y = op(x) on device vectors (both pt_apply and pt_apply_noalloc).  With
+// float16 split planes, the operators that run split launches (D^-1 and the
+// preconditioner) see their input scaled to unit norm per source, the range
+// the float16 inputs are sized for (the Krylov vectors GMRES feeds them), and
+// the output is scaled back: the operators are linear.
 pt_status apply_dispatch(pt_solver* S, int32_t op, const double2* xd, double2* yd, int nrhs) {
   const size_t n = (size_t)nrhs * S->Nt;
+  const bool unit = S->split_f16 &&
+                    (op == PT_OP_DINV || op == PT_OP_PRECOND || op == PT_OP_DINV_EXTRAP || op == PT_OP_PRECOND_EXTRAP);
+  // the input staged in s (unit norm per source when `unit`)
+  auto stage = [&](double2* dst) -> pt_status {
+    if (unit) {
+      HIPCHK(launch_knorm(xd, S->nrm.p, nrhs, S->Nt, S->st));
+      HIPCHK(launch_kscale(dst, xd, S->nrm.p, nrhs, S->Nt, S->st));
+    } else {
+      HIPCHK(hipMemcpyAsync(dst, xd, n * sizeof(double2), hipMemcpyDeviceToDevice, S->st));
+    }
+    return PT_OK;
+  };
   switch (op) {
     case PT_OP_A: PTCHK(apply_op(S, S->opA, xd, yd, nrhs)); break;
     case PT_OP_R: PTCHK(apply_op(S, S->opR, xd, yd, nrhs)); break;
-    case PT_OP_DINV: PTCHK(apply_dinv(S, xd, yd, nrhs)); break;
-    case PT_OP_PRECOND: {
+    case PT_OP_DINV:
+      if (unit) {
+        PTCHK(stage(S->s.p));
+        PTCHK(apply_dinv(S, S->s.p, yd, nrhs));
+      } else {
+        PTCHK(apply_dinv(S, xd, yd, nrhs));
+      }
+      break;
+    case PT_OP_PRECOND:
       // the preconditioner uses U1/U2 internally: stage the input in s
-      HIPCHK(hipMemcpyAsync(S->s.p, xd, n * sizeof(double2), hipMemcpyDeviceToDevice, S->st));
+      PTCHK(stage(S->s.p));
       PTCHK(precondition(S, S->s.p, yd, nrhs));
       break;
-    }
     case PT_OP_A_EXTRAP:
     case PT_OP_R_EXTRAP:
     case PT_OP_DINV_EXTRAP:
@@ -2523,15 +2590,20 @@ pt_status apply_dispatch(pt_solver* S, int32_t op, const double2* xd, double2* y
         HIPCHK(launch_zero(yd, (int64_t)n, S->st));  // its extrapolation rows are zero
         PTCHK(apply_op(S, S->opRX, xd, yd, nrhs));
       } else if (op == PT_OP_DINV_EXTRAP) {
-        HIPCHK(launch_copy(yd, xd, (int64_t)n, S->st));
+        if (unit) {
+          PTCHK(stage(yd));
+        } else {
+          HIPCHK(launch_copy(yd, xd, (int64_t)n, S->st));
+        }
         PTCHK(dinv_extrap_inplace(S, yd, nrhs));
       } else {
-        HIPCHK(hipMemcpyAsync(S->s.p, xd, n * sizeof(double2), hipMemcpyDeviceToDevice, S->st));
+        PTCHK(stage(S->s.p));
         PTCHK(precondition_extrap(S, S->s.p, yd, nrhs));
       }
       break;
     default: return fail(PT_EINVAL, "unknown operator");
   }
+  if (unit) HIPCHK(launch_kmulnorm(yd, S->nrm.p, nrhs, S->Nt, S->st));
   return PT_OK;
 }
 

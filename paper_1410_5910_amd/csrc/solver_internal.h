@@ -71,7 +71,7 @@ struct Launch {
   int job0 = 0, njobs = 0, maxterms = 0;
   int cls = PT_CLS_LOCAL;    // pt_launch_class
   bool plr = false;          // job terms point at compressed blocks
-  bool split = false;        // job terms point at split-bfloat16 planes
+  bool split = false;        // job terms point at split planes
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
   std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
@@ -141,6 +141,8 @@ struct pt_solver {
   DevBuf<float2> dinv32, blk32;
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
   bool split = false;
+  bool split_f16 = false;    // the split planes are float16 (PT_SPLIT_F16), else bfloat16
+  double split_alpha = 1.0;  // factor folded into the jobs of split launches (float16: 1 / both scales)
   DevBuf<float2> part;     // k-slice partial tiles of small split launches
   // interface Green's functions of the pre-solve: per layer, rows 1 and n of
   // (A^l)^-1 over the owned rows, NX x (n NX) each (null: line-by-line)

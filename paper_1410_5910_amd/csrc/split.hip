@@ -1,8 +1,11 @@
-// Split-bfloat16 block apply on MFMA (gfx950): Y = P + alpha sum_t M_t (Q_t + beta_t S_t)
-// with every complex block M_t held as four bfloat16 planes, M = (Mr_hi + Mr_lo) + i (Mi_hi + Mi_lo),
-// and the float64 input X = Q + beta S split the same way when it is staged.  Each real
-// product is formed as hi*hi + hi*lo + lo*hi with float32 accumulation (the lo*lo term,
-// 2^-16 below the result, is dropped), about 16 significant bits, which is what a
+// Split block apply on MFMA (gfx950): Y = P + alpha sum_t M_t (Q_t + beta_t S_t) with every
+// complex block M_t held as four 16-bit planes, M = (Mr_hi + Mr_lo) + i (Mi_hi + Mi_lo), and the
+// float64 input X = Q + beta S split the same way when it is staged.  Each real product is
+// formed as hi*hi + hi*lo + lo*hi with float32 accumulation (the lo*lo term is dropped).
+// Two element types: bfloat16 (about 16 significant bits per pair; float32's exponent range,
+// no scaling) and float16 (about 22 significant bits; a 5-bit exponent, so the blocks are
+// stored scaled by a power of two chosen at setup, the inputs are multiplied by 2^12 as they
+// are split, and both factors are folded into the jobs' alpha).  Either is what a
 // preconditioner needs: flexible GMRES restores full accuracy from float64 operators.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -15,17 +18,51 @@ namespace polar {
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSpK = 32;  // block columns (k) per chunk: the MFMA depth of v_mfma_f32_16x16x32_bf16
+// The element type of the split planes and the MFMA that consumes them.
+struct SpBf16 {
+  typedef __bf16 E;
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+  static constexpr double kX = 1.0;  // input scale at the split
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  // hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
+  static __device__ __forceinline__ void split(double x, E& hi, E& lo) {
+    hi = static_cast<__bf16>(static_cast<float>(x));
+    lo = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
+  }
+};
+struct SpF16 {
+  typedef _Float16 E;
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+  static constexpr double kX = 4096.0;
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void split(double x, E& hi, E& lo) {
+    hi = static_cast<_Float16>(static_cast<float>(x));
+    lo = static_cast<_Float16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
+  }
+};
+
+// a 16-byte vector at element i of a global array (a global_load, not a flat_load)
+template <typename V>
+__device__ __forceinline__ V gload(const void* p, int64_t i) {
+  typedef __attribute__((address_space(1))) const V gv;
+  return reinterpret_cast<const gv*>(reinterpret_cast<uintptr_t>(p))[i];
+}
+
+constexpr int kSpK = 32;  // block columns (k) per chunk: the MFMA depth of v_mfma_f32_16x16x32_{bf16,f16}
 
 __device__ __forceinline__ double2* sp_base(const Bases& b, int buf) {
   return buf == 0 ? b.b[0] : buf == 1 ? b.b[1] : buf == 2 ? b.b[2] : buf == 3 ? b.b[3] : nullptr;
 }
 
-// global-memory views: loads through them compile to global_load, not flat_load
-typedef __attribute__((address_space(1))) const bf16x8 gbf16x8;
+// global-memory views of the float64 inputs
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const d2v gdouble2;
 __device__ __forceinline__ const gdouble2* to_global(const double2* p) {
@@ -52,12 +89,6 @@ __device__ __forceinline__ int xcd_logical(int i, int G) {
 // across it (a full __syncthreads() also drains the vector-memory counter).
 __device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
-__device__ __forceinline__ void split2(double x, __bf16& hi, __bf16& lo) {
-  hi = static_cast<__bf16>(static_cast<float>(x));
-  lo = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
-}
-
 // ----------------------------------------------------------------------------
 // setup: float64 row-major blocks -> swizzled split planes
 // ----------------------------------------------------------------------------
@@ -65,38 +96,41 @@ __device__ __forceinline__ void split2(double x, __bf16& hi, __bf16& lo) {
 // 32 kt .. 32 kt + 31; it stores 4 planes (re hi, re lo, im hi, im lo) of 64
 // lanes x 8 values: lane l holds row 16 rt + l % 16, columns 32 kt + 8 (l / 16)
 // + 0..7, exactly the A operand of the MFMA, so a wave reads each plane of a
-// tile as one contiguous KiB.  Entries beyond n are zero.
-__global__ void split_planes_kernel(const double2* __restrict__ src, __bf16* __restrict__ dst, int n, int nrt16,
-                                    int nkt) {
+// tile as one contiguous KiB.  Entries beyond n are zero; entries are
+// multiplied by `scale` (a power of two: exact) before the split.
+template <typename T>
+__global__ void split_planes_kernel(const double2* __restrict__ src, typename T::E* __restrict__ dst, int n,
+                                    int nrt16, int nkt, double scale) {
+  typedef typename T::v8 v8;
   const int b = blockIdx.y;
   const int64_t tiles = (int64_t)nrt16 * nkt;
   const int64_t lanes = tiles * 64;
   const double2* M = src + (size_t)b * n * n;
-  __bf16* D = dst + (size_t)b * tiles * 4 * 512;
+  typename T::E* D = dst + (size_t)b * tiles * 4 * 512;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < lanes; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t tile = e >> 6;
     const int l = (int)(e & 63);
     const int rt = (int)(tile / nkt), kt = (int)(tile % nkt);
     const int row = rt * 16 + (l & 15);
     const int k0 = kt * kSpK + 8 * (l >> 4);
-    bf16x8 rh, rl, ih, il;
+    v8 rh, rl, ih, il;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u;
       const double2 v = (row < n && k < n) ? M[(size_t)row * n + k] : make_double2(0.0, 0.0);
-      __bf16 h, lo;
-      split2(v.x, h, lo);
+      typename T::E h, lo;
+      T::split(v.x * scale, h, lo);
       rh[u] = h;
       rl[u] = lo;
-      split2(v.y, h, lo);
+      T::split(v.y * scale, h, lo);
       ih[u] = h;
       il[u] = lo;
     }
-    bf16x8* T = reinterpret_cast<bf16x8*>(D + tile * 4 * 512);
-    T[0 * 64 + l] = rh;
-    T[1 * 64 + l] = rl;
-    T[2 * 64 + l] = ih;
-    T[3 * 64 + l] = il;
+    v8* P = reinterpret_cast<v8*>(D + tile * 4 * 512);
+    P[0 * 64 + l] = rh;
+    P[1 * 64 + l] = rl;
+    P[2 * 64 + l] = ih;
+    P[3 * 64 + l] = il;
   }
 }
 
@@ -115,9 +149,10 @@ __global__ void split_planes_kernel(const double2* __restrict__ src, __bf16* __r
 // MFMAs each per chunk, are interleaved so consecutive MFMAs are independent.
 // The KS partial tiles are summed through LDS in a fixed order by wave 0: no
 // atomics, deterministic results.
-template <int NB, int KS>
+template <typename T, int NB, int KS>
 __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restrict__ jobs, int n, int nrt16,
                                                               int nct, int nrhs, int64_t ld, Bases bases) {
+  typedef typename T::v8 bf16x8;
   __shared__ f32x4 red[KS > 1 ? KS - 1 : 1][4][NB][64];
   const int lane = threadIdx.x & 63;
   // wave-uniform, so chunk and term indices, job fields and base pointers stay scalar
@@ -150,10 +185,9 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
   auto fetch = [&](int q) {
     const int t = q / nkt;
     const int kt = q - t * nkt;
-    const gbf16x8* T = reinterpret_cast<const gbf16x8*>(
-        reinterpret_cast<uintptr_t>(static_cast<const __bf16*>(J.M[t]) + ((size_t)rt * nkt + kt) * 4 * 512));
+    const typename T::E* tp = static_cast<const typename T::E*>(J.M[t]) + ((size_t)rt * nkt + kt) * 4 * 512;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) pa[p] = T[p * 64 + lane];
+    for (int p = 0; p < 4; ++p) pa[p] = gload<bf16x8>(tp, p * 64 + lane);
     const VecRef qr = J.Q[t];
     const VecRef svr = J.S[t];
     has_q = qr.buf >= 0;
@@ -191,11 +225,11 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
           v.y += beta.x * w.y + beta.y * w.x;
         }
         if (!(col_ok && kfetch + u < n)) v = make_double2(0.0, 0.0);
-        __bf16 h, lo;
-        split2(v.x, h, lo);
+        typename T::E h, lo;
+        T::split(v.x * T::kX, h, lo);
         xr_h[b][u] = h;
         xr_l[b][u] = lo;
-        split2(v.y, h, lo);
+        T::split(v.y * T::kX, h, lo);
         xi_h[b][u] = h;
         xi_l[b][u] = lo;
       }
@@ -203,18 +237,18 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
     if (q + KS < nchunks) fetch(q + KS);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_h[b], acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_h[b], acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_h[b], acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_h[b], acc[3][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_l[b], acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_l[b], acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_l[b], acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_l[b], acc[3][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xr_h[b], acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xi_h[b], acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xi_h[b], acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xr_h[b], acc[3][b], 0, 0, 0);
+      acc[0][b] = T::mfma(ar_h, xr_h[b], acc[0][b]);
+      acc[1][b] = T::mfma(ai_h, xi_h[b], acc[1][b]);
+      acc[2][b] = T::mfma(ar_h, xi_h[b], acc[2][b]);
+      acc[3][b] = T::mfma(ai_h, xr_h[b], acc[3][b]);
+      acc[0][b] = T::mfma(ar_h, xr_l[b], acc[0][b]);
+      acc[1][b] = T::mfma(ai_h, xi_l[b], acc[1][b]);
+      acc[2][b] = T::mfma(ar_h, xi_l[b], acc[2][b]);
+      acc[3][b] = T::mfma(ai_h, xr_l[b], acc[3][b]);
+      acc[0][b] = T::mfma(ar_l, xr_h[b], acc[0][b]);
+      acc[1][b] = T::mfma(ai_l, xi_h[b], acc[1][b]);
+      acc[2][b] = T::mfma(ar_l, xi_h[b], acc[2][b]);
+      acc[3][b] = T::mfma(ai_l, xr_h[b], acc[3][b]);
     }
   }
 
@@ -269,11 +303,12 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
 // partial tiles are summed through LDS one group at a time, in a fixed order.
 constexpr int kWideRows = 64;
 
-template <int NB, int KS>
+template <typename T, int NB, int KS>
 __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* __restrict__ jobs, int n, int ntiles,
                                                                     int nct, int nrhs, int64_t ld, Bases bases,
                                                                     int kslices, int njobs,
                                                                     float2* __restrict__ part) {
+  typedef typename T::v8 bf16x8;
   constexpr int kWideCols = 16 * NB;
   constexpr int PPT = kSpK * kWideCols / 2 / 256;                          // row pairs per thread: NB
   constexpr size_t kPlane = (size_t)NB * 64 * sizeof(bf16x8);              // one plane of a chunk
@@ -326,10 +361,9 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
     const int q = qbeg + qi;
     const int t = q / nkt;
     const int kt = q - t * nkt;
-    const gbf16x8* T = reinterpret_cast<const gbf16x8*>(
-        reinterpret_cast<uintptr_t>(static_cast<const __bf16*>(J.M[t]) + ((size_t)rtc * nkt + kt) * 4 * 512));
+    const typename T::E* tp = static_cast<const typename T::E*>(J.M[t]) + ((size_t)rtc * nkt + kt) * 4 * 512;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) pa[p] = T[p * 64 + lane];
+    for (int p = 0; p < 4; ++p) pa[p] = gload<bf16x8>(tp, p * 64 + lane);
     const VecRef qr = J.Q[t];
     const VecRef svr = J.S[t];
     has_q = qr.buf >= 0;
@@ -363,7 +397,7 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
       const int pr = tid + 256 * j;
       const int kp = pr & 15, c = pr >> 4;  // row pair within the chunk, column within the tile
       const bool col_ok = live && col0 + c < nrhs;
-      __bf16 h[4][2];  // [plane][row of the pair]
+      typename T::E h[4][2];  // [plane][row of the pair]
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         double2 v = has_q ? xq[j][u] : make_double2(0.0, 0.0);
@@ -372,19 +406,18 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
           v.y += beta.x * xs[j][u].y + beta.y * xs[j][u].x;
         }
         if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
-        split2(v.x, h[0][u], h[1][u]);
-        split2(v.y, h[2][u], h[3][u]);
+        T::split(v.x * T::kX, h[0][u], h[1][u]);
+        T::split(v.y * T::kX, h[2][u], h[3][u]);
       }
       // rows 2 kp, 2 kp + 1 sit at positions (2 kp) % 8, +1 of lane (2 kp / 8) * 16 + c % 16 of tile c / 16
       const int l = ((2 * kp) >> 3) * 16 + (c & 15);
       const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {
-        typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-        bf16x2v w;
+        typename T::v2 w;
         w[0] = h[pl][0];
         w[1] = h[pl][1];
-        *reinterpret_cast<bf16x2v*>(gst + pl * kPlane + off) = w;
+        *reinterpret_cast<typename T::v2*>(gst + pl * kPlane + off) = w;
       }
     }
     const bool mult = live;
@@ -400,18 +433,18 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
       for (int b = 0; b < NB; ++b) {
         const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
         const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
-        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_h, acc[0][b], 0, 0, 0);
-        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_h, acc[1][b], 0, 0, 0);
-        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_h, acc[2][b], 0, 0, 0);
-        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_h, acc[3][b], 0, 0, 0);
-        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_l, acc[0][b], 0, 0, 0);
-        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_l, acc[1][b], 0, 0, 0);
-        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_l, acc[2][b], 0, 0, 0);
-        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_l, acc[3][b], 0, 0, 0);
-        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xr_h, acc[0][b], 0, 0, 0);
-        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xi_h, acc[1][b], 0, 0, 0);
-        acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xi_h, acc[2][b], 0, 0, 0);
-        acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xr_h, acc[3][b], 0, 0, 0);
+        acc[0][b] = T::mfma(ar_h, xr_h, acc[0][b]);
+        acc[1][b] = T::mfma(ai_h, xi_h, acc[1][b]);
+        acc[2][b] = T::mfma(ar_h, xi_h, acc[2][b]);
+        acc[3][b] = T::mfma(ai_h, xr_h, acc[3][b]);
+        acc[0][b] = T::mfma(ar_h, xr_l, acc[0][b]);
+        acc[1][b] = T::mfma(ai_h, xi_l, acc[1][b]);
+        acc[2][b] = T::mfma(ar_h, xi_l, acc[2][b]);
+        acc[3][b] = T::mfma(ai_h, xr_l, acc[3][b]);
+        acc[0][b] = T::mfma(ar_l, xr_h, acc[0][b]);
+        acc[1][b] = T::mfma(ai_l, xi_h, acc[1][b]);
+        acc[2][b] = T::mfma(ar_l, xi_h, acc[2][b]);
+        acc[3][b] = T::mfma(ai_l, xr_h, acc[3][b]);
       }
     }
     __syncthreads();
@@ -480,11 +513,12 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
 // (chunk index clamped, term pointers picked by selects), so two chunks can be
 // in flight while a third is multiplied; the arithmetic and its order are those
 // of block_split_wide_kernel<NB, 1>.
-template <int NB, bool HAS_S>
+template <typename T, int NB, bool HAS_S>
 __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __restrict__ jobs, int n, int ntiles,
                                                                  int nct, int nrhs, int64_t ld, Bases bases,
                                                                  int kslices, int njobs,
                                                                  float2* __restrict__ part) {
+  typedef typename T::v8 bf16x8;
   constexpr int kWideCols = 16 * NB;
   constexpr int PPT = kSpK * kWideCols / 2 / 256;              // row pairs per thread: NB
   constexpr size_t kPlane = (size_t)NB * 64 * sizeof(bf16x8);  // one plane of a chunk
@@ -506,8 +540,8 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
   const bool rt_ok = rt < nrt16;
   const int rtc = rt_ok ? rt : nrt16 - 1;
   const int col0 = ct * kWideCols;
-  const __bf16* const M0 = static_cast<const __bf16*>(J.M[0]);
-  const __bf16* const M1 = static_cast<const __bf16*>(J.M[1]);
+  const typename T::E* const M0 = static_cast<const typename T::E*>(J.M[0]);
+  const typename T::E* const M1 = static_cast<const typename T::E*>(J.M[1]);
   const double2* const q0 = sp_base(bases, J.Q[0].buf) + J.Q[0].off;
   const double2* const q1 = sp_base(bases, J.Q[1].buf) + J.Q[1].off;
   const double2* const s0 = HAS_S ? sp_base(bases, J.S[0].buf) + J.S[0].off : q0;
@@ -535,11 +569,9 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
     const int q = qbeg + min(qi, nchunks - 1);
     const bool t1 = q >= nkt;
     const int kt = t1 ? q - nkt : q;
-    const __bf16* Mt = t1 ? M1 : M0;
-    const gbf16x8* T =
-        reinterpret_cast<const gbf16x8*>(reinterpret_cast<uintptr_t>(Mt + ((size_t)rtc * nkt + kt) * 4 * 512));
+    const typename T::E* Mt = (t1 ? M1 : M0) + ((size_t)rtc * nkt + kt) * 4 * 512;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) F.pa[p] = T[p * 64 + lane];
+    for (int p = 0; p < 4; ++p) F.pa[p] = gload<bf16x8>(Mt, p * 64 + lane);
     const double2* qb = t1 ? q1 : q0;
     const double2* sb = t1 ? s1 : s0;
     const int kbase = kt * kSpK;
@@ -570,7 +602,7 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
       const int pr = tid + 256 * j;
       const int kp = pr & 15, c = pr >> 4;
       const bool col_ok = live && col0 + c < nrhs;
-      __bf16 h[4][2];
+      typename T::E h[4][2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         double2 v = F.xq[j][u];
@@ -579,18 +611,17 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
           v.y += beta.x * F.xs[j][u].y + beta.y * F.xs[j][u].x;
         }
         if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
-        split2(v.x, h[0][u], h[1][u]);
-        split2(v.y, h[2][u], h[3][u]);
+        T::split(v.x * T::kX, h[0][u], h[1][u]);
+        T::split(v.y * T::kX, h[2][u], h[3][u]);
       }
       const int l = ((2 * kp) >> 3) * 16 + (c & 15);
       const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {
-        typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-        bf16x2v w;
+        typename T::v2 w;
         w[0] = h[pl][0];
         w[1] = h[pl][1];
-        *reinterpret_cast<bf16x2v*>(gst + pl * kPlane + off) = w;
+        *reinterpret_cast<typename T::v2*>(gst + pl * kPlane + off) = w;
       }
     }
   };
@@ -603,18 +634,18 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
     for (int b = 0; b < NB; ++b) {
       const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
       const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_h, acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_h, acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_h, acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_h, acc[3][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xr_l, acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xi_l, acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_h, xi_l, acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_h, xr_l, acc[3][b], 0, 0, 0);
-      acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xr_h, acc[0][b], 0, 0, 0);
-      acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xi_h, acc[1][b], 0, 0, 0);
-      acc[2][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar_l, xi_h, acc[2][b], 0, 0, 0);
-      acc[3][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai_l, xr_h, acc[3][b], 0, 0, 0);
+      acc[0][b] = T::mfma(ar_h, xr_h, acc[0][b]);
+      acc[1][b] = T::mfma(ai_h, xi_h, acc[1][b]);
+      acc[2][b] = T::mfma(ar_h, xi_h, acc[2][b]);
+      acc[3][b] = T::mfma(ai_h, xr_h, acc[3][b]);
+      acc[0][b] = T::mfma(ar_h, xr_l, acc[0][b]);
+      acc[1][b] = T::mfma(ai_h, xi_l, acc[1][b]);
+      acc[2][b] = T::mfma(ar_h, xi_l, acc[2][b]);
+      acc[3][b] = T::mfma(ai_h, xr_l, acc[3][b]);
+      acc[0][b] = T::mfma(ar_l, xr_h, acc[0][b]);
+      acc[1][b] = T::mfma(ai_l, xi_h, acc[1][b]);
+      acc[2][b] = T::mfma(ar_l, xi_h, acc[2][b]);
+      acc[3][b] = T::mfma(ai_l, xr_h, acc[3][b]);
     }
   };
   auto round = [&](InFlight& F, int ahead) {
@@ -703,7 +734,7 @@ __global__ void split_reduce_kernel(const Job* __restrict__ jobs, int njobs, int
   }
 }
 
-template <int NB, int KS>
+template <typename T, int NB, int KS>
 hipError_t launch_wide(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                        hipEvent_t ev0, hipEvent_t ev1, int kslices = 1, float2* part = nullptr) {
   const int ntiles = (n + kWideRows - 1) / kWideRows;
@@ -711,56 +742,56 @@ hipError_t launch_wide(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, 
   const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
   if (kslices > 1) {
     // the stop event goes on the reduction, so a timed launch covers both kernels
-    hipExtLaunchKernelGGL((block_split_wide_kernel<NB, KS>), grid, dim3(256 * KS), 0, st, ev0, nullptr, 0, jobs, n,
+    hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS>), grid, dim3(256 * KS), 0, st, ev0, nullptr, 0, jobs, n,
                           ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
     const size_t per = (size_t)nrhs * n;
     const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
     hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
                           bases, kslices, (const float2*)part);
   } else {
-    hipExtLaunchKernelGGL((block_split_wide_kernel<NB, KS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, jobs, n,
+    hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, jobs, n,
                           ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
   }
   return hipGetLastError();
 }
 
-template <int NB, bool HAS_S>
+template <typename T, int NB, bool HAS_S>
 hipError_t launch_stream(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                          hipEvent_t ev0, hipEvent_t ev1, int kslices, float2* part) {
   const int ntiles = (n + kWideRows - 1) / kWideRows;
   const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
   const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
   if (kslices > 1) {
-    hipExtLaunchKernelGGL((block_split_stream_kernel<NB, HAS_S>), grid, dim3(256), 0, st, ev0, nullptr, 0, jobs, n,
+    hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S>), grid, dim3(256), 0, st, ev0, nullptr, 0, jobs, n,
                           ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
     const size_t per = (size_t)nrhs * n;
     const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
     hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
                           bases, kslices, (const float2*)part);
   } else {
-    hipExtLaunchKernelGGL((block_split_stream_kernel<NB, HAS_S>), grid, dim3(256), 0, st, ev0, ev1, 0, jobs, n,
+    hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S>), grid, dim3(256), 0, st, ev0, ev1, 0, jobs, n,
                           ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
   }
   return hipGetLastError();
 }
 
-template <int NB, int KS>
+template <typename T, int NB, int KS>
 hipError_t launch_sp(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                      hipEvent_t ev0, hipEvent_t ev1) {
   const int nrt16 = (n + 15) / 16;
   const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
   const dim3 grid((unsigned)njobs * nrt16 * nct);
-  hipExtLaunchKernelGGL((block_split_kernel<NB, KS>), grid, dim3(64 * KS), 0, st, ev0, ev1, 0, jobs, n, nrt16, nct,
+  hipExtLaunchKernelGGL((block_split_kernel<T, NB, KS>), grid, dim3(64 * KS), 0, st, ev0, ev1, 0, jobs, n, nrt16, nct,
                         nrhs, ld, bases);
   return hipGetLastError();
 }
 
-template <int NB>
+template <typename T, int NB>
 hipError_t launch_sp_ks(int ks, const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1) {
-  if (ks >= 4) return launch_sp<NB, 4>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
-  if (ks == 2) return launch_sp<NB, 2>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
-  return launch_sp<NB, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  if (ks >= 4) return launch_sp<T, NB, 4>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  if (ks == 2) return launch_sp<T, NB, 2>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  return launch_sp<T, NB, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
 }
 
 }  // namespace
@@ -770,15 +801,23 @@ size_t split_block_elems(int n) {
   return nrt16 * nkt * 4 * 512;
 }
 
-hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, hipStream_t st) {
+hipError_t launch_split_planes(const double2* src, void* dst, int nblk, int n, hipStream_t st, int f16,
+                               double scale) {
   if (nblk <= 0) return hipSuccess;
   const int nrt16 = (n + 15) / 16, nkt = (n + kSpK - 1) / kSpK;
   const int64_t lanes = (int64_t)nrt16 * nkt * 64;
   const unsigned gx = (unsigned)std::min<int64_t>((lanes + 255) / 256, 1024);
-  hipLaunchKernelGGL(split_planes_kernel, dim3(gx, nblk), dim3(256), 0, st, src, static_cast<__bf16*>(dst), n, nrt16,
-                     nkt);
+  if (f16)
+    hipLaunchKernelGGL(split_planes_kernel<SpF16>, dim3(gx, nblk), dim3(256), 0, st, src, static_cast<_Float16*>(dst),
+                       n, nrt16, nkt, scale);
+  else
+    hipLaunchKernelGGL(split_planes_kernel<SpBf16>, dim3(gx, nblk), dim3(256), 0, st, src, static_cast<__bf16*>(dst),
+                       n, nrt16, nkt, 1.0);
   return hipGetLastError();
 }
+
+double split_input_scale(int f16) { return f16 ? SpF16::kX : SpBf16::kX; }
+
 
 // right-hand sides per tile of the wide form (rule)
 constexpr int kWideColsRule = 32;
@@ -793,9 +832,11 @@ int split_kslices(int njobs, int n, int nrhs, int tile_rhs) {
   return ks;
 }
 
-hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
-                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, float2* part, SplitCfg cfg) {
-  if (njobs <= 0) return hipSuccess;
+namespace {
+
+template <typename T>
+hipError_t apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1, float2* part, SplitCfg cfg) {
   constexpr long kSimds = 1024;
   if (nrhs > 16) {
     // 64 x 32 (or 64 x 64) tiles; launches with fewer than four tiles per CU
@@ -806,23 +847,33 @@ hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs,
     if (cfg.stream) {  // every job: two terms with Q (and S iff stream == 2)
       const int k = part ? ks : 1;
       if (cfg.stream == 2)
-        return tr == 64 ? launch_stream<4, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
-                        : launch_stream<2, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
-      return tr == 64 ? launch_stream<4, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
-                      : launch_stream<2, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
+        return tr == 64 ? launch_stream<T, 4, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
+                        : launch_stream<T, 2, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
+      return tr == 64 ? launch_stream<T, 4, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
+                      : launch_stream<T, 2, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
     }
     if (ks > 1 && part) {
-      return tr == 64 ? launch_wide<4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part)
-                      : launch_wide<2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
+      return tr == 64 ? launch_wide<T, 4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part)
+                      : launch_wide<T, 2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
     }
-    return tr == 64 ? launch_wide<4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1)
-                    : launch_wide<2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+    return tr == 64 ? launch_wide<T, 4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1)
+                    : launch_wide<T, 2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
   }
   // 16-column tiles; the chunks of a tile are split over up to 4 waves until
   // the launch has about 4 waves per SIMD
   const long tasks = (long)njobs * ((n + 15) / 16) * ((nrhs + 15) / 16);
   const int ks = cfg.kslices > 0 ? cfg.kslices : tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
-  return launch_sp_ks<1>(ks, jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  return launch_sp_ks<T, 1>(ks, jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
 }
+
+}  // namespace
+
+hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
+                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, float2* part, SplitCfg cfg) {
+  if (njobs <= 0) return hipSuccess;
+  return cfg.f16 ? apply_split<SpF16>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, part, cfg)
+                 : apply_split<SpBf16>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, part, cfg);
+}
+
 
 }  // namespace polar

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpolar.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESINGULAR, PT_ENOCONV = range(6)
-PT_F64, PT_F32, PT_SPLIT_BF16 = 0, 1, 2
+PT_F64, PT_F32, PT_SPLIT_BF16, PT_SPLIT_F16 = 0, 1, 2, 3
 PT_LEARN_CORRECT, PT_LEARN_AUGMENT = 0, 1
 OP_A, OP_R, OP_DINV, OP_PRECOND = 0, 1, 2, 3
 # the same operators of the system closed by extrapolation (closure="extrap")
@@ -168,7 +168,7 @@ def _problem_options(nx, nz, npml, h, omega, C_pml, L, c, *, precision="f64", gs
         raise ValueError(f"c must have (nz+2npml)*(nx+2npml) = {NZ * NX} values")
     prob = PtProblem(int(nx), int(nz), int(npml), float(h), float(omega), float(C_pml), int(L),
                      c.ctypes.data_as(C.POINTER(C.c_double)))
-    prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16}[precision]
+    prec = {"f64": PT_F64, "f32": PT_F32, "split-bf16": PT_SPLIT_BF16, "split-f16": PT_SPLIT_F16}[precision]
     if presolve not in ("local", "green", "auto"):
         raise ValueError(f"presolve must be 'local', 'green' or 'auto', not {presolve!r}")
     if closure not in ("jump", "extrap"):

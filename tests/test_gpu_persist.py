@@ -23,6 +23,7 @@ def rel(a, b):
     (dict(precision="f64"), 3),                       # float64, Green's-function pre-solve (auto)
     (dict(precision="f64", presolve="local"), 20),    # line-by-line pre-solve, MFMA tiles, tuned
     (dict(precision="split-bf16"), 40),               # split-bfloat16 planes rebuilt from the loaded blocks
+    (dict(precision="split-f16", closure="extrap"), 40),  # split-float16 planes and scale rebuilt likewise
     (dict(precision="f32"), 20),                      # float32 factors and blocks stored as such
     (dict(precision="f64", plr=True, plr_eps=1e-10), 3),  # compressed blocks stored
     (dict(precision="f64", closure="extrap"), 5),     # extrapolation closure

@@ -27,7 +27,7 @@ def uneven_ref():
     return probs, [DirectSolver(p).solve(f) for p, f in probs]
 
 
-@pytest.mark.parametrize("precision", ["split-bf16", "f64"])
+@pytest.mark.parametrize("precision", ["split-bf16", "split-f16", "f64"])
 def test_uneven_batch_full_size(uneven_ref, precision):
     torch = pytest.importorskip("torch")
     probs, refs = uneven_ref
