@@ -34,6 +34,11 @@ struct SpBf16 {
     hi = static_cast<__bf16>(static_cast<float>(x));
     lo = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
   }
+  // the same from a float32 value (x - hi is exact in float32: at most 17 significant bits)
+  static __device__ __forceinline__ void splitf(float x, E& hi, E& lo) {
+    hi = static_cast<__bf16>(x);
+    lo = static_cast<__bf16>(x - static_cast<float>(hi));
+  }
 };
 struct SpF16 {
   typedef _Float16 E;
@@ -46,6 +51,10 @@ struct SpF16 {
   static __device__ __forceinline__ void split(double x, E& hi, E& lo) {
     hi = static_cast<_Float16>(static_cast<float>(x));
     lo = static_cast<_Float16>(static_cast<float>(x - static_cast<double>(static_cast<float>(hi))));
+  }
+  static __device__ __forceinline__ void splitf(float x, E& hi, E& lo) {
+    hi = static_cast<_Float16>(x);
+    lo = static_cast<_Float16>(x - static_cast<float>(hi));
   }
 };
 
@@ -88,6 +97,18 @@ __device__ __forceinline__ int xcd_logical(int i, int G) {
 // not for its global loads, so loads issued for later chunks stay in flight
 // across it (a full __syncthreads() also drains the vector-memory counter).
 __device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Q + beta S of one complex input entry, in float32 (the split pair keeps at most 22 bits of it)
+__device__ __forceinline__ float2 combine_f(double2 q, double2 sv, double2 beta, bool has_q, bool has_s) {
+  float2 v = has_q ? make_float2(static_cast<float>(q.x), static_cast<float>(q.y)) : make_float2(0.f, 0.f);
+  if (has_s) {
+    const float wx = static_cast<float>(sv.x), wy = static_cast<float>(sv.y);
+    const float bx = static_cast<float>(beta.x), by = static_cast<float>(beta.y);
+    v.x = fmaf(bx, wx, fmaf(-by, wy, v.x));
+    v.y = fmaf(bx, wy, fmaf(by, wx, v.y));
+  }
+  return v;
+}
 
 // ----------------------------------------------------------------------------
 // setup: float64 row-major blocks -> swizzled split planes
@@ -218,18 +239,13 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
       const bool col_ok = col0 + b * 16 + (lane & 15) < nrhs;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        double2 v = has_q ? xq[b][u] : make_double2(0.0, 0.0);
-        if (has_s) {
-          const double2 w = xs[b][u];
-          v.x += beta.x * w.x - beta.y * w.y;
-          v.y += beta.x * w.y + beta.y * w.x;
-        }
-        if (!(col_ok && kfetch + u < n)) v = make_double2(0.0, 0.0);
+        float2 v = combine_f(xq[b][u], xs[b][u], beta, has_q, has_s);
+        if (!(col_ok && kfetch + u < n)) v = make_float2(0.f, 0.f);
         typename T::E h, lo;
-        T::split(v.x * T::kX, h, lo);
+        T::splitf(v.x * static_cast<float>(T::kX), h, lo);
         xr_h[b][u] = h;
         xr_l[b][u] = lo;
-        T::split(v.y * T::kX, h, lo);
+        T::splitf(v.y * static_cast<float>(T::kX), h, lo);
         xi_h[b][u] = h;
         xi_l[b][u] = lo;
       }
@@ -400,14 +416,10 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
       typename T::E h[4][2];  // [plane][row of the pair]
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        double2 v = has_q ? xq[j][u] : make_double2(0.0, 0.0);
-        if (has_s) {
-          v.x += beta.x * xs[j][u].x - beta.y * xs[j][u].y;
-          v.y += beta.x * xs[j][u].y + beta.y * xs[j][u].x;
-        }
-        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
-        T::split(v.x * T::kX, h[0][u], h[1][u]);
-        T::split(v.y * T::kX, h[2][u], h[3][u]);
+        float2 v = combine_f(xq[j][u], xs[j][u], beta, has_q, has_s);
+        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_float2(0.f, 0.f);
+        T::splitf(v.x * static_cast<float>(T::kX), h[0][u], h[1][u]);
+        T::splitf(v.y * static_cast<float>(T::kX), h[2][u], h[3][u]);
       }
       // rows 2 kp, 2 kp + 1 sit at positions (2 kp) % 8, +1 of lane (2 kp / 8) * 16 + c % 16 of tile c / 16
       const int l = ((2 * kp) >> 3) * 16 + (c & 15);
@@ -605,14 +617,10 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
       typename T::E h[4][2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        double2 v = F.xq[j][u];
-        if constexpr (HAS_S) {
-          v.x += beta.x * F.xs[j][u].x - beta.y * F.xs[j][u].y;
-          v.y += beta.x * F.xs[j][u].y + beta.y * F.xs[j][u].x;
-        }
-        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_double2(0.0, 0.0);
-        T::split(v.x * T::kX, h[0][u], h[1][u]);
-        T::split(v.y * T::kX, h[2][u], h[3][u]);
+        float2 v = combine_f(F.xq[j][u], F.xs[HAS_S ? j : 0][u], beta, true, HAS_S);
+        if (!(col_ok && kbase + 2 * kp + u < n)) v = make_float2(0.f, 0.f);
+        T::splitf(v.x * static_cast<float>(T::kX), h[0][u], h[1][u]);
+        T::splitf(v.y * static_cast<float>(T::kX), h[2][u], h[3][u]);
       }
       const int l = ((2 * kp) >> 3) * 16 + (c & 15);
       const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
