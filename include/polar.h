@@ -172,6 +172,7 @@ typedef struct {
   double plr_ms;        /* wall time of the GPU compression inside pt_setup
                            (0 without PLR)                                        */
   int32_t max_nrhs;     /* the options' max_nrhs                                  */
+  int32_t plr_rmax;     /* leaf rank limit of the compressed blocks in use (0: none) */
   int32_t precision;    /* the options' pt_precision                              */
 } pt_layout;
 
@@ -357,10 +358,20 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * contents it overwrites) and keeps the fastest; later calls with the same
  * nrhs use it.  Candidates: float64 MFMA tiles of 16, 32 or 64 right-hand
  * sides, with the 16-wide tile's chunks split over 1, 2 or 4 wave groups;
- * split-bfloat16 tiles of 32 or 64 right-hand sides, split over 1..16
- * k-slices.  Classes with a single form (the row-streaming kernel for <= 4
- * right-hand sides, float32 blocks, compressed blocks) are reported with
- * tried = 1; the pre-solve products are not tuned (tried = 0).
+ * split tiles of 32 or 64 right-hand sides, split over 1..16 k-slices.
+ * Classes with a single form (the row-streaming kernel for <= 4 right-hand
+ * sides, float32 blocks, compressed blocks) are reported with tried = 1; the
+ * pre-solve products are not tuned (tried = 0).
+ * With compressed blocks (plr = 1) it first picks the leaf rank limit r_max,
+ * the partition threshold of Alg. 5, among ceil(sqrt(NX)) x {1/2, 1, 2, 4}
+ * (<= 64) at the solver's eps: each candidate tree is built on the GPU and the
+ * compressed-block launches of one GMRES iteration (sweeps, reflection terms,
+ * A) are timed; the fastest tree stays in use (pt_get_layout reports it).
+ * Every choice goes into a process-wide cache keyed by (NX, L, precision,
+ * closure, compressed or not, launch class, nrhs, the launch's job count);
+ * pt_tune reuses a cached choice instead of timing (cached = 1), and
+ * pt_tune_cache_save / pt_tune_cache_load keep the cache in a text file
+ * across processes (load merges; PT_EINVAL for a file that is not one).
  * out: PT_CLS_COUNT entries (may be NULL). */
 typedef struct {
   int32_t cls;        /* pt_launch_class                                          */
@@ -369,8 +380,11 @@ typedef struct {
   int32_t ksplit;     /* chosen wave groups or k-slices per tile                   */
   double best_us;     /* its mean launch time                                      */
   double default_us;  /* the built-in rule's mean launch time                      */
+  int32_t cached;     /* 1: taken from the tuning cache, not timed                 */
 } pt_tune_entry;
 pt_status pt_tune(pt_solver* s, int32_t nrhs, pt_tune_entry* out);
+pt_status pt_tune_cache_save(const char* path);
+pt_status pt_tune_cache_load(const char* path);
 
 /* ---- learned preconditioner stage --------------------------------------
  *

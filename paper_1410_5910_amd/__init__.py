@@ -5,8 +5,8 @@ The compute path is libpolar.so (HIP for gfx950, C-ABI in include/polar.h);
 ``spectral`` assembles the preconditioned operator on the GPU for eigenvalue
 diagnostics.
 """
-from .polar import (Solver, Learned, PolarError, lib, solve_batch, setup_batch, OP_A, OP_R, OP_DINV, OP_PRECOND,  # noqa: F401
+from .polar import (Solver, Learned, PolarError, lib, solve_batch, setup_batch, tune_cache_save, tune_cache_load, OP_A, OP_R, OP_DINV, OP_PRECOND,  # noqa: F401
                     OP_A_EXTRAP, OP_R_EXTRAP, OP_DINV_EXTRAP, OP_PRECOND_EXTRAP, EXPORTS)
 
-__all__ = ["Solver", "Learned", "PolarError", "solve_batch", "setup_batch", "lib", "OP_A", "OP_R", "OP_DINV", "OP_PRECOND",
+__all__ = ["Solver", "Learned", "PolarError", "solve_batch", "setup_batch", "tune_cache_save", "tune_cache_load", "lib", "OP_A", "OP_R", "OP_DINV", "OP_PRECOND",
            "OP_A_EXTRAP", "OP_R_EXTRAP", "OP_DINV_EXTRAP", "OP_PRECOND_EXTRAP", "EXPORTS"]

@@ -46,12 +46,12 @@ pt_status pt_save(const pt_solver* S, const char* path) {
   const int32_t pi[4] = {S->nx, S->nz, S->npml, S->L};
   const double pd[3] = {S->h, S->omega, S->C};
   const bool green = S->green.p != nullptr;
-  const int32_t flags[3] = {S->f32 ? 1 : 0, green ? 1 : 0, S->use_plr ? 1 : 0};
+  const int32_t flags[4] = {S->f32 ? 1 : 0, green ? 1 : 0, S->use_plr ? 1 : 0, S->plr_rmax};
   const size_t E = S->block_elems();
   bool ok = std::fwrite(kMagic, sizeof(kMagic), 1, fp) == 1 && rec_write_host(fp, ver, 2, 4) &&
             rec_write_host(fp, pi, 4, 4) && rec_write_host(fp, pd, 3, 8) &&
             rec_write_host(fp, &S->opt, 1, sizeof(pt_options)) &&
-            rec_write_host(fp, S->c_host.data(), S->c_host.size(), sizeof(double)) && rec_write_host(fp, flags, 3, 4);
+            rec_write_host(fp, S->c_host.data(), S->c_host.size(), sizeof(double)) && rec_write_host(fp, flags, 4, 4);
   // in the order setup reads them back
   if (ok && !S->f32) ok = rec_write_device(fp, S->dinv64.p, S->dinv64.n, sizeof(double2));
   if (ok && !S->f32 && S->L >= 2) ok = rec_write_device(fp, S->blk64.p, (uint64_t)S->nblk * E, sizeof(double2));
@@ -78,7 +78,7 @@ pt_status pt_load(const char* path, void* hip_stream, pt_solver** out) {
   FileCloser fc{fp};
   char magic[8];
   uint32_t ver[2];
-  int32_t pi[4], flags[3];
+  int32_t pi[4], flags[4];
   double pd[3];
   pt_options opt{};
   if (std::fread(magic, sizeof(magic), 1, fp) != 1 || std::memcmp(magic, kMagic, sizeof(kMagic)) != 0)
@@ -91,7 +91,7 @@ pt_status pt_load(const char* path, void* hip_stream, pt_solver** out) {
     return fail(PT_EINVAL, "saved solver: grid sizes");
   const size_t npad = (size_t)(pi[0] + 2 * pi[2]) * (pi[1] + 2 * pi[2]);
   std::vector<double> c(npad);
-  if (!rec_read_host(fp, c.data(), npad, sizeof(double)) || !rec_read_host(fp, flags, 3, 4))
+  if (!rec_read_host(fp, c.data(), npad, sizeof(double)) || !rec_read_host(fp, flags, 4, 4))
     return fail(PT_EINVAL, "saved solver: velocity");
   if ((flags[0] != 0) != (opt.precision == PT_F32) || (flags[2] != 0) != (opt.plr != 0 && pi[3] >= 2))
     return fail(PT_EINVAL, "saved solver: flags do not match the options");
@@ -127,6 +127,7 @@ pt_status pt_load(const char* path, void* hip_stream, pt_solver** out) {
   }
   for (const TuneRec& t : tr)
     if (t.cls >= 0 && t.cls < PT_CLS_COUNT) S->tune[t.cls][t.nrhs] = t.cfg;
+  if (S->use_plr) S->plr_rmax = flags[3];  // the tree in the file may carry a tuned rank limit
   *out = S;
   return PT_OK;
 }

@@ -52,6 +52,10 @@ struct PlrSet {
   // read them back into fresh device memory (false on an I/O or HIP error).
   bool save(FILE* fp) const;
   bool load(FILE* fp);
+  // Take over the compressed blocks of `o` (same block count) while keeping
+  // this set's block-descriptor array, so job terms that point at block(b)
+  // stay valid; o is left empty.
+  hipError_t adopt(PlrSet& o);
   const PlrBlockDev* block(int b) const { return d_blocks + b; }
   void release();
 };

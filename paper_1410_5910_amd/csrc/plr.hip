@@ -887,6 +887,33 @@ hipError_t PlrSet::expand(int b, double2* out, hipStream_t st) const {
   return hipGetLastError();
 }
 
+hipError_t PlrSet::adopt(PlrSet& o) {
+  if (o.stored.size() != stored.size() || !d_blocks || !o.d_blocks) return hipErrorInvalidValue;
+  const size_t nb = stored.size();
+  hipError_t e = hipMemcpy(d_blocks, o.d_blocks, nb * sizeof(PlrBlockDev), hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) return e;
+  PlrBlockDev* keep = d_blocks;
+  d_blocks = nullptr;
+  release();  // the old leaves, tile lists and data (not the descriptor array)
+  d_blocks = keep;
+  n = o.n;
+  d_leaves = o.d_leaves;
+  d_ptr = o.d_ptr;
+  d_list = o.d_list;
+  d_data = o.d_data;
+  data_entries = o.data_entries;
+  nleaves_total = o.nleaves_total;
+  stored = std::move(o.stored);
+  nleaves = std::move(o.nleaves);
+  (void)hipFree(o.d_blocks);
+  o.d_leaves = nullptr;
+  o.d_ptr = o.d_list = nullptr;
+  o.d_data = nullptr;
+  o.d_blocks = nullptr;
+  o.release();
+  return hipSuccess;
+}
+
 void PlrSet::release() {
   if (d_leaves) (void)hipFree(d_leaves);
   if (d_ptr) (void)hipFree(d_ptr);

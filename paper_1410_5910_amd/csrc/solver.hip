@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "persist.h"
@@ -2094,6 +2095,120 @@ static pt_status time_launch(pt_solver* S, const Launch& Lc, int nrhs, int64_t l
   return rc;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Process-wide cache of tuned choices, keyed by what they depend on: the
+// block size, the layer count, the form (precision, closure, compressed
+// blocks), the launch class, the right-hand-side count and the launch's job
+// count.  pt_tune reuses an entry instead of timing; pt_tune_cache_save /
+// pt_tune_cache_load keep it across processes.
+struct TuneKey {
+  int NX, L, precision, closure, plr, cls, nrhs, njobs;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(NX, L, precision, closure, plr, cls, nrhs, njobs) <
+           std::tie(o.NX, o.L, o.precision, o.closure, o.plr, o.cls, o.nrhs, o.njobs);
+  }
+};
+struct TuneVal {
+  int has_cfg = 0;  // 0: the built-in rule was fastest
+  TuneCfg cfg{};
+  double best_us = 0, default_us = 0;
+  int tried = 0;
+};
+constexpr int kClsPlrRank = PT_CLS_COUNT;  // pseudo-class: the leaf rank limit of compressed blocks (njobs = rank)
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+TuneKey tune_key(const pt_solver* S, int cls, int nrhs, int njobs) {
+  return TuneKey{S->NX, S->L, S->opt.precision, S->opt.closure, S->use_plr ? 1 : 0, cls, nrhs, njobs};
+}
+
+}  // namespace
+
+namespace polar_impl {
+
+// launches that apply the compressed blocks: refresh their streamed-entry counts (profiling bytes)
+void refresh_plr_bytes(pt_solver* S) {
+  auto fix = [&](Launch& Lc) {
+    if (!Lc.plr) return;
+    Lc.mat_elems = 0;
+    for (int j = Lc.job0; j < Lc.job0 + Lc.njobs; ++j)
+      for (int t = 0; t < S->hjobs[j].nterms; ++t)
+        Lc.mat_elems += (double)S->plr.stored_entries(S->blk_id(S->hjobs[j].M[t]));
+  };
+  for (Launch& Lc : S->sweep) fix(Lc);
+  for (Launch* Lc : {&S->bterm, &S->opA, &S->opA2, &S->opR, &S->opX, &S->opX2, &S->opRX, &S->gsRX, &S->tX}) fix(*Lc);
+}
+
+// Compressed blocks: the leaf rank limit r_max (Alg. 5's partition threshold) that makes the
+// per-iteration applies fastest for nrhs sources, at the solver's tolerance eps.  Each candidate
+// is compressed on the GPU and its sweep and operator launches timed; the fastest stays in use.
+pt_status tune_plr_rank(pt_solver* S, int nrhs, double& best_cost, int& tried, bool& cached) {
+  const int NX = S->NX;
+  const TuneKey key = tune_key(S, kClsPlrRank, nrhs, 0);
+  int best_r = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      best_r = it->second.cfg.tn;
+      best_cost = it->second.best_us;
+      tried = 0;
+      cached = true;
+    }
+  }
+  const int root = (int)std::ceil(std::sqrt((double)NX));
+  std::vector<int> cands;
+  if (!cached)
+    for (int r : {std::max(1, root / 2), root, 2 * root, 4 * root})
+      if (std::min(r, kPlrMaxRank) == r && std::find(cands.begin(), cands.end(), r) == cands.end()) cands.push_back(r);
+  Bases b{{S->s.p, S->U1.p, S->U2.p, nullptr}};
+  Bases bo{{S->U1.p, nullptr, S->tmp.p, nullptr}};
+  const int gs = std::max(1, S->opt.gs_iters);
+  auto rebuild = [&](int r) -> pt_status {
+    if (r == S->plr_rmax) return PT_OK;
+    PlrSet tmp;
+    const hipError_t e = tmp.build(S->blk64.p, S->nblk, NX, r, S->opt.plr_eps, S->st);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP, "PLR compression");
+    HIPCHK(S->plr.adopt(tmp));
+    S->plr_rmax = r;
+    refresh_plr_bytes(S);
+    return PT_OK;
+  };
+  best_cost = cached ? best_cost : 1e300;
+  for (int r : cands) {
+    PTCHK(rebuild(r));
+    // one GMRES iteration's compressed-block launches: gs sweeps of L-2 steps, gs-1 reflection launches, A
+    double t_sw = 0, t_bt = 0, t_op = 0;
+    if (!S->sweep.empty()) PTCHK(time_launch(S, S->sweep[S->sweep.size() / 2], nrhs, S->Nt, b, nullptr, 3, t_sw));
+    PTCHK(time_launch(S, S->bterm, nrhs, S->Nt, b, nullptr, 3, t_bt));
+    PTCHK(time_launch(S, S->opA, nrhs, S->Nt, bo, nullptr, 3, t_op));
+    const double cost = gs * (double)S->sweep.size() * t_sw + (gs - 1) * t_bt + t_op;
+    ++tried;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_r = r;
+    }
+  }
+  if (best_r > 0) PTCHK(rebuild(best_r));
+  if (!cached) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneVal v;
+    v.has_cfg = 1;
+    v.cfg.tn = best_r;
+    v.best_us = best_cost;
+    v.tried = tried;
+    g_tune_cache[key] = v;
+  }
+  return PT_OK;
+}
+
+}  // namespace polar_impl
+
+extern "C" {
+
 pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
   PTCHK(check_nrhs(S, nrhs));
   HIPCHK(hipStreamSynchronize(S->st));
@@ -2105,8 +2220,15 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
   HIPCHK(hipMemsetAsync(S->Bw.p, 0, S->Bw.n * sizeof(double2), S->st));
   if (L >= 2)
     for (auto* bf : {&S->U1, &S->U2, &S->tmp, &S->s}) HIPCHK(hipMemsetAsync(bf->p, 0, bf->n * sizeof(double2), S->st));
+  // compressed blocks: the leaf rank limit first (the launch shapes below are then those of its tree)
+  if (S->use_plr && L >= 2) {
+    double cost = 0;
+    int tried = 0;
+    bool cached = false;
+    PTCHK(tune_plr_rank(S, nrhs, cost, tried, cached));
+  }
   for (int cls = 0; cls < PT_CLS_COUNT; ++cls) {
-    pt_tune_entry e{cls, 0, 0, 0, 0.0, 0.0};
+    pt_tune_entry e{cls, 0, 0, 0, 0.0, 0.0, 0};
     const Launch* Lc = nullptr;
     Bases b{};
     int64_t ld = S->Nt;
@@ -2125,6 +2247,30 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       b = Bases{{S->U1.p, nullptr, S->tmp.p, nullptr}};
     }
     if (Lc && Lc->njobs > 0) {
+      const TuneKey key = tune_key(S, cls, nrhs, Lc->njobs);
+      bool hit = false;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+          hit = true;
+          if (it->second.has_cfg) {
+            S->tune[cls][nrhs] = it->second.cfg;
+            S->tune[cls][nrhs].njobs = Lc->njobs;
+            e.tile_rhs = it->second.cfg.tn ? it->second.cfg.tn : it->second.cfg.sp.tile_rhs;
+            e.ksplit = it->second.cfg.tn ? it->second.cfg.ks : it->second.cfg.sp.kslices;
+          } else {
+            S->tune[cls].erase(nrhs);
+          }
+          e.best_us = it->second.best_us;
+          e.default_us = it->second.default_us;
+          e.cached = 1;
+        }
+      }
+      if (hit) {
+        if (out) out[cls] = e;
+        continue;
+      }
       // candidate shapes of this launch
       std::vector<TuneCfg> cands;
       const ApplyGeom g = geom_for(S->NX, Lc->maxterms, nrhs, Lc->njobs);
@@ -2178,10 +2324,63 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       } else {
         S->tune[cls].erase(nrhs);
       }
+      TuneVal v;
+      v.has_cfg = best ? 1 : 0;
+      if (best) v.cfg = *best;
+      v.best_us = e.best_us;
+      v.default_us = e.default_us;
+      v.tried = e.tried;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = v;
     }
     if (out) out[cls] = e;
   }
   HIPCHK(hipStreamSynchronize(S->st));
+  return PT_OK;
+}
+
+pt_status pt_tune_cache_save(const char* path) {
+  if (!path) return fail(PT_EINVAL, "null path");
+  FILE* fp = std::fopen(path, "w");
+  if (!fp) return fail(PT_EINVAL, std::string("cannot open ") + path + " for writing");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  bool ok = std::fprintf(fp, "# libpolar tuning cache v1: NX L precision closure plr class nrhs njobs | has_cfg tn ks "
+                             "tile_rhs kslices stream f16 | best_us default_us tried\n") > 0;
+  for (const auto& kv : g_tune_cache) {
+    const TuneKey& k = kv.first;
+    const TuneVal& v = kv.second;
+    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.9g %.9g %d\n", k.NX, k.L, k.precision,
+                            k.closure, k.plr, k.cls, k.nrhs, k.njobs, v.has_cfg, v.cfg.tn, v.cfg.ks, v.cfg.sp.tile_rhs,
+                            v.cfg.sp.kslices, v.cfg.sp.stream, v.cfg.sp.f16, v.best_us, v.default_us, v.tried) > 0;
+  }
+  ok = std::fclose(fp) == 0 && ok;
+  return ok ? PT_OK : fail(PT_EINVAL, std::string("writing ") + path + " failed");
+}
+
+pt_status pt_tune_cache_load(const char* path) {
+  if (!path) return fail(PT_EINVAL, "null path");
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return fail(PT_EINVAL, std::string("cannot open ") + path);
+  char line[512];
+  std::map<TuneKey, TuneVal> add;
+  bool ok = std::fgets(line, sizeof(line), fp) && std::strncmp(line, "# libpolar tuning cache v1", 26) == 0;
+  while (ok && std::fgets(line, sizeof(line), fp)) {
+    TuneKey k{};
+    TuneVal v{};
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf %d", &k.NX, &k.L,
+                                &k.precision, &k.closure, &k.plr, &k.cls, &k.nrhs, &k.njobs, &v.has_cfg, &v.cfg.tn,
+                                &v.cfg.ks, &v.cfg.sp.tile_rhs, &v.cfg.sp.kslices, &v.cfg.sp.stream, &v.cfg.sp.f16,
+                                &v.best_us, &v.default_us, &v.tried);
+    ok = got == 18 && k.cls >= 0 && k.cls <= kClsPlrRank && k.nrhs >= 1 && v.cfg.tn >= 0 && v.cfg.tn <= 64 &&
+         v.cfg.ks >= 0 && v.cfg.ks <= 16 && v.cfg.sp.kslices >= 0 && v.cfg.sp.kslices <= 16 &&
+         (v.cfg.sp.tile_rhs == 0 || v.cfg.sp.tile_rhs == 32 || v.cfg.sp.tile_rhs == 64) && v.cfg.sp.stream >= 0 &&
+         v.cfg.sp.stream <= 2;
+    if (ok) add[k] = v;
+  }
+  std::fclose(fp);
+  if (!ok) return fail(PT_EINVAL, std::string(path) + " is not a tuning cache of this library");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : add) g_tune_cache[kv.first] = kv.second;
   return PT_OK;
 }
 
@@ -2323,6 +2522,7 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
   if (opt->plr && S->L >= 2) {
     int rmax = opt->plr_rmax > 0 ? opt->plr_rmax : (int)std::ceil(std::sqrt((double)NX));
     rmax = std::min(rmax, kPlrMaxRank);
+    S->plr_rmax = rmax;
     const auto tp = std::chrono::steady_clock::now();
     if (src) {
       if (!src->plr || !S->plr.load(src->fp) || (int)S->plr.stored.size() != S->nblk || S->plr.n != NX)
@@ -2455,6 +2655,7 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   o->green_bytes = S->green.p ? (int64_t)(S->green.n * sizeof(double2)) : 0;
   o->factor_bytes = (int64_t)S->sumR * S->block_elems() * es;
   o->max_nrhs = S->opt.max_nrhs;
+  o->plr_rmax = S->use_plr ? S->plr_rmax : 0;
   o->precision = S->opt.precision;
   return PT_OK;
 }

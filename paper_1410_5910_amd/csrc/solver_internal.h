@@ -137,6 +137,7 @@ struct pt_solver {
   // device data
   PlrSet plr;
   bool use_plr = false;
+  int plr_rmax = 0;  // leaf rank limit of the compressed blocks in use
   DevBuf<double2> dinv64, blk64;
   DevBuf<float2> dinv32, blk32;
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)

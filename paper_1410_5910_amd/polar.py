@@ -36,7 +36,7 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
            "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel", "pt_apply_noalloc",
-           "pt_setup_batch", "pt_save", "pt_load")
+           "pt_setup_batch", "pt_save", "pt_load", "pt_tune_cache_save", "pt_tune_cache_load")
 CLASSES = ("local", "sweep", "reflect", "operator", "presolve")
 
 
@@ -62,7 +62,7 @@ class PtLayout(C.Structure):
                 ("top_ext", C.c_int32 * 64), ("bot_ext", C.c_int32 * 64), ("setup_ms", C.c_double),
                 ("block_bytes", C.c_int64), ("factor_bytes", C.c_int64), ("dense_block_bytes", C.c_int64),
                 ("plr_leaves", C.c_int64), ("green_bytes", C.c_int64), ("plr_ms", C.c_double),
-                ("max_nrhs", C.c_int32), ("precision", C.c_int32)]
+                ("max_nrhs", C.c_int32), ("plr_rmax", C.c_int32), ("precision", C.c_int32)]
 
 
 class PtKernelStats(C.Structure):
@@ -72,7 +72,7 @@ class PtKernelStats(C.Structure):
 
 class PtTuneEntry(C.Structure):
     _fields_ = [("cls", C.c_int32), ("tried", C.c_int32), ("tile_rhs", C.c_int32), ("ksplit", C.c_int32),
-                ("best_us", C.c_double), ("default_us", C.c_double)]
+                ("best_us", C.c_double), ("default_us", C.c_double), ("cached", C.c_int32)]
 
 
 class PolarError(RuntimeError):
@@ -102,6 +102,8 @@ def lib():
         L.pt_solve.argtypes = [vp, i32, vp, vp, i32, C.POINTER(PtRhsInfo)]
         L.pt_setup_batch.argtypes = [i32, C.POINTER(PtProblem), C.POINTER(PtOptions), C.POINTER(vp), C.POINTER(vp)]
         L.pt_save.argtypes = [vp, C.c_char_p]
+        L.pt_tune_cache_save.argtypes = [C.c_char_p]
+        L.pt_tune_cache_load.argtypes = [C.c_char_p]
         L.pt_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
         L.pt_free.argtypes = [vp]
         L.pt_free.restype = None
@@ -244,7 +246,7 @@ class Solver:
                 "bot_ext": list(o.bot_ext[:L]), "setup_ms": o.setup_ms, "block_bytes": o.block_bytes,
                 "factor_bytes": o.factor_bytes, "dense_block_bytes": o.dense_block_bytes,
                 "plr_leaves": o.plr_leaves, "green_bytes": o.green_bytes,
-                "plr_ms": o.plr_ms, "max_nrhs": o.max_nrhs, "precision": o.precision}
+                "plr_ms": o.plr_ms, "max_nrhs": o.max_nrhs, "plr_rmax": o.plr_rmax, "precision": o.precision}
 
     def profile(self, enable: bool):
         """Start (reset) / stop recording HIP events around every block-apply launch."""
@@ -266,7 +268,8 @@ class Solver:
         arr = (PtTuneEntry * len(CLASSES))()
         _check(self._lib.pt_tune(self._h, int(nrhs), arr))
         return {CLASSES[e.cls]: {"tried": e.tried, "tile_rhs": e.tile_rhs, "ksplit": e.ksplit,
-                                 "best_us": e.best_us, "default_us": e.default_us} for e in arr}
+                                 "best_us": e.best_us, "default_us": e.default_us, "cached": bool(e.cached)}
+                for e in arr}
 
     def get_block(self, layer: int, j: str, k: str) -> np.ndarray:
         """K^layer_{j,k} (NX x NX, rows: target x) for j, k in {'0', '1', 'n', 'n+1'}."""
@@ -538,3 +541,13 @@ def setup_batch(probs, streams=None, **kw):
         sv._adopt(C.c_void_p(out[i]), streams[i] if streams else None)
         res.append(sv)
     return res
+
+
+def tune_cache_save(path: str):
+    """Write the process-wide tuning cache (every choice pt_tune made or loaded) to a text file."""
+    _check(lib().pt_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str):
+    """Merge a tuning cache written by tune_cache_save into this process's cache."""
+    _check(lib().pt_tune_cache_load(os.fsencode(path)))

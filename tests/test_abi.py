@@ -91,3 +91,19 @@ def test_load_rejects_non_solver_files_without_a_gpu(tmp_path):
     assert out.value is None
     assert L.pt_load(str(tmp_path / "missing").encode(), None, C.byref(out)) == P.polar.PT_EINVAL
     assert L.pt_setup_batch(0, None, None, None, None) == P.polar.PT_OK
+
+
+def test_tune_cache_files_without_a_gpu(tmp_path):
+    # the tuning cache is host data: saving, loading and rejecting foreign files need no device
+    P = pytest.importorskip("paper_1410_5910_amd")
+    path = str(tmp_path / "tune.txt")
+    P.tune_cache_save(path)
+    assert open(path).readline().startswith("# libpolar tuning cache v1")
+    P.tune_cache_load(path)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# libpolar tuning cache v1\n1 2 3\n")
+    with pytest.raises(P.PolarError):
+        P.tune_cache_load(str(bad))
+    bad.write_text("something else\n")
+    with pytest.raises(P.PolarError):
+        P.tune_cache_load(str(bad))

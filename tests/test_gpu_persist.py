@@ -95,3 +95,49 @@ def test_setup_batch_matches_separate_setups():
     with pytest.raises(P.PolarError) as e:
         P.setup_batch([probs[0][0], bad], tol=1e-10)
     assert "problem 1" in str(e.value)
+
+
+def test_tune_cache_reuse_and_file_roundtrip(tmp_path):
+    prob, f = synth.config_small(nx=40, nz=48, npml=6, L=4, nrhs=24, seed=130)
+    a = P.Solver.from_problem(prob, max_nrhs=24, tol=1e-10, maxit=60, precision="split-bf16")
+    t1 = a.tune(24)
+    u1, _ = a.solve(f)
+    b = P.Solver.from_problem(prob, max_nrhs=24, tol=1e-10, maxit=60, precision="split-bf16")
+    t2 = b.tune(24)  # same shape and form: every timed class comes from the cache
+    for cls, e in t1.items():
+        if e["tried"] > 0:
+            assert t2[cls]["cached"] and t2[cls]["tile_rhs"] == e["tile_rhs"] and t2[cls]["ksplit"] == e["ksplit"]
+    u2, _ = b.solve(f)
+    assert np.array_equal(u1.view(np.float64), u2.view(np.float64))
+    path = str(tmp_path / "tune.txt")
+    P.tune_cache_save(path)
+    lines = [ln for ln in open(path) if not ln.startswith("#")]
+    assert len(lines) >= sum(1 for e in t1.values() if e["tried"] > 0)
+    P.tune_cache_load(path)  # merging the same entries back changes nothing
+    c = P.Solver.from_problem(prob, max_nrhs=24, tol=1e-10, maxit=60, precision="split-bf16")
+    c.tune(24)
+    u3, _ = c.solve(f)
+    assert np.array_equal(u1.view(np.float64), u3.view(np.float64))
+    for s in (a, b, c):
+        s.close()
+
+
+def test_tuner_picks_plr_rank():
+    prob, f = synth.config_small(nx=90, nz=60, npml=8, L=4, nrhs=1, seed=131)
+    s = P.Solver.from_problem(prob, plr=True, plr_eps=1e-10, max_nrhs=2, tol=1e-10, maxit=60)
+    r0 = s.layout()["plr_rmax"]
+    root = int(np.ceil(np.sqrt(prob.NX)))
+    assert r0 == root
+    s.tune(1)
+    r1 = s.layout()["plr_rmax"]
+    assert r1 in {max(1, root // 2), root, 2 * root, 4 * root}
+    u, info = s.solve(f)
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
+    # a second solver of the same shape takes the cached rank without timing
+    s2 = P.Solver.from_problem(prob, plr=True, plr_eps=1e-10, max_nrhs=2, tol=1e-10, maxit=60)
+    s2.tune(1)
+    assert s2.layout()["plr_rmax"] == r1
+    u2, _ = s2.solve(f)
+    assert np.array_equal(u.view(np.float64), u2.view(np.float64))
+    s.close()
+    s2.close()
