@@ -1078,6 +1078,40 @@ __global__ void pack_block_kernel(const double2* __restrict__ W, int64_t ld, int
   if (dst32) dst32[e] = make_float2((float)o.x, (float)o.y);
 }
 
+// C = alpha A (B + shift I) for row-major complex n x n blocks (setup only): 16 x 16 output tiles, the
+// k-range walked in 16-wide LDS slices, each output summed in a fixed order
+__global__ __launch_bounds__(256) void setup_gemm_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                         double2* __restrict__ C, int n, double2 alpha,
+                                                         double shift) {
+  __shared__ double2 As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    As[ty][tx] = (row < n && ka < n) ? A[(size_t)row * n + ka] : make_double2(0.0, 0.0);
+    double2 b = (kb < n && col < n) ? B[(size_t)kb * n + col] : make_double2(0.0, 0.0);
+    if (kb == col && kb < n) b.x += shift;
+    Bs[ty][tx] = b;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = cadd(acc, cmul(As[ty][k], Bs[k][tx]));
+    __syncthreads();
+  }
+  if (row < n && col < n) C[(size_t)row * n + col] = cmul(alpha, acc);
+}
+
+// dst = sign src + shift I (row-major n x n)
+__global__ void sign_copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int n, double sign,
+                                 double shift) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const double2 v = src[e];
+  double2 o = make_double2(sign * v.x, sign * v.y);
+  if (e / n == e % n) o.x += shift;
+  dst[e] = o;
+}
+
 __global__ void copy_kernel(double2* __restrict__ d, const double2* __restrict__ s, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     d[e] = s[e];
@@ -1415,6 +1449,18 @@ hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n
   const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(pack_block_kernel, dim3(gx), dim3(kThreads), 0, st, W, ld, q, row, n, sign, shift, dst64,
                      dst32);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_gemm(const double2* A, const double2* B, double2* C, int n, double2 alpha, double shift,
+                             hipStream_t st) {
+  const unsigned t = (unsigned)((n + 15) / 16);
+  hipLaunchKernelGGL(setup_gemm_kernel, dim3(t, t), dim3(256), 0, st, A, B, C, n, alpha, shift);
+  return hipGetLastError();
+}
+hipError_t launch_sign_copy(const double2* src, double2* dst, int n, double sign, double shift, hipStream_t st) {
+  const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(sign_copy_kernel, dim3(gx), dim3(kThreads), 0, st, src, dst, n, sign, shift);
   return hipGetLastError();
 }
 

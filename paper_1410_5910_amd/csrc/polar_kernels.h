@@ -185,6 +185,11 @@ hipError_t launch_identity_rhs(double2* W, const int32_t* rows, int nq, int n, i
 // Copy with optional scale/identity shift of one n x n block out of a local
 // field with nrhs = nq*n columns: dst(i, c) = sign * W[c + q*n, row, i] + shift*(i==c),
 // stored row-major.
+// C = alpha A (B + shift I), row-major complex n x n (setup)
+hipError_t launch_setup_gemm(const double2* A, const double2* B, double2* C, int n, double2 alpha, double shift,
+                             hipStream_t st);
+// dst = sign src + shift I, row-major complex n x n
+hipError_t launch_sign_copy(const double2* src, double2* dst, int n, double sign, double shift, hipStream_t st);
 hipError_t launch_pack_block(const double2* W, int64_t ld, int q, int row, int n, double sign,
                              double shift, double2* dst64, float2* dst32, hipStream_t st);
 

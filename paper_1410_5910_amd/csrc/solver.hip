@@ -729,16 +729,19 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
   int maxq = 0;
   int maxR = 0;
   for (auto& y : S->lay) {
-    maxq = std::max(maxq, (y.top_ext ? 2 : 0) + (y.bot_ext ? 2 : 0));
+    maxq = std::max(maxq, (y.top_ext ? 1 : 0) + (y.bot_ext ? 1 : 0));
     maxR = std::max(maxR, y.R);
   }
-  DevBuf<double2> Wx, Bx;
+  DevBuf<double2> Wx, Bx, Kr;
   DevBuf<int32_t> rows;
   const size_t wel = (size_t)maxq * NX * maxR * NX;
   pt_status rc = PT_OK;
-  if (Wx.alloc(wel) != hipSuccess || Bx.alloc(wel) != hipSuccess || rows.alloc(4) != hipSuccess) {
+  // raw blocks K_{j,k} of one layer, j in {0, 1, n, n+1} x k in {0, 1, n, n+1}
+  if (Wx.alloc(wel) != hipSuccess || Bx.alloc(wel) != hipSuccess || rows.alloc(4) != hipSuccess ||
+      Kr.alloc(16 * E) != hipSuccess) {
     Wx.release();
     Bx.release();
+    Kr.release();
     rows.release();
     return fail(PT_ENOMEM, "extraction workspace");
   }
@@ -798,15 +801,11 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
   const size_t saved_jobs = S->hjobs.size();
   for (int l = 0; l < L && rc == PT_OK; ++l) {
     const Layer& y = S->lay[l];
+    // unit right-hand sides at rows 1 and n only: the columns at rows 0 and n+1
+    // follow from them (Lemma 4 with the layer's reciprocity, below)
     std::vector<int32_t> src;
-    if (y.top_ext) {
-      src.push_back(y.r0);
-      src.push_back(y.r1);
-    }
-    if (y.bot_ext) {
-      src.push_back(y.rn);
-      src.push_back(y.rn1);
-    }
+    if (y.top_ext) src.push_back(y.r1);
+    if (y.bot_ext) src.push_back(y.rn);
     const int nq = (int)src.size();
     const int nrhs = nq * NX;
     const int64_t ld = (int64_t)y.R * NX;
@@ -857,10 +856,49 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
       }
       if (rc != PT_OK) break;
     }
-    // pack the signed blocks (column q of the solve = source row src[q])
+    // Raw blocks K_{j,k} (slot 4 j' + k' for j, k in rows {0, 1, n, n+1}).  The
+    // columns at rows 1 and n come from the solve; the others from Lemma 4 read
+    // column-wise through the layer's reciprocity (the extrapolators equal their
+    // Dalpha-scaled transposes), with E_up = -u_0 Delta_0^-1, E_dn = -l_{n+1} Sigma_{n+1}^-1:
+    //   K_{j,0} = K_{j,1} E_up (j >= 1),      K_{0,0} = E_up (K_{1,0} + I),
+    //   K_{j,n+1} = K_{j,n} E_dn (j <= n),    K_{n+1,n+1} = E_dn (K_{n,n+1} + I).
+    const int trow[4] = {y.r0, y.r1, y.rn, y.rn1};
+    auto kslot = [&](int jj, int kk) { return Kr.p + (size_t)(jj * 4 + kk) * E; };
     auto qof = [&](int row) {
       for (int q = 0; q < nq; ++q)
         if (src[q] == row) return q;
+      return -1;
+    };
+    for (int jj = 0; jj < 4 && rc == PT_OK; ++jj)
+      for (int kk : {1, 2})
+        if (trow[jj] >= 0 && qof(trow[kk]) >= 0 &&
+            launch_pack_block(Wx.p, ld, qof(trow[kk]), trow[jj], NX, 1.0, 0.0, kslot(jj, kk), nullptr, st) !=
+                hipSuccess)
+          rc = fail(PT_EHIP, "pack_block");
+    if (rc == PT_OK && y.top_ext) {
+      const double2 up = d2(-S->ucoef[y.rowbase + y.r0]);
+      const double2* dinv0 = S->dinv64.p + (size_t)(y.rowbase + y.r0) * E;
+      for (int jj : {1, 2, 3})
+        if (rc == PT_OK && trow[jj] >= 0 &&
+            launch_setup_gemm(kslot(jj, 1), dinv0, kslot(jj, 0), NX, up, 0.0, st) != hipSuccess)
+          rc = fail(PT_EHIP, "setup_gemm");
+      if (rc == PT_OK && launch_setup_gemm(dinv0, kslot(1, 0), kslot(0, 0), NX, up, 1.0, st) != hipSuccess)
+        rc = fail(PT_EHIP, "setup_gemm");
+    }
+    if (rc == PT_OK && y.bot_ext) {
+      const double2 lo = d2(-S->lcoef[y.rowbase + y.rn1]);
+      const double2* dinv1 = S->dinv64.p + (size_t)(y.rowbase + y.rn1) * E;
+      for (int jj : {0, 1, 2})
+        if (rc == PT_OK && trow[jj] >= 0 &&
+            launch_setup_gemm(kslot(jj, 2), dinv1, kslot(jj, 3), NX, lo, 0.0, st) != hipSuccess)
+          rc = fail(PT_EHIP, "setup_gemm");
+      if (rc == PT_OK && launch_setup_gemm(dinv1, kslot(2, 3), kslot(3, 3), NX, lo, 1.0, st) != hipSuccess)
+        rc = fail(PT_EHIP, "setup_gemm");
+    }
+    // pack the signed blocks
+    auto slot_of = [&](int row) {
+      for (int jj = 0; jj < 4; ++jj)
+        if (trow[jj] == row) return jj;
       return -1;
     };
     struct P {
@@ -895,18 +933,18 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
       packs.push_back({B_DN, 1, 1, y.r1, y.r0, -1, -1});
     }
     for (const P& pk : packs) {
+      if (rc != PT_OK) break;
       const int id = S->bidx[((l * 4 + pk.type) * 2 + pk.a) * 2 + pk.b];
-      if (launch_pack_block(Wx.p, ld, qof(pk.srow), pk.trow, NX, pk.sign, pk.shift, S->blk64.p + (size_t)id * E,
-                            nullptr, st) != hipSuccess) {
+      if (launch_sign_copy(kslot(slot_of(pk.trow), slot_of(pk.srow)), S->blk64.p + (size_t)id * E, NX, pk.sign,
+                           pk.shift, st) != hipSuccess)
         rc = fail(PT_EHIP, "pack_block");
-        break;
-      }
     }
     if (hipStreamSynchronize(st) != hipSuccess && rc == PT_OK) rc = fail(PT_EHIP, "extraction sync");
   }
   S->hjobs.resize(saved_jobs);
   Wx.release();
   Bx.release();
+  Kr.release();
   rows.release();
   gax.release();
   gaz.release();
