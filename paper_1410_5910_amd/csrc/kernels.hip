@@ -763,90 +763,136 @@ hipError_t launch_apply_t(const Job* jobs, int njobs, const ApplyGeom& g, int nr
 // ----------------------------------------------------------------------------
 // setup: Gauss-Jordan inversion with partial pivoting
 // ----------------------------------------------------------------------------
-// grid.x = ntile^2 (64 x 64 tiles), grid.y = matrix; 256 threads.
-__global__ __launch_bounds__(kThreads) void gj_step_kernel(double2* const* __restrict__ A,
-                                                           double2* const* __restrict__ B, int n, int k,
-                                                           int32_t* __restrict__ perm, int32_t* __restrict__ flag) {
+// At step k the pivot is the largest |a_ik|^2 over rows i >= k (smallest index
+// on ties), rows k and p are swapped, row k is divided by the pivot and
+// eliminated from every other row, and column k takes the inverse's entries
+// (in place: a zero or NaN column keeps its row order and raises the flag).
+// Blocked: one panel of kGjBw columns at a time.  gj_panel_kernel runs
+// the steps k0 .. k0+bw-1 on the panel columns alone, in place (one workgroup
+// per matrix; the panel stays in L2): pivot search over rows >= k, the row
+// swap within the panel, the elimination.  gj_update_kernel then brings every
+// other column through the same steps at once: with the panel's row swaps
+// applied to it (row source map), column j becomes
+//   new[i][j] = [i outside the pivot rows] old[src(i)][j] + sum_t P[i][t] old[src(k0+t)][j],
+// P the transformed panel, written out of place.  Columns are column-major.
+constexpr int kGjBw = 16;   // panel width
+constexpr int kGjCols = 16; // columns per workgroup of the update
+
+__global__ __launch_bounds__(1024) void gj_panel_kernel(double2* const* __restrict__ A, int n, int k0, int bw,
+                                                        int32_t* __restrict__ perm, int32_t* __restrict__ flag) {
+  const int b = blockIdx.x;
+  double2* __restrict__ a = A[b] + (size_t)k0 * n;  // panel column c at a + c n
+  const int tid = threadIdx.x;
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ double2 fi[4096];
+  __shared__ double2 wj[kGjBw];
+  for (int c = 0; c < bw; ++c) {
+    const int k = k0 + c;
+    // pivot: largest |a_ik|^2 over i >= k, smallest index on ties
+    double bv = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += 1024) {
+      const double2 v = a[(size_t)c * n + i];
+      const double m = v.x * v.x + v.y * v.y;
+      if (m > bv) {
+        bv = m;
+        bi = i;
+      }
+    }
+    sv[tid] = bv;
+    si[tid] = bi;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double v2 = sv[tid + st];
+        const int i2 = si[tid + st];
+        if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
+          sv[tid] = v2;
+          si[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const bool singular = !(sv[0] > 0.0) || si[0] >= n;
+    const int p = singular ? k : si[0];
+    if (tid == 0) {
+      perm[(size_t)b * n + k] = p;
+      if (singular) atomicOr(flag, 1);
+    }
+    // swap rows k and p of the panel
+    if (tid < bw && p != k) {
+      const double2 t = a[(size_t)tid * n + k];
+      a[(size_t)tid * n + k] = a[(size_t)tid * n + p];
+      a[(size_t)tid * n + p] = t;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) fi[i] = a[(size_t)c * n + i];
+    if (tid < bw) wj[tid] = a[(size_t)tid * n + k];
+    __syncthreads();
+    const double2 piv = singular ? make_double2(1.0, 0.0) : fi[k];
+    const double2 inv = cdiv(make_double2(1.0, 0.0), piv);
+    for (int e = tid; e < n * bw; e += 1024) {
+      const int t = e / n, i = e - t * n;
+      double2 out;
+      if (i == k) {
+        out = (t == c) ? inv : cmul(wj[t], inv);
+      } else if (t == c) {
+        const double2 q = cmul(fi[i], inv);
+        out = make_double2(-q.x, -q.y);
+      } else {
+        const double2 q = cmul(fi[i], cmul(wj[t], inv));
+        const double2 v = a[(size_t)t * n + i];
+        out = make_double2(v.x - q.x, v.y - q.y);
+      }
+      a[(size_t)t * n + i] = out;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_update_kernel(double2* const* __restrict__ A, double2* const* __restrict__ B,
+                                                        int n, int k0, int bw, const int32_t* __restrict__ perm) {
   const int b = blockIdx.y;
   const double2* __restrict__ a = A[b];
   double2* __restrict__ o = B[b];
   const int tid = threadIdx.x;
-  __shared__ double sv[kThreads];
-  __shared__ int si[kThreads];
-  __shared__ double2 wj[64];
-  __shared__ double2 fi[64];
-
-  // pivot: largest |a_ik|^2 over i >= k, smallest index on ties
-  double bv = -1.0;
-  int bi = n;
-  for (int i = k + tid; i < n; i += kThreads) {
-    const double2 v = a[(size_t)k * n + i];
-    const double m = v.x * v.x + v.y * v.y;
-    if (m > bv) {
-      bv = m;
-      bi = i;
-    }
-  }
-  sv[tid] = bv;
-  si[tid] = bi;
+  __shared__ int src[4096];
+  __shared__ double2 bv[kGjCols][kGjBw];
+  for (int i = tid; i < n; i += 256) src[i] = i;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double v2 = sv[tid + s];
-      const int i2 = si[tid + s];
-      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
-        sv[tid] = v2;
-        si[tid] = i2;
+  if (tid == 0)
+    for (int c = 0; c < bw; ++c) {
+      const int k = k0 + c, p = perm[(size_t)b * n + k];
+      const int t = src[k];
+      src[k] = src[p];
+      src[p] = t;
+    }
+  __syncthreads();
+  const int j0 = blockIdx.x * kGjCols;
+  for (int e = tid; e < kGjCols * bw; e += 256) {
+    const int jj = e / bw, t = e - jj * bw, j = j0 + jj;
+    bv[jj][t] = j < n ? a[(size_t)j * n + src[k0 + t]] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) {
+    double2 pn[kGjBw];
+#pragma unroll
+    for (int t = 0; t < kGjBw; ++t) pn[t] = t < bw ? a[(size_t)(k0 + t) * n + i] : make_double2(0.0, 0.0);
+    const int si_ = src[i];
+    const bool piv_row = i >= k0 && i < k0 + bw;
+    for (int jj = 0; jj < kGjCols; ++jj) {
+      const int j = j0 + jj;
+      if (j >= n) break;
+      if (j >= k0 && j < k0 + bw) {  // panel column: already final
+        o[(size_t)j * n + i] = a[(size_t)j * n + i];
+        continue;
       }
+      double2 v = piv_row ? make_double2(0.0, 0.0) : a[(size_t)j * n + si_];
+#pragma unroll
+      for (int t = 0; t < kGjBw; ++t) v = cadd(v, cmul(pn[t], bv[jj][t]));
+      o[(size_t)j * n + i] = v;
     }
-    __syncthreads();
-  }
-  // a column of zeros or NaNs has no pivot: flag it and keep the row order
-  const bool singular = !(sv[0] > 0.0) || si[0] >= n;
-  const int p = singular ? k : si[0];
-  const double2 piv = singular ? make_double2(1.0, 0.0) : a[(size_t)k * n + p];
-  const double2 inv = cdiv(make_double2(1.0, 0.0), piv);
-  if (blockIdx.x == 0 && tid == 0) {
-    perm[(size_t)b * n + k] = p;
-    if (singular) atomicOr(flag, 1);
-  }
-
-  const int nt = (n + 63) / 64;
-  const int ti = blockIdx.x % nt;
-  const int tj = blockIdx.x / nt;
-  if (tid < 64) {
-    const int col = tj * 64 + tid;
-    if (col < n) wj[tid] = (col == k) ? inv : cmul(a[(size_t)col * n + p], inv);
-  } else if (tid < 128) {
-    const int row = ti * 64 + (tid - 64);
-    if (row < n) {
-      const int src = (row == k) ? p : (row == p ? k : row);
-      fi[tid - 64] = a[(size_t)k * n + src];
-    }
-  }
-  __syncthreads();
-
-  const int lr = tid & 63;
-  const int row = ti * 64 + lr;
-  if (row >= n) return;
-  const int src = (row == k) ? p : (row == p ? k : row);
-  const double2 f = fi[lr];
-  for (int q = 0; q < 16; ++q) {
-    const int lc = (tid >> 6) + 4 * q;
-    const int col = tj * 64 + lc;
-    if (col >= n) break;
-    double2 out;
-    if (row == k) {
-      out = wj[lc];
-    } else if (col == k) {
-      const double2 t = cmul(f, inv);
-      out = make_double2(-t.x, -t.y);
-    } else {
-      const double2 t = cmul(f, wj[lc]);
-      const double2 v = a[(size_t)col * n + src];
-      out = make_double2(v.x - t.x, v.y - t.y);
-    }
-    o[(size_t)col * n + row] = out;
   }
 }
 
@@ -1340,12 +1386,21 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
              : launch_apply_t<false>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
 }
 
-hipError_t launch_gj_step(double2* const* A, double2* const* B, int nb, int n, int k, int32_t* perm, int32_t* flag,
-                          hipStream_t st) {
-  const int nt = (n + 63) / 64;
-  hipLaunchKernelGGL(gj_step_kernel, dim3(nt * nt, nb), dim3(kThreads), 0, st, A, B, n, k, perm, flag);
+
+hipError_t launch_gj_panel(double2* const* A, int nb, int n, int k0, int bw, int32_t* perm, int32_t* flag,
+                           hipStream_t st) {
+  if (n > 4096 || bw > kGjBw) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gj_panel_kernel, dim3(nb), dim3(1024), 0, st, A, n, k0, bw, perm, flag);
   return hipGetLastError();
 }
+hipError_t launch_gj_update(double2* const* A, double2* const* B, int nb, int n, int k0, int bw, const int32_t* perm,
+                            hipStream_t st) {
+  if (n > 4096 || bw > kGjBw) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gj_update_kernel, dim3((n + kGjCols - 1) / kGjCols, nb), dim3(256), 0, st, A, B, n, k0, bw,
+                     perm);
+  return hipGetLastError();
+}
+int gj_panel_width() { return kGjBw; }
 
 hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipStream_t st) {
   hipLaunchKernelGGL(gj_perm_kernel, dim3((nb + 63) / 64), dim3(64), 0, st, perm, pi, nb, n);

@@ -128,8 +128,13 @@ double split_input_scale(int f16);
 // column-major matrices.  One call performs elimination step k on every
 // matrix: reads A[b], writes B[b], records perm[b*n + k], raises *flag on a
 // zero pivot.
-hipError_t launch_gj_step(double2* const* A, double2* const* B, int nb, int n, int k, int32_t* perm,
-                          int32_t* flag, hipStream_t st);
+// blocked Gauss-Jordan: the steps k0 .. k0+bw-1 on the panel columns (in place), then every other column
+// through the same steps, out of place (A -> B); bw <= gj_panel_width(), n <= 4096
+hipError_t launch_gj_panel(double2* const* A, int nb, int n, int k0, int bw, int32_t* perm, int32_t* flag,
+                           hipStream_t st);
+hipError_t launch_gj_update(double2* const* A, double2* const* B, int nb, int n, int k0, int bw, const int32_t* perm,
+                            hipStream_t st);
+int gj_panel_width();
 // Composes the column un-scrambling permutation of each matrix (pi[b*n + c]).
 hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipStream_t st);
 

@@ -553,15 +553,20 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
   std::vector<int> cur(NC, 0);  // which of the chain's two buffers holds its current matrix
 
   // Invert the nb matrices whose pointers are in pA (scratch in pB); returns whether the result is in pB.
+  // Blocked: one panel of columns per pair of launches (panel steps in place, then the other columns
+  // out of place), instead of one launch per pivot.
   auto gj_invert = [&](int nb) {
-    for (int k = 0; k < NX && rc == PT_OK; ++k) {
-      if (k % 2 == 0)
-        chk(launch_gj_step(pA.p, pB.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
-      else
-        chk(launch_gj_step(pB.p, pA.p, nb, NX, k, perm.p, S->flag.p, st), "gj_step");
+    const int bw = gj_panel_width();
+    int np = 0;
+    for (int k0 = 0; k0 < NX && rc == PT_OK; k0 += bw, ++np) {
+      const int w = std::min(bw, NX - k0);
+      DevBuf<double2*>& from = (np % 2 == 0) ? pA : pB;
+      DevBuf<double2*>& to = (np % 2 == 0) ? pB : pA;
+      chk(launch_gj_panel(from.p, nb, NX, k0, w, perm.p, S->flag.p, st), "gj_panel");
+      chk(launch_gj_update(from.p, to.p, nb, NX, k0, w, perm.p, st), "gj_update");
     }
     chk(launch_gj_perm(perm.p, pi.p, nb, NX, st), "gj_perm");
-    return (NX % 2) == 1;
+    return (np % 2) == 1;
   };
   auto upload = [&](DevBuf<double2*>& d, const std::vector<double2*>& h) {
     return chk(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(double2*), hipMemcpyHostToDevice, st), "copy");
