@@ -310,7 +310,13 @@ def roofline(form):
             "alg_flops_per_launch": st["alg_flops"] / st["launches"],
             "class_share_of_step": st["kernel_ms"] / k["nprof"] / form["ms_per_step"],
             "nprof": k["nprof"],
-            "all_classes_ms_per_step": {c: v["kernel_ms"] / k["nprof"] for c, v in k["classes"].items()}}
+            "all_classes_ms_per_step": {c: v["kernel_ms"] / k["nprof"] for c, v in k["classes"].items()},
+            # every class: launches per step, mean launch time, algorithmic TFLOP/s and GB/s
+            "classes": {c: {"launches_per_step": v["launches"] / k["nprof"],
+                            "avg_launch_us": 1e3 * v["kernel_ms"] / v["launches"],
+                            "alg_tflops": v["alg_flops"] / (v["kernel_ms"] / 1e3) / 1e12,
+                            "alg_gbs": v["alg_bytes"] / (v["kernel_ms"] / 1e3) / 1e9}
+                        for c, v in k["classes"].items() if v["launches"] > 0 and v["kernel_ms"] > 0}}
     gbs = st["alg_bytes"] / sec / 1e9
     if (form["nrhs"] > 4 and name != "plr_apply_kernel") or dt in ("bf16", "f16"):
         # algorithmic flops: 8 per complex multiply-add, whatever the number of real products that form it
@@ -359,6 +365,40 @@ def run_spectral(P, torch, cpu=True):
     return out
 
 
+def hbm_probe(torch, sizes_mb=(12.5, 25, 50, 100, 200, 400, 1600), reps=20):
+    """Achievable HBM rate at the transfer sizes of single launches: a device-to-device copy (reads and writes
+    N bytes) and a sum (reads N bytes) of N-byte float64 tensors, each from a cold start (a 2 GiB fill between
+    repetitions evicts the data from the caches), timed with HIP events on the current stream."""
+    flush = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0")
+    out = []
+    for mb in sizes_mb:
+        n = int(mb * 1e6) // 8
+        a = torch.rand(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        t_copy, t_sum = [], []
+        for _ in range(reps):
+            for kind in ("copy", "sum"):
+                flush.fill_(1.0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                if kind == "copy":
+                    b.copy_(a)
+                else:
+                    a.sum()
+                e1.record()
+                e1.synchronize()
+                (t_copy if kind == "copy" else t_sum).append(e0.elapsed_time(e1) * 1e-3)
+        t_copy.sort()
+        t_sum.sort()
+        mc, ms = t_copy[len(t_copy) // 2], t_sum[len(t_sum) // 2]
+        out.append({"mb": mb, "copy_us": 1e6 * mc, "copy_gbs": 2 * n * 8 / mc / 1e9, "sum_us": 1e6 * ms,
+                    "sum_gbs": n * 8 / ms / 1e9})
+        log(f"  hbm probe {mb:g} MB: copy {out[-1]['copy_gbs']:.0f} GB/s, read (sum) {out[-1]['sum_gbs']:.0f} GB/s")
+        del a, b
+    del flush
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -401,6 +441,11 @@ def main():
     ap.add_argument("--spectral", action="store_true",
                     help="also the spectral diagnostics of D^-1 A (homogeneous medium vs PML width, resonant "
                          "cavity vs frequency); on with --all-forms")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="also time plain copies and reads of 12.5 MB..1.6 GB (the achievable HBM rate per launch size)")
+    ap.add_argument("--tune-cache", default="", metavar="PATH",
+                    help="tuning cache file: loaded before the forms are tuned (if it exists) and written after, so "
+                         "that profiled runs use the launch shapes an unprofiled run chose")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
@@ -434,6 +479,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        P.tune_cache_load(args.tune_cache)
+        log(f"tuning cache {args.tune_cache} loaded")
 
     if args.calibrate_copy:
         nel = args.calibrate_copy * (1 << 20) // 8
@@ -491,10 +539,18 @@ def main():
                 log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step")
                 runs.append((form, "uneven8", parts))
 
+    probe = None
+    if args.hbm_probe:
+        log("hbm probe")
+        probe = hbm_probe(torch)
+
     spec = None
     if args.spectral or args.all_forms:
         log("spectral diagnostics")
         spec = run_spectral(P, torch, cpu=not args.no_cpu)
+
+    if args.tune_cache:
+        P.tune_cache_save(args.tune_cache)
 
     # ---- oracle check of every source (outside every timed region)
     refs = OracleReferences()
@@ -542,6 +598,8 @@ def main():
     }
     if spec is not None:
         out["spectral"] = spec
+    if probe is not None:
+        out["hbm_probe"] = probe
     if not args.no_cpu:
         log("cpu baseline: oracle direct solve (factorisation and a 32-source batch, medians of 3)")
         cb = cpu_direct_baseline(prob, f)
