@@ -870,9 +870,12 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double2* const* __restri
     }
   __syncthreads();
   const int j0 = blockIdx.x * kGjCols;
-  for (int e = tid; e < kGjCols * bw; e += 256) {
-    const int jj = e / bw, t = e - jj * bw, j = j0 + jj;
-    bv[jj][t] = j < n ? a[(size_t)j * n + src[k0 + t]] : make_double2(0.0, 0.0);
+  // every entry of bv is written: the product below runs over all kGjBw
+  // panel columns, and LDS left over from an earlier workgroup may hold NaN
+  // bit patterns that a zero factor would not cancel
+  for (int e = tid; e < kGjCols * kGjBw; e += 256) {
+    const int jj = e / kGjBw, t = e - jj * kGjBw, j = j0 + jj;
+    bv[jj][t] = (j < n && t < bw) ? a[(size_t)j * n + src[k0 + t]] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   for (int i = tid; i < n; i += 256) {
