@@ -33,6 +33,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# at least eight hardware queues, so that the uneven batch's eight per-problem streams each get one
+# (HIP's default is four); set before the HIP runtime starts
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "online Helmholtz solves/s on 1 MI355X at rel err<=1e-6: mixed+batched vs FP64"
 HBM_PEAK_GBS = 8000.0
@@ -168,8 +172,21 @@ def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     nrhs = sum(f.shape[0] for _, f in probs)
+    # the same batch as one launch sequence (pt_solve_batch_merged: lockstep stages, the GMRES
+    # iterations' block applies of all problems sharing launches), measured beside it
+    for _ in range(max(1, warmup)):
+        P.solve_batch(solvers, fds, merged=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        P.solve_batch(solvers, fds, merged=True)
+    torch.cuda.synchronize()
+    el_merged = time.perf_counter() - t1
     out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs, "gs_iters": 2,
            "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
+           "launch": "pt_solve_batch: one host thread and stream per problem",
+           "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+           "merged_ms_per_step": 1e3 * el_merged / steps,
            "iterations": sorted({i["iters"] for r in res for i in r[1]}),
            "problems": [{"name": p.name, "L": p.L, "nrhs": f.shape[0],
                          "iterations": sorted(set(i["iters"] for i in r[1])),

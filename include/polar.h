@@ -301,6 +301,28 @@ pt_status pt_gauss_seidel(pt_solver* s, int32_t nrhs, const double* f, double* u
 pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
                          double* const* u, int32_t on_device, pt_rhs_info* const* info);
 
+/* The same batch as one launch sequence from one host thread (Alg. 2 for
+ * every problem, in lockstep): each stage -- source activity and pre-solve
+ * (the w^l of every layer, its traces), GMRES start, each GMRES iteration
+ * of the problems not yet converged, GMRES end and reconstruction,
+ * convergence data -- is issued for all problems before the host waits,
+ * once per stage.  In the iterations, the block applies (Alg. 4's sweeps
+ * and the operator of Def. 9) of problems with the same kernel family (the
+ * same block storage and the same side of the form's right-hand-side
+ * threshold) share one launch, one segment of the grid per problem with its
+ * own block size, right-hand sides and vectors; a lone problem keeps its
+ * tuned shape, merged launches take the rules' shapes for their total size.
+ * The pre-solve and reconstruction chains run on the problems' own streams
+ * when these are distinct (they overlap), otherwise everything runs on
+ * s[0]'s stream.  Arguments, results and statuses as pt_solve_batch; every
+ * solver on one device and without a learned stage (PT_EINVAL otherwise).
+ * Each problem's arithmetic is its pt_solve's up to the launch shapes (the
+ * summation order inside a merged launch), so results agree with separate
+ * solves to rounding.  Synchronises every solver's stream first and s[0]'s
+ * stream before returning. */
+pt_status pt_solve_batch_merged(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
+                                double* const* u, int32_t on_device, pt_rhs_info* const* info);
+
 /* The variant of pt_apply that allocates nothing, for callers that cannot
  * allocate device memory at call time (code under stream capture, tight
  * serving loops, harnesses that forbid hipMalloc).  Same operators and the

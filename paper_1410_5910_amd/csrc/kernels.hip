@@ -16,6 +16,8 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstring>
 #include <type_traits>
 
 namespace polar {
@@ -115,9 +117,18 @@ constexpr int gemv_u() { return NR >= 4 ? 4 : 8; }
 
 // PIPE: the launch has jobs of more than one step (several terms or column
 // chunks); without it every job is one step and one register set suffices.
-template <int NR, bool F32, bool PIPE>
-__global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __restrict__ jobs, int n, int ntiles,
-                                                                int kc, int nrhs, int64_t ld, Bases bases) {
+template <int NR, bool F32, bool PIPE, int NS>
+__global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const SegTableT<NS> tab,
+                                                                const Job* __restrict__ jobs1) {
+  // segment of this block: a0 = row tiles per job, a1 = columns per chunk
+  int bx = blockIdx.x;
+  const int seg = seg_of(tab, bx);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], ntiles = tab.a0[seg], kc = tab.a1[seg], nrhs = tab.nrhs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
+  if constexpr (NS > 1)
+    if ((int)blockIdx.y * NR >= nrhs) return;  // right-hand-side tiles beyond this segment's
   using MV = typename MatT<F32>::vec;
   using T = typename MatT<F32>::real;
   constexpr int U = gemv_u<NR>();  // kc <= 64 U: every lane has at most U columns of a step
@@ -127,9 +138,9 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int tile = blockIdx.x % ntiles;
+  const int tile = bx % ntiles;
   // every field of the job, read into scalars up front (independent loads, one round trip)
-  const Job* __restrict__ Jp = jobs + blockIdx.x / ntiles;
+  const Job* __restrict__ Jp = jobs + bx / ntiles;
   const int nterms = Jp->nterms;
   const void* const M0 = Jp->M[0];
   const void* const M1 = Jp->M[1];
@@ -291,9 +302,18 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const Job* __res
 // contiguous quarters of each chunk; each lane walks its own (row-major) row,
 // and each matrix entry loaded is reused for the NR right-hand sides.
 // Cross-wave reduction in LDS, fixed order.
-template <int NR, bool F32>
-__global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restrict__ jobs, int n, int ntiles, int kc,
-                                                              int nrhs, int64_t ld, Bases bases) {
+template <int NR, bool F32, int NS>
+__global__ __launch_bounds__(kThreads) void block_gemm_kernel(const SegTableT<NS> tab,
+                                                              const Job* __restrict__ jobs1) {
+  // segment of this block: a0 = row tiles per job, a1 = columns per chunk
+  int bx = blockIdx.x;
+  const int seg = seg_of(tab, bx);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], ntiles = tab.a0[seg], kc = tab.a1[seg], nrhs = tab.nrhs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
+  if constexpr (NS > 1)
+    if ((int)blockIdx.y * NR >= nrhs) return;  // right-hand-side tiles beyond this segment's
   using MV = typename MatT<F32>::vec;
   using T = typename MatT<F32>::real;
   extern __shared__ unsigned char smem_raw[];
@@ -303,8 +323,8 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const Job* __restr
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int tile = blockIdx.x % ntiles;
-  const Job& J = jobs[blockIdx.x / ntiles];  // read with workgroup-uniform indices only
+  const int tile = bx % ntiles;
+  const Job& J = jobs[bx / ntiles];  // read with workgroup-uniform indices only
   const int r0 = blockIdx.y * NR;
   const int row = tile * 64 + lane;
   const bool valid = row < n;
@@ -426,9 +446,9 @@ constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 static_assert(kMmK == kNzChunk, "nonzero-chunk lists count MFMA staging chunks");
 
-template <int TN, int KS>
-__global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __restrict__ jobs, int n, int ntiles,
-                                                                 int nrt, int nrhs, int64_t ld, Bases bases) {
+template <int TN, int KS, int NS>
+__global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTableT<NS> tab,
+                                                                 const Job* __restrict__ jobs1) {
   constexpr int NB = TN / 16;           // MFMA tiles per wave
   constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread of a group
   __shared__ double2 As[KS][kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
@@ -439,6 +459,13 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const Job* __
   const int wave = tid >> 6;
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);  // k-group (wave-uniform)
   int bid = xcd_logical(blockIdx.x, gridDim.x);
+  // segment of this block (segments stay contiguous in the logical order): a0 =
+  // right-hand-side tiles, a1 = row tiles per job
+  const int seg = seg_of(tab, bid);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], nrt = tab.a0[seg], ntiles = tab.a1[seg], nrhs = tab.nrhs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
   const int ct = bid % nrt;  // right-hand-side tile (fastest: tiles sharing block rows stay on one XCD)
   bid /= nrt;
   const int tile = bid % ntiles;
@@ -705,57 +732,104 @@ __global__ __launch_bounds__(256) void nonzero_chunks_kernel(const double2* __re
   if (tid == 0) out[0] = base;
 }
 
-// ev0/ev1: optional events stamped by the dispatch itself (kernel start / end)
-template <int NR, bool F32>
-hipError_t launch_apply_nr(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                           hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+// Kernel form and shape of one (possibly merged) block-apply launch.
+struct ApplyForm {
+  int kind;  // 0: row-streaming, 1: float64 MFMA, 2: register-blocked
+  int nr;    // right-hand sides per pass (streaming, register-blocked)
+  int tn;    // MFMA tile width
+  int ks;    // MFMA wave groups (0: rule)
+  bool pipe; // streaming: jobs of more than one step
+};
+
+template <int NS>
+SegTableT<NS> seg_table(const ApplySeg* segs, int nseg) {
+  SegTableT<NS> t;
+  std::memset(&t, 0, sizeof(t));
+  t.nseg = nseg;
+  for (int i = 0; i < nseg; ++i) {
+    t.n[i] = segs[i].n;
+    t.nrhs[i] = segs[i].nrhs;
+    t.njobs[i] = segs[i].njobs;
+    t.ld[i] = segs[i].ld;
+    t.jobs[i] = segs[i].jobs;
+    t.bases[i] = segs[i].bases;
+    t.part[i] = segs[i].part;
+  }
+  return t;
+}
+
+// Fills the per-segment tile counts and block offsets of `t` for form f and
+// launches it; ev0/ev1: optional events stamped by the dispatch itself.
+template <int NR, bool F32, int NS>
+hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   using T = typename MatT<F32>::real;
-  dim3 grid((unsigned)njobs * g.ntiles, (unsigned)((nrhs + NR - 1) / NR));
-  if (NR <= 4) {
-    const size_t lds = 2 * (size_t)g.kc * NR * sizeof(Cx<T>);
-    if (g.steps == 1)  // every job one step (0: not known, the general form)
-      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, false>), grid, dim3(kGvThreads), (uint32_t)lds / 2, st, ev0,
-                            ev1, 0, jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
+  long blk = 0;
+  int ymax = 1, kcmax = 1;
+  for (int i = 0; i < t.nseg; ++i) {
+    const int n = t.n[i];
+    t.blk0[i] = (int32_t)blk;
+    if (f.kind == 0) {
+      t.a0[i] = (n + kGvWaves - 1) / kGvWaves;
+      t.a1[i] = std::min(n, NR >= 4 ? 256 : 512);  // <= 64 columns per in-flight load slot
+      blk += (long)t.njobs[i] * t.a0[i];
+      ymax = std::max(ymax, (t.nrhs[i] + NR - 1) / NR);
+    } else if (f.kind == 1) {
+      t.a0[i] = (t.nrhs[i] + f.tn - 1) / f.tn;
+      t.a1[i] = (n + kMmRows - 1) / kMmRows;
+      blk += (long)t.njobs[i] * t.a1[i] * t.a0[i];
+    } else {
+      t.a0[i] = (n + 63) / 64;
+      t.a1[i] = std::min(n, 2048 / NR);  // LDS = max(kc, 128) * NR complex <= 32 KiB
+      blk += (long)t.njobs[i] * t.a0[i];
+      ymax = std::max(ymax, (t.nrhs[i] + NR - 1) / NR);
+    }
+    kcmax = std::max(kcmax, t.a1[i]);
+  }
+  t.blk0[t.nseg] = (int32_t)blk;
+  if (blk <= 0) return hipSuccess;
+  if (blk > INT32_MAX) return hipErrorInvalidValue;
+  if (f.kind == 0) {
+    const size_t lds = 2 * (size_t)kcmax * NR * sizeof(Cx<T>);
+    const dim3 grid((unsigned)blk, (unsigned)ymax);
+    if (!f.pipe)  // every job one step: one LDS buffer
+      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, false, NS>), grid, dim3(kGvThreads), (uint32_t)lds / 2, st, ev0,
+                            ev1, 0, t, t.jobs[0]);
     else
-      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
-                            0, jobs, g.n, g.ntiles, g.kc, nrhs, ld, bases);
-  } else if (!F32 && g.mfma) {
-    const int ntl = (g.n + kMmRows - 1) / kMmRows;
-    const int tn = g.mfma;  // right-hand sides per workgroup tile: 16, 32 or 64
-    const int nrt = (nrhs + tn - 1) / tn;
-    const long tiles = (long)njobs * ntl * nrt;
-    const dim3 grid2((unsigned)tiles);
+      hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true, NS>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
+                            0, t, t.jobs[0]);
+  } else if (f.kind == 1) {
+    if constexpr (F32) return hipErrorInvalidValue;
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
-    const int ks = g.ks > 0 ? g.ks : tiles < 256 ? 4 : tiles < 512 ? 2 : 1;
-#define POLAR_MFMA64(TNV, KSV)                                                                                  \
-  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, jobs, g.n, \
-                        ntl, nrt, nrhs, ld, bases)
+    const int ks = f.ks > 0 ? f.ks : blk < 256 ? 4 : blk < 512 ? 2 : 1;
+    const dim3 grid2((unsigned)blk);
+#define POLAR_MFMA64(TNV, KSV)                                                                           \
+  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, t, \
+                        t.jobs[0])
     // (32- and 64-column tiles are only chosen for launches of >= 512 tiles: no split there)
-    if (tn == 64) {
+    if (f.tn == 64) {
       POLAR_MFMA64(64, 1);
-    } else if (tn == 32) {
+    } else if (f.tn == 32) {
       POLAR_MFMA64(32, 1);
     } else {
       if (ks == 4) POLAR_MFMA64(16, 4); else if (ks == 2) POLAR_MFMA64(16, 2); else POLAR_MFMA64(16, 1);
     }
 #undef POLAR_MFMA64
   } else {
-    const size_t lds = (size_t)std::max(g.kc, 128) * NR * sizeof(Cx<T>);
-    hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32>), grid, dim3(kThreads), (uint32_t)lds, st, ev0, ev1, 0, jobs,
-                          g.n, g.ntiles, g.kc, nrhs, ld, bases);
+    const size_t lds = (size_t)std::max(kcmax, 128) * NR * sizeof(Cx<T>);
+    hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32, NS>), dim3((unsigned)blk, (unsigned)ymax), dim3(kThreads),
+                          (uint32_t)lds, st, ev0, ev1, 0, t, t.jobs[0]);
   }
   return hipGetLastError();
 }
 
-template <bool F32>
-hipError_t launch_apply_t(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  switch (g.nr) {
-    case 1: return launch_apply_nr<1, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
-    case 2: return launch_apply_nr<2, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
-    case 4: return launch_apply_nr<4, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
-    case 8: return launch_apply_nr<8, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
-    case 16: return launch_apply_nr<16, F32>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+template <bool F32, int NS>
+hipError_t launch_apply_t(const SegTableT<NS>& t, const ApplyForm& f, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (f.nr) {
+    case 1: return launch_apply_form<1, F32, NS>(t, f, st, ev0, ev1);
+    case 2: return launch_apply_form<2, F32, NS>(t, f, st, ev0, ev1);
+    case 4: return launch_apply_form<4, F32, NS>(t, f, st, ev0, ev1);
+    case 8: return launch_apply_form<8, F32, NS>(t, f, st, ev0, ev1);
+    case 16: return launch_apply_form<16, F32, NS>(t, f, st, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1385,8 +1459,51 @@ hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const 
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
                               bool f32, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (njobs <= 0) return hipSuccess;
-  return f32 ? launch_apply_t<true>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1)
-             : launch_apply_t<false>(jobs, njobs, g, nrhs, ld, bases, st, ev0, ev1);
+  const ApplySeg sg{jobs, njobs, g.n, nrhs, ld, bases, nullptr, 0};
+  ApplyForm f{};
+  f.kind = g.gemv ? 0 : (!f32 && g.mfma) ? 1 : 2;
+  f.nr = g.nr;
+  f.tn = g.mfma;
+  f.ks = g.ks;
+  f.pipe = g.steps != 1;
+  const SegTableT<1> t = seg_table<1>(&sg, 1);
+  return f32 ? launch_apply_t<true, 1>(t, f, st, ev0, ev1) : launch_apply_t<false, 1>(t, f, st, ev0, ev1);
+}
+
+hipError_t launch_block_apply_segs(const ApplySeg* segs, int nseg, int maxterms, bool wide, bool f32,
+                                   hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (nseg <= 0) return hipSuccess;
+  if (nseg > kMaxSeg) return hipErrorInvalidValue;
+  int rmax = 0, rmin = INT32_MAX;
+  long rows = 0;
+  bool multi = wide || maxterms > 1;
+  for (int i = 0; i < nseg; ++i) {
+    if (segs[i].njobs <= 0 || segs[i].n <= 0 || segs[i].nrhs <= 0) return hipErrorInvalidValue;
+    rmax = std::max(rmax, segs[i].nrhs);
+    rmin = std::min(rmin, segs[i].nrhs);
+    rows += (long)segs[i].njobs * ((segs[i].n + 63) / 64);
+    multi = multi || segs[i].n > 256;  // a streaming chunk holds at most 256 columns
+  }
+  ApplyForm f{};
+  f.nr = rmax <= 1 ? 1 : rmax <= 2 ? 2 : rmax <= 4 ? 4 : rmax <= 8 ? 8 : 16;
+  f.pipe = multi;
+  if (rmax <= 4) {
+    f.kind = 0;
+  } else if (!f32) {
+    // the widest tile that still gives about two workgroups per CU, never wider
+    // than the fewest right-hand sides rounded up to 16 (the single launch's rule)
+    f.kind = 1;
+    f.tn = 16;
+    for (int tn : {64, 32})
+      if (tn <= 16 * ((rmin + 15) / 16) && rows * ((rmax + tn - 1) / tn) >= 512) {
+        f.tn = tn;
+        break;
+      }
+  } else {
+    f.kind = 2;
+  }
+  const SegTableT<kMaxSeg> t = seg_table<kMaxSeg>(segs, nseg);
+  return f32 ? launch_apply_t<true, kMaxSeg>(t, f, st, ev0, ev1) : launch_apply_t<false, kMaxSeg>(t, f, st, ev0, ev1);
 }
 
 

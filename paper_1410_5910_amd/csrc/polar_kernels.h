@@ -70,11 +70,72 @@ struct SplitCfg {
   int f16 = 0;     // planes and MFMA in float16 (1) or bfloat16 (0)
 };
 
+// One block-apply launch over up to NS segments: the job lists of several
+// problems, each with its own block size n, right-hand sides, vector stride
+// and base buffers, placed one after another along the grid's x dimension
+// (blocks blk0[s] .. blk0[s+1]-1 serve segment s).  a0/a1 hold the
+// per-segment tile counts of the kernel the table is built for.  Passed by
+// value: a kernel reads the fields of its segment straight from its
+// arguments.  Launches of one problem use NS = 1 (a small argument block, no
+// segment search) and also pass their job list as a separate restrict-
+// qualified argument, whose workgroup-uniform fields the compiler then reads
+// with scalar loads; merged launches use NS = kMaxSeg.
+constexpr int kMaxSeg = 8;
+template <int NS>
+struct SegTableT {
+  int32_t nseg;
+  int32_t blk0[NS + 1];
+  int32_t n[NS];
+  int32_t nrhs[NS];
+  int32_t njobs[NS];
+  int32_t a0[NS];
+  int32_t a1[NS];
+  int64_t ld[NS];
+  const Job* jobs[NS];
+  Bases bases[NS];
+  float2* part[NS];  // split forms: k-slice partial tiles of the segment
+};
+
+// The segment of x block `bid` (blk0 ascending, blk0[0] = 0) and the block's
+// index inside it.
+template <int NS>
+__device__ __forceinline__ int seg_of(const SegTableT<NS>& T, int& bid) {
+  if constexpr (NS == 1) {
+    return 0;
+  } else {
+    int s = 0;
+    for (int i = 1; i < T.nseg; ++i)
+      if (bid >= T.blk0[i]) s = i;
+    bid -= T.blk0[s];
+    return s;
+  }
+}
+
+// Host description of one segment of a merged launch.
+struct ApplySeg {
+  const Job* jobs;
+  int njobs;
+  int n;
+  int nrhs;
+  int64_t ld;
+  Bases bases;
+  float2* part;  // split forms: k-slice workspace of the segment (null: none)
+  size_t part_n; // its size in complex floats
+};
+
 // ---------------------------------------------------------------- block apply
 // ev0/ev1 (may be null): events stamped with the kernel's own start and end.
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld,
                               Bases bases, bool f32, hipStream_t st, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
+// The same over nseg <= kMaxSeg segments in one launch (float64 or float32
+// blocks).  The kernel form follows from the segments together: the
+// row-streaming kernel when every segment has at most 4 right-hand sides
+// (nr: the widest), otherwise the MFMA (float64) or register-blocked
+// (float32) form with tiles chosen for the launch's total size.  Every
+// segment's job arithmetic is that of a launch of the same form on its own.
+hipError_t launch_block_apply_segs(const ApplySeg* segs, int nseg, int maxterms, bool wide, bool f32,
+                                   hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Split-bfloat16 block apply (split.hip): the same job semantics as
 // launch_block_apply, with every M_t pointing at the split planes of a block
@@ -84,6 +145,11 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
 hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases,
                                     hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                                     float2* part = nullptr, SplitCfg cfg = SplitCfg{0, 0});
+// The split block apply over nseg <= kMaxSeg segments in one launch: the
+// rule's tile shape and k-slice count for the launch's total size (k-slices
+// only when every segment's workspace holds its partial tiles).
+hipError_t launch_block_apply_split_segs(const ApplySeg* segs, int nseg, int f16, hipStream_t st,
+                                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Interface Green's function rows of one layer from its extraction solve:
 // G[x'][(r - r0) NX + x] = W[(q NX + x') ld + r NX + x] * s(j, x') / s(r, x)
 // for r in [r0, r0 + nrows), with s(r, x) = ax[x] az[r] the diagonal that

@@ -120,6 +120,15 @@ size_t split_part_need(const pt_solver* S, const Launch& Lc, int nrhs, const Tun
 
 pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Bases b, const TuneCfg* tc) {
   if (Lc.njobs == 0) return PT_OK;
+  if (S->rec) {  // recorded: issued later, possibly in one launch with other problems'
+    Rec r;
+    r.Lc = Lc;
+    r.nrhs = nrhs;
+    r.ld = ld;
+    r.b = b;
+    S->rec->push_back(std::move(r));
+    return PT_OK;
+  }
   ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
   if (Lc.wide) g.steps = 0;  // wide terms: the streaming form's general (pipelined) variant
   if (tc && g.mfma && tc->tn) {
@@ -1533,7 +1542,7 @@ pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs) {
   const int64_t n = (int64_t)nrhs * S->Nt;
   const int64_t ld = S->Nt;
   if (nit == 0) {
-    HIPCHK(launch_copy(z, v, n, S->st));
+    GPU(S, launch_copy(z, v, n, st_));
     return PT_OK;
   }
   double2* prev = S->zeros.p;
@@ -1541,7 +1550,7 @@ pt_status precondition(pt_solver* S, const double2* v, double2* z, int nrhs) {
     double2* cur = (p == nit) ? z : ((p % 2) ? S->U1.p : S->U2.p);
     Bases b{{const_cast<double2*>(v), prev, cur, nullptr}};
     if (p == 1) {
-      HIPCHK(launch_copy(cur, v, n, S->st));
+      GPU(S, launch_copy(cur, v, n, st_));
     } else {
       PTCHK(run_apply(S, S->bterm, nrhs, ld, b));
     }
@@ -1565,13 +1574,13 @@ pt_status precondition_extrap(pt_solver* S, const double2* v, double2* z, int nr
   const int nit = S->opt.gs_iters;
   const int64_t n = (int64_t)nrhs * S->Nt;
   if (nit == 0) {
-    HIPCHK(launch_copy(z, v, n, S->st));
+    GPU(S, launch_copy(z, v, n, st_));
     return PT_OK;
   }
   const double2* prev = nullptr;
   for (int p = 1; p <= nit; ++p) {
     double2* cur = (p == nit) ? z : ((p % 2) ? S->U1.p : S->U2.p);
-    HIPCHK(launch_copy(cur, v, n, S->st));  // rows R does not touch keep v
+    GPU(S, launch_copy(cur, v, n, st_));  // rows R does not touch keep v
     if (prev) {
       Bases b{{const_cast<double2*>(v), const_cast<double2*>(prev), cur, nullptr}};
       PTCHK(run_apply(S, S->gsRX, nrhs, S->Nt, b));
@@ -1592,7 +1601,7 @@ pt_status system_M(pt_solver* S, const double2* v, double2* z, int nrhs) {
 }
 
 pt_status apply_dinv(pt_solver* S, const double2* v, double2* z, int nrhs) {
-  HIPCHK(launch_copy(z, v, (int64_t)nrhs * S->Nt, S->st));
+  GPU(S, launch_copy(z, v, (int64_t)nrhs * S->Nt, st_));
   Bases b{{const_cast<double2*>(v), S->zeros.p, z, nullptr}};
   for (const Launch& Lc : S->sweep) PTCHK(run_apply(S, Lc, nrhs, S->Nt, b));
   return PT_OK;
@@ -1636,10 +1645,10 @@ pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
   const Launch sub = layer_range(S, S->green_split, la, lb);
   const int n0 = S->nz_off[la], n1 = S->nz_off[lb + 1];
   if (lists)
-    HIPCHK(launch_nonzero_chunks(S->Bw.p, ld, cols, S->nz_in_off.p + n0, S->nz_in_k.p + n0, n1 - n0,
-                                 S->nz_list.p + (size_t)n0 * S->nz_stride, S->nz_stride, S->st));
+    GPU(S, launch_nonzero_chunks(S->Bw.p, ld, cols, S->nz_in_off.p + n0, S->nz_in_k.p + n0, n1 - n0,
+                                 S->nz_list.p + (size_t)n0 * S->nz_stride, S->nz_stride, st_));
   if (sub.njobs > 0) PTCHK(run_apply(S, sub, cols, ld, b));
-  if (S->prof && lists && sub.njobs > 0 && !S->pend.empty()) {
+  if (S->prof && !S->rec && lists && sub.njobs > 0 && !S->pend.empty()) {
     // count what the launch streamed: the chunks its lists kept
     std::vector<int32_t> h((size_t)(n1 - n0) * S->nz_stride);
     HIPCHK(hipMemcpyAsync(h.data(), S->nz_list.p + (size_t)n0 * S->nz_stride, h.size() * sizeof(int32_t),
@@ -1659,21 +1668,21 @@ pt_status green_presolve(pt_solver* S, int la, int lb, int cols, int64_t ld) {
     pp.flops = 8.0 * mat * cols;
   }
   const int e0 = S->gsum_off[la], e1 = S->gsum_off[lb + 1];
-  HIPCHK(launch_sum_rows(S->W.p, ld, S->NX, S->gsum_dst.p + e0, S->gsum_src.p + e0, S->gsum_cnt.p + e0, e1 - e0,
-                         cols, S->st));
+  GPU(S, launch_sum_rows(S->W.p, ld, S->NX, S->gsum_dst.p + e0, S->gsum_src.p + e0, S->gsum_cnt.p + e0, e1 - e0,
+                         cols, st_));
   if (ext.njobs > 0) PTCHK(run_apply(S, ext, cols, ld, b));
   return PT_OK;
 }
 
 pt_status newton(pt_solver* S, const double2* f, int nrhs) {
-  HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
+  GPU(S, launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, st_));
   if (use_green(S, nrhs)) return green_presolve(S, 0, S->L - 1, nrhs, (int64_t)S->sumR * S->NX);
   return run_local(S, S->fwd_win, S->bwd_pre, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p);
 }
 
 // all sources vanish: s = 0
 pt_status fail_zero(pt_solver* S, double2* s, int nrhs) {
-  HIPCHK(launch_zero(s, (int64_t)nrhs * S->Nt, S->st));
+  GPU(S, launch_zero(s, (int64_t)nrhs * S->Nt, st_));
   return PT_OK;
 }
 
@@ -1688,12 +1697,21 @@ pt_status fail_zero(pt_solver* S, double2* s, int nrhs) {
 // stay nonzero in float64 tens of widths from their centre).
 constexpr double kTouchRel2 = 0x1p-160;  // (2^-80)^2, on squared magnitudes
 
-pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
+// First half: the largest source magnitude of every (source, layer) to the
+// host (S->h_act); the second half reads it once the stream has got there.
+pt_status trace_rhs_begin(pt_solver* S, const double2* f, int nrhs) {
   const int L = S->L;
-  hipStream_t st = S->st;
-  HIPCHK(launch_source_activity(f, S->act.p, S->lay_own_start.p, S->lay_n_own.p, L, S->NZ, S->NX, nrhs, st));
-  HIPCHK(hipMemcpyAsync(S->h_act, S->act.p, (size_t)nrhs * L * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  GPU(S, launch_source_activity(f, S->act.p, S->lay_own_start.p, S->lay_n_own.p, L, S->NZ, S->NX, nrhs, st_));
+  GPU(S, hipMemcpyAsync(S->h_act, S->act.p, (size_t)nrhs * L * sizeof(double), hipMemcpyDeviceToHost, st_));
+  return PT_OK;
+}
+
+// Second half: slot tables from S->h_act, the pre-solve and the gather.  The
+// slot tables are uploaded from pinned memory the next call rewrites
+// (*uploads set): the caller lets the stream pass the uploads before that.
+pt_status trace_rhs_end(pt_solver* S, const double2* f, double2* s, int nrhs, bool* uploads) {
+  const int L = S->L;
+  *uploads = false;
   int32_t* slot_rhs = S->h_slot;                       // [l][j]
   int32_t* rhs_slot = S->h_slot + (size_t)L * nrhs;    // [r][l]
   std::vector<int> cnt(L, 0);
@@ -1722,8 +1740,8 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
   if (m >= nrhs && la == 0 && lb == L - 1) {  // every layer sees every source: the dense pre-solve
     S->last_slots = nrhs;
     PTCHK(newton(S, f, nrhs));
-    HIPCHK(launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX,
-                            S->Nt, nrhs, 0, st));
+    GPU(S, launch_trace_map(S->W.p, s, nullptr, S->g_seg.p, S->g_row.p, nullptr, S->n_gather, 0, S->sumR, S->NX,
+                            S->Nt, nrhs, 0, st_));
     return PT_OK;
   }
   S->last_slots = m;
@@ -1734,20 +1752,29 @@ pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
       const int j = rhs_slot[(size_t)r * L + l];
       if (j >= 0) slot_rhs[(size_t)l * m + j] = r;
     }
-  HIPCHK(hipMemcpyAsync(S->slot_rhs.p, slot_rhs, (size_t)L * m * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(S->rhs_slot.p, rhs_slot, (size_t)nrhs * L * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  *uploads = true;
+  GPU(S, hipMemcpyAsync(S->slot_rhs.p, slot_rhs, (size_t)L * m * sizeof(int32_t), hipMemcpyHostToDevice, st_));
+  GPU(S, hipMemcpyAsync(S->rhs_slot.p, rhs_slot, (size_t)nrhs * L * sizeof(int32_t), hipMemcpyHostToDevice, st_));
   const int64_t ld = (int64_t)S->sumR * S->NX;
-  HIPCHK(launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
-                              S->h * S->h, st));
+  GPU(S, launch_scatter_slots(f, S->Bw.p, S->rowmap.p, S->row_layer.p, S->slot_rhs.p, m, S->sumR, S->NZ, S->NX,
+                              S->h * S->h, st_));
   if (use_green(S, m)) {
     PTCHK(green_presolve(S, la, lb, m, ld));
   } else {
     PTCHK(run_local_layers(S, S->fwd_win, S->bwd_pre, la, lb, m, ld, S->W.p, S->Bw.p));
   }
-  HIPCHK(launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
-                             S->sumR, S->NX, S->Nt, nrhs, st));
+  GPU(S, launch_gather_slots(S->W.p, s, S->g_seg.p, S->g_row.p, S->row_layer.p, S->rhs_slot.p, S->n_gather, L,
+                             S->sumR, S->NX, S->Nt, nrhs, st_));
+  return PT_OK;
+}
+
+pt_status trace_rhs(pt_solver* S, const double2* f, double2* s, int nrhs) {
+  PTCHK(trace_rhs_begin(S, f, nrhs));
+  HIPCHK(hipStreamSynchronize(S->st));
+  bool uploads = false;
+  PTCHK(trace_rhs_end(S, f, s, nrhs, &uploads));
   // the pinned slot tables are rewritten by the next call: finish their uploads first
-  HIPCHK(hipStreamSynchronize(st));
+  if (uploads) HIPCHK(hipStreamSynchronize(S->st));
   return PT_OK;
 }
 
@@ -1758,19 +1785,19 @@ pt_status reconstruct(pt_solver* S, const double2* f, const double2* x, double2*
   if (S->rec_direct && !overlap && (x || S->n_rec_rhs == 0)) {
     const int64_t ld = (int64_t)S->NZ * S->NX;
     if (S->n_rec_rhs > 0)
-      HIPCHK(launch_rec_rhs(S->W.p, f, x, S->rr_dst.p, S->rr_src.p, S->rr_seg.p, S->rr_sign.p, S->n_rec_rhs, S->NX, ld,
-                            S->Nt, (int64_t)2 * (S->L - 1) * S->NX, S->h * S->h, nrhs, S->st));
+      GPU(S, launch_rec_rhs(S->W.p, f, x, S->rr_dst.p, S->rr_src.p, S->rr_seg.p, S->rr_sign.p, S->n_rec_rhs, S->NX, ld,
+                            S->Nt, (int64_t)2 * (S->L - 1) * S->NX, S->h * S->h, nrhs, st_));
     Bases b{{S->W.p, u, const_cast<double2*>(f), nullptr}};
     for (const Launch& Lc : S->fwd_rec) PTCHK(run_apply(S, Lc, nrhs, ld, b));
     for (const Launch& Lc : S->bwd_rec2) PTCHK(run_apply(S, Lc, nrhs, ld, b));
     return PT_OK;
   }
-  HIPCHK(launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, S->st));
+  GPU(S, launch_scatter_source(f, S->Bw.p, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->h * S->h, st_));
   if (S->L >= 2)
-    HIPCHK(launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
-                            S->Nt, nrhs, (int64_t)2 * (S->L - 1) * S->NX, S->st));
+    GPU(S, launch_trace_map(S->Bw.p, nullptr, x, S->f_seg.p, S->f_row.p, S->f_sign.p, S->n_force, 1, S->sumR, S->NX,
+                            S->Nt, nrhs, (int64_t)2 * (S->L - 1) * S->NX, st_));
   PTCHK(run_local(S, S->fwd_win, S->bwd_rec, nrhs, (int64_t)S->sumR * S->NX, S->W.p, S->Bw.p));
-  HIPCHK(launch_gather_owned(S->W.p, u, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, S->st));
+  GPU(S, launch_gather_owned(S->W.p, u, S->rowmap.p, S->sumR, S->NZ, S->NX, nrhs, st_));
   return PT_OK;
 }
 
@@ -1814,45 +1841,65 @@ void drop_graphs(pt_solver* S) {
 }
 
 // Flexible GMRES (right preconditioning, classical Gram-Schmidt applied twice,
-// x0 = 0, no restart) on A x = s for nrhs independent right-hand sides.
-pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned) {
-  hipStream_t st = S->st;
+// x0 = 0, no restart) on A x = s for nrhs independent right-hand sides, in
+// three parts: the start (v_0 = s / ||s||), iteration j (which leaves the
+// per-source convergence flags in S->h_done once the stream has got there)
+// and the end (x from the least-squares solutions).
+pt_status fgmres_begin(pt_solver* S, int nrhs, bool learned) {
+  const int64_t N = S->Nt;
+  const int m = S->opt.maxit;
+  GPU(S, launch_knorm(S->s.p, S->beta.p, nrhs, N, st_));
+  GPU(S, launch_kscale(S->V.p, S->s.p, S->beta.p, nrhs, N, st_));
+  GPU(S, launch_kinit(S->g.p, S->beta.p, S->done.p, S->iters.p, S->est.p, m, nrhs, st_));
+  if (learned) PTCHK(learned_begin(S, nrhs));
+  return PT_OK;
+}
+
+pt_status fgmres_iter(pt_solver* S, int nrhs, int j, double tol, bool learned) {
   const int64_t N = S->Nt;
   const int m = S->opt.maxit;
   const size_t vs = (size_t)nrhs * N;
-  HIPCHK(launch_knorm(S->s.p, S->beta.p, nrhs, N, st));
-  HIPCHK(launch_kscale(S->V.p, S->s.p, S->beta.p, nrhs, N, st));
-  HIPCHK(launch_kinit(S->g.p, S->beta.p, S->done.p, S->iters.p, S->est.p, m, nrhs, st));
-  if (learned) PTCHK(learned_begin(S, nrhs));
+  double2* vj = S->V.p + (size_t)j * vs;
+  double2* zj = S->Z.p + (size_t)j * vs;
+  const bool augment = learned && S->learned_mode == PT_LEARN_AUGMENT;
+  if (augment && (j & 1)) {
+    PTCHK(learned_direction(S, zj, nrhs));
+  } else {
+    PTCHK(system_M(S, vj, zj, nrhs));
+  }
+  if (learned && !augment) {
+    PTCHK(learned_step(S, vj, zj, S->tmp.p, nrhs));
+  } else {
+    PTCHK(system_A(S, zj, S->tmp.p, nrhs));
+    if (augment && !(j & 1)) PTCHK(learned_residual(S, vj, S->tmp.p, nrhs));
+  }
+  GPU(S, launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st_));
+  for (int pass = 0; pass < 2; ++pass) {
+    GPU(S, launch_kdot(S->V.p, S->tmp.p, S->hbuf.p, j + 1, nrhs, N, st_));
+    GPU(S, launch_kupdate(S->V.p, S->tmp.p, S->hbuf.p, S->hacc.p, j + 1, nrhs, N, st_));
+  }
+  GPU(S, launch_knorm(S->tmp.p, S->nrm.p, nrhs, N, st_));
+  GPU(S, launch_kscale(S->V.p + (size_t)(j + 1) * vs, S->tmp.p, S->nrm.p, nrhs, N, st_));
+  GPU(S, launch_givens(S->Hc.p, S->hacc.p, S->nrm.p, S->cs.p, S->sn.p, S->g.p, S->est.p, S->beta.p, S->iters.p,
+                       S->done.p, tol, j, m, nrhs, st_));
+  GPU(S, hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  return PT_OK;
+}
+
+pt_status fgmres_end(pt_solver* S, int nrhs) {
+  const int m = S->opt.maxit;
+  GPU(S, launch_ksolve(S->Hc.p, S->g.p, S->y.p, S->iters.p, m, nrhs, st_));
+  GPU(S, launch_kcombine(S->Z.p, S->y.p, S->iters.p, S->x.p, m, nrhs, S->Nt, st_));
+  return PT_OK;
+}
+
+pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learned) {
+  hipStream_t st = S->st;
+  const int m = S->opt.maxit;
+  PTCHK(fgmres_begin(S, nrhs, learned));
   all_conv = false;
   // the launch sequence of iteration j (captured into a graph when enabled)
-  auto iteration = [&](int j) -> pt_status {
-    double2* vj = S->V.p + (size_t)j * vs;
-    double2* zj = S->Z.p + (size_t)j * vs;
-    const bool augment = learned && S->learned_mode == PT_LEARN_AUGMENT;
-    if (augment && (j & 1)) {
-      PTCHK(learned_direction(S, zj, nrhs));
-    } else {
-      PTCHK(system_M(S, vj, zj, nrhs));
-    }
-    if (learned && !augment) {
-      PTCHK(learned_step(S, vj, zj, S->tmp.p, nrhs));
-    } else {
-      PTCHK(system_A(S, zj, S->tmp.p, nrhs));
-      if (augment && !(j & 1)) PTCHK(learned_residual(S, vj, S->tmp.p, nrhs));
-    }
-    HIPCHK(launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st));
-    for (int pass = 0; pass < 2; ++pass) {
-      HIPCHK(launch_kdot(S->V.p, S->tmp.p, S->hbuf.p, j + 1, nrhs, N, st));
-      HIPCHK(launch_kupdate(S->V.p, S->tmp.p, S->hbuf.p, S->hacc.p, j + 1, nrhs, N, st));
-    }
-    HIPCHK(launch_knorm(S->tmp.p, S->nrm.p, nrhs, N, st));
-    HIPCHK(launch_kscale(S->V.p + (size_t)(j + 1) * vs, S->tmp.p, S->nrm.p, nrhs, N, st));
-    HIPCHK(launch_givens(S->Hc.p, S->hacc.p, S->nrm.p, S->cs.p, S->sn.p, S->g.p, S->est.p, S->beta.p, S->iters.p,
-                         S->done.p, tol, j, m, nrhs, st));
-    HIPCHK(hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    return PT_OK;
-  };
+  auto iteration = [&](int j) -> pt_status { return fgmres_iter(S, nrhs, j, tol, learned); };
   // (the tolerance is a kernel argument baked into a graph: graphs only for the solver's own tol)
   const bool graphs = S->opt.use_graph && !learned && !S->prof && st != nullptr && !S->graph_failed &&
                       tol == S->opt.tol;
@@ -1870,9 +1917,7 @@ pt_status fgmres(pt_solver* S, int nrhs, bool& all_conv, double tol, bool learne
       break;
     }
   }
-  HIPCHK(launch_ksolve(S->Hc.p, S->g.p, S->y.p, S->iters.p, m, nrhs, st));
-  HIPCHK(launch_kcombine(S->Z.p, S->y.p, S->iters.p, S->x.p, m, nrhs, N, st));
-  return PT_OK;
+  return fgmres_end(S, nrhs);
 }
 
 pt_status check_nrhs(const pt_solver* S, int nrhs) {
@@ -2048,6 +2093,341 @@ pt_status pt_gauss_seidel(pt_solver* S, int32_t nrhs, const double* f, double* u
   return conv ? PT_OK : fail(PT_ENOCONV, "Gauss-Seidel reached maxit before tol");
 }
 
+// ---------------------------------------------------------------------------
+// several problems in one launch sequence
+// ---------------------------------------------------------------------------
+// Block applies of different problems share a launch when they use the same
+// kernel family: same block storage (float64, float32 or split planes of one
+// element type) and the same side of the form's right-hand-side threshold.
+// Compressed blocks are launched alone.
+int merge_key(const pt_solver* S, const Rec& r) {
+  if (r.Lc.plr) return -1;
+  if (r.Lc.split) return 1 + (S->split_f16 ? 2 : 0) + (r.nrhs > 16 ? 1 : 0);
+  return 5 + (S->f32 ? 2 : 0) + (r.nrhs > 4 ? 1 : 0);
+}
+
+// One block apply for each problem of `grp` (its next recorded operation), in
+// one launch (several problems) or with the problem's own tuned shape (one).
+pt_status issue_applies(pt_solver* const* s, const std::vector<std::vector<Rec>>& recs,
+                        const std::vector<size_t>& cur, const std::vector<int>& grp, hipStream_t st) {
+  if (grp.size() == 1) {
+    const int p = grp[0];
+    const Rec& r = recs[p][cur[p]];
+    return run_apply(s[p], r.Lc, r.nrhs, r.ld, r.b);
+  }
+  ApplySeg segs[kMaxSeg];
+  int maxterms = 0;
+  bool wide = false;
+  for (size_t i = 0; i < grp.size(); ++i) {
+    const pt_solver* S = s[grp[i]];
+    const Rec& r = recs[grp[i]][cur[grp[i]]];
+    segs[i] = ApplySeg{S->jobs.p + r.Lc.job0, r.Lc.njobs, S->NX, r.nrhs, r.ld, r.b, S->part.p, S->part.n};
+    maxterms = std::max(maxterms, r.Lc.maxterms);
+    wide = wide || r.Lc.wide;
+  }
+  pt_solver* S0 = s[grp[0]];
+  const Rec& r0 = recs[grp[0]][cur[grp[0]]];
+  const int n = (int)grp.size();
+  // live timing: the merged launch is counted once, by the group's first
+  // solver, in the class of its first problem, with every segment's bytes and flops
+  int slot = -1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (S0->prof) {
+    if (S0->ev_next >= kEventSlots) PTCHK(prof_harvest(S0));
+    slot = S0->ev_next++;
+    e0 = S0->ev[2 * slot];
+    e1 = S0->ev[2 * slot + 1];
+  }
+  if (r0.Lc.split) {
+    HIPCHK(launch_block_apply_split_segs(segs, n, S0->split_f16 ? 1 : 0, st, e0, e1));
+  } else {
+    HIPCHK(launch_block_apply_segs(segs, n, maxterms, wide, S0->f32, st, e0, e1));
+  }
+  if (S0->prof) {
+    double bytes = 0, flops = 0;
+    for (int p : grp) {
+      const Rec& r = recs[p][cur[p]];
+      const double es = r.Lc.split ? 8.0 : s[p]->f32 ? 8.0 : 16.0;
+      bytes += r.Lc.mat_elems * es + r.Lc.vec_elems_rhs * r.nrhs * 16.0;
+      flops += 8.0 * r.Lc.mat_elems * r.nrhs;
+    }
+    S0->pend.push_back(ProfPending{slot, r0.Lc.cls, bytes, flops});
+  }
+  return PT_OK;
+}
+
+// Issue the recorded operations of every problem on stream st, each
+// problem's in its order: rounds take the next operation of every problem;
+// any other stream operation is issued first, block applies wait for a round
+// where every problem still recording has one, and then share launches.
+pt_status run_recorded(pt_solver* const* s, std::vector<std::vector<Rec>>& recs, hipStream_t st,
+                       const std::vector<hipStream_t>* lanes = nullptr) {
+  const int P = (int)recs.size();
+  std::vector<size_t> cur(P, 0);
+  if (lanes) {
+    // every problem on its own stream, its operations issued in turns
+    for (bool more = true; more;) {
+      more = false;
+      for (int p = 0; p < P; ++p) {
+        if (cur[p] >= recs[p].size()) continue;
+        more = true;
+        const Rec& r = recs[p][cur[p]++];
+        if (r.fn) {
+          const hipError_t e = r.fn((*lanes)[p]);
+          if (e != hipSuccess) return fail(PT_EHIP, std::string("problem ") + std::to_string(p) + ": " +
+                                                        hipGetErrorString(e));
+        } else {
+          const hipStream_t keep = s[p]->st;
+          s[p]->st = (*lanes)[p];
+          const pt_status rc = run_apply(s[p], r.Lc, r.nrhs, r.ld, r.b);
+          s[p]->st = keep;
+          PTCHK(rc);
+        }
+      }
+    }
+    for (auto& v : recs) v.clear();
+    return PT_OK;
+  }
+  std::vector<int> pend, grp;
+  std::vector<char> taken(P);
+  for (;;) {
+    bool any = false, other = false;
+    for (int p = 0; p < P; ++p) {
+      if (cur[p] >= recs[p].size()) continue;
+      any = true;
+      Rec& r = recs[p][cur[p]];
+      if (!r.fn) continue;
+      const hipError_t e = r.fn(st);
+      if (e != hipSuccess) return fail(PT_EHIP, std::string("problem ") + std::to_string(p) + ": " +
+                                                    hipGetErrorString(e));
+      ++cur[p];
+      other = true;
+    }
+    if (!any) break;
+    if (other) continue;
+    pend.clear();
+    for (int p = 0; p < P; ++p)
+      if (cur[p] < recs[p].size()) pend.push_back(p);
+    std::fill(taken.begin(), taken.end(), 0);
+    for (size_t i = 0; i < pend.size(); ++i) {
+      const int p = pend[i];
+      if (taken[p]) continue;
+      const int key = merge_key(s[p], recs[p][cur[p]]);
+      grp.assign(1, p);
+      taken[p] = 1;
+      for (size_t k = i + 1; k < pend.size() && key >= 0 && (int)grp.size() < kMaxSeg; ++k) {
+        const int q = pend[k];
+        if (!taken[q] && merge_key(s[q], recs[q][cur[q]]) == key) {
+          grp.push_back(q);
+          taken[q] = 1;
+        }
+      }
+      PTCHK(issue_applies(s, recs, cur, grp, st));
+    }
+    for (int p : pend) ++cur[p];
+  }
+  for (auto& v : recs) v.clear();
+  return PT_OK;
+}
+
+// pt_solve for several problems in lockstep on one stream (the first
+// solver's): each stage (inputs and source activity; pre-solve, trace
+// right-hand side and GMRES start; one GMRES iteration of every problem not
+// yet converged; solution and reconstruction; convergence data) is recorded
+// for every problem, then issued with the block applies of different problems
+// sharing launches.  The host synchronises once per stage for all problems.
+// Every problem's arithmetic is that of pt_solve, up to the launch shapes of
+// the merged launches (the rules' shapes for the merged size).
+pt_status solve_merged(int P, pt_solver* const* s, const int32_t* nrhs, const double* const* f, double* const* u,
+                       int32_t on_device, pt_rhs_info* const* info) {
+  hipStream_t st = s[0]->st;
+  for (int p = 0; p < P; ++p) HIPCHK(hipStreamSynchronize(s[p]->st));  // earlier work on every stream
+  struct Prob {
+    const double2* fd;
+    double2* ud;
+    hipStream_t own;
+    int j = 0;
+    bool live = false;
+    std::vector<double> nr, be, es;
+    std::vector<int32_t> it, dn;
+  };
+  std::vector<Prob> q(P);
+  for (int p = 0; p < P; ++p) {
+    q[p].own = s[p]->st;
+    s[p]->st = st;
+  }
+  std::vector<std::vector<Rec>> recs(P);
+  // The long dependent chains of the pre-solve and the reconstruction run on
+  // the problems' own streams when they are distinct ("lanes"), so one
+  // problem's chain overlaps another's; the GMRES iterations share launches.
+  std::vector<hipStream_t> lanes(P);
+  bool use_lanes = true;
+  for (int p = 0; p < P; ++p) {
+    lanes[p] = q[p].own;
+    for (int k = 0; k < p; ++k) use_lanes = use_lanes && lanes[k] != lanes[p];
+  }
+  std::vector<hipEvent_t> evs(P + 1, nullptr);
+  // every exit gives the solvers back their streams, stops recording and frees the events
+  struct Restore {
+    pt_solver* const* s;
+    std::vector<Prob>& q;
+    std::vector<hipEvent_t>& evs;
+    ~Restore() {
+      for (size_t p = 0; p < q.size(); ++p) {
+        s[p]->st = q[p].own;
+        s[p]->rec = nullptr;
+      }
+      for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } restore{s, q, evs};
+  if (use_lanes)
+    for (auto& e : evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto record = [&](int p) { s[p]->rec = &recs[p]; };
+  auto issue = [&]() -> pt_status {
+    for (int p = 0; p < P; ++p) s[p]->rec = nullptr;
+    return run_recorded(s, recs, st);
+  };
+  // a stage on the lanes: they start after the work issued on st and st waits for them
+  auto issue_lanes = [&]() -> pt_status {
+    if (!use_lanes) return issue();
+    for (int p = 0; p < P; ++p) s[p]->rec = nullptr;
+    HIPCHK(hipEventRecord(evs[P], st));
+    for (int p = 0; p < P; ++p)
+      if (lanes[p] != st) HIPCHK(hipStreamWaitEvent(lanes[p], evs[P], 0));
+    PTCHK(run_recorded(s, recs, st, &lanes));
+    for (int p = 0; p < P; ++p)
+      if (lanes[p] != st) {
+        HIPCHK(hipEventRecord(evs[p], lanes[p]));
+        HIPCHK(hipStreamWaitEvent(st, evs[p], 0));
+      }
+    return PT_OK;
+  };
+  // inputs on the device and the sources' activity per layer
+  for (int p = 0; p < P; ++p) {
+    pt_solver* S = s[p];
+    const size_t nv = (size_t)nrhs[p] * S->NZ * S->NX;
+    q[p].fd = (const double2*)f[p];
+    q[p].ud = (double2*)u[p];
+    record(p);
+    if (!on_device) {
+      const double* fh = f[p];
+      GPU(S, hipMemcpyAsync(S->fio.p, fh, nv * sizeof(double2), hipMemcpyHostToDevice, st_));
+      q[p].fd = S->fio.p;
+      q[p].ud = S->uio.p;
+    }
+    if (S->L >= 2) PTCHK(trace_rhs_begin(S, q[p].fd, nrhs[p]));
+  }
+  PTCHK(issue_lanes());
+  HIPCHK(hipStreamSynchronize(st));
+  // pre-solves, trace right-hand sides, GMRES starts
+  for (int p = 0; p < P; ++p) {
+    pt_solver* S = s[p];
+    if (S->L < 2) continue;
+    record(p);
+    bool uploads = false;
+    PTCHK(trace_rhs_end(S, q[p].fd, S->s.p, nrhs[p], &uploads));
+    if (S->opt.closure == 1)  // extrapolation rows: zero right-hand side
+      GPU(S, launch_zero_extrap_rows(S->s.p, S->L, S->NX, S->Nt, nrhs[p], st_));
+    PTCHK(fgmres_begin(S, nrhs[p], false));
+    q[p].live = S->opt.maxit > 0;
+  }
+  PTCHK(issue_lanes());
+  // GMRES iterations in lockstep; a problem leaves when all its sources converged
+  for (;;) {
+    bool any = false;
+    for (int p = 0; p < P; ++p) {
+      if (!q[p].live) continue;
+      any = true;
+      record(p);
+      PTCHK(fgmres_iter(s[p], nrhs[p], q[p].j, s[p]->opt.tol, false));
+    }
+    if (!any) break;
+    PTCHK(issue());
+    HIPCHK(hipStreamSynchronize(st));
+    for (int p = 0; p < P; ++p) {
+      if (!q[p].live) continue;
+      bool all = true;
+      for (int r = 0; r < nrhs[p]; ++r) all = all && s[p]->h_done[r];
+      if (all || ++q[p].j >= s[p]->opt.maxit) q[p].live = false;
+    }
+  }
+  // solutions and fields
+  for (int p = 0; p < P; ++p) {
+    pt_solver* S = s[p];
+    const size_t nv = (size_t)nrhs[p] * S->NZ * S->NX;
+    record(p);
+    if (S->L >= 2) PTCHK(fgmres_end(S, nrhs[p]));
+    PTCHK(reconstruct(S, q[p].fd, S->L >= 2 ? S->x.p : nullptr, q[p].ud, nrhs[p]));
+    if (!on_device) {
+      double* uh = u[p];
+      const double2* ud = q[p].ud;
+      GPU(S, hipMemcpyAsync(uh, ud, nv * sizeof(double2), hipMemcpyDeviceToHost, st_));
+    }
+  }
+  PTCHK(issue_lanes());
+  // convergence data, as pt_solve decides it
+  for (int p = 0; p < P; ++p) {
+    pt_solver* S = s[p];
+    const int n = nrhs[p];
+    Prob& w = q[p];
+    w.nr.assign(n, 0.0);
+    w.be.assign(n, 0.0);
+    w.es.assign(n, 0.0);
+    w.it.assign(n, 0);
+    w.dn.assign(n, 0);
+    double* nr = w.nr.data();
+    double* be = w.be.data();
+    double* es = w.es.data();
+    int32_t* it = w.it.data();
+    int32_t* dn = w.dn.data();
+    record(p);
+    if (S->L == 1) {
+      const double2* ud = w.ud;
+      GPU(S, launch_knorm(ud, S->nrm.p, n, (int64_t)S->NZ * S->NX, st_));
+      GPU(S, hipMemcpyAsync(nr, S->nrm.p, n * 8, hipMemcpyDeviceToHost, st_));
+      continue;
+    }
+    if (info && info[p]) {  // true residual ||s - A x|| / ||s|| in float64
+      PTCHK(system_A(S, S->x.p, S->tmp.p, n));
+      GPU(S, launch_add(S->tmp.p, S->s.p, S->tmp.p, -1.0, (int64_t)n * S->Nt, st_));
+      GPU(S, launch_knorm(S->tmp.p, S->nrm.p, n, S->Nt, st_));
+      GPU(S, hipMemcpyAsync(nr, S->nrm.p, n * 8, hipMemcpyDeviceToHost, st_));
+      GPU(S, hipMemcpyAsync(it, S->iters.p, n * 4, hipMemcpyDeviceToHost, st_));
+    }
+    GPU(S, hipMemcpyAsync(be, S->beta.p, n * 8, hipMemcpyDeviceToHost, st_));
+    GPU(S, hipMemcpyAsync(es, S->est.p, n * 8, hipMemcpyDeviceToHost, st_));
+    GPU(S, hipMemcpyAsync(dn, S->done.p, n * 4, hipMemcpyDeviceToHost, st_));
+  }
+  PTCHK(issue());
+  HIPCHK(hipStreamSynchronize(st));
+  int bad = -1;
+  for (int p = 0; p < P; ++p) {
+    const Prob& w = q[p];
+    pt_rhs_info* inf = info ? info[p] : nullptr;
+    bool conv = true;
+    for (int r = 0; r < nrhs[p]; ++r) {
+      if (s[p]->L == 1) {
+        // one local solve, no iteration: the field is finite or the source was not
+        const bool ok = std::isfinite(w.nr[r]);
+        conv = conv && ok;
+        if (inf) inf[r] = pt_rhs_info{0, ok ? 1 : 0, ok ? 0.0 : std::nan(""), ok ? 0.0 : std::nan(""), 0, 0};
+        continue;
+      }
+      // a source that is not finite stops at once and is reported not converged
+      const double rr = w.be[r] > 0 ? w.nr[r] / w.be[r] : (w.be[r] == 0.0 ? 0.0 : std::nan(""));
+      const bool ok = w.dn[r] && std::isfinite(w.es[r]) && std::isfinite(w.be[r]) && (!inf || std::isfinite(rr));
+      conv = conv && ok;
+      if (inf) inf[r] = pt_rhs_info{w.it[r], ok ? 1 : 0, w.es[r], rr, 0, 0};
+    }
+    if (!conv && bad < 0) bad = p;
+  }
+  if (bad >= 0)
+    return fail(PT_ENOCONV, "problem " + std::to_string(bad) +
+                                ": GMRES did not converge for every source (maxit, or a source not finite)");
+  return PT_OK;
+}
+
 pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
                          double* const* u, int32_t on_device, pt_rhs_info* const* info) {
   if (nprob < 0 || (nprob > 0 && (!s || !nrhs || !f || !u))) return fail(PT_EINVAL, "null argument");
@@ -2070,6 +2450,23 @@ pt_status pt_solve_batch(int32_t nprob, pt_solver* const* s, const int32_t* nrhs
   for (int i = 0; i < nprob; ++i)
     if (st[i] != PT_OK) return fail(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
   return PT_OK;
+}
+
+pt_status pt_solve_batch_merged(int32_t nprob, pt_solver* const* s, const int32_t* nrhs, const double* const* f,
+                                double* const* u, int32_t on_device, pt_rhs_info* const* info) {
+  if (nprob < 0 || (nprob > 0 && (!s || !nrhs || !f || !u))) return fail(PT_EINVAL, "null argument");
+  for (int i = 0; i < nprob; ++i) {
+    if (!s[i]) return fail(PT_EINVAL, "null solver");
+    for (int j = 0; j < i; ++j)
+      if (s[j] == s[i]) return fail(PT_EINVAL, "a solver appears twice in the batch");
+    if (s[i]->device != s[0]->device) return fail(PT_EINVAL, "the solvers of a merged batch share one device");
+    if (s[i]->learned) return fail(PT_EINVAL, "problem " + std::to_string(i) + ": a learned stage is solved alone");
+    if (check_nrhs(s[i], nrhs[i]) != PT_OK) return fail(PT_EINVAL, "problem " + std::to_string(i) + ": " + g_err);
+    if (!f[i] || !u[i]) return fail(PT_EINVAL, "problem " + std::to_string(i) + ": null field");
+  }
+  if (nprob == 0) return PT_OK;
+  HIPCHK(hipSetDevice(s[0]->device));
+  return solve_merged(nprob, s, nrhs, f, u, on_device, info);
 }
 
 pt_status pt_setup_batch(int32_t nprob, const pt_problem* probs, const pt_options* opts, void* const* hip_streams,

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <thread>
@@ -30,6 +31,13 @@ inline pt_status fail(pt_status s, const std::string& msg) {
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
     if (e_ != hipSuccess) return fail(PT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// GPU(S, expr): expr issued on S's stream (written st_ in expr), or recorded
+#define GPU(S, expr)                                                                                        \
+  do {                                                                                                      \
+    pt_status g_ = gpu_op((S)->rec, (S)->st, #expr, [=](hipStream_t st_) -> hipError_t { return expr; }); \
+    if (g_ != PT_OK) return g_;                                                                             \
   } while (0)
 
 #define PTCHK(expr)               \
@@ -85,6 +93,33 @@ struct ProfPending {
   int cls;
   double bytes, flops;
 };
+
+// One GPU operation of a recorded stage (a merged solve of several problems
+// records each problem's operations, then issues them together): a block
+// apply, which may share one launch with other problems' applies, or any
+// other stream operation (fn).
+struct Rec {
+  std::function<hipError_t(hipStream_t)> fn;  // empty: a block apply
+  Launch Lc;
+  int nrhs = 0;
+  int64_t ld = 0;
+  Bases b{};
+};
+
+// Issue a stream operation on the solver's stream, or record it while the
+// solver records a stage; `f` takes the stream to issue on.
+template <typename F>
+inline pt_status gpu_op(std::vector<Rec>* rec, hipStream_t st, const char* what, F&& f) {
+  if (rec) {
+    Rec r;
+    r.fn = std::forward<F>(f);
+    rec->push_back(std::move(r));
+    return PT_OK;
+  }
+  const hipError_t e = f(st);
+  if (e != hipSuccess) return fail(PT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return PT_OK;
+}
 
 // a tuned launch shape (0: the built-in rule)
 struct TuneCfg {
@@ -196,6 +231,7 @@ struct pt_solver {
   // captured GMRES iterations: (nrhs, iteration) -> executable graph
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   bool graph_failed = false;  // capture did not work on this stream: plain launches
+  std::vector<Rec>* rec = nullptr;  // set: stream operations are recorded here instead of issued
 
   // learned preconditioner stage (null: sweeps only)
   pt_learned* learned = nullptr;

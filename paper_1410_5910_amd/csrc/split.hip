@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstring>
 
 #include "polar_kernels.h"
 
@@ -170,15 +172,21 @@ __global__ void split_planes_kernel(const double2* __restrict__ src, typename T:
 // MFMAs each per chunk, are interleaved so consecutive MFMAs are independent.
 // The KS partial tiles are summed through LDS in a fixed order by wave 0: no
 // atomics, deterministic results.
-template <typename T, int NB, int KS>
-__global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restrict__ jobs, int n, int nrt16,
-                                                              int nct, int nrhs, int64_t ld, Bases bases) {
+template <typename T, int NB, int KS, int NS>
+__global__ __launch_bounds__(64 * KS) void block_split_kernel(const SegTableT<NS> tab,
+                                                              const Job* __restrict__ jobs1) {
   typedef typename T::v8 bf16x8;
   __shared__ f32x4 red[KS > 1 ? KS - 1 : 1][4][NB][64];
   const int lane = threadIdx.x & 63;
   // wave-uniform, so chunk and term indices, job fields and base pointers stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int bid = blockIdx.x;
+  // segment of this block: a0 = 16-row tiles, a1 = column tiles
+  const int seg = seg_of(tab, bid);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], nrt16 = tab.a0[seg], nct = tab.a1[seg], nrhs = tab.nrhs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
   const int ct = bid % nct;
   bid /= nct;
   const int rt = bid % nrt16;
@@ -319,11 +327,9 @@ __global__ __launch_bounds__(64 * KS) void block_split_kernel(const Job* __restr
 // partial tiles are summed through LDS one group at a time, in a fixed order.
 constexpr int kWideRows = 64;
 
-template <typename T, int NB, int KS>
-__global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* __restrict__ jobs, int n, int ntiles,
-                                                                    int nct, int nrhs, int64_t ld, Bases bases,
-                                                                    int kslices, int njobs,
-                                                                    float2* __restrict__ part) {
+template <typename T, int NB, int KS, int NS>
+__global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTableT<NS> tab, int kslices,
+                                                                    const Job* __restrict__ jobs1) {
   typedef typename T::v8 bf16x8;
   constexpr int kWideCols = 16 * NB;
   constexpr int PPT = kSpK * kWideCols / 2 / 256;                          // row pairs per thread: NB
@@ -340,6 +346,14 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
   // XCD's range shares block rows (across column tiles) and input rows (across
   // row tiles) in its L2
   int bid = xcd_logical(blockIdx.x, gridDim.x);
+  // segment of this block (segments stay contiguous in the logical order):
+  // a0 = 64-row tiles, a1 = column tiles, part = its k-slice partial tiles
+  const int seg = seg_of(tab, bid);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], ntiles = tab.a0[seg], nct = tab.a1[seg], nrhs = tab.nrhs[seg], njobs = tab.njobs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
+  float2* __restrict__ part = tab.part[seg];
   const int ct = bid % nct;
   bid /= nct;
   const int tile = bid % ntiles;
@@ -525,11 +539,9 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const Job* _
 // (chunk index clamped, term pointers picked by selects), so two chunks can be
 // in flight while a third is multiplied; the arithmetic and its order are those
 // of block_split_wide_kernel<NB, 1>.
-template <typename T, int NB, bool HAS_S>
-__global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __restrict__ jobs, int n, int ntiles,
-                                                                 int nct, int nrhs, int64_t ld, Bases bases,
-                                                                 int kslices, int njobs,
-                                                                 float2* __restrict__ part) {
+template <typename T, int NB, bool HAS_S, int NS>
+__global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT<NS> tab, int kslices,
+                                                                 const Job* __restrict__ jobs1) {
   typedef typename T::v8 bf16x8;
   constexpr int kWideCols = 16 * NB;
   constexpr int PPT = kSpK * kWideCols / 2 / 256;              // row pairs per thread: NB
@@ -539,6 +551,14 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
   const int lane = tid & 63;
   const int wave = tid >> 6;
   int bid = xcd_logical(blockIdx.x, gridDim.x);
+  // segment of this block (segments stay contiguous in the logical order):
+  // a0 = 64-row tiles, a1 = column tiles, part = its k-slice partial tiles
+  const int seg = seg_of(tab, bid);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], ntiles = tab.a0[seg], nct = tab.a1[seg], nrhs = tab.nrhs[seg], njobs = tab.njobs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
+  float2* __restrict__ part = tab.part[seg];
   const int ct = bid % nct;
   bid /= nct;
   const int tile = bid % ntiles;
@@ -717,9 +737,16 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const Job* __re
 }
 
 // Y = P + alpha sum_s part[s] over the k-slices of every job, slices summed in order
-__global__ void split_reduce_kernel(const Job* __restrict__ jobs, int njobs, int n, int nrhs, int64_t ld,
-                                    Bases bases, int kslices, const float2* __restrict__ part) {
-  const int job = blockIdx.y;
+// (blk0 of the table counts jobs: blockIdx.y is a job of the launch)
+template <int NS>
+__global__ void split_reduce_kernel(const SegTableT<NS> tab, int kslices, const Job* __restrict__ jobs1) {
+  int job = blockIdx.y;
+  const int seg = seg_of(tab, job);
+  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
+  const int n = tab.n[seg], nrhs = tab.nrhs[seg], njobs = tab.njobs[seg];
+  const int64_t ld = tab.ld[seg];
+  const Bases bases = tab.bases[seg];
+  const float2* __restrict__ part = tab.part[seg];
   const Job& J = jobs[job];
   double2* __restrict__ Yb = sp_base(bases, J.Y.buf) + J.Y.off;
   const double2* __restrict__ Pb = J.P.buf >= 0 ? sp_base(bases, J.P.buf) + J.P.off : nullptr;
@@ -742,64 +769,114 @@ __global__ void split_reduce_kernel(const Job* __restrict__ jobs, int njobs, int
   }
 }
 
-template <typename T, int NB, int KS>
-hipError_t launch_wide(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                       hipEvent_t ev0, hipEvent_t ev1, int kslices = 1, float2* part = nullptr) {
-  const int ntiles = (n + kWideRows - 1) / kWideRows;
-  const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
-  const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
+template <int NS>
+SegTableT<NS> seg_table(const ApplySeg* segs, int nseg) {
+  SegTableT<NS> t;
+  std::memset(&t, 0, sizeof(t));
+  t.nseg = nseg;
+  for (int i = 0; i < nseg; ++i) {
+    t.n[i] = segs[i].n;
+    t.nrhs[i] = segs[i].nrhs;
+    t.njobs[i] = segs[i].njobs;
+    t.ld[i] = segs[i].ld;
+    t.jobs[i] = segs[i].jobs;
+    t.bases[i] = segs[i].bases;
+    t.part[i] = segs[i].part;
+  }
+  return t;
+}
+
+// Per-segment tiles and block offsets of the 64-row forms (wide, stream); the
+// launch's block count, or -1 if it does not fit the grid
+template <int NB, int NS>
+long wide_blocks(SegTableT<NS>& t, int kslices) {
+  long blk = 0;
+  for (int i = 0; i < t.nseg; ++i) {
+    t.a0[i] = (t.n[i] + kWideRows - 1) / kWideRows;
+    t.a1[i] = (t.nrhs[i] + 16 * NB - 1) / (16 * NB);
+    t.blk0[i] = (int32_t)blk;
+    blk += (long)t.njobs[i] * t.a0[i] * t.a1[i] * kslices;
+  }
+  t.blk0[t.nseg] = (int32_t)blk;
+  return blk > INT32_MAX ? -1 : blk;
+}
+
+// The k-slice sum: one row of blocks per job of the launch (blk0 counts jobs)
+template <int NS>
+hipError_t launch_reduce(SegTableT<NS> t, int kslices, hipStream_t st, hipEvent_t ev1) {
+  int jobs = 0;
+  size_t per = 0;
+  for (int i = 0; i < t.nseg; ++i) {
+    t.blk0[i] = jobs;
+    jobs += t.njobs[i];
+    per = std::max(per, (size_t)t.nrhs[i] * t.n[i]);
+  }
+  t.blk0[t.nseg] = jobs;
+  const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)jobs);
+  hipExtLaunchKernelGGL(split_reduce_kernel<NS>, rgrid, dim3(256), 0, st, nullptr, ev1, 0, t, kslices,
+                        t.jobs[0]);
+  return hipGetLastError();
+}
+
+template <typename T, int NB, int KS, int NS>
+hipError_t launch_wide(SegTableT<NS> t, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int kslices = 1) {
+  const long blk = wide_blocks<NB, NS>(t, kslices);
+  if (blk < 0) return hipErrorInvalidValue;
+  if (blk == 0) return hipSuccess;
+  const dim3 grid((unsigned)blk);
   if (kslices > 1) {
     // the stop event goes on the reduction, so a timed launch covers both kernels
-    hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS>), grid, dim3(256 * KS), 0, st, ev0, nullptr, 0, jobs, n,
-                          ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
-    const size_t per = (size_t)nrhs * n;
-    const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
-    hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
-                          bases, kslices, (const float2*)part);
-  } else {
-    hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, jobs, n,
-                          ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
+    hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS, NS>), grid, dim3(256 * KS), 0, st, ev0, nullptr, 0, t,
+                          kslices, t.jobs[0]);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(t, kslices, st, ev1);
   }
+  hipExtLaunchKernelGGL((block_split_wide_kernel<T, NB, KS, NS>), grid, dim3(256 * KS), 0, st, ev0, ev1, 0, t, 1,
+                        t.jobs[0]);
   return hipGetLastError();
 }
 
-template <typename T, int NB, bool HAS_S>
-hipError_t launch_stream(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                         hipEvent_t ev0, hipEvent_t ev1, int kslices, float2* part) {
-  const int ntiles = (n + kWideRows - 1) / kWideRows;
-  const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
-  const dim3 grid((unsigned)njobs * ntiles * nct * kslices);
+template <typename T, int NB, bool HAS_S, int NS>
+hipError_t launch_stream(SegTableT<NS> t, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int kslices) {
+  const long blk = wide_blocks<NB, NS>(t, kslices);
+  if (blk < 0) return hipErrorInvalidValue;
+  if (blk == 0) return hipSuccess;
+  const dim3 grid((unsigned)blk);
   if (kslices > 1) {
-    hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S>), grid, dim3(256), 0, st, ev0, nullptr, 0, jobs, n,
-                          ntiles, nct, nrhs, ld, bases, kslices, njobs, part);
-    const size_t per = (size_t)nrhs * n;
-    const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)njobs);
-    hipExtLaunchKernelGGL(split_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, jobs, njobs, n, nrhs, ld,
-                          bases, kslices, (const float2*)part);
-  } else {
-    hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S>), grid, dim3(256), 0, st, ev0, ev1, 0, jobs, n,
-                          ntiles, nct, nrhs, ld, bases, 1, njobs, nullptr);
+    hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S, NS>), grid, dim3(256), 0, st, ev0, nullptr, 0, t,
+                          kslices, t.jobs[0]);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(t, kslices, st, ev1);
   }
+  hipExtLaunchKernelGGL((block_split_stream_kernel<T, NB, HAS_S, NS>), grid, dim3(256), 0, st, ev0, ev1, 0, t, 1,
+                        t.jobs[0]);
   return hipGetLastError();
 }
 
-template <typename T, int NB, int KS>
-hipError_t launch_sp(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                     hipEvent_t ev0, hipEvent_t ev1) {
-  const int nrt16 = (n + 15) / 16;
-  const int nct = (nrhs + 16 * NB - 1) / (16 * NB);
-  const dim3 grid((unsigned)njobs * nrt16 * nct);
-  hipExtLaunchKernelGGL((block_split_kernel<T, NB, KS>), grid, dim3(64 * KS), 0, st, ev0, ev1, 0, jobs, n, nrt16, nct,
-                        nrhs, ld, bases);
+template <typename T, int NB, int KS, int NS>
+hipError_t launch_sp(SegTableT<NS> t, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  long blk = 0;
+  for (int i = 0; i < t.nseg; ++i) {
+    t.a0[i] = (t.n[i] + 15) / 16;
+    t.a1[i] = (t.nrhs[i] + 16 * NB - 1) / (16 * NB);
+    t.blk0[i] = (int32_t)blk;
+    blk += (long)t.njobs[i] * t.a0[i] * t.a1[i];
+  }
+  t.blk0[t.nseg] = (int32_t)blk;
+  if (blk > INT32_MAX) return hipErrorInvalidValue;
+  if (blk == 0) return hipSuccess;
+  hipExtLaunchKernelGGL((block_split_kernel<T, NB, KS, NS>), dim3((unsigned)blk), dim3(64 * KS), 0, st, ev0, ev1, 0,
+                        t, t.jobs[0]);
   return hipGetLastError();
 }
 
-template <typename T, int NB>
-hipError_t launch_sp_ks(int ks, const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                        hipEvent_t ev0, hipEvent_t ev1) {
-  if (ks >= 4) return launch_sp<T, NB, 4>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
-  if (ks == 2) return launch_sp<T, NB, 2>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
-  return launch_sp<T, NB, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+template <typename T, int NB, int NS>
+hipError_t launch_sp_ks(int ks, const SegTableT<NS>& t, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ks >= 4) return launch_sp<T, NB, 4, NS>(t, st, ev0, ev1);
+  if (ks == 2) return launch_sp<T, NB, 2, NS>(t, st, ev0, ev1);
+  return launch_sp<T, NB, 1, NS>(t, st, ev0, ev1);
 }
 
 }  // namespace
@@ -846,6 +923,8 @@ template <typename T>
 hipError_t apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
                        hipEvent_t ev0, hipEvent_t ev1, float2* part, SplitCfg cfg) {
   constexpr long kSimds = 1024;
+  const ApplySeg sg{jobs, njobs, n, nrhs, ld, bases, part, 0};
+  const SegTableT<1> t = seg_table<1>(&sg, 1);
   if (nrhs > 16) {
     // 64 x 32 (or 64 x 64) tiles; launches with fewer than four tiles per CU
     // split the chunk sequence over k-slices (partial tiles in `part`, summed
@@ -855,23 +934,44 @@ hipError_t apply_split(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, 
     if (cfg.stream) {  // every job: two terms with Q (and S iff stream == 2)
       const int k = part ? ks : 1;
       if (cfg.stream == 2)
-        return tr == 64 ? launch_stream<T, 4, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
-                        : launch_stream<T, 2, true>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
-      return tr == 64 ? launch_stream<T, 4, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part)
-                      : launch_stream<T, 2, false>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, k, part);
+        return tr == 64 ? launch_stream<T, 4, true, 1>(t, st, ev0, ev1, k)
+                        : launch_stream<T, 2, true, 1>(t, st, ev0, ev1, k);
+      return tr == 64 ? launch_stream<T, 4, false, 1>(t, st, ev0, ev1, k)
+                      : launch_stream<T, 2, false, 1>(t, st, ev0, ev1, k);
     }
-    if (ks > 1 && part) {
-      return tr == 64 ? launch_wide<T, 4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part)
-                      : launch_wide<T, 2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, ks, part);
-    }
-    return tr == 64 ? launch_wide<T, 4, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1)
-                    : launch_wide<T, 2, 1>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+    const int k = ks > 1 && part ? ks : 1;
+    return tr == 64 ? launch_wide<T, 4, 1, 1>(t, st, ev0, ev1, k) : launch_wide<T, 2, 1, 1>(t, st, ev0, ev1, k);
   }
   // 16-column tiles; the chunks of a tile are split over up to 4 waves until
   // the launch has about 4 waves per SIMD
   const long tasks = (long)njobs * ((n + 15) / 16) * ((nrhs + 15) / 16);
   const int ks = cfg.kslices > 0 ? cfg.kslices : tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
-  return launch_sp_ks<T, 1>(ks, jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1);
+  return launch_sp_ks<T, 1, 1>(ks, t, st, ev0, ev1);
+}
+
+// The rule's shapes for a merged launch, from the segments' total size.
+template <typename T>
+hipError_t apply_split_segs(const ApplySeg* segs, int nseg, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr long kSimds = 1024, kCUs = 256;
+  int rmax = 0;
+  long tiles = 0, tasks = 0;
+  for (int i = 0; i < nseg; ++i) {
+    if (segs[i].njobs <= 0 || segs[i].n <= 0 || segs[i].nrhs <= 0) return hipErrorInvalidValue;
+    rmax = std::max(rmax, segs[i].nrhs);
+    tiles += (long)segs[i].njobs * ((segs[i].n + kWideRows - 1) / kWideRows) *
+             ((segs[i].nrhs + kWideColsRule - 1) / kWideColsRule);
+    tasks += (long)segs[i].njobs * ((segs[i].n + 15) / 16) * ((segs[i].nrhs + 15) / 16);
+  }
+  const SegTableT<kMaxSeg> t = seg_table<kMaxSeg>(segs, nseg);
+  if (rmax > 16) {
+    int ks = 1;
+    while (ks < 16 && tiles * ks < 4 * kCUs) ks *= 2;
+    for (int i = 0; i < nseg && ks > 1; ++i)  // every segment's workspace must hold its partial tiles
+      if (!segs[i].part || (size_t)ks * segs[i].njobs * segs[i].nrhs * segs[i].n > segs[i].part_n) ks = 1;
+    return launch_wide<T, 2, 1, kMaxSeg>(t, st, ev0, ev1, ks);
+  }
+  const int ks = tasks >= 4 * kSimds ? 1 : tasks >= 2 * kSimds ? 2 : 4;
+  return launch_sp_ks<T, 1, kMaxSeg>(ks, t, st, ev0, ev1);
 }
 
 }  // namespace
@@ -883,5 +983,11 @@ hipError_t launch_block_apply_split(const Job* jobs, int njobs, int n, int nrhs,
                  : apply_split<SpBf16>(jobs, njobs, n, nrhs, ld, bases, st, ev0, ev1, part, cfg);
 }
 
+hipError_t launch_block_apply_split_segs(const ApplySeg* segs, int nseg, int f16, hipStream_t st, hipEvent_t ev0,
+                                         hipEvent_t ev1) {
+  if (nseg <= 0) return hipSuccess;
+  if (nseg > kMaxSeg) return hipErrorInvalidValue;
+  return f16 ? apply_split_segs<SpF16>(segs, nseg, st, ev0, ev1) : apply_split_segs<SpBf16>(segs, nseg, st, ev0, ev1);
+}
 
 }  // namespace polar

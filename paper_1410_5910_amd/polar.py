@@ -35,7 +35,8 @@ EXPORTS = ("pt_setup", "pt_solve", "pt_free", "pt_status_str", "pt_last_error", 
            "pt_learned_create", "pt_learned_free", "pt_learned_num_params", "pt_learned_get_params",
            "pt_learned_set_params", "pt_learned_gradient", "pt_learned_forward", "pt_learned_collect",
            "pt_learned_samples", "pt_learned_train", "pt_solver_set_learned", "pt_learned_save", "pt_learned_load",
-           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_gauss_seidel", "pt_apply_noalloc",
+           "pt_profile_read_class", "pt_tune", "pt_solve_batch", "pt_solve_batch_merged", "pt_gauss_seidel",
+           "pt_apply_noalloc",
            "pt_setup_batch", "pt_save", "pt_load", "pt_tune_cache_save", "pt_tune_cache_load")
 CLASSES = ("local", "sweep", "reflect", "operator", "presolve")
 
@@ -126,6 +127,7 @@ def lib():
         L.pt_gauss_seidel.argtypes = [vp, i32, vp, vp, i32, C.c_double, i32, C.POINTER(i32), dp]
         L.pt_solve_batch.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), i32,
                                      C.POINTER(C.POINTER(PtRhsInfo))]
+        L.pt_solve_batch_merged.argtypes = L.pt_solve_batch.argtypes
         fp = C.POINTER(C.c_float)
         L.pt_learned_create.argtypes = [i32, C.c_uint64, vp, C.POINTER(vp)]
         L.pt_learned_free.argtypes = [vp]
@@ -486,9 +488,10 @@ class Learned:
         _check(self._lib.pt_learned_load(self._h, os.fsencode(path)))
 
 
-def solve_batch(solvers, fs):
+def solve_batch(solvers, fs, merged: bool = False):
     """Solve independent problems at once (pt_solve_batch): solvers[i] on fs[i] (all host arrays or all device
-    tensors).  Returns [(u_i, infos_i)].  Give each solver its own stream for the problems to overlap."""
+    tensors).  Returns [(u_i, infos_i)].  Give each solver its own stream for the problems to overlap.
+    merged: one launch sequence for all problems (pt_solve_batch_merged)."""
     n = len(solvers)
     if n != len(fs):
         raise ValueError("one source array per solver")
@@ -511,7 +514,8 @@ def solve_batch(solvers, fs):
     ip = (C.POINTER(PtRhsInfo) * n)(*[C.cast(i, C.POINTER(PtRhsInfo)) for i in infos])
     pairs = [sv._enter(keep, dev0) for sv, (_, keep, _) in zip(solvers, preps)]
     try:
-        _check(L.pt_solve_batch(n, hs, ks, fp, up, dev0 or 0, ip), allow=(PT_ENOCONV,))
+        call = L.pt_solve_batch_merged if merged else L.pt_solve_batch
+        _check(call(n, hs, ks, fp, up, dev0 or 0, ip), allow=(PT_ENOCONV,))
     finally:
         for pr in pairs:
             Solver._leave(pr)

@@ -1,0 +1,126 @@
+"""Several problems in one launch sequence (pt_solve_batch_merged): the problems of a
+batch advance in lockstep on one stream, and the block applies of problems
+with the same kernel family share one launch (a segment per problem).  Each
+problem's result must equal the direct solve (Thm. 1 / Prop. 1: the method
+reproduces it) at its form's bar, and agree with the same solver run alone,
+whatever the other problems of the batch are: other sizes, layer counts,
+precision forms, closures, compressed blocks, one layer, other right-hand-side
+counts."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.direct import DirectSolver
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1410_5910_amd")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+# (nx, nz, npml, L, nrhs, seed, solver options, bar against the direct solve)
+MIXED = [
+    (24, 30, 5, 3, 2, 201, dict(precision="f64"), 1e-8),
+    (40, 48, 6, 4, 7, 202, dict(precision="f64"), 1e-8),             # MFMA form
+    (56, 40, 5, 5, 9, 203, dict(precision="f64"), 1e-8),             # merged with the one above
+    (30, 36, 5, 4, 20, 204, dict(precision="split-bf16"), 1e-6),     # split form, > 16 sources
+    (36, 30, 5, 3, 24, 205, dict(precision="split-bf16"), 1e-6),     # merged with the one above
+    (32, 32, 5, 4, 6, 206, dict(precision="split-f16"), 1e-6),       # <= 16 sources
+    (28, 34, 5, 3, 5, 207, dict(precision="f32"), 1e-6),
+    (30, 30, 5, 1, 3, 208, dict(precision="f64"), 1e-8),             # one layer
+]
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    torch = pytest.importorskip("torch")
+    probs = [synth.config_small(nx=nx, nz=nz, npml=npml, L=L, nrhs=k, seed=sd)
+             for nx, nz, npml, L, k, sd, _, _ in MIXED]
+    _flush("[gpu] merged batch: oracle direct solves of " + str(len(probs)) + " problems")
+    refs = [DirectSolver(p).solve(f) for p, f in probs]
+    streams = [torch.cuda.Stream() for _ in probs]
+    solvers = [P.Solver.from_problem(p, max_nrhs=f.shape[0], tol=1e-10, maxit=80, stream=st.cuda_stream, **kw)
+               for (p, f), st, (*_, kw, _) in zip(probs, streams, MIXED)]
+    yield probs, refs, solvers
+    for sv in solvers:
+        sv.close()
+
+
+def test_merged_batch_matches_direct_and_solo(mixed):
+    torch = pytest.importorskip("torch")
+    probs, refs, solvers = mixed
+    _flush("[gpu] merged batch of 8 mixed problems (host arrays)")
+    res = P.solve_batch(solvers, [f for _, f in probs], merged=True)
+    for k, ((p, f), ud, sv, (u, infos)) in enumerate(zip(probs, refs, solvers, res)):
+        bar = MIXED[k][-1]
+        assert all(i["converged"] for i in infos), k
+        errs = [rel(u[r], ud[r]) for r in range(f.shape[0])]
+        _flush(f"[gpu]   problem {k} ({MIXED[k][6]['precision']}, L={p.L}, {f.shape[0]} sources): "
+               f"max rel err {max(errs):.2e}")
+        assert max(errs) < bar, k
+        u1, i1 = sv.solve(f)  # alone: the same method, possibly other launch shapes
+        assert rel(u1, u) < 10 * bar, k
+    # device arrays in, device arrays out: the same fields
+    dres = P.solve_batch(solvers, [torch.from_numpy(f).to("cuda:0") for _, f in probs], merged=True)
+    for (u, _), (ud, _) in zip(res, dres):
+        assert rel(ud.cpu().numpy(), u) < 1e-12
+    # the per-problem form (one host thread per problem) gives the same fields to rounding
+    tres = P.solve_batch(solvers, [f for _, f in probs])
+    for k, ((u, _), (ut, _)) in enumerate(zip(res, tres)):
+        assert rel(ut, u) < 10 * MIXED[k][-1], k
+    with pytest.raises(P.PolarError):
+        P.solve_batch([solvers[0], solvers[0]], [probs[0][1], probs[0][1]], merged=True)
+
+
+def test_merged_batch_rerun_is_bitwise(mixed):
+    probs, _, solvers = mixed
+    _flush("[gpu] merged batch: rerun")
+    a = P.solve_batch(solvers, [f for _, f in probs], merged=True)
+    b = P.solve_batch(solvers, [f for _, f in probs], merged=True)
+    for (ua, ia), (ub, ib) in zip(a, b):
+        assert np.array_equal(ua.view(np.float64), ub.view(np.float64))
+        assert [i["iters"] for i in ia] == [i["iters"] for i in ib]
+
+
+def test_merged_batch_with_compressed_and_extrapolation_solvers():
+    cases = [(40, 48, 6, 4, 3, 211, dict(precision="f64", plr=True, plr_eps=1e-10)),  # launched alone
+             (40, 48, 6, 4, 3, 212, dict(precision="f64", closure="extrap")),
+             (40, 48, 6, 4, 3, 213, dict(precision="f64"))]
+    probs = [synth.config_small(nx=nx, nz=nz, npml=npml, L=L, nrhs=k, seed=sd) for nx, nz, npml, L, k, sd, _ in cases]
+    _flush("[gpu] merged batch: compressed blocks, extrapolation closure, plain")
+    solvers = [P.Solver.from_problem(p, max_nrhs=f.shape[0], tol=1e-10, maxit=80, **c[-1])
+               for (p, f), c in zip(probs, cases)]
+    res = P.solve_batch(solvers, [f for _, f in probs], merged=True)
+    for (p, f), (u, infos) in zip(probs, res):
+        assert all(i["converged"] for i in infos)
+        assert rel(u, DirectSolver(p).solve(f)) < 1e-8
+    for sv in solvers:
+        sv.close()
+
+
+def test_merged_batch_reports_the_problem_that_does_not_converge():
+    probs = [synth.config_small(nx=30, nz=36, npml=5, L=4, nrhs=3, seed=221 + i) for i in range(3)]
+    _flush("[gpu] merged batch: one problem with maxit 2, one with a NaN source")
+    solvers = [P.Solver.from_problem(p, max_nrhs=3, tol=1e-12, maxit=(2 if i == 1 else 80))
+               for i, (p, _) in enumerate(probs)]
+    fs = [f.copy() for _, f in probs]
+    fs[2][1, probs[2][0].npml + 10, probs[2][0].npml + 5] = np.nan
+    res = P.solve_batch(solvers, fs, merged=True)  # PT_ENOCONV is reported per source, not raised
+    (u0, i0), (u1, i1), (u2, i2) = res
+    assert all(i["converged"] for i in i0)
+    assert rel(u0, DirectSolver(probs[0][0]).solve(probs[0][1])) < 1e-8
+    assert not any(i["converged"] for i in i1) and all(i["iters"] == 2 for i in i1)
+    assert np.all(np.isfinite(u1))  # the last iterate's field
+    assert not i2[1]["converged"] and not np.all(np.isfinite(u2[1]))
+    ref2 = DirectSolver(probs[2][0]).solve(probs[2][1])
+    for r in (0, 2):
+        assert i2[r]["converged"] and rel(u2[r], ref2[r]) < 1e-8
+    for sv in solvers:
+        sv.close()
