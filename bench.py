@@ -595,7 +595,7 @@ def main():
         "metric": METRIC, "value": chosen["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": chosen["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"split-bf16": "f64+bf16x2", "split-f16": "f64+f16x2", "f32": "f32+f64",
+        "dtype": {"split-bf16": "f64+bf16x2", "split-f16": "f64+f16x2", "f32": "f64+f32",
                   "f64": "f64"}[chosen["precision"]],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": [prob.NZ, prob.NX], "L": prob.L, "nrhs": nrhs,
@@ -604,7 +604,8 @@ def main():
                                           "operator A, Krylov vectors and residuals in float64",
                             "split-f16": "mixed: Gauss-Seidel sweeps on split-float16 MFMA blocks (scaled), local "
                                          "solves, operator A, Krylov vectors and residuals in float64",
-                            "f32": "float32 blocks and local factors, float64 Krylov vectors",
+                            "f32": "mixed: Gauss-Seidel sweeps on float32 blocks, local solves, operator A, "
+                                   "Krylov vectors and residuals in float64",
                             "f64": "float64"}[chosen["precision"]],
                    "gmres_tol": args.tol, "gs_iters": chosen["gs_iters"], "iterations": chosen["iterations"]},
         "roofline": chosen["roofline"],

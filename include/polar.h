@@ -67,9 +67,13 @@ typedef enum {
 
 typedef enum {
   PT_F64 = 0,        /* every block apply and local solve in complex float64     */
-  PT_F32 = 1,        /* Green's blocks and local factors stored and applied in
-                        complex float32 (FP32 accumulation); Krylov vectors,
-                        Arnoldi, least squares and true residuals stay float64 */
+  PT_F32 = 1,        /* the Gauss-Seidel preconditioner (sweeps and reflection
+                        terms) applies float32 copies of the trace blocks
+                        (complex float32, float32 accumulation); local solves,
+                        the operator A inside GMRES, Krylov vectors, Arnoldi,
+                        least squares and true residuals stay float64, so
+                        flexible GMRES converges to the float64 solution (both
+                        block copies are kept) */
   PT_SPLIT_BF16 = 2, /* mixed: the Gauss-Seidel preconditioner (sweeps and
                         reflection terms) applies the trace blocks as split
                         bfloat16 pairs (hi + lo) on MFMA with float32
@@ -236,7 +240,7 @@ pt_status pt_get_layout(const pt_solver* s, pt_layout* out);
  * (Def. 1: G^l(z_j, z_k) = h K_{j,k}).  Written to host `out` as an NX x NX
  * row-major complex matrix (rows: target x).  PT_EINVAL if the layer has no
  * such row (layer 0 has no rows 0, 1; layer L-1 no rows n, n+1).  Reads the
- * stored float64 blocks (PT_F32 solvers: the float32 copy, widened). */
+ * stored float64 blocks. */
 pt_status pt_get_block(const pt_solver* s, int32_t layer, int32_t j, int32_t k, double* out);
 
 /* The same block as pt_get_block, expanded from its partitioned low-rank form

@@ -18,7 +18,7 @@
 namespace {
 
 constexpr char kMagic[8] = {'P', 'T', 'S', 'O', 'L', 'V', 'E', 'R'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct FileCloser {
   FILE* fp;
@@ -53,14 +53,10 @@ pt_status pt_save(const pt_solver* S, const char* path) {
             rec_write_host(fp, &S->opt, 1, sizeof(pt_options)) &&
             rec_write_host(fp, S->c_host.data(), S->c_host.size(), sizeof(double)) && rec_write_host(fp, flags, 4, 4);
   // in the order setup reads them back
-  if (ok && !S->f32) ok = rec_write_device(fp, S->dinv64.p, S->dinv64.n, sizeof(double2));
-  if (ok && !S->f32 && S->L >= 2) ok = rec_write_device(fp, S->blk64.p, (uint64_t)S->nblk * E, sizeof(double2));
+  if (ok) ok = rec_write_device(fp, S->dinv64.p, S->dinv64.n, sizeof(double2));
+  if (ok && S->L >= 2) ok = rec_write_device(fp, S->blk64.p, (uint64_t)S->nblk * E, sizeof(double2));
   if (ok && green) ok = rec_write_device(fp, S->green.p, S->green.n, sizeof(double2));
   if (ok && S->use_plr) ok = S->plr.save(fp);
-  if (ok && S->f32) {
-    ok = rec_write_device(fp, S->dinv32.p, (uint64_t)S->sumR * E, sizeof(float2)) &&
-         rec_write_device(fp, S->blk32.p, (uint64_t)S->nblk * E, sizeof(float2));
-  }
   std::vector<TuneRec> tr;
   for (int c = 0; c < PT_CLS_COUNT; ++c)
     for (const auto& kv : S->tune[c]) tr.push_back(TuneRec{c, kv.first, kv.second});
@@ -106,7 +102,6 @@ pt_status pt_load(const char* path, void* hip_stream, pt_solver** out) {
   prob.c = c.data();
   LoadSrc src;
   src.fp = fp;
-  src.f32 = flags[0] != 0;
   src.green = flags[1] != 0;
   src.plr = flags[2] != 0;
   // the saved Green's functions are used as they were (no memory heuristic on load)

@@ -155,11 +155,11 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
   else {
-    HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, S->f32, S->st, e0, e1));
+    HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, Lc.f32, S->st, e0, e1));
   }
   if (S->prof) {
     // bytes per stored complex entry: 4 bfloat16 planes, float32 or float64 pairs
-    const double es = Lc.split ? 8.0 : S->f32 ? 8.0 : 16.0;
+    const double es = Lc.split ? 8.0 : Lc.f32 ? 8.0 : 16.0;
     S->pend.push_back(ProfPending{slot, Lc.cls, Lc.mat_elems * es + Lc.vec_elems_rhs * nrhs * 16.0,
                                   8.0 * Lc.mat_elems * nrhs});
   }
@@ -175,7 +175,8 @@ Launch push_launch(pt_solver* S, const std::vector<Job>& js, int cls, bool plr_t
   Launch Lc;
   Lc.cls = cls;
   Lc.split = split_terms && S->split;
-  if (Lc.split) plr_terms = false;
+  Lc.f32 = split_terms && S->f32 && !S->split;  // the float32 form's preconditioner blocks
+  if (Lc.split || Lc.f32) plr_terms = false;
   Lc.job0 = (int)S->hjobs.size();
   Lc.njobs = (int)js.size();
   for (const Job& j : js) Lc.maxterms = std::max(Lc.maxterms, j.nterms);
@@ -711,7 +712,6 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
         for (int ab = 0; ab < 4; ++ab) S->bidx[(l * 4 + t) * 4 + ab] = nb++;
   }
   S->nblk = nb;
-  if (src && src->f32) return PT_OK;  // the float32 copies are read after the other offline data
   HIPCHK(S->blk64.alloc((size_t)nb * E));
   if (L == 1) return PT_OK;
   if (src) {
@@ -1390,7 +1390,7 @@ void build_online_jobs(pt_solver* S) {
   //   y_up(k, 0)   = a_k(0)   + u Delta_0^-1   [(a_k(1) - y_up(k, 1)) + ((1 + u) / u) d_k(n+1)]
   // (l, u: the couplings of those rows; -1 in the paper's A scaling, where the
   // second terms vanish): 10 block reads per interface instead of 16.
-  const bool extrap = !S->use_plr && !S->f32;
+  const bool extrap = !S->use_plr;
   S->opA2 = Launch{};
   for (int which = 0; which < 2; ++which) {
     std::vector<Job> js, js2;
@@ -2103,7 +2103,7 @@ pt_status pt_gauss_seidel(pt_solver* S, int32_t nrhs, const double* f, double* u
 int merge_key(const pt_solver* S, const Rec& r) {
   if (r.Lc.plr) return -1;
   if (r.Lc.split) return 1 + (S->split_f16 ? 2 : 0) + (r.nrhs > 16 ? 1 : 0);
-  return 5 + (S->f32 ? 2 : 0) + (r.nrhs > 4 ? 1 : 0);
+  return 5 + (r.Lc.f32 ? 2 : 0) + (r.nrhs > 4 ? 1 : 0);
 }
 
 // One block apply for each problem of `grp` (its next recorded operation), in
@@ -2141,13 +2141,13 @@ pt_status issue_applies(pt_solver* const* s, const std::vector<std::vector<Rec>>
   if (r0.Lc.split) {
     HIPCHK(launch_block_apply_split_segs(segs, n, S0->split_f16 ? 1 : 0, st, e0, e1));
   } else {
-    HIPCHK(launch_block_apply_segs(segs, n, maxterms, wide, S0->f32, st, e0, e1));
+    HIPCHK(launch_block_apply_segs(segs, n, maxterms, wide, r0.Lc.f32, st, e0, e1));
   }
   if (S0->prof) {
     double bytes = 0, flops = 0;
     for (int p : grp) {
       const Rec& r = recs[p][cur[p]];
-      const double es = r.Lc.split ? 8.0 : s[p]->f32 ? 8.0 : 16.0;
+      const double es = r.Lc.split ? 8.0 : r.Lc.f32 ? 8.0 : 16.0;
       bytes += r.Lc.mat_elems * es + r.Lc.vec_elems_rhs * r.nrhs * 16.0;
       flops += 8.0 * r.Lc.mat_elems * r.nrhs;
     }
@@ -2733,7 +2733,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
             cands.push_back(c);
           }
         }
-      } else if (!Lc->plr && !S->f32 && g.mfma) {
+      } else if (!Lc->plr && !Lc->f32 && g.mfma) {
         for (int tn : {16, 32, 64})
           for (int ks : {1, 2, 4})
             if (tn == 16 || ks == 1) {
@@ -2899,7 +2899,7 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
     return s;
   };
   if (S->flag.alloc(1) != hipSuccess) return bail(fail(PT_ENOMEM, "flag"));
-  if (!(src && src->f32) && S->dinv64.alloc((size_t)S->sumR * S->block_elems()) != hipSuccess)
+  if (S->dinv64.alloc((size_t)S->sumR * S->block_elems()) != hipSuccess)
     return bail(fail(PT_ENOMEM, "local factors"));
   if (S->rowmap.alloc(S->sumR) != hipSuccess ||
       hipMemcpy(S->rowmap.p, rowmap.data(), S->sumR * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
@@ -2907,7 +2907,7 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
 
   if (!src) {
     rc = factorize(S, diag, west, east);
-  } else if (!src->f32 && !rec_read_device(src->fp, S->dinv64.p, S->dinv64.n, sizeof(double2))) {
+  } else if (!rec_read_device(src->fp, S->dinv64.p, S->dinv64.n, sizeof(double2))) {
     rc = fail(PT_EINVAL, "saved solver: local factors");
   }
   if (rc != PT_OK) return bail(rc);
@@ -3022,24 +3022,15 @@ pt_status polar_impl::setup_impl(const pt_problem* prob, const pt_options* opt, 
     }
   }
 
-  // reduced-precision copies of the factors and blocks
-  if (opt->precision == PT_F32 && src) {
-    const size_t nd = (size_t)S->sumR * S->block_elems(), nbk = (size_t)S->nblk * S->block_elems();
-    if (S->dinv32.alloc(nd) != hipSuccess || S->blk32.alloc(nbk) != hipSuccess)
-      return bail(fail(PT_ENOMEM, "float32 copies"));
-    if (!rec_read_device(src->fp, S->dinv32.p, nd, sizeof(float2)) ||
-        !rec_read_device(src->fp, S->blk32.p, nbk, sizeof(float2)))
-      return bail(fail(PT_EINVAL, "saved solver: float32 factors and blocks"));
-    S->f32 = true;
-  } else if (opt->precision == PT_F32) {
-    if (S->dinv32.alloc(S->dinv64.n) != hipSuccess || S->blk32.alloc(S->blk64.n) != hipSuccess)
-      return bail(fail(PT_ENOMEM, "float32 copies"));
-    if (launch_to_f32(S->dinv32.p, S->dinv64.p, (int64_t)S->dinv64.n, S->st) != hipSuccess ||
-        (S->blk64.n && launch_to_f32(S->blk32.p, S->blk64.p, (int64_t)S->blk64.n, S->st) != hipSuccess) ||
+  // float32 form: float32 copies of the trace blocks for the Gauss-Seidel
+  // preconditioner (Alg. 4); the operator, the local solves and the
+  // reconstruction keep the float64 factors and blocks (also when loaded:
+  // the copies are made from the float64 blocks read back)
+  if (opt->precision == PT_F32) {
+    if (S->blk32.alloc(S->blk64.n) != hipSuccess) return bail(fail(PT_ENOMEM, "float32 copies"));
+    if ((S->blk64.n && launch_to_f32(S->blk32.p, S->blk64.p, (int64_t)S->blk64.n, S->st) != hipSuccess) ||
         hipStreamSynchronize(S->st) != hipSuccess)
       return bail(fail(PT_EHIP, "float32 conversion"));
-    S->dinv64.release();
-    S->blk64.release();
     S->f32 = true;
   }
 
@@ -3088,7 +3079,7 @@ pt_status pt_get_layout(const pt_solver* S, pt_layout* o) {
   }
   o->setup_ms = S->setup_ms;
   o->plr_ms = S->plr_ms;
-  const size_t es = S->f32 ? sizeof(float2) : sizeof(double2);
+  const size_t es = sizeof(double2);
   o->dense_block_bytes = (int64_t)S->nblk * S->block_elems() * es;
   o->block_bytes = S->use_plr ? (int64_t)(S->plr.data_entries * sizeof(double2)) : o->dense_block_bytes;
   o->plr_leaves = S->use_plr ? (int64_t)S->plr.nleaves_total : 0;
@@ -3147,13 +3138,7 @@ pt_status pt_get_block(const pt_solver* S, int32_t layer, int32_t j, int32_t k, 
   if (st != PT_OK) return st;
   const size_t n = S->block_elems();
   std::vector<double2> col(n);
-  if (S->f32) {
-    std::vector<float2> tmp(n);
-    HIPCHK(hipMemcpy(tmp.data(), S->blk32.p + (size_t)id * n, n * sizeof(float2), hipMemcpyDeviceToHost));
-    for (size_t q = 0; q < n; ++q) col[q] = make_double2(tmp[q].x, tmp[q].y);
-  } else {
-    HIPCHK(hipMemcpy(col.data(), S->blk64.p + (size_t)id * n, n * sizeof(double2), hipMemcpyDeviceToHost));
-  }
+  HIPCHK(hipMemcpy(col.data(), S->blk64.p + (size_t)id * n, n * sizeof(double2), hipMemcpyDeviceToHost));
   unpack_block(col, S->NX, sign, shift, out);
   return PT_OK;
 }

@@ -80,6 +80,7 @@ struct Launch {
   int cls = PT_CLS_LOCAL;    // pt_launch_class
   bool plr = false;          // job terms point at compressed blocks
   bool split = false;        // job terms point at split planes
+  bool f32 = false;          // job terms point at float32 blocks
   double mat_elems = 0;      // matrix entries streamed by one launch
   double vec_elems_rhs = 0;  // vector entries read + written per right-hand side
   std::vector<int> lay_off;  // local-solve launches: first job of each layer (L + 1 entries; jobs in layer order)
@@ -161,7 +162,7 @@ struct pt_solver {
   std::vector<Layer> lay;
   int sumR = 0, Rmax = 0;
   int64_t Nt = 0;  // complex entries of one polarized vector
-  bool f32 = false;
+  bool f32 = false;  // float32 form: the Gauss-Seidel preconditioner's blocks in float32 (blk32)
   double plr_ms = 0;
   double setup_ms = 0;
 
@@ -256,8 +257,12 @@ struct pt_solver {
   size_t block_elems() const { return (size_t)NX * NX; }
   const void* blk(int l, int type, int a, int b) const {
     const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
-    if (id < 0) return nullptr;
-    return f32 ? (const void*)(blk32.p + (size_t)id * block_elems()) : (const void*)(blk64.p + (size_t)id * block_elems());
+    return id < 0 ? nullptr : (const void*)(blk64.p + (size_t)id * block_elems());
+  }
+  // the float32 copy of a block (float32 form: the preconditioner's blocks)
+  const void* blk_f32(int l, int type, int a, int b) const {
+    const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
+    return id < 0 ? nullptr : (const void*)(blk32.p + (size_t)id * block_elems());
   }
   // what a trace-block job term points at: the dense block or its compressed form
   const void* blk_term(int l, int type, int a, int b) const {
@@ -269,17 +274,17 @@ struct pt_solver {
     const int id = bidx[((l * 4 + type) * 2 + a) * 2 + b];
     return id < 0 ? nullptr : (const void*)(blkbf.p + (size_t)id * split_block_elems(NX));
   }
-  // block term of a preconditioner job: the split planes in the mixed form
+  // block term of a preconditioner job: the split planes or the float32 copy
+  // in the reduced-precision forms
   const void* blk_pre(int l, int type, int a, int b) const {
-    return split ? blk_split(l, type, a, b) : blk_term(l, type, a, b);
+    return split ? blk_split(l, type, a, b) : f32 ? blk_f32(l, type, a, b) : blk_term(l, type, a, b);
   }
   int blk_id(const void* term) const {
     if (!use_plr) return -1;
     return (int)((const PlrBlockDev*)term - plr.d_blocks);
   }
   const void* dinv(int l, int r) const {
-    const size_t off = (size_t)(lay[l].rowbase + r) * block_elems();
-    return f32 ? (const void*)(dinv32.p + off) : (const void*)(dinv64.p + off);
+    return (const void*)(dinv64.p + (size_t)(lay[l].rowbase + r) * block_elems());
   }
   // offset of trace segment (half h: 0 down, 1 up; interface k; row a)
   int64_t seg(int hh, int k, int a) const { return ((int64_t)(hh * (L - 1) + k) * 2 + a) * NX; }
@@ -293,7 +298,6 @@ namespace polar_impl {
 // instead of computing them.
 struct LoadSrc {
   FILE* fp = nullptr;
-  bool f32 = false;    // float32 factors and blocks stored (no float64 copies)
   bool green = false;  // interface Green's functions stored
   bool plr = false;    // compressed blocks stored
 };

@@ -293,9 +293,10 @@ def test_f32_blocks_and_factors_small():
     u, info = gs.solve(f)
     err = rel(u, DirectSolver(prob).solve(f))
     _flush(f"[gpu] f32 small rel err {err:.2e}, iters {[i['iters'] for i in info]}")
-    # FP32 factors and blocks: the trace solve still converges in FP64 (flexible GMRES), the
-    # local solves carry FP32 rounding: the reduced-precision bar is 1e-6
-    assert err < 1e-6
+    # float32 blocks in the preconditioner only: flexible GMRES with the float64 operator converges
+    # to the float64 solution, so the float64 bar holds
+    assert err < 1e-8
+    assert all(i["converged"] and i["relres"] < 1e-9 for i in info)
     gs.close()
 
 
@@ -306,7 +307,7 @@ def test_f32_thirteen_sources():
     gs = P.Solver.from_problem(prob, precision="f32", max_nrhs=13, tol=1e-10, maxit=60)
     u, info = gs.solve(f)
     ud = DirectSolver(prob).solve(f)
-    assert max(rel(u[r], ud[r]) for r in range(13)) < 1e-6
+    assert max(rel(u[r], ud[r]) for r in range(13)) < 1e-8
     gs.close()
 
 
@@ -317,7 +318,7 @@ def test_f32_bumps440_single_source():
     u, info = gs.solve(f)
     err = rel(u, DirectSolver(prob).solve(f))
     _flush(f"[gpu] f32 bumps440 rel err {err:.2e}, iters {info[0]['iters']}")
-    assert err < 1e-6
+    assert err < 1e-8
     gs.close()
 
 
