@@ -426,6 +426,71 @@ def _cpu_model():
     return "unknown"
 
 
+def learned_study(args):
+    """The learned stage at scale: training pairs from the method's own solves on args.learned_study models
+    (smooth-bump and layered media alternating, 256x256 interior, L=8, 4 sources each), Adam on the GPU, then
+    held-out 512x512 models x 16 sources solved with the sweeps only and with the network in both modes
+    (iterations, wall time, true residual).  A learned solve that misses its float64 checks is redone with the
+    sweeps only inside pt_solve, so every result meets the float64 bar either way."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1410_5910_amd as P
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    net = P.Learned(capacity=64 * args.learned_study, seed=11)
+    for i in range(args.learned_study):
+        prob, f = synth.learned_model(i, n=256, L=8, npml=20, nrhs=4)
+        s = P.Solver.from_problem(prob, max_nrhs=4, tol=1e-10, maxit=60)
+        net.collect(s, f)
+        s.close()
+        if (i + 1) % 25 == 0:
+            log(f"learned study: collected from {i + 1} models, {net.samples()[0]} samples")
+    t_collect = time.perf_counter() - t0
+    cnt, nx = net.samples()
+    t0 = time.perf_counter()
+    losses = net.train(args.learned_steps, batch=64, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    log(f"learned study: {cnt} samples, loss {losses[:20].mean():.3f} -> {losses[-200:].mean():.3f}")
+    evals = []
+    for j in range(args.learned_eval):
+        prob, f = synth.learned_model(100000 + j, n=512, L=8, npml=20, nrhs=16)
+        s = P.Solver.from_problem(prob, max_nrhs=16, tol=1e-8, maxit=60)
+        fd = torch.from_numpy(f).to("cuda:0")
+        row = {"model": prob.name}
+        for mode in ("sweeps", "correct", "augment"):
+            if mode == "sweeps":
+                P.Learned.detach(s)
+            else:
+                net.attach(s, mode)
+            s.solve(fd)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = s.solve(fd)
+            torch.cuda.synchronize()
+            row[mode] = {"ms": 1e3 * (time.perf_counter() - t1),
+                         "iters_mean": float(np.mean([i["iters"] for i in info])),
+                         "max_relres": float(max(i["relres"] for i in info)),
+                         "learned_kept": int(sum(bool(i["learned"]) for i in info))}
+        P.Learned.detach(s)
+        s.close()
+        log(f"learned study: {row['model']}: " + ", ".join(f"{m} {row[m]['iters_mean']:.2f} it {row[m]['ms']:.1f} ms"
+                                                            for m in ("sweeps", "correct", "augment")))
+        evals.append(row)
+    tot = {m: {"ms": float(sum(r[m]["ms"] for r in evals)),
+               "iters_mean": float(np.mean([r[m]["iters_mean"] for r in evals]))} for m in ("sweeps", "correct",
+                                                                                        "augment")}
+    out = {"study": "learned stage vs sweeps only", "train_models": args.learned_study, "train_grid": "256x256 L8",
+           "samples": cnt, "interface_points": nx, "adam_steps": args.learned_steps,
+           "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-200:].mean()),
+           "collect_s": t_collect, "train_s": t_train, "eval_models": len(evals), "eval_grid": "512x512 L8 x 16",
+           "totals": tot, "gain_iters": {m: tot["sweeps"]["iters_mean"] / tot[m]["iters_mean"] for m in
+                                         ("correct", "augment")},
+           "gain_time": {m: tot["sweeps"]["ms"] / tot[m]["ms"] for m in ("correct", "augment")}, "models": evals}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,7 +531,15 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two fresh device buffers (a known-size kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE); outside the timed steps")
+    ap.add_argument("--learned-study", type=int, default=0, metavar="N",
+                    help="instead of the throughput forms: train the learned stage on N models (256x256, L=8, "
+                         "4 sources each) and compare it with the sweeps alone on held-out 512x512 models x 16 "
+                         "sources (--learned-eval of them); prints one JSON line")
+    ap.add_argument("--learned-eval", type=int, default=8, metavar="M", help="held-out models of the study")
+    ap.add_argument("--learned-steps", type=int, default=4000, help="Adam steps of the study's training")
     args = ap.parse_args()
+    if args.learned_study:
+        return learned_study(args)
     gs_arg = args.gs_iters if args.gs_iters == "auto" else int(args.gs_iters)
     if args.plr and args.precision not in ("auto", "f64"):
         print("--plr takes float64 blocks: use --precision f64", file=sys.stderr)
