@@ -428,7 +428,9 @@ pt_status pt_tune_cache_load(const char* path);
  * The network sees each interface separately as 8 real channels ({down, up}
  * x {row n, row n+1} x {re, im}) of r divided by their RMS; its output is
  * scaled back.  Architecture: 4 convolutions 8 -> 32 -> 32 -> 32 -> 8,
- * kernel 5, zero padding, ReLU between layers; bfloat16 weights, float32
+ * kernel 5 with dilations 1, 2, 4, 8 (taps (k - 2) d apart: 61 interface
+ * points around each output), zero padding, ReLU between layers; bfloat16
+ * weights, float32
  * activations and accumulation, float32 master weights trained with Adam.
  * Training pairs (r, e) come from the method's own solves: for every Krylov
  * vector v of a sweep-only GMRES, r = v - A GS(v) and e = A^{-1} r from a

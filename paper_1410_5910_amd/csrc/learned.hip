@@ -19,6 +19,9 @@ constexpr int kK = 5;
 constexpr int kPad = 2;
 constexpr int kCin[kLayers] = {8, 32, 32, 32};
 constexpr int kCout[kLayers] = {32, 32, 32, 8};
+// dilation of each layer: taps at offsets (k - kPad) d, so the network sees
+// 1 + 2 kPad (1 + 2 + 4 + 8) = 61 interface points around each output point
+constexpr int kDil[kLayers] = {1, 2, 4, 8};
 constexpr int kThreadsL = 256;
 
 constexpr int64_t w_size(int l) { return (int64_t)kCout[l] * kCin[l] * kK; }
@@ -41,11 +44,11 @@ __device__ __forceinline__ uint16_t f_to_bf16(float f) {  // round to nearest ev
   return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
 
-// y[b][o][i] = bias[o] + sum_{c,k} w[o][c][k] x[b][c][i+k-2], optional ReLU.
+// y[b][o][i] = bias[o] + sum_{c,k} w[o][c][k] x[b][c][i+(k-2)d], optional ReLU.
 // grid (ceil(n/256), Cout, B)
 __global__ __launch_bounds__(kThreadsL) void conv_fwd_kernel(const float* __restrict__ x, const uint16_t* __restrict__ w,
                                                               const float* __restrict__ bias, float* __restrict__ y,
-                                                              int Cin, int Cout, int n, int relu) {
+                                                              int Cin, int Cout, int n, int relu, int d) {
   __shared__ float ws[32 * kK];
   const int o = blockIdx.y, b = blockIdx.z;
   for (int q = threadIdx.x; q < Cin * kK; q += kThreadsL) ws[q] = bf16_to_f(w[(size_t)o * Cin * kK + q]);
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(kThreadsL) void conv_fwd_kernel(const float* __rest
   for (int c = 0; c < Cin; ++c)
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
-      const int j = i + k - kPad;
+      const int j = i + (k - kPad) * d;
       if (j >= 0 && j < n) acc = fmaf(ws[c * kK + k], xb[(size_t)c * n + j], acc);
     }
   if (relu) acc = fmaxf(acc, 0.f);
@@ -68,12 +71,13 @@ __device__ __forceinline__ float masked(const float* g, const float* yl, size_t 
   return (yl == nullptr || yl[e] > 0.f) ? g[e] : 0.f;
 }
 
-// dx[b][c][j] = sum_{o,k} w[o][c][k] gm[b][o][j-k+2], gm = g masked by ReLU'(layer output yl)
+// dx[b][c][j] = sum_{o,k} w[o][c][k] gm[b][o][j-(k-2)d], gm = g masked by ReLU'(layer output yl)
 // grid (ceil(n/256), Cin, B)
 __global__ __launch_bounds__(kThreadsL) void conv_bwd_data_kernel(const float* __restrict__ g,
                                                                    const float* __restrict__ yl,
                                                                    const uint16_t* __restrict__ w,
-                                                                   float* __restrict__ dx, int Cin, int Cout, int n) {
+                                                                   float* __restrict__ dx, int Cin, int Cout, int n,
+                                                                   int d) {
   __shared__ float ws[32 * kK];
   const int c = blockIdx.y, b = blockIdx.z;
   for (int q = threadIdx.x; q < Cout * kK; q += kThreadsL) {
@@ -88,20 +92,20 @@ __global__ __launch_bounds__(kThreadsL) void conv_bwd_data_kernel(const float* _
     const size_t base = ((size_t)b * Cout + o) * n;
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
-      const int i = j - k + kPad;
+      const int i = j - (k - kPad) * d;
       if (i >= 0 && i < n) acc = fmaf(ws[o * kK + k], masked(g, yl, base + i), acc);
     }
   }
   dx[((size_t)b * Cin + c) * n + j] = acc;
 }
 
-// dw[o][c][k] = sum_{b,i} gm[b][o][i] x[b][c][i+k-2];  db[o] = sum gm[b][o][i] (written by c == 0)
+// dw[o][c][k] = sum_{b,i} gm[b][o][i] x[b][c][i+(k-2)d];  db[o] = sum gm[b][o][i] (written by c == 0)
 // grid (Cout, Cin), fixed-order reduction
 __global__ __launch_bounds__(kThreadsL) void conv_bwd_weight_kernel(const float* __restrict__ g,
                                                                      const float* __restrict__ yl,
                                                                      const float* __restrict__ x,
                                                                      float* __restrict__ dw, float* __restrict__ db,
-                                                                     int B, int Cin, int Cout, int n) {
+                                                                     int B, int Cin, int Cout, int n, int d) {
   __shared__ float red[kK + 1][kThreadsL];
   const int o = blockIdx.x, c = blockIdx.y;
   float acc[kK + 1] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(kThreadsL) void conv_bwd_weight_kernel(const float*
     const float* xb = x + ((size_t)b * Cin + c) * n;
 #pragma unroll
     for (int k = 0; k < kK; ++k) {
-      const int j = i + k - kPad;
+      const int j = i + (k - kPad) * d;
       if (j >= 0 && j < n) acc[k] = fmaf(gv, xb[j], acc[k]);
     }
     acc[kK] += gv;
@@ -361,7 +365,7 @@ pt_status net_forward(pt_learned* N, int B, int n) {
   for (int l = 0; l < kLayers; ++l) {
     hipLaunchKernelGGL(conv_fwd_kernel, dim3(blocks_for(n), kCout[l], B), dim3(kThreadsL), 0, N->st, N->act[l].p,
                        N->w16.p + w_off(l), N->w32.p + w_off(l) + w_size(l), N->act[l + 1].p, kCin[l], kCout[l], n,
-                       l < kLayers - 1 ? 1 : 0);
+                       l < kLayers - 1 ? 1 : 0, kDil[l]);
     HIPCHK(hipGetLastError());
   }
   return PT_OK;
@@ -377,11 +381,12 @@ pt_status net_backward(pt_learned* N, int B, int n) {
   for (int l = kLayers - 1; l >= 0; --l) {
     const float* mask = l < kLayers - 1 ? N->act[l + 1].p : nullptr;
     hipLaunchKernelGGL(conv_bwd_weight_kernel, dim3(kCout[l], kCin[l]), dim3(kThreadsL), 0, N->st, g, mask,
-                       N->act[l].p, N->grad.p + w_off(l), N->grad.p + w_off(l) + w_size(l), B, kCin[l], kCout[l], n);
+                       N->act[l].p, N->grad.p + w_off(l), N->grad.p + w_off(l) + w_size(l), B, kCin[l], kCout[l], n,
+                       kDil[l]);
     HIPCHK(hipGetLastError());
     if (l > 0) {
       hipLaunchKernelGGL(conv_bwd_data_kernel, dim3(blocks_for(n), kCin[l], B), dim3(kThreadsL), 0, N->st, g, mask,
-                         N->w16.p + w_off(l), gn, kCin[l], kCout[l], n);
+                         N->w16.p + w_off(l), gn, kCin[l], kCout[l], n, kDil[l]);
       HIPCHK(hipGetLastError());
       std::swap(g, gn);
     }
@@ -710,7 +715,7 @@ pt_status pt_learned_save(const pt_learned* N, const char* path) {
   PTCHK(pt_learned_get_params(N, h.data()));
   std::ofstream o(path, std::ios::binary);
   if (!o) return fail(PT_EINVAL, "cannot open file");
-  const char magic[8] = {'P', 'T', 'C', 'N', 'N', '1', 0, 0};
+  const char magic[8] = {'P', 'T', 'C', 'N', 'N', '2', 0, 0};  // 2: the dilated layers
   o.write(magic, 8);
   const int64_t np = N->np;
   o.write(reinterpret_cast<const char*>(&np), 8);
@@ -726,7 +731,7 @@ pt_status pt_learned_load(pt_learned* N, const char* path) {
   int64_t np = 0;
   in.read(magic, 8);
   in.read(reinterpret_cast<char*>(&np), 8);
-  if (!in || std::memcmp(magic, "PTCNN1", 6) != 0 || np != N->np) return fail(PT_EINVAL, "not a network file");
+  if (!in || std::memcmp(magic, "PTCNN2", 6) != 0 || np != N->np) return fail(PT_EINVAL, "not a network file");
   std::vector<float> h(np);
   in.read(reinterpret_cast<char*>(h.data()), np * 4);
   if (!in) return fail(PT_EINVAL, "truncated network file");

@@ -400,7 +400,8 @@ def _fptr(a: np.ndarray):
 
 class Learned:
     """The learned preconditioner stage: a 1D CNN along the interfaces (8 -> 32 -> 32 -> 32 -> 8 channels,
-    kernel 5), trained on the GPU from the solver's own Krylov vectors and applied as z = GS(v) + N(v)."""
+    kernel 5, dilations 1, 2, 4, 8), trained on the GPU from the solver's own Krylov vectors and applied as
+    z = GS(v) + N(v)."""
 
     def __init__(self, capacity: int = 4096, seed: int = 0, stream=None):
         self._lib = lib()

@@ -124,3 +124,20 @@ def test_merged_batch_reports_the_problem_that_does_not_converge():
         assert i2[r]["converged"] and rel(u2[r], ref2[r]) < 1e-8
     for sv in solvers:
         sv.close()
+
+
+def test_merged_batch_of_more_problems_than_segments():
+    # eleven problems of one kernel family: their block applies need two merged launches (at most eight
+    # segments each); every problem must still match its solo solve and the direct solve
+    probs = [synth.config_small(nx=20 + 2 * i, nz=24 + i, npml=4, L=2 + i % 3, nrhs=6, seed=240 + i)
+             for i in range(11)]
+    _flush("[gpu] merged batch: 11 problems")
+    solvers = [P.Solver.from_problem(p, max_nrhs=6, tol=1e-10, maxit=80) for p, _ in probs]
+    res = P.solve_batch(solvers, [f for _, f in probs], merged=True)
+    for (p, f), sv, (u, infos) in zip(probs, solvers, res):
+        assert all(i["converged"] for i in infos)
+        assert rel(u, DirectSolver(p).solve(f)) < 1e-8
+        u1, _ = sv.solve(f)
+        assert rel(u1, u) < 1e-9
+    for sv in solvers:
+        sv.close()

@@ -21,6 +21,7 @@ P = pytest.importorskip("paper_1410_5910_amd")
 
 CH = (8, 32, 32, 32, 8)
 K = 5
+DIL = (1, 2, 4, 8)  # the library network's dilation per layer
 
 
 def rel(a, b):
@@ -68,7 +69,7 @@ def test_forward_matches_oracle(net, B, n):
     rng = np.random.default_rng(B * 1000 + n)
     x = rng.standard_normal((B, 8, n)).astype(np.float32)
     y = net.forward(x)
-    ref, _ = cnn.forward(unflatten(net.params), x.astype(np.float64))
+    ref, _ = cnn.forward(unflatten(net.params), x.astype(np.float64), DIL)
     assert rel(y, ref) < 1e-4, rel(y, ref)
 
 
@@ -79,9 +80,9 @@ def test_gradient_matches_oracle(net, B, n):
     t = rng.standard_normal((B, 8, n)).astype(np.float32)
     loss, g = net.gradient(x, t)
     ps = unflatten(net.params)
-    y, acts = cnn.forward(ps, x.astype(np.float64))
+    y, acts = cnn.forward(ps, x.astype(np.float64), DIL)
     ref_loss = cnn.loss(y, t.astype(np.float64))
-    ref_g = flatten(cnn.backward(ps, acts, cnn.loss_grad(y, t.astype(np.float64))))
+    ref_g = flatten(cnn.backward(ps, acts, cnn.loss_grad(y, t.astype(np.float64)), DIL))
     assert abs(loss - ref_loss) < 1e-5 * ref_loss
     assert rel(g, ref_g) < 1e-4, rel(g, ref_g)
     # every layer's weight and bias gradient, not just the total
