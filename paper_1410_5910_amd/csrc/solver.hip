@@ -1243,6 +1243,15 @@ void build_online_jobs(pt_solver* S) {
       S->gsum_off.assign(L + 1, 0);
       bool room = true;  // every layer has 4 free owned rows between its trace rows
       for (const Layer& y : S->lay) room = room && (y.n - 3) / 4 >= 1;
+      // ranges per layer: at least 8, and enough that a range spans about 256
+      // chunks of kNzChunk columns (a tall layer's ranges then keep their
+      // nonzero-chunk lists, and no workgroup walks a long chunk sequence),
+      // within the room for the partial rows
+      auto ranges = [&](const Layer& y) {
+        const long chunks = ((long)y.n * NX + kNzChunk - 1) / kNzChunk;
+        const int want = (int)std::max<long>(8, (chunks + 255) / 256);
+        return std::max(1, std::min(want, (y.n - 3) / 4));
+      };
       // one nonzero-chunk list per (layer, owned-row range), shared by the
       // layer's trace rows: the products skip the chunks where every source
       // column is zero (compact sources leave most of a layer's inputs zero)
@@ -1252,7 +1261,7 @@ void build_online_jobs(pt_solver* S) {
       int stride = 1;
       for (int l = 0; l < L && room; ++l) {
         const Layer& y = S->lay[l];
-        const int ns = std::min(8, (y.n - 3) / 4), per = (y.n + ns - 1) / ns;
+        const int ns = ranges(y), per = (y.n + ns - 1) / ns;
         for (int p = 0; p < ns; ++p) {
           const int r_lo = p * per, r_hi = std::min(y.n, r_lo + per);
           if (r_lo >= r_hi) continue;
@@ -1275,7 +1284,7 @@ void build_online_jobs(pt_solver* S) {
       for (int l = 0; l < L && room; ++l) {
         const Layer& y = S->lay[l];
         const std::vector<int> src = green_rows(y);
-        const int ns = std::min(8, (y.n - 3) / 4);  // rows te+2 .. te+1+2 ns stay below row n-1
+        const int ns = ranges(y);  // rows te+2 .. te+1+2 ns stay below row n-1
         const int per = (y.n + ns - 1) / ns;
         for (size_t k = 0; k < src.size(); ++k) {
           const int prow0 = y.rowbase + y.top_ext + 2 + (int)k * ns;
