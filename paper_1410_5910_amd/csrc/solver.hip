@@ -1864,10 +1864,12 @@ pt_status fgmres_begin(pt_solver* S, int nrhs, bool learned) {
   return PT_OK;
 }
 
-pt_status fgmres_iter(pt_solver* S, int nrhs, int j, double tol, bool learned) {
-  const int64_t N = S->Nt;
-  const int m = S->opt.maxit;
-  const size_t vs = (size_t)nrhs * N;
+// Iteration j in two halves: the preconditioner and operator applies
+// (z_j = M^-1 v_j, w = A z_j), then the Arnoldi step on w (classical
+// Gram-Schmidt twice, the new basis vector, the Givens update, the
+// convergence flags to S->h_done).
+pt_status fgmres_iter_apply(pt_solver* S, int nrhs, int j, bool learned) {
+  const size_t vs = (size_t)nrhs * S->Nt;
   double2* vj = S->V.p + (size_t)j * vs;
   double2* zj = S->Z.p + (size_t)j * vs;
   const bool augment = learned && S->learned_mode == PT_LEARN_AUGMENT;
@@ -1882,6 +1884,13 @@ pt_status fgmres_iter(pt_solver* S, int nrhs, int j, double tol, bool learned) {
     PTCHK(system_A(S, zj, S->tmp.p, nrhs));
     if (augment && !(j & 1)) PTCHK(learned_residual(S, vj, S->tmp.p, nrhs));
   }
+  return PT_OK;
+}
+
+pt_status fgmres_iter_arnoldi(pt_solver* S, int nrhs, int j, double tol) {
+  const int64_t N = S->Nt;
+  const int m = S->opt.maxit;
+  const size_t vs = (size_t)nrhs * N;
   GPU(S, launch_zero(S->hacc.p, (int64_t)(j + 1) * nrhs, st_));
   for (int pass = 0; pass < 2; ++pass) {
     GPU(S, launch_kdot(S->V.p, S->tmp.p, S->hbuf.p, j + 1, nrhs, N, st_));
@@ -1893,6 +1902,11 @@ pt_status fgmres_iter(pt_solver* S, int nrhs, int j, double tol, bool learned) {
                        S->done.p, tol, j, m, nrhs, st_));
   GPU(S, hipMemcpyAsync(S->h_done, S->done.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
   return PT_OK;
+}
+
+pt_status fgmres_iter(pt_solver* S, int nrhs, int j, double tol, bool learned) {
+  PTCHK(fgmres_iter_apply(S, nrhs, j, learned));
+  return fgmres_iter_arnoldi(S, nrhs, j, tol);
 }
 
 pt_status fgmres_end(pt_solver* S, int nrhs) {
@@ -2342,17 +2356,26 @@ pt_status solve_merged(int P, pt_solver* const* s, const int32_t* nrhs, const do
     q[p].live = S->opt.maxit > 0;
   }
   PTCHK(issue_lanes());
-  // GMRES iterations in lockstep; a problem leaves when all its sources converged
+  // GMRES iterations in lockstep; a problem leaves when all its sources
+  // converged.  The preconditioner and operator applies share launches; the
+  // Arnoldi steps (small reductions, a handful of launches per problem) run on
+  // the lanes, concurrently
   for (;;) {
     bool any = false;
     for (int p = 0; p < P; ++p) {
       if (!q[p].live) continue;
       any = true;
       record(p);
-      PTCHK(fgmres_iter(s[p], nrhs[p], q[p].j, s[p]->opt.tol, false));
+      PTCHK(fgmres_iter_apply(s[p], nrhs[p], q[p].j, false));
     }
     if (!any) break;
     PTCHK(issue());
+    for (int p = 0; p < P; ++p) {
+      if (!q[p].live) continue;
+      record(p);
+      PTCHK(fgmres_iter_arnoldi(s[p], nrhs[p], q[p].j, s[p]->opt.tol));
+    }
+    PTCHK(issue_lanes());
     HIPCHK(hipStreamSynchronize(st));
     for (int p = 0; p < P; ++p) {
       if (!q[p].live) continue;
