@@ -154,14 +154,21 @@ def profile_classes(solvers, nprof, run):
     return {"nprof": nprof, "total": tot, "classes": cls}
 
 
-def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8):
+def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8, tune=True):
     """The uneven batch: 8 independent problems (grids 240..850 padded, L 4..16), 32 sources each, one
-    pt_solve_batch call per step, each problem on its own stream; sources device-resident."""
+    pt_solve_batch call per step, each problem on its own stream; sources device-resident.  Each
+    problem's tile shapes are tuned (pt_tune) after setup, outside the timed steps."""
     streams = [torch.cuda.Stream() for _ in probs]
     t0 = time.perf_counter()
     solvers = [P.Solver.from_problem(p, precision=precision, tol=tol, maxit=60, max_nrhs=f.shape[0],
                                      stream=st.cuda_stream) for (p, f), st in zip(probs, streams)]
     setup_s = time.perf_counter() - t0
+    tune_s = 0.0
+    if tune:
+        t0 = time.perf_counter()
+        for sv, (_, f) in zip(solvers, probs):
+            sv.tune(f.shape[0])
+        tune_s = time.perf_counter() - t0
     fds = [torch.from_numpy(f).to("cuda:0") for _, f in probs]
     for _ in range(warmup):
         res = P.solve_batch(solvers, fds)
@@ -184,7 +191,7 @@ def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8):
     el_merged = time.perf_counter() - t1
     out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs, "gs_iters": 2,
            "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
-           "launch": "pt_solve_batch: one host thread and stream per problem",
+           "tune_s": tune_s, "tuned": tune, "launch": "pt_solve_batch: one host thread and stream per problem",
            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "merged_ms_per_step": 1e3 * el_merged / steps,
            "iterations": sorted({i["iters"] for r in res for i in r[1]}),
@@ -624,7 +631,8 @@ def main():
         if not args.no_uneven:
             for prec in ("split-bf16", "split-f16", "f64"):
                 log(f"form uneven8 {prec}: 8 problems x 32 sources, one pt_solve_batch per step")
-                form, parts = run_uneven(P, torch, prec, args.steps, args.warmup, inputs["uneven8"], tol=args.tol)
+                form, parts = run_uneven(P, torch, prec, args.steps, args.warmup, inputs["uneven8"], tol=args.tol,
+                                         tune=not args.no_tune)
                 form["roofline"] = roofline(form)
                 log(f"  {form['solves_per_s']:.1f} solves/s, {form['ms_per_step']:.1f} ms/step")
                 runs.append((form, "uneven8", parts))
