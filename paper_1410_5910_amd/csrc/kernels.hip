@@ -441,10 +441,30 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const SegTableT<NS
 // Ai Bi, Ci += Ar Bi + Ai Br, issued so that consecutive MFMAs update different
 // accumulators.  Groups 1..KS-1 hand their partial tiles to group 0 through
 // LDS, summed in a fixed order: deterministic, no atomics.
+//
+// The staging stores write one row (A) or right-hand side (B) from several
+// lanes at k rows 1 KiB apart, which would all land in the same LDS banks; the
+// row / column index within a staged k row is therefore XORed with a function
+// of k (stg_swz_a / stg_swz_b) that spreads every 8 consecutive lanes of a
+// store over the 8 16-byte bank groups.  The XOR only permutes indices within
+// aligned groups of 16, so the fragment reads (16 consecutive rows or columns
+// of one k row) stay conflict-free.
 typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 static_assert(kMmK == kNzChunk, "nonzero-chunk lists count MFMA staging chunks");
+
+// A is staged by 4 lanes per row, each taking 4 consecutive k: lanes 4 i + j
+// write row i at k = 4 j + u.
+__device__ __forceinline__ int stg_swz_a(int k) { return 2 * ((k >> 2) & 3); }
+// B is staged by 16 / BPT lanes per right-hand side, each taking BPT
+// consecutive k (BPT = TN / 16).
+template <int TN>
+__device__ __forceinline__ int stg_swz_b(int k) {
+  constexpr int BPT = kMmK * TN / 256;
+  constexpr int G = kMmK / BPT;  // lanes per right-hand side
+  return G >= 16 ? k : (k / BPT) * (8 / G);
+}
 
 template <int TN, int KS, int NS>
 __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTableT<NS> tab,
@@ -575,22 +595,25 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   auto stage = [&](const Stage& S) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      As[grp][sc + u][sr] = (S.live && arow_ok && S.c0 + sc + u < S.kc) ? S.pa[u] : make_double2(0.0, 0.0);
+      As[grp][sc + u][sr ^ stg_swz_a(sc + u)] =
+          (S.live && arow_ok && S.c0 + sc + u < S.kc) ? S.pa[u] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
       double2 v = S.has_q ? S.pq[u] : make_double2(0.0, 0.0);
       if (S.has_s) v = cadd(v, cmul(S.be, S.ps[u]));
-      Bs[grp][bc + u][bq] = (S.live && brhs_ok && S.c0 + bc + u < S.kc) ? v : make_double2(0.0, 0.0);
+      Bs[grp][bc + u][bq ^ stg_swz_b<TN>(bc + u)] =
+          (S.live && brhs_ok && S.c0 + bc + u < S.kc) ? v : make_double2(0.0, 0.0);
     }
   };
   auto multiply = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kMmK; kk += 4) {
-      const double2 av = As[grp][kk + (lane >> 4)][wr + (lane & 15)];
+      const int kr = kk + (lane >> 4);
+      const double2 av = As[grp][kr][wr + ((lane & 15) ^ stg_swz_a(kr))];
       const double as = av.x + av.y;
       double2 bv[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = Bs[grp][kk + (lane >> 4)][b * 16 + (lane & 15)];
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[grp][kr][b * 16 + ((lane & 15) ^ stg_swz_b<TN>(kr))];
 #pragma unroll
       for (int b = 0; b < NB; ++b) p1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, p1[b], 0, 0, 0);
 #pragma unroll

@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTab
     }
     const bool mult = live;
     const bf16x8 ar_h = pa[0], ar_l = pa[1], ai_h = pa[2], ai_l = pa[3];
-    __syncthreads();
+    lds_barrier();
     fetch((i + 1) * KS + grp);
     if (mult) {
       const bf16x8* P0 = reinterpret_cast<const bf16x8*>(gst);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTab
         acc[3][b] = T::mfma(ai_l, xr_h, acc[3][b]);
       }
     }
-    __syncthreads();
+    lds_barrier();  // the next chunk's loads stay in flight
   }
 
   if constexpr (KS > 1) {
@@ -535,10 +535,10 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTab
 
 // The wide form specialised for launches whose jobs all have two terms with
 // an input Q each and, when HAS_S, an S each (the Gauss-Seidel sweep steps and
-// the reflection terms).  Every fetch issues the same loads with no branches
-// (chunk index clamped, term pointers picked by selects), so two chunks can be
-// in flight while a third is multiplied; the arithmetic and its order are those
-// of block_split_wide_kernel<NB, 1>.
+// the reflection terms).  Every fetch of a chunk inside the slice issues the
+// same loads with no branches (term pointers picked by selects), so two chunks
+// can be in flight while a third is multiplied; the arithmetic and its order
+// are those of block_split_wide_kernel<NB, 1>.
 template <typename T, int NB, bool HAS_S, int NS>
 __global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT<NS> tab, int kslices,
                                                                  const Job* __restrict__ jobs1) {
@@ -598,7 +598,8 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT
   };
   auto fetch = [&](InFlight& F, int qi) {
     F.qi = qi;
-    const int q = qbeg + min(qi, nchunks - 1);
+    if (qi >= nchunks) return;  // past the slice (workgroup-uniform): staged as zeros, not multiplied
+    const int q = qbeg + qi;
     const bool t1 = q >= nkt;
     const int kt = t1 ? q - nkt : q;
     const typename T::E* Mt = (t1 ? M1 : M0) + ((size_t)rtc * nkt + kt) * 4 * 512;
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT
   // otherwise
   constexpr int DEPTH = (NB == 2 && HAS_S) ? 3 : 2;
   if (nchunks > 0) {  // workgroup-uniform
-    InFlight f[DEPTH];
+    InFlight f[DEPTH] = {};
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) fetch(f[d], d);
     for (int i = 0; i < nchunks; i += DEPTH) {
