@@ -423,6 +423,31 @@ def hbm_probe(torch, sizes_mb=(12.5, 25, 50, 100, 200, 400, 1600), reps=20):
     return out
 
 
+def zgemm_probe(torch, shapes=((32, 440, 128), (32, 440, 64), (16, 880, 128), (1, 4096, 4096)), reps=20):
+    """The vendor library on the block-apply contraction, for comparison: torch.bmm (rocBLAS / hipBLASLt) of
+    b contiguous complex float64 blocks n x n times n x k, timed with HIP events on the current stream; 8
+    flops per complex multiply-add, as the roofline counts them."""
+    out = []
+    g = torch.Generator(device="cuda:0").manual_seed(0)
+    for b, n, k in shapes:
+        A = torch.randn(b, n, n, dtype=torch.complex128, device="cuda:0", generator=g)
+        X = torch.randn(b, n, k, dtype=torch.complex128, device="cuda:0", generator=g)
+        for _ in range(3):
+            torch.bmm(A, X)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.bmm(A, X)
+        e1.record()
+        e1.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3 / reps
+        out.append({"batch": b, "n": n, "k": k, "us": 1e6 * dt, "alg_tflops": 8.0 * b * n * n * k / dt / 1e12})
+        log(f"  zgemm probe {b} x ({n} x {n}) @ ({n} x {k}): {out[-1]['us']:.1f} us, "
+            f"{out[-1]['alg_tflops']:.1f} algorithmic TFLOP/s")
+        del A, X
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -532,6 +557,9 @@ def main():
                          "cavity vs frequency); on with --all-forms")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time plain copies and reads of 12.5 MB..1.6 GB (the achievable HBM rate per launch size)")
+    ap.add_argument("--zgemm-probe", action="store_true",
+                    help="also time torch.bmm (the vendor library) on complex float64 block products of the "
+                         "block-apply shapes, for comparison with the MFMA kernel")
     ap.add_argument("--tune-cache", default="", metavar="PATH",
                     help="tuning cache file: loaded before the forms are tuned (if it exists) and written after, so "
                          "that profiled runs use the launch shapes an unprofiled run chose")
@@ -641,6 +669,10 @@ def main():
     if args.hbm_probe:
         log("hbm probe")
         probe = hbm_probe(torch)
+    zprobe = None
+    if args.zgemm_probe:
+        log("zgemm probe")
+        zprobe = zgemm_probe(torch)
 
     spec = None
     if args.spectral or args.all_forms:
@@ -699,6 +731,8 @@ def main():
         out["spectral"] = spec
     if probe is not None:
         out["hbm_probe"] = probe
+    if zprobe is not None:
+        out["zgemm_probe"] = zprobe
     if not args.no_cpu:
         log("cpu baseline: oracle direct solve (factorisation and a 32-source batch, medians of 3)")
         cb = cpu_direct_baseline(prob, f)
