@@ -100,6 +100,12 @@ __device__ __forceinline__ int xcd_logical(int i, int G) {
 // across it (a full __syncthreads() also drains the vector-memory counter).
 __device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Slot of B-operand lane l in a staged 16-column plane tile (64 slots of 16 bytes).  The staging
+// stores write 4-byte pairs: the 16 lanes of a column put row pairs into slots l, l + 16, l + 32 and
+// l + 48, which share LDS banks; XORing bits 1-2 of the slot with bits 4-5 spreads one 32-lane
+// store over all 32 banks, and any 8 consecutive operand reads still cover the 8 bank groups.
+__device__ __forceinline__ int sp_swz(int l) { return l ^ (2 * ((l >> 4) & 3)); }
+
 // Q + beta S of one complex input entry, in float32 (the split pair keeps at most 22 bits of it)
 __device__ __forceinline__ float2 combine_f(double2 q, double2 sv, double2 beta, bool has_q, bool has_s) {
   float2 v = has_q ? make_float2(static_cast<float>(q.x), static_cast<float>(q.y)) : make_float2(0.f, 0.f);
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTab
         T::splitf(v.y * static_cast<float>(T::kX), h[2][u], h[3][u]);
       }
       // rows 2 kp, 2 kp + 1 sit at positions (2 kp) % 8, +1 of lane (2 kp / 8) * 16 + c % 16 of tile c / 16
-      const int l = ((2 * kp) >> 3) * 16 + (c & 15);
+      const int l = sp_swz(((2 * kp) >> 3) * 16 + (c & 15));
       const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {
@@ -457,8 +463,9 @@ __global__ __launch_bounds__(256 * KS) void block_split_wide_kernel(const SegTab
       const bf16x8* P3 = reinterpret_cast<const bf16x8*>(gst + 3 * kPlane);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
-        const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
+        const int sl = b * 64 + sp_swz(lane);
+        const bf16x8 xr_h = P0[sl], xr_l = P1[sl];
+        const bf16x8 xi_h = P2[sl], xi_l = P3[sl];
         acc[0][b] = T::mfma(ar_h, xr_h, acc[0][b]);
         acc[1][b] = T::mfma(ai_h, xi_h, acc[1][b]);
         acc[2][b] = T::mfma(ar_h, xi_h, acc[2][b]);
@@ -643,7 +650,7 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT
         T::splitf(v.x * static_cast<float>(T::kX), h[0][u], h[1][u]);
         T::splitf(v.y * static_cast<float>(T::kX), h[2][u], h[3][u]);
       }
-      const int l = ((2 * kp) >> 3) * 16 + (c & 15);
+      const int l = sp_swz(((2 * kp) >> 3) * 16 + (c & 15));
       const size_t off = ((size_t)(c >> 4) * 64 + l) * sizeof(bf16x8) + (size_t)((2 * kp) & 7) * 2;
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) {
@@ -661,8 +668,9 @@ __global__ __launch_bounds__(256) void block_split_stream_kernel(const SegTableT
     const bf16x8* P3 = reinterpret_cast<const bf16x8*>(gst + 3 * kPlane);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const bf16x8 xr_h = P0[b * 64 + lane], xr_l = P1[b * 64 + lane];
-      const bf16x8 xi_h = P2[b * 64 + lane], xi_l = P3[b * 64 + lane];
+      const int sl = b * 64 + sp_swz(lane);
+      const bf16x8 xr_h = P0[sl], xr_l = P1[sl];
+      const bf16x8 xi_h = P2[sl], xi_l = P3[sl];
       acc[0][b] = T::mfma(ar_h, xr_h, acc[0][b]);
       acc[1][b] = T::mfma(ai_h, xi_h, acc[1][b]);
       acc[2][b] = T::mfma(ar_h, xi_h, acc[2][b]);
