@@ -295,9 +295,10 @@ KERNELS = {
 }
 
 
-def measured_traffic(kernel, cls, workload, precision):
+def measured_traffic(kernel, cls, workload, precision, tile_rhs=None):
     """HBM bytes per launch recorded by a rocprofv3 FETCH_SIZE/WRITE_SIZE profile under profiles/, if the
-    kernel source it was measured on is the current one (else None)."""
+    kernel source it was measured on is the current one and the record's tile width (when it names one) is
+    the one this run's launches used (else None)."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -307,6 +308,8 @@ def measured_traffic(kernel, cls, workload, precision):
             kv = dict(tok.split("=", 1) for tok in line.split()[1:])
             if (kv.get("kernel"), kv.get("class"), kv.get("workload"), kv.get("precision")) != \
                     (kernel, cls, workload, precision):
+                continue
+            if "tile_rhs" in kv and (tile_rhs is None or int(kv["tile_rhs"]) != tile_rhs):
                 continue
             src = os.path.join(ROOT, kv["source"])
             if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == kv["sha256"]:
@@ -326,7 +329,9 @@ def roofline(form):
         name = "block_split_kernel"
     elif dt not in ("bf16", "f16") and form["nrhs"] <= 4:
         name = "block_gemv_kernel"
-    traffic = measured_traffic(name, cls, form.get("workload"), form["precision"])
+    tuned = (form.get("tuned") or {}).get(cls)
+    traffic = measured_traffic(name, cls, form.get("workload"), form["precision"],
+                               tuned["tile_rhs"] if tuned else None)
     base = {"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
             "class": cls, "kernel": name, "launches_per_step": st["launches"] / k["nprof"],
             "avg_launch_us": 1e3 * st["kernel_ms"] / st["launches"],

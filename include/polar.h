@@ -381,8 +381,10 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * rules.  pt_tune times, for nrhs right-hand sides, every candidate shape of
  * each launch class on one representative launch of that class (HIP events,
  * one warm-up and three timed runs on the solver's own work buffers, whose
- * contents it overwrites) and keeps the fastest; later calls with the same
- * nrhs use it.  Candidates: float64 MFMA tiles of 16, 32 or 64 right-hand
+ * contents it overwrites) and keeps the fastest if it is at least 2% faster
+ * than the built-in rule's shape (else the rule's shape stays, so that shapes
+ * within the timing noise of each other do not change from run to run);
+ * later calls with the same nrhs use it.  Candidates: float64 MFMA tiles of 16, 32 or 64 right-hand
  * sides, with the 16-wide tile's chunks split over 1, 2 or 4 wave groups;
  * split tiles of 32 or 64 right-hand sides, split over 1..16 k-slices.
  * Classes with a single form (the row-streaming kernel for <= 4 right-hand
@@ -402,8 +404,9 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
 typedef struct {
   int32_t cls;        /* pt_launch_class                                          */
   int32_t tried;      /* candidate shapes timed (0: no launch, or not tuned)       */
-  int32_t tile_rhs;   /* chosen right-hand sides per tile (0: rule / single form)  */
-  int32_t ksplit;     /* chosen wave groups or k-slices per tile                   */
+  int32_t tile_rhs;   /* right-hand sides per tile of the shape in use, the rule's  */
+                      /* when no candidate replaced it (0: single form)            */
+  int32_t ksplit;     /* wave groups or k-slices per tile of that shape            */
   double best_us;     /* its mean launch time                                      */
   double default_us;  /* the built-in rule's mean launch time                      */
   int32_t cached;     /* 1: taken from the tuning cache, not timed                 */

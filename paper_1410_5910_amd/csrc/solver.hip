@@ -2686,6 +2686,30 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
   HIPCHK(hipStreamSynchronize(S->st));
   drop_graphs(S);  // captured launches carry the old shapes
   constexpr int kReps = 3;
+  constexpr double kTuneMargin = 0.98;
+  // the shape the built-in rules give a launch: reported when no candidate replaces it
+  auto rule_shape = [&](const Launch& Lc, int32_t& tile, int32_t& ks) {
+    tile = 0;
+    ks = 0;
+    if (Lc.split) {
+      if (nrhs > 16) {
+        tile = 32;
+        ks = split_kslices(Lc.njobs, S->NX, nrhs, 32);
+        if ((size_t)ks * Lc.njobs * nrhs * S->NX > S->part.n) ks = 1;  // no room for the partial tiles
+      } else {
+        const long tasks = (long)Lc.njobs * ((S->NX + 15) / 16) * ((nrhs + 15) / 16);
+        tile = 16;
+        ks = tasks >= 4096 ? 1 : tasks >= 2048 ? 2 : 4;
+      }
+      return;
+    }
+    const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
+    if (!Lc.plr && !Lc.f32 && g.mfma) {
+      tile = g.mfma;
+      const long tiles = (long)Lc.njobs * g.ntiles * ((nrhs + g.mfma - 1) / g.mfma);
+      ks = g.mfma == 16 ? (tiles < 256 ? 4 : tiles < 512 ? 2 : 1) : 1;
+    }
+  };
   const int L = S->L;
   // work buffers as inputs and outputs of the trial launches (contents overwritten)
   HIPCHK(hipMemsetAsync(S->W.p, 0, S->W.n * sizeof(double2), S->st));
@@ -2733,6 +2757,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
             e.ksplit = it->second.cfg.tn ? it->second.cfg.ks : it->second.cfg.sp.kslices;
           } else {
             S->tune[cls].erase(nrhs);
+            rule_shape(*Lc, e.tile_rhs, e.ksplit);
           }
           e.best_us = it->second.best_us;
           e.default_us = it->second.default_us;
@@ -2779,11 +2804,14 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       e.best_us = e.default_us;
       e.tried = 1;
       const TuneCfg* best = nullptr;
+      // a candidate replaces the rules' shape only when it is at least 2% faster, so that
+      // shapes within the timing noise of each other do not change from run to run
+      const double bar = kTuneMargin * e.default_us;
       for (const TuneCfg& c : cands) {
         double us = 0;
         PTCHK(time_launch(S, *Lc, nrhs, ld, b, &c, kReps, us));
         ++e.tried;
-        if (us < e.best_us) {
+        if (us < e.best_us && us < bar) {
           e.best_us = us;
           best = &c;
         }
@@ -2795,6 +2823,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
         e.ksplit = best->tn ? best->ks : best->sp.kslices;
       } else {
         S->tune[cls].erase(nrhs);
+        rule_shape(*Lc, e.tile_rhs, e.ksplit);
       }
       TuneVal v;
       v.has_cfg = best ? 1 : 0;
