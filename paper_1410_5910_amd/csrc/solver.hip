@@ -2290,12 +2290,15 @@ pt_status solve_merged(int P, pt_solver* const* s, const int32_t* nrhs, const do
     for (int k = 0; k < p; ++k) use_lanes = use_lanes && lanes[k] != lanes[p];
   }
   std::vector<hipEvent_t> evs(P + 1, nullptr);
-  // every exit gives the solvers back their streams, stops recording and frees the events
+  // every exit drains the problems' streams (an early one may leave copies into
+  // this call's host vectors, or waits on its events, in flight), gives the
+  // solvers back their streams, stops recording and frees the events
   struct Restore {
     pt_solver* const* s;
     std::vector<Prob>& q;
     std::vector<hipEvent_t>& evs;
     ~Restore() {
+      for (size_t p = 0; p < q.size(); ++p) (void)hipStreamSynchronize(q[p].own);
       for (size_t p = 0; p < q.size(); ++p) {
         s[p]->st = q[p].own;
         s[p]->rec = nullptr;
@@ -3383,6 +3386,12 @@ pt_status pt_solve(pt_solver* S, int32_t nrhs, const double* f, double* u, int32
   bool used_learned = false;
   std::vector<double> nr(nrhs), be(nrhs), es(nrhs);
   std::vector<int32_t> it(nrhs), dn(nrhs), kept(nrhs, 0);
+  // an early exit may leave copies into these vectors in flight: drain the
+  // stream before they go (a no-op after the final synchronisation)
+  struct Drain {
+    hipStream_t st;
+    ~Drain() { (void)hipStreamSynchronize(st); }
+  } drain{S->st};
   // true residual ||s - A x|| / ||s|| in float64, with the GMRES data, to the host
   auto residuals = [&]() -> pt_status {
     PTCHK(system_A(S, S->x.p, S->tmp.p, nrhs));
