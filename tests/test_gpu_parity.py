@@ -480,6 +480,11 @@ def test_tune_keeps_results(precision, nrhs):
         assert e["tried"] >= 1 and e["best_us"] > 0 and e["best_us"] <= e["default_us"]
         if nrhs > 4 and precision == "f64":
             assert e["tried"] > 1, cls  # float64 MFMA shapes were timed
+        if e["tried"] > 1:
+            # the shape in use is reported, the rule's included; a candidate replaces the rule's shape
+            # only when at least 2% faster
+            assert e["tile_rhs"] in (16, 32, 64) and e["ksplit"] >= 1, (cls, e)
+            assert e["best_us"] == e["default_us"] or e["best_us"] < 0.98 * e["default_us"], (cls, e)
     s = gs.layout()  # the solver is still usable
     assert s["L"] == prob.L
     u1, info = gs.solve(f)
