@@ -60,8 +60,15 @@ struct PlrSet {
   void release();
 };
 
+// Workspace of a PLR apply whose tiles' leaf lists are sliced over several
+// workgroups: one 64-row partial per (tile, right-hand side, slice).
+constexpr size_t kPlrPartEntries = (size_t)1 << 17;
+
 // Y = P + alpha * sum_t PLR_t (Q_t + beta_t S_t) for jobs whose M_t point at PlrBlockDev.
+// A launch with few tiles spreads each tile's leaves over several workgroups
+// whose partial tiles go to `part` (part_n complex entries) and are summed in a
+// fixed order by a second kernel; without a workspace one workgroup takes a tile.
 hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1);
+                            hipEvent_t ev0, hipEvent_t ev1, double2* part = nullptr, size_t part_n = 0);
 
 }  // namespace polar

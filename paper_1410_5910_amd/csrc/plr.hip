@@ -547,7 +547,7 @@ constexpr int kXs = 128;
 
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restrict__ jobs, int n, int ntiles,
-                                                            int64_t ld, Bases bases) {
+                                                            int64_t ld, Bases bases, double2* __restrict__ out_part) {
   __shared__ double2 part[NW][64];
   __shared__ double2 tb[NW][kPlrMaxRank];
   __shared__ double2 xs[NW][kXs];
@@ -555,6 +555,7 @@ __global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restric
   const int tile = blockIdx.x % ntiles;
   const Job& J = jobs[blockIdx.x / ntiles];
   const int r = blockIdx.y;
+  const int slices = gridDim.z, slice = blockIdx.z;  // slice z takes leaves z NW + w, step slices NW
   const int row = tile * 64 + lane;
   double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 1
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restric
     const double2* sp = sr.buf >= 0 ? zbase(bases, sr.buf) + sr.off + (int64_t)r * ld : nullptr;
     const double2 be = J.beta[t];
     const int l0 = B->tile_ptr[tile], l1 = B->tile_ptr[tile + 1];
-    for (int li = l0 + wave; li < l1; li += NW) {
+    for (int li = l0 + slice * NW + wave; li < l1; li += slices * NW) {
       const PlrLeafDev L = B->leaves[B->tile_leaf[li]];
       if (L.k == 0) continue;  // a zero leaf
       const bool in = row >= L.r0 && row < L.r0 + L.m;
@@ -621,14 +622,36 @@ __global__ __launch_bounds__(64 * NW) void plr_apply_kernel(const Job* __restric
   __syncthreads();  // every wave is done with its LDS rows before they hold the partials
   part[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && row < n) {
+  if (wave == 0) {
     double2 s = part[0][lane];
 #pragma unroll
     for (int w = 1; w < NW; ++w) s = zadd(s, part[w][lane]);
-    double2 y = zmul(J.alpha, s);
-    if (J.P.buf >= 0) y = zadd(y, zbase(bases, J.P.buf)[J.P.off + (int64_t)r * ld + row]);
-    zbase(bases, J.Y.buf)[J.Y.off + (int64_t)r * ld + row] = y;
+    if (slices > 1) {  // this slice's partial tile; plr_reduce_kernel finishes the rows
+      out_part[(((size_t)r * gridDim.x + blockIdx.x) * slices + slice) * 64 + lane] = s;
+    } else if (row < n) {
+      double2 y = zmul(J.alpha, s);
+      if (J.P.buf >= 0) y = zadd(y, zbase(bases, J.P.buf)[J.P.off + (int64_t)r * ld + row]);
+      zbase(bases, J.Y.buf)[J.Y.off + (int64_t)r * ld + row] = y;
+    }
   }
+}
+
+// Y = P + alpha * (sum over the slices of a tile's partials, in slice order);
+// grid: (jobs x tiles, right-hand sides), one 64-lane wave per tile
+__global__ __launch_bounds__(64) void plr_reduce_kernel(const Job* __restrict__ jobs, int n, int ntiles, int64_t ld,
+                                                        Bases bases, int slices, const double2* __restrict__ part) {
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.x % ntiles;
+  const Job& J = jobs[blockIdx.x / ntiles];
+  const int r = blockIdx.y;
+  const int row = tile * 64 + lane;
+  if (row >= n) return;
+  const double2* p = part + ((size_t)r * gridDim.x + blockIdx.x) * slices * 64 + lane;
+  double2 s = p[0];
+  for (int z = 1; z < slices; ++z) s = zadd(s, p[(size_t)z * 64]);
+  double2 y = zmul(J.alpha, s);
+  if (J.P.buf >= 0) y = zadd(y, zbase(bases, J.P.buf)[J.P.off + (int64_t)r * ld + row]);
+  zbase(bases, J.Y.buf)[J.Y.off + (int64_t)r * ld + row] = y;
 }
 
 }  // namespace
@@ -931,16 +954,31 @@ void PlrSet::release() {
 }
 
 hipError_t launch_plr_apply(const Job* jobs, int njobs, int n, int nrhs, int64_t ld, Bases bases, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1) {
+                            hipEvent_t ev0, hipEvent_t ev1, double2* part, size_t part_n) {
   if (njobs <= 0) return hipSuccess;
   const int ntiles = (n + 63) / 64;
-  // few workgroups (one source, a sweep step's four blocks): 16 waves share a tile's leaves
-  if ((long)njobs * ntiles * nrhs < 512)
-    hipExtLaunchKernelGGL(plr_apply_kernel<16>, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(1024), 0, st, ev0,
-                          ev1, 0, jobs, n, ntiles, ld, bases);
-  else
-    hipExtLaunchKernelGGL(plr_apply_kernel<4>, dim3((unsigned)njobs * ntiles, (unsigned)nrhs), dim3(256), 0, st, ev0,
-                          ev1, 0, jobs, n, ntiles, ld, bases);
+  const long tiles = (long)njobs * ntiles * nrhs;
+  const dim3 grid((unsigned)njobs * ntiles, (unsigned)nrhs);
+  if (tiles >= 512) {
+    hipExtLaunchKernelGGL(plr_apply_kernel<4>, grid, dim3(256), 0, st, ev0, ev1, 0, jobs, n, ntiles, ld, bases,
+                          nullptr);
+    return hipGetLastError();
+  }
+  // few tiles (one source; a sweep step has four blocks): a tile's leaves are
+  // spread over up to 16 four-wave workgroups, about 1024 in the launch
+  int slices = (int)std::min<long>(16, (1024 + tiles - 1) / tiles);
+  while (slices > 1 && (size_t)slices * tiles * 64 > part_n) --slices;
+  if (!part || slices < 2) {  // no workspace: 16 waves of one workgroup share a tile's leaves
+    hipExtLaunchKernelGGL(plr_apply_kernel<16>, grid, dim3(1024), 0, st, ev0, ev1, 0, jobs, n, ntiles, ld, bases,
+                          nullptr);
+    return hipGetLastError();
+  }
+  hipExtLaunchKernelGGL(plr_apply_kernel<4>, dim3(grid.x, grid.y, (unsigned)slices), dim3(256), 0, st, ev0, nullptr,
+                        0, jobs, n, ntiles, ld, bases, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL(plr_reduce_kernel, grid, dim3(64), 0, st, nullptr, ev1, 0, jobs, n, ntiles, ld, bases, slices,
+                        part);
   return hipGetLastError();
 }
 

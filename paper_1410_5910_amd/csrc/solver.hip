@@ -145,7 +145,8 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
   }
   // with profiling on, the dispatch itself stamps e0 / e1 at kernel start / end
   if (Lc.plr)
-    HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1));
+    HIPCHK(launch_plr_apply(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, S->plr_part.p,
+                            S->plr_part.n));
   else if (Lc.split) {
     SplitCfg sc = tc ? tc->sp : SplitCfg{0, 0};
     if (sc.stream && sc.stream != Lc.two_term) sc.stream = 0;  // the form only serves launches it fits
@@ -1517,6 +1518,7 @@ pt_status alloc_online(pt_solver* S) {
         }
       HIPCHK(S->part.alloc(need));
     }
+    if (S->use_plr) HIPCHK(S->plr_part.alloc(kPlrPartEntries));
     // source-to-layer activity tables
     const int L = S->L;
     std::vector<int32_t> rl(S->sumR), os(L), no(L);
@@ -2008,6 +2010,7 @@ void pt_free(pt_solver* S) {
   S->blk32.release();
   S->blkbf.release();
   S->part.release();
+  S->plr_part.release();
   release_green(S);
   S->gsum_dst.release();
   S->gsum_src.release();

@@ -181,6 +181,7 @@ struct pt_solver {
   bool split_f16 = false;    // the split planes are float16 (PT_SPLIT_F16), else bfloat16
   double split_alpha = 1.0;  // factor folded into the jobs of split launches (float16: 1 / both scales)
   DevBuf<float2> part;     // k-slice partial tiles of small split launches
+  DevBuf<double2> plr_part;  // leaf-slice partial tiles of small compressed-block launches
   // interface Green's functions of the pre-solve: per layer, rows 1 and n of
   // (A^l)^-1 over the owned rows, NX x (n NX) each (null: line-by-line)
   DevBuf<double2> green;
