@@ -1282,19 +1282,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// grid: (m, nrhs), 256 threads
-__global__ __launch_bounds__(kThreads) void kdot_kernel(const double2* __restrict__ V, const double2* __restrict__ w,
-                                                        double2* __restrict__ hout, int nrhs, int64_t N) {
+// The Krylov reductions (one dot product or norm per workgroup: a few to a
+// few hundred workgroups per launch) use 1024-thread workgroups, so that a
+// launch for one or a few sources still has many loads in flight; the 16 wave
+// sums are added in wave order.
+constexpr int kRedThreads = 1024;
+constexpr int kRedWaves = kRedThreads / 64;
+
+// grid: (m, nrhs), kRedThreads threads
+__global__ __launch_bounds__(kRedThreads) void kdot_kernel(const double2* __restrict__ V, const double2* __restrict__ w,
+                                                           double2* __restrict__ hout, int nrhs, int64_t N) {
   const int i = blockIdx.x, r = blockIdx.y;
   const double2* v = V + ((int64_t)i * nrhs + r) * N;
   const double2* x = w + (int64_t)r * N;
   double re = 0.0, im = 0.0;
-  for (int64_t e = threadIdx.x; e < N; e += kThreads) {
+  for (int64_t e = threadIdx.x; e < N; e += kRedThreads) {
     const double2 t = cconjmul(v[e], x[e]);
     re += t.x;
     im += t.y;
   }
-  __shared__ double sre[4], sim[4];
+  __shared__ double sre[kRedWaves], sim[kRedWaves];
   re = wave_sum(re);
   im = wave_sum(im);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1303,8 +1310,14 @@ __global__ __launch_bounds__(kThreads) void kdot_kernel(const double2* __restric
     sim[wv] = im;
   }
   __syncthreads();
-  if (threadIdx.x == 0) hout[(int64_t)i * nrhs + r] = make_double2(sre[0] + sre[1] + sre[2] + sre[3],
-                                                                  sim[0] + sim[1] + sim[2] + sim[3]);
+  if (threadIdx.x == 0) {
+    double a = sre[0], b = sim[0];
+    for (int k = 1; k < kRedWaves; ++k) {
+      a += sre[k];
+      b += sim[k];
+    }
+    hout[(int64_t)i * nrhs + r] = make_double2(a, b);
+  }
 }
 
 __global__ void kupdate_kernel(const double2* __restrict__ V, double2* __restrict__ w, const double2* __restrict__ h,
@@ -1326,17 +1339,21 @@ __global__ void kupdate_kernel(const double2* __restrict__ V, double2* __restric
   }
 }
 
-__global__ __launch_bounds__(kThreads) void knorm_kernel(const double2* __restrict__ w, double* __restrict__ nrm,
-                                                         int64_t N) {
+__global__ __launch_bounds__(kRedThreads) void knorm_kernel(const double2* __restrict__ w, double* __restrict__ nrm,
+                                                            int64_t N) {
   const int r = blockIdx.x;
   const double2* x = w + (int64_t)r * N;
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < N; e += kThreads) s += x[e].x * x[e].x + x[e].y * x[e].y;
-  __shared__ double ss[4];
+  for (int64_t e = threadIdx.x; e < N; e += kRedThreads) s += x[e].x * x[e].x + x[e].y * x[e].y;
+  __shared__ double ss[kRedWaves];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) ss[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) nrm[r] = sqrt(ss[0] + ss[1] + ss[2] + ss[3]);
+  if (threadIdx.x == 0) {
+    double t = ss[0];
+    for (int k = 1; k < kRedWaves; ++k) t += ss[k];
+    nrm[r] = sqrt(t);
+  }
 }
 
 __global__ void kscale_kernel(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N) {
@@ -1694,7 +1711,7 @@ hipError_t launch_add(double2* y, const double2* x, const double2* z, double sig
 
 hipError_t launch_kdot(const double2* V, const double2* w, double2* hout, int m, int nrhs, int64_t N,
                        hipStream_t st) {
-  hipLaunchKernelGGL(kdot_kernel, dim3(m, nrhs), dim3(kThreads), 0, st, V, w, hout, nrhs, N);
+  hipLaunchKernelGGL(kdot_kernel, dim3(m, nrhs), dim3(kRedThreads), 0, st, V, w, hout, nrhs, N);
   return hipGetLastError();
 }
 hipError_t launch_kupdate(const double2* V, double2* w, const double2* h, double2* hacc, int m, int nrhs, int64_t N,
@@ -1704,7 +1721,7 @@ hipError_t launch_kupdate(const double2* V, double2* w, const double2* h, double
   return hipGetLastError();
 }
 hipError_t launch_knorm(const double2* w, double* nrm, int nrhs, int64_t N, hipStream_t st) {
-  hipLaunchKernelGGL(knorm_kernel, dim3(nrhs), dim3(kThreads), 0, st, w, nrm, N);
+  hipLaunchKernelGGL(knorm_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, w, nrm, N);
   return hipGetLastError();
 }
 hipError_t launch_kscale(double2* v, const double2* w, const double* nrm, int nrhs, int64_t N, hipStream_t st) {
