@@ -1082,25 +1082,27 @@ __global__ void scatter_source_kernel(const double2* __restrict__ f, double2* __
 }
 
 // amax[r * L + l] = max |f[r]|^2 over the owned rows of layer l (fixed-order tree, deterministic)
-__global__ __launch_bounds__(kThreads) void source_activity_kernel(const double2* __restrict__ f,
-                                                                    double* __restrict__ amax,
-                                                                    const int32_t* __restrict__ own_start,
-                                                                    const int32_t* __restrict__ n_own, int L,
-                                                                    int NZ, int NX) {
-  __shared__ double red[kThreads];
+// 1024 threads per (layer, source): with one source a launch has only L workgroups
+constexpr int kActThreads = 1024;
+__global__ __launch_bounds__(kActThreads) void source_activity_kernel(const double2* __restrict__ f,
+                                                                       double* __restrict__ amax,
+                                                                       const int32_t* __restrict__ own_start,
+                                                                       const int32_t* __restrict__ n_own, int L,
+                                                                       int NZ, int NX) {
+  __shared__ double red[kActThreads];
   const int l = blockIdx.x, r = blockIdx.y;
   const double2* fr = f + ((size_t)r * NZ + own_start[l]) * NX;
   const int64_t cnt = (int64_t)n_own[l] * NX;
   // a max that keeps NaN (fmax would drop it): a NaN source must reach every layer
   auto nmax = [](double a, double b) { return (b > a || b != b) ? b : a; };
   double mx = 0.0;
-  for (int64_t e = threadIdx.x; e < cnt; e += kThreads) {
+  for (int64_t e = threadIdx.x; e < cnt; e += kActThreads) {
     const double2 v = fr[e];
     mx = nmax(mx, v.x * v.x + v.y * v.y);
   }
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = kActThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
@@ -1599,8 +1601,8 @@ hipError_t launch_scatter_source(const double2* f, double2* W, const int32_t* ro
 
 hipError_t launch_source_activity(const double2* f, double* amax, const int32_t* own_start, const int32_t* n_own,
                                   int L, int NZ, int NX, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(source_activity_kernel, dim3(L, nrhs), dim3(kThreads), 0, st, f, amax, own_start, n_own, L, NZ,
-                     NX);
+  hipLaunchKernelGGL(source_activity_kernel, dim3(L, nrhs), dim3(kActThreads), 0, st, f, amax, own_start, n_own, L,
+                     NZ, NX);
   return hipGetLastError();
 }
 
