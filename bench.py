@@ -191,7 +191,7 @@ def run_uneven(P, torch, precision, steps, warmup, probs, tol=1e-8, tune=True):
     el_merged = time.perf_counter() - t1
     out = {"workload": "uneven8", "precision": precision, "blocks": "dense", "nrhs": nrhs, "gs_iters": 2,
            "solves_per_s": steps * nrhs / el, "ms_per_step": 1e3 * el / steps, "setup_s": setup_s,
-           "tune_s": tune_s, "tuned": tune, "launch": "pt_solve_batch: one host thread and stream per problem",
+           "tune_s": tune_s, "tile_shapes_tuned": tune, "launch": "pt_solve_batch: one host thread and stream per problem",
            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "merged_ms_per_step": 1e3 * el_merged / steps,
            "iterations": sorted({i["iters"] for r in res for i in r[1]}),
@@ -329,7 +329,8 @@ def roofline(form):
         name = "block_split_kernel"
     elif dt not in ("bf16", "f16") and form["nrhs"] <= 4:
         name = "block_gemv_kernel"
-    tuned = (form.get("tuned") or {}).get(cls)
+    tuned = form.get("tuned")
+    tuned = tuned.get(cls) if isinstance(tuned, dict) else None
     traffic = measured_traffic(name, cls, form.get("workload"), form["precision"],
                                tuned["tile_rhs"] if tuned else None)
     base = {"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
