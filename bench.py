@@ -292,6 +292,10 @@ KERNELS = {
     ("presolve", "split-f16"): ("block_mfma64_kernel", "f64"),
     ("sweep", "split-f16"): ("block_split_wide_kernel", "f16"),
     ("reflect", "split-f16"): ("block_split_wide_kernel", "f16"),
+    # float32 preconditioner blocks on the FP32 MFMA; the rest of the float32 form is float64
+    ("sweep", "f32"): ("block_mfma64_kernel", "f32"), ("reflect", "f32"): ("block_mfma64_kernel", "f32"),
+    ("local", "f32"): ("block_mfma64_kernel", "f64"), ("operator", "f32"): ("block_mfma64_kernel", "f64"),
+    ("presolve", "f32"): ("block_mfma64_kernel", "f64"),
 }
 
 

@@ -450,6 +450,7 @@ __global__ __launch_bounds__(kThreads) void block_gemm_kernel(const SegTableT<NS
 // aligned groups of 16, so the fragment reads (16 consecutive rows or columns
 // of one k row) stay conflict-free.
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kMmRows = 64;  // rows per workgroup tile
 constexpr int kMmK = 16;     // columns per staged chunk
 static_assert(kMmK == kNzChunk, "nonzero-chunk lists count MFMA staging chunks");
@@ -466,13 +467,37 @@ __device__ __forceinline__ int stg_swz_b(int k) {
   return G >= 16 ? k : (k / BPT) * (8 / G);
 }
 
-template <int TN, int KS, int NS>
+// The same tiles for float32 blocks (the float32 form's preconditioner blocks)
+// on v_mfma_f32_16x16x4f32: its operand layout is that of the float64
+// instruction (one real per lane and operand), its four accumulator entries of
+// lane l are rows 4 (l / 16) + 0..3 instead of 4 i + l / 16.
+template <bool F32>
+struct MmT;
+template <>
+struct MmT<false> {
+  using acc = d4v;
+  static __device__ __forceinline__ d4v mfma(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MmT<true> {
+  using acc = f4v;
+  static __device__ __forceinline__ f4v mfma(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int TN, int KS, int NS, bool F32>
 __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTableT<NS> tab,
                                                                  const Job* __restrict__ jobs1) {
+  using R = typename MatT<F32>::real;   // element type of the blocks and of the MFMA
+  using R2 = typename MatT<F32>::vec;
+  using Acc = typename MmT<F32>::acc;
   constexpr int NB = TN / 16;           // MFMA tiles per wave
   constexpr int BPT = kMmK * TN / 256;  // staged B entries per thread of a group
-  __shared__ double2 As[KS][kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
-  __shared__ double2 Bs[KS][kMmK][TN];
+  __shared__ R2 As[KS][kMmK][kMmRows];  // k-major: fragment reads are 16 consecutive rows
+  __shared__ R2 Bs[KS][kMmK][TN];
   __shared__ int32_t kls[kKlMax];
   const int tid = threadIdx.x & 255;    // thread within its k-group
   const int lane = tid & 63;
@@ -504,18 +529,28 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   const int brhs = col0 + bq;
   const bool brhs_ok = brhs < nrhs;
 
-  // Three real products per complex one (Gauss): p1 = Re A Re B, p2 = Im A Im B,
-  // p3 = (Re A + Im A)(Re B + Im B); then Re = p1 - p2, Im = p3 - p1 - p2.
-  // A quarter fewer MFMAs than the four-product form; the error stays within a
-  // small multiple of the unit roundoff times |A||B| (normwise).
-  d4v p1[NB], p2[NB], p3[NB];
+  // float64: three real products per complex one (Gauss): p1 = Re A Re B,
+  // p2 = Im A Im B, p3 = (Re A + Im A)(Re B + Im B); then Re = p1 - p2,
+  // Im = p3 - p1 - p2.  A quarter fewer MFMAs than the four-product form; the
+  // error stays within a small multiple of the unit roundoff times |A||B|
+  // (normwise).  float32: the four products (p3 = Re A Im B, p4 = Im A Re B,
+  // Im = p3 + p4), since in single precision the cancellation in p3 - p1 - p2
+  // costs the imaginary part digits whenever it is much smaller than the real.
+  Acc p1[NB], p2[NB], p3[NB], p4[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    p1[b] = d4v{0.0, 0.0, 0.0, 0.0};
-    p2[b] = d4v{0.0, 0.0, 0.0, 0.0};
-    p3[b] = d4v{0.0, 0.0, 0.0, 0.0};
+    p1[b] = Acc{};
+    p2[b] = Acc{};
+    p3[b] = Acc{};
+    p4[b] = Acc{};
   }
   const int wr = wave * 16;
+  auto r2 = [](R x, R y) -> R2 {
+    if constexpr (F32)
+      return make_float2(x, y);
+    else
+      return make_double2(x, y);
+  };
 
   // columns and row stride of each term (wide terms: kw > 0), chunks of kMmK per term
   // chunks of term 0 with nonzero inputs (null: all), copied to LDS once so
@@ -542,7 +577,8 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   // vectors): masking and the combination Q + beta S wait until the chunk is
   // staged, so all its loads are in flight together.
   struct Stage {
-    double2 pa[4], pq[BPT], ps[BPT];
+    R2 pa[4];
+    double2 pq[BPT], ps[BPT];
     double2 be;
     int c0, kc;
     bool live, has_q, has_s;
@@ -562,12 +598,14 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
       }
     S.c0 = (kl && t == 0 ? kls[q] : q) * kMmK;
     S.kc = K;
-    const gd2* __restrict__ M =
-        reinterpret_cast<const gd2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * ldm;
+    typedef R rv2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) const rv2 grv2;
+    const grv2* __restrict__ M =
+        reinterpret_cast<const grv2*>(reinterpret_cast<uintptr_t>(J.M[t])) + (size_t)arow * ldm;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const d2v a = M[min(S.c0 + sc + u, K - 1)];
-      S.pa[u] = make_double2(a.x, a.y);
+      const rv2 a = M[min(S.c0 + sc + u, K - 1)];
+      S.pa[u] = r2(a.x, a.y);
     }
     const VecRef qr = J.Q[t];
     const VecRef svr = J.S[t];
@@ -596,31 +634,37 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       As[grp][sc + u][sr ^ stg_swz_a(sc + u)] =
-          (S.live && arow_ok && S.c0 + sc + u < S.kc) ? S.pa[u] : make_double2(0.0, 0.0);
+          (S.live && arow_ok && S.c0 + sc + u < S.kc) ? S.pa[u] : r2((R)0, (R)0);
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
       double2 v = S.has_q ? S.pq[u] : make_double2(0.0, 0.0);
       if (S.has_s) v = cadd(v, cmul(S.be, S.ps[u]));
       Bs[grp][bc + u][bq ^ stg_swz_b<TN>(bc + u)] =
-          (S.live && brhs_ok && S.c0 + bc + u < S.kc) ? v : make_double2(0.0, 0.0);
+          (S.live && brhs_ok && S.c0 + bc + u < S.kc) ? r2((R)v.x, (R)v.y) : r2((R)0, (R)0);
     }
   };
   auto multiply = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kMmK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      const double2 av = As[grp][kr][wr + ((lane & 15) ^ stg_swz_a(kr))];
-      const double as = av.x + av.y;
-      double2 bv[NB];
+      const R2 av = As[grp][kr][wr + ((lane & 15) ^ stg_swz_a(kr))];
+      const R as = av.x + av.y;
+      R2 bv[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) bv[b] = Bs[grp][kr][b * 16 + ((lane & 15) ^ stg_swz_b<TN>(kr))];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) p1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv[b].x, p1[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b) p1[b] = MmT<F32>::mfma(av.x, bv[b].x, p1[b]);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) p2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv[b].y, p2[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b) p2[b] = MmT<F32>::mfma(av.y, bv[b].y, p2[b]);
+      if constexpr (F32) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        p3[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bv[b].x + bv[b].y, p3[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b) p3[b] = MmT<F32>::mfma(av.x, bv[b].y, p3[b]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) p4[b] = MmT<F32>::mfma(av.y, bv[b].x, p4[b]);
+      } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) p3[b] = MmT<F32>::mfma(as, bv[b].x + bv[b].y, p3[b]);
+      }
     }
   };
   Stage s0;
@@ -632,19 +676,22 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
     multiply();
     __syncthreads();
   }
-  d4v cr[NB], ci[NB];
+  Acc cr[NB], ci[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     cr[b] = p1[b] - p2[b];
-    ci[b] = p3[b] - p1[b] - p2[b];
+    if constexpr (F32)
+      ci[b] = p3[b] + p4[b];
+    else
+      ci[b] = p3[b] - p1[b] - p2[b];
   }
 
   if constexpr (KS > 1) {
     // partial tiles of groups 1..KS-1 through the (now idle) staging buffers
-    static_assert((KS - 1) * 4 * 64 * NB * 8 * sizeof(double) <= sizeof(As) + sizeof(Bs) || KS == 1,
+    static_assert((KS - 1) * 4 * 64 * NB * 8 * sizeof(R) <= sizeof(As) + sizeof(Bs) || KS == 1,
                   "reduction does not fit the staging buffers");
-    double* red = reinterpret_cast<double*>(&As[0][0][0]);
-    auto at = [&](int g, int b, int j) -> double& {
+    R* red = reinterpret_cast<R*>(&As[0][0][0]);
+    auto at = [&](int g, int b, int j) -> R& {
       return red[((((size_t)(g - 1) * 4 + wave) * NB + b) * 8 + j) * 64 + lane];
     };
     if (grp > 0)
@@ -674,10 +721,11 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = row0 + wr + 4 * i + (lane >> 4);
+      // accumulator entry i of lane l: row 4 i + l / 16 (float64), 4 (l / 16) + i (float32)
+      const int row = row0 + wr + (F32 ? 4 * (lane >> 4) + i : 4 * i + (lane >> 4));
       const int rhs = col0 + b * 16 + (lane & 15);
       if (row < n && rhs < nrhs) {
-        double2 y = cmul(J.alpha, make_double2(cr[b][i], ci[b][i]));
+        double2 y = cmul(J.alpha, make_double2((double)cr[b][i], (double)ci[b][i]));
         if (Pb) y = cadd(y, Pb[(int64_t)rhs * ld + row]);
         Yb[(int64_t)rhs * ld + row] = y;
       }
@@ -821,12 +869,11 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
       hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true, NS>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
                             0, t, t.jobs[0]);
   } else if (f.kind == 1) {
-    if constexpr (F32) return hipErrorInvalidValue;
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
     const int ks = f.ks > 0 ? f.ks : blk < 256 ? 4 : blk < 512 ? 2 : 1;
     const dim3 grid2((unsigned)blk);
 #define POLAR_MFMA64(TNV, KSV)                                                                           \
-  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, t, \
+  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS, F32>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, t, \
                         t.jobs[0])
     // (32- and 64-column tiles are only chosen for launches of >= 512 tiles: no split there)
     if (f.tn == 64) {
@@ -1503,7 +1550,7 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
   if (njobs <= 0) return hipSuccess;
   const ApplySeg sg{jobs, njobs, g.n, nrhs, ld, bases, nullptr, 0};
   ApplyForm f{};
-  f.kind = g.gemv ? 0 : (!f32 && g.mfma) ? 1 : 2;
+  f.kind = g.gemv ? 0 : g.mfma ? 1 : 2;
   f.nr = g.nr;
   f.tn = g.mfma;
   f.ks = g.ks;
@@ -1531,7 +1578,7 @@ hipError_t launch_block_apply_segs(const ApplySeg* segs, int nseg, int maxterms,
   f.pipe = multi;
   if (rmax <= 4) {
     f.kind = 0;
-  } else if (!f32) {
+  } else {
     // the widest tile that still gives about two workgroups per CU, never wider
     // than the fewest right-hand sides rounded up to 16 (the single launch's rule)
     f.kind = 1;
@@ -1541,8 +1588,6 @@ hipError_t launch_block_apply_segs(const ApplySeg* segs, int nseg, int maxterms,
         f.tn = tn;
         break;
       }
-  } else {
-    f.kind = 2;
   }
   const SegTableT<kMaxSeg> t = seg_table<kMaxSeg>(segs, nseg);
   return f32 ? launch_apply_t<true, kMaxSeg>(t, f, st, ev0, ev1) : launch_apply_t<false, kMaxSeg>(t, f, st, ev0, ev1);

@@ -2710,7 +2710,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
       return;
     }
     const ApplyGeom g = geom_for(S->NX, Lc.maxterms, nrhs, Lc.njobs);
-    if (!Lc.plr && !Lc.f32 && g.mfma) {
+    if (!Lc.plr && g.mfma) {
       tile = g.mfma;
       const long tiles = (long)Lc.njobs * g.ntiles * ((nrhs + g.mfma - 1) / g.mfma);
       ks = g.mfma == 16 ? (tiles < 256 ? 4 : tiles < 512 ? 2 : 1) : 1;
@@ -2796,7 +2796,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
             cands.push_back(c);
           }
         }
-      } else if (!Lc->plr && !Lc->f32 && g.mfma) {
+      } else if (!Lc->plr && g.mfma) {
         for (int tn : {16, 32, 64})
           for (int ks : {1, 2, 4})
             if (tn == 16 || ks == 1) {
