@@ -326,7 +326,7 @@ def roofline(form):
     k = form["kernel"]
     cls, st = max(k["classes"].items(), key=lambda kv: kv[1]["kernel_ms"])
     sec = st["kernel_ms"] / 1e3
-    name, dt = KERNELS.get((cls, form["precision"]), ("block_gemm_kernel", form["precision"]))
+    name, dt = KERNELS.get((cls, form["precision"]), ("block_mfma64_kernel", "f64"))
     if form.get("blocks", "dense") != "dense" and cls in ("sweep", "reflect", "operator"):
         name, dt = "plr_apply_kernel", "f64"
     elif dt in ("bf16", "f16") and form["nrhs"] <= 16:

@@ -69,7 +69,8 @@ typedef enum {
   PT_F64 = 0,        /* every block apply and local solve in complex float64     */
   PT_F32 = 1,        /* the Gauss-Seidel preconditioner (sweeps and reflection
                         terms) applies float32 copies of the trace blocks
-                        (complex float32, float32 accumulation); local solves,
+                        (complex float32, float32 accumulation; on the FP32
+                        MFMA with more than 4 sources); local solves,
                         the operator A inside GMRES, Krylov vectors, Arnoldi,
                         least squares and true residuals stay float64, so
                         flexible GMRES converges to the float64 solution (both

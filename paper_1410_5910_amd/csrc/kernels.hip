@@ -295,135 +295,6 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const SegTableT<
 }
 
 // ----------------------------------------------------------------------------
-// block_apply, many right-hand sides (NR = 8, 16): register-blocked form
-// ----------------------------------------------------------------------------
-// One workgroup = 4 waves = 64 output rows (one per lane) x NR right-hand
-// sides; the columns are walked in LDS-staged chunks of kc, the 4 waves take
-// contiguous quarters of each chunk; each lane walks its own (row-major) row,
-// and each matrix entry loaded is reused for the NR right-hand sides.
-// Cross-wave reduction in LDS, fixed order.
-template <int NR, bool F32, int NS>
-__global__ __launch_bounds__(kThreads) void block_gemm_kernel(const SegTableT<NS> tab,
-                                                              const Job* __restrict__ jobs1) {
-  // segment of this block: a0 = row tiles per job, a1 = columns per chunk
-  int bx = blockIdx.x;
-  const int seg = seg_of(tab, bx);
-  const Job* __restrict__ jobs = NS == 1 ? jobs1 : tab.jobs[seg];
-  const int n = tab.n[seg], ntiles = tab.a0[seg], kc = tab.a1[seg], nrhs = tab.nrhs[seg];
-  const int64_t ld = tab.ld[seg];
-  const Bases bases = tab.bases[seg];
-  if constexpr (NS > 1)
-    if ((int)blockIdx.y * NR >= nrhs) return;  // right-hand-side tiles beyond this segment's
-  using MV = typename MatT<F32>::vec;
-  using T = typename MatT<F32>::real;
-  extern __shared__ unsigned char smem_raw[];
-  Cx<T>* xs = reinterpret_cast<Cx<T>*>(smem_raw);  // max(kc, 128) * NR
-  Cx<T>* red = xs;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int tile = bx % ntiles;
-  const Job& J = jobs[bx / ntiles];  // read with workgroup-uniform indices only
-  const int r0 = blockIdx.y * NR;
-  const int row = tile * 64 + lane;
-  const bool valid = row < n;
-  const int rowc = valid ? row : n - 1;
-
-  Cx<T> acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = Cx<T>{(T)0, (T)0};
-
-  bool first_chunk = true;
-#pragma unroll 1
-  for (int t = 0; t < 4; ++t) {
-    if (t >= J.nterms) break;
-    const MV* __restrict__ Mrow = reinterpret_cast<const MV*>(J.M[t]) + (size_t)rowc * n;
-    const VecRef qr = J.Q[t];
-    const VecRef sr = J.S[t];
-    const gd2* __restrict__ qg = qr.buf >= 0 ? to_gd2(base_of(bases, qr.buf) + qr.off) : nullptr;
-    const gd2* __restrict__ sg = sr.buf >= 0 ? to_gd2(base_of(bases, sr.buf) + sr.off) : nullptr;
-    const double2 be = J.beta[t];
-#pragma unroll 1
-    for (int c0 = 0; c0 < n; c0 += kc) {
-      const int kw = min(kc, n - c0);
-      if (!first_chunk) __syncthreads();
-      first_chunk = false;
-      for (int c = tid; c < kw * NR; c += kThreads) {
-        const int cj = c0 + c / NR;
-        const int r = c % NR;
-        const int64_t e = (int64_t)min(r0 + r, nrhs - 1) * ld + cj;
-        const d2v vq = qg ? qg[e] : d2v{0.0, 0.0};
-        const d2v vs = sg ? sg[e] : d2v{0.0, 0.0};
-        double2 v = make_double2(vq.x, vq.y);
-        if (sg) v = cadd(v, cmul(be, make_double2(vs.x, vs.y)));
-        if (r0 + r >= nrhs) v = make_double2(0.0, 0.0);
-        xs[c] = Cx<T>{(T)v.x, (T)v.y};
-      }
-      __syncthreads();
-      // the 4 waves take contiguous quarters of the chunk; each lane walks its own row
-      const int per = (kw + 3) / 4;
-      const int cb = wave * per;
-      const int ce = min(kw, cb + per);
-      const MV* __restrict__ M = Mrow + c0 + cb;
-      const Cx<T>* xp = xs + (size_t)cb * NR;
-      const int cnt = max(0, ce - cb);
-      int c = 0;
-      for (; c + 4 <= cnt; c += 4) {
-        MV m[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) m[u] = M[c + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const Cx<T> mm{(T)m[u].x, (T)m[u].y};
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[(c + u) * NR + r]);
-        }
-      }
-      for (; c < cnt; ++c) {
-        const MV m = M[c];
-        const Cx<T> mm{(T)m.x, (T)m.y};
-#pragma unroll
-        for (int r = 0; r < NR; ++r) cfma(acc[r], mm, xp[c * NR + r]);
-      }
-    }
-  }
-
-  // pairwise reduction of the four waves: (w0 + w2) + (w1 + w3)
-  __syncthreads();
-  if (wave >= 2) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) red[((wave - 2) * 64 + lane) * NR + r] = acc[r];
-  }
-  __syncthreads();
-  if (wave < 2) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const Cx<T> v = red[(wave * 64 + lane) * NR + r];
-      acc[r].x += v.x;
-      acc[r].y += v.y;
-    }
-  }
-  __syncthreads();
-  if (wave == 1) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) red[lane * NR + r] = acc[r];
-  }
-  __syncthreads();
-  if (wave == 0 && valid) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r0 + r < nrhs) {
-        const Cx<T> v = red[lane * NR + r];
-        double2 y = cmul(J.alpha, make_double2((double)acc[r].x + (double)v.x, (double)acc[r].y + (double)v.y));
-        if (J.P.buf >= 0) y = cadd(y, base_of(bases, J.P.buf)[J.P.off + (int64_t)(r0 + r) * ld + row]);
-        base_of(bases, J.Y.buf)[J.Y.off + (int64_t)(r0 + r) * ld + row] = y;
-      }
-    }
-  }
-}
-
-// ----------------------------------------------------------------------------
 // block_apply, many right-hand sides in float64: MFMA form
 // ----------------------------------------------------------------------------
 // One workgroup = KS groups of 4 waves = a 64-row x TN-right-hand-side output
@@ -805,8 +676,8 @@ __global__ __launch_bounds__(256) void nonzero_chunks_kernel(const double2* __re
 
 // Kernel form and shape of one (possibly merged) block-apply launch.
 struct ApplyForm {
-  int kind;  // 0: row-streaming, 1: float64 MFMA, 2: register-blocked
-  int nr;    // right-hand sides per pass (streaming, register-blocked)
+  int kind;  // 0: row-streaming (<= 4 right-hand sides), 1: MFMA tiles
+  int nr;    // right-hand sides per pass (streaming)
   int tn;    // MFMA tile width
   int ks;    // MFMA wave groups (0: rule)
   bool pipe; // streaming: jobs of more than one step
@@ -844,15 +715,10 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
       t.a1[i] = std::min(n, NR >= 4 ? 256 : 512);  // <= 64 columns per in-flight load slot
       blk += (long)t.njobs[i] * t.a0[i];
       ymax = std::max(ymax, (t.nrhs[i] + NR - 1) / NR);
-    } else if (f.kind == 1) {
+    } else {
       t.a0[i] = (t.nrhs[i] + f.tn - 1) / f.tn;
       t.a1[i] = (n + kMmRows - 1) / kMmRows;
       blk += (long)t.njobs[i] * t.a1[i] * t.a0[i];
-    } else {
-      t.a0[i] = (n + 63) / 64;
-      t.a1[i] = std::min(n, 2048 / NR);  // LDS = max(kc, 128) * NR complex <= 32 KiB
-      blk += (long)t.njobs[i] * t.a0[i];
-      ymax = std::max(ymax, (t.nrhs[i] + NR - 1) / NR);
     }
     kcmax = std::max(kcmax, t.a1[i]);
   }
@@ -868,7 +734,7 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
     else
       hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true, NS>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
                             0, t, t.jobs[0]);
-  } else if (f.kind == 1) {
+  } else {
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
     const int ks = f.ks > 0 ? f.ks : blk < 256 ? 4 : blk < 512 ? 2 : 1;
     const dim3 grid2((unsigned)blk);
@@ -884,10 +750,6 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
       if (ks == 4) POLAR_MFMA64(16, 4); else if (ks == 2) POLAR_MFMA64(16, 2); else POLAR_MFMA64(16, 1);
     }
 #undef POLAR_MFMA64
-  } else {
-    const size_t lds = (size_t)std::max(kcmax, 128) * NR * sizeof(Cx<T>);
-    hipExtLaunchKernelGGL((block_gemm_kernel<NR, F32, NS>), dim3((unsigned)blk, (unsigned)ymax), dim3(kThreads),
-                          (uint32_t)lds, st, ev0, ev1, 0, t, t.jobs[0]);
   }
   return hipGetLastError();
 }
@@ -1550,7 +1412,8 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
   if (njobs <= 0) return hipSuccess;
   const ApplySeg sg{jobs, njobs, g.n, nrhs, ld, bases, nullptr, 0};
   ApplyForm f{};
-  f.kind = g.gemv ? 0 : g.mfma ? 1 : 2;
+  if (!g.gemv && !g.mfma) return hipErrorInvalidValue;  // every shape is one of the two forms
+  f.kind = g.gemv ? 0 : 1;
   f.nr = g.nr;
   f.tn = g.mfma;
   f.ks = g.ks;

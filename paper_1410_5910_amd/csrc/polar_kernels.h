@@ -131,8 +131,8 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
 // The same over nseg <= kMaxSeg segments in one launch (float64 or float32
 // blocks).  The kernel form follows from the segments together: the
 // row-streaming kernel when every segment has at most 4 right-hand sides
-// (nr: the widest), otherwise the MFMA (float64) or register-blocked
-// (float32) form with tiles chosen for the launch's total size.  Every
+// (nr: the widest), otherwise the MFMA form (float64 or float32 blocks) with
+// tiles chosen for the launch's total size.  Every
 // segment's job arithmetic is that of a launch of the same form on its own.
 hipError_t launch_block_apply_segs(const ApplySeg* segs, int nseg, int maxterms, bool wide, bool f32,
                                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
