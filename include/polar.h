@@ -131,9 +131,9 @@ typedef struct {
                         j = 0, 1, n, n+1 of (A^l)^-1 over every owned row, kept on
                         the device after setup (Def. 3 with the source restricted
                         to the layer), one launch instead of ~R dependent ones;
-                        float64 factors only; PT_ENOMEM if they do not fit.
+                        PT_ENOMEM if they do not fit.
                         2: kept when they take at most a third of the free
-                        device memory at setup (and float64 factors); used for
+                        device memory at setup; used for
                         every pre-solve (passes of more than 4 columns split
                         each product over row ranges).                         */
   int32_t closure;   /* how the polarized system is closed (Section 3.4).

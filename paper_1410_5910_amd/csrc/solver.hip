@@ -760,9 +760,10 @@ pt_status extract_blocks(pt_solver* S, const LoadSrc* src) {
     rows.release();
     return fail(PT_ENOMEM, "extraction workspace");
   }
-  // interface Green's functions of the pre-solve (float64 factors only)
+  // interface Green's functions of the pre-solve (from the float64 factors,
+  // which every precision form keeps)
   S->green_off.assign((size_t)L * 4, SIZE_MAX);
-  if (S->opt.presolve != 0 && S->opt.precision != PT_F32) {
+  if (S->opt.presolve != 0) {
     size_t need = 0;
     for (int l = 0; l < L; ++l) {
       const Layer& y = S->lay[l];
