@@ -385,12 +385,14 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * contents it overwrites) and keeps the fastest if it is at least 2% faster
  * than the built-in rule's shape (else the rule's shape stays, so that shapes
  * within the timing noise of each other do not change from run to run);
- * later calls with the same nrhs use it.  Candidates: float64 MFMA tiles of 16, 32 or 64 right-hand
- * sides, with the 16-wide tile's chunks split over 1, 2 or 4 wave groups;
- * split tiles of 32 or 64 right-hand sides, split over 1..16 k-slices.
- * Classes with a single form (the row-streaming kernel for <= 4 right-hand
- * sides, float32 blocks, compressed blocks) are reported with tried = 1; the
- * pre-solve products are not tuned (tried = 0).
+ * later calls with the same nrhs use it.  Candidates: MFMA tiles (float64
+ * or float32 blocks) of 16, 32 or 64 right-hand sides, with the 16-wide
+ * tile's chunks split over 1, 2 or 4 wave groups, or, where the solver's
+ * workspace holds the partial tiles (the sweep steps of the float64 and
+ * float32 forms), over 2, 4 or 8 workgroups; split tiles of 32 or 64
+ * right-hand sides, split over 1..16 k-slices.  Classes with a single form
+ * (the row-streaming kernel for <= 4 right-hand sides, compressed blocks) are
+ * reported with tried = 1; the pre-solve products are not tuned (tried = 0).
  * With compressed blocks (plr = 1) it first picks the leaf rank limit r_max,
  * the partition threshold of Alg. 5, among ceil(sqrt(NX)) x {1/2, 1, 2, 4}
  * (<= 64) at the solver's eps: each candidate tree is built on the GPU and the

@@ -361,7 +361,8 @@ struct MmT<true> {
 
 template <int TN, int KS, int NS, bool F32>
 __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTableT<NS> tab,
-                                                                 const Job* __restrict__ jobs1) {
+                                                                 const Job* __restrict__ jobs1, int kslices,
+                                                                 double2* __restrict__ mpart) {
   using R = typename MatT<F32>::real;   // element type of the blocks and of the MFMA
   using R2 = typename MatT<F32>::vec;
   using Acc = typename MmT<F32>::acc;
@@ -385,7 +386,10 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   const int ct = bid % nrt;  // right-hand-side tile (fastest: tiles sharing block rows stay on one XCD)
   bid /= nrt;
   const int tile = bid % ntiles;
-  const Job& J = jobs[bid / ntiles];
+  bid /= ntiles;
+  const int slice = bid % kslices;  // k-slice of the tile (kslices > 1: its partial tile goes to mpart)
+  const int job = bid / kslices;
+  const Job& J = jobs[job];
   const int row0 = tile * kMmRows;
   const int col0 = ct * TN;
 
@@ -442,7 +446,11 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
     lt[t] = J.ldm[t] > 0 ? J.ldm[t] : kt[t];
     nct[t] = t < J.nterms ? (t == 0 && kl ? kl_cnt : (kt[t] + kMmK - 1) / kMmK) : 0;
   }
-  const int nchunks = nct[0] + nct[1] + nct[2] + nct[3];
+  // this slice's chunks of the job's (term, chunk) sequence: qbeg .. qbeg + nchunks - 1
+  const int nall = nct[0] + nct[1] + nct[2] + nct[3];
+  const int cps = (nall + kslices - 1) / kslices;
+  const int qbeg = min(slice * cps, nall);
+  const int nchunks = min(nall, qbeg + cps) - qbeg;
   const int rounds = (nchunks + KS - 1) / KS;  // the same for every group: barriers stay uniform
   // Raw loads of a chunk, all unconditional (indices clamped into the block and
   // vectors): masking and the combination Q + beta S wait until the chunk is
@@ -457,6 +465,7 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
   auto fetch = [&](Stage& S, int q) {
     S.live = q < nchunks;
     if (!S.live) return;
+    q += qbeg;
     // term t of chunk q and the chunk within it (array indices stay compile-time constants)
     int t = 0, K = kt[0], ldm = lt[0];
 #pragma unroll
@@ -586,6 +595,20 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
         }
   }
 
+  if (kslices > 1) {
+    // this slice's partial tile, before alpha and P: mpart[((slice * njobs + job) * nrhs + rhs) * n + row];
+    // mfma_reduce_kernel sums the slices in order and finishes the rows
+    double2* __restrict__ pt = mpart + ((size_t)slice * tab.njobs[seg] + job) * nrhs * n;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + wr + (F32 ? 4 * (lane >> 4) + i : 4 * i + (lane >> 4));
+        const int rhs = col0 + b * 16 + (lane & 15);
+        if (row < n && rhs < nrhs) pt[(size_t)rhs * n + row] = make_double2((double)cr[b][i], (double)ci[b][i]);
+      }
+    return;
+  }
   double2* __restrict__ Yb = base_of(bases, J.Y.buf) + J.Y.off;
   const double2* __restrict__ Pb = J.P.buf >= 0 ? base_of(bases, J.P.buf) + J.P.off : nullptr;
 #pragma unroll
@@ -601,6 +624,25 @@ __global__ __launch_bounds__(256 * KS, 2) void block_mfma64_kernel(const SegTabl
         Yb[(int64_t)rhs * ld + row] = y;
       }
     }
+}
+
+// Y = P + alpha * (the k-slice partial tiles of block_mfma64_kernel summed in
+// slice order) for every job of a single-problem launch; grid: (<= 256, jobs)
+__global__ void mfma_reduce_kernel(const Job* __restrict__ jobs, int n, int nrhs, int njobs, int64_t ld, Bases bases,
+                                   int kslices, const double2* __restrict__ mpart) {
+  const int job = blockIdx.y;
+  const Job& J = jobs[job];
+  double2* __restrict__ Yb = base_of(bases, J.Y.buf) + J.Y.off;
+  const double2* __restrict__ Pb = J.P.buf >= 0 ? base_of(bases, J.P.buf) + J.P.off : nullptr;
+  const size_t per = (size_t)nrhs * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const int rhs = (int)(e / n), row = (int)(e % n);
+    double2 s = mpart[(size_t)job * per + e];
+    for (int sl = 1; sl < kslices; ++sl) s = cadd(s, mpart[((size_t)sl * njobs + job) * per + e]);
+    double2 y = cmul(J.alpha, s);
+    if (Pb) y = cadd(y, Pb[(int64_t)rhs * ld + row]);
+    Yb[(int64_t)rhs * ld + row] = y;
+  }
 }
 
 // G[x'][e] for e = (r - r0) NX + x: row x' of the trace-row block j of the
@@ -681,6 +723,8 @@ struct ApplyForm {
   int tn;    // MFMA tile width
   int ks;    // MFMA wave groups (0: rule)
   bool pipe; // streaming: jobs of more than one step
+  int mks = 1;                // MFMA k-slices over workgroups (single-problem launches)
+  double2* mpart = nullptr;   // their partial tiles
 };
 
 template <int NS>
@@ -737,10 +781,14 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
   } else {
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
     const int ks = f.ks > 0 ? f.ks : blk < 256 ? 4 : blk < 512 ? 2 : 1;
-    const dim3 grid2((unsigned)blk);
-#define POLAR_MFMA64(TNV, KSV)                                                                           \
-  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS, F32>), grid2, dim3(256 * KSV), 0, st, ev0, ev1, 0, t, \
-                        t.jobs[0])
+    // k-slices over workgroups (partial tiles summed by a second kernel): single-problem launches only
+    const int mks = NS == 1 && f.mks > 1 && f.mpart ? f.mks : 1;
+    if (blk * mks > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid2((unsigned)(blk * mks));
+    hipEvent_t ev_end = mks > 1 ? nullptr : ev1;  // with k-slices the stop event goes on the sum
+#define POLAR_MFMA64(TNV, KSV)                                                                               \
+  hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS, F32>), grid2, dim3(256 * KSV), 0, st, ev0, ev_end, 0, \
+                        t, t.jobs[0], mks, f.mpart)
     // (32- and 64-column tiles are only chosen for launches of >= 512 tiles: no split there)
     if (f.tn == 64) {
       POLAR_MFMA64(64, 1);
@@ -750,6 +798,14 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
       if (ks == 4) POLAR_MFMA64(16, 4); else if (ks == 2) POLAR_MFMA64(16, 2); else POLAR_MFMA64(16, 1);
     }
 #undef POLAR_MFMA64
+    if (mks > 1) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const size_t per = (size_t)t.nrhs[0] * t.n[0];
+      const dim3 rgrid((unsigned)std::min<size_t>((per + 255) / 256, 256), (unsigned)t.njobs[0]);
+      hipExtLaunchKernelGGL(mfma_reduce_kernel, rgrid, dim3(256), 0, st, nullptr, ev1, 0, t.jobs[0], t.n[0], t.nrhs[0],
+                            t.njobs[0], t.ld[0], t.bases[0], mks, f.mpart);
+    }
   }
   return hipGetLastError();
 }
@@ -1408,7 +1464,8 @@ hipError_t launch_nonzero_chunks(const double2* B, int64_t ld, int ncols, const 
 // launchers
 // ----------------------------------------------------------------------------
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld, Bases bases,
-                              bool f32, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                              bool f32, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, double2* mpart,
+                              size_t mpart_n) {
   if (njobs <= 0) return hipSuccess;
   const ApplySeg sg{jobs, njobs, g.n, nrhs, ld, bases, nullptr, 0};
   ApplyForm f{};
@@ -1418,6 +1475,11 @@ hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, in
   f.tn = g.mfma;
   f.ks = g.ks;
   f.pipe = g.steps != 1;
+  // MFMA k-slices only where the workspace holds every slice's partial tiles
+  if (g.mks > 1 && mpart && (size_t)g.mks * njobs * nrhs * g.n <= mpart_n) {
+    f.mks = g.mks;
+    f.mpart = mpart;
+  }
   const SegTableT<1> t = seg_table<1>(&sg, 1);
   return f32 ? launch_apply_t<true, 1>(t, f, st, ev0, ev1) : launch_apply_t<false, 1>(t, f, st, ev0, ev1);
 }

@@ -49,6 +49,8 @@ struct Bases {
 };
 
 // Launch geometry of one block-apply launch (host-computed).
+constexpr int kMfmaSlicesMax = 8;  // most MFMA k-slices over workgroups
+
 struct ApplyGeom {
   int n;        // block size NX
   int ntiles;   // row tiles per job: ceil(n / 8) for nr <= 4 (one row per wave), ceil(n / 64) otherwise
@@ -58,6 +60,7 @@ struct ApplyGeom {
                 // right-hand sides per workgroup tile (16, 32 or 64); 0: not used
   int gemv;     // 1: the row-streaming kernel (nr <= 4 right-hand sides per pass)
   int ks;       // float64 MFMA: wave groups splitting a tile's chunks (0: rule)
+  int mks;      // MFMA: workgroups splitting a tile's chunks (k-slices; 0 or 1: none)
   int steps;    // streaming form: most (term, column chunk) steps of a job in the launch
 };
 
@@ -125,9 +128,11 @@ struct ApplySeg {
 
 // ---------------------------------------------------------------- block apply
 // ev0/ev1 (may be null): events stamped with the kernel's own start and end.
+// mpart (mpart_n complex doubles, may be null): workspace of MFMA k-slices
+// (g.mks > 1), used only when it holds every slice's partial tiles.
 hipError_t launch_block_apply(const Job* jobs, int njobs, const ApplyGeom& g, int nrhs, int64_t ld,
                               Bases bases, bool f32, hipStream_t st, hipEvent_t ev0 = nullptr,
-                              hipEvent_t ev1 = nullptr);
+                              hipEvent_t ev1 = nullptr, double2* mpart = nullptr, size_t mpart_n = 0);
 // The same over nseg <= kMaxSeg segments in one launch (float64 or float32
 // blocks).  The kernel form follows from the segments together: the
 // row-streaming kernel when every segment has at most 4 right-hand sides

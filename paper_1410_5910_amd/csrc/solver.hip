@@ -134,6 +134,7 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
   if (tc && g.mfma && tc->tn) {
     g.mfma = tc->tn;
     g.ks = tc->ks;
+    g.mks = tc->mks;
   }
   int slot = -1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -156,7 +157,8 @@ pt_status run_apply_cfg(pt_solver* S, const Launch& Lc, int nrhs, int64_t ld, Ba
     HIPCHK(launch_block_apply_split(S->jobs.p + Lc.job0, Lc.njobs, S->NX, nrhs, ld, b, S->st, e0, e1, part, sc));
   }
   else {
-    HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, Lc.f32, S->st, e0, e1));
+    HIPCHK(launch_block_apply(S->jobs.p + Lc.job0, Lc.njobs, g, nrhs, ld, b, Lc.f32, S->st, e0, e1, S->mpart.p,
+                              S->mpart.n));
   }
   if (S->prof) {
     // bytes per stored complex entry: 4 bfloat16 planes, float32 or float64 pairs
@@ -1520,6 +1522,10 @@ pt_status alloc_online(pt_solver* S) {
       HIPCHK(S->part.alloc(need));
     }
     if (S->use_plr) HIPCHK(S->plr_part.alloc(kPlrPartEntries));
+    // k-slices of the MFMA sweep steps (float64 and float32 blocks, more than 4 sources): up to
+    // kMfmaSlicesMax partial tiles per output entry of a sweep launch
+    if (!S->split && !S->use_plr && nr > 4 && !S->sweep.empty())
+      HIPCHK(S->mpart.alloc((size_t)kMfmaSlicesMax * S->sweep[0].njobs * nr * S->NX));
     // source-to-layer activity tables
     const int L = S->L;
     std::vector<int32_t> rl(S->sumR), os(L), no(L);
@@ -2012,6 +2018,7 @@ void pt_free(pt_solver* S) {
   S->blkbf.release();
   S->part.release();
   S->plr_part.release();
+  S->mpart.release();
   release_green(S);
   S->gsum_dst.release();
   S->gsum_src.release();
@@ -2761,7 +2768,8 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
             S->tune[cls][nrhs] = it->second.cfg;
             S->tune[cls][nrhs].njobs = Lc->njobs;
             e.tile_rhs = it->second.cfg.tn ? it->second.cfg.tn : it->second.cfg.sp.tile_rhs;
-            e.ksplit = it->second.cfg.tn ? it->second.cfg.ks : it->second.cfg.sp.kslices;
+            e.ksplit = it->second.cfg.tn ? std::max(it->second.cfg.ks, it->second.cfg.mks)
+                                         : it->second.cfg.sp.kslices;
           } else {
             S->tune[cls].erase(nrhs);
             rule_shape(*Lc, e.tile_rhs, e.ksplit);
@@ -2806,6 +2814,16 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
               c.ks = ks;
               cands.push_back(c);
             }
+        // k-slices over workgroups, where the workspace holds the partial tiles
+        for (int tn : {16, 32, 64})
+          for (int mks = 2; mks <= kMfmaSlicesMax; mks *= 2)
+            if ((size_t)mks * Lc->njobs * nrhs * S->NX <= S->mpart.n) {
+              TuneCfg c;
+              c.tn = tn;
+              c.ks = 1;
+              c.mks = mks;
+              cands.push_back(c);
+            }
       }
       PTCHK(time_launch(S, *Lc, nrhs, ld, b, nullptr, kReps, e.default_us));
       e.best_us = e.default_us;
@@ -2827,7 +2845,7 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
         S->tune[cls][nrhs] = *best;
         S->tune[cls][nrhs].njobs = Lc->njobs;
         e.tile_rhs = best->tn ? best->tn : best->sp.tile_rhs;
-        e.ksplit = best->tn ? best->ks : best->sp.kslices;
+        e.ksplit = best->tn ? std::max(best->ks, best->mks) : best->sp.kslices;
       } else {
         S->tune[cls].erase(nrhs);
         rule_shape(*Lc, e.tile_rhs, e.ksplit);
@@ -2852,14 +2870,15 @@ pt_status pt_tune_cache_save(const char* path) {
   FILE* fp = std::fopen(path, "w");
   if (!fp) return fail(PT_EINVAL, std::string("cannot open ") + path + " for writing");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  bool ok = std::fprintf(fp, "# libpolar tuning cache v1: NX L precision closure plr class nrhs njobs | has_cfg tn ks "
-                             "tile_rhs kslices stream f16 | best_us default_us tried\n") > 0;
+  bool ok = std::fprintf(fp, "# libpolar tuning cache v2: NX L precision closure plr class nrhs njobs | has_cfg tn ks "
+                             "mks tile_rhs kslices stream f16 | best_us default_us tried\n") > 0;
   for (const auto& kv : g_tune_cache) {
     const TuneKey& k = kv.first;
     const TuneVal& v = kv.second;
-    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.9g %.9g %d\n", k.NX, k.L, k.precision,
-                            k.closure, k.plr, k.cls, k.nrhs, k.njobs, v.has_cfg, v.cfg.tn, v.cfg.ks, v.cfg.sp.tile_rhs,
-                            v.cfg.sp.kslices, v.cfg.sp.stream, v.cfg.sp.f16, v.best_us, v.default_us, v.tried) > 0;
+    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.9g %.9g %d\n", k.NX, k.L,
+                            k.precision, k.closure, k.plr, k.cls, k.nrhs, k.njobs, v.has_cfg, v.cfg.tn, v.cfg.ks,
+                            v.cfg.mks, v.cfg.sp.tile_rhs, v.cfg.sp.kslices, v.cfg.sp.stream, v.cfg.sp.f16, v.best_us,
+                            v.default_us, v.tried) > 0;
   }
   ok = std::fclose(fp) == 0 && ok;
   return ok ? PT_OK : fail(PT_EINVAL, std::string("writing ") + path + " failed");
@@ -2871,16 +2890,17 @@ pt_status pt_tune_cache_load(const char* path) {
   if (!fp) return fail(PT_EINVAL, std::string("cannot open ") + path);
   char line[512];
   std::map<TuneKey, TuneVal> add;
-  bool ok = std::fgets(line, sizeof(line), fp) && std::strncmp(line, "# libpolar tuning cache v1", 26) == 0;
+  bool ok = std::fgets(line, sizeof(line), fp) && std::strncmp(line, "# libpolar tuning cache v2", 26) == 0;
   while (ok && std::fgets(line, sizeof(line), fp)) {
     TuneKey k{};
     TuneVal v{};
-    const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf %d", &k.NX, &k.L,
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf %lf %d", &k.NX, &k.L,
                                 &k.precision, &k.closure, &k.plr, &k.cls, &k.nrhs, &k.njobs, &v.has_cfg, &v.cfg.tn,
-                                &v.cfg.ks, &v.cfg.sp.tile_rhs, &v.cfg.sp.kslices, &v.cfg.sp.stream, &v.cfg.sp.f16,
-                                &v.best_us, &v.default_us, &v.tried);
-    ok = got == 18 && k.cls >= 0 && k.cls <= kClsPlrRank && k.nrhs >= 1 && v.cfg.tn >= 0 && v.cfg.tn <= 64 &&
-         v.cfg.ks >= 0 && v.cfg.ks <= 16 && v.cfg.sp.kslices >= 0 && v.cfg.sp.kslices <= 16 &&
+                                &v.cfg.ks, &v.cfg.mks, &v.cfg.sp.tile_rhs, &v.cfg.sp.kslices, &v.cfg.sp.stream,
+                                &v.cfg.sp.f16, &v.best_us, &v.default_us, &v.tried);
+    ok = got == 19 && k.cls >= 0 && k.cls <= kClsPlrRank && k.nrhs >= 1 && v.cfg.tn >= 0 && v.cfg.tn <= 64 &&
+         v.cfg.ks >= 0 && v.cfg.ks <= 16 && v.cfg.mks >= 0 && v.cfg.mks <= kMfmaSlicesMax &&
+         v.cfg.sp.kslices >= 0 && v.cfg.sp.kslices <= 16 &&
          (v.cfg.sp.tile_rhs == 0 || v.cfg.sp.tile_rhs == 32 || v.cfg.sp.tile_rhs == 64) && v.cfg.sp.stream >= 0 &&
          v.cfg.sp.stream <= 2;
     if (ok) add[k] = v;

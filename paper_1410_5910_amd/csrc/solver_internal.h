@@ -124,7 +124,8 @@ inline pt_status gpu_op(std::vector<Rec>* rec, hipStream_t st, const char* what,
 
 // a tuned launch shape (0: the built-in rule)
 struct TuneCfg {
-  int tn = 0, ks = 0;         // float64 MFMA tile width and wave groups
+  int tn = 0, ks = 0;         // MFMA tile width and wave groups
+  int mks = 0;                // MFMA k-slices over workgroups (0, 1: none)
   SplitCfg sp{0, 0};          // split-bfloat16 tile width and k-slices
   int njobs = 0;              // jobs of the launch the shape was timed on
 };
@@ -182,6 +183,7 @@ struct pt_solver {
   double split_alpha = 1.0;  // factor folded into the jobs of split launches (float16: 1 / both scales)
   DevBuf<float2> part;     // k-slice partial tiles of small split launches
   DevBuf<double2> plr_part;  // leaf-slice partial tiles of small compressed-block launches
+  DevBuf<double2> mpart;     // k-slice partial tiles of MFMA sweep launches (float64 and float32 forms)
   // interface Green's functions of the pre-solve: per layer, rows 1 and n of
   // (A^l)^-1 over the owned rows, NX x (n NX) each (null: line-by-line)
   DevBuf<double2> green;

@@ -98,10 +98,14 @@ def test_tune_cache_files_without_a_gpu(tmp_path):
     P = pytest.importorskip("paper_1410_5910_amd")
     path = str(tmp_path / "tune.txt")
     P.tune_cache_save(path)
-    assert open(path).readline().startswith("# libpolar tuning cache v1")
+    assert open(path).readline().startswith("# libpolar tuning cache v2")
     P.tune_cache_load(path)
     bad = tmp_path / "bad.txt"
-    bad.write_text("# libpolar tuning cache v1\n1 2 3\n")
+    bad.write_text("# libpolar tuning cache v2\n1 2 3\n")
+    with pytest.raises(P.PolarError):
+        P.tune_cache_load(str(bad))
+    # a file of the previous format (no k-slice column for the MFMA tiles) is rejected whole
+    bad.write_text("# libpolar tuning cache v1\n440 16 2 0 0 1 128 4 1 0 0 32 4 0 0 20.6 30.9 21\n")
     with pytest.raises(P.PolarError):
         P.tune_cache_load(str(bad))
     bad.write_text("something else\n")
