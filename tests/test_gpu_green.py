@@ -115,14 +115,19 @@ def test_green_solves_match_direct(pair):
     assert rel(u1, ud[2]) < 1e-8
 
 
-def test_green_is_float64_only():
+def test_green_in_the_float32_form():
+    # every precision form keeps float64 factors, so the float32 form (float32 preconditioner blocks) forms
+    # its pre-solve from the same float64 Green's functions and meets the float64 bar
     prob, f = synth.config_small(nx=24, nz=31, npml=5, L=3, nrhs=2, seed=21)
     _flush("[gpu] green f32")
     s = P.Solver.from_problem(prob, precision="f32", max_nrhs=2, tol=1e-10, maxit=60, presolve="green")
-    assert s.layout()["green_bytes"] == 0  # float32 factors keep the line-by-line pre-solve
-    u, _ = s.solve(f)
-    assert rel(u, DirectSolver(prob).solve(f)) < 1e-6
+    g = P.Solver.from_problem(prob, precision="f64", max_nrhs=2, tol=1e-10, maxit=60, presolve="green")
+    assert s.layout()["green_bytes"] == g.layout()["green_bytes"] > 0
+    u, info = s.solve(f)
+    assert all(i["converged"] for i in info)
+    assert rel(u, DirectSolver(prob).solve(f)) < 1e-8
     s.close()
+    g.close()
     with pytest.raises(ValueError):
         P.Solver.from_problem(prob, presolve="nope")
 
