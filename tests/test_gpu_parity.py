@@ -495,6 +495,39 @@ def test_tune_keeps_results(precision, nrhs):
     gs.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_mfma_kslices_match_the_unsliced_apply(tmp_path, precision):
+    # the sweep steps forced onto 32-source MFMA tiles split over 4 workgroups (partial tiles summed by a
+    # second kernel) through the tuning cache: the solve must match the rule's shapes and the direct solve
+    # (a grid size no other test uses, so the forced cache entry touches nothing else)
+    prob, f = synth.config_small(nx=62, nz=60, npml=6, L=5, nrhs=40, seed=63)
+    _flush(f"[gpu] MFMA k-slices {precision}")
+    sv = P.Solver.from_problem(prob, precision=precision, max_nrhs=40, tol=1e-11, maxit=60)
+    u0, _ = sv.solve(f)  # the rules' shapes
+    sv.tune(40)
+    path = tmp_path / "tune.txt"
+    P.tune_cache_save(str(path))
+    lines = path.read_text().splitlines()
+    out, hit = [lines[0]], False
+    for line in lines[1:]:
+        x = line.split()  # NX L precision closure plr class nrhs njobs | has_cfg tn ks mks ...
+        if int(x[0]) == sv.NX and int(x[1]) == prob.L and int(x[5]) == 1 and int(x[6]) == 40:
+            x[8], x[9], x[10], x[11] = "1", "32", "1", "4"
+            hit = True
+        out.append(" ".join(x))
+    assert hit
+    path.write_text("\n".join(out) + "\n")
+    P.tune_cache_load(str(path))
+    t = sv.tune(40)
+    assert t["sweep"]["cached"] and t["sweep"]["tile_rhs"] == 32 and t["sweep"]["ksplit"] == 4, t["sweep"]
+    u1, info = sv.solve(f)
+    assert all(i["converged"] for i in info)
+    assert rel(u1, u0) < 1e-9
+    ud = DirectSolver(prob).solve(f)
+    assert max(rel(u1[r], ud[r]) for r in range(f.shape[0])) < 1e-8
+    sv.close()
+
+
 # ---------------------------------------------------------------- several problems at once
 def test_solve_batch_uneven_problems():
     import torch
