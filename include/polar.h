@@ -388,8 +388,9 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * later calls with the same nrhs use it.  Candidates: MFMA tiles (float64
  * or float32 blocks) of 16, 32 or 64 right-hand sides, with the 16-wide
  * tile's chunks split over 1, 2 or 4 wave groups, or, where the solver's
- * workspace holds the partial tiles (the sweep steps of the float64 and
- * float32 forms), over 2, 4 or 8 workgroups; split tiles of 32 or 64
+ * workspace holds the partial tiles (sweep steps and reflection terms of the
+ * float64 and float32 forms, operator A of every form; not the local solves'
+ * passes), over 2, 4 or 8 workgroups; split tiles of 32 or 64
  * right-hand sides, split over 1..16 k-slices.  Classes with a single form
  * (the row-streaming kernel for <= 4 right-hand sides, compressed blocks) are
  * reported with tried = 1; the pre-solve products are not tuned (tried = 0).
@@ -402,7 +403,8 @@ pt_status pt_profile_read_class(pt_solver* s, int32_t cls, pt_kernel_stats* out)
  * closure, compressed or not, launch class, nrhs, the launch's job count);
  * pt_tune reuses a cached choice instead of timing (cached = 1), and
  * pt_tune_cache_save / pt_tune_cache_load keep the cache in a text file
- * across processes (load merges; PT_EINVAL for a file that is not one).
+ * across processes (load merges; PT_EINVAL, and nothing merged, for a file
+ * that is not one or that names a tile shape the kernels do not have).
  * out: PT_CLS_COUNT entries (may be NULL). */
 typedef struct {
   int32_t cls;        /* pt_launch_class                                          */

@@ -295,10 +295,12 @@ __global__ __launch_bounds__(kGvThreads) void block_gemv_kernel(const SegTableT<
 }
 
 // ----------------------------------------------------------------------------
-// block_apply, many right-hand sides in float64: MFMA form
+// block_apply, many right-hand sides, float64 or float32 blocks: MFMA form
 // ----------------------------------------------------------------------------
 // One workgroup = KS groups of 4 waves = a 64-row x TN-right-hand-side output
-// tile of one job (TN = 16, 32 or 64).  The job's columns are walked in chunks
+// tile of one job (TN = 16, 32 or 64), or with kslices > 1 the partial tile of
+// one contiguous share of the job's chunk sequence (mfma_reduce_kernel sums
+// the shares).  The job's columns are walked in chunks
 // of 16 (term by term); k-group g takes chunks g, g + KS, ..., so a launch with
 // few tiles (a local-solve step with few right-hand sides, a sweep step) still
 // has KS times the waves in flight.  Each group stages the 64 x 16 slice of the
@@ -779,6 +781,7 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
       hipExtLaunchKernelGGL((block_gemv_kernel<NR, F32, true, NS>), grid, dim3(kGvThreads), (uint32_t)lds, st, ev0, ev1,
                             0, t, t.jobs[0]);
   } else {
+    if (f.tn != 16 && f.tn != 32 && f.tn != 64) return hipErrorInvalidValue;  // the kernel's tile widths
     // k-split over 4 groups when the launch has fewer tiles than CUs, 2 below two per CU
     const int ks = f.ks > 0 ? f.ks : blk < 256 ? 4 : blk < 512 ? 2 : 1;
     // k-slices over workgroups (partial tiles summed by a second kernel): single-problem launches only
@@ -789,7 +792,8 @@ hipError_t launch_apply_form(SegTableT<NS> t, const ApplyForm& f, hipStream_t st
 #define POLAR_MFMA64(TNV, KSV)                                                                               \
   hipExtLaunchKernelGGL((block_mfma64_kernel<TNV, KSV, NS, F32>), grid2, dim3(256 * KSV), 0, st, ev0, ev_end, 0, \
                         t, t.jobs[0], mks, f.mpart)
-    // (32- and 64-column tiles are only chosen for launches of >= 512 tiles: no split there)
+    // (32- and 64-column tiles take one wave group: the rules choose them for launches of >= 512
+    // tiles, the tuner pairs them with k-slices over workgroups where the launch is smaller)
     if (f.tn == 64) {
       POLAR_MFMA64(64, 1);
     } else if (f.tn == 32) {
@@ -1007,8 +1011,8 @@ __global__ void twist_combine_kernel(double2* const* G, const double2* const* Y,
 }
 
 __global__ void finish_row_kernel(double2* const* B, const int32_t* pi, double2* const* dinv64,
-                                  float2* const* dinv32, double2* const* nextD, const double2* const* next_diag,
-                                  const double2* coef, const double2* west, const double2* east, int n) {
+                                  double2* const* nextD, const double2* const* next_diag, const double2* coef,
+                                  const double2* west, const double2* east, int n) {
   const int b = blockIdx.y;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
@@ -1016,7 +1020,6 @@ __global__ void finish_row_kernel(double2* const* B, const int32_t* pi, double2*
   const double2 v = B[b][(size_t)pi[(size_t)b * n + c] * n + i];
   const size_t er = (size_t)i * n + c;  // stored factors are row-major
   if (dinv64[b]) dinv64[b][er] = v;
-  if (dinv32[b]) dinv32[b][er] = make_float2((float)v.x, (float)v.y);
   if (next_diag[b]) {
     const double2 t = cmul(coef[b], v);
     const double2 d = tridiag_entry(i, c, next_diag[b], west, east);
@@ -1553,12 +1556,12 @@ hipError_t launch_twist_combine(double2* const* G, const double2* const* Y, cons
   return hipGetLastError();
 }
 
-hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64, float2* const* dinv32,
-                             double2* const* nextD, const double2* const* next_diag, const double2* coef,
-                             const double2* west, const double2* east, int nb, int n, hipStream_t st) {
+hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64, double2* const* nextD,
+                             const double2* const* next_diag, const double2* coef, const double2* west,
+                             const double2* east, int nb, int n, hipStream_t st) {
   const unsigned gx = (unsigned)(((size_t)n * n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(finish_row_kernel, dim3(gx, nb), dim3(kThreads), 0, st, B, pi, dinv64, dinv32, nextD,
-                     next_diag, coef, west, east, n);
+  hipLaunchKernelGGL(finish_row_kernel, dim3(gx, nb), dim3(kThreads), 0, st, B, pi, dinv64, nextD, next_diag, coef,
+                     west, east, n);
   return hipGetLastError();
 }
 

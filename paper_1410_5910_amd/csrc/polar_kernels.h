@@ -213,11 +213,10 @@ hipError_t launch_gj_perm(const int32_t* perm, int32_t* pi, int nb, int n, hipSt
 hipError_t launch_init_delta(double2* const* out, const double2* const* diag, const double2* west,
                              const double2* east, int nb, int n, hipStream_t st);
 
-// Finishes local row r of nb layers: Dinv = B[:, pi] (stored row-major as f64
-// and/or f32), and if next_diag[b] != nullptr also writes the next Schur complement
+// Finishes local row r of nb layers: Dinv = B[:, pi] (stored row-major, where
+// dinv64[b] != nullptr), and if next_diag[b] != nullptr also writes the next Schur complement
 // Delta_{r+1} = tridiag(A_{r+1}) - coef[b] * Dinv into nextD[b].
-hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64,
-                             float2* const* dinv32, double2* const* nextD,
+hipError_t launch_finish_row(double2* const* B, const int32_t* pi, double2* const* dinv64, double2* const* nextD,
                              const double2* const* next_diag, const double2* coef, const double2* west,
                              const double2* east, int nb, int n, hipStream_t st);
 

@@ -522,14 +522,12 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
   DevBuf<double2> dg, dw, de, gjA, gjB, coef;
   DevBuf<int32_t> perm, pi;
   DevBuf<double2*> pA, pB, pD, pN, pDiag, pY;
-  DevBuf<float2*> pD32;
   pt_status rc = PT_OK;
   auto cleanup = [&]() {
     for (auto* b : {&dg, &dw, &de, &gjA, &gjB, &coef}) b->release();
     perm.release();
     pi.release();
     for (auto* b : {&pA, &pB, &pD, &pN, &pDiag, &pY}) b->release();
-    pD32.release();
   };
   auto chk = [&](hipError_t e, const char* what) {
     if (e != hipSuccess && rc == PT_OK) rc = fail(e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EHIP,
@@ -540,8 +538,7 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
       !chk(gjA.alloc(E * NC), "alloc gj") || !chk(gjB.alloc(E * NC), "alloc gj") || !chk(coef.alloc(NC), "alloc") ||
       !chk(perm.alloc((size_t)NC * NX), "alloc") || !chk(pi.alloc((size_t)NC * NX), "alloc") ||
       !chk(pA.alloc(NC), "alloc") || !chk(pB.alloc(NC), "alloc") || !chk(pD.alloc(NC), "alloc") ||
-      !chk(pN.alloc(NC), "alloc") || !chk(pDiag.alloc(NC), "alloc") || !chk(pY.alloc(NC), "alloc") ||
-      !chk(pD32.alloc(NC), "alloc")) {
+      !chk(pN.alloc(NC), "alloc") || !chk(pDiag.alloc(NC), "alloc") || !chk(pY.alloc(NC), "alloc")) {
     cleanup();
     return rc;
   }
@@ -598,7 +595,6 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
     chk(launch_init_delta(pA.p, (const double2* const*)pDiag.p, dw.p, de.p, NC, NX, st), "init_delta");
     chk(hipStreamSynchronize(st), "sync");
   }
-  std::vector<float2*> hD32(NC, nullptr);
   for (int f = 0; f < F && rc == PT_OK; ++f) {
     std::vector<int> act;
     for (int c = 0; c < NC; ++c)
@@ -635,10 +631,8 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
     upload(pD, hD);
     upload(pN, hN);
     upload(pDiag, hDiag);
-    chk(hipMemcpyAsync(pD32.p, hD32.data(), nb * sizeof(float2*), hipMemcpyHostToDevice, st), "copy");
     chk(hipMemcpyAsync(coef.p, hcoef.data(), nb * sizeof(double2), hipMemcpyHostToDevice, st), "copy");
-    chk(launch_finish_row(pB.p, pi.p, pD.p, pD32.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, nb,
-                          NX, st),
+    chk(launch_finish_row(pB.p, pi.p, pD.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, nb, NX, st),
         "finish_row");
     chk(hipStreamSynchronize(st), "sync");
   }
@@ -666,9 +660,7 @@ pt_status factorize(pt_solver* S, const std::vector<cd>& diag_all, const std::ve
     upload(pN, hN);
     for (auto& d : hDiag) d = nullptr;
     upload(pDiag, hDiag);
-    chk(hipMemcpyAsync(pD32.p, hD32.data(), L * sizeof(float2*), hipMemcpyHostToDevice, st), "copy");
-    chk(launch_finish_row(pB.p, pi.p, pD.p, pD32.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, L, NX,
-                          st),
+    chk(launch_finish_row(pB.p, pi.p, pD.p, pN.p, (const double2* const*)pDiag.p, coef.p, dw.p, de.p, L, NX, st),
         "finish_row");
     chk(hipStreamSynchronize(st), "sync");
   }
@@ -1522,10 +1514,19 @@ pt_status alloc_online(pt_solver* S) {
       HIPCHK(S->part.alloc(need));
     }
     if (S->use_plr) HIPCHK(S->plr_part.alloc(kPlrPartEntries));
-    // k-slices of the MFMA sweep steps (float64 and float32 blocks, more than 4 sources): up to
-    // kMfmaSlicesMax partial tiles per output entry of a sweep launch
-    if (!S->split && !S->use_plr && nr > 4 && !S->sweep.empty())
-      HIPCHK(S->mpart.alloc((size_t)kMfmaSlicesMax * S->sweep[0].njobs * nr * S->NX));
+    // k-slices over workgroups of the MFMA block applies (more than 4 sources, dense blocks): up
+    // to kMfmaSlicesMax partial tiles per output entry of the launch the tuner times for each
+    // class (sweep steps, reflection terms, operator A; the local solves' passes too, which the
+    // tuner does not slice but a loaded tuning cache may); split launches have their own workspace
+    if (!S->use_plr && nr > 4) {
+      int nj = 0;
+      if (!S->fwd.empty()) nj = S->fwd[S->fwd.size() / 2].njobs;
+      if (!S->sweep.empty() && !S->sweep[S->sweep.size() / 2].split)
+        nj = std::max(nj, S->sweep[S->sweep.size() / 2].njobs);
+      if (!S->bterm.split) nj = std::max(nj, S->bterm.njobs);
+      nj = std::max(nj, S->opA.njobs);
+      if (nj > 0) HIPCHK(S->mpart.alloc((size_t)kMfmaSlicesMax * nj * nr * S->NX));
+    }
     // source-to-layer activity tables
     const int L = S->L;
     std::vector<int32_t> rl(S->sumR), os(L), no(L);
@@ -2013,7 +2014,6 @@ void pt_free(pt_solver* S) {
   for (auto* b : {&S->dinv64, &S->blk64, &S->W, &S->Bw, &S->fio, &S->uio, &S->s, &S->V, &S->Z, &S->U1,
                   &S->U2, &S->tmp, &S->zeros, &S->x, &S->hbuf, &S->hacc, &S->Hc, &S->sn, &S->g, &S->y})
     b->release();
-  S->dinv32.release();
   S->blk32.release();
   S->blkbf.release();
   S->part.release();
@@ -2814,10 +2814,12 @@ pt_status pt_tune(pt_solver* S, int32_t nrhs, pt_tune_entry* out) {
               c.ks = ks;
               cands.push_back(c);
             }
-        // k-slices over workgroups, where the workspace holds the partial tiles
+        // k-slices over workgroups, where the workspace holds the partial tiles; not for the local
+        // solves, whose passes differ in length and input window from the one timed here: two
+        // slices won 2% on that pass and lost 4% over the class as a whole
         for (int tn : {16, 32, 64})
           for (int mks = 2; mks <= kMfmaSlicesMax; mks *= 2)
-            if ((size_t)mks * Lc->njobs * nrhs * S->NX <= S->mpart.n) {
+            if (cls != PT_CLS_LOCAL && (size_t)mks * Lc->njobs * nrhs * S->NX <= S->mpart.n) {
               TuneCfg c;
               c.tn = tn;
               c.ks = 1;
@@ -2898,8 +2900,11 @@ pt_status pt_tune_cache_load(const char* path) {
                                 &k.precision, &k.closure, &k.plr, &k.cls, &k.nrhs, &k.njobs, &v.has_cfg, &v.cfg.tn,
                                 &v.cfg.ks, &v.cfg.mks, &v.cfg.sp.tile_rhs, &v.cfg.sp.kslices, &v.cfg.sp.stream,
                                 &v.cfg.sp.f16, &v.best_us, &v.default_us, &v.tried);
-    ok = got == 19 && k.cls >= 0 && k.cls <= kClsPlrRank && k.nrhs >= 1 && v.cfg.tn >= 0 && v.cfg.tn <= 64 &&
-         v.cfg.ks >= 0 && v.cfg.ks <= 16 && v.cfg.mks >= 0 && v.cfg.mks <= kMfmaSlicesMax &&
+    // MFMA tiles: the kernel's widths 16, 32, 64 (0: the rules'), wave groups 1, 2, 4 (0: the rules')
+    ok = got == 19 && k.cls >= 0 && k.cls <= kClsPlrRank && k.nrhs >= 1 &&
+         (v.cfg.tn == 0 || v.cfg.tn == 16 || v.cfg.tn == 32 || v.cfg.tn == 64) &&
+         (v.cfg.ks == 0 || v.cfg.ks == 1 || v.cfg.ks == 2 || v.cfg.ks == 4) && v.cfg.mks >= 0 &&
+         v.cfg.mks <= kMfmaSlicesMax &&
          v.cfg.sp.kslices >= 0 && v.cfg.sp.kslices <= 16 &&
          (v.cfg.sp.tile_rhs == 0 || v.cfg.sp.tile_rhs == 32 || v.cfg.sp.tile_rhs == 64) && v.cfg.sp.stream >= 0 &&
          v.cfg.sp.stream <= 2;

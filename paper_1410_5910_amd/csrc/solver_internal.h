@@ -176,7 +176,7 @@ struct pt_solver {
   bool use_plr = false;
   int plr_rmax = 0;  // leaf rank limit of the compressed blocks in use
   DevBuf<double2> dinv64, blk64;
-  DevBuf<float2> dinv32, blk32;
+  DevBuf<float2> blk32;
   DevBuf<uint16_t> blkbf;  // split-bfloat16 planes of every block (preconditioner of the mixed form)
   bool split = false;
   bool split_f16 = false;    // the split planes are float16 (PT_SPLIT_F16), else bfloat16

@@ -108,6 +108,13 @@ def test_tune_cache_files_without_a_gpu(tmp_path):
     bad.write_text("# libpolar tuning cache v1\n440 16 2 0 0 1 128 4 1 0 0 32 4 0 0 20.6 30.9 21\n")
     with pytest.raises(P.PolarError):
         P.tune_cache_load(str(bad))
+    # MFMA tile widths and wave-group counts the kernel does not have
+    for cfg in ("1 48 1 1", "1 16 3 1"):
+        bad.write_text("# libpolar tuning cache v2\n440 16 2 0 0 1 128 4 " + cfg + " 0 0 0 0 20.6 30.9 21\n")
+        with pytest.raises(P.PolarError):
+            P.tune_cache_load(str(bad))
+    bad.write_text("# libpolar tuning cache v2\n440 16 2 0 0 1 128 4 1 16 4 2 0 0 0 0 20.6 30.9 21\n")
+    P.tune_cache_load(str(bad))  # a shape the kernel has
     bad.write_text("something else\n")
     with pytest.raises(P.PolarError):
         P.tune_cache_load(str(bad))

@@ -495,11 +495,12 @@ def test_tune_keeps_results(precision, nrhs):
     gs.close()
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "split-bf16"])
 def test_mfma_kslices_match_the_unsliced_apply(tmp_path, precision):
-    # the sweep steps forced onto 32-source MFMA tiles split over 4 workgroups (partial tiles summed by a
-    # second kernel) through the tuning cache: the solve must match the rule's shapes and the direct solve
-    # (a grid size no other test uses, so the forced cache entry touches nothing else)
+    # the local solves' passes and operator A (every form), the sweep steps and reflection terms (float64
+    # and float32 blocks) forced onto 32-source MFMA tiles split over 4 workgroups (partial tiles summed by a
+    # second kernel) through the tuning cache: the solve must match the rules' shapes and the direct solve
+    # (a grid size no other test uses, so the forced cache entries touch nothing else)
     prob, f = synth.config_small(nx=62, nz=60, npml=6, L=5, nrhs=40, seed=63)
     _flush(f"[gpu] MFMA k-slices {precision}")
     sv = P.Solver.from_problem(prob, precision=precision, max_nrhs=40, tol=1e-11, maxit=60)
@@ -508,22 +509,25 @@ def test_mfma_kslices_match_the_unsliced_apply(tmp_path, precision):
     path = tmp_path / "tune.txt"
     P.tune_cache_save(str(path))
     lines = path.read_text().splitlines()
-    out, hit = [lines[0]], False
+    names = ["local", "sweep", "reflect", "operator"]  # tuning classes 0..3
+    forced = {0, 3} if precision.startswith("split") else {0, 1, 2, 3}
+    out, hit = [lines[0]], set()
     for line in lines[1:]:
         x = line.split()  # NX L precision closure plr class nrhs njobs | has_cfg tn ks mks ...
-        if int(x[0]) == sv.NX and int(x[1]) == prob.L and int(x[5]) == 1 and int(x[6]) == 40:
+        if int(x[0]) == sv.NX and int(x[1]) == prob.L and int(x[5]) in forced and int(x[6]) == 40:
             x[8], x[9], x[10], x[11] = "1", "32", "1", "4"
-            hit = True
+            hit.add(int(x[5]))
         out.append(" ".join(x))
-    assert hit
+    assert hit == forced
     path.write_text("\n".join(out) + "\n")
     P.tune_cache_load(str(path))
     t = sv.tune(40)
-    assert t["sweep"]["cached"] and t["sweep"]["tile_rhs"] == 32 and t["sweep"]["ksplit"] == 4, t["sweep"]
+    for cls in (names[c] for c in forced):
+        assert t[cls]["cached"] and t[cls]["tile_rhs"] == 32 and t[cls]["ksplit"] == 4, (cls, t[cls])
     u1, info = sv.solve(f)
     assert all(i["converged"] for i in info)
     assert rel(u1, u0) < 1e-9
-    ud = DirectSolver(prob).solve(f)
+    ud = DirectSolver(prob).solve(f)  # reduced-precision forms too: the outer solve is float64 to 1e-11
     assert max(rel(u1[r], ud[r]) for r in range(f.shape[0])) < 1e-8
     sv.close()
 
