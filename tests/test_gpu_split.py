@@ -62,6 +62,21 @@ def test_split_operators_match_oracle(mid, nrhs):
             assert err > 1e-12  # really the reduced-precision path
 
 
+@pytest.mark.parametrize("nrhs", [100, 448])
+def test_split_kslice_sums_are_deterministic(mid, nrhs):
+    # the sweep and reflection launches split their chunks over k-slices here, whose partial tiles are summed
+    # in slice order: repeated applies give the same bits
+    prob, gs, ps = mid
+    _flush(f"[gpu] split k-slice sums, reruns, nrhs={nrhs}")
+    rng = np.random.default_rng(100 + nrhs)
+    shp = ps.zeros(nrhs).shape
+    x = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    for code in (P.OP_DINV, P.OP_PRECOND):
+        y0 = gs.apply(code, x)
+        for _ in range(3):
+            assert np.array_equal(gs.apply(code, x).view(np.float64), y0.view(np.float64)), code
+
+
 @pytest.mark.parametrize("nrhs", [3, 40])  # 16-column kernel / wide kernels with k-slices
 def test_split_f16_operators_are_closer_than_bf16(mid, nrhs):
     prob, gs, ps = mid
