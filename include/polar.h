@@ -339,6 +339,8 @@ pt_status pt_solve_batch_merged(int32_t nprob, pt_solver* const* s, const int32_
  * address is taken at the first pt_setup on that device).  It needs
  * 3 * nrhs * 4(L-1)NX * 16 bytes (each rounded up to 256) plus the partial
  * tiles; larger calls return PT_EINVAL with the size in pt_last_error().
+ * MFMA launches that pt_tune split into k-slices over workgroups keep their
+ * partial tiles in the solver's own workspace, allocated by pt_setup.
  * Every call on one GPU shares that array and overwrites it (nothing in it
  * needs to start at zero), so calls that overlap on one GPU, from any
  * solvers or streams, race: serialise them.  Synchronises the solver's
