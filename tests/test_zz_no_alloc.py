@@ -36,18 +36,21 @@ def test_noalloc_apply_matches_apply(precision, closure):
     if closure == "extrap":
         ops += [P.OP_A_EXTRAP, P.OP_R_EXTRAP, P.OP_DINV_EXTRAP, P.OP_PRECOND_EXTRAP]
     g = torch.Generator(device="cuda:0").manual_seed(7)
-    for nrhs in (40, 7):  # two calls in a row, the second smaller
-        shape = (nrhs, 2, prob.L - 1, 2, prob.NX)
-        x = torch.complex(torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g),
-                          torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g))
-        for op in ops:
-            ref = s.apply(op, x)
-            y = torch.full_like(x, complex(np.nan, np.nan))
-            torch.cuda.synchronize()
-            st = fn(s._h, op, nrhs, x.data_ptr(), y.data_ptr())
-            assert st == 0, P.lib().pt_last_error().decode()
-            torch.cuda.synchronize()
-            assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref)), (nrhs, op)
+    for tuned in (False, True):  # the rules' launch shapes, then pt_tune's (MFMA k-slices where it picks them)
+        if tuned:
+            s.tune(40)
+        for nrhs in (40, 7):  # two calls in a row, the second smaller
+            shape = (nrhs, 2, prob.L - 1, 2, prob.NX)
+            x = torch.complex(torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g),
+                              torch.randn(shape, dtype=torch.float64, device="cuda:0", generator=g))
+            for op in ops:
+                ref = s.apply(op, x)
+                y = torch.full_like(x, complex(np.nan, np.nan))
+                torch.cuda.synchronize()
+                st = fn(s._h, op, nrhs, x.data_ptr(), y.data_ptr())
+                assert st == 0, P.lib().pt_last_error().decode()
+                torch.cuda.synchronize()
+                assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref)), (tuned, nrhs, op)
     s.close()
 
 
